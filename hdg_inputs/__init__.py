@@ -1,0 +1,114 @@
+"""Seeded synthetic inputs shared by the CPU oracle tests and the GPU path.
+
+This module holds none of the method's arithmetic: it only produces meshes
+(vertex coordinates and cell->vertex connectivity) and evaluates analytic
+velocity fields at points that the caller supplies.  Both the oracle and the
+GPU library project those point values themselves.
+
+Workload recipe (the paper's test setup, Section "Setup": the unit square cut
+into n x n squares, each split into two right-angled triangles):
+
+* mesh: vertex (i, j) has id j*(n+1)+i and coordinates (i/n, j/n); square
+  (i, j) is cut along its "/" diagonal into the cells (v00, v10, v11) and
+  (v00, v11, v01), both counter-clockwise, cell ids 2*(j*n+i) and 2*(j*n+i)+1.
+* initial velocity: the curl Q = (d_y psi, -d_x psi) of the stream function
+  psi = sum_m A_m sin(k_m pi x) sin(l_m pi y), m = 1..4, drawn from
+  numpy.random.default_rng(seed) in the order A_m = standard_normal(),
+  k_m = integers(1, 4), l_m = integers(1, 4) per term.  psi vanishes on the
+  boundary, so n.Q = 0 on the walls.
+* Taylor-Green vortex (Section "Taylor Green vortex"): velocity and forcing
+  as printed; the pressure is the mean-zero field that satisfies the momentum
+  equation (the printed pressure does not).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "unit_square_mesh",
+    "stream_function_params",
+    "streamfunction_velocity",
+    "taylor_green_velocity",
+    "taylor_green_forcing",
+    "taylor_green_pressure",
+    "random_mesh_perturbation",
+]
+
+
+def unit_square_mesh(n: int):
+    """Return (coords float64[(n+1)^2, 2], cells int32[2 n^2, 3])."""
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    i, j = np.meshgrid(np.arange(n + 1), np.arange(n + 1), indexing="xy")
+    coords = np.stack([i.ravel() / n, j.ravel() / n], axis=1).astype(np.float64)
+    si, sj = np.meshgrid(np.arange(n), np.arange(n), indexing="xy")
+    si = si.ravel()
+    sj = sj.ravel()
+    v00 = sj * (n + 1) + si
+    v10 = v00 + 1
+    v01 = v00 + (n + 1)
+    v11 = v01 + 1
+    cells = np.empty((2 * n * n, 3), dtype=np.int32)
+    cells[0::2] = np.stack([v00, v10, v11], axis=1)
+    cells[1::2] = np.stack([v00, v11, v01], axis=1)
+    return coords, cells
+
+
+def random_mesh_perturbation(coords: np.ndarray, n: int, amplitude: float, seed: int):
+    """Move interior vertices of a unit-square mesh by a seeded random offset.
+
+    Boundary vertices stay put, so the domain is unchanged.  amplitude is a
+    fraction of the grid spacing 1/n (keep it below ~0.3 to keep cells valid).
+    """
+    rng = np.random.default_rng(seed)
+    out = coords.copy()
+    interior = (
+        (coords[:, 0] > 1e-12) & (coords[:, 0] < 1 - 1e-12)
+        & (coords[:, 1] > 1e-12) & (coords[:, 1] < 1 - 1e-12)
+    )
+    out[interior] += amplitude / n * rng.uniform(-1.0, 1.0, size=(int(interior.sum()), 2))
+    return out
+
+
+def stream_function_params(seed: int, nterms: int = 4):
+    """Amplitudes and wavenumbers of the seeded stream function."""
+    rng = np.random.default_rng(seed)
+    amp = np.empty(nterms)
+    kx = np.empty(nterms, dtype=np.int64)
+    ky = np.empty(nterms, dtype=np.int64)
+    for m in range(nterms):
+        amp[m] = rng.standard_normal()
+        kx[m] = rng.integers(1, 4)
+        ky[m] = rng.integers(1, 4)
+    return amp, kx, ky
+
+
+def streamfunction_velocity(params, x: np.ndarray, y: np.ndarray):
+    """Q = (d psi/dy, -d psi/dx) at the points (x, y); returns shape x.shape + (2,)."""
+    amp, kx, ky = params
+    qx = np.zeros(np.broadcast(x, y).shape)
+    qy = np.zeros_like(qx)
+    for a, k, l in zip(amp, kx, ky):
+        qx += a * l * np.pi * np.sin(k * np.pi * x) * np.cos(l * np.pi * y)
+        qy -= a * k * np.pi * np.cos(k * np.pi * x) * np.sin(l * np.pi * y)
+    return np.stack([qx, qy], axis=-1)
+
+
+def _tg_angles(x, y):
+    return (2.0 * x - 1.0) * np.pi / 2.0, (2.0 * y - 1.0) * np.pi / 2.0
+
+
+def taylor_green_velocity(x, y, t: float = 0.0, kappa: float = 0.5):
+    a, b = _tg_angles(np.asarray(x, float), np.asarray(y, float))
+    e = np.exp(-kappa * t)
+    return np.stack([-e * np.cos(a) * np.sin(b), e * np.sin(a) * np.cos(b)], axis=-1)
+
+
+def taylor_green_forcing(x, y, t: float, kappa: float = 0.5):
+    return -kappa * taylor_green_velocity(x, y, t, kappa)
+
+
+def taylor_green_pressure(x, y, t: float = 0.0, kappa: float = 0.5):
+    """Mean-zero pressure that balances (Q.grad)Q for the Taylor-Green velocity."""
+    a, b = _tg_angles(np.asarray(x, float), np.asarray(y, float))
+    return -0.25 * np.exp(-2.0 * kappa * t) * (np.cos(2.0 * a) + np.cos(2.0 * b))

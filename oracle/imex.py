@@ -1,0 +1,200 @@
+"""IMEX-HDG time stepping (oracle side; test infrastructure).
+
+* Butcher tableaux in the paper's form (Appendix A): s stages, implicit
+  tableau with a zero first column (a^im_{i,0} = b^im_0 = 0).  IMEX Euler is
+  printed in the paper.  ARS(2,2,2) and ARS(2,3,3) are the Ascher-Ruuth-
+  Spiteri schemes the paper cites; their coefficients are not printed there and
+  are pinned by the IMEX order conditions in the tests.
+* ``stage_residual`` / ``final_residual``: eqs. (imex_residual) and
+  (final_residual), the recursion that replaces f_im(Q_j) by
+  (M Q_j - r_j) / a_jj.
+* ``IMEXHDG.richardson``: Algorithm 2 (Steps I-III), with the weak divergence
+  as the right-hand side of the psi-equation of Step II (the printed Step II
+  puts it on the w-line with swapped test functions; the mixed-Poisson reading
+  delta Q + grad p = 0, div delta Q = b fixes it to the psi-equation).
+* ``IMEXHDG.step``: Algorithm 1; the final projection uses c = dt b^im_{s-1}
+  (Algorithm 1 prints b^im, eq. (Q_nplus1_equation) prints b^ex; b^ex_{s-1}
+  vanishes for the schemes used, which would make the system singular).
+* ``IMEXHDG.reconstruct``: eq. (pressure_reconstruction_compact) with
+  f_p = -f + (Q.grad_h)Q.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.sparse.linalg as spla
+
+from .hdg import HDGSolver
+
+
+@dataclass(frozen=True)
+class Tableau:
+    name: str
+    Aex: np.ndarray
+    bex: np.ndarray
+    Aim: np.ndarray
+    bim: np.ndarray
+
+    @property
+    def s(self) -> int:
+        return self.Aex.shape[0]
+
+    @property
+    def c(self) -> np.ndarray:
+        return self.Aex.sum(axis=1)
+
+
+def imex_euler() -> Tableau:
+    return Tableau("imex_euler",
+                   np.array([[0.0, 0.0], [1.0, 0.0]]), np.array([1.0, 0.0]),
+                   np.array([[0.0, 0.0], [0.0, 1.0]]), np.array([0.0, 1.0]))
+
+
+def ars222() -> Tableau:
+    g = 1.0 - 1.0 / np.sqrt(2.0)
+    d = 1.0 - 1.0 / (2.0 * g)
+    return Tableau("ars222",
+                   np.array([[0.0, 0.0, 0.0], [g, 0.0, 0.0], [d, 1.0 - d, 0.0]]),
+                   np.array([d, 1.0 - d, 0.0]),
+                   np.array([[0.0, 0.0, 0.0], [0.0, g, 0.0], [0.0, 1.0 - g, g]]),
+                   np.array([0.0, 1.0 - g, g]))
+
+
+def ars233() -> Tableau:
+    g = (3.0 + np.sqrt(3.0)) / 6.0
+    return Tableau("ars233",
+                   np.array([[0.0, 0.0, 0.0], [g, 0.0, 0.0], [g - 1.0, 2.0 * (1.0 - g), 0.0]]),
+                   np.array([0.0, 0.5, 0.5]),
+                   np.array([[0.0, 0.0, 0.0], [0.0, g, 0.0], [0.0, 1.0 - 2.0 * g, g]]),
+                   np.array([0.0, 0.5, 0.5]))
+
+
+TABLEAUX = {"imex_euler": imex_euler, "ars222": ars222, "ars233": ars233}
+
+
+def stage_residual(tab: Tableau, i: int, MQn, MQ, r, fex, dt):
+    """r_i = M Q^n + sum_{j=1}^{i-1} a_ij/a_jj (M Q_j - r_j) + dt sum_{j=0}^{i-1} a^ex_ij f^ex_j.
+
+    MQ, r: lists indexed by stage (entry 0 unused); fex: list of explicit
+    forcing duals f^ex(t^n + c_j dt), or None for zero forcing."""
+    out = MQn.copy()
+    for j in range(1, i):
+        out = out + tab.Aim[i, j] / tab.Aim[j, j] * (MQ[j] - r[j])
+    if fex is not None:
+        for j in range(0, i):
+            out = out + dt * tab.Aex[i, j] * fex[j]
+    return out
+
+
+def final_residual(tab: Tableau, MQn, MQ, r, fex, dt):
+    """r^{n+1} = M Q^n + sum_i b^im_i/a_ii (M Q_i - r_i) + dt sum_i b^ex_i f^ex_i."""
+    out = MQn.copy()
+    for i in range(1, tab.s):
+        out = out + tab.bim[i] / tab.Aim[i, i] * (MQ[i] - r[i])
+    if fex is not None:
+        for i in range(tab.s):
+            out = out + dt * tab.bex[i] * fex[i]
+    return out
+
+
+class IMEXHDG:
+    def __init__(self, disc, dt: float, tableau: Tableau, n_richardson: int = 3,
+                 forcing=None, pressure_update: str = "reconstruct"):
+        self.disc = disc
+        self.dt = float(dt)
+        self.tab = tableau
+        self.nR = int(n_richardson)
+        self.forcing = forcing  # callable f(x, y, t) -> (..., 2), or None
+        if pressure_update not in ("reconstruct", "first_order"):
+            raise ValueError(pressure_update)
+        self.pressure_update = pressure_update
+        self.M = disc.mass()
+        self.ops = disc.static_operators()
+        self.hdg1 = HDGSolver(disc, 1.0)
+        self.hdg_final = HDGSolver(disc, self.dt * tableau.bim[-1])
+        self.log = []
+
+    # ------------------------------------------------------------------
+    def forcing_dual(self, t):
+        """f^ex(w; t) = (w . f(t))_Omega as a dual vector (eq. f_expl)."""
+        d = self.disc
+        vals = self.forcing(d.cx[..., 0], d.cx[..., 1], t)
+        return np.einsum("kq,qi,kqc->kci", d.cw, d.Vu, vals).reshape(-1)
+
+    def reconstruct(self, Q, t):
+        """Pressure reconstruction: mixed problem with psi-data Div(psi, f_p) and
+        wall data -<mu n.f>; returns (p, lambda) with int p = 0."""
+        d = self.disc
+        cell, fac = d.convection_points(Q)
+        if self.forcing is not None:
+            fcell = self.forcing(d.cx[..., 0], d.cx[..., 1], t)
+            ffac = self.forcing(d.cf_x[..., 0], d.cf_x[..., 1], t)
+            cell = cell - fcell
+            fac = fac - ffac
+            Fmu = d.boundary_normal_flux(ffac)
+        else:
+            Fmu = np.zeros(d.nT)
+        Fpsi = d.div_c_points(cell, fac)
+        _, p, lam = self.hdg1.solve(np.zeros(d.nQ), Fpsi, Fmu)
+        return p, lam
+
+    def initial_state(self, velocity_fun, t: float = 0.0):
+        Q = self.disc.l2_project_velocity(velocity_fun)
+        p, lam = self.reconstruct(Q, t)
+        return Q, p, lam
+
+    # ------------------------------------------------------------------
+    def richardson(self, r_i, a_ii, Qs, Q, p, lam):
+        """Algorithm 2: n_R preconditioned Richardson iterations for stage i."""
+        d = self.disc
+        adt = a_ii * self.dt
+        A = d.advection(Qs)
+        lu = spla.splu((self.M - adt * A).tocsc())
+        zQ, zT = np.zeros(d.nQ), np.zeros(d.nT)
+        for _ in range(self.nR):
+            dr = r_i - self.M @ Q + adt * (A @ Q + d.g(p, lam))
+            Qbar = lu.solve(dr)                                  # Step I
+            Fpsi = -d.div_c(Qbar) / adt
+            dQ, dp, dl = self.hdg1.solve(zQ, Fpsi, zT)            # Step II
+            Q = Q + Qbar + adt * dQ                               # Step III
+            p = p + dp
+            lam = lam + dl
+            self.log.append(dict(dr=float(np.linalg.norm(dr)), Qbar=float(np.linalg.norm(Qbar))))
+        return Q, p, lam
+
+    def step(self, Q, p, lam, t):
+        """Algorithm 1: one IMEX-HDG step from (Q^n, p^n, lambda^n) at time t."""
+        d, tab, dt = self.disc, self.tab, self.dt
+        s = tab.s
+        MQn = self.M @ Q
+        fex = None
+        if self.forcing is not None:
+            fex = [self.forcing_dual(t + tab.c[j] * dt) for j in range(s)]
+        Qs_ = [Q] + [None] * (s - 1)
+        ps_ = [p] + [None] * (s - 1)
+        ls_ = [lam] + [None] * (s - 1)
+        MQ = [MQn] + [None] * (s - 1)
+        r = [None] * s
+        for i in range(1, s):
+            r[i] = stage_residual(tab, i, MQn, MQ, r, fex, dt)
+            Qstar = d.bdm_project(Qs_[i - 1])
+            Qs_[i], ps_[i], ls_[i] = self.richardson(r[i], tab.Aim[i, i], Qstar, Qs_[i - 1], ps_[i - 1], ls_[i - 1])
+            MQ[i] = self.M @ Qs_[i]
+        rn = final_residual(tab, MQn, MQ, r, fex, dt)
+        Qn, dp, dl = self.hdg_final.solve(rn, np.zeros(d.nP), np.zeros(d.nT))
+        if self.pressure_update == "reconstruct":
+            pn, ln = self.reconstruct(Qn, t + dt)
+        else:
+            pn, ln = self.hdg1.normalise(ps_[-1] + dp, ls_[-1] + dl)
+        self.last_final = (dp, dl)
+        return Qn, pn, ln
+
+    def run(self, Q, p, lam, t0, nsteps, callback=None):
+        t = t0
+        for n in range(nsteps):
+            Q, p, lam = self.step(Q, p, lam, t)
+            t += self.dt
+            if callback is not None:
+                callback(n + 1, t, Q, p, lam)
+        return Q, p, lam

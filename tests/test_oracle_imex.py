@@ -1,0 +1,162 @@
+"""Pins of the oracle's IMEX-HDG time stepping (CPU only).
+
+P9:  tableau order conditions (including the IMEX coupling conditions), and
+     the observed order of the stage-residual recursion on a scalar linear
+     ODE with explicit forcing.
+P10: after a step, Gamma(psi, mu, Q^{n+1}, dp, dlambda) = 0: the hybridised
+     normal flux is single-valued and divergence-free cell by cell.
+P11: zero forcing: the kinetic energy never increases (upwind and penalty
+     terms only dissipate).
+P12: Taylor-Green vortex: the velocity error decreases under refinement with
+     dt ~ h at least at the rate the paper reports (h^k); the reconstructed
+     pressure of the exact velocity converges to the exact pressure.
+P13: a zero state with zero forcing stays exactly zero.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import hdg_inputs as hi
+from oracle.forms import Discretisation
+from oracle.imex import IMEXHDG, TABLEAUX, ars222, ars233, final_residual, imex_euler, stage_residual
+
+
+def _conds(tab):
+    Ae, be, Ai, bi = tab.Aex, tab.bex, tab.Aim, tab.bim
+    ce, ci = Ae.sum(1), Ai.sum(1)
+    return Ae, be, ce, Ai, bi, ci
+
+
+@pytest.mark.parametrize("name,order", [("imex_euler", 1), ("ars222", 2), ("ars233", 3)])
+def test_p9_order_conditions(name, order):
+    tab = TABLEAUX[name]()
+    Ae, be, ce, Ai, bi, ci = _conds(tab)
+    # the paper's structural assumptions: explicit tableau strictly lower
+    # triangular, implicit first column and b_0^im zero
+    assert np.allclose(np.triu(Ae), 0) and np.allclose(Ai[:, 0], 0) and bi[0] == 0
+    assert np.allclose(ce, ci)
+    assert abs(be.sum() - 1) < 1e-15 and abs(bi.sum() - 1) < 1e-15
+    if order >= 2:
+        for b, c in itertools.product((be, bi), (ce, ci)):
+            assert abs(b @ c - 0.5) < 1e-15
+    if order >= 3:
+        for b, c in itertools.product((be, bi), (ce, ci)):
+            assert abs(b @ c**2 - 1 / 3) < 1e-15
+        for b, A, c in itertools.product((be, bi), (Ae, Ai), (ce, ci)):
+            assert abs(b @ A @ c - 1 / 6) < 1e-15
+
+
+@pytest.mark.parametrize("name,order", [("imex_euler", 1), ("ars222", 2), ("ars233", 3)])
+def test_p9_scalar_ode_order(name, order):
+    """y' = lam y + g(t), lam implicit, g explicit; exact y = 1 + sin t."""
+    tab = TABLEAUX[name]()
+    lam = -2.0
+    g = lambda t: np.cos(t) - lam * (1.0 + np.sin(t))
+    errs = []
+    for nt in (20, 40, 80):
+        dt = 1.0 / nt
+        y, t = 1.0, 0.0
+        for _ in range(nt):
+            MQn = np.array([y])
+            fex = [np.array([g(t + tab.c[j] * dt)]) for j in range(tab.s)]
+            MQ, r = [MQn] + [None] * (tab.s - 1), [None] * tab.s
+            for i in range(1, tab.s):
+                r[i] = stage_residual(tab, i, MQn, MQ, r, fex, dt)
+                MQ[i] = r[i] / (1.0 - dt * tab.Aim[i, i] * lam)
+            y = float(final_residual(tab, MQn, MQ, r, fex, dt)[0])
+            t += dt
+        errs.append(abs(y - (1.0 + np.sin(1.0))))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert rates.min() > order - 0.15, rates
+
+
+def _cfg(n, k, seed=0, dt=1e-3, tab=None, nR=3):
+    X, C = hi.unit_square_mesh(n)
+    d = Discretisation(X, C, k)
+    st = IMEXHDG(d, dt, tab or ars222(), nR)
+    par = hi.stream_function_params(seed)
+    Q, p, lam = st.initial_state(lambda x, y: hi.streamfunction_velocity(par, x, y))
+    return d, st, Q, p, lam
+
+
+@pytest.mark.parametrize("n,k", [(8, 1), (6, 3)])
+def test_p10_p11_constraint_and_energy(n, k):
+    d, st, Q, p, lam = _cfg(n, k, dt=2e-3)
+    ke = [d.kinetic_energy(Q)]
+    t = 0.0
+    for _ in range(4):
+        Q, p, lam = st.step(Q, p, lam, t)
+        t += st.dt
+        dp, dl = st.last_final
+        gp, gm = d.gamma(Q, dp, dl)
+        ops = d.static_operators()
+        # backward-error scale: |operator| |argument| of the largest term
+        scale = max(abs(ops["Dv"]).sum(axis=1).max() * np.abs(Q).max(),
+                    abs(ops["Cl"]).sum(axis=1).max() * np.abs(Q).max(),
+                    abs(ops["Tpl"]).sum(axis=1).max() * np.abs(dl).max())
+        assert np.abs(gp).max() < 1e-12 * scale
+        assert np.abs(gm).max() < 1e-12 * scale
+        ke.append(d.kinetic_energy(Q))
+        assert abs(d.pressure_integral(p)) < 1e-12
+    assert np.all(np.diff(ke) <= 1e-12 * ke[0]), ke
+
+
+@pytest.mark.slow
+def test_p11_config1_energy_decreases():
+    """The small parity workload: n=16, k=1, ARS(2,2,2), dt=1e-3, 10 steps, n_R=3."""
+    d, st, Q, p, lam = _cfg(16, 1)
+    ke = [d.kinetic_energy(Q)]
+    for s in range(10):
+        Q, p, lam = st.step(Q, p, lam, s * 1e-3)
+        ke.append(d.kinetic_energy(Q))
+    assert np.all(np.diff(ke) < 0)
+
+
+def test_p13_zero_state_stays_zero():
+    X, C = hi.unit_square_mesh(4)
+    d = Discretisation(X, C, 2)
+    st = IMEXHDG(d, 1e-2, ars233(), 2)
+    Q, p, lam = np.zeros(d.nQ), np.zeros(d.nP), np.zeros(d.nT)
+    Q, p, lam = st.step(Q, p, lam, 0.0)
+    assert not Q.any() and not p.any() and not lam.any()
+
+
+def _tg_errors(d, Q, p, t):
+    val, _ = d.eval_cell(Q)
+    ex = hi.taylor_green_velocity(d.cx[..., 0], d.cx[..., 1], t)
+    eq = np.sqrt(np.sum(d.cw[..., None] * (val - ex) ** 2))
+    pv = np.einsum("qs,ks->kq", d.Vp, p.reshape(-1, d.npp))
+    ep = np.sqrt(np.sum(d.cw * (pv - hi.taylor_green_pressure(d.cx[..., 0], d.cx[..., 1], t)) ** 2))
+    return eq, ep
+
+
+@pytest.mark.parametrize("tab,k,ns,minrate", [(imex_euler, 1, (4, 8, 16), 0.8), (ars222, 2, (4, 8), 2.0)])
+def test_p12_taylor_green_convergence(tab, k, ns, minrate):
+    T = 0.5
+    errs = []
+    for n in ns:
+        X, C = hi.unit_square_mesh(n)
+        d = Discretisation(X, C, k)
+        nt = n // 2
+        st = IMEXHDG(d, T / nt, tab(), 2, forcing=hi.taylor_green_forcing)
+        Q, p, lam = st.initial_state(lambda x, y: hi.taylor_green_velocity(x, y, 0.0))
+        Q, p, lam = st.run(Q, p, lam, 0.0, nt)
+        errs.append(_tg_errors(d, Q, p, T))
+    errs = np.array(errs)
+    rates = np.log2(errs[:-1] / errs[1:])
+    assert rates[:, 0].min() > minrate, rates
+    assert rates[:, 1].min() > minrate, rates
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_p12_pressure_reconstruction_of_exact_velocity(k):
+    errs = []
+    for n in (4, 8, 16):
+        X, C = hi.unit_square_mesh(n)
+        d = Discretisation(X, C, k)
+        st = IMEXHDG(d, 0.1, imex_euler(), 1, forcing=hi.taylor_green_forcing)
+        Q, p, lam = st.initial_state(lambda x, y: hi.taylor_green_velocity(x, y, 0.0))
+        errs.append(_tg_errors(d, Q, p, 0.0)[1])
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert rates.min() > k + 0.5, rates
