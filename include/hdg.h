@@ -1,0 +1,168 @@
+/*
+ * hdg.h - C ABI of the MI355X HDG-IMEX library (libhdg.so).
+ *
+ * The library advances the incompressible Euler equations with the
+ * hybridised DG discretisation and IMEX Runge-Kutta time stepping of
+ * Mueller, "A Higher-order Hybridisable Discontinuous Galerkin IMEX method
+ * for the incompressible Euler equations" (arXiv:2410.09790):
+ *   - problem: eqs. (incompressible_euler_momentum/constraint), n.Q = 0 walls;
+ *   - spaces: V_Q = [DG_{k+1}]^2, V_p = DG_k with int p = 0, V_trace = P_k on
+ *     the facets (Section "Discontinuous Galerkin spaces", "Hybridisation");
+ *   - one time step: Algorithm 1, each implicit stage solved by Algorithm 2
+ *     (Chorin-split preconditioned Richardson iteration);
+ *   - the hybridised mixed solve of Step II, of the final projection and of
+ *     the pressure reconstruction: static condensation onto the trace,
+ *     multigrid-preconditioned CG on the trace system, back-substitution
+ *     (Section "Solvers and preconditioners").
+ * Only two-dimensional triangle meshes are supported; the forcing f is zero.
+ *
+ * Data layout (all state and right-hand-side arrays):
+ *   Q[cell][c*ns + s]  velocity, component c in {x, y}, ns = (k+2)(k+3)/2;
+ *   p[cell][s]         pressure, s < (k+1)(k+2)/2;
+ *   lam[facet][m]      trace, m < k+1.
+ *   Cell basis: orthonormal Dubiner basis on the reference triangle
+ *   {xi, eta >= 0, xi + eta <= 1}, mapped by x = v0 + (v1-v0) xi + (v2-v0) eta
+ *   with (v0, v1, v2) the cell's vertices in the order given to hdg_create;
+ *     phi_ij = sqrt(2(2i+1)(i+j+1)) P_i(a) ((1-b)/2)^i P_j^{(2i+1,0)}(b),
+ *     r = 2xi-1, s = 2eta-1, a = 2(1+r)/(1-s)-1, b = s, ordered by total
+ *     degree i+j, then by i ascending.
+ *   Facets: the distinct vertex pairs (lo, hi), lo < hi, numbered in
+ *   lexicographic order; facet basis mu_m(t) = sqrt(2m+1) P_m(2t-1) with t
+ *   running from vertex lo (t=0) to vertex hi (t=1).
+ *   A dual vector (a right-hand side F_w(w) = sum_i F_i w_i) uses the same
+ *   index as the unknown it tests.
+ *
+ * Conventions:
+ *   - Every compute entry point takes DEVICE pointers (e.g. the data_ptr() of
+ *     a torch tensor on the context's device), enqueues its work on the
+ *     context's HIP stream and returns after that work has completed.
+ *   - Buffers passed in stay owned by the caller; the context owns every
+ *     internal device allocation and frees it in hdg_destroy.
+ *   - No exception crosses the ABI: every function returns an hdg_status;
+ *     hdg_last_error() gives a message.  A context is used by one host
+ *     thread at a time.
+ */
+#ifndef HDG_H
+#define HDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HDG_OK = 0,
+  HDG_ERR_INVALID_ARG = 1,   /* bad pointer, size or parameter */
+  HDG_ERR_OUT_OF_MEMORY = 2, /* device allocation failed */
+  HDG_ERR_DEVICE = 3,        /* a HIP call failed */
+  HDG_ERR_NOT_CONVERGED = 4, /* a Krylov solve hit its iteration cap; the result is kept */
+  HDG_ERR_BAD_STATE = 5,     /* e.g. hdg_advance before any state was set */
+  HDG_ERR_UNSUPPORTED = 6    /* feature outside this build (3D, degree > 4, ...) */
+} hdg_status;
+
+typedef enum { HDG_IMEX_EULER = 0, HDG_ARS222 = 1, HDG_ARS233 = 2 } hdg_imex_scheme;
+typedef enum { HDG_TRACE_JACOBI_PCG = 0, HDG_TRACE_MG_PCG = 1 } hdg_trace_solver;
+typedef enum { HDG_PRESSURE_RECONSTRUCT = 0, HDG_PRESSURE_FIRST_ORDER = 1 } hdg_pressure_update;
+
+typedef struct hdg_ctx hdg_ctx;
+
+/* Discretisation and solver parameters.  Paper values (Section "Setup"):
+ * tau = alpha = delta_up = 1; the paper uses n_R = 2 Richardson iterations. */
+typedef struct {
+  int degree;            /* k: pressure and trace degree, velocity degree k+1; 1..4 */
+  double tau;            /* HDG stabilisation, eq. (flux_hdg) */
+  double alpha;          /* interior-penalty weight, eq. (f_impl) */
+  double delta_up;       /* upwind weight, eq. (f_impl) */
+  int imex;              /* hdg_imex_scheme */
+  int n_richardson;      /* n_R of Algorithm 2 */
+  int trace_solver;      /* hdg_trace_solver */
+  double rtol_trace;     /* PCG: ||g - S lam||_2 <= rtol ||g||_2 */
+  double rtol_velocity;  /* Step I BiCGStab: same criterion on the mass-scaled system */
+  int max_it_trace;
+  int max_it_velocity;
+  int pressure_update;   /* hdg_pressure_update */
+} hdg_params;
+
+/* Fill p with the defaults: k=1, tau=alpha=delta_up=1, ARS(2,2,2), n_R=3,
+ * MG-PCG, rtol 1e-12 for both solvers, caps 5000 / 20000, reconstruction. */
+void hdg_default_params(hdg_params* p);
+
+/* Create a context on the current HIP device.  coords: host [nv][2];
+ * cells: host [nc][3] vertex ids, counter-clockwise (det J > 0).  stream:
+ * a hipStream_t (NULL = the null stream).  The mesh is copied.  Errors:
+ * INVALID_ARG (bad mesh or parameters; message via hdg_last_error(NULL)),
+ * UNSUPPORTED (degree), OUT_OF_MEMORY, DEVICE. */
+int hdg_create(int64_t nv, const double* coords, int64_t nc, const int32_t* cells,
+               const hdg_params* prm, void* stream, hdg_ctx** out);
+void hdg_destroy(hdg_ctx* ctx);
+
+/* Last error message of ctx, or of the last failed hdg_create in this
+ * thread when ctx is NULL.  Never NULL. */
+const char* hdg_last_error(const hdg_ctx* ctx);
+
+/* Sizes, written to out[0..n-1] (n <= 8): ncells, nfacets, dim V_Q, dim
+ * V_p, dim V_trace, number of cell quadrature points per cell, number of
+ * vertices, degree. */
+int hdg_sizes(const hdg_ctx* ctx, int64_t* out, int n);
+
+/* Physical coordinates of the cell quadrature points, HOST buffer
+ * [ncells][nq][2].  The caller evaluates the initial velocity there and
+ * passes the values to hdg_set_velocity_from_points. */
+int hdg_cell_points(const hdg_ctx* ctx, double* xy);
+
+/* Initial state (the paper leaves it open): Q = cell-wise L2 projection of
+ * the given point values [ncells][nq][2] with the cell rule; (p, lam) from
+ * the pressure reconstruction of Q. */
+int hdg_set_velocity_from_points(hdg_ctx* ctx, const double* qvals);
+
+int hdg_set_state(hdg_ctx* ctx, const double* Q, const double* p, const double* lam);
+int hdg_get_state(const hdg_ctx* ctx, double* Q, double* p, double* lam);
+
+/* Algorithm 1: nsteps IMEX-HDG steps of size dt from the current state. */
+int hdg_advance(hdg_ctx* ctx, double dt, int nsteps);
+
+/* One hybridised mixed solve (paper, Section "Solvers and preconditioners"):
+ * find (U, p, lam) with
+ *   (U, w) - c g(w, p, lam) = Fw(w),  Gamma(psi, mu, U, p, lam) = Fpsi(psi) + Fmu(mu)
+ * for all (w, psi, mu); g and Gamma as in Section "Hybridisation".  The data
+ * must satisfy Fpsi(1) = Fmu(1) (the component violating it is removed);
+ * (p, lam) is normalised to int p = 0.  c > 0. */
+int hdg_solve_trace(hdg_ctx* ctx, double c, const double* Fw, const double* Fpsi,
+                    const double* Fmu, double* U, double* p, double* lam);
+
+/* y = S_c x for the condensed trace operator of hdg_solve_trace (a1). */
+int hdg_trace_matvec(hdg_ctx* ctx, double c, const double* x, double* y);
+
+/* Q* = P(Q), the H(div)-conforming (BDM) interpolant used as advecting
+ * velocity (Section "Original fully-implicit DG method"): normal moments of
+ * the facet average against P_{k+1}(F) (zero on walls) and interior moments
+ * against the first-kind Nedelec space of degree k. */
+int hdg_bdm_project(hdg_ctx* ctx, const double* Q, double* Qstar);
+
+/* out = Div(psi, F) for all psi (dual vector in V_p): the weak divergence of
+ * Section "Splitting method", central flux {F}.n on interior facets and
+ * zero flux on walls. */
+int hdg_weak_divergence(hdg_ctx* ctx, const double* F, double* out);
+
+/* Algorithm 2, residual step: out(w) = r(w) - (Q, w) + adt (f_im(w, Q, Qstar)
+ * + g(w, p, lam)), with f_im of eq. (f_impl). */
+int hdg_momentum_residual(hdg_ctx* ctx, double adt, const double* r, const double* Qstar,
+                          const double* Q, const double* p, const double* lam, double* out);
+
+/* Algorithm 2, Step I: solve (Qbar, w) - adt f_im(w, Qbar, Qstar) = rhs(w). */
+int hdg_tentative_velocity(hdg_ctx* ctx, double adt, const double* Qstar, const double* rhs,
+                           double* Qbar);
+
+/* Pressure reconstruction (Section "Pressure reconstruction", f = 0): the
+ * mixed problem with psi-data Div(psi, (Q.grad_h)Q); returns (p, lam). */
+int hdg_reconstruct_pressure(hdg_ctx* ctx, const double* Q, double* p, double* lam);
+
+/* JSON with sizes, iteration counts of the last calls, timings. */
+int hdg_get_info(const hdg_ctx* ctx, char* buf, size_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HDG_H */

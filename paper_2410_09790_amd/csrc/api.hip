@@ -1,0 +1,801 @@
+// C ABI, device memory management, Krylov solvers and the IMEX-HDG driver.
+//
+// Paper map:
+//   Algorithm 1 (IMEX-HDG step)          -> Ctx::step
+//   Algorithm 2 (Richardson, Steps I-III) -> Ctx::richardson
+//   static condensation + trace solve     -> Ctx::solve_trace (a1, a7, a8, a9)
+//   non-nested multigrid (P1 coarse space, facet-block smoother, AMG coarse
+//   solve; Section "Solvers and preconditioners") -> Ctx::mg_apply
+//   pressure reconstruction               -> Ctx::reconstruct
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/hdg.h"
+#include "hdg_impl.h"
+#include "kernels.h"
+
+namespace hdg {
+
+static thread_local std::string g_create_error;
+
+struct HipError : std::runtime_error {
+  explicit HipError(const std::string& s) : std::runtime_error(s) {}
+};
+struct OomError : std::runtime_error {
+  explicit OomError(const std::string& s) : std::runtime_error(s) {}
+};
+struct ArgError : std::runtime_error {
+  explicit ArgError(const std::string& s) : std::runtime_error(s) {}
+};
+struct SolverBreakdown : std::runtime_error {
+  explicit SolverBreakdown(const std::string& s) : std::runtime_error(s) {}
+};
+
+#define HIPCHK(call)                                                                              \
+  do {                                                                                            \
+    hipError_t e_ = (call);                                                                       \
+    if (e_ != hipSuccess) throw ::hdg::HipError(std::string(#call) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+#define KCHK() HIPCHK(hipGetLastError())
+
+struct Tableau {
+  int s;
+  double Aex[3][3], bex[3], Aim[3][3], bim[3];
+};
+
+static Tableau make_tableau(int which) {
+  Tableau t{};
+  if (which == HDG_IMEX_EULER) {
+    t.s = 2;
+    t.Aex[1][0] = 1.0; t.bex[0] = 1.0;
+    t.Aim[1][1] = 1.0; t.bim[1] = 1.0;
+  } else if (which == HDG_ARS222) {
+    const double g = 1.0 - 1.0 / std::sqrt(2.0), d = 1.0 - 1.0 / (2.0 * g);
+    t.s = 3;
+    t.Aex[1][0] = g; t.Aex[2][0] = d; t.Aex[2][1] = 1.0 - d;
+    t.bex[0] = d; t.bex[1] = 1.0 - d;
+    t.Aim[1][1] = g; t.Aim[2][1] = 1.0 - g; t.Aim[2][2] = g;
+    t.bim[1] = 1.0 - g; t.bim[2] = g;
+  } else if (which == HDG_ARS233) {
+    const double g = (3.0 + std::sqrt(3.0)) / 6.0;
+    t.s = 3;
+    t.Aex[1][0] = g; t.Aex[2][0] = g - 1.0; t.Aex[2][1] = 2.0 * (1.0 - g);
+    t.bex[1] = 0.5; t.bex[2] = 0.5;
+    t.Aim[1][1] = g; t.Aim[2][1] = 1.0 - 2.0 * g; t.Aim[2][2] = g;
+    t.bim[1] = 0.5; t.bim[2] = 0.5;
+  } else {
+    throw ArgError("unknown IMEX scheme");
+  }
+  return t;
+}
+
+struct DevLevel {
+  int n = 0;
+  DCsr A{}, P{}, R{};
+  double* dinv = nullptr;
+  double omega = 0.0;
+  double *b = nullptr, *x = nullptr, *x2 = nullptr, *r = nullptr;
+};
+
+struct TraceOp {
+  double c = 0.0;
+  double* Pinv = nullptr;
+  double* vals = nullptr;
+  int* cols = nullptr;
+  double* Dinv = nullptr;
+  bool mg = false;
+  DCsr Pt{}, Rt{};
+  std::vector<DevLevel> levels;
+  int ncoarse = 0;
+  double* coarse_pinv = nullptr;
+  double *cb = nullptr, *cx = nullptr;  // coarsest rhs / solution
+};
+
+}  // namespace hdg
+
+struct hdg_ctx {
+  hdg_params prm{};
+  int k = 1;
+  hipStream_t st = nullptr;
+  hdg::HostMesh hm;
+  hdg::RefTables rt;
+  hdg::DMesh dm{};
+  hdg::DTab dt{};
+  int ns = 0, np = 0, nf = 0, nu = 0, nlam = 0, nqc = 0, nqf = 0;
+  long nQ = 0, nP = 0, nT = 0;
+  double area = 0.0;
+  std::vector<void*> allocs;
+  std::map<double, std::unique_ptr<hdg::TraceOp>> ops;
+  // work vectors
+  double *ycell = nullptr, *g = nullptr, *part = nullptr, *part2 = nullptr, *scal = nullptr;
+  double *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr, *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;
+  double *bx = nullptr, *br = nullptr, *brh = nullptr, *bp = nullptr, *bv = nullptr, *bs = nullptr, *bt = nullptr,
+         *bsc = nullptr;
+  double *adv = nullptr, *Qs = nullptr, *dr = nullptr, *Qbar = nullptr, *dQ = nullptr, *dp = nullptr, *dl = nullptr,
+         *fpsi = nullptr, *Ut = nullptr;
+  double *Q = nullptr, *p = nullptr, *lam = nullptr;
+  double* stQ[3] = {nullptr, nullptr, nullptr};
+  double* stP[3] = {nullptr, nullptr, nullptr};
+  double* stL[3] = {nullptr, nullptr, nullptr};
+  double* stR[3] = {nullptr, nullptr, nullptr};
+  double* stMQ[3] = {nullptr, nullptr, nullptr};
+  double* h_pinned = nullptr;
+  bool have_state = false;
+  std::string err;
+  // statistics
+  std::vector<int> pcg_iters, bicg_iters;
+  long total_pcg = 0, total_bicg = 0, n_trace_solves = 0, n_velocity_solves = 0;
+  double t_trace = 0.0, t_velocity = 0.0, t_other = 0.0;
+  int max_pcg_bicg_seen = 0;
+  bool not_converged = false;
+
+  template <class T>
+  T* dalloc(size_t n) {
+    void* p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) throw hdg::OomError("hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+    allocs.push_back(p);
+    return static_cast<T*>(p);
+  }
+  template <class T>
+  T* upload(const std::vector<T>& v) {
+    T* d = dalloc<T>(v.size());
+    HIPCHK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    return d;
+  }
+  void sync() { HIPCHK(hipStreamSynchronize(st)); }
+  double read_scalar(const double* d) {
+    HIPCHK(hipMemcpyAsync(h_pinned, d, sizeof(double), hipMemcpyDeviceToHost, st));
+    sync();
+    return h_pinned[0];
+  }
+
+  void setup();
+  hdg::TraceOp& trace_op(double c);
+  void build_mg(hdg::TraceOp& op);
+  void precond(hdg::TraceOp& op, const double* r, double* z);
+  void mg_apply(hdg::TraceOp& op, const double* r, double* z);
+  void vcycle(hdg::TraceOp& op, int l);
+  int pcg(hdg::TraceOp& op, const double* g, double* x);
+  void solve_trace(double c, const double* Fw, const double* Fpsi, const double* Fmu, double* U, double* p,
+                   double* lam);
+  int bicgstab(double adt, const double* b, double* x);
+  void reconstruct(const double* Qin, double* pout, double* lout);
+  void richardson(double adt, const double* r, double* Q, double* p, double* lam);
+  void step(double dt);
+};
+
+using namespace hdg;
+
+void hdg_ctx::setup() {
+  ns = rt.ns; np = rt.np; nf = rt.nf; nu = 2 * ns; nlam = 3 * nf; nqc = rt.nqc; nqf = rt.nqf;
+  const long nc = hm.nc, nF = hm.nF;
+  nQ = nc * nu; nP = nc * np; nT = nF * nf;
+  area = 0.0;
+  for (long e = 0; e < nc; ++e) area += 0.5 * hm.geo[G_DET * nc + e];
+  // mesh
+  std::vector<double> geo((size_t)kDGeo * nc);
+  const int map[kDGeo] = {G_DET, G_IJ00, G_IJ01, G_IJ10, G_IJ11, G_NX0, G_NY0, G_NX1, G_NY1, G_NX2, G_NY2,
+                          G_H0, G_H1, G_H2, G_J00, G_J01, G_J10, G_J11};
+  for (int f = 0; f < kDGeo; ++f)
+    std::memcpy(&geo[(size_t)f * nc], &hm.geo[(size_t)map[f] * nc], nc * sizeof(double));
+  dm.nc = (int)nc;
+  dm.nF = (int)nF;
+  dm.geo = upload(geo);
+  dm.cf_facet = upload(hm.cf_facet);
+  dm.cf_nb = upload(hm.cf_nb);
+  dm.cf_nbf = upload(hm.cf_nbf);
+  dm.cf_flip = upload(hm.cf_flip);
+  dm.fc_cell = upload(hm.fc_cell);
+  dm.fc_f = upload(hm.fc_f);
+  // tables
+  dt.Bu = upload(rt.Bu); dt.Gux = upload(rt.Gux); dt.Guy = upload(rt.Guy);
+  dt.Bp = upload(rt.Bp); dt.Gpx = upload(rt.Gpx); dt.Gpy = upload(rt.Gpy); dt.cw = upload(rt.cq_w);
+  dt.FBu = upload(rt.FBu); dt.FGux = upload(rt.FGux); dt.FGuy = upload(rt.FGuy); dt.FBp = upload(rt.FBp);
+  dt.fw = upload(rt.fq_w); dt.MU = upload(rt.MU); dt.NUB = upload(rt.NUB);
+  dt.Dx = upload(rt.Dx); dt.Dy = upload(rt.Dy); dt.Rx = upload(rt.Rx); dt.Ry = upload(rt.Ry);
+  dt.Chat = upload(rt.Chat); dt.That = upload(rt.That); dt.Ehat = upload(rt.Ehat); dt.CC = upload(rt.CC);
+  dt.KDD = upload(rt.KDD); dt.CD = upload(rt.CD); dt.BDMinv = upload(rt.BDMinv); dt.NED = upload(rt.NED);
+  // work
+  const long nb = (nc + kBlock - 1) / kBlock;
+  ycell = dalloc<double>(nc * nlam);
+  g = dalloc<double>(nT);
+  part = dalloc<double>(std::max<long>(kRedBlocks, nb));
+  part2 = dalloc<double>(2 * kRedBlocks);
+  const int mt = prm.max_it_trace + 4, mv = prm.max_it_velocity + 4;
+  scal = dalloc<double>(3 * mt + 16);
+  bsc = dalloc<double>(8 * (long)mv + 16);
+  pr = dalloc<double>(nT); pz = dalloc<double>(nT); pp = dalloc<double>(nT); pq = dalloc<double>(nT);
+  t1 = dalloc<double>(nT); t2 = dalloc<double>(nT); t3 = dalloc<double>(nT);
+  bx = dalloc<double>(nQ); br = dalloc<double>(nQ); brh = dalloc<double>(nQ); bp = dalloc<double>(nQ);
+  bv = dalloc<double>(nQ); bs = dalloc<double>(nQ); bt = dalloc<double>(nQ);
+  adv = dalloc<double>((long)nc * (2 * nqc + 3 * nqf));
+  Qs = dalloc<double>(nQ); dr = dalloc<double>(nQ); Qbar = dalloc<double>(nQ); dQ = dalloc<double>(nQ);
+  dp = dalloc<double>(nP); dl = dalloc<double>(nT); fpsi = dalloc<double>(nP); Ut = dalloc<double>(nQ);
+  Q = dalloc<double>(nQ); p = dalloc<double>(nP); lam = dalloc<double>(nT);
+  for (int i = 0; i < 3; ++i) {
+    stQ[i] = dalloc<double>(nQ); stP[i] = dalloc<double>(nP); stL[i] = dalloc<double>(nT);
+    stR[i] = dalloc<double>(nQ); stMQ[i] = dalloc<double>(nQ);
+  }
+  HIPCHK(hipHostMalloc((void**)&h_pinned, 64 * sizeof(double), hipHostMallocDefault));
+  sync();
+}
+
+TraceOp& hdg_ctx::trace_op(double c) {
+  auto it = ops.find(c);
+  if (it != ops.end()) return *it->second;
+  auto op = std::make_unique<TraceOp>();
+  op->c = c;
+  const long nc = hm.nc, nF = hm.nF;
+  op->Pinv = dalloc<double>(nc * np * np);
+  double* SK = nullptr;
+  HIPCHK(hipMalloc(&SK, sizeof(double) * nc * nlam * nlam));
+  op->vals = dalloc<double>(5 * nF * nf * nf);
+  op->cols = dalloc<int>(5 * nF);
+  op->Dinv = dalloc<double>(nF * nf * nf);
+  launch_condense(k, st, dm, dt, c, prm.tau, op->Pinv, SK);
+  KCHK();
+  launch_assemble(k, st, dm, SK, op->vals, op->cols, op->Dinv);
+  KCHK();
+  sync();
+  HIPCHK(hipFree(SK));
+  if (prm.trace_solver == HDG_TRACE_MG_PCG) build_mg(*op);
+  TraceOp& ref = *op;
+  ops[c] = std::move(op);
+  return ref;
+}
+
+// Galerkin P1 coarse operator and AMG hierarchy (host setup, device apply)
+void hdg_ctx::build_mg(TraceOp& op) {
+  const long nF = hm.nF;
+  std::vector<double> vals(5 * nF * nf * nf);
+  std::vector<int> cols(5 * nF);
+  HIPCHK(hipMemcpyAsync(vals.data(), op.vals, vals.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(cols.data(), op.cols, cols.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+  sync();
+  Csr S;
+  S.nrows = S.ncols = nT;
+  S.ptr.assign(nT + 1, 0);
+  for (long F = 0; F < nF; ++F)
+    for (int i = 0; i < nf; ++i) {
+      const long row = F * nf + i;
+      for (int s = 0; s < 5; ++s)
+        for (int j = 0; j < nf; ++j) {
+          double v = vals[((long)(s * nf + i) * nf + j) * nF + F];
+          if (v == 0.0) continue;
+          S.idx.push_back(cols[s * nF + F] * nf + j);
+          S.val.push_back(v);
+        }
+      S.ptr[row + 1] = (int32_t)S.idx.size();
+    }
+  Csr Pt;
+  Pt.nrows = nT;
+  Pt.ncols = hm.nv;
+  Pt.ptr.assign(nT + 1, 0);
+  const double r3 = 0.5 / std::sqrt(3.0);
+  for (long F = 0; F < nF; ++F)
+    for (int i = 0; i < nf; ++i) {
+      const long row = F * nf + i;
+      if (i == 0) {  // mean of the linear function
+        Pt.idx.push_back(hm.facet_lo[F]); Pt.val.push_back(0.5);
+        Pt.idx.push_back(hm.facet_hi[F]); Pt.val.push_back(0.5);
+      } else if (i == 1) {  // slope in the orthonormal Legendre basis
+        Pt.idx.push_back(hm.facet_lo[F]); Pt.val.push_back(-r3);
+        Pt.idx.push_back(hm.facet_hi[F]); Pt.val.push_back(r3);
+      }
+      Pt.ptr[row + 1] = (int32_t)Pt.idx.size();
+    }
+  Csr Rt = csr_transpose(Pt);
+  Csr Ac = csr_multiply(Rt, csr_multiply(S, Pt));
+  AmgHierarchy h;
+  amg_setup(Ac, h, 200);
+  auto up = [&](const Csr& A) {
+    DCsr d;
+    d.n = (int)A.nrows;
+    d.ptr = upload(A.ptr);
+    d.idx = A.idx.empty() ? dalloc<int>(1) : upload(A.idx);
+    d.val = A.val.empty() ? dalloc<double>(1) : upload(A.val);
+    return d;
+  };
+  op.Pt = up(Pt);
+  op.Rt = up(Rt);
+  for (auto& L : h.levels) {
+    DevLevel d;
+    d.n = (int)L.A.nrows;
+    d.A = up(L.A); d.P = up(L.P); d.R = up(L.R);
+    d.dinv = upload(L.dinv);
+    d.omega = L.omega;
+    d.b = dalloc<double>(d.n); d.x = dalloc<double>(d.n); d.x2 = dalloc<double>(d.n); d.r = dalloc<double>(d.n);
+    op.levels.push_back(d);
+  }
+  op.ncoarse = (int)h.ncoarse;
+  op.coarse_pinv = upload(h.coarse_pinv);
+  op.cb = dalloc<double>(op.ncoarse);
+  op.cx = dalloc<double>(op.ncoarse);
+  op.mg = true;
+  sync();
+}
+
+void hdg_ctx::vcycle(TraceOp& op, int l) {
+  // level l solves A_l x = b with b in levels[l].b (or op.cb on the coarsest level)
+  if (l == (int)op.levels.size()) {
+    launch_dense_mv(st, op.ncoarse, op.coarse_pinv, op.cb, op.cx);
+    return;
+  }
+  DevLevel& L = op.levels[l];
+  launch_csr_jacobi(st, L.A, L.dinv, L.omega, L.b, nullptr, L.x);
+  launch_csr_jacobi(st, L.A, L.dinv, L.omega, L.b, L.x, L.x2);
+  launch_csr_spmv(st, L.A, L.x2, L.r, 0.0);
+  launch_axpby(st, L.n, 1.0, L.b, -1.0, L.r);
+  const bool last = (l + 1 == (int)op.levels.size());
+  double* bc = last ? op.cb : op.levels[l + 1].b;
+  double* xc = last ? op.cx : op.levels[l + 1].x;
+  launch_csr_spmv(st, L.R, L.r, bc, 0.0);
+  vcycle(op, l + 1);
+  // on the next level the result of vcycle is in its x (levels) or cx (coarsest)
+  launch_csr_spmv(st, L.P, xc, L.x2, 1.0);
+  launch_csr_jacobi(st, L.A, L.dinv, L.omega, L.b, L.x2, L.x);
+  launch_csr_jacobi(st, L.A, L.dinv, L.omega, L.b, L.x, L.x2);
+  launch_copy(st, L.n, L.x2, L.x);
+}
+
+// z = B r: two damped facet-block-Jacobi sweeps, P1 coarse correction, two sweeps
+void hdg_ctx::mg_apply(TraceOp& op, const double* r, double* z) {
+  const int nF = (int)hm.nF;
+  const double om = 0.7;
+  launch_jacobi_sweep(k, st, nF, op.vals, op.cols, op.Dinv, om, r, nullptr, t1);
+  launch_jacobi_sweep(k, st, nF, op.vals, op.cols, op.Dinv, om, r, t1, t2);
+  launch_residual(k, st, nF, op.vals, op.cols, r, t2, t3);
+  double* b0 = op.levels.empty() ? op.cb : op.levels[0].b;
+  double* x0 = op.levels.empty() ? op.cx : op.levels[0].x;
+  launch_csr_spmv(st, op.Rt, t3, b0, 0.0);
+  vcycle(op, 0);
+  launch_csr_spmv(st, op.Pt, x0, t2, 1.0);
+  launch_jacobi_sweep(k, st, nF, op.vals, op.cols, op.Dinv, om, r, t2, t1);
+  launch_jacobi_sweep(k, st, nF, op.vals, op.cols, op.Dinv, om, r, t1, z);
+}
+
+void hdg_ctx::precond(TraceOp& op, const double* r, double* z) {
+  if (op.mg) mg_apply(op, r, z);
+  else launch_blockdiag(k, st, (int)hm.nF, op.Dinv, r, z);
+  KCHK();
+}
+
+// preconditioned CG on S x = g (g orthogonal to the constant trace), x0 = 0
+int hdg_ctx::pcg(TraceOp& op, const double* gin, double* x) {
+  const long n = nT;
+  const int nF = (int)hm.nF;
+  const int maxit = prm.max_it_trace;
+  double* rz = scal;               // [maxit+2]
+  double* pqv = scal + (maxit + 4);  // [maxit+1]
+  double* rr = scal + 2 * (maxit + 4);
+  launch_fill(st, n, 0.0, x);
+  launch_copy(st, n, gin, pr);
+  launch_dot(st, n, pr, nullptr, part);
+  launch_finish(st, part, kRedBlocks, rr + maxit + 2);
+  const double gnorm = std::sqrt(read_scalar(rr + maxit + 2));
+  if (gnorm == 0.0) return 0;
+  precond(op, pr, pz);
+  launch_dot(st, n, pr, pz, part);
+  launch_finish(st, part, kRedBlocks, rz);
+  launch_copy(st, n, pz, pp);
+  for (int it = 0; it < maxit; ++it) {
+    launch_spmv(k, st, nF, op.vals, op.cols, pp, pq);
+    launch_dot(st, n, pp, pq, part);
+    launch_finish(st, part, kRedBlocks, pqv + it);
+    launch_pcg_update(st, n, rz + it, pqv + it, pp, pq, x, pr, part);
+    launch_finish(st, part, kRedBlocks, rr + it);
+    KCHK();
+    const double res = std::sqrt(read_scalar(rr + it));
+    if (!(res == res)) throw SolverBreakdown("PCG breakdown (NaN residual)");
+    if (res <= prm.rtol_trace * gnorm) return it + 1;
+    precond(op, pr, pz);
+    launch_dot(st, n, pr, pz, part);
+    launch_finish(st, part, kRedBlocks, rz + it + 1);
+    launch_pcg_direction(st, n, rz + it + 1, rz + it, pz, pp);
+  }
+  not_converged = true;
+  return maxit;
+}
+
+void hdg_ctx::solve_trace(double c, const double* Fw, const double* Fpsi, const double* Fmu, double* U, double* pout,
+                          double* lout) {
+  auto t0 = std::chrono::steady_clock::now();
+  TraceOp& op = trace_op(c);
+  launch_rhs_condense(k, st, dm, dt, c, prm.tau, op.Pinv, Fw, Fpsi, ycell);
+  launch_gather_rhs(k, st, dm, ycell, Fmu, g);
+  // remove the component along the null vector (constant trace = e_0 on every facet)
+  launch_dot_sub(st, hm.nF, nf, 0, g, part);
+  launch_finish(st, part, kRedBlocks, scal + 3 * (prm.max_it_trace + 4));
+  launch_project_const(st, (int)hm.nF, nf, scal + 3 * (prm.max_it_trace + 4), g);
+  KCHK();
+  const int its = pcg(op, g, lout);
+  pcg_iters.push_back(its);
+  total_pcg += its;
+  ++n_trace_solves;
+  const long nb = (hm.nc + kBlock - 1) / kBlock;
+  launch_backsub(k, st, dm, dt, c, prm.tau, op.Pinv, Fw, Fpsi, lout, U, pout, part);
+  launch_finish_mean(st, part, (int)nb, area, scal + 3 * (prm.max_it_trace + 4) + 1);
+  launch_shift_mean(k, st, dm, scal + 3 * (prm.max_it_trace + 4) + 1, pout, lout);
+  KCHK();
+  sync();
+  t_trace += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// BiCGStab on the mass-scaled Step I operator  x - (adt/det) f_im(x) = b
+int hdg_ctx::bicgstab(double adt, const double* b, double* x) {
+  const long n = nQ;
+  const int maxit = prm.max_it_velocity;
+  launch_fill(st, n, 0.0, x);
+  launch_copy(st, n, b, br);
+  launch_copy(st, n, b, brh);
+  launch_dot(st, n, br, nullptr, part);
+  launch_finish(st, part, kRedBlocks, bsc);
+  launch_copy(st, 1, bsc, bsc + 4);
+  const double bnorm = std::sqrt(read_scalar(bsc));
+  if (bnorm == 0.0) return 0;
+  for (int it = 0; it < maxit; ++it) {
+    launch_bicg_p(st, n, bsc, it, br, bv, bp);
+    launch_apply(k, st, 0, dm, dt, adv, prm.alpha, adt, bp, nullptr, nullptr, nullptr, bv);
+    launch_dot(st, n, brh, bv, part);
+    launch_finish(st, part, kRedBlocks, bsc + 8 * it + 1);
+    launch_bicg_s(st, n, bsc, it, br, bv, bs);
+    launch_apply(k, st, 0, dm, dt, adv, prm.alpha, adt, bs, nullptr, nullptr, nullptr, bt);
+    launch_dot2(st, n, bt, bs, bt, part2);
+    launch_finish2(st, part2, bsc + 8 * it + 2);
+    launch_bicg_xr(st, n, bsc, it, bp, bs, bt, x, br, brh, part2);
+    launch_finish2(st, part2, bsc + 8 * (it + 1));
+    KCHK();
+    HIPCHK(hipMemcpyAsync(h_pinned, bsc + 8 * (it + 1), 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+    sync();
+    // finish2 wrote rhat.r into [0] and r.r into [1]; keep r.r in slot 4 as documented
+    const double rr = h_pinned[1];
+    launch_copy(st, 1, bsc + 8 * (it + 1) + 1, bsc + 8 * (it + 1) + 4);
+    const double res = std::sqrt(rr);
+    if (!(res == res)) throw SolverBreakdown("BiCGStab breakdown (NaN residual); the result is invalid");
+    if (res <= prm.rtol_velocity * bnorm) return it + 1;
+  }
+  not_converged = true;
+  return maxit;
+}
+
+void hdg_ctx::reconstruct(const double* Qin, double* pout, double* lout) {
+  launch_recon_rhs(k, st, dm, dt, Qin, fpsi);
+  KCHK();
+  solve_trace(1.0, nullptr, fpsi, nullptr, Ut, pout, lout);
+}
+
+// Algorithm 2 for one stage: (Q, p, lam) hold the iterate on entry and exit
+void hdg_ctx::richardson(double adt, const double* r, double* Qv, double* pv, double* lv) {
+  for (int it = 0; it < prm.n_richardson; ++it) {
+    auto t0 = std::chrono::steady_clock::now();
+    launch_apply(k, st, 1, dm, dt, adv, prm.alpha, adt, Qv, r, pv, lv, dr);  // delta r / det
+    KCHK();
+    const int its = bicgstab(adt, dr, Qbar);  // Step I
+    bicg_iters.push_back(its);
+    total_bicg += its;
+    ++n_velocity_solves;
+    launch_div(k, st, dm, dt, Qbar, -1.0 / adt, fpsi);  // Step II data
+    KCHK();
+    sync();
+    t_velocity += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    solve_trace(1.0, nullptr, fpsi, nullptr, dQ, dp, dl);
+    // Step III
+    launch_axpby(st, nQ, 1.0, Qbar, 1.0, Qv);
+    launch_axpby(st, nQ, adt, dQ, 1.0, Qv);
+    launch_axpby(st, nP, 1.0, dp, 1.0, pv);
+    launch_axpby(st, nT, 1.0, dl, 1.0, lv);
+    KCHK();
+  }
+}
+
+// Algorithm 1
+void hdg_ctx::step(double dtv) {
+  const Tableau tab = make_tableau(prm.imex);
+  const int s = tab.s;
+  double* MQn = stMQ[0];
+  launch_mass(k, st, dm, 1.0, Q, MQn);
+  launch_copy(st, nQ, Q, stQ[0]);
+  launch_copy(st, nP, p, stP[0]);
+  launch_copy(st, nT, lam, stL[0]);
+  for (int i = 1; i < s; ++i) {
+    // stage residual r_i (forcing is zero)
+    launch_copy(st, nQ, MQn, stR[i]);
+    for (int j = 1; j < i; ++j) {
+      const double w = tab.Aim[i][j] / tab.Aim[j][j];
+      launch_axpby(st, nQ, w, stMQ[j], 1.0, stR[i]);
+      launch_axpby(st, nQ, -w, stR[j], 1.0, stR[i]);
+    }
+    launch_bdm(k, st, dm, dt, stQ[i - 1], Qs);
+    launch_prep_adv(k, st, dm, dt, Qs, prm.delta_up, adv);
+    launch_copy(st, nQ, stQ[i - 1], stQ[i]);
+    launch_copy(st, nP, stP[i - 1], stP[i]);
+    launch_copy(st, nT, stL[i - 1], stL[i]);
+    KCHK();
+    richardson(tab.Aim[i][i] * dtv, stR[i], stQ[i], stP[i], stL[i]);
+    launch_mass(k, st, dm, 1.0, stQ[i], stMQ[i]);
+  }
+  // final residual and projection
+  double* rn = dr;
+  launch_copy(st, nQ, MQn, rn);
+  for (int i = 1; i < s; ++i) {
+    const double w = tab.bim[i] / tab.Aim[i][i];
+    launch_axpby(st, nQ, w, stMQ[i], 1.0, rn);
+    launch_axpby(st, nQ, -w, stR[i], 1.0, rn);
+  }
+  KCHK();
+  solve_trace(dtv * tab.bim[s - 1], rn, nullptr, nullptr, Q, dp, dl);
+  if (prm.pressure_update == HDG_PRESSURE_RECONSTRUCT) {
+    reconstruct(Q, p, lam);
+  } else {
+    launch_copy(st, nP, stP[s - 1], p);
+    launch_copy(st, nT, stL[s - 1], lam);
+    launch_axpby(st, nP, 1.0, dp, 1.0, p);
+    launch_axpby(st, nT, 1.0, dl, 1.0, lam);  // both terms have int p = 0 already
+    KCHK();
+  }
+  sync();
+}
+
+// ======================================================================= ABI
+#define API_BEGIN try {
+#define API_END(ctxp)                                                   \
+  }                                                                     \
+  catch (const hdg::OomError& e) { (ctxp)->err = e.what(); return HDG_ERR_OUT_OF_MEMORY; } \
+  catch (const hdg::ArgError& e) { (ctxp)->err = e.what(); return HDG_ERR_INVALID_ARG; }   \
+  catch (const hdg::SolverBreakdown& e) { (ctxp)->err = e.what(); return HDG_ERR_NOT_CONVERGED; } \
+  catch (const std::exception& e) { (ctxp)->err = e.what(); return HDG_ERR_DEVICE; }       \
+  return (ctxp)->not_converged ? HDG_ERR_NOT_CONVERGED : HDG_OK;
+
+extern "C" {
+
+void hdg_default_params(hdg_params* p) {
+  if (!p) return;
+  p->degree = 1;
+  p->tau = 1.0;
+  p->alpha = 1.0;
+  p->delta_up = 1.0;
+  p->imex = HDG_ARS222;
+  p->n_richardson = 3;
+  p->trace_solver = HDG_TRACE_MG_PCG;
+  p->rtol_trace = 1e-12;
+  p->rtol_velocity = 1e-12;
+  p->max_it_trace = 5000;
+  p->max_it_velocity = 20000;
+  p->pressure_update = HDG_PRESSURE_RECONSTRUCT;
+}
+
+int hdg_create(int64_t nv, const double* coords, int64_t nc, const int32_t* cells, const hdg_params* prm,
+               void* stream, hdg_ctx** out) {
+  if (!out || !prm) { g_create_error = "null argument"; return HDG_ERR_INVALID_ARG; }
+  *out = nullptr;
+  if (prm->degree < 1 || prm->degree > kMaxDegree) {
+    g_create_error = "degree must be in 1..4";
+    return HDG_ERR_UNSUPPORTED;
+  }
+  if (prm->tau <= 0 || prm->alpha < 0 || prm->delta_up < 0 || prm->n_richardson < 1 || prm->max_it_trace < 1 ||
+      prm->max_it_velocity < 1 || !(prm->rtol_trace > 0) || !(prm->rtol_velocity > 0) || prm->imex < 0 ||
+      prm->imex > 2 || prm->trace_solver < 0 || prm->trace_solver > 1 || prm->pressure_update < 0 ||
+      prm->pressure_update > 1) {
+    g_create_error = "invalid parameter";
+    return HDG_ERR_INVALID_ARG;
+  }
+  auto ctx = std::make_unique<hdg_ctx>();
+  ctx->prm = *prm;
+  ctx->k = prm->degree;
+  ctx->st = (hipStream_t)stream;
+  std::string e = build_mesh(nv, coords, nc, cells, ctx->hm);
+  if (!e.empty()) { g_create_error = e; return HDG_ERR_INVALID_ARG; }
+  try {
+    build_reference(ctx->k, ctx->rt);
+    ctx->setup();
+  } catch (const OomError& ex) {
+    g_create_error = ex.what();
+    hdg_destroy(ctx.release());
+    return HDG_ERR_OUT_OF_MEMORY;
+  } catch (const std::exception& ex) {
+    g_create_error = ex.what();
+    hdg_destroy(ctx.release());
+    return HDG_ERR_DEVICE;
+  }
+  *out = ctx.release();
+  return HDG_OK;
+}
+
+void hdg_destroy(hdg_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->st);
+  for (void* p : ctx->allocs) (void)hipFree(p);
+  if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
+  delete ctx;
+}
+
+const char* hdg_last_error(const hdg_ctx* ctx) {
+  if (!ctx) return g_create_error.c_str();
+  return ctx->err.c_str();
+}
+
+int hdg_sizes(const hdg_ctx* ctx, int64_t* out, int n) {
+  if (!ctx || !out || n < 0 || n > 8) return HDG_ERR_INVALID_ARG;
+  const int64_t v[8] = {ctx->hm.nc, ctx->hm.nF, ctx->nQ, ctx->nP, ctx->nT, ctx->nqc, ctx->hm.nv, ctx->k};
+  for (int i = 0; i < n; ++i) out[i] = v[i];
+  return HDG_OK;
+}
+
+int hdg_cell_points(const hdg_ctx* ctx, double* xy) {
+  if (!ctx || !xy) return HDG_ERR_INVALID_ARG;
+  const auto& m = ctx->hm;
+  const auto& t = ctx->rt;
+  for (int64_t e = 0; e < m.nc; ++e) {
+    const double* v0 = &m.coords[2 * m.cells[3 * e]];
+    const double* v1 = &m.coords[2 * m.cells[3 * e + 1]];
+    const double* v2 = &m.coords[2 * m.cells[3 * e + 2]];
+    for (int q = 0; q < t.nqc; ++q) {
+      const double a = t.cq_xi[q], b = t.cq_eta[q];
+      xy[(e * t.nqc + q) * 2] = v0[0] + (v1[0] - v0[0]) * a + (v2[0] - v0[0]) * b;
+      xy[(e * t.nqc + q) * 2 + 1] = v0[1] + (v1[1] - v0[1]) * a + (v2[1] - v0[1]) * b;
+    }
+  }
+  return HDG_OK;
+}
+
+int hdg_set_velocity_from_points(hdg_ctx* ctx, const double* qvals) {
+  if (!ctx || !qvals) return HDG_ERR_INVALID_ARG;
+  ctx->not_converged = false;
+  API_BEGIN
+  launch_project(ctx->k, ctx->st, ctx->dm, ctx->dt, qvals, ctx->Q);
+  KCHK();
+  ctx->reconstruct(ctx->Q, ctx->p, ctx->lam);
+  ctx->have_state = true;
+  API_END(ctx)
+}
+
+int hdg_set_state(hdg_ctx* ctx, const double* Qv, const double* pv, const double* lv) {
+  if (!ctx || !Qv || !pv || !lv) return HDG_ERR_INVALID_ARG;
+  ctx->not_converged = false;
+  API_BEGIN
+  launch_copy(ctx->st, ctx->nQ, Qv, ctx->Q);
+  launch_copy(ctx->st, ctx->nP, pv, ctx->p);
+  launch_copy(ctx->st, ctx->nT, lv, ctx->lam);
+  KCHK();
+  ctx->sync();
+  ctx->have_state = true;
+  API_END(ctx)
+}
+
+int hdg_get_state(const hdg_ctx* cctx, double* Qv, double* pv, double* lv) {
+  hdg_ctx* ctx = const_cast<hdg_ctx*>(cctx);
+  if (!ctx) return HDG_ERR_INVALID_ARG;
+  if (!ctx->have_state) { ctx->err = "no state set"; return HDG_ERR_BAD_STATE; }
+  ctx->not_converged = false;
+  API_BEGIN
+  if (Qv) launch_copy(ctx->st, ctx->nQ, ctx->Q, Qv);
+  if (pv) launch_copy(ctx->st, ctx->nP, ctx->p, pv);
+  if (lv) launch_copy(ctx->st, ctx->nT, ctx->lam, lv);
+  KCHK();
+  ctx->sync();
+  API_END(ctx)
+}
+
+int hdg_advance(hdg_ctx* ctx, double dtv, int nsteps) {
+  if (!ctx || !(dtv > 0) || nsteps < 0) return HDG_ERR_INVALID_ARG;
+  if (!ctx->have_state) { ctx->err = "no state set"; return HDG_ERR_BAD_STATE; }
+  ctx->not_converged = false;
+  API_BEGIN
+  for (int n = 0; n < nsteps; ++n) ctx->step(dtv);
+  API_END(ctx)
+}
+
+int hdg_solve_trace(hdg_ctx* ctx, double c, const double* Fw, const double* Fpsi, const double* Fmu, double* U,
+                    double* pv, double* lv) {
+  if (!ctx || !(c > 0) || !U || !pv || !lv) return HDG_ERR_INVALID_ARG;
+  ctx->not_converged = false;
+  API_BEGIN
+  ctx->solve_trace(c, Fw, Fpsi, Fmu, U, pv, lv);
+  API_END(ctx)
+}
+
+int hdg_trace_matvec(hdg_ctx* ctx, double c, const double* x, double* y) {
+  if (!ctx || !(c > 0) || !x || !y) return HDG_ERR_INVALID_ARG;
+  ctx->not_converged = false;
+  API_BEGIN
+  TraceOp& op = ctx->trace_op(c);
+  launch_spmv(ctx->k, ctx->st, (int)ctx->hm.nF, op.vals, op.cols, x, y);
+  KCHK();
+  ctx->sync();
+  API_END(ctx)
+}
+
+int hdg_bdm_project(hdg_ctx* ctx, const double* Qv, double* Qsv) {
+  if (!ctx || !Qv || !Qsv) return HDG_ERR_INVALID_ARG;
+  ctx->not_converged = false;
+  API_BEGIN
+  launch_bdm(ctx->k, ctx->st, ctx->dm, ctx->dt, Qv, Qsv);
+  KCHK();
+  ctx->sync();
+  API_END(ctx)
+}
+
+int hdg_weak_divergence(hdg_ctx* ctx, const double* F, double* out) {
+  if (!ctx || !F || !out) return HDG_ERR_INVALID_ARG;
+  ctx->not_converged = false;
+  API_BEGIN
+  launch_div(ctx->k, ctx->st, ctx->dm, ctx->dt, F, 1.0, out);
+  KCHK();
+  ctx->sync();
+  API_END(ctx)
+}
+
+int hdg_momentum_residual(hdg_ctx* ctx, double adt, const double* r, const double* Qsv, const double* Qv,
+                          const double* pv, const double* lv, double* out) {
+  if (!ctx || !r || !Qsv || !Qv || !pv || !lv || !out) return HDG_ERR_INVALID_ARG;
+  ctx->not_converged = false;
+  API_BEGIN
+  launch_prep_adv(ctx->k, ctx->st, ctx->dm, ctx->dt, Qsv, ctx->prm.delta_up, ctx->adv);
+  launch_apply(ctx->k, ctx->st, 2, ctx->dm, ctx->dt, ctx->adv, ctx->prm.alpha, adt, Qv, r, pv, lv, out);
+  KCHK();
+  ctx->sync();
+  API_END(ctx)
+}
+
+int hdg_tentative_velocity(hdg_ctx* ctx, double adt, const double* Qsv, const double* rhs, double* Qbar) {
+  if (!ctx || !Qsv || !rhs || !Qbar) return HDG_ERR_INVALID_ARG;
+  ctx->not_converged = false;
+  API_BEGIN
+  launch_prep_adv(ctx->k, ctx->st, ctx->dm, ctx->dt, Qsv, ctx->prm.delta_up, ctx->adv);
+  // mass-scaled right-hand side rhs / det: the residual kernel with Q = p = lam = 0
+  {
+    launch_fill(ctx->st, ctx->nQ, 0.0, ctx->Ut);
+    launch_fill(ctx->st, ctx->nP, 0.0, ctx->dp);
+    launch_fill(ctx->st, ctx->nT, 0.0, ctx->dl);
+    launch_apply(ctx->k, ctx->st, 1, ctx->dm, ctx->dt, ctx->adv, ctx->prm.alpha, adt, ctx->Ut, rhs, ctx->dp,
+                 ctx->dl, ctx->dr);
+  }
+  KCHK();
+  int its = ctx->bicgstab(adt, ctx->dr, Qbar);
+  ctx->bicg_iters.push_back(its);
+  ctx->sync();
+  API_END(ctx)
+}
+
+int hdg_reconstruct_pressure(hdg_ctx* ctx, const double* Qv, double* pv, double* lv) {
+  if (!ctx || !Qv || !pv || !lv) return HDG_ERR_INVALID_ARG;
+  ctx->not_converged = false;
+  API_BEGIN
+  ctx->reconstruct(Qv, pv, lv);
+  API_END(ctx)
+}
+
+int hdg_get_info(const hdg_ctx* ctx, char* buf, size_t cap) {
+  if (!ctx || !buf || cap == 0) return HDG_ERR_INVALID_ARG;
+  auto last = [](const std::vector<int>& v, size_t n) {
+    std::string s = "[";
+    size_t st = v.size() > n ? v.size() - n : 0;
+    for (size_t i = st; i < v.size(); ++i) s += (i > st ? "," : "") + std::to_string(v[i]);
+    return s + "]";
+  };
+  std::string s = "{\"ncells\":" + std::to_string(ctx->hm.nc) + ",\"nfacets\":" + std::to_string(ctx->hm.nF) +
+                  ",\"degree\":" + std::to_string(ctx->k) + ",\"n_trace_dofs\":" + std::to_string(ctx->nT) +
+                  ",\"trace_solves\":" + std::to_string(ctx->n_trace_solves) +
+                  ",\"pcg_iterations_total\":" + std::to_string(ctx->total_pcg) +
+                  ",\"velocity_solves\":" + std::to_string(ctx->n_velocity_solves) +
+                  ",\"bicgstab_iterations_total\":" + std::to_string(ctx->total_bicg) +
+                  ",\"pcg_iterations_last\":" + last(ctx->pcg_iters, 16) +
+                  ",\"bicgstab_iterations_last\":" + last(ctx->bicg_iters, 16) +
+                  ",\"seconds_trace\":" + std::to_string(ctx->t_trace) +
+                  ",\"seconds_velocity\":" + std::to_string(ctx->t_velocity) + "}";
+  std::snprintf(buf, cap, "%s", s.c_str());
+  return s.size() < cap ? HDG_OK : HDG_ERR_INVALID_ARG;
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+// Device-side data views and kernel launchers of the HDG-IMEX library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace hdg {
+
+// per-cell geometry fields, stored field-major [field][cell]
+enum DGeo { D_DET = 0, D_IJ00, D_IJ01, D_IJ10, D_IJ11, D_NX0, D_NY0, D_NX1, D_NY1, D_NX2, D_NY2,
+            D_H0, D_H1, D_H2, D_J00, D_J01, D_J10, D_J11, kDGeo };
+
+struct DMesh {
+  int nc, nF;
+  const double* geo;       // [kDGeo][nc]
+  const int* cf_facet;     // [3][nc]
+  const int* cf_nb;        // [3][nc]
+  const int* cf_nbf;       // [3][nc]
+  const int* cf_flip;      // [3][nc]
+  const int* fc_cell;      // [2][nF]
+  const int* fc_f;         // [2][nF]
+};
+
+struct DTab {
+  const double *Bu, *Gux, *Guy, *Bp, *Gpx, *Gpy, *cw;
+  const double *FBu, *FGux, *FGuy, *FBp, *fw, *MU, *NUB;
+  const double *Dx, *Dy, *Rx, *Ry, *Chat, *That, *Ehat, *CC, *KDD, *CD, *BDMinv, *NED;
+};
+
+struct DCsr {
+  int n;
+  const int* ptr;
+  const int* idx;
+  const double* val;
+};
+
+constexpr int kBlock = 256;
+constexpr int kRedBlocks = 1024;  // fixed grid for deterministic reductions
+
+// launchers (k = degree); all enqueue on `st`
+void launch_condense(int k, hipStream_t st, DMesh m, DTab t, double c, double tau, double* Pinv, double* SK);
+void launch_assemble(int k, hipStream_t st, DMesh m, const double* SK, double* vals, int* cols, double* Dinv);
+void launch_spmv(int k, hipStream_t st, int nF, const double* vals, const int* cols, const double* x, double* y);
+void launch_residual(int k, hipStream_t st, int nF, const double* vals, const int* cols, const double* b,
+                     const double* x, double* r);
+void launch_jacobi_sweep(int k, hipStream_t st, int nF, const double* vals, const int* cols, const double* Dinv,
+                         double omega, const double* b, const double* xin, double* xout);
+void launch_blockdiag(int k, hipStream_t st, int nF, const double* Dinv, const double* x, double* y);
+void launch_rhs_condense(int k, hipStream_t st, DMesh m, DTab t, double c, double tau, const double* Pinv,
+                         const double* Fw, const double* Fpsi, double* ycell);
+void launch_gather_rhs(int k, hipStream_t st, DMesh m, const double* ycell, const double* Fmu, double* g);
+void launch_backsub(int k, hipStream_t st, DMesh m, DTab t, double c, double tau, const double* Pinv,
+                    const double* Fw, const double* Fpsi, const double* lam, double* U, double* p, double* part);
+void launch_prep_adv(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, double* adv);
+// mode 0: out = x - (adt/det) f_im(x)          (mass-scaled Step I operator)
+// mode 1: out = (r - det x + adt (f_im(x) + g(p, lam))) / det  (mass-scaled residual)
+// mode 2: out = r - det x + adt (f_im(x) + g(p, lam))           (residual, dual vector)
+void launch_apply(int k, hipStream_t st, int mode, DMesh m, DTab t, const double* adv, double alpha, double adt,
+                  const double* x, const double* r, const double* p, const double* lam, double* out);
+void launch_div(int k, hipStream_t st, DMesh m, DTab t, const double* F, double scale, double* out);
+void launch_bdm(int k, hipStream_t st, DMesh m, DTab t, const double* Q, double* Qs);
+void launch_recon_rhs(int k, hipStream_t st, DMesh m, DTab t, const double* Q, double* out);
+void launch_project(int k, hipStream_t st, DMesh m, DTab t, const double* vals, double* Q);
+void launch_mass(int k, hipStream_t st, DMesh m, double s, const double* x, double* y);
+void launch_shift_mean(int k, hipStream_t st, DMesh m, const double* mean, double* p, double* lam);
+
+void launch_csr_spmv(hipStream_t st, DCsr A, const double* x, double* y, double beta);
+void launch_csr_jacobi(hipStream_t st, DCsr A, const double* dinv, double omega, const double* b,
+                       const double* xin, double* xout);
+void launch_dense_mv(hipStream_t st, int n, const double* M, const double* x, double* y);
+
+// reductions: partial sums into part[kRedBlocks], then out[0] = sum
+void launch_dot(hipStream_t st, long n, const double* a, const double* b, double* part);
+void launch_dot_sub(hipStream_t st, long n, int stride, int off, const double* a, double* part);
+void launch_finish(hipStream_t st, const double* part, int nparts, double* out);
+void launch_finish_mean(hipStream_t st, const double* part, int nparts, double area, double* out);
+
+// vectors: y = a*x + b*y with host scalars
+void launch_axpby(hipStream_t st, long n, double a, const double* x, double b, double* y);
+void launch_copy(hipStream_t st, long n, const double* x, double* y);
+void launch_fill(hipStream_t st, long n, double v, double* y);
+void launch_project_const(hipStream_t st, int nF, int nf, const double* sum, double* g);
+
+// Krylov helpers with device scalars
+void launch_pcg_update(hipStream_t st, long n, const double* rz, const double* pq, const double* p, const double* q,
+                       double* x, double* r, double* part_rr);
+void launch_pcg_direction(hipStream_t st, long n, const double* rz_new, const double* rz_old, const double* z, double* p);
+void launch_bicg_p(hipStream_t st, long n, const double* sc, int it, const double* r, const double* v, double* p);
+void launch_bicg_s(hipStream_t st, long n, const double* sc, int it, const double* r, const double* v, double* s);
+void launch_bicg_xr(hipStream_t st, long n, const double* sc, int it, const double* p, const double* s,
+                    const double* t, double* x, double* r, const double* rhat, double* part2);
+void launch_dot2(hipStream_t st, long n, const double* a, const double* b, const double* c, double* part2);
+void launch_finish2(hipStream_t st, const double* part2, double* out2);
+
+}  // namespace hdg

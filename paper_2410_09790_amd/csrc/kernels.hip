@@ -1,0 +1,1158 @@
+// gfx950 kernels of the HDG-IMEX library.
+//
+// One thread per cell (or per facet) for the element kernels: every wave
+// walks the same reference-table entries at the same time, so table reads are
+// uniform (broadcast) and per-cell data are laid out field-major [field][cell]
+// so that a wave's loads of one field are contiguous.  Templated on the degree
+// k so that every loop over basis functions and quadrature points unrolls.
+// All reductions use a fixed grid and a fixed summation order, so results are
+// bitwise reproducible run to run.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace hdg {
+
+template <int K>
+struct Dims {
+  static constexpr int NS = (K + 2) * (K + 3) / 2;
+  static constexpr int NP = (K + 1) * (K + 2) / 2;
+  static constexpr int NF = K + 1;
+  static constexpr int NU = 2 * NS;
+  static constexpr int NLAM = 3 * NF;
+  static constexpr int NQ1 = (3 * K + 4) / 2;
+  static constexpr int NQC = NQ1 * NQ1;
+  static constexpr int NQF = (3 * K + 5) / 2;
+  static constexpr int NNED = K * (K + 2);
+  static constexpr int NM = K + 2;
+};
+
+struct CellGeo {
+  double det, ij[2][2], J[2][2], n[3][2], h[3];
+};
+
+__device__ __forceinline__ CellGeo load_geo(const DMesh& m, int e) {
+  CellGeo g;
+  const double* G = m.geo;
+  const int nc = m.nc;
+  g.det = G[D_DET * nc + e];
+  g.ij[0][0] = G[D_IJ00 * nc + e]; g.ij[0][1] = G[D_IJ01 * nc + e];
+  g.ij[1][0] = G[D_IJ10 * nc + e]; g.ij[1][1] = G[D_IJ11 * nc + e];
+  g.J[0][0] = G[D_J00 * nc + e]; g.J[0][1] = G[D_J01 * nc + e];
+  g.J[1][0] = G[D_J10 * nc + e]; g.J[1][1] = G[D_J11 * nc + e];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    g.n[f][0] = G[(D_NX0 + 2 * f) * nc + e];
+    g.n[f][1] = G[(D_NY0 + 2 * f) * nc + e];
+    g.h[f] = G[(D_H0 + f) * nc + e];
+  }
+  return g;
+}
+
+__device__ __forceinline__ double sgn(int flip, int m) { return (flip && (m & 1)) ? -1.0 : 1.0; }
+
+__device__ __forceinline__ double block_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  __shared__ double s[kBlock / 64];
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) s[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) r += s[i];
+  }
+  return r;
+}
+
+static inline int nblocks(long n) { return (int)((n + kBlock - 1) / kBlock); }
+
+// ===================================================================== a1
+// Local condensation.  With the orthonormal basis the velocity mass matrix is
+// det*I, so the cell problem [[M, -c D^T], [D, T]] reduces to the pressure
+// Schur complement P = T + (c/det) D D^T, and the trace operator of the cell
+// is S_K = F + (c/det) C C^T - G P^{-1} G^T with G = E + (c/det) C D^T.
+// D, C, E, T are linear combinations of reference matrices with geometric
+// weights, and so are the products D D^T, C C^T, C D^T.
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_condense(DMesh m, DTab t, double c, double tau, double* __restrict__ Pinv,
+                                                     double* __restrict__ SK) {
+  using D = Dims<K>;
+  constexpr int NP = D::NP, NF = D::NF, NL = D::NLAM;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m.nc) return;
+  const CellGeo g = load_geo(m, e);
+  int flip[3];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) flip[f] = m.cf_flip[f * m.nc + e];
+  double Gm[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) Gm[a][b] = g.ij[a][0] * g.ij[b][0] + g.ij[a][1] * g.ij[b][1];
+  double L[NP][NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i)
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      double v = tau * (g.h[0] * t.That[(0 * NP + i) * NP + j] + g.h[1] * t.That[(1 * NP + i) * NP + j] +
+                        g.h[2] * t.That[(2 * NP + i) * NP + j]);
+      double dd = 0.0;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) dd += Gm[a][b] * t.KDD[((a * 2 + b) * NP + i) * NP + j];
+      L[i][j] = v + c * g.det * dd;
+    }
+  // Cholesky (lower), in place
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    double d = L[j][j];
+#pragma unroll
+    for (int q = 0; q < j; ++q) d -= L[j][q] * L[j][q];
+    d = sqrt(d);
+    L[j][j] = d;
+    double inv = 1.0 / d;
+#pragma unroll
+    for (int i = j + 1; i < NP; ++i) {
+      double v = L[i][j];
+#pragma unroll
+      for (int q = 0; q < j; ++q) v -= L[i][q] * L[j][q];
+      L[i][j] = v * inv;
+    }
+  }
+  // Linv (lower) by forward substitution, stored in the upper triangle of a new array
+  double Li[NP][NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      if (i < j) { Li[i][j] = 0.0; continue; }
+      double v = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+      for (int q = j; q < i; ++q) v -= L[i][q] * Li[q][j];
+      Li[i][j] = v / L[i][i];
+    }
+  }
+  // P^{-1} = Linv^T Linv
+#pragma unroll
+  for (int i = 0; i < NP; ++i)
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      double v = 0.0;
+#pragma unroll
+      for (int q = (i > j ? i : j); q < NP; ++q) v += Li[q][i] * Li[q][j];
+      Pinv[(i * NP + j) * (long)m.nc + e] = v;
+    }
+  // W = Linv G^T  (NP x NL)
+  double W[NP][NL];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    double nu[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) nu[a] = g.n[f][0] * g.ij[a][0] + g.n[f][1] * g.ij[a][1];
+#pragma unroll
+    for (int mm = 0; mm < NF; ++mm) {
+      const double sc = g.h[f] * sgn(flip[f], mm);
+      double Grow[NP];
+#pragma unroll
+      for (int j = 0; j < NP; ++j)
+        Grow[j] = sc * (tau * t.Ehat[(f * NF + mm) * NP + j] + c * (nu[0] * t.CD[((f * 2 + 0) * NF + mm) * NP + j] +
+                                                                    nu[1] * t.CD[((f * 2 + 1) * NF + mm) * NP + j]));
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j <= i; ++j) v += Li[i][j] * Grow[j];
+        W[i][f * NF + mm] = v;
+      }
+    }
+  }
+  const double cod = c / g.det;
+#pragma unroll
+  for (int f = 0; f < 3; ++f)
+#pragma unroll
+    for (int mm = 0; mm < NF; ++mm)
+#pragma unroll
+      for (int gg = 0; gg < 3; ++gg)
+#pragma unroll
+        for (int l = 0; l < NF; ++l) {
+          const int r = f * NF + mm, s = gg * NF + l;
+          double v = (r == s) ? tau * g.h[f] : 0.0;
+          const double nn = g.n[f][0] * g.n[gg][0] + g.n[f][1] * g.n[gg][1];
+          v += cod * g.h[f] * g.h[gg] * sgn(flip[f], mm) * sgn(flip[gg], l) * nn * t.CC[((f * 3 + gg) * NF + mm) * NF + l];
+          double ww = 0.0;
+#pragma unroll
+          for (int i = 0; i < NP; ++i) ww += W[i][r] * W[i][s];
+          SK[(r * NL + s) * (long)m.nc + e] = v - ww;
+        }
+}
+
+// Facet-block ELL assembly of S = sum_K S_K, one thread per facet (no atomics).
+// Slot 0: the facet itself; slots 1-2: the other facets of K+; slots 3-4: of K-.
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_assemble(DMesh m, const double* __restrict__ SK, double* __restrict__ vals,
+                                                     int* __restrict__ cols, double* __restrict__ Dinv) {
+  using D = Dims<K>;
+  constexpr int NF = D::NF, NL = D::NLAM;
+  const int F = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nF = m.nF;
+  if (F >= nF) return;
+  const long nc = m.nc;
+  const int Kp = m.fc_cell[F], fp = m.fc_f[F], Km = m.fc_cell[nF + F], fm = m.fc_f[nF + F];
+  auto put = [&](int slot, int col, int cell, int fr, int fcol, bool add) {
+    if (!add) cols[slot * nF + F] = col;
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+#pragma unroll
+      for (int j = 0; j < NF; ++j) {
+        double v = cell >= 0 ? SK[((fr * NF + i) * NL + fcol * NF + j) * nc + cell] : 0.0;
+        long idx = ((long)(slot * NF + i) * NF + j) * nF + F;
+        vals[idx] = add ? vals[idx] + v : v;
+      }
+  };
+  put(0, F, Kp, fp, fp, false);
+  if (Km >= 0) put(0, F, Km, fm, fm, true);
+#pragma unroll
+  for (int o = 1; o <= 2; ++o) {
+    const int gq = (fp + o) % 3;
+    put(o, m.cf_facet[gq * nc + Kp], Kp, fp, gq, false);
+  }
+#pragma unroll
+  for (int o = 1; o <= 2; ++o) {
+    if (Km >= 0) {
+      const int gq = (fm + o) % 3;
+      put(2 + o, m.cf_facet[gq * nc + Km], Km, fm, gq, false);
+    } else {
+      put(2 + o, F, -1, 0, 0, false);
+    }
+  }
+  // inverse of the diagonal block (SPD), Gauss-Jordan without pivoting
+  double A[NF][NF], B[NF][NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i)
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+      A[i][j] = vals[((long)(0 * NF + i) * NF + j) * nF + F];
+      B[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+#pragma unroll
+  for (int cidx = 0; cidx < NF; ++cidx) {
+    double d = 1.0 / A[cidx][cidx];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) { A[cidx][j] *= d; B[cidx][j] *= d; }
+#pragma unroll
+    for (int r = 0; r < NF; ++r) {
+      if (r == cidx) continue;
+      double f = A[r][cidx];
+#pragma unroll
+      for (int j = 0; j < NF; ++j) { A[r][j] -= f * A[cidx][j]; B[r][j] -= f * B[cidx][j]; }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NF; ++i)
+#pragma unroll
+    for (int j = 0; j < NF; ++j) Dinv[(long)(i * NF + j) * nF + F] = B[i][j];
+}
+
+// ===================================================================== a8
+// Trace SpMV, one thread per (facet, row): the five blocks of a facet row are
+// stored slot-major, then row, then column, with the facet index fastest.
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_spmv(int nF, const double* __restrict__ vals, const int* __restrict__ cols,
+                                                 const double* __restrict__ x, const double* __restrict__ b,
+                                                 double* __restrict__ y) {
+  constexpr int NF = K + 1;
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (long)nF * NF) return;
+  const int F = (int)(tid % nF);
+  const int i = (int)(tid / nF);
+  double acc = 0.0;
+#pragma unroll
+  for (int s = 0; s < 5; ++s) {
+    const int col = cols[s * nF + F];
+    const double* xc = x + (long)col * NF;
+#pragma unroll
+    for (int j = 0; j < NF; ++j) acc += vals[((long)(s * NF + i) * NF + j) * nF + F] * xc[j];
+  }
+  if (b) y[(long)F * NF + i] = b[(long)F * NF + i] - acc;
+  else y[(long)F * NF + i] = acc;
+}
+
+// damped block-Jacobi sweep: xout = xin + omega Dinv (b - S xin); xin == nullptr means xin = 0
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_jacobi(int nF, const double* __restrict__ vals, const int* __restrict__ cols,
+                                                   const double* __restrict__ Dinv, double omega,
+                                                   const double* __restrict__ b, const double* __restrict__ xin,
+                                                   double* __restrict__ xout) {
+  constexpr int NF = K + 1;
+  const int F = blockIdx.x * blockDim.x + threadIdx.x;
+  if (F >= nF) return;
+  double r[NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) r[i] = b[(long)F * NF + i];
+  if (xin) {
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+      const int col = cols[s * nF + F];
+      double xc[NF];
+#pragma unroll
+      for (int j = 0; j < NF; ++j) xc[j] = xin[(long)col * NF + j];
+#pragma unroll
+      for (int i = 0; i < NF; ++i)
+#pragma unroll
+        for (int j = 0; j < NF; ++j) r[i] -= vals[((long)(s * NF + i) * NF + j) * nF + F] * xc[j];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NF; ++i) {
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < NF; ++j) v += Dinv[(long)(i * NF + j) * nF + F] * r[j];
+    xout[(long)F * NF + i] = (xin ? xin[(long)F * NF + i] : 0.0) + omega * v;
+  }
+}
+
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_blockdiag(int nF, const double* __restrict__ Dinv,
+                                                      const double* __restrict__ x, double* __restrict__ y) {
+  constexpr int NF = K + 1;
+  const int F = blockIdx.x * blockDim.x + threadIdx.x;
+  if (F >= nF) return;
+  double xv[NF];
+#pragma unroll
+  for (int j = 0; j < NF; ++j) xv[j] = x[(long)F * NF + j];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) {
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < NF; ++j) v += Dinv[(long)(i * NF + j) * nF + F] * xv[j];
+    y[(long)F * NF + i] = v;
+  }
+}
+
+// ================================================================ a7, a9
+// helpers shared by the condensation right-hand side and back-substitution:
+// u_a[s] = sum_c iJ[a][c] F[c][s];  (D F)_i = det sum_a sum_s Dhat_a[i][s] u_a[s]
+template <int K>
+__device__ __forceinline__ void pressure_solve(const DTab& t, const CellGeo& g, double c, const double* Pinv, long nc,
+                                               int e, const double (&fw)[Dims<K>::NU], const double (&fpsi)[Dims<K>::NP],
+                                               double (&p)[Dims<K>::NP]) {
+  using D = Dims<K>;
+  constexpr int NS = D::NS, NP = D::NP;
+  double b[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    double v = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const double u0 = g.ij[0][0] * fw[s] + g.ij[0][1] * fw[NS + s];
+      const double u1 = g.ij[1][0] * fw[s] + g.ij[1][1] * fw[NS + s];
+      v += t.Dx[i * NS + s] * u0 + t.Dy[i * NS + s] * u1;
+    }
+    b[i] = fpsi[i] - v;  // f_psi - D f_w / det
+  }
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) v += Pinv[(i * NP + j) * nc + e] * b[j];
+    p[i] = v;
+  }
+  (void)c;
+}
+
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_rhs_condense(DMesh m, DTab t, double c, double tau,
+                                                         const double* __restrict__ Pinv, const double* __restrict__ Fw,
+                                                         const double* __restrict__ Fpsi, double* __restrict__ ycell) {
+  using D = Dims<K>;
+  constexpr int NS = D::NS, NP = D::NP, NF = D::NF, NU = D::NU;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m.nc) return;
+  const long nc = m.nc;
+  const CellGeo g = load_geo(m, e);
+  double fw[NU], fpsi[NP], p[NP];
+#pragma unroll
+  for (int i = 0; i < NU; ++i) fw[i] = Fw ? Fw[(long)e * NU + i] : 0.0;
+#pragma unroll
+  for (int i = 0; i < NP; ++i) fpsi[i] = Fpsi ? Fpsi[(long)e * NP + i] : 0.0;
+  pressure_solve<K>(t, g, c, Pinv, nc, e, fw, fpsi, p);
+  const double idet = 1.0 / g.det;
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const int flip = m.cf_flip[f * nc + e];
+    double nu[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) nu[a] = g.n[f][0] * g.ij[a][0] + g.n[f][1] * g.ij[a][1];
+#pragma unroll
+    for (int mm = 0; mm < NF; ++mm) {
+      double cf = 0.0;  // (C f_w) / (h sigma)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) cf += t.Chat[(f * NF + mm) * NS + s] * (g.n[f][0] * fw[s] + g.n[f][1] * fw[NS + s]);
+      double gp = 0.0;  // (G p) / (h sigma)
+#pragma unroll
+      for (int j = 0; j < NP; ++j)
+        gp += (tau * t.Ehat[(f * NF + mm) * NP + j] +
+               c * (nu[0] * t.CD[((f * 2 + 0) * NF + mm) * NP + j] + nu[1] * t.CD[((f * 2 + 1) * NF + mm) * NP + j])) *
+              p[j];
+      ycell[(long)(f * NF + mm) * nc + e] = g.h[f] * sgn(flip, mm) * (cf * idet + gp);
+    }
+  }
+}
+
+// g_F = sum over the cells of F of their condensed contributions - F_mu
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_gather_rhs(DMesh m, const double* __restrict__ ycell,
+                                                       const double* __restrict__ Fmu, double* __restrict__ gout) {
+  constexpr int NF = K + 1;
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nF = m.nF;
+  if (tid >= (long)nF * NF) return;
+  const int F = (int)(tid / NF), mm = (int)(tid % NF);
+  const long nc = m.nc;
+  const int Kp = m.fc_cell[F], fp = m.fc_f[F], Km = m.fc_cell[nF + F], fm = m.fc_f[nF + F];
+  double v = ycell[(long)(fp * NF + mm) * nc + Kp];
+  if (Km >= 0) v += ycell[(long)(fm * NF + mm) * nc + Km];
+  if (Fmu) v -= Fmu[tid];
+  gout[tid] = v;
+}
+
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_backsub(DMesh m, DTab t, double c, double tau,
+                                                    const double* __restrict__ Pinv, const double* __restrict__ Fw,
+                                                    const double* __restrict__ Fpsi, const double* __restrict__ lam,
+                                                    double* __restrict__ U, double* __restrict__ P,
+                                                    double* __restrict__ part) {
+  using D = Dims<K>;
+  constexpr int NS = D::NS, NP = D::NP, NF = D::NF, NU = D::NU;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  double pint = 0.0;
+  if (e < m.nc) {
+    const long nc = m.nc;
+    const CellGeo g = load_geo(m, e);
+    double fw[NU], fpsi[NP], p[NP];
+#pragma unroll
+    for (int i = 0; i < NU; ++i) fw[i] = Fw ? Fw[(long)e * NU + i] : 0.0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) fpsi[i] = Fpsi ? Fpsi[(long)e * NP + i] : 0.0;
+    // f_w -= c C^T lam;  f_psi += E^T lam
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      const int F = m.cf_facet[f * nc + e];
+      const int flip = m.cf_flip[f * nc + e];
+      double l[NF];
+#pragma unroll
+      for (int mm = 0; mm < NF; ++mm) l[mm] = sgn(flip, mm) * lam[(long)F * NF + mm] * g.h[f];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        double v = 0.0;
+#pragma unroll
+        for (int mm = 0; mm < NF; ++mm) v += t.Chat[(f * NF + mm) * NS + s] * l[mm];
+        fw[s] -= c * g.n[f][0] * v;
+        fw[NS + s] -= c * g.n[f][1] * v;
+      }
+#pragma unroll
+      for (int j = 0; j < NP; ++j) {
+        double v = 0.0;
+#pragma unroll
+        for (int mm = 0; mm < NF; ++mm) v += t.Ehat[(f * NF + mm) * NP + j] * l[mm];
+        fpsi[j] += tau * v;
+      }
+    }
+    pressure_solve<K>(t, g, c, Pinv, nc, e, fw, fpsi, p);
+    const double idet = 1.0 / g.det;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      double d0 = 0.0, d1 = 0.0;  // sum_i Dhat_a[i][s] p_i
+#pragma unroll
+      for (int i = 0; i < NP; ++i) { d0 += t.Dx[i * NS + s] * p[i]; d1 += t.Dy[i * NS + s] * p[i]; }
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc)
+        U[(long)e * NU + cc * NS + s] = fw[cc * NS + s] * idet + c * (g.ij[0][cc] * d0 + g.ij[1][cc] * d1);
+    }
+#pragma unroll
+    for (int i = 0; i < NP; ++i) P[(long)e * NP + i] = p[i];
+    pint = g.det * p[0] * 0.70710678118654752440;  // int_K p = det p_0 int phi_0, int phi_0 = 1/sqrt(2)
+  }
+  if (part) {
+    double s = block_sum(pint);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+  }
+}
+
+// shift (p, lam) by -mean: p_0 -= mean/sqrt(2) (phi_0 = sqrt 2), lam_0 -= mean (mu_0 = 1)
+template <int K>
+__global__ void k_shift_mean(DMesh m, const double* __restrict__ mean, double* __restrict__ p, double* __restrict__ lam) {
+  constexpr int NP = Dims<K>::NP, NF = K + 1;
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const double mv = mean[0];
+  if (tid < m.nc) p[tid * NP] -= mv * 0.70710678118654752440;
+  if (tid < m.nF && lam) lam[tid * NF] -= mv;
+}
+
+// ================================================================ a4, a5
+// Per-stage advection data from Q*: weighted reference-direction velocities
+// at the cell points and the facet weights (1/2 qn - delta |qn|) w h at the
+// facet points (own side; qn = Q*.n is single-valued for the BDM field).
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_prep_adv(DMesh m, DTab t, const double* __restrict__ Qs, double delta_up,
+                                                     double* __restrict__ adv) {
+  using D = Dims<K>;
+  constexpr int NS = D::NS, NU = D::NU, NQC = D::NQC, NQF = D::NQF;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m.nc) return;
+  const long nc = m.nc;
+  const CellGeo g = load_geo(m, e);
+  double q[NU];
+#pragma unroll
+  for (int i = 0; i < NU; ++i) q[i] = Qs[(long)e * NU + i];
+  for (int qq = 0; qq < NQC; ++qq) {
+    double vx = 0.0, vy = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) { const double b = t.Bu[qq * NS + s]; vx += b * q[s]; vy += b * q[NS + s]; }
+    const double w = t.cw[qq] * g.det;
+    adv[(long)(0 * NQC + qq) * nc + e] = w * (g.ij[0][0] * vx + g.ij[0][1] * vy);
+    adv[(long)(1 * NQC + qq) * nc + e] = w * (g.ij[1][0] * vx + g.ij[1][1] * vy);
+  }
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const bool inner = m.cf_nb[f * nc + e] >= 0;
+    for (int qq = 0; qq < NQF; ++qq) {
+      double vx = 0.0, vy = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) { const double b = t.FBu[(f * NQF + qq) * NS + s]; vx += b * q[s]; vy += b * q[NS + s]; }
+      const double qn = vx * g.n[f][0] + vy * g.n[f][1];
+      adv[(long)(2 * NQC + f * NQF + qq) * nc + e] = inner ? t.fw[qq] * g.h[f] * (0.5 * qn - delta_up * fabs(qn)) : 0.0;
+    }
+  }
+}
+
+// f_im applied matrix-free (eq. f_impl), cell by cell; each interior facet
+// term is evaluated from both of its cells, so no scatter is needed.
+template <int K, int MODE>
+__global__ void __launch_bounds__(kBlock) k_apply(DMesh m, DTab t, const double* __restrict__ adv, double alpha,
+                                                  double adt, const double* __restrict__ x, const double* __restrict__ r,
+                                                  const double* __restrict__ pp, const double* __restrict__ lam,
+                                                  double* __restrict__ out) {
+  using D = Dims<K>;
+  constexpr int NS = D::NS, NU = D::NU, NQC = D::NQC, NQF = D::NQF, NP = D::NP, NF = D::NF;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m.nc) return;
+  const long nc = m.nc;
+  const CellGeo g = load_geo(m, e);
+  double xv[NU], y[NU];
+#pragma unroll
+  for (int i = 0; i < NU; ++i) { xv[i] = x[(long)e * NU + i]; y[i] = 0.0; }
+  // volume: -(w . (Q* . grad) x)
+  for (int qq = 0; qq < NQC; ++qq) {
+    const double a0 = adv[(long)(0 * NQC + qq) * nc + e], a1 = adv[(long)(1 * NQC + qq) * nc + e];
+    double v[2];
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+      double dx = 0.0, dy = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) { dx += t.Gux[qq * NS + s] * xv[cc * NS + s]; dy += t.Guy[qq * NS + s] * xv[cc * NS + s]; }
+      v[cc] = a0 * dx + a1 * dy;
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const double b = t.Bu[qq * NS + s];
+      y[s] -= b * v[0];
+      y[NS + s] -= b * v[1];
+    }
+  }
+  // facets: central + upwind (weight beta) and interior penalty
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const int nb = m.cf_nb[f * nc + e];
+    double xn[NU];
+    int fn = 0, rev = 0;
+    if (nb >= 0) {
+      fn = m.cf_nbf[f * nc + e];
+      rev = m.cf_flip[f * nc + e] != m.cf_flip[fn * nc + nb];
+#pragma unroll
+      for (int i = 0; i < NU; ++i) xn[i] = x[(long)nb * NU + i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < NU; ++i) xn[i] = 0.0;
+    }
+    for (int qq = 0; qq < NQF; ++qq) {
+      const int qn = rev ? NQF - 1 - qq : qq;
+      double jx = 0.0, jy = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const double b = t.FBu[(f * NQF + qq) * NS + s];
+        jx += b * xv[s];
+        jy += b * xv[NS + s];
+      }
+      if (nb >= 0) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const double b = t.FBu[(fn * NQF + qn) * NS + s];
+          jx -= b * xn[s];
+          jy -= b * xn[NS + s];
+        }
+      }
+      const double beta = adv[(long)(2 * NQC + f * NQF + qq) * nc + e];
+      const double pen = alpha * t.fw[qq] * (jx * g.n[f][0] + jy * g.n[f][1]);
+      const double cx = beta * jx - pen * g.n[f][0];
+      const double cy = beta * jy - pen * g.n[f][1];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const double b = t.FBu[(f * NQF + qq) * NS + s];
+        y[s] += b * cx;
+        y[NS + s] += b * cy;
+      }
+    }
+  }
+  if (MODE == 0) {
+    const double sc = adt / g.det;
+#pragma unroll
+    for (int i = 0; i < NU; ++i) out[(long)e * NU + i] = xv[i] - sc * y[i];
+    return;
+  }
+  // g(w, p, lam) = (p, div w) - <lam, w.n>
+  double pv[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) pv[i] = pp[(long)e * NP + i];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) { d0 += t.Dx[i * NS + s] * pv[i]; d1 += t.Dy[i * NS + s] * pv[i]; }
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) y[cc * NS + s] += g.det * (g.ij[0][cc] * d0 + g.ij[1][cc] * d1);
+  }
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const int F = m.cf_facet[f * nc + e];
+    const int flip = m.cf_flip[f * nc + e];
+    double l[NF];
+#pragma unroll
+    for (int mm = 0; mm < NF; ++mm) l[mm] = sgn(flip, mm) * lam[(long)F * NF + mm] * g.h[f];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      double v = 0.0;
+#pragma unroll
+      for (int mm = 0; mm < NF; ++mm) v += t.Chat[(f * NF + mm) * NS + s] * l[mm];
+      y[s] -= g.n[f][0] * v;
+      y[NS + s] -= g.n[f][1] * v;
+    }
+  }
+  const double sc = (MODE == 1) ? 1.0 / g.det : 1.0;
+#pragma unroll
+  for (int i = 0; i < NU; ++i) out[(long)e * NU + i] = sc * (r[(long)e * NU + i] - g.det * xv[i] + adt * y[i]);
+}
+
+// ===================================================================== a6
+// Div(psi, F) = sum_K [ -(grad psi, F)_K + <psi {F}.n_K>_dK ], {F}.n = 0 on walls
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_div(DMesh m, DTab t, const double* __restrict__ F, double scale,
+                                                double* __restrict__ out) {
+  using D = Dims<K>;
+  constexpr int NS = D::NS, NU = D::NU, NP = D::NP, NQF = D::NQF;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m.nc) return;
+  const long nc = m.nc;
+  const CellGeo g = load_geo(m, e);
+  double fv[NU], o[NP];
+#pragma unroll
+  for (int i = 0; i < NU; ++i) fv[i] = F[(long)e * NU + i];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    double v = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const double u0 = g.ij[0][0] * fv[s] + g.ij[0][1] * fv[NS + s];
+      const double u1 = g.ij[1][0] * fv[s] + g.ij[1][1] * fv[NS + s];
+      v += t.Rx[i * NS + s] * u0 + t.Ry[i * NS + s] * u1;
+    }
+    o[i] = -g.det * v;
+  }
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const int nb = m.cf_nb[f * nc + e];
+    if (nb < 0) continue;
+    const int fn = m.cf_nbf[f * nc + e];
+    const int rev = m.cf_flip[f * nc + e] != m.cf_flip[fn * nc + nb];
+    double xn[NU];
+#pragma unroll
+    for (int i = 0; i < NU; ++i) xn[i] = F[(long)nb * NU + i];
+    for (int qq = 0; qq < NQF; ++qq) {
+      const int qn = rev ? NQF - 1 - qq : qq;
+      double ax = 0.0, ay = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const double b = t.FBu[(f * NQF + qq) * NS + s], bn = t.FBu[(fn * NQF + qn) * NS + s];
+        ax += b * fv[s] + bn * xn[s];
+        ay += b * fv[NS + s] + bn * xn[NS + s];
+      }
+      const double flux = 0.5 * t.fw[qq] * g.h[f] * (ax * g.n[f][0] + ay * g.n[f][1]);
+#pragma unroll
+      for (int i = 0; i < NP; ++i) o[i] += t.FBp[(f * NQF + qq) * NP + i] * flux;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NP; ++i) out[(long)e * NP + i] = scale * o[i];
+}
+
+// ===================================================================== a3
+// BDM interpolant through the reference element: the physical moments equal
+// the reference moments of the contravariant Piola pull-back, so
+// Qhat* = R^{-1} m and Q* = J Qhat* / det.
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_bdm(DMesh m, DTab t, const double* __restrict__ Q, double* __restrict__ Qs) {
+  using D = Dims<K>;
+  constexpr int NS = D::NS, NU = D::NU, NQC = D::NQC, NQF = D::NQF, NNED = D::NNED, NM = D::NM;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m.nc) return;
+  const long nc = m.nc;
+  const CellGeo g = load_geo(m, e);
+  double qv[NU], mom[NU];
+#pragma unroll
+  for (int i = 0; i < NU; ++i) { qv[i] = Q[(long)e * NU + i]; mom[i] = 0.0; }
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const int nb = m.cf_nb[f * nc + e];
+    if (nb < 0) continue;  // wall: zero normal moments
+    const int fn = m.cf_nbf[f * nc + e];
+    const int rev = m.cf_flip[f * nc + e] != m.cf_flip[fn * nc + nb];
+    double xn[NU];
+#pragma unroll
+    for (int i = 0; i < NU; ++i) xn[i] = Q[(long)nb * NU + i];
+    for (int qq = 0; qq < NQF; ++qq) {
+      const int qn = rev ? NQF - 1 - qq : qq;
+      double ax = 0.0, ay = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const double b = t.FBu[(f * NQF + qq) * NS + s], bn = t.FBu[(fn * NQF + qn) * NS + s];
+        ax += b * qv[s] + bn * xn[s];
+        ay += b * qv[NS + s] + bn * xn[NS + s];
+      }
+      const double flux = 0.5 * t.fw[qq] * g.h[f] * (ax * g.n[f][0] + ay * g.n[f][1]);
+#pragma unroll
+      for (int j = 0; j < NM; ++j) mom[f * NM + j] += t.NUB[qq * NM + j] * flux;
+    }
+  }
+  for (int qq = 0; qq < NQC; ++qq) {
+    double vx = 0.0, vy = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) { const double b = t.Bu[qq * NS + s]; vx += b * qv[s]; vy += b * qv[NS + s]; }
+    // reference components of the covariant pull-back: (J^{-T} vhat) . Q = vhat . (J^{-1} Q)
+    const double w = t.cw[qq] * g.det;
+    const double r0 = w * (g.ij[0][0] * vx + g.ij[0][1] * vy);
+    const double r1 = w * (g.ij[1][0] * vx + g.ij[1][1] * vy);
+#pragma unroll
+    for (int l = 0; l < NNED; ++l) mom[3 * NM + l] += t.NED[(qq * NNED + l) * 2 + 0] * r0 + t.NED[(qq * NNED + l) * 2 + 1] * r1;
+  }
+  double qh[NU];
+#pragma unroll
+  for (int i = 0; i < NU; ++i) {
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < NU; ++j) v += t.BDMinv[i * NU + j] * mom[j];
+    qh[i] = v;
+  }
+  const double idet = 1.0 / g.det;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    Qs[(long)e * NU + s] = idet * (g.J[0][0] * qh[s] + g.J[0][1] * qh[NS + s]);
+    Qs[(long)e * NU + NS + s] = idet * (g.J[1][0] * qh[s] + g.J[1][1] * qh[NS + s]);
+  }
+}
+
+// ==================================================================== a12
+// psi-data of the pressure reconstruction: Div(psi, f_p), f_p = (Q.grad_h)Q
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_recon_rhs(DMesh m, DTab t, const double* __restrict__ Q,
+                                                      double* __restrict__ out) {
+  using D = Dims<K>;
+  constexpr int NS = D::NS, NU = D::NU, NP = D::NP, NQC = D::NQC, NQF = D::NQF;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m.nc) return;
+  const long nc = m.nc;
+  const CellGeo g = load_geo(m, e);
+  double qv[NU], o[NP];
+#pragma unroll
+  for (int i = 0; i < NU; ++i) qv[i] = Q[(long)e * NU + i];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) o[i] = 0.0;
+  auto conv = [&](const double* B, const double* Gx, const double* Gy, const double* qc, const double (&ij)[2][2],
+                  double& fx, double& fy) {
+    double vx = 0.0, vy = 0.0, d[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      vx += B[s] * qc[s]; vy += B[s] * qc[NS + s];
+      d[0][0] += Gx[s] * qc[s]; d[0][1] += Gy[s] * qc[s];
+      d[1][0] += Gx[s] * qc[NS + s]; d[1][1] += Gy[s] * qc[NS + s];
+    }
+    // physical derivative d_dd Q_c = sum_a iJ[a][dd] dref_a Q_c
+    const double gxx = ij[0][0] * d[0][0] + ij[1][0] * d[0][1], gxy = ij[0][1] * d[0][0] + ij[1][1] * d[0][1];
+    const double gyx = ij[0][0] * d[1][0] + ij[1][0] * d[1][1], gyy = ij[0][1] * d[1][0] + ij[1][1] * d[1][1];
+    fx = vx * gxx + vy * gxy;
+    fy = vx * gyx + vy * gyy;
+  };
+  for (int qq = 0; qq < NQC; ++qq) {
+    double fx, fy;
+    conv(t.Bu + qq * NS, t.Gux + qq * NS, t.Guy + qq * NS, qv, g.ij, fx, fy);
+    const double w = t.cw[qq] * g.det;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const double gx = g.ij[0][0] * t.Gpx[qq * NP + i] + g.ij[1][0] * t.Gpy[qq * NP + i];
+      const double gy = g.ij[0][1] * t.Gpx[qq * NP + i] + g.ij[1][1] * t.Gpy[qq * NP + i];
+      o[i] -= w * (gx * fx + gy * fy);
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const int nb = m.cf_nb[f * nc + e];
+    if (nb < 0) continue;
+    const int fn = m.cf_nbf[f * nc + e];
+    const int rev = m.cf_flip[f * nc + e] != m.cf_flip[fn * nc + nb];
+    double xn[NU];
+#pragma unroll
+    for (int i = 0; i < NU; ++i) xn[i] = Q[(long)nb * NU + i];
+    double ijn[2][2];
+    ijn[0][0] = m.geo[D_IJ00 * nc + nb]; ijn[0][1] = m.geo[D_IJ01 * nc + nb];
+    ijn[1][0] = m.geo[D_IJ10 * nc + nb]; ijn[1][1] = m.geo[D_IJ11 * nc + nb];
+    for (int qq = 0; qq < NQF; ++qq) {
+      const int qn = rev ? NQF - 1 - qq : qq;
+      double fx, fy, gx, gy;
+      conv(t.FBu + (f * NQF + qq) * NS, t.FGux + (f * NQF + qq) * NS, t.FGuy + (f * NQF + qq) * NS, qv, g.ij, fx, fy);
+      conv(t.FBu + (fn * NQF + qn) * NS, t.FGux + (fn * NQF + qn) * NS, t.FGuy + (fn * NQF + qn) * NS, xn, ijn, gx, gy);
+      const double flux = 0.5 * t.fw[qq] * g.h[f] * ((fx + gx) * g.n[f][0] + (fy + gy) * g.n[f][1]);
+#pragma unroll
+      for (int i = 0; i < NP; ++i) o[i] += t.FBp[(f * NQF + qq) * NP + i] * flux;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NP; ++i) out[(long)e * NP + i] = o[i];
+}
+
+// L2 projection of point values [cell][q][2] (orthonormal basis: M = det I)
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_project(DMesh m, DTab t, const double* __restrict__ vals,
+                                                    double* __restrict__ Q) {
+  using D = Dims<K>;
+  constexpr int NS = D::NS, NU = D::NU, NQC = D::NQC;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m.nc) return;
+  double o[NU];
+#pragma unroll
+  for (int i = 0; i < NU; ++i) o[i] = 0.0;
+  for (int qq = 0; qq < NQC; ++qq) {
+    const double vx = vals[((long)e * NQC + qq) * 2], vy = vals[((long)e * NQC + qq) * 2 + 1];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const double b = t.cw[qq] * t.Bu[qq * NS + s];
+      o[s] += b * vx;
+      o[NS + s] += b * vy;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NU; ++i) Q[(long)e * NU + i] = o[i];
+}
+
+template <int K>
+__global__ void k_mass(DMesh m, double s, const double* __restrict__ x, double* __restrict__ y) {
+  constexpr int NU = Dims<K>::NU;
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (long)m.nc * NU) return;
+  const int e = (int)(tid / NU);
+  y[tid] = s * m.geo[D_DET * (long)m.nc + e] * x[tid];
+}
+
+// ================================================================ generic
+__global__ void k_csr_spmv(DCsr A, const double* __restrict__ x, double* __restrict__ y, double beta) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+  double acc = 0.0;
+  for (int p = A.ptr[i]; p < A.ptr[i + 1]; ++p) acc += A.val[p] * x[A.idx[p]];
+  y[i] = (beta != 0.0 ? beta * y[i] : 0.0) + acc;
+}
+
+__global__ void k_csr_jacobi(DCsr A, const double* __restrict__ dinv, double omega, const double* __restrict__ b,
+                             const double* __restrict__ xin, double* __restrict__ xout) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+  double r = b[i];
+  if (xin) {
+    for (int p = A.ptr[i]; p < A.ptr[i + 1]; ++p) r -= A.val[p] * xin[A.idx[p]];
+    xout[i] = xin[i] + omega * dinv[i] * r;
+  } else {
+    xout[i] = omega * dinv[i] * r;
+  }
+}
+
+__global__ void k_dense_mv(int n, const double* __restrict__ M, const double* __restrict__ x, double* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int j = 0; j < n; ++j) acc += M[(long)i * n + j] * x[j];
+  y[i] = acc;
+}
+
+__global__ void __launch_bounds__(kBlock) k_dot(long n, const double* __restrict__ a, const double* __restrict__ b,
+                                                double* __restrict__ part) {
+  double v = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    v += a[i] * (b ? b[i] : a[i]);
+  v = block_sum(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// sum of a[j*stride + off]
+__global__ void __launch_bounds__(kBlock) k_dot_sub(long n, int stride, int off, const double* __restrict__ a,
+                                                    double* __restrict__ part) {
+  double v = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    v += a[i * stride + off];
+  v = block_sum(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_dot2(long n, const double* __restrict__ a, const double* __restrict__ b,
+                                                 const double* __restrict__ c, double* __restrict__ part2) {
+  double v = 0.0, w = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    v += a[i] * b[i];
+    w += a[i] * c[i];
+  }
+  v = block_sum(v);
+  w = block_sum(w);
+  if (threadIdx.x == 0) { part2[blockIdx.x] = v; part2[kRedBlocks + blockIdx.x] = w; }
+}
+
+__global__ void __launch_bounds__(kBlock) k_finish(const double* __restrict__ part, int np, double* __restrict__ out) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) v += part[i];
+  v = block_sum(v);
+  if (threadIdx.x == 0) out[0] = v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_finish_mean(const double* __restrict__ part, int np, double area,
+                                                        double* __restrict__ out) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) v += part[i];
+  v = block_sum(v);
+  if (threadIdx.x == 0) out[0] = v / area;
+}
+
+__global__ void __launch_bounds__(kBlock) k_finish2(const double* __restrict__ part2, double* __restrict__ out2) {
+  double v = 0.0, w = 0.0;
+  for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) { v += part2[i]; w += part2[kRedBlocks + i]; }
+  v = block_sum(v);
+  w = block_sum(w);
+  if (threadIdx.x == 0) { out2[0] = v; out2[1] = w; }
+}
+
+__global__ void k_axpby(long n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i] + (b != 0.0 ? b * y[i] : 0.0);
+}
+__global__ void k_copy(long n, const double* __restrict__ x, double* __restrict__ y) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i];
+}
+__global__ void k_fill(long n, double v, double* __restrict__ y) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = v;
+}
+// remove the constant-trace component: g_F,0 -= sum / nF
+__global__ void k_project_const(int nF, int nf, const double* __restrict__ sum, double* __restrict__ g) {
+  const int F = blockIdx.x * blockDim.x + threadIdx.x;
+  if (F < nF) g[(long)F * nf] -= sum[0] / (double)nF;
+}
+
+__global__ void __launch_bounds__(kBlock) k_pcg_update(long n, const double* __restrict__ rz, const double* __restrict__ pq,
+                                                       const double* __restrict__ p, const double* __restrict__ q,
+                                                       double* __restrict__ x, double* __restrict__ r,
+                                                       double* __restrict__ part) {
+  const double alpha = rz[0] / pq[0];
+  double v = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    v += ri * ri;
+  }
+  v = block_sum(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+__global__ void k_pcg_direction(long n, const double* __restrict__ rzn, const double* __restrict__ rzo,
+                                const double* __restrict__ z, double* __restrict__ p) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = z[i] + (rzn[0] / rzo[0]) * p[i];
+}
+
+// BiCGStab scalars, 8 per iteration i: [0] rho_i = rhat.r_i, [1] rhat.v_i,
+// [2] t.s, [3] t.t, [4] r_i.r_i
+__device__ __forceinline__ double bicg_alpha(const double* sc, int i) { return sc[8 * i] / sc[8 * i + 1]; }
+__device__ __forceinline__ double bicg_omega(const double* sc, int i) { return sc[8 * i + 2] / sc[8 * i + 3]; }
+
+__global__ void k_bicg_p(long n, const double* __restrict__ sc, int it, const double* __restrict__ r,
+                         const double* __restrict__ v, double* __restrict__ p) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (it == 0) { p[i] = r[i]; return; }
+  const double om = bicg_omega(sc, it - 1);
+  const double beta = (sc[8 * it] / sc[8 * (it - 1)]) * (bicg_alpha(sc, it - 1) / om);
+  p[i] = r[i] + beta * (p[i] - om * v[i]);
+}
+
+__global__ void k_bicg_s(long n, const double* __restrict__ sc, int it, const double* __restrict__ r,
+                         const double* __restrict__ v, double* __restrict__ s) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) s[i] = r[i] - bicg_alpha(sc, it) * v[i];
+}
+
+__global__ void __launch_bounds__(kBlock) k_bicg_xr(long n, const double* __restrict__ sc, int it,
+                                                    const double* __restrict__ p, const double* __restrict__ s,
+                                                    const double* __restrict__ t, double* __restrict__ x,
+                                                    double* __restrict__ r, const double* __restrict__ rhat,
+                                                    double* __restrict__ part2) {
+  const double al = bicg_alpha(sc, it), om = bicg_omega(sc, it);
+  double a = 0.0, b = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    x[i] += al * p[i] + om * s[i];
+    const double ri = s[i] - om * t[i];
+    r[i] = ri;
+    a += rhat[i] * ri;
+    b += ri * ri;
+  }
+  a = block_sum(a);
+  b = block_sum(b);
+  if (threadIdx.x == 0) { part2[blockIdx.x] = a; part2[kRedBlocks + blockIdx.x] = b; }
+}
+
+// ============================================================== launchers
+#define HDG_DISPATCH(k, CALL)       \
+  switch (k) {                      \
+    case 1: { constexpr int KK = 1; CALL; } break; \
+    case 2: { constexpr int KK = 2; CALL; } break; \
+    case 3: { constexpr int KK = 3; CALL; } break; \
+    case 4: { constexpr int KK = 4; CALL; } break; \
+    default: break;                 \
+  }
+
+void launch_condense(int k, hipStream_t st, DMesh m, DTab t, double c, double tau, double* Pinv, double* SK) {
+  HDG_DISPATCH(k, (k_condense<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, c, tau, Pinv, SK)));
+}
+void launch_assemble(int k, hipStream_t st, DMesh m, const double* SK, double* vals, int* cols, double* Dinv) {
+  HDG_DISPATCH(k, (k_assemble<KK><<<nblocks(m.nF), kBlock, 0, st>>>(m, SK, vals, cols, Dinv)));
+}
+void launch_spmv(int k, hipStream_t st, int nF, const double* vals, const int* cols, const double* x, double* y) {
+  HDG_DISPATCH(k, (k_spmv<KK><<<nblocks((long)nF * (k + 1)), kBlock, 0, st>>>(nF, vals, cols, x, nullptr, y)));
+}
+void launch_residual(int k, hipStream_t st, int nF, const double* vals, const int* cols, const double* b,
+                     const double* x, double* r) {
+  HDG_DISPATCH(k, (k_spmv<KK><<<nblocks((long)nF * (k + 1)), kBlock, 0, st>>>(nF, vals, cols, x, b, r)));
+}
+void launch_jacobi_sweep(int k, hipStream_t st, int nF, const double* vals, const int* cols, const double* Dinv,
+                         double omega, const double* b, const double* xin, double* xout) {
+  HDG_DISPATCH(k, (k_jacobi<KK><<<nblocks(nF), kBlock, 0, st>>>(nF, vals, cols, Dinv, omega, b, xin, xout)));
+}
+void launch_blockdiag(int k, hipStream_t st, int nF, const double* Dinv, const double* x, double* y) {
+  HDG_DISPATCH(k, (k_blockdiag<KK><<<nblocks(nF), kBlock, 0, st>>>(nF, Dinv, x, y)));
+}
+void launch_rhs_condense(int k, hipStream_t st, DMesh m, DTab t, double c, double tau, const double* Pinv,
+                         const double* Fw, const double* Fpsi, double* ycell) {
+  HDG_DISPATCH(k, (k_rhs_condense<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, c, tau, Pinv, Fw, Fpsi, ycell)));
+}
+void launch_gather_rhs(int k, hipStream_t st, DMesh m, const double* ycell, const double* Fmu, double* g) {
+  HDG_DISPATCH(k, (k_gather_rhs<KK><<<nblocks((long)m.nF * (k + 1)), kBlock, 0, st>>>(m, ycell, Fmu, g)));
+}
+void launch_backsub(int k, hipStream_t st, DMesh m, DTab t, double c, double tau, const double* Pinv,
+                    const double* Fw, const double* Fpsi, const double* lam, double* U, double* p, double* part) {
+  // one partial sum per block: part holds ceil(nc / kBlock) entries
+  HDG_DISPATCH(k, (k_backsub<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, c, tau, Pinv, Fw, Fpsi, lam, U, p, part)));
+}
+void launch_prep_adv(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, double* adv) {
+  HDG_DISPATCH(k, (k_prep_adv<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, Qs, delta_up, adv)));
+}
+void launch_apply(int k, hipStream_t st, int mode, DMesh m, DTab t, const double* adv, double alpha, double adt,
+                  const double* x, const double* r, const double* p, const double* lam, double* out) {
+  if (mode == 0) {
+    HDG_DISPATCH(k, (k_apply<KK, 0><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, adv, alpha, adt, x, r, p, lam, out)));
+  } else if (mode == 1) {
+    HDG_DISPATCH(k, (k_apply<KK, 1><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, adv, alpha, adt, x, r, p, lam, out)));
+  } else {
+    HDG_DISPATCH(k, (k_apply<KK, 2><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, adv, alpha, adt, x, r, p, lam, out)));
+  }
+}
+void launch_div(int k, hipStream_t st, DMesh m, DTab t, const double* F, double scale, double* out) {
+  HDG_DISPATCH(k, (k_div<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, F, scale, out)));
+}
+void launch_bdm(int k, hipStream_t st, DMesh m, DTab t, const double* Q, double* Qs) {
+  HDG_DISPATCH(k, (k_bdm<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, Q, Qs)));
+}
+void launch_recon_rhs(int k, hipStream_t st, DMesh m, DTab t, const double* Q, double* out) {
+  HDG_DISPATCH(k, (k_recon_rhs<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, Q, out)));
+}
+void launch_project(int k, hipStream_t st, DMesh m, DTab t, const double* vals, double* Q) {
+  HDG_DISPATCH(k, (k_project<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, vals, Q)));
+}
+void launch_mass(int k, hipStream_t st, DMesh m, double s, const double* x, double* y) {
+  HDG_DISPATCH(k, (k_mass<KK><<<nblocks((long)m.nc * Dims<KK>::NU), kBlock, 0, st>>>(m, s, x, y)));
+}
+void launch_shift_mean(int k, hipStream_t st, DMesh m, const double* mean, double* p, double* lam) {
+  const long n = m.nc > m.nF ? m.nc : m.nF;
+  HDG_DISPATCH(k, (k_shift_mean<KK><<<nblocks(n), kBlock, 0, st>>>(m, mean, p, lam)));
+}
+void launch_csr_spmv(hipStream_t st, DCsr A, const double* x, double* y, double beta) {
+  k_csr_spmv<<<nblocks(A.n), kBlock, 0, st>>>(A, x, y, beta);
+}
+void launch_csr_jacobi(hipStream_t st, DCsr A, const double* dinv, double omega, const double* b, const double* xin,
+                       double* xout) {
+  k_csr_jacobi<<<nblocks(A.n), kBlock, 0, st>>>(A, dinv, omega, b, xin, xout);
+}
+void launch_dense_mv(hipStream_t st, int n, const double* M, const double* x, double* y) {
+  k_dense_mv<<<nblocks(n), kBlock, 0, st>>>(n, M, x, y);
+}
+void launch_dot(hipStream_t st, long n, const double* a, const double* b, double* part) {
+  k_dot<<<kRedBlocks, kBlock, 0, st>>>(n, a, b, part);
+}
+void launch_dot_sub(hipStream_t st, long n, int stride, int off, const double* a, double* part) {
+  k_dot_sub<<<kRedBlocks, kBlock, 0, st>>>(n, stride, off, a, part);
+}
+void launch_finish(hipStream_t st, const double* part, int nparts, double* out) {
+  k_finish<<<1, kBlock, 0, st>>>(part, nparts, out);
+}
+void launch_finish_mean(hipStream_t st, const double* part, int nparts, double area, double* out) {
+  k_finish_mean<<<1, kBlock, 0, st>>>(part, nparts, area, out);
+}
+void launch_axpby(hipStream_t st, long n, double a, const double* x, double b, double* y) {
+  k_axpby<<<nblocks(n), kBlock, 0, st>>>(n, a, x, b, y);
+}
+void launch_copy(hipStream_t st, long n, const double* x, double* y) { k_copy<<<nblocks(n), kBlock, 0, st>>>(n, x, y); }
+void launch_fill(hipStream_t st, long n, double v, double* y) { k_fill<<<nblocks(n), kBlock, 0, st>>>(n, v, y); }
+void launch_project_const(hipStream_t st, int nF, int nf, const double* sum, double* g) {
+  k_project_const<<<nblocks(nF), kBlock, 0, st>>>(nF, nf, sum, g);
+}
+void launch_pcg_update(hipStream_t st, long n, const double* rz, const double* pq, const double* p, const double* q,
+                       double* x, double* r, double* part_rr) {
+  k_pcg_update<<<kRedBlocks, kBlock, 0, st>>>(n, rz, pq, p, q, x, r, part_rr);
+}
+void launch_pcg_direction(hipStream_t st, long n, const double* rzn, const double* rzo, const double* z, double* p) {
+  k_pcg_direction<<<nblocks(n), kBlock, 0, st>>>(n, rzn, rzo, z, p);
+}
+void launch_bicg_p(hipStream_t st, long n, const double* sc, int it, const double* r, const double* v, double* p) {
+  k_bicg_p<<<nblocks(n), kBlock, 0, st>>>(n, sc, it, r, v, p);
+}
+void launch_bicg_s(hipStream_t st, long n, const double* sc, int it, const double* r, const double* v, double* s) {
+  k_bicg_s<<<nblocks(n), kBlock, 0, st>>>(n, sc, it, r, v, s);
+}
+void launch_bicg_xr(hipStream_t st, long n, const double* sc, int it, const double* p, const double* s,
+                    const double* t, double* x, double* r, const double* rhat, double* part2) {
+  k_bicg_xr<<<kRedBlocks, kBlock, 0, st>>>(n, sc, it, p, s, t, x, r, rhat, part2);
+}
+void launch_dot2(hipStream_t st, long n, const double* a, const double* b, const double* c, double* part2) {
+  k_dot2<<<kRedBlocks, kBlock, 0, st>>>(n, a, b, c, part2);
+}
+void launch_finish2(hipStream_t st, const double* part2, double* out2) { k_finish2<<<1, kBlock, 0, st>>>(part2, out2); }
+
+}  // namespace hdg

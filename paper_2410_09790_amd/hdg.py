@@ -1,0 +1,225 @@
+"""Thin ctypes binding of libhdg.so (see include/hdg.h for the contract).
+
+Argument marshalling only: every numerical step runs in the HIP library.
+torch supplies device memory (float64 CUDA tensors) and the HIP stream.
+Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhdg.so")
+
+IMEX = {"imex_euler": 0, "ars222": 1, "ars233": 2}
+TRACE_SOLVER = {"jacobi_pcg": 0, "mg_pcg": 1}
+PRESSURE = {"reconstruct": 0, "first_order": 1}
+STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NOT_CONVERGED", 5: "BAD_STATE",
+          6: "UNSUPPORTED"}
+
+EXPORTS = [
+    "hdg_default_params", "hdg_create", "hdg_destroy", "hdg_last_error", "hdg_sizes", "hdg_cell_points",
+    "hdg_set_velocity_from_points", "hdg_set_state", "hdg_get_state", "hdg_advance", "hdg_solve_trace",
+    "hdg_trace_matvec", "hdg_bdm_project", "hdg_weak_divergence", "hdg_momentum_residual",
+    "hdg_tentative_velocity", "hdg_reconstruct_pressure", "hdg_get_info",
+]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("degree", ctypes.c_int),
+        ("tau", ctypes.c_double),
+        ("alpha", ctypes.c_double),
+        ("delta_up", ctypes.c_double),
+        ("imex", ctypes.c_int),
+        ("n_richardson", ctypes.c_int),
+        ("trace_solver", ctypes.c_int),
+        ("rtol_trace", ctypes.c_double),
+        ("rtol_velocity", ctypes.c_double),
+        ("max_it_trace", ctypes.c_int),
+        ("max_it_velocity", ctypes.c_int),
+        ("pressure_update", ctypes.c_int),
+    ]
+
+
+class HDGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libhdg.so (raises if it is missing) and declare the signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2410_09790_amd/build.py")
+    lib = ctypes.CDLL(path)
+    P, D, I64, I = ctypes.c_void_p, ctypes.c_double, ctypes.c_int64, ctypes.c_int
+    sig = {
+        "hdg_default_params": (None, [ctypes.POINTER(Params)]),
+        "hdg_create": (I, [I64, P, I64, P, ctypes.POINTER(Params), P, ctypes.POINTER(P)]),
+        "hdg_destroy": (None, [P]),
+        "hdg_last_error": (ctypes.c_char_p, [P]),
+        "hdg_sizes": (I, [P, P, I]),
+        "hdg_cell_points": (I, [P, P]),
+        "hdg_set_velocity_from_points": (I, [P, P]),
+        "hdg_set_state": (I, [P, P, P, P]),
+        "hdg_get_state": (I, [P, P, P, P]),
+        "hdg_advance": (I, [P, D, I]),
+        "hdg_solve_trace": (I, [P, D, P, P, P, P, P, P]),
+        "hdg_trace_matvec": (I, [P, D, P, P]),
+        "hdg_bdm_project": (I, [P, P, P]),
+        "hdg_weak_divergence": (I, [P, P, P]),
+        "hdg_momentum_residual": (I, [P, D, P, P, P, P, P, P]),
+        "hdg_tentative_velocity": (I, [P, D, P, P, P]),
+        "hdg_reconstruct_pressure": (I, [P, P, P, P]),
+        "hdg_get_info": (I, [P, ctypes.c_char_p, ctypes.c_size_t]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def default_params(**kw) -> Params:
+    lib = load_library()
+    p = Params()
+    lib.hdg_default_params(ctypes.byref(p))
+    for key, val in kw.items():
+        if key == "imex" and isinstance(val, str):
+            val = IMEX[val]
+        elif key == "trace_solver" and isinstance(val, str):
+            val = TRACE_SOLVER[val]
+        elif key == "pressure_update" and isinstance(val, str):
+            val = PRESSURE[val]
+        setattr(p, key, val)
+    return p
+
+
+def _ptr(t):
+    import torch
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One HDG-IMEX instance on the current CUDA (HIP) device."""
+
+    def __init__(self, coords, cells, stream=None, **params):
+        import torch
+        self._lib = load_library()
+        coords = np.ascontiguousarray(coords, dtype=np.float64)
+        cells = np.ascontiguousarray(cells, dtype=np.int32)
+        self.params = default_params(**params)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.device = stream.device
+        h = ctypes.c_void_p()
+        st = self._lib.hdg_create(coords.shape[0], coords.ctypes.data_as(ctypes.c_void_p), cells.shape[0],
+                                  cells.ctypes.data_as(ctypes.c_void_p), ctypes.byref(self.params),
+                                  ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if st != 0:
+            raise HDGError(st, self._lib.hdg_last_error(None).decode())
+        self._h = h
+        out = (ctypes.c_int64 * 8)()
+        self._check(self._lib.hdg_sizes(self._h, out, 8))
+        (self.ncells, self.nfacets, self.nQ, self.nP, self.nT, self.nq_cell, self.nverts, self.degree) = list(out)
+
+    def _check(self, st):
+        if st != 0:
+            raise HDGError(st, self._lib.hdg_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hdg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _empty(self, n):
+        import torch
+        return torch.empty(n, dtype=torch.float64, device=self.device)
+
+    # ------------------------------------------------------------- state
+    def cell_points(self) -> np.ndarray:
+        xy = np.empty((self.ncells, self.nq_cell, 2))
+        self._check(self._lib.hdg_cell_points(self._h, xy.ctypes.data_as(ctypes.c_void_p)))
+        return xy
+
+    def set_velocity_from_points(self, values):
+        import torch
+        v = torch.as_tensor(np.ascontiguousarray(values, dtype=np.float64)).to(self.device)
+        self._check(self._lib.hdg_set_velocity_from_points(self._h, _ptr(v)))
+
+    def set_state(self, Q, p, lam):
+        self._check(self._lib.hdg_set_state(self._h, _ptr(Q), _ptr(p), _ptr(lam)))
+
+    def get_state(self):
+        Q, p, lam = self._empty(self.nQ), self._empty(self.nP), self._empty(self.nT)
+        self._check(self._lib.hdg_get_state(self._h, _ptr(Q), _ptr(p), _ptr(lam)))
+        return Q, p, lam
+
+    def advance(self, dt: float, nsteps: int):
+        self._check(self._lib.hdg_advance(self._h, float(dt), int(nsteps)))
+
+    # ------------------------------------------------------- path pieces
+    def solve_trace(self, c, Fw=None, Fpsi=None, Fmu=None):
+        U, p, lam = self._empty(self.nQ), self._empty(self.nP), self._empty(self.nT)
+        self._check(self._lib.hdg_solve_trace(self._h, float(c), _ptr(Fw), _ptr(Fpsi), _ptr(Fmu), _ptr(U), _ptr(p),
+                                              _ptr(lam)))
+        return U, p, lam
+
+    def trace_matvec(self, c, x):
+        y = self._empty(self.nT)
+        self._check(self._lib.hdg_trace_matvec(self._h, float(c), _ptr(x), _ptr(y)))
+        return y
+
+    def bdm_project(self, Q):
+        out = self._empty(self.nQ)
+        self._check(self._lib.hdg_bdm_project(self._h, _ptr(Q), _ptr(out)))
+        return out
+
+    def weak_divergence(self, F):
+        out = self._empty(self.nP)
+        self._check(self._lib.hdg_weak_divergence(self._h, _ptr(F), _ptr(out)))
+        return out
+
+    def momentum_residual(self, adt, r, Qstar, Q, p, lam):
+        out = self._empty(self.nQ)
+        self._check(self._lib.hdg_momentum_residual(self._h, float(adt), _ptr(r), _ptr(Qstar), _ptr(Q), _ptr(p),
+                                                    _ptr(lam), _ptr(out)))
+        return out
+
+    def tentative_velocity(self, adt, Qstar, rhs):
+        out = self._empty(self.nQ)
+        self._check(self._lib.hdg_tentative_velocity(self._h, float(adt), _ptr(Qstar), _ptr(rhs), _ptr(out)))
+        return out
+
+    def reconstruct_pressure(self, Q):
+        p, lam = self._empty(self.nP), self._empty(self.nT)
+        self._check(self._lib.hdg_reconstruct_pressure(self._h, _ptr(Q), _ptr(p), _ptr(lam)))
+        return p, lam
+
+    def info(self) -> dict:
+        buf = ctypes.create_string_buffer(1 << 16)
+        self._check(self._lib.hdg_get_info(self._h, buf, len(buf)))
+        return json.loads(buf.value.decode())

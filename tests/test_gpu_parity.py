@@ -1,0 +1,194 @@
+"""GPU parity: every step of the HDG-IMEX path through the C ABI against the
+CPU FP64 oracle, on the same seeded inputs.  FP64 bar: relative L2 <= 1e-10
+(1e-12 for single operator applications), meshes spanning several cells with
+perturbed (non-uniform) geometry.
+"""
+import numpy as np
+import pytest
+
+import hdg_inputs as hi
+from oracle.forms import Discretisation
+from oracle.hdg import HDGSolver, monolithic_matrix
+from oracle.imex import IMEXHDG, ars222, ars233, imex_euler
+
+from gpu_util import compatible_rhs, context, dev, host, mesh, rel_l2_cells, rel_l2_trace, torch_or_skip
+
+pytestmark = pytest.mark.gpu
+
+OPS = [(3, 1, 0.0), (3, 2, 0.2), (4, 3, 0.15), (2, 4, 0.2)]
+
+
+@pytest.mark.parametrize("n,k,pert", OPS)
+@pytest.mark.parametrize("c", [1.0, 2.9e-4])
+def test_a1_trace_operator(n, k, pert, c):
+    torch = torch_or_skip()
+    X, C = mesh(n, pert)
+    d = Discretisation(X, C, k)
+    S = HDGSolver(d, c).S
+    ctx = context(X, C, degree=k)
+    x = np.random.default_rng(3).standard_normal(d.nT)
+    y = host(ctx.trace_matvec(c, dev(torch, x)))
+    ref = S @ x
+    assert np.linalg.norm(y - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("n,k,pert", OPS)
+@pytest.mark.parametrize("c", [1.0, 2.9e-4])
+@pytest.mark.parametrize("solver", ["jacobi_pcg", "mg_pcg"])
+def test_a7_a9_solve_trace(n, k, pert, c, solver):
+    torch = torch_or_skip()
+    X, C = mesh(n, pert)
+    d = Discretisation(X, C, k)
+    Fw, Fpsi, Fmu = compatible_rhs(d, 5)
+    U, p, lam = HDGSolver(d, c).solve(Fw, Fpsi, Fmu)
+    ctx = context(X, C, degree=k, trace_solver=solver, rtol_trace=1e-13)
+    Ug, pg, lg = (host(t) for t in ctx.solve_trace(c, dev(torch, Fw), dev(torch, Fpsi), dev(torch, Fmu)))
+    # backward error against the oracle's assembled (U, p, lambda) operator
+    H = monolithic_matrix(d, c)
+    x = np.concatenate([Ug, pg, lg])
+    assert np.abs(H @ x - np.concatenate([Fw, Fpsi, Fmu])).max() <= 1e-12 * abs(H).max() * np.abs(x).max()
+    # forward agreement; for small c the solution is ~1/c times the data and
+    # the oracle's direct solve itself carries errors of that order
+    tol = 1e-10 if c >= 0.1 else 1e-9
+    assert rel_l2_cells(d, Ug, U, d.nu) < tol
+    assert rel_l2_cells(d, pg, p, d.npp) < tol
+    assert rel_l2_trace(d, lg, lam) < tol
+
+
+@pytest.mark.parametrize("n,k,pert", OPS)
+def test_a3_bdm_projection(n, k, pert):
+    torch = torch_or_skip()
+    X, C = mesh(n, pert)
+    d = Discretisation(X, C, k)
+    Q = np.random.default_rng(7).standard_normal(d.nQ)
+    ref = d.bdm_project(Q)
+    got = host(context(X, C, degree=k).bdm_project(dev(torch, Q)))
+    assert rel_l2_cells(d, got, ref, d.nu) < 1e-12
+
+
+@pytest.mark.parametrize("n,k,pert", OPS)
+def test_a6_weak_divergence(n, k, pert):
+    torch = torch_or_skip()
+    X, C = mesh(n, pert)
+    d = Discretisation(X, C, k)
+    F = np.random.default_rng(8).standard_normal(d.nQ)
+    ref = d.div_c(F)
+    got = host(context(X, C, degree=k).weak_divergence(dev(torch, F)))
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("n,k,pert", OPS)
+def test_a4_momentum_residual(n, k, pert):
+    torch = torch_or_skip()
+    X, C = mesh(n, pert)
+    d = Discretisation(X, C, k)
+    rng = np.random.default_rng(9)
+    r, Q = rng.standard_normal(d.nQ), rng.standard_normal(d.nQ)
+    p, lam = rng.standard_normal(d.nP), rng.standard_normal(d.nT)
+    Qs = d.bdm_project(10.0 * rng.standard_normal(d.nQ))
+    adt = 0.01
+    ref = r - d.mass() @ Q + adt * (d.advection(Qs) @ Q + d.g(p, lam))
+    ctx = context(X, C, degree=k)
+    got = host(ctx.momentum_residual(adt, dev(torch, r), dev(torch, Qs), dev(torch, Q), dev(torch, p),
+                                     dev(torch, lam)))
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("n,k,pert", OPS)
+def test_a5_tentative_velocity(n, k, pert):
+    import scipy.sparse.linalg as spla
+    torch = torch_or_skip()
+    X, C = mesh(n, pert)
+    d = Discretisation(X, C, k)
+    rng = np.random.default_rng(10)
+    # the method advects with the BDM projection of a (nearly) divergence-free velocity
+    par = hi.stream_function_params(1)
+    Qs = d.bdm_project(d.l2_project_velocity(lambda x, y: hi.streamfunction_velocity(par, x, y)))
+    rhs = rng.standard_normal(d.nQ)
+    adt = 0.01
+    ref = spla.splu((d.mass() - adt * d.advection(Qs)).tocsc()).solve(rhs)
+    ctx = context(X, C, degree=k, rtol_velocity=1e-13)
+    got = host(ctx.tentative_velocity(adt, dev(torch, Qs), dev(torch, rhs)))
+    assert rel_l2_cells(d, got, ref, d.nu) < 1e-11
+
+
+@pytest.mark.parametrize("n,k,pert", OPS)
+def test_a12_pressure_reconstruction(n, k, pert):
+    torch = torch_or_skip()
+    X, C = mesh(n, pert)
+    d = Discretisation(X, C, k)
+    st = IMEXHDG(d, 1e-3, ars222(), 1)
+    par = hi.stream_function_params(1)
+    Q = d.l2_project_velocity(lambda x, y: hi.streamfunction_velocity(par, x, y))
+    p, lam = st.reconstruct(Q, 0.0)
+    ctx = context(X, C, degree=k, rtol_trace=1e-13)
+    pg, lg = ctx.reconstruct_pressure(dev(torch, Q))
+    assert rel_l2_cells(d, host(pg), p, d.npp) < 1e-10
+    assert rel_l2_trace(d, host(lg), lam) < 1e-10
+
+
+def _initial(ctx, par):
+    xy = ctx.cell_points()
+    ctx.set_velocity_from_points(hi.streamfunction_velocity(par, xy[..., 0], xy[..., 1]))
+
+
+@pytest.mark.parametrize("n,k", [(4, 1), (3, 3)])
+def test_initial_state(n, k):
+    torch_or_skip()
+    X, C = mesh(n)
+    d = Discretisation(X, C, k)
+    par = hi.stream_function_params(0)
+    st = IMEXHDG(d, 1e-3, ars222(), 3)
+    Q, p, lam = st.initial_state(lambda x, y: hi.streamfunction_velocity(par, x, y))
+    ctx = context(X, C, degree=k, rtol_trace=1e-13)
+    _initial(ctx, par)
+    Qg, pg, lg = ctx.get_state()
+    assert rel_l2_cells(d, host(Qg), Q, d.nu) < 1e-13
+    assert rel_l2_cells(d, host(pg), p, d.npp) < 1e-10
+    assert rel_l2_trace(d, host(lg), lam) < 1e-10
+
+
+def _run_both(n, k, nsteps, dt, tab, scheme, nR, pert=0.0, solver="mg_pcg", seed=0):
+    X, C = mesh(n, pert)
+    d = Discretisation(X, C, k)
+    par = hi.stream_function_params(seed)
+    st = IMEXHDG(d, dt, tab, nR)
+    Q, p, lam = st.initial_state(lambda x, y: hi.streamfunction_velocity(par, x, y))
+    Q, p, lam = st.run(Q, p, lam, 0.0, nsteps)
+    ctx = context(X, C, degree=k, imex=scheme, n_richardson=nR, trace_solver=solver, rtol_trace=1e-13,
+                  rtol_velocity=1e-13)
+    _initial(ctx, par)
+    ctx.advance(dt, nsteps)
+    Qg, pg, lg = ctx.get_state()
+    return d, (Q, p, lam), tuple(host(t) for t in (Qg, pg, lg)), ctx
+
+
+@pytest.mark.parametrize("scheme,tab", [("imex_euler", imex_euler), ("ars222", ars222), ("ars233", ars233)])
+def test_step_small(scheme, tab):
+    torch_or_skip()
+    d, ref, got, _ = _run_both(4, 2, 2, 5e-3, tab(), scheme, 2, pert=0.15)
+    assert rel_l2_cells(d, got[0], ref[0], d.nu) < 1e-10
+    assert rel_l2_cells(d, got[1], ref[1], d.npp) < 1e-9
+    assert rel_l2_trace(d, got[2], ref[2]) < 1e-9
+
+
+def test_config1_parity():
+    """The small parity workload: 16x16 unit square (512 cells), k=1, stream-function
+    data of seed 0, ARS(2,2,2), dt=1e-3, 10 steps, 3 Richardson iterations,
+    facet-block-Jacobi PCG."""
+    torch_or_skip()
+    d, ref, got, ctx = _run_both(16, 1, 10, 1e-3, ars222(), "ars222", 3, solver="jacobi_pcg")
+    assert rel_l2_cells(d, got[0], ref[0], d.nu) < 1e-10
+    assert rel_l2_cells(d, got[1], ref[1], d.npp) < 1e-10
+    assert rel_l2_trace(d, got[2], ref[2]) < 1e-10
+    info = ctx.info()
+    assert info["trace_solves"] == 1 + 10 * (2 * 3 + 2)
+    assert info["velocity_solves"] == 10 * 2 * 3
+
+
+def test_degree3_mg_parity():
+    torch_or_skip()
+    d, ref, got, _ = _run_both(8, 3, 3, 1e-3, ars222(), "ars222", 3, pert=0.1)
+    assert rel_l2_cells(d, got[0], ref[0], d.nu) < 1e-10
+    assert rel_l2_cells(d, got[1], ref[1], d.npp) < 1e-10
+    assert rel_l2_trace(d, got[2], ref[2]) < 1e-10
