@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the HDG-IMEX step on one MI355X.
+
+Workload: the 256 x 256 unit square cut into 131072 triangles, pressure/trace
+degree k = 3 (velocity degree 4), stream-function initial velocity of seed 0,
+zero forcing, ARS(2,2,2) IMEX, dt = 1e-3, 3 Richardson iterations, trace
+systems solved by PCG with the P1-coarse-space multigrid, FP64.
+
+A step is one IMEX-HDG time step (Algorithm 1): two implicit stages of three
+Richardson iterations each (residual, tentative-velocity solve, weak
+divergence, hybridised mixed solve, update), the BDM interpolant per stage,
+the final projection and the pressure reconstruction.
+
+Metric: trace DOF-IMEX-stages per second = N_trace * (s-1) * steps / wall time,
+with the state resident on the device before the timed region starts.
+
+Output: one JSON line on stdout (everything else goes to stderr).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WORKLOAD = {"workload": "unit_square_256x256_k3_ars222", "n": 256, "k": 3, "seed": 0, "scheme": "ars222",
+            "dt": 1e-3, "n_richardson": 3, "trace_solver": "mg_pcg", "precision": "fp64",
+            # the paper's solver tolerances: trace system 1e-12, tentative velocity 1e-10
+            "rtol_trace": 1e-12, "rtol_velocity": 1e-10}
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_cost(kernel: str, k: int, nc: int, nF: int):
+    """(bytes, flops) that one launch of `kernel` must move / execute at minimum.
+
+    apply_step1_operator (mass-scaled Step I operator, matrix-free f_im): per
+    cell it reads the input velocity (2 ns doubles), the per-stage advection
+    data (2 nq_cell + 3 nq_facet doubles), det J and the three normals (7
+    doubles) and 12 int32 connectivity entries, and writes 2 ns doubles.
+    trace_spmv (facet-block ELL, FP64): per facet row 5 blocks of (k+1)^2
+    values, 5 int32 column ids, reads x and writes y ((k+1) doubles each).
+    """
+    ns = (k + 2) * (k + 3) // 2
+    nq1 = (3 * k + 4) // 2
+    nqc, nqf = nq1 * nq1, (3 * k + 5) // 2
+    nf = k + 1
+    if kernel == "apply_step1_operator":
+        nbytes = nc * (8 * (2 * ns + 2 * nqc + 3 * nqf + 7) + 4 * 12 + 8 * 2 * ns)
+        per_q_cell = 12 * ns + 6
+        per_q_facet = 12 * ns + 12
+        flops = nc * (nqc * per_q_cell + 3 * nqf * per_q_facet + 4 * ns)
+        return nbytes, flops
+    if kernel == "trace_spmv":
+        nbytes = nF * (8 * 5 * nf * nf + 4 * 5 + 8 * 2 * nf)
+        flops = nF * 2 * 5 * nf * nf
+        return nbytes, flops
+    return None, None
+
+
+def cpu_baseline(max_seconds: float = 30.0):
+    """The oracle (NumPy/SciPy, FP64, one thread) on a bounded sample: one step of
+    the same scheme, degree, dt, n_R and seed on the 32 x 32 mesh."""
+    from threadpoolctl import threadpool_limits
+
+    import numpy as np
+
+    import hdg_inputs as hi
+    from oracle.forms import Discretisation
+    from oracle.imex import IMEXHDG, ars222
+    n = 32
+    with threadpool_limits(limits=1):
+        X, C = hi.unit_square_mesh(n)
+        d = Discretisation(X, C, WORKLOAD["k"])
+        st = IMEXHDG(d, WORKLOAD["dt"], ars222(), WORKLOAD["n_richardson"])
+        par = hi.stream_function_params(WORKLOAD["seed"])
+        Q, p, lam = st.initial_state(lambda x, y: hi.streamfunction_velocity(par, x, y))
+        t0 = time.perf_counter()
+        Q, p, lam = st.step(Q, p, lam, 0.0)
+        el = time.perf_counter() - t0
+    assert np.all(np.isfinite(Q))
+    value = d.nT * (ars222().s - 1) / el
+    return {"value": value, "unit": "trace-DOF-stages/s", "cores": 1, "kind": "oracle",
+            "sample": f"one ARS(2,2,2) step, k=3, dt=1e-3, n_R=3, seed 0 on the 32x32 mesh ({d.nT} trace DOFs), "
+                      f"{el:.1f} s, one thread (SuperLU direct solves)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=WORKLOAD["n"], help="mesh size (experiments only)")
+    ap.add_argument("--k", type=int, default=WORKLOAD["k"], help="degree (experiments only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="do not time kernels with events")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
+              "(the multi-GPU decomposition is a design, not code)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import hdg_inputs as hi
+    from paper_2410_09790_amd import hdg
+
+    torch.cuda.set_device(0)
+    w = dict(WORKLOAD)
+    w["n"], w["k"] = args.n, args.k
+    if (args.n, args.k) != (WORKLOAD["n"], WORKLOAD["k"]):
+        w["workload"] = f"unit_square_{args.n}x{args.n}_k{args.k}_ars222"
+    X, C = hi.unit_square_mesh(w["n"])
+    t0 = time.perf_counter()
+    ctx = hdg.Context(X, C, degree=w["k"], imex=w["scheme"], n_richardson=w["n_richardson"],
+                      trace_solver=w["trace_solver"], rtol_trace=w["rtol_trace"],
+                      rtol_velocity=w["rtol_velocity"])
+    par = hi.stream_function_params(w["seed"])
+    xy = ctx.cell_points()
+    ctx.set_velocity_from_points(hi.streamfunction_velocity(par, xy[..., 0], xy[..., 1]))
+    torch.cuda.synchronize()
+    log(f"setup {time.perf_counter() - t0:.2f} s: {ctx.ncells} cells, {ctx.nT} trace DOFs, {ctx.nQ} velocity DOFs")
+    t0 = time.perf_counter()
+    ctx.advance(w["dt"], args.warmup)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} step(s) {time.perf_counter() - t0:.2f} s")
+    before = ctx.info()
+    if not args.no_profile:
+        ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.advance(w["dt"], args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    info = ctx.info()
+    ctx.profile(False)
+    Q, p, lam = ctx.get_state()
+    assert bool(torch.isfinite(Q).all()), "non-finite velocity"
+    stages = 2
+    value = ctx.nT * stages * args.steps / el
+    pcg = info["pcg_iterations_total"] - before["pcg_iterations_total"]
+    bicg = info["bicgstab_iterations_total"] - before["bicgstab_iterations_total"]
+    nsolves = info["trace_solves"] - before["trace_solves"]
+    nvel = info["velocity_solves"] - before["velocity_solves"]
+    log(f"BiCGStab iterations per solve (last): {info['bicgstab_iterations_last']}, restarts {info.get('bicgstab_restarts')}")
+    log(f"PCG iterations per solve (last): {info['pcg_iterations_last']}")
+    log(f"timed {args.steps} steps: {el:.3f} s, {1e3 * el / args.steps:.1f} ms/step; "
+        f"PCG {pcg} its over {nsolves} trace solves, BiCGStab {bicg} its over {nvel} velocity solves")
+    kernels = info.get("kernels", {})
+    for name, kv in sorted(kernels.items(), key=lambda kv: -kv[1]["ms"]):
+        if kv["launches"]:
+            log(f"  {name:24s} {kv['launches']:7d} launches {kv['ms']:10.2f} ms  {kv['ms'] / kv['launches'] * 1e3:9.1f} us/launch")
+    roofline = None
+    timed = {n_: kv for n_, kv in kernels.items() if kv["launches"] and algorithmic_cost(n_, 1, 1, 1)[0] is not None}
+    if timed:
+        dom = max(timed, key=lambda n_: timed[n_]["ms"])
+        nbytes, flops = algorithmic_cost(dom, w["k"], ctx.ncells, ctx.nfacets)
+        avg_s = timed[dom]["ms"] / timed[dom]["launches"] * 1e-3
+        t_mem, t_alu = nbytes / (HBM_PEAK_GBS * 1e9), flops / (FP64_PEAK_TFLOPS * 1e12)
+        if t_mem >= t_alu:
+            ach = nbytes / avg_s / 1e9
+            roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                        "algorithmic_bytes_per_launch": nbytes, "avg_launch_us": round(avg_s * 1e6, 2),
+                        "share_of_step": round(timed[dom]["ms"] * 1e-3 / el, 3)}
+        else:
+            ach = flops / avg_s / 1e12
+            roofline = {"bound": "alu", "achieved": round(ach, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(ach / FP64_PEAK_TFLOPS, 4), "traffic": None, "kernel": dom,
+                        "algorithmic_flops_per_launch": flops, "avg_launch_us": round(avg_s * 1e6, 2),
+                        "share_of_step": round(timed[dom]["ms"] * 1e-3 / el, 3)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline()
+        log(f"cpu baseline: {cpu['value']:.1f} {cpu['unit']} ({cpu['sample']})")
+    out = {
+        "metric": "trace DOF-IMEX-stages/sec (FP64)",
+        "value": value,
+        "unit": "trace-DOF-stages/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w["workload"], "cells": ctx.ncells, "trace_dofs": ctx.nT, "degree": w["k"],
+                   "imex": w["scheme"], "dt": w["dt"], "n_richardson": w["n_richardson"],
+                   "trace_solver": w["trace_solver"], "pcg_iterations": pcg, "trace_solves": nsolves,
+                   "bicgstab_iterations": bicg, "velocity_solves": nvel},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

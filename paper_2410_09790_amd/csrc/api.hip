@@ -100,9 +100,71 @@ struct TraceOp {
   double *cb = nullptr, *cx = nullptr;  // coarsest rhs / solution
 };
 
+// Optional per-kernel-class timing with HIP events on the context stream.
+enum KClass { KC_APPLY_OP = 0, KC_APPLY_RES, KC_TRACE_SPMV, KC_SMOOTH, KC_AMG, KC_CONDENSE, KC_RHS, KC_BACKSUB,
+              KC_BDM, KC_DIV, KC_RECON, KC_VECTOR, kNumKClass };
+static const char* kKClassName[kNumKClass] = {"apply_step1_operator", "apply_residual", "trace_spmv",
+                                              "trace_jacobi_sweep", "amg_coarse", "condense_assemble",
+                                              "rhs_condense", "backsub", "bdm", "weak_div", "recon_rhs",
+                                              "krylov_vector"};
+
+struct Profiler {
+  bool on = false;
+  hipStream_t st = nullptr;
+  std::vector<hipEvent_t> pool;
+  struct Pending { int cls; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  double ms[kNumKClass] = {};
+  long launches[kNumKClass] = {};
+  hipEvent_t get() {
+    if (pool.empty()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) throw std::runtime_error("hipEventCreate failed");
+      return e;
+    }
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  void harvest() {  // after a stream synchronisation
+    for (auto& p : pending) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) ms[p.cls] += t;
+      launches[p.cls] += 1;
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+  void reset() {
+    for (int i = 0; i < kNumKClass; ++i) { ms[i] = 0.0; launches[i] = 0; }
+  }
+  ~Profiler() {
+    for (auto& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+struct Timed {
+  Profiler& pr;
+  int cls;
+  hipEvent_t a = nullptr;
+  Timed(Profiler& p, int c) : pr(p), cls(c) {
+    if (pr.on) { a = pr.get(); (void)hipEventRecord(a, pr.st); }
+  }
+  ~Timed() {
+    if (pr.on && a) {
+      hipEvent_t b = pr.get();
+      (void)hipEventRecord(b, pr.st);
+      pr.pending.push_back({cls, a, b});
+    }
+  }
+};
+
 }  // namespace hdg
 
 struct hdg_ctx {
+  hdg::Profiler prof;
   hdg_params prm{};
   int k = 1;
   hipStream_t st = nullptr;
@@ -133,7 +195,7 @@ struct hdg_ctx {
   std::string err;
   // statistics
   std::vector<int> pcg_iters, bicg_iters;
-  long total_pcg = 0, total_bicg = 0, n_trace_solves = 0, n_velocity_solves = 0;
+  long total_pcg = 0, total_bicg = 0, n_trace_solves = 0, n_velocity_solves = 0, bicg_restarts = 0;
   double t_trace = 0.0, t_velocity = 0.0, t_other = 0.0;
   int max_pcg_bicg_seen = 0;
   bool not_converged = false;
@@ -153,7 +215,10 @@ struct hdg_ctx {
     HIPCHK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
     return d;
   }
-  void sync() { HIPCHK(hipStreamSynchronize(st)); }
+  void sync() {
+    HIPCHK(hipStreamSynchronize(st));
+    if (prof.on || !prof.pending.empty()) prof.harvest();
+  }
   double read_scalar(const double* d) {
     HIPCHK(hipMemcpyAsync(h_pinned, d, sizeof(double), hipMemcpyDeviceToHost, st));
     sync();
@@ -228,6 +293,7 @@ void hdg_ctx::setup() {
     stR[i] = dalloc<double>(nQ); stMQ[i] = dalloc<double>(nQ);
   }
   HIPCHK(hipHostMalloc((void**)&h_pinned, 64 * sizeof(double), hipHostMallocDefault));
+  prof.st = st;
   sync();
 }
 
@@ -243,10 +309,13 @@ TraceOp& hdg_ctx::trace_op(double c) {
   op->vals = dalloc<double>(5 * nF * nf * nf);
   op->cols = dalloc<int>(5 * nF);
   op->Dinv = dalloc<double>(nF * nf * nf);
-  launch_condense(k, st, dm, dt, c, prm.tau, op->Pinv, SK);
-  KCHK();
-  launch_assemble(k, st, dm, SK, op->vals, op->cols, op->Dinv);
-  KCHK();
+  {
+    Timed tm(prof, KC_CONDENSE);
+    launch_condense(k, st, dm, dt, c, prm.tau, op->Pinv, SK);
+    KCHK();
+    launch_assemble(k, st, dm, SK, op->vals, op->cols, op->Dinv);
+    KCHK();
+  }
   sync();
   HIPCHK(hipFree(SK));
   if (prm.trace_solver == HDG_TRACE_MG_PCG) build_mg(*op);
@@ -333,6 +402,7 @@ void hdg_ctx::vcycle(TraceOp& op, int l) {
     return;
   }
   DevLevel& L = op.levels[l];
+  Timed tm(prof, KC_AMG);
   launch_csr_jacobi(st, L.A, L.dinv, L.omega, L.b, nullptr, L.x);
   launch_csr_jacobi(st, L.A, L.dinv, L.omega, L.b, L.x, L.x2);
   launch_csr_spmv(st, L.A, L.x2, L.r, 0.0);
@@ -353,14 +423,18 @@ void hdg_ctx::vcycle(TraceOp& op, int l) {
 void hdg_ctx::mg_apply(TraceOp& op, const double* r, double* z) {
   const int nF = (int)hm.nF;
   const double om = 0.7;
-  launch_jacobi_sweep(k, st, nF, op.vals, op.cols, op.Dinv, om, r, nullptr, t1);
-  launch_jacobi_sweep(k, st, nF, op.vals, op.cols, op.Dinv, om, r, t1, t2);
-  launch_residual(k, st, nF, op.vals, op.cols, r, t2, t3);
+  {
+    Timed tm(prof, KC_SMOOTH);
+    launch_jacobi_sweep(k, st, nF, op.vals, op.cols, op.Dinv, om, r, nullptr, t1);
+    launch_jacobi_sweep(k, st, nF, op.vals, op.cols, op.Dinv, om, r, t1, t2);
+    launch_residual(k, st, nF, op.vals, op.cols, r, t2, t3);
+  }
   double* b0 = op.levels.empty() ? op.cb : op.levels[0].b;
   double* x0 = op.levels.empty() ? op.cx : op.levels[0].x;
   launch_csr_spmv(st, op.Rt, t3, b0, 0.0);
   vcycle(op, 0);
   launch_csr_spmv(st, op.Pt, x0, t2, 1.0);
+  Timed tm(prof, KC_SMOOTH);
   launch_jacobi_sweep(k, st, nF, op.vals, op.cols, op.Dinv, om, r, t2, t1);
   launch_jacobi_sweep(k, st, nF, op.vals, op.cols, op.Dinv, om, r, t1, z);
 }
@@ -390,7 +464,10 @@ int hdg_ctx::pcg(TraceOp& op, const double* gin, double* x) {
   launch_finish(st, part, kRedBlocks, rz);
   launch_copy(st, n, pz, pp);
   for (int it = 0; it < maxit; ++it) {
-    launch_spmv(k, st, nF, op.vals, op.cols, pp, pq);
+    {
+      Timed tm(prof, KC_TRACE_SPMV);
+      launch_spmv(k, st, nF, op.vals, op.cols, pp, pq);
+    }
     launch_dot(st, n, pp, pq, part);
     launch_finish(st, part, kRedBlocks, pqv + it);
     launch_pcg_update(st, n, rz + it, pqv + it, pp, pq, x, pr, part);
@@ -412,8 +489,11 @@ void hdg_ctx::solve_trace(double c, const double* Fw, const double* Fpsi, const 
                           double* lout) {
   auto t0 = std::chrono::steady_clock::now();
   TraceOp& op = trace_op(c);
-  launch_rhs_condense(k, st, dm, dt, c, prm.tau, op.Pinv, Fw, Fpsi, ycell);
-  launch_gather_rhs(k, st, dm, ycell, Fmu, g);
+  {
+    Timed tm(prof, KC_RHS);
+    launch_rhs_condense(k, st, dm, dt, c, prm.tau, op.Pinv, Fw, Fpsi, ycell);
+    launch_gather_rhs(k, st, dm, ycell, Fmu, g);
+  }
   // remove the component along the null vector (constant trace = e_0 on every facet)
   launch_dot_sub(st, hm.nF, nf, 0, g, part);
   launch_finish(st, part, kRedBlocks, scal + 3 * (prm.max_it_trace + 4));
@@ -424,7 +504,10 @@ void hdg_ctx::solve_trace(double c, const double* Fw, const double* Fpsi, const 
   total_pcg += its;
   ++n_trace_solves;
   const long nb = (hm.nc + kBlock - 1) / kBlock;
-  launch_backsub(k, st, dm, dt, c, prm.tau, op.Pinv, Fw, Fpsi, lout, U, pout, part);
+  {
+    Timed tm(prof, KC_BACKSUB);
+    launch_backsub(k, st, dm, dt, c, prm.tau, op.Pinv, Fw, Fpsi, lout, U, pout, part);
+  }
   launch_finish_mean(st, part, (int)nb, area, scal + 3 * (prm.max_it_trace + 4) + 1);
   launch_shift_mean(k, st, dm, scal + 3 * (prm.max_it_trace + 4) + 1, pout, lout);
   KCHK();
@@ -432,46 +515,85 @@ void hdg_ctx::solve_trace(double c, const double* Fw, const double* Fpsi, const 
   t_trace += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
-// BiCGStab on the mass-scaled Step I operator  x - (adt/det) f_im(x) = b
+// BiCGStab on the mass-scaled Step I operator  x - (adt/det) f_im(x) = b,
+// restarted from the current iterate (true residual, new shadow vector) when
+// rho or omega break down.
 int hdg_ctx::bicgstab(double adt, const double* b, double* x) {
   const long n = nQ;
   const int maxit = prm.max_it_velocity;
   launch_fill(st, n, 0.0, x);
   launch_copy(st, n, b, br);
-  launch_copy(st, n, b, brh);
   launch_dot(st, n, br, nullptr, part);
   launch_finish(st, part, kRedBlocks, bsc);
-  launch_copy(st, 1, bsc, bsc + 4);
   const double bnorm = std::sqrt(read_scalar(bsc));
   if (bnorm == 0.0) return 0;
+  int j = 0;  // iteration index since the last (re)start
+  bool restart = true;
+  double best = bnorm;
+  int restarts = 0;
   for (int it = 0; it < maxit; ++it) {
-    launch_bicg_p(st, n, bsc, it, br, bv, bp);
-    launch_apply(k, st, 0, dm, dt, adv, prm.alpha, adt, bp, nullptr, nullptr, nullptr, bv);
+    if (restart) {
+      if (it > 0) {  // true residual r = b - A x
+        {
+          Timed tm(prof, KC_APPLY_OP);
+          launch_apply(k, st, 0, dm, dt, adv, prm.alpha, adt, x, nullptr, nullptr, nullptr, bt);
+        }
+        launch_copy(st, n, b, br);
+        launch_axpby(st, n, -1.0, bt, 1.0, br);
+        ++restarts;
+        ++bicg_restarts;
+        if (restarts > 50) throw SolverBreakdown("BiCGStab: too many restarts");
+      }
+      launch_copy(st, n, br, brh);
+      launch_dot(st, n, br, nullptr, part);
+      launch_finish(st, part, kRedBlocks, bsc);
+      launch_copy(st, 1, bsc, bsc + 4);
+      j = 0;
+      restart = false;
+    }
+    launch_bicg_p(st, n, bsc, j, br, bv, bp);
+    {
+      Timed tm(prof, KC_APPLY_OP);
+      launch_apply(k, st, 0, dm, dt, adv, prm.alpha, adt, bp, nullptr, nullptr, nullptr, bv);
+    }
     launch_dot(st, n, brh, bv, part);
-    launch_finish(st, part, kRedBlocks, bsc + 8 * it + 1);
-    launch_bicg_s(st, n, bsc, it, br, bv, bs);
-    launch_apply(k, st, 0, dm, dt, adv, prm.alpha, adt, bs, nullptr, nullptr, nullptr, bt);
+    launch_finish(st, part, kRedBlocks, bsc + 8 * j + 1);
+    launch_bicg_s(st, n, bsc, j, br, bv, bs);
+    {
+      Timed tm(prof, KC_APPLY_OP);
+      launch_apply(k, st, 0, dm, dt, adv, prm.alpha, adt, bs, nullptr, nullptr, nullptr, bt);
+    }
     launch_dot2(st, n, bt, bs, bt, part2);
-    launch_finish2(st, part2, bsc + 8 * it + 2);
-    launch_bicg_xr(st, n, bsc, it, bp, bs, bt, x, br, brh, part2);
-    launch_finish2(st, part2, bsc + 8 * (it + 1));
+    launch_finish2(st, part2, bsc + 8 * j + 2);
+    launch_bicg_xr(st, n, bsc, j, bp, bs, bt, x, br, brh, part2);
+    launch_finish2(st, part2, bsc + 8 * (j + 1));
     KCHK();
-    HIPCHK(hipMemcpyAsync(h_pinned, bsc + 8 * (it + 1), 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+    // scalars of this iteration: [8j..8j+3] and the new (rhat.r, r.r)
+    HIPCHK(hipMemcpyAsync(h_pinned, bsc + 8 * j, 10 * sizeof(double), hipMemcpyDeviceToHost, st));
     sync();
-    // finish2 wrote rhat.r into [0] and r.r into [1]; keep r.r in slot 4 as documented
-    const double rr = h_pinned[1];
-    launch_copy(st, 1, bsc + 8 * (it + 1) + 1, bsc + 8 * (it + 1) + 4);
+    const double rho = h_pinned[0], rv = h_pinned[1], tt = h_pinned[3];
+    const double rho_new = h_pinned[8], rr = h_pinned[9];
+    // keep r.r in slot 4 of the new iteration (slot 1 is reused for rhat.v)
+    launch_copy(st, 1, bsc + 8 * (j + 1) + 1, bsc + 8 * (j + 1) + 4);
     const double res = std::sqrt(rr);
     if (!(res == res)) throw SolverBreakdown("BiCGStab breakdown (NaN residual); the result is invalid");
+    best = std::min(best, res);
     if (res <= prm.rtol_velocity * bnorm) return it + 1;
+    ++j;
+    const bool bad = rv == 0.0 || tt == 0.0 || !(std::fabs(rho_new) > 1e-30 * rr) || !(std::fabs(rho) > 0.0) ||
+                     8 * (j + 2) > 8 * (maxit + 2);
+    if (bad) restart = true;
   }
   not_converged = true;
   return maxit;
 }
 
 void hdg_ctx::reconstruct(const double* Qin, double* pout, double* lout) {
-  launch_recon_rhs(k, st, dm, dt, Qin, fpsi);
-  KCHK();
+  {
+    Timed tm(prof, KC_RECON);
+    launch_recon_rhs(k, st, dm, dt, Qin, fpsi);
+    KCHK();
+  }
   solve_trace(1.0, nullptr, fpsi, nullptr, Ut, pout, lout);
 }
 
@@ -479,14 +601,20 @@ void hdg_ctx::reconstruct(const double* Qin, double* pout, double* lout) {
 void hdg_ctx::richardson(double adt, const double* r, double* Qv, double* pv, double* lv) {
   for (int it = 0; it < prm.n_richardson; ++it) {
     auto t0 = std::chrono::steady_clock::now();
-    launch_apply(k, st, 1, dm, dt, adv, prm.alpha, adt, Qv, r, pv, lv, dr);  // delta r / det
-    KCHK();
+    {
+      Timed tm(prof, KC_APPLY_RES);
+      launch_apply(k, st, 1, dm, dt, adv, prm.alpha, adt, Qv, r, pv, lv, dr);  // delta r / det
+      KCHK();
+    }
     const int its = bicgstab(adt, dr, Qbar);  // Step I
     bicg_iters.push_back(its);
     total_bicg += its;
     ++n_velocity_solves;
-    launch_div(k, st, dm, dt, Qbar, -1.0 / adt, fpsi);  // Step II data
-    KCHK();
+    {
+      Timed tm(prof, KC_DIV);
+      launch_div(k, st, dm, dt, Qbar, -1.0 / adt, fpsi);  // Step II data
+      KCHK();
+    }
     sync();
     t_velocity += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     solve_trace(1.0, nullptr, fpsi, nullptr, dQ, dp, dl);
@@ -516,8 +644,11 @@ void hdg_ctx::step(double dtv) {
       launch_axpby(st, nQ, w, stMQ[j], 1.0, stR[i]);
       launch_axpby(st, nQ, -w, stR[j], 1.0, stR[i]);
     }
-    launch_bdm(k, st, dm, dt, stQ[i - 1], Qs);
-    launch_prep_adv(k, st, dm, dt, Qs, prm.delta_up, adv);
+    {
+      Timed tm(prof, KC_BDM);
+      launch_bdm(k, st, dm, dt, stQ[i - 1], Qs);
+      launch_prep_adv(k, st, dm, dt, Qs, prm.delta_up, adv);
+    }
     launch_copy(st, nQ, stQ[i - 1], stQ[i]);
     launch_copy(st, nP, stP[i - 1], stP[i]);
     launch_copy(st, nT, stL[i - 1], stL[i]);
@@ -776,6 +907,16 @@ int hdg_reconstruct_pressure(hdg_ctx* ctx, const double* Qv, double* pv, double*
   API_END(ctx)
 }
 
+int hdg_profile(hdg_ctx* ctx, int enable) {
+  if (!ctx) return HDG_ERR_INVALID_ARG;
+  ctx->not_converged = false;
+  API_BEGIN
+  ctx->sync();
+  ctx->prof.reset();
+  ctx->prof.on = enable != 0;
+  API_END(ctx)
+}
+
 int hdg_get_info(const hdg_ctx* ctx, char* buf, size_t cap) {
   if (!ctx || !buf || cap == 0) return HDG_ERR_INVALID_ARG;
   auto last = [](const std::vector<int>& v, size_t n) {
@@ -790,10 +931,16 @@ int hdg_get_info(const hdg_ctx* ctx, char* buf, size_t cap) {
                   ",\"pcg_iterations_total\":" + std::to_string(ctx->total_pcg) +
                   ",\"velocity_solves\":" + std::to_string(ctx->n_velocity_solves) +
                   ",\"bicgstab_iterations_total\":" + std::to_string(ctx->total_bicg) +
+                  ",\"bicgstab_restarts\":" + std::to_string(ctx->bicg_restarts) +
                   ",\"pcg_iterations_last\":" + last(ctx->pcg_iters, 16) +
                   ",\"bicgstab_iterations_last\":" + last(ctx->bicg_iters, 16) +
                   ",\"seconds_trace\":" + std::to_string(ctx->t_trace) +
-                  ",\"seconds_velocity\":" + std::to_string(ctx->t_velocity) + "}";
+                  ",\"seconds_velocity\":" + std::to_string(ctx->t_velocity) + ",\"kernels\":{";
+  for (int i = 0; i < kNumKClass; ++i) {
+    s += std::string(i ? "," : "") + "\"" + kKClassName[i] + "\":{\"launches\":" +
+         std::to_string(ctx->prof.launches[i]) + ",\"ms\":" + std::to_string(ctx->prof.ms[i]) + "}";
+  }
+  s += "}}";
   std::snprintf(buf, cap, "%s", s.c_str());
   return s.size() < cap ? HDG_OK : HDG_ERR_INVALID_ARG;
 }

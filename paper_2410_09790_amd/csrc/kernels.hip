@@ -991,8 +991,13 @@ __global__ void k_pcg_direction(long n, const double* __restrict__ rzn, const do
 
 // BiCGStab scalars, 8 per iteration i: [0] rho_i = rhat.r_i, [1] rhat.v_i,
 // [2] t.s, [3] t.t, [4] r_i.r_i
-__device__ __forceinline__ double bicg_alpha(const double* sc, int i) { return sc[8 * i] / sc[8 * i + 1]; }
-__device__ __forceinline__ double bicg_omega(const double* sc, int i) { return sc[8 * i + 2] / sc[8 * i + 3]; }
+// alpha and omega fall back to 0 on an exact breakdown; the host then restarts
+__device__ __forceinline__ double bicg_alpha(const double* sc, int i) {
+  return sc[8 * i + 1] != 0.0 ? sc[8 * i] / sc[8 * i + 1] : 0.0;
+}
+__device__ __forceinline__ double bicg_omega(const double* sc, int i) {
+  return sc[8 * i + 3] > 0.0 ? sc[8 * i + 2] / sc[8 * i + 3] : 0.0;
+}
 
 __global__ void k_bicg_p(long n, const double* __restrict__ sc, int it, const double* __restrict__ r,
                          const double* __restrict__ v, double* __restrict__ p) {

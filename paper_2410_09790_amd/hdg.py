@@ -25,7 +25,7 @@ EXPORTS = [
     "hdg_default_params", "hdg_create", "hdg_destroy", "hdg_last_error", "hdg_sizes", "hdg_cell_points",
     "hdg_set_velocity_from_points", "hdg_set_state", "hdg_get_state", "hdg_advance", "hdg_solve_trace",
     "hdg_trace_matvec", "hdg_bdm_project", "hdg_weak_divergence", "hdg_momentum_residual",
-    "hdg_tentative_velocity", "hdg_reconstruct_pressure", "hdg_get_info",
+    "hdg_tentative_velocity", "hdg_reconstruct_pressure", "hdg_profile", "hdg_get_info",
 ]
 
 
@@ -82,6 +82,7 @@ def load_library(path: str = LIB_PATH):
         "hdg_momentum_residual": (I, [P, D, P, P, P, P, P, P]),
         "hdg_tentative_velocity": (I, [P, D, P, P, P]),
         "hdg_reconstruct_pressure": (I, [P, P, P, P]),
+        "hdg_profile": (I, [P, I]),
         "hdg_get_info": (I, [P, ctypes.c_char_p, ctypes.c_size_t]),
     }
     for name, (res, args) in sig.items():
@@ -218,6 +219,9 @@ class Context:
         p, lam = self._empty(self.nP), self._empty(self.nT)
         self._check(self._lib.hdg_reconstruct_pressure(self._h, _ptr(Q), _ptr(p), _ptr(lam)))
         return p, lam
+
+    def profile(self, enable: bool):
+        self._check(self._lib.hdg_profile(self._h, int(bool(enable))))
 
     def info(self) -> dict:
         buf = ctypes.create_string_buffer(1 << 16)
