@@ -79,14 +79,16 @@ typedef struct {
   int n_richardson;      /* n_R of Algorithm 2 */
   int trace_solver;      /* hdg_trace_solver */
   double rtol_trace;     /* PCG: ||g - S lam||_2 <= rtol ||g||_2 */
-  double rtol_velocity;  /* Step I BiCGStab: same criterion on the mass-scaled system */
+  double rtol_velocity;  /* Step I: same criterion on the mass-scaled system */
   int max_it_trace;
   int max_it_velocity;
   int pressure_update;   /* hdg_pressure_update */
+  int idr_s;             /* Step I Krylov method: IDR(s) with this s (1..8), or 0 = BiCGStab */
 } hdg_params;
 
 /* Fill p with the defaults: k=1, tau=alpha=delta_up=1, ARS(2,2,2), n_R=3,
- * MG-PCG, rtol 1e-12 for both solvers, caps 5000 / 20000, reconstruction. */
+ * MG-PCG, rtol 1e-12 for both solvers, caps 5000 / 20000, reconstruction,
+ * BiCGStab for Step I. */
 void hdg_default_params(hdg_params* p);
 
 /* Create a context on the current HIP device.  coords: host [nv][2];

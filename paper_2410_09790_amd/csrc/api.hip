@@ -180,7 +180,7 @@ struct hdg_ctx {
   // work vectors
   double *ycell = nullptr, *g = nullptr, *part = nullptr, *part2 = nullptr, *scal = nullptr;
   double *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr, *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;
-  double *bx = nullptr, *br = nullptr, *brh = nullptr, *bp = nullptr, *bv = nullptr, *bs = nullptr, *bt = nullptr,
+  double *bb = nullptr, *bx = nullptr, *br = nullptr, *brh = nullptr, *bp = nullptr, *bv = nullptr, *bs = nullptr, *bt = nullptr,
          *bsc = nullptr;
   double *adv = nullptr, *Qs = nullptr, *dr = nullptr, *Qbar = nullptr, *dQ = nullptr, *dp = nullptr, *dl = nullptr,
          *fpsi = nullptr, *Ut = nullptr;
@@ -235,6 +235,11 @@ struct hdg_ctx {
   void solve_trace(double c, const double* Fw, const double* Fpsi, const double* Fmu, double* U, double* p,
                    double* lam);
   int bicgstab(double adt, const double* b, double* x);
+  int idrs(double adt, const double* b, double* x);
+  int velocity_solve(double adt, const double* b, double* x) {
+    return prm.idr_s > 0 ? idrs(adt, b, x) : bicgstab(adt, b, x);
+  }
+  double *iP = nullptr, *iG = nullptr, *iU = nullptr, *ired = nullptr;
   void reconstruct(const double* Qin, double* pout, double* lout);
   void richardson(double adt, const double* r, double* Q, double* p, double* lam);
   void step(double dt);
@@ -263,26 +268,27 @@ void hdg_ctx::setup() {
   dm.cf_flip = upload(hm.cf_flip);
   dm.fc_cell = upload(hm.fc_cell);
   dm.fc_f = upload(hm.fc_f);
-  // tables
-  dt.Bu = upload(rt.Bu); dt.Gux = upload(rt.Gux); dt.Guy = upload(rt.Guy);
-  dt.Bp = upload(rt.Bp); dt.Gpx = upload(rt.Gpx); dt.Gpy = upload(rt.Gpy); dt.cw = upload(rt.cq_w);
-  dt.FBu = upload(rt.FBu); dt.FGux = upload(rt.FGux); dt.FGuy = upload(rt.FGuy); dt.FBp = upload(rt.FBp);
-  dt.fw = upload(rt.fq_w); dt.MU = upload(rt.MU); dt.NUB = upload(rt.NUB);
-  dt.Dx = upload(rt.Dx); dt.Dy = upload(rt.Dy); dt.Rx = upload(rt.Rx); dt.Ry = upload(rt.Ry);
-  dt.Chat = upload(rt.Chat); dt.That = upload(rt.That); dt.Ehat = upload(rt.Ehat); dt.CC = upload(rt.CC);
-  dt.KDD = upload(rt.KDD); dt.CD = upload(rt.CD); dt.BDMinv = upload(rt.BDMinv); dt.NED = upload(rt.NED);
+  // tables (constant address space on the device side)
+  auto cu = [&](const std::vector<double>& v) { return (cdptr)upload(v); };
+  dt.Bu = cu(rt.Bu); dt.Gux = cu(rt.Gux); dt.Guy = cu(rt.Guy);
+  dt.Bp = cu(rt.Bp); dt.Gpx = cu(rt.Gpx); dt.Gpy = cu(rt.Gpy); dt.cw = cu(rt.cq_w);
+  dt.FBu = cu(rt.FBu); dt.FGux = cu(rt.FGux); dt.FGuy = cu(rt.FGuy); dt.FBp = cu(rt.FBp);
+  dt.fw = cu(rt.fq_w); dt.MU = cu(rt.MU); dt.NUB = cu(rt.NUB);
+  dt.Dx = cu(rt.Dx); dt.Dy = cu(rt.Dy); dt.Rx = cu(rt.Rx); dt.Ry = cu(rt.Ry);
+  dt.Chat = cu(rt.Chat); dt.That = cu(rt.That); dt.Ehat = cu(rt.Ehat); dt.CC = cu(rt.CC);
+  dt.KDD = cu(rt.KDD); dt.CD = cu(rt.CD); dt.BDMinv = cu(rt.BDMinv); dt.NED = cu(rt.NED);
   // work
   const long nb = (nc + kBlock - 1) / kBlock;
   ycell = dalloc<double>(nc * nlam);
   g = dalloc<double>(nT);
-  part = dalloc<double>(std::max<long>(kRedBlocks, nb));
+  part = dalloc<double>(std::max<long>((long)kRedBlocks * kIdrMax, 4 * nb + 16));
   part2 = dalloc<double>(2 * kRedBlocks);
   const int mt = prm.max_it_trace + 4, mv = prm.max_it_velocity + 4;
   scal = dalloc<double>(3 * mt + 16);
   bsc = dalloc<double>(8 * (long)mv + 16);
   pr = dalloc<double>(nT); pz = dalloc<double>(nT); pp = dalloc<double>(nT); pq = dalloc<double>(nT);
   t1 = dalloc<double>(nT); t2 = dalloc<double>(nT); t3 = dalloc<double>(nT);
-  bx = dalloc<double>(nQ); br = dalloc<double>(nQ); brh = dalloc<double>(nQ); bp = dalloc<double>(nQ);
+  bb = dalloc<double>(nQ); bx = dalloc<double>(nQ); br = dalloc<double>(nQ); brh = dalloc<double>(nQ); bp = dalloc<double>(nQ);
   bv = dalloc<double>(nQ); bs = dalloc<double>(nQ); bt = dalloc<double>(nQ);
   adv = dalloc<double>((long)nc * (2 * nqc + 3 * nqf));
   Qs = dalloc<double>(nQ); dr = dalloc<double>(nQ); Qbar = dalloc<double>(nQ); dQ = dalloc<double>(nQ);
@@ -515,34 +521,43 @@ void hdg_ctx::solve_trace(double c, const double* Fw, const double* Fpsi, const 
   t_trace += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
-// BiCGStab on the mass-scaled Step I operator  x - (adt/det) f_im(x) = b,
-// restarted from the current iterate (true residual, new shadow vector) when
-// rho or omega break down.
-int hdg_ctx::bicgstab(double adt, const double* b, double* x) {
+// BiCGStab on the mass-scaled Step I operator  x - (adt/det) f_im(x) = b.
+// Vectors are kept structure-of-arrays inside the solver (coalesced loads in
+// the two-threads-per-cell operator kernel, which also produces the dot
+// products BiCGStab needs next).  The residual is checked on the host every
+// kCheck iterations; alpha and omega are guarded on the device, and a
+// breakdown restarts from the current iterate with the true residual.
+int hdg_ctx::bicgstab(double adt, const double* b_aos, double* x_aos) {
+  constexpr int kCheck = 4;
   const long n = nQ;
   const int maxit = prm.max_it_velocity;
+  const int nbk = apply_soa_blocks(hm.nc);
+  double* b = bb;
+  double* x = bx;
+  launch_to_soa(k, st, dm, 0, b_aos, b);
   launch_fill(st, n, 0.0, x);
   launch_copy(st, n, b, br);
   launch_dot(st, n, br, nullptr, part);
   launch_finish(st, part, kRedBlocks, bsc);
   const double bnorm = std::sqrt(read_scalar(bsc));
-  if (bnorm == 0.0) return 0;
-  int j = 0;  // iteration index since the last (re)start
+  if (bnorm == 0.0) {
+    launch_fill(st, n, 0.0, x_aos);
+    return 0;
+  }
+  int j = 0, it = 0;
   bool restart = true;
-  double best = bnorm;
   int restarts = 0;
-  for (int it = 0; it < maxit; ++it) {
+  while (it < maxit) {
     if (restart) {
       if (it > 0) {  // true residual r = b - A x
         {
           Timed tm(prof, KC_APPLY_OP);
-          launch_apply(k, st, 0, dm, dt, adv, prm.alpha, adt, x, nullptr, nullptr, nullptr, bt);
+          launch_apply_soa(k, st, 0, dm, dt, adv, prm.alpha, adt, x, nullptr, bt, nullptr);
         }
         launch_copy(st, n, b, br);
         launch_axpby(st, n, -1.0, bt, 1.0, br);
-        ++restarts;
         ++bicg_restarts;
-        if (restarts > 50) throw SolverBreakdown("BiCGStab: too many restarts");
+        if (++restarts > 50) throw SolverBreakdown("BiCGStab: too many restarts");
       }
       launch_copy(st, n, br, brh);
       launch_dot(st, n, br, nullptr, part);
@@ -554,38 +569,151 @@ int hdg_ctx::bicgstab(double adt, const double* b, double* x) {
     launch_bicg_p(st, n, bsc, j, br, bv, bp);
     {
       Timed tm(prof, KC_APPLY_OP);
-      launch_apply(k, st, 0, dm, dt, adv, prm.alpha, adt, bp, nullptr, nullptr, nullptr, bv);
+      launch_apply_soa(k, st, 1, dm, dt, adv, prm.alpha, adt, bp, brh, bv, part);
     }
-    launch_dot(st, n, brh, bv, part);
-    launch_finish(st, part, kRedBlocks, bsc + 8 * j + 1);
+    launch_finish_sets(st, part, nbk, 1, bsc + 8 * j + 1);
     launch_bicg_s(st, n, bsc, j, br, bv, bs);
     {
       Timed tm(prof, KC_APPLY_OP);
-      launch_apply(k, st, 0, dm, dt, adv, prm.alpha, adt, bs, nullptr, nullptr, nullptr, bt);
+      launch_apply_soa(k, st, 2, dm, dt, adv, prm.alpha, adt, bs, nullptr, bt, part);
     }
-    launch_dot2(st, n, bt, bs, bt, part2);
-    launch_finish2(st, part2, bsc + 8 * j + 2);
+    launch_finish_sets(st, part, nbk, 2, bsc + 8 * j + 2);
     launch_bicg_xr(st, n, bsc, j, bp, bs, bt, x, br, brh, part2);
     launch_finish2(st, part2, bsc + 8 * (j + 1));
-    KCHK();
-    // scalars of this iteration: [8j..8j+3] and the new (rhat.r, r.r)
-    HIPCHK(hipMemcpyAsync(h_pinned, bsc + 8 * j, 10 * sizeof(double), hipMemcpyDeviceToHost, st));
-    sync();
-    const double rho = h_pinned[0], rv = h_pinned[1], tt = h_pinned[3];
-    const double rho_new = h_pinned[8], rr = h_pinned[9];
     // keep r.r in slot 4 of the new iteration (slot 1 is reused for rhat.v)
     launch_copy(st, 1, bsc + 8 * (j + 1) + 1, bsc + 8 * (j + 1) + 4);
-    const double res = std::sqrt(rr);
-    if (!(res == res)) throw SolverBreakdown("BiCGStab breakdown (NaN residual); the result is invalid");
-    best = std::min(best, res);
-    if (res <= prm.rtol_velocity * bnorm) return it + 1;
+    KCHK();
+    ++it;
     ++j;
-    const bool bad = rv == 0.0 || tt == 0.0 || !(std::fabs(rho_new) > 1e-30 * rr) || !(std::fabs(rho) > 0.0) ||
-                     8 * (j + 2) > 8 * (maxit + 2);
-    if (bad) restart = true;
+    if (it % kCheck == 0 || it >= maxit || 8 * (j + 2) > 8 * (maxit + 2)) {
+      HIPCHK(hipMemcpyAsync(h_pinned, bsc + 8 * (j - 1), 10 * sizeof(double), hipMemcpyDeviceToHost, st));
+      sync();
+      const double rv = h_pinned[1], tt = h_pinned[3], rho_new = h_pinned[8], rr = h_pinned[9];
+      const double res = std::sqrt(rr);
+      if (!(res == res)) throw SolverBreakdown("BiCGStab breakdown (NaN residual); the result is invalid");
+      if (res <= prm.rtol_velocity * bnorm) break;
+      if (rv == 0.0 || tt == 0.0 || !(std::fabs(rho_new) > 1e-30 * rr) || 8 * (j + 2) > 8 * (maxit + 2))
+        restart = true;
+    }
   }
-  not_converged = true;
-  return maxit;
+  if (it >= maxit) not_converged = true;
+  launch_to_aos(k, st, dm, x, x_aos);
+  KCHK();
+  return it;
+}
+
+// IDR(s) with bi-orthogonalisation on the mass-scaled Step I operator.  The
+// shadow space is spanned by s counter-based random vectors, orthonormalised
+// once.  Each inner step needs one operator application and one pass of s
+// dot products; the small triangular systems are solved on the host.  The
+// dimension-reduction step uses omega from the local minimal residual,
+// enlarged when the angle between t and r is small (|cos| < 0.7).
+int hdg_ctx::idrs(double adt, const double* b, double* x) {
+  const long n = nQ;
+  const int s = prm.idr_s;
+  const int maxit = prm.max_it_velocity;
+  if (!iP) {
+    iP = dalloc<double>((long)s * n);
+    iG = dalloc<double>((long)s * n);
+    iU = dalloc<double>((long)s * n);
+    ired = dalloc<double>(kIdrMax + 8);
+    for (int j = 0; j < s; ++j) {  // modified Gram-Schmidt
+      double* pj = iP + (long)j * n;
+      launch_random(st, n, 0x5eedull + 7919ull * j, pj);
+      for (int i = 0; i < j; ++i) {
+        launch_dot(st, n, iP + (long)i * n, pj, part);
+        launch_finish(st, part, kRedBlocks, ired);
+        const double d = read_scalar(ired);
+        launch_axpby(st, n, -d, iP + (long)i * n, 1.0, pj);
+      }
+      launch_dot(st, n, pj, nullptr, part);
+      launch_finish(st, part, kRedBlocks, ired);
+      const double nrm = std::sqrt(read_scalar(ired));
+      launch_axpby(st, n, 0.0, pj, 1.0 / nrm, pj);
+    }
+    KCHK();
+  }
+  launch_fill(st, n, 0.0, x);
+  launch_copy(st, n, b, br);
+  launch_fill(st, (long)s * n, 0.0, iG);
+  launch_fill(st, (long)s * n, 0.0, iU);
+  launch_dot(st, n, br, nullptr, part);
+  launch_finish(st, part, kRedBlocks, ired);
+  const double bnorm = std::sqrt(read_scalar(ired));
+  if (bnorm == 0.0) return 0;
+  const double tol = prm.rtol_velocity * bnorm;
+  double M[kIdrMax][kIdrMax] = {}, f[kIdrMax], m[kIdrMax];
+  for (int i = 0; i < s; ++i) M[i][i] = 1.0;
+  double om = 1.0, normr = bnorm;
+  int it = 0;
+  auto read_vec = [&](int cnt, double* out) {
+    HIPCHK(hipMemcpyAsync(h_pinned, ired, cnt * sizeof(double), hipMemcpyDeviceToHost, st));
+    sync();
+    for (int i = 0; i < cnt; ++i) out[i] = h_pinned[i];
+  };
+  while (normr > tol && it < maxit) {
+    launch_multidot(st, n, s, iP, br, part, ired);
+    read_vec(s, f);
+    for (int kk = 0; kk < s; ++kk) {
+      IdrCoef c{};
+      for (int i = kk; i < s; ++i) {  // M(kk:s, kk:s) c = f(kk:s), lower triangular
+        double v = f[i];
+        for (int j = kk; j < i; ++j) v -= M[i][j] * c.v[j - kk];
+        c.v[i - kk] = v / M[i][i];
+      }
+      launch_idr_u(st, n, kk, s, c, om, br, iG, iU);
+      {
+        Timed tm(prof, KC_APPLY_OP);
+        launch_apply(k, st, 0, dm, dt, adv, prm.alpha, adt, iU + (long)kk * n, nullptr, nullptr, nullptr,
+                     iG + (long)kk * n);
+      }
+      launch_multidot(st, n, s, iP, iG + (long)kk * n, part, ired);
+      read_vec(s, m);
+      IdrCoef al{};
+      for (int i = 0; i < kk; ++i) {  // bi-orthogonalise against P_0..P_{kk-1}
+        double v = m[i];
+        for (int j = 0; j < i; ++j) v -= M[i][j] * al.v[j];
+        al.v[i] = v / M[i][i];
+      }
+      for (int i = kk; i < s; ++i) {
+        double v = m[i];
+        for (int j = 0; j < kk; ++j) v -= al.v[j] * M[i][j];
+        M[i][kk] = v;
+      }
+      if (M[kk][kk] == 0.0) throw SolverBreakdown("IDR(s) breakdown (M_kk = 0)");
+      const double beta = f[kk] / M[kk][kk];
+      launch_idr_update(st, n, kk, al, beta, iG, iU, br, x, part);
+      launch_finish(st, part, kRedBlocks, ired);
+      KCHK();
+      normr = std::sqrt(read_scalar(ired));
+      if (!(normr == normr)) throw SolverBreakdown("IDR(s) breakdown (NaN residual)");
+      ++it;
+      if (normr <= tol || it >= maxit) break;
+      for (int i = kk + 1; i < s; ++i) f[i] -= beta * M[i][kk];
+    }
+    if (normr <= tol || it >= maxit) break;
+    {
+      Timed tm(prof, KC_APPLY_OP);
+      launch_apply(k, st, 0, dm, dt, adv, prm.alpha, adt, br, nullptr, nullptr, nullptr, bt);
+    }
+    launch_dot2(st, n, bt, br, bt, part2);
+    launch_finish2(st, part2, ired);
+    double tr_tt[2];
+    read_vec(2, tr_tt);
+    if (!(tr_tt[1] > 0.0)) throw SolverBreakdown("IDR(s) breakdown (t = 0)");
+    om = tr_tt[0] / tr_tt[1];
+    const double rho = std::fabs(tr_tt[0]) / (std::sqrt(tr_tt[1]) * normr);
+    if (rho < 0.7) om *= 0.7 / rho;
+    if (om == 0.0) throw SolverBreakdown("IDR(s) breakdown (omega = 0)");
+    launch_idr_reduce(st, n, om, bt, br, x, part);
+    launch_finish(st, part, kRedBlocks, ired);
+    KCHK();
+    normr = std::sqrt(read_scalar(ired));
+    if (!(normr == normr)) throw SolverBreakdown("IDR(s) breakdown (NaN residual)");
+    ++it;
+  }
+  if (normr > tol) not_converged = true;
+  return it;
 }
 
 void hdg_ctx::reconstruct(const double* Qin, double* pout, double* lout) {
@@ -606,7 +734,7 @@ void hdg_ctx::richardson(double adt, const double* r, double* Qv, double* pv, do
       launch_apply(k, st, 1, dm, dt, adv, prm.alpha, adt, Qv, r, pv, lv, dr);  // delta r / det
       KCHK();
     }
-    const int its = bicgstab(adt, dr, Qbar);  // Step I
+    const int its = velocity_solve(adt, dr, Qbar);  // Step I
     bicg_iters.push_back(its);
     total_bicg += its;
     ++n_velocity_solves;
@@ -704,6 +832,7 @@ void hdg_default_params(hdg_params* p) {
   p->max_it_trace = 5000;
   p->max_it_velocity = 20000;
   p->pressure_update = HDG_PRESSURE_RECONSTRUCT;
+  p->idr_s = 0;
 }
 
 int hdg_create(int64_t nv, const double* coords, int64_t nc, const int32_t* cells, const hdg_params* prm,
@@ -717,7 +846,7 @@ int hdg_create(int64_t nv, const double* coords, int64_t nc, const int32_t* cell
   if (prm->tau <= 0 || prm->alpha < 0 || prm->delta_up < 0 || prm->n_richardson < 1 || prm->max_it_trace < 1 ||
       prm->max_it_velocity < 1 || !(prm->rtol_trace > 0) || !(prm->rtol_velocity > 0) || prm->imex < 0 ||
       prm->imex > 2 || prm->trace_solver < 0 || prm->trace_solver > 1 || prm->pressure_update < 0 ||
-      prm->pressure_update > 1) {
+      prm->pressure_update > 1 || prm->idr_s < 0 || prm->idr_s > kIdrMax) {
     g_create_error = "invalid parameter";
     return HDG_ERR_INVALID_ARG;
   }
@@ -893,7 +1022,7 @@ int hdg_tentative_velocity(hdg_ctx* ctx, double adt, const double* Qsv, const do
                  ctx->dl, ctx->dr);
   }
   KCHK();
-  int its = ctx->bicgstab(adt, ctx->dr, Qbar);
+  int its = ctx->velocity_solve(adt, ctx->dr, Qbar);
   ctx->bicg_iters.push_back(its);
   ctx->sync();
   API_END(ctx)
@@ -930,10 +1059,10 @@ int hdg_get_info(const hdg_ctx* ctx, char* buf, size_t cap) {
                   ",\"trace_solves\":" + std::to_string(ctx->n_trace_solves) +
                   ",\"pcg_iterations_total\":" + std::to_string(ctx->total_pcg) +
                   ",\"velocity_solves\":" + std::to_string(ctx->n_velocity_solves) +
-                  ",\"bicgstab_iterations_total\":" + std::to_string(ctx->total_bicg) +
+                  ",\"velocity_iterations_total\":" + std::to_string(ctx->total_bicg) +
                   ",\"bicgstab_restarts\":" + std::to_string(ctx->bicg_restarts) +
                   ",\"pcg_iterations_last\":" + last(ctx->pcg_iters, 16) +
-                  ",\"bicgstab_iterations_last\":" + last(ctx->bicg_iters, 16) +
+                  ",\"velocity_iterations_last\":" + last(ctx->bicg_iters, 16) +
                   ",\"seconds_trace\":" + std::to_string(ctx->t_trace) +
                   ",\"seconds_velocity\":" + std::to_string(ctx->t_velocity) + ",\"kernels\":{";
   for (int i = 0; i < kNumKClass; ++i) {

@@ -20,10 +20,13 @@ struct DMesh {
   const int* fc_f;         // [2][nF]
 };
 
+// Reference tables live in the constant address space: every wave reads the
+// same entry at the same time, so the loads become scalar (s_load) loads.
+typedef const __attribute__((address_space(4))) double* cdptr;
 struct DTab {
-  const double *Bu, *Gux, *Guy, *Bp, *Gpx, *Gpy, *cw;
-  const double *FBu, *FGux, *FGuy, *FBp, *fw, *MU, *NUB;
-  const double *Dx, *Dy, *Rx, *Ry, *Chat, *That, *Ehat, *CC, *KDD, *CD, *BDMinv, *NED;
+  cdptr Bu, Gux, Guy, Bp, Gpx, Gpy, cw;
+  cdptr FBu, FGux, FGuy, FBp, fw, MU, NUB;
+  cdptr Dx, Dy, Rx, Ry, Chat, That, Ehat, CC, KDD, CD, BDMinv, NED;
 };
 
 struct DCsr {
@@ -34,6 +37,10 @@ struct DCsr {
 };
 
 constexpr int kBlock = 256;
+constexpr int kIdrMax = 8;  // largest IDR(s) shadow-space dimension
+struct IdrCoef {
+  double v[kIdrMax];
+};
 constexpr int kRedBlocks = 1024;  // fixed grid for deterministic reductions
 
 // launchers (k = degree); all enqueue on `st`
@@ -56,6 +63,14 @@ void launch_prep_adv(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, d
 // mode 2: out = r - det x + adt (f_im(x) + g(p, lam))           (residual, dual vector)
 void launch_apply(int k, hipStream_t st, int mode, DMesh m, DTab t, const double* adv, double alpha, double adt,
                   const double* x, const double* r, const double* p, const double* lam, double* out);
+// Step I operator on structure-of-arrays vectors (2 threads per cell), with an
+// optional fused reduction: dot 1 -> sum w.out; dot 2 -> sum out.x and sum out.out
+// (second set of partials at part + apply_soa_blocks(nc))
+void launch_apply_soa(int k, hipStream_t st, int dot, DMesh m, DTab t, const double* adv, double alpha, double adt,
+                      const double* x, const double* w, double* out, double* part);
+int apply_soa_blocks(long nc);
+void launch_to_soa(int k, hipStream_t st, DMesh m, int inv_det, const double* x, double* y);
+void launch_to_aos(int k, hipStream_t st, DMesh m, const double* x, double* y);
 void launch_div(int k, hipStream_t st, DMesh m, DTab t, const double* F, double scale, double* out);
 void launch_bdm(int k, hipStream_t st, DMesh m, DTab t, const double* Q, double* Qs);
 void launch_recon_rhs(int k, hipStream_t st, DMesh m, DTab t, const double* Q, double* out);
@@ -90,5 +105,13 @@ void launch_bicg_xr(hipStream_t st, long n, const double* sc, int it, const doub
                     const double* t, double* x, double* r, const double* rhat, double* part2);
 void launch_dot2(hipStream_t st, long n, const double* a, const double* b, const double* c, double* part2);
 void launch_finish2(hipStream_t st, const double* part2, double* out2);
+void launch_finish_sets(hipStream_t st, const double* part, int np, int nsets, double* out);
+void launch_idr_u(hipStream_t st, long n, int k, int s, IdrCoef c, double om, const double* r, const double* G,
+                  double* U);
+void launch_multidot(hipStream_t st, long n, int s, const double* P, const double* g, double* part, double* out);
+void launch_idr_update(hipStream_t st, long n, int k, IdrCoef a, double beta, double* G, double* U, double* r,
+                       double* x, double* part);
+void launch_idr_reduce(hipStream_t st, long n, double om, const double* t, double* r, double* x, double* part);
+void launch_random(hipStream_t st, long n, unsigned long long seed, double* y);
 
 }  // namespace hdg

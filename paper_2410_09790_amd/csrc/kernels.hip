@@ -647,6 +647,112 @@ __global__ void __launch_bounds__(kBlock) k_apply(DMesh m, DTab t, const double*
   for (int i = 0; i < NU; ++i) out[(long)e * NU + i] = sc * (r[(long)e * NU + i] - g.det * xv[i] + adt * y[i]);
 }
 
+// Step I operator on structure-of-arrays vectors, x[(c*NS + s)*nc + e]: two
+// threads per cell, one per velocity component (lanes 2i, 2i+1 hold the same
+// cell).  The normal jump at a facet point needs both components; the pair
+// exchanges them with a lane shuffle.  Optional fused reductions of the
+// output against other vectors:
+//   DOT = 1: part[b] = sum w.out;  DOT = 2: part[b] = sum out.x, part[nb+b] = sum out.out
+template <int K, int DOT>
+__global__ void __launch_bounds__(kBlock) k_apply_soa(DMesh m, DTab t, const double* __restrict__ adv, double alpha,
+                                                      double adt, const double* __restrict__ x,
+                                                      const double* __restrict__ w, double* __restrict__ out,
+                                                      double* __restrict__ part) {
+  using D = Dims<K>;
+  constexpr int NS = D::NS, NQC = D::NQC, NQF = D::NQF;
+  // the neighbour's trace table is indexed by the neighbour's local facet and
+  // orientation, which differ between lanes: stage it in LDS
+  __shared__ double sFBu[3 * NQF * NS];
+  for (int i = threadIdx.x; i < 3 * NQF * NS; i += blockDim.x) sFBu[i] = t.FBu[i];
+  __syncthreads();
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nc = m.nc;
+  const int e = (int)(tid >> 1);
+  const int c = (int)(tid & 1);
+  double d1 = 0.0, d2 = 0.0;
+  if (e < nc) {
+    double xv[NS], y[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) { xv[s] = x[(long)(c * NS + s) * nc + e]; y[s] = 0.0; }
+    for (int qq = 0; qq < NQC; ++qq) {
+      const double a0 = adv[(long)(0 * NQC + qq) * nc + e], a1 = adv[(long)(1 * NQC + qq) * nc + e];
+      double dx = 0.0, dy = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) { dx += t.Gux[qq * NS + s] * xv[s]; dy += t.Guy[qq * NS + s] * xv[s]; }
+      const double v = a0 * dx + a1 * dy;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) y[s] -= t.Bu[qq * NS + s] * v;
+    }
+    const double det = m.geo[D_DET * nc + e];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      const int nb = m.cf_nb[f * nc + e];
+      const double nx = m.geo[(D_NX0 + 2 * f) * nc + e], ny = m.geo[(D_NY0 + 2 * f) * nc + e];
+      const double nc_ = c ? ny : nx;
+      int fn = 0, rev = 0;
+      double xn[NS];
+      if (nb >= 0) {
+        fn = m.cf_nbf[f * nc + e];
+        rev = m.cf_flip[f * nc + e] != m.cf_flip[fn * nc + nb];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) xn[s] = x[(long)(c * NS + s) * nc + nb];
+      } else {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) xn[s] = 0.0;
+      }
+      for (int qq = 0; qq < NQF; ++qq) {
+        const int qn = rev ? NQF - 1 - qq : qq;
+        double j = 0.0, jn_ = 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) { j += t.FBu[(f * NQF + qq) * NS + s] * xv[s]; jn_ += sFBu[(fn * NQF + qn) * NS + s] * xn[s]; }
+        j -= jn_;
+        const double jo = __shfl_xor(j, 1, 64);
+        const double jdotn = c ? (jo * nx + j * ny) : (j * nx + jo * ny);
+        const double beta = adv[(long)(2 * NQC + f * NQF + qq) * nc + e];
+        const double con = beta * j - alpha * t.fw[qq] * jdotn * nc_;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) y[s] += t.FBu[(f * NQF + qq) * NS + s] * con;
+      }
+    }
+    const double sc = adt / det;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const long idx = (long)(c * NS + s) * nc + e;
+      const double o = xv[s] - sc * y[s];
+      out[idx] = o;
+      if (DOT == 1) d1 += w[idx] * o;
+      if (DOT == 2) { d1 += o * xv[s]; d2 += o * o; }
+    }
+  }
+  if (DOT >= 1) {
+    const double s1 = block_sum(d1);
+    if (threadIdx.x == 0) part[blockIdx.x] = s1;
+  }
+  if (DOT == 2) {
+    const double s2 = block_sum(d2);
+    if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = s2;
+  }
+}
+
+// AoS [cell][2 ns] <-> SoA [(c ns + s) nc + cell]; scale multiplies by 1/det^pw
+template <int K>
+__global__ void k_to_soa(DMesh m, int inv_det, const double* __restrict__ x, double* __restrict__ y) {
+  constexpr int NU = Dims<K>::NU;
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (long)m.nc * NU) return;
+  const long e = tid % m.nc, i = tid / m.nc;
+  const double sc = inv_det ? 1.0 / m.geo[D_DET * (long)m.nc + e] : 1.0;
+  y[tid] = sc * x[e * NU + i];
+}
+template <int K>
+__global__ void k_to_aos(DMesh m, const double* __restrict__ x, double* __restrict__ y) {
+  constexpr int NU = Dims<K>::NU;
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (long)m.nc * NU) return;
+  const long e = tid / NU, i = tid % NU;
+  y[tid] = x[i * m.nc + e];
+}
+
 // ===================================================================== a6
 // Div(psi, F) = sum_K [ -(grad psi, F)_K + <psi {F}.n_K>_dK ], {F}.n = 0 on walls
 template <int K>
@@ -780,7 +886,7 @@ __global__ void __launch_bounds__(kBlock) k_recon_rhs(DMesh m, DTab t, const dou
   for (int i = 0; i < NU; ++i) qv[i] = Q[(long)e * NU + i];
 #pragma unroll
   for (int i = 0; i < NP; ++i) o[i] = 0.0;
-  auto conv = [&](const double* B, const double* Gx, const double* Gy, const double* qc, const double (&ij)[2][2],
+  auto conv = [&](cdptr B, cdptr Gx, cdptr Gy, const double* qc, const double (&ij)[2][2],
                   double& fx, double& fy) {
     double vx = 0.0, vy = 0.0, d[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
 #pragma unroll
@@ -941,6 +1047,17 @@ __global__ void __launch_bounds__(kBlock) k_finish_mean(const double* __restrict
   if (threadIdx.x == 0) out[0] = v / area;
 }
 
+// out[j] = sum_{i < np} part[j * np + i] for j < nsets
+__global__ void __launch_bounds__(kBlock) k_finish_sets(const double* __restrict__ part, int np, int nsets,
+                                                        double* __restrict__ out) {
+  for (int j = 0; j < nsets; ++j) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) v += part[(long)j * np + i];
+    v = block_sum(v);
+    if (threadIdx.x == 0) out[j] = v;
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) k_finish2(const double* __restrict__ part2, double* __restrict__ out2) {
   double v = 0.0, w = 0.0;
   for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) { v += part2[i]; w += part2[kRedBlocks + i]; }
@@ -1005,7 +1122,9 @@ __global__ void k_bicg_p(long n, const double* __restrict__ sc, int it, const do
   if (i >= n) return;
   if (it == 0) { p[i] = r[i]; return; }
   const double om = bicg_omega(sc, it - 1);
-  const double beta = (sc[8 * it] / sc[8 * (it - 1)]) * (bicg_alpha(sc, it - 1) / om);
+  // a vanished omega or rho leaves beta = 0 (steepest-descent direction) until the host restarts
+  const double rho_old = sc[8 * (it - 1)];
+  const double beta = (om != 0.0 && rho_old != 0.0) ? (sc[8 * it] / rho_old) * (bicg_alpha(sc, it - 1) / om) : 0.0;
   p[i] = r[i] + beta * (p[i] - om * v[i]);
 }
 
@@ -1032,6 +1151,95 @@ __global__ void __launch_bounds__(kBlock) k_bicg_xr(long n, const double* __rest
   a = block_sum(a);
   b = block_sum(b);
   if (threadIdx.x == 0) { part2[blockIdx.x] = a; part2[kRedBlocks + blockIdx.x] = b; }
+}
+
+// ----------------------------------------------------------------- IDR(s)
+// U_k = om r + sum_{i=k}^{s-1} c_i (U_i - om G_i)   (G, U stored column-major, n per column)
+__global__ void k_idr_u(long n, int k, int s, IdrCoef c, double om, const double* __restrict__ r,
+                        const double* __restrict__ G, double* __restrict__ U) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v = om * r[i];
+  for (int j = k; j < s; ++j) v += c.v[j - k] * (U[(long)j * n + i] - om * G[(long)j * n + i]);
+  U[(long)k * n + i] = v;
+}
+
+// partial sums of P_j . g for j < s: part[j * kRedBlocks + block]
+__global__ void __launch_bounds__(kBlock) k_multidot(long n, int s, const double* __restrict__ P,
+                                                     const double* __restrict__ g, double* __restrict__ part) {
+  double acc[kIdrMax];
+#pragma unroll
+  for (int j = 0; j < kIdrMax; ++j) acc[j] = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double gi = g[i];
+#pragma unroll
+    for (int j = 0; j < kIdrMax; ++j)
+      if (j < s) acc[j] += P[(long)j * n + i] * gi;
+  }
+#pragma unroll
+  for (int j = 0; j < kIdrMax; ++j) {
+    if (j >= s) break;
+    const double v = block_sum(acc[j]);
+    if (threadIdx.x == 0) part[j * kRedBlocks + blockIdx.x] = v;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_finish_multi(const double* __restrict__ part, int s, double* __restrict__ out) {
+  for (int j = 0; j < s; ++j) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) v += part[j * kRedBlocks + i];
+    v = block_sum(v);
+    if (threadIdx.x == 0) out[j] = v;
+  }
+}
+
+// G_k -= sum_{i<k} a_i G_i; U_k -= sum_{i<k} a_i U_i; r -= beta G_k; x += beta U_k; partial |r|^2
+__global__ void __launch_bounds__(kBlock) k_idr_update(long n, int k, IdrCoef a, double beta, double* __restrict__ G,
+                                                       double* __restrict__ U, double* __restrict__ r,
+                                                       double* __restrict__ x, double* __restrict__ part) {
+  double acc = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double g = G[(long)k * n + i], u = U[(long)k * n + i];
+    for (int j = 0; j < k; ++j) {
+      g -= a.v[j] * G[(long)j * n + i];
+      u -= a.v[j] * U[(long)j * n + i];
+    }
+    G[(long)k * n + i] = g;
+    U[(long)k * n + i] = u;
+    const double ri = r[i] - beta * g;
+    r[i] = ri;
+    x[i] += beta * u;
+    acc += ri * ri;
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// x += om r; r -= om t; partial |r|^2
+__global__ void __launch_bounds__(kBlock) k_idr_reduce(long n, double om, const double* __restrict__ t,
+                                                       double* __restrict__ r, double* __restrict__ x,
+                                                       double* __restrict__ part) {
+  double acc = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double ri = r[i];
+    x[i] += om * ri;
+    const double rn = ri - om * t[i];
+    r[i] = rn;
+    acc += rn * rn;
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// counter-based pseudo-random shadow vectors in (-1, 1) (splitmix64 finaliser)
+__global__ void k_random(long n, unsigned long long seed, double* __restrict__ y) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  unsigned long long z = seed + 0x9E3779B97F4A7C15ull * (unsigned long long)(i + 1);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  y[i] = 2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
 }
 
 // ============================================================== launchers
@@ -1088,6 +1296,24 @@ void launch_apply(int k, hipStream_t st, int mode, DMesh m, DTab t, const double
   } else {
     HDG_DISPATCH(k, (k_apply<KK, 2><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, adv, alpha, adt, x, r, p, lam, out)));
   }
+}
+void launch_apply_soa(int k, hipStream_t st, int dot, DMesh m, DTab t, const double* adv, double alpha, double adt,
+                      const double* x, const double* w, double* out, double* part) {
+  const int nb = nblocks(2L * m.nc);
+  if (dot == 0) {
+    HDG_DISPATCH(k, (k_apply_soa<KK, 0><<<nb, kBlock, 0, st>>>(m, t, adv, alpha, adt, x, w, out, part)));
+  } else if (dot == 1) {
+    HDG_DISPATCH(k, (k_apply_soa<KK, 1><<<nb, kBlock, 0, st>>>(m, t, adv, alpha, adt, x, w, out, part)));
+  } else {
+    HDG_DISPATCH(k, (k_apply_soa<KK, 2><<<nb, kBlock, 0, st>>>(m, t, adv, alpha, adt, x, w, out, part)));
+  }
+}
+int apply_soa_blocks(long nc) { return nblocks(2L * nc); }
+void launch_to_soa(int k, hipStream_t st, DMesh m, int inv_det, const double* x, double* y) {
+  HDG_DISPATCH(k, (k_to_soa<KK><<<nblocks((long)m.nc * Dims<KK>::NU), kBlock, 0, st>>>(m, inv_det, x, y)));
+}
+void launch_to_aos(int k, hipStream_t st, DMesh m, const double* x, double* y) {
+  HDG_DISPATCH(k, (k_to_aos<KK><<<nblocks((long)m.nc * Dims<KK>::NU), kBlock, 0, st>>>(m, x, y)));
 }
 void launch_div(int k, hipStream_t st, DMesh m, DTab t, const double* F, double scale, double* out) {
   HDG_DISPATCH(k, (k_div<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, F, scale, out)));
@@ -1159,5 +1385,26 @@ void launch_dot2(hipStream_t st, long n, const double* a, const double* b, const
   k_dot2<<<kRedBlocks, kBlock, 0, st>>>(n, a, b, c, part2);
 }
 void launch_finish2(hipStream_t st, const double* part2, double* out2) { k_finish2<<<1, kBlock, 0, st>>>(part2, out2); }
+void launch_finish_sets(hipStream_t st, const double* part, int np, int nsets, double* out) {
+  k_finish_sets<<<1, kBlock, 0, st>>>(part, np, nsets, out);
+}
+void launch_idr_u(hipStream_t st, long n, int k, int s, IdrCoef c, double om, const double* r, const double* G,
+                  double* U) {
+  k_idr_u<<<nblocks(n), kBlock, 0, st>>>(n, k, s, c, om, r, G, U);
+}
+void launch_multidot(hipStream_t st, long n, int s, const double* P, const double* g, double* part, double* out) {
+  k_multidot<<<kRedBlocks, kBlock, 0, st>>>(n, s, P, g, part);
+  k_finish_multi<<<1, kBlock, 0, st>>>(part, s, out);
+}
+void launch_idr_update(hipStream_t st, long n, int k, IdrCoef a, double beta, double* G, double* U, double* r,
+                       double* x, double* part) {
+  k_idr_update<<<kRedBlocks, kBlock, 0, st>>>(n, k, a, beta, G, U, r, x, part);
+}
+void launch_idr_reduce(hipStream_t st, long n, double om, const double* t, double* r, double* x, double* part) {
+  k_idr_reduce<<<kRedBlocks, kBlock, 0, st>>>(n, om, t, r, x, part);
+}
+void launch_random(hipStream_t st, long n, unsigned long long seed, double* y) {
+  k_random<<<nblocks(n), kBlock, 0, st>>>(n, seed, y);
+}
 
 }  // namespace hdg

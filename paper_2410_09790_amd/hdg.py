@@ -43,6 +43,7 @@ class Params(ctypes.Structure):
         ("max_it_trace", ctypes.c_int),
         ("max_it_velocity", ctypes.c_int),
         ("pressure_update", ctypes.c_int),
+        ("idr_s", ctypes.c_int),
     ]
 
 
