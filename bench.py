@@ -35,6 +35,13 @@ WORKLOAD = {"workload": "unit_square_256x256_k3_ars222", "n": 256, "k": 3, "seed
             "rtol_trace": 1e-12, "rtol_velocity": 1e-10}
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+KERNELS_SRC = os.path.join(ROOT, "paper_2410_09790_amd", "csrc", "kernels.hip")
+# HBM bytes per launch of the dominant kernel from the FETCH_SIZE / WRITE_SIZE
+# counter passes (each scaled by the counts of a 256 MiB copy), valid only for
+# the kernel source they were taken on (sha256 prefix of kernels.hip)
+MEASURED_TRAFFIC = {
+    "apply_step1_operator": {"kernels_sha256": "8054e6aacf10f9a8", "bytes_per_launch": 313.8e6},
+}
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
 
 
@@ -67,6 +74,16 @@ def algorithmic_cost(kernel: str, k: int, nc: int, nF: int):
         flops = nF * 2 * 5 * nf * nf
         return nbytes, flops
     return None, None
+
+
+def measured_traffic(kernel: str):
+    import hashlib
+    rec = MEASURED_TRAFFIC.get(kernel)
+    if rec is None:
+        return None
+    with open(KERNELS_SRC, "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()[:16]
+    return rec["bytes_per_launch"] if sha == rec["kernels_sha256"] else None
 
 
 def cpu_baseline(max_seconds: float = 30.0):
@@ -105,6 +122,8 @@ def main():
     ap.add_argument("--k", type=int, default=WORKLOAD["k"], help="degree (experiments only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with events")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
+                    help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -117,6 +136,15 @@ def main():
     from paper_2410_09790_amd import hdg
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE counters
+        # calibrate the byte counters of the HDG kernels
+        src = torch.ones(args.copy_probe * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe} MiB read + {args.copy_probe} MiB written per launch, 3 launches")
     w = dict(WORKLOAD)
     w["n"], w["k"] = args.n, args.k
     if (args.n, args.k) != (WORKLOAD["n"], WORKLOAD["k"]):
@@ -171,13 +199,13 @@ def main():
         if t_mem >= t_alu:
             ach = nbytes / avg_s / 1e9
             roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                        "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom), "kernel": dom,
                         "algorithmic_bytes_per_launch": nbytes, "avg_launch_us": round(avg_s * 1e6, 2),
                         "share_of_step": round(timed[dom]["ms"] * 1e-3 / el, 3)}
         else:
             ach = flops / avg_s / 1e12
             roofline = {"bound": "alu", "achieved": round(ach, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                        "frac": round(ach / FP64_PEAK_TFLOPS, 4), "traffic": None, "kernel": dom,
+                        "frac": round(ach / FP64_PEAK_TFLOPS, 4), "traffic": measured_traffic(dom), "kernel": dom,
                         "algorithmic_flops_per_launch": flops, "avg_launch_us": round(avg_s * 1e6, 2),
                         "share_of_step": round(timed[dom]["ms"] * 1e-3 / el, 3)}
     cpu = None
