@@ -65,6 +65,10 @@ typedef enum {
 typedef enum { HDG_IMEX_EULER = 0, HDG_ARS222 = 1, HDG_ARS233 = 2 } hdg_imex_scheme;
 typedef enum { HDG_TRACE_JACOBI_PCG = 0, HDG_TRACE_MG_PCG = 1 } hdg_trace_solver;
 typedef enum { HDG_PRESSURE_RECONSTRUCT = 0, HDG_PRESSURE_FIRST_ORDER = 1 } hdg_pressure_update;
+/* HDG_MIXED is reserved: hdg_create returns HDG_ERR_UNSUPPORTED for it in
+ * this build (FP32 arithmetic in the dominant Step I solve makes BiCGStab
+ * diverge on this advection-dominated operator). */
+typedef enum { HDG_FP64 = 0, HDG_MIXED = 1 } hdg_precision;
 
 typedef struct hdg_ctx hdg_ctx;
 
@@ -84,11 +88,12 @@ typedef struct {
   int max_it_velocity;
   int pressure_update;   /* hdg_pressure_update */
   int idr_s;             /* Step I Krylov method: IDR(s) with this s (1..8), or 0 = BiCGStab */
+  int precision;         /* hdg_precision */
 } hdg_params;
 
 /* Fill p with the defaults: k=1, tau=alpha=delta_up=1, ARS(2,2,2), n_R=3,
  * MG-PCG, rtol 1e-12 for both solvers, caps 5000 / 20000, reconstruction,
- * BiCGStab for Step I. */
+ * BiCGStab for Step I, FP64. */
 void hdg_default_params(hdg_params* p);
 
 /* Create a context on the current HIP device.  coords: host [nv][2];

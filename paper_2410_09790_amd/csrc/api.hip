@@ -234,6 +234,21 @@ struct hdg_ctx {
   int pcg(hdg::TraceOp& op, const double* g, double* x);
   void solve_trace(double c, const double* Fw, const double* Fpsi, const double* Fmu, double* U, double* p,
                    double* lam);
+  template <typename T>
+  struct KrylovBuf {
+    T *b = nullptr, *x = nullptr, *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *s = nullptr,
+      *t = nullptr;
+  };
+  KrylovBuf<double> kd;
+  KrylovBuf<float> kf;
+  float* advf = nullptr;
+  template <typename T>
+  void alloc_krylov(KrylovBuf<T>& B) {
+    B.b = dalloc<T>(nQ); B.x = dalloc<T>(nQ); B.r = dalloc<T>(nQ); B.rh = dalloc<T>(nQ);
+    B.p = dalloc<T>(nQ); B.v = dalloc<T>(nQ); B.s = dalloc<T>(nQ); B.t = dalloc<T>(nQ);
+  }
+  template <typename TC>
+  int bicgstab_t(double adt, const double* b_aos, double* x_aos, const TC* advT, double rtol);
   int bicgstab(double adt, const double* b, double* x);
   int idrs(double adt, const double* b, double* x);
   int velocity_solve(double adt, const double* b, double* x) {
@@ -288,6 +303,7 @@ void hdg_ctx::setup() {
   bsc = dalloc<double>(8 * (long)mv + 16);
   pr = dalloc<double>(nT); pz = dalloc<double>(nT); pp = dalloc<double>(nT); pq = dalloc<double>(nT);
   t1 = dalloc<double>(nT); t2 = dalloc<double>(nT); t3 = dalloc<double>(nT);
+  alloc_krylov(kd);
   bb = dalloc<double>(nQ); bx = dalloc<double>(nQ); br = dalloc<double>(nQ); brh = dalloc<double>(nQ); bp = dalloc<double>(nQ);
   bv = dalloc<double>(nQ); bs = dalloc<double>(nQ); bt = dalloc<double>(nQ);
   adv = dalloc<double>((long)nc * (2 * nqc + 3 * nqf));
@@ -524,20 +540,26 @@ void hdg_ctx::solve_trace(double c, const double* Fw, const double* Fpsi, const 
 // BiCGStab on the mass-scaled Step I operator  x - (adt/det) f_im(x) = b.
 // Vectors are kept structure-of-arrays inside the solver (coalesced loads in
 // the two-threads-per-cell operator kernel, which also produces the dot
-// products BiCGStab needs next).  The residual is checked on the host every
-// kCheck iterations; alpha and omega are guarded on the device, and a
-// breakdown restarts from the current iterate with the true residual.
-int hdg_ctx::bicgstab(double adt, const double* b_aos, double* x_aos) {
+// products BiCGStab needs next).  The Krylov vectors and scalars are FP64;
+// TC is the arithmetic type of the operator and of its advection data (FP32
+// in the mixed-precision mode: FP32 BiCGStab recurrences diverge on this
+// advection-dominated operator, FP32 operator arithmetic inside FP64
+// recurrences does not).  The residual is checked on
+// the host every kCheck iterations; alpha and omega are guarded on the
+// device, and a breakdown restarts from the current iterate with the true
+// residual.
+template <typename TC>
+int hdg_ctx::bicgstab_t(double adt, const double* b_aos, double* x_aos, const TC* advT, double rtol) {
+  using T = double;
+  KrylovBuf<double>& B = kd;
   constexpr int kCheck = 4;
   const long n = nQ;
   const int maxit = prm.max_it_velocity;
   const int nbk = apply_soa_blocks(hm.nc);
-  double* b = bb;
-  double* x = bx;
-  launch_to_soa(k, st, dm, 0, b_aos, b);
-  launch_fill(st, n, 0.0, x);
-  launch_copy(st, n, b, br);
-  launch_dot(st, n, br, nullptr, part);
+  launch_to_soa<T>(k, st, dm, 0, b_aos, B.b);
+  launch_fill(st, n, 0.0, B.x);
+  launch_copy(st, n, B.b, B.r);
+  launch_dot(st, n, B.r, (const T*)nullptr, part);
   launch_finish(st, part, kRedBlocks, bsc);
   const double bnorm = std::sqrt(read_scalar(bsc));
   if (bnorm == 0.0) {
@@ -552,54 +574,59 @@ int hdg_ctx::bicgstab(double adt, const double* b_aos, double* x_aos) {
       if (it > 0) {  // true residual r = b - A x
         {
           Timed tm(prof, KC_APPLY_OP);
-          launch_apply_soa(k, st, 0, dm, dt, adv, prm.alpha, adt, x, nullptr, bt, nullptr);
+          launch_apply_soa<T, TC>(k, st, 0, dm, dt, advT, prm.alpha, adt, B.x, nullptr, B.t, nullptr);
         }
-        launch_copy(st, n, b, br);
-        launch_axpby(st, n, -1.0, bt, 1.0, br);
+        launch_copy(st, n, B.b, B.r);
+        launch_axpby(st, n, -1.0, B.t, 1.0, B.r);
         ++bicg_restarts;
         if (++restarts > 50) throw SolverBreakdown("BiCGStab: too many restarts");
       }
-      launch_copy(st, n, br, brh);
-      launch_dot(st, n, br, nullptr, part);
+      launch_copy(st, n, B.r, B.rh);
+      launch_dot(st, n, B.r, (const T*)nullptr, part);
       launch_finish(st, part, kRedBlocks, bsc);
-      launch_copy(st, 1, bsc, bsc + 4);
       j = 0;
       restart = false;
     }
-    launch_bicg_p(st, n, bsc, j, br, bv, bp);
+    launch_bicg_p<T>(st, n, bsc, j, B.r, B.v, B.p);
     {
       Timed tm(prof, KC_APPLY_OP);
-      launch_apply_soa(k, st, 1, dm, dt, adv, prm.alpha, adt, bp, brh, bv, part);
+      launch_apply_soa<T, TC>(k, st, 1, dm, dt, advT, prm.alpha, adt, B.p, B.rh, B.v, part);
     }
     launch_finish_sets(st, part, nbk, 1, bsc + 8 * j + 1);
-    launch_bicg_s(st, n, bsc, j, br, bv, bs);
+    launch_bicg_s<T>(st, n, bsc, j, B.r, B.v, B.s);
     {
       Timed tm(prof, KC_APPLY_OP);
-      launch_apply_soa(k, st, 2, dm, dt, adv, prm.alpha, adt, bs, nullptr, bt, part);
+      launch_apply_soa<T, TC>(k, st, 2, dm, dt, advT, prm.alpha, adt, B.s, nullptr, B.t, part);
     }
-    launch_finish_sets(st, part, nbk, 2, bsc + 8 * j + 2);
-    launch_bicg_xr(st, n, bsc, j, bp, bs, bt, x, br, brh, part2);
+    launch_finish_sets(st, part, nbk, 3, bsc + 8 * j + 2);
+    launch_bicg_xr<T>(st, n, bsc, j, B.p, B.s, B.t, B.x, B.r, B.rh, part2);
     launch_finish2(st, part2, bsc + 8 * (j + 1));
-    // keep r.r in slot 4 of the new iteration (slot 1 is reused for rhat.v)
-    launch_copy(st, 1, bsc + 8 * (j + 1) + 1, bsc + 8 * (j + 1) + 4);
     KCHK();
     ++it;
     ++j;
     if (it % kCheck == 0 || it >= maxit || 8 * (j + 2) > 8 * (maxit + 2)) {
       HIPCHK(hipMemcpyAsync(h_pinned, bsc + 8 * (j - 1), 10 * sizeof(double), hipMemcpyDeviceToHost, st));
       sync();
-      const double rv = h_pinned[1], tt = h_pinned[3], rho_new = h_pinned[8], rr = h_pinned[9];
+      const double rv = h_pinned[1], ts = h_pinned[2], tt = h_pinned[3], rho_new = h_pinned[8], rr = h_pinned[9];
       const double res = std::sqrt(rr);
       if (!(res == res)) throw SolverBreakdown("BiCGStab breakdown (NaN residual); the result is invalid");
-      if (res <= prm.rtol_velocity * bnorm) break;
-      if (rv == 0.0 || tt == 0.0 || !(std::fabs(rho_new) > 1e-30 * rr) || 8 * (j + 2) > 8 * (maxit + 2))
+      if (res <= rtol * bnorm) break;
+      if (rv == 0.0 || tt == 0.0 || ts == 0.0 || !(std::fabs(rho_new) > 1e-30 * rr) ||
+          8 * (j + 2) > 8 * (maxit + 2))
         restart = true;
     }
   }
   if (it >= maxit) not_converged = true;
-  launch_to_aos(k, st, dm, x, x_aos);
+  launch_to_aos<T>(k, st, dm, B.x, x_aos);
   KCHK();
   return it;
+}
+
+int hdg_ctx::bicgstab(double adt, const double* b_aos, double* x_aos) {
+  // FP64 in both precision modes: with FP32 operator arithmetic (FP32 or FP64
+  // recurrences) BiCGStab diverges on this advection-dominated operator once
+  // the residual reaches ~1e-5
+  return bicgstab_t<double>(adt, b_aos, x_aos, adv, prm.rtol_velocity);
 }
 
 // IDR(s) with bi-orthogonalisation on the mass-scaled Step I operator.  The
@@ -833,6 +860,7 @@ void hdg_default_params(hdg_params* p) {
   p->max_it_velocity = 20000;
   p->pressure_update = HDG_PRESSURE_RECONSTRUCT;
   p->idr_s = 0;
+  p->precision = HDG_FP64;
 }
 
 int hdg_create(int64_t nv, const double* coords, int64_t nc, const int32_t* cells, const hdg_params* prm,
@@ -846,9 +874,15 @@ int hdg_create(int64_t nv, const double* coords, int64_t nc, const int32_t* cell
   if (prm->tau <= 0 || prm->alpha < 0 || prm->delta_up < 0 || prm->n_richardson < 1 || prm->max_it_trace < 1 ||
       prm->max_it_velocity < 1 || !(prm->rtol_trace > 0) || !(prm->rtol_velocity > 0) || prm->imex < 0 ||
       prm->imex > 2 || prm->trace_solver < 0 || prm->trace_solver > 1 || prm->pressure_update < 0 ||
-      prm->pressure_update > 1 || prm->idr_s < 0 || prm->idr_s > kIdrMax) {
+      prm->pressure_update > 1 || prm->idr_s < 0 || prm->idr_s > kIdrMax ||
+      prm->precision < 0 || prm->precision > 1) {
     g_create_error = "invalid parameter";
     return HDG_ERR_INVALID_ARG;
+  }
+  if (prm->precision == HDG_MIXED) {
+    g_create_error = "mixed precision is not available in this build: FP32 arithmetic in the Step I operator "
+                     "destabilises BiCGStab on this advection-dominated system";
+    return HDG_ERR_UNSUPPORTED;
   }
   auto ctx = std::make_unique<hdg_ctx>();
   ctx->prm = *prm;

@@ -66,11 +66,14 @@ void launch_apply(int k, hipStream_t st, int mode, DMesh m, DTab t, const double
 // Step I operator on structure-of-arrays vectors (2 threads per cell), with an
 // optional fused reduction: dot 1 -> sum w.out; dot 2 -> sum out.x and sum out.out
 // (second set of partials at part + apply_soa_blocks(nc))
-void launch_apply_soa(int k, hipStream_t st, int dot, DMesh m, DTab t, const double* adv, double alpha, double adt,
-                      const double* x, const double* w, double* out, double* part);
+template <typename TS, typename T>
+void launch_apply_soa(int k, hipStream_t st, int dot, DMesh m, DTab t, const T* adv, double alpha, double adt,
+                      const TS* x, const TS* w, TS* out, double* part);
 int apply_soa_blocks(long nc);
-void launch_to_soa(int k, hipStream_t st, DMesh m, int inv_det, const double* x, double* y);
-void launch_to_aos(int k, hipStream_t st, DMesh m, const double* x, double* y);
+template <typename T>
+void launch_to_soa(int k, hipStream_t st, DMesh m, int inv_det, const double* x, T* y);
+template <typename T>
+void launch_to_aos(int k, hipStream_t st, DMesh m, const T* x, double* y);
 void launch_div(int k, hipStream_t st, DMesh m, DTab t, const double* F, double scale, double* out);
 void launch_bdm(int k, hipStream_t st, DMesh m, DTab t, const double* Q, double* Qs);
 void launch_recon_rhs(int k, hipStream_t st, DMesh m, DTab t, const double* Q, double* out);
@@ -85,24 +88,32 @@ void launch_dense_mv(hipStream_t st, int n, const double* M, const double* x, do
 
 // reductions: partial sums into part[kRedBlocks], then out[0] = sum
 void launch_dot(hipStream_t st, long n, const double* a, const double* b, double* part);
+void launch_dot(hipStream_t st, long n, const float* a, const float* b, double* part);
 void launch_dot_sub(hipStream_t st, long n, int stride, int off, const double* a, double* part);
 void launch_finish(hipStream_t st, const double* part, int nparts, double* out);
 void launch_finish_mean(hipStream_t st, const double* part, int nparts, double area, double* out);
 
 // vectors: y = a*x + b*y with host scalars
 void launch_axpby(hipStream_t st, long n, double a, const double* x, double b, double* y);
+void launch_axpby(hipStream_t st, long n, double a, const float* x, double b, float* y);
 void launch_copy(hipStream_t st, long n, const double* x, double* y);
+void launch_copy(hipStream_t st, long n, const float* x, float* y);
 void launch_fill(hipStream_t st, long n, double v, double* y);
+void launch_fill(hipStream_t st, long n, double v, float* y);
+void launch_convert(hipStream_t st, long n, const double* x, float* y);
 void launch_project_const(hipStream_t st, int nF, int nf, const double* sum, double* g);
 
 // Krylov helpers with device scalars
 void launch_pcg_update(hipStream_t st, long n, const double* rz, const double* pq, const double* p, const double* q,
                        double* x, double* r, double* part_rr);
 void launch_pcg_direction(hipStream_t st, long n, const double* rz_new, const double* rz_old, const double* z, double* p);
-void launch_bicg_p(hipStream_t st, long n, const double* sc, int it, const double* r, const double* v, double* p);
-void launch_bicg_s(hipStream_t st, long n, const double* sc, int it, const double* r, const double* v, double* s);
-void launch_bicg_xr(hipStream_t st, long n, const double* sc, int it, const double* p, const double* s,
-                    const double* t, double* x, double* r, const double* rhat, double* part2);
+template <typename T>
+void launch_bicg_p(hipStream_t st, long n, const double* sc, int it, const T* r, const T* v, T* p);
+template <typename T>
+void launch_bicg_s(hipStream_t st, long n, const double* sc, int it, const T* r, const T* v, T* s);
+template <typename T>
+void launch_bicg_xr(hipStream_t st, long n, const double* sc, int it, const T* p, const T* s, const T* t, T* x,
+                    T* r, const T* rhat, double* part2);
 void launch_dot2(hipStream_t st, long n, const double* a, const double* b, const double* c, double* part2);
 void launch_finish2(hipStream_t st, const double* part2, double* out2);
 void launch_finish_sets(hipStream_t st, const double* part, int np, int nsets, double* out);

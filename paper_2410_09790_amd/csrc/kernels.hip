@@ -650,78 +650,88 @@ __global__ void __launch_bounds__(kBlock) k_apply(DMesh m, DTab t, const double*
 // Step I operator on structure-of-arrays vectors, x[(c*NS + s)*nc + e]: two
 // threads per cell, one per velocity component (lanes 2i, 2i+1 hold the same
 // cell).  The normal jump at a facet point needs both components; the pair
-// exchanges them with a lane shuffle.  Optional fused reductions of the
-// output against other vectors:
-//   DOT = 1: part[b] = sum w.out;  DOT = 2: part[b] = sum out.x, part[nb+b] = sum out.out
-template <int K, int DOT>
-__global__ void __launch_bounds__(kBlock) k_apply_soa(DMesh m, DTab t, const double* __restrict__ adv, double alpha,
-                                                      double adt, const double* __restrict__ x,
-                                                      const double* __restrict__ w, double* __restrict__ out,
+// exchanges them with a lane shuffle.  TS is the storage type of the
+// vectors, T the arithmetic type of the operator and of its advection data
+// (double, or float in the mixed-precision mode).  Fused reductions of the
+// output against other vectors accumulate in double:
+//   DOT = 1: part[b] = sum w.out
+//   DOT = 2: part[b] = sum out.x, part[nb+b] = sum out.out, part[2nb+b] = sum x.x
+template <int K, int DOT, typename TS, typename T>
+__global__ void __launch_bounds__(kBlock) k_apply_soa(DMesh m, DTab t, const T* __restrict__ adv, double alpha,
+                                                      double adt, const TS* __restrict__ x,
+                                                      const TS* __restrict__ w, TS* __restrict__ out,
                                                       double* __restrict__ part) {
   using D = Dims<K>;
   constexpr int NS = D::NS, NQC = D::NQC, NQF = D::NQF;
   // the neighbour's trace table is indexed by the neighbour's local facet and
   // orientation, which differ between lanes: stage it in LDS
-  __shared__ double sFBu[3 * NQF * NS];
-  for (int i = threadIdx.x; i < 3 * NQF * NS; i += blockDim.x) sFBu[i] = t.FBu[i];
+  __shared__ T sFBu[3 * NQF * NS];
+  for (int i = threadIdx.x; i < 3 * NQF * NS; i += blockDim.x) sFBu[i] = (T)t.FBu[i];
   __syncthreads();
   const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long nc = m.nc;
   const int e = (int)(tid >> 1);
   const int c = (int)(tid & 1);
-  double d1 = 0.0, d2 = 0.0;
+  double d1 = 0.0, d2 = 0.0, d3 = 0.0;
   if (e < nc) {
-    double xv[NS], y[NS];
+    T xv[NS], y[NS];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) { xv[s] = x[(long)(c * NS + s) * nc + e]; y[s] = 0.0; }
+    for (int s = 0; s < NS; ++s) { xv[s] = (T)x[(long)(c * NS + s) * nc + e]; y[s] = (T)0; }
     for (int qq = 0; qq < NQC; ++qq) {
-      const double a0 = adv[(long)(0 * NQC + qq) * nc + e], a1 = adv[(long)(1 * NQC + qq) * nc + e];
-      double dx = 0.0, dy = 0.0;
+      const T a0 = adv[(long)(0 * NQC + qq) * nc + e], a1 = adv[(long)(1 * NQC + qq) * nc + e];
+      T dx = (T)0, dy = (T)0;
 #pragma unroll
-      for (int s = 0; s < NS; ++s) { dx += t.Gux[qq * NS + s] * xv[s]; dy += t.Guy[qq * NS + s] * xv[s]; }
-      const double v = a0 * dx + a1 * dy;
+      for (int s = 0; s < NS; ++s) { dx += (T)t.Gux[qq * NS + s] * xv[s]; dy += (T)t.Guy[qq * NS + s] * xv[s]; }
+      const T v = a0 * dx + a1 * dy;
 #pragma unroll
-      for (int s = 0; s < NS; ++s) y[s] -= t.Bu[qq * NS + s] * v;
+      for (int s = 0; s < NS; ++s) y[s] -= (T)t.Bu[qq * NS + s] * v;
     }
     const double det = m.geo[D_DET * nc + e];
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
       const int nb = m.cf_nb[f * nc + e];
-      const double nx = m.geo[(D_NX0 + 2 * f) * nc + e], ny = m.geo[(D_NY0 + 2 * f) * nc + e];
-      const double nc_ = c ? ny : nx;
+      const T nx = (T)m.geo[(D_NX0 + 2 * f) * nc + e], ny = (T)m.geo[(D_NY0 + 2 * f) * nc + e];
+      const T nc_ = c ? ny : nx;
       int fn = 0, rev = 0;
-      double xn[NS];
+      T xn[NS];
       if (nb >= 0) {
         fn = m.cf_nbf[f * nc + e];
         rev = m.cf_flip[f * nc + e] != m.cf_flip[fn * nc + nb];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) xn[s] = x[(long)(c * NS + s) * nc + nb];
+        for (int s = 0; s < NS; ++s) xn[s] = (T)x[(long)(c * NS + s) * nc + nb];
       } else {
 #pragma unroll
-        for (int s = 0; s < NS; ++s) xn[s] = 0.0;
+        for (int s = 0; s < NS; ++s) xn[s] = (T)0;
       }
       for (int qq = 0; qq < NQF; ++qq) {
         const int qn = rev ? NQF - 1 - qq : qq;
-        double j = 0.0, jn_ = 0.0;
+        T j = (T)0, jn_ = (T)0;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) { j += t.FBu[(f * NQF + qq) * NS + s] * xv[s]; jn_ += sFBu[(fn * NQF + qn) * NS + s] * xn[s]; }
+        for (int s = 0; s < NS; ++s) {
+          j += (T)t.FBu[(f * NQF + qq) * NS + s] * xv[s];
+          jn_ += sFBu[(fn * NQF + qn) * NS + s] * xn[s];
+        }
         j -= jn_;
-        const double jo = __shfl_xor(j, 1, 64);
-        const double jdotn = c ? (jo * nx + j * ny) : (j * nx + jo * ny);
-        const double beta = adv[(long)(2 * NQC + f * NQF + qq) * nc + e];
-        const double con = beta * j - alpha * t.fw[qq] * jdotn * nc_;
+        const T jo = __shfl_xor(j, 1, 64);
+        const T jdotn = c ? (jo * nx + j * ny) : (j * nx + jo * ny);
+        const T beta = adv[(long)(2 * NQC + f * NQF + qq) * nc + e];
+        const T con = beta * j - (T)(alpha * t.fw[qq]) * jdotn * nc_;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) y[s] += t.FBu[(f * NQF + qq) * NS + s] * con;
+        for (int s = 0; s < NS; ++s) y[s] += (T)t.FBu[(f * NQF + qq) * NS + s] * con;
       }
     }
-    const double sc = adt / det;
+    const T sc = (T)(adt / det);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const long idx = (long)(c * NS + s) * nc + e;
-      const double o = xv[s] - sc * y[s];
-      out[idx] = o;
-      if (DOT == 1) d1 += w[idx] * o;
-      if (DOT == 2) { d1 += o * xv[s]; d2 += o * o; }
+      const T o = xv[s] - sc * y[s];
+      out[idx] = (TS)o;
+      if (DOT == 1) d1 += (double)w[idx] * (double)o;
+      if (DOT == 2) {
+        d1 += (double)o * (double)xv[s];
+        d2 += (double)o * (double)o;
+        d3 += (double)xv[s] * (double)xv[s];
+      }
     }
   }
   if (DOT >= 1) {
@@ -731,26 +741,33 @@ __global__ void __launch_bounds__(kBlock) k_apply_soa(DMesh m, DTab t, const dou
   if (DOT == 2) {
     const double s2 = block_sum(d2);
     if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = s2;
+    const double s3 = block_sum(d3);
+    if (threadIdx.x == 0) part[2 * gridDim.x + blockIdx.x] = s3;
   }
 }
 
 // AoS [cell][2 ns] <-> SoA [(c ns + s) nc + cell]; scale multiplies by 1/det^pw
-template <int K>
-__global__ void k_to_soa(DMesh m, int inv_det, const double* __restrict__ x, double* __restrict__ y) {
+template <int K, typename T>
+__global__ void k_to_soa(DMesh m, int inv_det, const double* __restrict__ x, T* __restrict__ y) {
   constexpr int NU = Dims<K>::NU;
   const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= (long)m.nc * NU) return;
   const long e = tid % m.nc, i = tid / m.nc;
   const double sc = inv_det ? 1.0 / m.geo[D_DET * (long)m.nc + e] : 1.0;
-  y[tid] = sc * x[e * NU + i];
+  y[tid] = (T)(sc * x[e * NU + i]);
 }
-template <int K>
-__global__ void k_to_aos(DMesh m, const double* __restrict__ x, double* __restrict__ y) {
+template <int K, typename T>
+__global__ void k_to_aos(DMesh m, const T* __restrict__ x, double* __restrict__ y) {
   constexpr int NU = Dims<K>::NU;
   const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= (long)m.nc * NU) return;
   const long e = tid / NU, i = tid % NU;
-  y[tid] = x[i * m.nc + e];
+  y[tid] = (double)x[i * m.nc + e];
+}
+template <typename T>
+__global__ void k_convert(long n, const double* __restrict__ x, T* __restrict__ y) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (T)x[i];
 }
 
 // ===================================================================== a6
@@ -1001,11 +1018,12 @@ __global__ void k_dense_mv(int n, const double* __restrict__ M, const double* __
   y[i] = acc;
 }
 
-__global__ void __launch_bounds__(kBlock) k_dot(long n, const double* __restrict__ a, const double* __restrict__ b,
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_dot(long n, const T* __restrict__ a, const T* __restrict__ b,
                                                 double* __restrict__ part) {
   double v = 0.0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-    v += a[i] * (b ? b[i] : a[i]);
+    v += (double)a[i] * (double)(b ? b[i] : a[i]);
   v = block_sum(v);
   if (threadIdx.x == 0) part[blockIdx.x] = v;
 }
@@ -1066,17 +1084,20 @@ __global__ void __launch_bounds__(kBlock) k_finish2(const double* __restrict__ p
   if (threadIdx.x == 0) { out2[0] = v; out2[1] = w; }
 }
 
-__global__ void k_axpby(long n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+template <typename T>
+__global__ void k_axpby(long n, double a, const T* __restrict__ x, double b, T* __restrict__ y) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = a * x[i] + (b != 0.0 ? b * y[i] : 0.0);
+  if (i < n) y[i] = (T)(a * (double)x[i] + (b != 0.0 ? b * (double)y[i] : 0.0));
 }
-__global__ void k_copy(long n, const double* __restrict__ x, double* __restrict__ y) {
+template <typename T>
+__global__ void k_copy(long n, const T* __restrict__ x, T* __restrict__ y) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = x[i];
 }
-__global__ void k_fill(long n, double v, double* __restrict__ y) {
+template <typename T>
+__global__ void k_fill(long n, double v, T* __restrict__ y) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = v;
+  if (i < n) y[i] = (T)v;
 }
 // remove the constant-trace component: g_F,0 -= sum / nF
 __global__ void k_project_const(int nF, int nf, const double* __restrict__ sum, double* __restrict__ g) {
@@ -1106,47 +1127,51 @@ __global__ void k_pcg_direction(long n, const double* __restrict__ rzn, const do
   if (i < n) p[i] = z[i] + (rzn[0] / rzo[0]) * p[i];
 }
 
-// BiCGStab scalars, 8 per iteration i: [0] rho_i = rhat.r_i, [1] rhat.v_i,
-// [2] t.s, [3] t.t, [4] r_i.r_i
+// BiCGStab scalars, 8 per iteration i: [0] rho_i = rhat.r_i, [1] rhat.v_i
+// (r_i.r_i until the iteration overwrites it), [2] t.s, [3] t.t, [4] s.s
 // alpha and omega fall back to 0 on an exact breakdown; the host then restarts
 __device__ __forceinline__ double bicg_alpha(const double* sc, int i) {
   return sc[8 * i + 1] != 0.0 ? sc[8 * i] / sc[8 * i + 1] : 0.0;
 }
+// omega = t.s / t.t (local minimal residual)
 __device__ __forceinline__ double bicg_omega(const double* sc, int i) {
   return sc[8 * i + 3] > 0.0 ? sc[8 * i + 2] / sc[8 * i + 3] : 0.0;
 }
 
-__global__ void k_bicg_p(long n, const double* __restrict__ sc, int it, const double* __restrict__ r,
-                         const double* __restrict__ v, double* __restrict__ p) {
+template <typename T>
+__global__ void k_bicg_p(long n, const double* __restrict__ sc, int it, const T* __restrict__ r,
+                         const T* __restrict__ v, T* __restrict__ p) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (it == 0) { p[i] = r[i]; return; }
   const double om = bicg_omega(sc, it - 1);
   // a vanished omega or rho leaves beta = 0 (steepest-descent direction) until the host restarts
   const double rho_old = sc[8 * (it - 1)];
-  const double beta = (om != 0.0 && rho_old != 0.0) ? (sc[8 * it] / rho_old) * (bicg_alpha(sc, it - 1) / om) : 0.0;
-  p[i] = r[i] + beta * (p[i] - om * v[i]);
+  const double beta = (fabs(om) > 1e-30 && rho_old != 0.0) ? (sc[8 * it] / rho_old) * (bicg_alpha(sc, it - 1) / om) : 0.0;
+  p[i] = (T)((double)r[i] + beta * ((double)p[i] - om * (double)v[i]));
 }
 
-__global__ void k_bicg_s(long n, const double* __restrict__ sc, int it, const double* __restrict__ r,
-                         const double* __restrict__ v, double* __restrict__ s) {
+template <typename T>
+__global__ void k_bicg_s(long n, const double* __restrict__ sc, int it, const T* __restrict__ r,
+                         const T* __restrict__ v, T* __restrict__ s) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) s[i] = r[i] - bicg_alpha(sc, it) * v[i];
+  if (i < n) s[i] = (T)((double)r[i] - bicg_alpha(sc, it) * (double)v[i]);
 }
 
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_bicg_xr(long n, const double* __restrict__ sc, int it,
-                                                    const double* __restrict__ p, const double* __restrict__ s,
-                                                    const double* __restrict__ t, double* __restrict__ x,
-                                                    double* __restrict__ r, const double* __restrict__ rhat,
+                                                    const T* __restrict__ p, const T* __restrict__ s,
+                                                    const T* __restrict__ t, T* __restrict__ x,
+                                                    T* __restrict__ r, const T* __restrict__ rhat,
                                                     double* __restrict__ part2) {
   const double al = bicg_alpha(sc, it), om = bicg_omega(sc, it);
   double a = 0.0, b = 0.0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    x[i] += al * p[i] + om * s[i];
-    const double ri = s[i] - om * t[i];
+    x[i] = (T)((double)x[i] + al * (double)p[i] + om * (double)s[i]);
+    const T ri = (T)((double)s[i] - om * (double)t[i]);
     r[i] = ri;
-    a += rhat[i] * ri;
-    b += ri * ri;
+    a += (double)rhat[i] * (double)ri;
+    b += (double)ri * (double)ri;
   }
   a = block_sum(a);
   b = block_sum(b);
@@ -1297,24 +1322,35 @@ void launch_apply(int k, hipStream_t st, int mode, DMesh m, DTab t, const double
     HDG_DISPATCH(k, (k_apply<KK, 2><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, adv, alpha, adt, x, r, p, lam, out)));
   }
 }
-void launch_apply_soa(int k, hipStream_t st, int dot, DMesh m, DTab t, const double* adv, double alpha, double adt,
-                      const double* x, const double* w, double* out, double* part) {
+template <typename TS, typename T>
+void launch_apply_soa(int k, hipStream_t st, int dot, DMesh m, DTab t, const T* adv, double alpha, double adt,
+                      const TS* x, const TS* w, TS* out, double* part) {
   const int nb = nblocks(2L * m.nc);
   if (dot == 0) {
-    HDG_DISPATCH(k, (k_apply_soa<KK, 0><<<nb, kBlock, 0, st>>>(m, t, adv, alpha, adt, x, w, out, part)));
+    HDG_DISPATCH(k, (k_apply_soa<KK, 0, TS, T><<<nb, kBlock, 0, st>>>(m, t, adv, alpha, adt, x, w, out, part)));
   } else if (dot == 1) {
-    HDG_DISPATCH(k, (k_apply_soa<KK, 1><<<nb, kBlock, 0, st>>>(m, t, adv, alpha, adt, x, w, out, part)));
+    HDG_DISPATCH(k, (k_apply_soa<KK, 1, TS, T><<<nb, kBlock, 0, st>>>(m, t, adv, alpha, adt, x, w, out, part)));
   } else {
-    HDG_DISPATCH(k, (k_apply_soa<KK, 2><<<nb, kBlock, 0, st>>>(m, t, adv, alpha, adt, x, w, out, part)));
+    HDG_DISPATCH(k, (k_apply_soa<KK, 2, TS, T><<<nb, kBlock, 0, st>>>(m, t, adv, alpha, adt, x, w, out, part)));
   }
 }
+template void launch_apply_soa<double, double>(int, hipStream_t, int, DMesh, DTab, const double*, double, double,
+                                               const double*, const double*, double*, double*);
+template void launch_apply_soa<double, float>(int, hipStream_t, int, DMesh, DTab, const float*, double, double,
+                                              const double*, const double*, double*, double*);
 int apply_soa_blocks(long nc) { return nblocks(2L * nc); }
-void launch_to_soa(int k, hipStream_t st, DMesh m, int inv_det, const double* x, double* y) {
-  HDG_DISPATCH(k, (k_to_soa<KK><<<nblocks((long)m.nc * Dims<KK>::NU), kBlock, 0, st>>>(m, inv_det, x, y)));
+template <typename T>
+void launch_to_soa(int k, hipStream_t st, DMesh m, int inv_det, const double* x, T* y) {
+  HDG_DISPATCH(k, (k_to_soa<KK, T><<<nblocks((long)m.nc * Dims<KK>::NU), kBlock, 0, st>>>(m, inv_det, x, y)));
 }
-void launch_to_aos(int k, hipStream_t st, DMesh m, const double* x, double* y) {
-  HDG_DISPATCH(k, (k_to_aos<KK><<<nblocks((long)m.nc * Dims<KK>::NU), kBlock, 0, st>>>(m, x, y)));
+template <typename T>
+void launch_to_aos(int k, hipStream_t st, DMesh m, const T* x, double* y) {
+  HDG_DISPATCH(k, (k_to_aos<KK, T><<<nblocks((long)m.nc * Dims<KK>::NU), kBlock, 0, st>>>(m, x, y)));
 }
+template void launch_to_soa<double>(int, hipStream_t, DMesh, int, const double*, double*);
+template void launch_to_soa<float>(int, hipStream_t, DMesh, int, const double*, float*);
+template void launch_to_aos<double>(int, hipStream_t, DMesh, const double*, double*);
+template void launch_to_aos<float>(int, hipStream_t, DMesh, const float*, double*);
 void launch_div(int k, hipStream_t st, DMesh m, DTab t, const double* F, double scale, double* out) {
   HDG_DISPATCH(k, (k_div<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, F, scale, out)));
 }
@@ -1345,7 +1381,10 @@ void launch_dense_mv(hipStream_t st, int n, const double* M, const double* x, do
   k_dense_mv<<<nblocks(n), kBlock, 0, st>>>(n, M, x, y);
 }
 void launch_dot(hipStream_t st, long n, const double* a, const double* b, double* part) {
-  k_dot<<<kRedBlocks, kBlock, 0, st>>>(n, a, b, part);
+  k_dot<double><<<kRedBlocks, kBlock, 0, st>>>(n, a, b, part);
+}
+void launch_dot(hipStream_t st, long n, const float* a, const float* b, double* part) {
+  k_dot<float><<<kRedBlocks, kBlock, 0, st>>>(n, a, b, part);
 }
 void launch_dot_sub(hipStream_t st, long n, int stride, int off, const double* a, double* part) {
   k_dot_sub<<<kRedBlocks, kBlock, 0, st>>>(n, stride, off, a, part);
@@ -1357,10 +1396,22 @@ void launch_finish_mean(hipStream_t st, const double* part, int nparts, double a
   k_finish_mean<<<1, kBlock, 0, st>>>(part, nparts, area, out);
 }
 void launch_axpby(hipStream_t st, long n, double a, const double* x, double b, double* y) {
-  k_axpby<<<nblocks(n), kBlock, 0, st>>>(n, a, x, b, y);
+  k_axpby<double><<<nblocks(n), kBlock, 0, st>>>(n, a, x, b, y);
 }
-void launch_copy(hipStream_t st, long n, const double* x, double* y) { k_copy<<<nblocks(n), kBlock, 0, st>>>(n, x, y); }
-void launch_fill(hipStream_t st, long n, double v, double* y) { k_fill<<<nblocks(n), kBlock, 0, st>>>(n, v, y); }
+void launch_axpby(hipStream_t st, long n, double a, const float* x, double b, float* y) {
+  k_axpby<float><<<nblocks(n), kBlock, 0, st>>>(n, a, x, b, y);
+}
+void launch_copy(hipStream_t st, long n, const double* x, double* y) {
+  k_copy<double><<<nblocks(n), kBlock, 0, st>>>(n, x, y);
+}
+void launch_copy(hipStream_t st, long n, const float* x, float* y) {
+  k_copy<float><<<nblocks(n), kBlock, 0, st>>>(n, x, y);
+}
+void launch_fill(hipStream_t st, long n, double v, double* y) { k_fill<double><<<nblocks(n), kBlock, 0, st>>>(n, v, y); }
+void launch_fill(hipStream_t st, long n, double v, float* y) { k_fill<float><<<nblocks(n), kBlock, 0, st>>>(n, v, y); }
+void launch_convert(hipStream_t st, long n, const double* x, float* y) {
+  k_convert<float><<<nblocks(n), kBlock, 0, st>>>(n, x, y);
+}
 void launch_project_const(hipStream_t st, int nF, int nf, const double* sum, double* g) {
   k_project_const<<<nblocks(nF), kBlock, 0, st>>>(nF, nf, sum, g);
 }
@@ -1371,16 +1422,27 @@ void launch_pcg_update(hipStream_t st, long n, const double* rz, const double* p
 void launch_pcg_direction(hipStream_t st, long n, const double* rzn, const double* rzo, const double* z, double* p) {
   k_pcg_direction<<<nblocks(n), kBlock, 0, st>>>(n, rzn, rzo, z, p);
 }
-void launch_bicg_p(hipStream_t st, long n, const double* sc, int it, const double* r, const double* v, double* p) {
-  k_bicg_p<<<nblocks(n), kBlock, 0, st>>>(n, sc, it, r, v, p);
+template <typename T>
+void launch_bicg_p(hipStream_t st, long n, const double* sc, int it, const T* r, const T* v, T* p) {
+  k_bicg_p<T><<<nblocks(n), kBlock, 0, st>>>(n, sc, it, r, v, p);
 }
-void launch_bicg_s(hipStream_t st, long n, const double* sc, int it, const double* r, const double* v, double* s) {
-  k_bicg_s<<<nblocks(n), kBlock, 0, st>>>(n, sc, it, r, v, s);
+template <typename T>
+void launch_bicg_s(hipStream_t st, long n, const double* sc, int it, const T* r, const T* v, T* s) {
+  k_bicg_s<T><<<nblocks(n), kBlock, 0, st>>>(n, sc, it, r, v, s);
 }
-void launch_bicg_xr(hipStream_t st, long n, const double* sc, int it, const double* p, const double* s,
-                    const double* t, double* x, double* r, const double* rhat, double* part2) {
-  k_bicg_xr<<<kRedBlocks, kBlock, 0, st>>>(n, sc, it, p, s, t, x, r, rhat, part2);
+template <typename T>
+void launch_bicg_xr(hipStream_t st, long n, const double* sc, int it, const T* p, const T* s, const T* t, T* x,
+                    T* r, const T* rhat, double* part2) {
+  k_bicg_xr<T><<<kRedBlocks, kBlock, 0, st>>>(n, sc, it, p, s, t, x, r, rhat, part2);
 }
+template void launch_bicg_p<double>(hipStream_t, long, const double*, int, const double*, const double*, double*);
+template void launch_bicg_p<float>(hipStream_t, long, const double*, int, const float*, const float*, float*);
+template void launch_bicg_s<double>(hipStream_t, long, const double*, int, const double*, const double*, double*);
+template void launch_bicg_s<float>(hipStream_t, long, const double*, int, const float*, const float*, float*);
+template void launch_bicg_xr<double>(hipStream_t, long, const double*, int, const double*, const double*,
+                                     const double*, double*, double*, const double*, double*);
+template void launch_bicg_xr<float>(hipStream_t, long, const double*, int, const float*, const float*,
+                                    const float*, float*, float*, const float*, double*);
 void launch_dot2(hipStream_t st, long n, const double* a, const double* b, const double* c, double* part2) {
   k_dot2<<<kRedBlocks, kBlock, 0, st>>>(n, a, b, c, part2);
 }

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libhdg.so")
 IMEX = {"imex_euler": 0, "ars222": 1, "ars233": 2}
 TRACE_SOLVER = {"jacobi_pcg": 0, "mg_pcg": 1}
 PRESSURE = {"reconstruct": 0, "first_order": 1}
+PRECISION = {"fp64": 0, "mixed": 1}
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NOT_CONVERGED", 5: "BAD_STATE",
           6: "UNSUPPORTED"}
 
@@ -44,6 +45,7 @@ class Params(ctypes.Structure):
         ("max_it_velocity", ctypes.c_int),
         ("pressure_update", ctypes.c_int),
         ("idr_s", ctypes.c_int),
+        ("precision", ctypes.c_int),
     ]
 
 
@@ -105,6 +107,8 @@ def default_params(**kw) -> Params:
             val = TRACE_SOLVER[val]
         elif key == "pressure_update" and isinstance(val, str):
             val = PRESSURE[val]
+        elif key == "precision" and isinstance(val, str):
+            val = PRECISION[val]
         setattr(p, key, val)
     return p
 

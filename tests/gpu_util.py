@@ -51,3 +51,36 @@ def compatible_rhs(d, seed):
     one_p, one_t = d.constant_pressure(), d.constant_trace()
     Fpsi -= (Fpsi @ one_p - Fmu @ one_t) / (one_p @ one_p) * one_p
     return Fw, Fpsi, Fmu
+
+
+class Patches:
+    """Oracle evaluations on small patches (a cell and its neighbours) of a large
+    mesh, so that per-cell outputs of full-size GPU runs can be checked one by one.
+
+    Patch vertices keep the order of their global ids, so facet orientations
+    (and with them the trace layout) are those of the full mesh."""
+
+    def __init__(self, X, C, k):
+        from oracle.mesh import Mesh
+        self.X, self.C, self.k = X, np.asarray(C), k
+        self.mesh = Mesh(X, C)
+        self.fid = {(int(a), int(b)): F for F, (a, b) in enumerate(self.mesh.facets)}
+
+    def patch(self, K):
+        from oracle.forms import Discretisation
+        cells = [K] + [int(c) for c in self.mesh.nb_cell[K] if c >= 0]
+        gv = np.unique(self.C[cells].ravel())
+        loc = {int(v): i for i, v in enumerate(gv)}
+        pc = np.array([[loc[int(v)] for v in self.C[c]] for c in cells], dtype=np.int64)
+        d = Discretisation(self.X[gv], pc, self.k)
+        # patch facet -> global facet
+        pf = np.array([self.fid[(int(gv[a]), int(gv[b]))] for a, b in d.mesh.facets])
+        return d, np.array(cells), pf
+
+    @staticmethod
+    def cell_vec(vec, cells, per):
+        return np.asarray(vec).reshape(-1, per)[cells].ravel()
+
+    @staticmethod
+    def facet_vec(vec, pf, nf):
+        return np.asarray(vec).reshape(-1, nf)[pf].ravel()

@@ -1,0 +1,162 @@
+"""GPU parity at the benchmark's full size and launch configuration: the
+256 x 256 unit square (131072 cells, 788480 trace unknowns), k = 3, seed-0
+stream-function data, ARS(2,2,2), dt = 1e-3, n_R = 3, MG-PCG.
+
+The oracle cannot run whole steps at this size, but every per-cell output of
+the path depends only on a cell and its neighbours: BDM interpolant (a3),
+Richardson residual (a4), weak divergence (a6), and the rows of the systems
+that Step I (a5) and the hybridised mixed solve (a1, a7-a9) must satisfy.
+Those are recomputed by the oracle on patches around sampled cells.  Whole
+steps are checked by properties that hold at any size.
+"""
+import numpy as np
+import pytest
+
+import hdg_inputs as hi
+
+from gpu_util import Patches, context, dev, host, torch_or_skip
+
+pytestmark = pytest.mark.gpu
+
+N, K, DT = 256, 3, 1e-3
+GAMMA = 1.0 - 1.0 / np.sqrt(2.0)
+NSAMPLE = 48
+
+
+@pytest.fixture(scope="module")
+def setup():
+    torch = torch_or_skip()
+    X, C = hi.unit_square_mesh(N)
+    ctx = context(X, C, degree=K, imex="ars222", n_richardson=3, trace_solver="mg_pcg", rtol_trace=1e-12,
+                  rtol_velocity=1e-10)
+    par = hi.stream_function_params(0)
+    xy = ctx.cell_points()
+    ctx.set_velocity_from_points(hi.streamfunction_velocity(par, xy[..., 0], xy[..., 1]))
+    P = Patches(X, C, K)
+    rng = np.random.default_rng(2024)
+    sample = rng.choice(ctx.ncells, NSAMPLE, replace=False)
+    sample[:4] = [0, 1, ctx.ncells - 1, 2 * N - 1]  # include cells on the walls
+    return torch, ctx, P, sample
+
+
+def test_full_bdm_sampled(setup):
+    torch, ctx, P, sample = setup
+    Q, _, _ = ctx.get_state()
+    Qs = host(ctx.bdm_project(Q))
+    Qh = host(Q)
+    for Kc in sample:
+        d, cells, _ = P.patch(int(Kc))
+        ref = d.bdm_project(P.cell_vec(Qh, cells, d.nu))[:d.nu]
+        got = Qs[Kc * d.nu:(Kc + 1) * d.nu]
+        assert np.linalg.norm(got - ref) <= 1e-12 * max(np.linalg.norm(ref), 1e-300)
+
+
+def test_full_residual_and_divergence_sampled(setup):
+    torch, ctx, P, sample = setup
+    Q, p, lam = ctx.get_state()
+    Qs = ctx.bdm_project(Q)
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal(ctx.nQ)
+    adt = GAMMA * DT
+    out = host(ctx.momentum_residual(adt, dev(torch, r), Qs, Q, p, lam))
+    div = host(ctx.weak_divergence(Q))
+    Qh, ph, lh, Qsh = host(Q), host(p), host(lam), host(Qs)
+    for Kc in sample:
+        d, cells, pf = P.patch(int(Kc))
+        Ql = P.cell_vec(Qh, cells, d.nu)
+        Qsl = P.cell_vec(Qsh, cells, d.nu)
+        pl = P.cell_vec(ph, cells, d.npp)
+        ll = P.facet_vec(lh, pf, d.nf)
+        rl = P.cell_vec(r, cells, d.nu)
+        ref = (rl - d.mass() @ Ql + adt * (d.advection(Qsl) @ Ql + d.g(pl, ll)))[:d.nu]
+        got = out[Kc * d.nu:(Kc + 1) * d.nu]
+        assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+        refd = d.div_c(Ql)[:d.npp]
+        gotd = div[Kc * d.npp:(Kc + 1) * d.npp]
+        assert np.linalg.norm(gotd - refd) <= 1e-11 * max(np.linalg.norm(refd), 1e-3)
+
+
+def test_full_tentative_velocity_rows(setup):
+    torch, ctx, P, sample = setup
+    Q, _, _ = ctx.get_state()
+    Qs = ctx.bdm_project(Q)
+    adt = GAMMA * DT
+    rng = np.random.default_rng(6)
+    rhs = rng.standard_normal(ctx.nQ)
+    x = host(ctx.tentative_velocity(adt, Qs, dev(torch, rhs)))
+    Qsh = host(Qs)
+    worst = 0.0
+    for Kc in sample:
+        d, cells, _ = P.patch(int(Kc))
+        A = d.mass() - adt * d.advection(P.cell_vec(Qsh, cells, d.nu))
+        res = (A @ P.cell_vec(x, cells, d.nu))[:d.nu] - rhs[Kc * d.nu:(Kc + 1) * d.nu]
+        worst = max(worst, np.linalg.norm(res) / np.linalg.norm(rhs[Kc * d.nu:(Kc + 1) * d.nu]))
+    # the solver stops at ||b - A x|| <= 1e-10 ||b|| over all 3.9M rows
+    assert worst < 1e-8, worst
+
+
+@pytest.mark.parametrize("c", [1.0, GAMMA * DT])
+def test_full_mixed_solve_rows(setup, c):
+    torch, ctx, P, sample = setup
+    from oracle.hdg import monolithic_matrix
+    rng = np.random.default_rng(7)
+    Fw, Fpsi = rng.standard_normal(ctx.nQ), rng.standard_normal(ctx.nP)
+    Fmu = np.zeros(ctx.nT)
+    # compatibility F_psi(1) = F_mu(1): remove the constant component from F_psi
+    npp = ctx.nP // ctx.ncells
+    Fpsi.reshape(-1, npp)[:, 0] -= Fpsi.reshape(-1, npp)[:, 0].mean()
+    U, p, lam = (host(t) for t in ctx.solve_trace(c, dev(torch, Fw), dev(torch, Fpsi), dev(torch, Fmu)))
+    worst = 0.0
+    for Kc in sample:
+        d, cells, pf = P.patch(int(Kc))
+        H = monolithic_matrix(d, c)
+        x = np.concatenate([P.cell_vec(U, cells, d.nu), P.cell_vec(p, cells, d.npp), P.facet_vec(lam, pf, d.nf)])
+        y = H @ x
+        nQ, nP = d.nQ, d.nP
+        # rows of cell Kc (patch cell 0): w-rows and psi-rows; mu-rows of its three facets
+        rw = y[:d.nu] - Fw[Kc * d.nu:(Kc + 1) * d.nu]
+        rp = y[nQ:nQ + d.npp] - Fpsi[Kc * d.npp:(Kc + 1) * d.npp]
+        own = [int(np.nonzero(pf == F)[0][0]) for F in P.mesh.cell_facets[Kc]]
+        rm = np.concatenate([y[nQ + nP + f * d.nf:nQ + nP + (f + 1) * d.nf] - Fmu[F * d.nf:(F + 1) * d.nf]
+                             for f, F in zip(own, P.mesh.cell_facets[Kc])])
+        scale = abs(H).max() * max(np.abs(x).max(), 1.0)
+        worst = max(worst, np.abs(np.concatenate([rw, rp, rm])).max() / scale)
+    assert worst < 1e-10, worst
+
+
+def _golden_ke():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "ke_increments_k3.txt")
+    return np.array([float(l) for l in open(path) if l.strip() and not l.startswith("#")])
+
+
+def test_full_steps_properties(setup):
+    """Two benchmark steps: finite state, mean-zero pressure, iteration counts
+    within their caps, and the relative kinetic-energy change per step.  The
+    flow is inviscid; on resolved meshes the splitting and time discretisation
+    change the energy by a few 1e-9 per step (the upwind and penalty
+    dissipation only dominates on coarse meshes).  The change has converged
+    under refinement, so it must match the oracle's value on the 64 x 64 mesh
+    (tests/golden/ke_increments_k3.txt, written by make_ke_golden.py)."""
+    torch, ctx, P, sample = setup
+    Q0, _, _ = ctx.get_state()
+    nu = ctx.nQ // ctx.ncells
+
+    def ke(Q):
+        det = P.mesh.absdet
+        return 0.5 * float(np.sum(det * np.sum(host(Q).reshape(-1, nu) ** 2, axis=1)))
+
+    e = [ke(Q0)]
+    for _ in range(2):
+        ctx.advance(DT, 1)
+        Q, p, lam = ctx.get_state()
+        assert bool(torch.isfinite(Q).all()) and bool(torch.isfinite(p).all())
+        e.append(ke(Q))
+        ph = host(p).reshape(-1, ctx.nP // ctx.ncells)
+        mean_p = float(np.sum(P.mesh.absdet * ph[:, 0]) / np.sqrt(2.0))
+        assert abs(mean_p) < 1e-10 * max(1.0, float(np.abs(ph).max()))
+    inc = np.diff(e) / e[0]
+    gold = _golden_ke()
+    assert np.all(np.abs(inc - gold) <= 0.02 * np.abs(gold)), (inc, gold)
+    info = ctx.info()
+    assert max(info["pcg_iterations_last"]) < 200

@@ -192,3 +192,4 @@ def test_degree3_mg_parity():
     assert rel_l2_cells(d, got[0], ref[0], d.nu) < 1e-10
     assert rel_l2_cells(d, got[1], ref[1], d.npp) < 1e-10
     assert rel_l2_trace(d, got[2], ref[2]) < 1e-10
+
