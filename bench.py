@@ -163,7 +163,6 @@ def main():
     ctx.advance(w["dt"], args.warmup)
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} step(s) {time.perf_counter() - t0:.2f} s")
-    Q0, p0, l0 = ctx.get_state()
     before = ctx.info()
     if not args.no_profile:
         ctx.profile(True)
@@ -210,7 +209,11 @@ def main():
                         "algorithmic_flops_per_launch": flops, "avg_launch_us": round(avg_s * 1e6, 2),
                         "share_of_step": round(timed[dom]["ms"] * 1e-3 / el, 3)}
     cpu = None
-    if not args.no_cpu_baseline:    out = {
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline()
+        log(f"cpu baseline: {cpu['value']:.1f} {cpu['unit']} ({cpu['sample']})")
+    out = {
         "metric": "trace DOF-IMEX-stages/sec (FP64)",
         "value": value,
         "unit": "trace-DOF-stages/s",
