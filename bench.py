@@ -52,22 +52,24 @@ def log(*a):
 def algorithmic_cost(kernel: str, k: int, nc: int, nF: int):
     """(bytes, flops) that one launch of `kernel` must move / execute at minimum.
 
-    apply_step1_operator (mass-scaled Step I operator, matrix-free f_im): per
-    cell it reads the input velocity (2 ns doubles), the per-stage advection
-    data (2 nq_cell + 3 nq_facet doubles), det J and the three normals (7
-    doubles) and 12 int32 connectivity entries, and writes 2 ns doubles.
+    apply_step1_operator (mass-scaled Step I operator on structure-of-arrays
+    vectors; the event class covers its two BiCGStab launches, v = A p with
+    rh.v, and s = r - alpha v, t = A s with four inner products, so the figure
+    is their mean): per cell the ns x ns volume matrix, 3 nq_facet upwind
+    weights, det J and the three normals (7 doubles), 9 int32 connectivity
+    entries, and 4 velocity vectors of 2 ns doubles (3 for the first launch,
+    5 for the second).  Flops: per cell and component ns^2 FMA for the volume
+    matrix, and per facet point 3 ns FMA (own trace, neighbour trace,
+    projection) plus ~10 for the jump and flux.
     trace_spmv (facet-block ELL, FP64): per facet row 5 blocks of (k+1)^2
     values, 5 int32 column ids, reads x and writes y ((k+1) doubles each).
     """
     ns = (k + 2) * (k + 3) // 2
-    nq1 = (3 * k + 4) // 2
-    nqc, nqf = nq1 * nq1, (3 * k + 5) // 2
+    nqf = (3 * k + 5) // 2
     nf = k + 1
     if kernel == "apply_step1_operator":
-        nbytes = nc * (8 * (2 * ns + 2 * nqc + 3 * nqf + 7) + 4 * 12 + 8 * 2 * ns)
-        per_q_cell = 12 * ns + 6
-        per_q_facet = 12 * ns + 12
-        flops = nc * (nqc * per_q_cell + 3 * nqf * per_q_facet + 4 * ns)
+        nbytes = nc * (8 * (ns * ns + 3 * nqf + 7 + 4 * 2 * ns) + 4 * 9)
+        flops = nc * 2 * (2 * ns * ns + 3 * nqf * (6 * ns + 10) + 2 * ns)
         return nbytes, flops
     if kernel == "trace_spmv":
         nbytes = nF * (8 * 5 * nf * nf + 4 * 5 + 8 * 2 * nf)

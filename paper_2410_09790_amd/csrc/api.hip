@@ -180,8 +180,9 @@ struct hdg_ctx {
   // work vectors
   double *ycell = nullptr, *g = nullptr, *part = nullptr, *part2 = nullptr, *scal = nullptr;
   double *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr, *t1 = nullptr, *t2 = nullptr, *t3 = nullptr;
-  double *bb = nullptr, *bx = nullptr, *br = nullptr, *brh = nullptr, *bp = nullptr, *bv = nullptr, *bs = nullptr, *bt = nullptr,
-         *bsc = nullptr;
+  double *br = nullptr, *bt = nullptr;  // IDR(s) residual and work vector
+  double* bsc = nullptr;                 // BiCGStab scalar slots
+  double* kpart = nullptr;               // partials of t = A s (4 sets)
   double *adv = nullptr, *Qs = nullptr, *dr = nullptr, *Qbar = nullptr, *dQ = nullptr, *dp = nullptr, *dl = nullptr,
          *fpsi = nullptr, *Ut = nullptr;
   double *Q = nullptr, *p = nullptr, *lam = nullptr;
@@ -190,6 +191,7 @@ struct hdg_ctx {
   double* stL[3] = {nullptr, nullptr, nullptr};
   double* stR[3] = {nullptr, nullptr, nullptr};
   double* stMQ[3] = {nullptr, nullptr, nullptr};
+  static constexpr int kPinned = 512;
   double* h_pinned = nullptr;
   bool have_state = false;
   std::string err;
@@ -234,21 +236,20 @@ struct hdg_ctx {
   int pcg(hdg::TraceOp& op, const double* g, double* x);
   void solve_trace(double c, const double* Fw, const double* Fpsi, const double* Fmu, double* U, double* p,
                    double* lam);
-  template <typename T>
+  // BiCGStab vectors, structure-of-arrays
   struct KrylovBuf {
-    T *b = nullptr, *x = nullptr, *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *s = nullptr,
-      *t = nullptr;
+    double *b = nullptr, *x = nullptr, *r = nullptr, *rh = nullptr, *s = nullptr, *t = nullptr, *p = nullptr,
+           *v = nullptr;
   };
-  KrylovBuf<double> kd;
-  KrylovBuf<float> kf;
-  float* advf = nullptr;
-  template <typename T>
-  void alloc_krylov(KrylovBuf<T>& B) {
-    B.b = dalloc<T>(nQ); B.x = dalloc<T>(nQ); B.r = dalloc<T>(nQ); B.rh = dalloc<T>(nQ);
-    B.p = dalloc<T>(nQ); B.v = dalloc<T>(nQ); B.s = dalloc<T>(nQ); B.t = dalloc<T>(nQ);
+  KrylovBuf kd;
+  // per-stage Step I data of the current Q*: cell volume matrices and facet
+  // upwind weights (tiles of 32 cells) for the structure-of-arrays operator,
+  // and the advection data of the cell-major residual kernels
+  double *vk = nullptr, *vbeta = nullptr;
+  void prepare_step1(const double* Qstar) {
+    hdg::launch_prep_adv(k, st, dm, dt, Qstar, prm.delta_up, adv);
+    hdg::launch_step1_matrix(k, st, dm, dt, Qstar, prm.delta_up, vk, vbeta);
   }
-  template <typename TC>
-  int bicgstab_t(double adt, const double* b_aos, double* x_aos, const TC* advT, double rtol);
   int bicgstab(double adt, const double* b, double* x);
   int idrs(double adt, const double* b, double* x);
   int velocity_solve(double adt, const double* b, double* x) {
@@ -281,6 +282,20 @@ void hdg_ctx::setup() {
   dm.cf_nb = upload(hm.cf_nb);
   dm.cf_nbf = upload(hm.cf_nbf);
   dm.cf_flip = upload(hm.cf_flip);
+  {
+    // packed neighbour descriptor: one load gives the neighbour, its local
+    // facet and whether the two local facet parametrisations run opposite
+    std::vector<int32_t> nbx(3 * (size_t)nc, -1);
+    for (int f = 0; f < 3; ++f)
+      for (long e = 0; e < nc; ++e) {
+        const int en = hm.cf_nb[f * nc + e];
+        if (en < 0) continue;
+        const int fn = hm.cf_nbf[f * nc + e];
+        const int rev = hm.cf_flip[f * nc + e] != hm.cf_flip[(long)fn * nc + en];
+        nbx[f * nc + e] = (en << 3) | (fn << 1) | rev;
+      }
+    dm.cf_nbx = upload(nbx);
+  }
   dm.fc_cell = upload(hm.fc_cell);
   dm.fc_f = upload(hm.fc_f);
   // tables (constant address space on the device side)
@@ -293,19 +308,21 @@ void hdg_ctx::setup() {
   dt.Chat = cu(rt.Chat); dt.That = cu(rt.That); dt.Ehat = cu(rt.Ehat); dt.CC = cu(rt.CC);
   dt.KDD = cu(rt.KDD); dt.CD = cu(rt.CD); dt.BDMinv = cu(rt.BDMinv); dt.NED = cu(rt.NED);
   // work
-  const long nb = (nc + kBlock - 1) / kBlock;
   ycell = dalloc<double>(nc * nlam);
   g = dalloc<double>(nT);
-  part = dalloc<double>(std::max<long>((long)kRedBlocks * kIdrMax, 4 * nb + 16));
+  part = dalloc<double>(std::max<long>((long)kRedBlocks * kIdrMax, 4L * apply_soa_blocks(nc) + 16));
   part2 = dalloc<double>(2 * kRedBlocks);
   const int mt = prm.max_it_trace + 4, mv = prm.max_it_velocity + 4;
   scal = dalloc<double>(3 * mt + 16);
-  bsc = dalloc<double>(8 * (long)mv + 16);
+  bsc = dalloc<double>((long)BS_STRIDE * (mv + 2));
+  kpart = dalloc<double>(4L * apply_soa_blocks(nc) + 16);
   pr = dalloc<double>(nT); pz = dalloc<double>(nT); pp = dalloc<double>(nT); pq = dalloc<double>(nT);
   t1 = dalloc<double>(nT); t2 = dalloc<double>(nT); t3 = dalloc<double>(nT);
-  alloc_krylov(kd);
-  bb = dalloc<double>(nQ); bx = dalloc<double>(nQ); br = dalloc<double>(nQ); brh = dalloc<double>(nQ); bp = dalloc<double>(nQ);
-  bv = dalloc<double>(nQ); bs = dalloc<double>(nQ); bt = dalloc<double>(nQ);
+  for (double** v : {&kd.b, &kd.x, &kd.r, &kd.rh, &kd.s, &kd.t, &kd.p, &kd.v}) *v = dalloc<double>(nQ);
+  const long nc32 = (nc + 31) / 32 * 32;
+  vk = dalloc<double>((long)ns * ns * nc32);
+  vbeta = dalloc<double>(3L * nqf * nc32);
+  br = dalloc<double>(nQ); bt = dalloc<double>(nQ);
   adv = dalloc<double>((long)nc * (2 * nqc + 3 * nqf));
   Qs = dalloc<double>(nQ); dr = dalloc<double>(nQ); Qbar = dalloc<double>(nQ); dQ = dalloc<double>(nQ);
   dp = dalloc<double>(nP); dl = dalloc<double>(nT); fpsi = dalloc<double>(nP); Ut = dalloc<double>(nQ);
@@ -314,7 +331,7 @@ void hdg_ctx::setup() {
     stQ[i] = dalloc<double>(nQ); stP[i] = dalloc<double>(nP); stL[i] = dalloc<double>(nT);
     stR[i] = dalloc<double>(nQ); stMQ[i] = dalloc<double>(nQ);
   }
-  HIPCHK(hipHostMalloc((void**)&h_pinned, 64 * sizeof(double), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&h_pinned, kPinned * sizeof(double), hipHostMallocDefault));
   prof.st = st;
   sync();
 }
@@ -537,96 +554,99 @@ void hdg_ctx::solve_trace(double c, const double* Fw, const double* Fpsi, const 
   t_trace += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
-// BiCGStab on the mass-scaled Step I operator  x - (adt/det) f_im(x) = b.
-// Vectors are kept structure-of-arrays inside the solver (coalesced loads in
-// the two-threads-per-cell operator kernel, which also produces the dot
-// products BiCGStab needs next).  The Krylov vectors and scalars are FP64;
-// TC is the arithmetic type of the operator and of its advection data (FP32
-// in the mixed-precision mode: FP32 BiCGStab recurrences diverge on this
-// advection-dominated operator, FP32 operator arithmetic inside FP64
-// recurrences does not).  The residual is checked on
-// the host every kCheck iterations; alpha and omega are guarded on the
-// device, and a breakdown restarts from the current iterate with the true
-// residual.
-template <typename TC>
-int hdg_ctx::bicgstab_t(double adt, const double* b_aos, double* x_aos, const TC* advT, double rtol) {
-  using T = double;
-  KrylovBuf<double>& B = kd;
-  constexpr int kCheck = 4;
+// BiCGStab on the mass-scaled Step I operator  x - (adt/det) f_im(x) = b,
+// all in FP64 (with FP32 operator arithmetic BiCGStab stalls or diverges on
+// this advection-dominated operator).  An iteration is four launches: v = A p
+// (with partials of rh.v), s = r - alpha v (alpha finished there), t = A s
+// (with partials of t.s, t.t, rh.s, rh.t), and the x, r, p updates (omega
+// and beta finished there, partials of r.r).  Coefficients stay in device memory, so the host only
+// enqueues; every kCheck iterations it reads the slots back: the residual
+// r.r of the current iterate, NaNs and breakdown flags.  A breakdown (zero
+// divisor) restarts from the current iterate with the true residual.
+int hdg_ctx::bicgstab(double adt, const double* b_aos, double* x_aos) {
+  KrylovBuf& B = kd;
+  constexpr int kCheck = 8;
+  static_assert(BS_STRIDE * kCheck <= kPinned, "pinned buffer holds kCheck slots");
   const long n = nQ;
   const int maxit = prm.max_it_velocity;
-  const int nbk = apply_soa_blocks(hm.nc);
-  launch_to_soa<T>(k, st, dm, 0, b_aos, B.b);
-  launch_fill(st, n, 0.0, B.x);
-  launch_copy(st, n, B.b, B.r);
-  launch_dot(st, n, B.r, (const T*)nullptr, part);
+  const double rtol = prm.rtol_velocity;
+  const double* beta = vbeta;
+  launch_to_soa(k, st, dm, 0, b_aos, B.b);
+  launch_dot(st, n, B.b, nullptr, part);
   launch_finish(st, part, kRedBlocks, bsc);
   const double bnorm = std::sqrt(read_scalar(bsc));
+  if (!(bnorm == bnorm)) throw SolverBreakdown("BiCGStab: non-finite right-hand side");
   if (bnorm == 0.0) {
-    launch_fill(st, n, 0.0, x_aos);
+    launch_fill(st, nQ, 0.0, x_aos);
     return 0;
   }
-  int j = 0, it = 0;
+  launch_fill(st, n, 0.0, B.x);
+  int it = 0, j = 0, jc = 0, restarts = 0;
   bool restart = true;
-  int restarts = 0;
-  while (it < maxit) {
+  while (true) {
     if (restart) {
-      if (it > 0) {  // true residual r = b - A x
+      if (it == 0) {
+        launch_copy(st, n, B.b, B.r);
+      } else {  // true residual of the current iterate
         {
           Timed tm(prof, KC_APPLY_OP);
-          launch_apply_soa<T, TC>(k, st, 0, dm, dt, advT, prm.alpha, adt, B.x, nullptr, B.t, nullptr);
+          launch_apply_soa(k, st, 0, dm, dt, vk, beta, prm.alpha, adt, B.x, nullptr, B.t, nullptr);
         }
         launch_copy(st, n, B.b, B.r);
         launch_axpby(st, n, -1.0, B.t, 1.0, B.r);
         ++bicg_restarts;
         if (++restarts > 50) throw SolverBreakdown("BiCGStab: too many restarts");
       }
+      launch_copy(st, n, B.r, B.p);
       launch_copy(st, n, B.r, B.rh);
-      launch_dot(st, n, B.r, (const T*)nullptr, part);
-      launch_finish(st, part, kRedBlocks, bsc);
-      j = 0;
+      launch_bicg_init(st, bsc);
+      launch_dot(st, n, B.rh, nullptr, part);
+      launch_finish(st, part, kRedBlocks, bsc + BS_RHO);
+      j = jc = 0;
       restart = false;
     }
-    launch_bicg_p<T>(st, n, bsc, j, B.r, B.v, B.p);
+    double* sc = bsc + (long)BS_STRIDE * j;
     {
       Timed tm(prof, KC_APPLY_OP);
-      launch_apply_soa<T, TC>(k, st, 1, dm, dt, advT, prm.alpha, adt, B.p, B.rh, B.v, part);
+      launch_apply_soa(k, st, 1, dm, dt, vk, beta, prm.alpha, adt, B.p, B.rh, B.v, part);
     }
-    launch_finish_sets(st, part, nbk, 1, bsc + 8 * j + 1);
-    launch_bicg_s<T>(st, n, bsc, j, B.r, B.v, B.s);
+    {
+      Timed tm(prof, KC_VECTOR);
+      launch_bicg_s(st, n, hm.nc, part, sc, B.r, B.v, B.s);
+    }
     {
       Timed tm(prof, KC_APPLY_OP);
-      launch_apply_soa<T, TC>(k, st, 2, dm, dt, advT, prm.alpha, adt, B.s, nullptr, B.t, part);
+      launch_apply_soa(k, st, 2, dm, dt, vk, beta, prm.alpha, adt, B.s, B.rh, B.t, kpart);
     }
-    launch_finish_sets(st, part, nbk, 3, bsc + 8 * j + 2);
-    launch_bicg_xr<T>(st, n, bsc, j, B.p, B.s, B.t, B.x, B.r, B.rh, part2);
-    launch_finish2(st, part2, bsc + 8 * (j + 1));
+    {
+      Timed tm(prof, KC_VECTOR);
+      launch_bicg_xrp(st, n, hm.nc, kpart, sc, B.s, B.t, B.v, B.x, B.r, B.p, part);
+    }
     KCHK();
     ++it;
     ++j;
-    if (it % kCheck == 0 || it >= maxit || 8 * (j + 2) > 8 * (maxit + 2)) {
-      HIPCHK(hipMemcpyAsync(h_pinned, bsc + 8 * (j - 1), 10 * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (j - jc == kCheck || it >= maxit) {
+      const int cnt = j - jc;
+      launch_finish(st, part, kRedBlocks, sc + BS_RR);
+      HIPCHK(hipMemcpyAsync(h_pinned, bsc + (long)BS_STRIDE * jc, (size_t)BS_STRIDE * cnt * sizeof(double),
+                            hipMemcpyDeviceToHost, st));
       sync();
-      const double rv = h_pinned[1], ts = h_pinned[2], tt = h_pinned[3], rho_new = h_pinned[8], rr = h_pinned[9];
-      const double res = std::sqrt(rr);
-      if (!(res == res)) throw SolverBreakdown("BiCGStab breakdown (NaN residual); the result is invalid");
-      if (res <= rtol * bnorm) break;
-      if (rv == 0.0 || tt == 0.0 || ts == 0.0 || !(std::fabs(rho_new) > 1e-30 * rr) ||
-          8 * (j + 2) > 8 * (maxit + 2))
-        restart = true;
+      const double rr = h_pinned[BS_STRIDE * (cnt - 1) + BS_RR];
+      if (!(rr == rr)) throw SolverBreakdown("BiCGStab breakdown (NaN residual); the result is invalid");
+      if (std::sqrt(rr) <= rtol * bnorm) break;
+      if (it >= maxit) {
+        not_converged = true;
+        break;
+      }
+      bool flag = false;
+      for (int i = 0; i < cnt; ++i) flag |= h_pinned[BS_STRIDE * i + BS_FLAG] != 0.0;
+      jc = j;
+      if (flag) restart = true;
     }
   }
-  if (it >= maxit) not_converged = true;
-  launch_to_aos<T>(k, st, dm, B.x, x_aos);
+  launch_to_aos(k, st, dm, B.x, x_aos);
   KCHK();
   return it;
-}
-
-int hdg_ctx::bicgstab(double adt, const double* b_aos, double* x_aos) {
-  // FP64 in both precision modes: with FP32 operator arithmetic (FP32 or FP64
-  // recurrences) BiCGStab diverges on this advection-dominated operator once
-  // the residual reaches ~1e-5
-  return bicgstab_t<double>(adt, b_aos, x_aos, adv, prm.rtol_velocity);
 }
 
 // IDR(s) with bi-orthogonalisation on the mass-scaled Step I operator.  The
@@ -802,7 +822,7 @@ void hdg_ctx::step(double dtv) {
     {
       Timed tm(prof, KC_BDM);
       launch_bdm(k, st, dm, dt, stQ[i - 1], Qs);
-      launch_prep_adv(k, st, dm, dt, Qs, prm.delta_up, adv);
+      prepare_step1(Qs);
     }
     launch_copy(st, nQ, stQ[i - 1], stQ[i]);
     launch_copy(st, nP, stP[i - 1], stP[i]);
@@ -1046,7 +1066,7 @@ int hdg_tentative_velocity(hdg_ctx* ctx, double adt, const double* Qsv, const do
   if (!ctx || !Qsv || !rhs || !Qbar) return HDG_ERR_INVALID_ARG;
   ctx->not_converged = false;
   API_BEGIN
-  launch_prep_adv(ctx->k, ctx->st, ctx->dm, ctx->dt, Qsv, ctx->prm.delta_up, ctx->adv);
+  ctx->prepare_step1(Qsv);
   // mass-scaled right-hand side rhs / det: the residual kernel with Q = p = lam = 0
   {
     launch_fill(ctx->st, ctx->nQ, 0.0, ctx->Ut);

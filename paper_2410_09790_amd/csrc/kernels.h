@@ -16,6 +16,7 @@ struct DMesh {
   const int* cf_nb;        // [3][nc]
   const int* cf_nbf;       // [3][nc]
   const int* cf_flip;      // [3][nc]
+  const int* cf_nbx;       // [3][nc] -1 on walls, else (nb << 3) | (nb's local facet << 1) | reversed
   const int* fc_cell;      // [2][nF]
   const int* fc_f;         // [2][nF]
 };
@@ -43,6 +44,17 @@ struct IdrCoef {
 };
 constexpr int kRedBlocks = 1024;  // fixed grid for deterministic reductions
 
+// Device scalars of one BiCGStab iteration (BS_STRIDE doubles per slot).
+enum BiCGSlot {
+  BS_RHO = 0,              // rho = rh.r of this iteration
+  BS_RV, BS_ALPHA,         // after v = A p: rh.v, alpha
+  BS_TS, BS_TT, BS_OMEGA,  // after t = A s: t.s, t.t, omega
+  BS_BETA,                 // for the next direction
+  BS_RR,                   // r.r after the updates (filled when the host checks)
+  BS_FLAG,                 // 1 on a breakdown (zero divisor)
+  BS_STRIDE = 16
+};
+
 // launchers (k = degree); all enqueue on `st`
 void launch_condense(int k, hipStream_t st, DMesh m, DTab t, double c, double tau, double* Pinv, double* SK);
 void launch_assemble(int k, hipStream_t st, DMesh m, const double* SK, double* vals, int* cols, double* Dinv);
@@ -63,17 +75,31 @@ void launch_prep_adv(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, d
 // mode 2: out = r - det x + adt (f_im(x) + g(p, lam))           (residual, dual vector)
 void launch_apply(int k, hipStream_t st, int mode, DMesh m, DTab t, const double* adv, double alpha, double adt,
                   const double* x, const double* r, const double* p, const double* lam, double* out);
-// Step I operator on structure-of-arrays vectors (2 threads per cell), with an
-// optional fused reduction: dot 1 -> sum w.out; dot 2 -> sum out.x and sum out.out
-// (second set of partials at part + apply_soa_blocks(nc))
-template <typename TS, typename T>
-void launch_apply_soa(int k, hipStream_t st, int dot, DMesh m, DTab t, const T* adv, double alpha, double adt,
-                      const TS* x, const TS* w, TS* out, double* part);
+// Per-stage data of the Step I operator for advecting velocity Qs (AoS): the
+// per-cell volume matrices V (ns*ns entries) and the facet upwind weights
+// beta (3*nq_facet entries), both in tiles of 32 cells (entry j of cell e at
+// ((e/32)*nj + j)*32 + e%32; arrays hold ceil(nc/32)*32 cells)
+void launch_step1_matrix(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, double* V,
+                         double* beta);
+// Step I operator on structure-of-arrays vectors (2 threads per cell):
+// out = x - (adt/det) f_im(x), with partial sums (apply_soa_blocks(nc) per set):
+// dot 0 none; dot 1 w.out; dot 2 out.x, out.out, w.x, w.out
+void launch_apply_soa(int k, hipStream_t st, int dot, DMesh m, DTab t, const double* V, const double* beta,
+                      double alpha, double adt, const double* x, const double* w, double* out, double* part);
 int apply_soa_blocks(long nc);
-template <typename T>
-void launch_to_soa(int k, hipStream_t st, DMesh m, int inv_det, const double* x, T* y);
-template <typename T>
-void launch_to_aos(int k, hipStream_t st, DMesh m, const T* x, double* y);
+// BiCGStab pieces (slot sc of BS_STRIDE scalars):
+//   v = A p: launch_apply_soa dot 1 with rh (partials in part)
+//   s = r - alpha v, alpha from those partials: launch_bicg_s
+//   t = A s: launch_apply_soa dot 2 with rh (partials in part2)
+//   x, r, p updates, omega and beta from part2, partials of r.r
+//   (kRedBlocks of them) in part: launch_bicg_xrp
+void launch_bicg_s(hipStream_t st, long n, long nc, const double* part, double* sc, const double* r, const double* v,
+                   double* s);
+void launch_bicg_xrp(hipStream_t st, long n, long nc, const double* part2, double* sc, const double* s,
+                     const double* tv, const double* v, double* x, double* r, double* p, double* part);
+void launch_bicg_init(hipStream_t st, double* sc);  // zero a slot except BS_RHO
+void launch_to_soa(int k, hipStream_t st, DMesh m, int inv_det, const double* x, double* y);
+void launch_to_aos(int k, hipStream_t st, DMesh m, const double* x, double* y);
 void launch_div(int k, hipStream_t st, DMesh m, DTab t, const double* F, double scale, double* out);
 void launch_bdm(int k, hipStream_t st, DMesh m, DTab t, const double* Q, double* Qs);
 void launch_recon_rhs(int k, hipStream_t st, DMesh m, DTab t, const double* Q, double* out);
@@ -88,35 +114,22 @@ void launch_dense_mv(hipStream_t st, int n, const double* M, const double* x, do
 
 // reductions: partial sums into part[kRedBlocks], then out[0] = sum
 void launch_dot(hipStream_t st, long n, const double* a, const double* b, double* part);
-void launch_dot(hipStream_t st, long n, const float* a, const float* b, double* part);
 void launch_dot_sub(hipStream_t st, long n, int stride, int off, const double* a, double* part);
 void launch_finish(hipStream_t st, const double* part, int nparts, double* out);
 void launch_finish_mean(hipStream_t st, const double* part, int nparts, double area, double* out);
 
 // vectors: y = a*x + b*y with host scalars
 void launch_axpby(hipStream_t st, long n, double a, const double* x, double b, double* y);
-void launch_axpby(hipStream_t st, long n, double a, const float* x, double b, float* y);
 void launch_copy(hipStream_t st, long n, const double* x, double* y);
-void launch_copy(hipStream_t st, long n, const float* x, float* y);
 void launch_fill(hipStream_t st, long n, double v, double* y);
-void launch_fill(hipStream_t st, long n, double v, float* y);
-void launch_convert(hipStream_t st, long n, const double* x, float* y);
 void launch_project_const(hipStream_t st, int nF, int nf, const double* sum, double* g);
 
 // Krylov helpers with device scalars
 void launch_pcg_update(hipStream_t st, long n, const double* rz, const double* pq, const double* p, const double* q,
                        double* x, double* r, double* part_rr);
 void launch_pcg_direction(hipStream_t st, long n, const double* rz_new, const double* rz_old, const double* z, double* p);
-template <typename T>
-void launch_bicg_p(hipStream_t st, long n, const double* sc, int it, const T* r, const T* v, T* p);
-template <typename T>
-void launch_bicg_s(hipStream_t st, long n, const double* sc, int it, const T* r, const T* v, T* s);
-template <typename T>
-void launch_bicg_xr(hipStream_t st, long n, const double* sc, int it, const T* p, const T* s, const T* t, T* x,
-                    T* r, const T* rhat, double* part2);
 void launch_dot2(hipStream_t st, long n, const double* a, const double* b, const double* c, double* part2);
 void launch_finish2(hipStream_t st, const double* part2, double* out2);
-void launch_finish_sets(hipStream_t st, const double* part, int np, int nsets, double* out);
 void launch_idr_u(hipStream_t st, long n, int k, int s, IdrCoef c, double om, const double* r, const double* G,
                   double* U);
 void launch_multidot(hipStream_t st, long n, int s, const double* P, const double* g, double* part, double* out);

@@ -647,127 +647,344 @@ __global__ void __launch_bounds__(kBlock) k_apply(DMesh m, DTab t, const double*
   for (int i = 0; i < NU; ++i) out[(long)e * NU + i] = sc * (r[(long)e * NU + i] - g.det * xv[i] + adt * y[i]);
 }
 
-// Step I operator on structure-of-arrays vectors, x[(c*NS + s)*nc + e]: two
-// threads per cell, one per velocity component (lanes 2i, 2i+1 hold the same
-// cell).  The normal jump at a facet point needs both components; the pair
-// exchanges them with a lane shuffle.  TS is the storage type of the
-// vectors, T the arithmetic type of the operator and of its advection data
-// (double, or float in the mixed-precision mode).  Fused reductions of the
-// output against other vectors accumulate in double:
-//   DOT = 1: part[b] = sum w.out
-//   DOT = 2: part[b] = sum out.x, part[nb+b] = sum out.out, part[2nb+b] = sum x.x
-template <int K, int DOT, typename TS, typename T>
-__global__ void __launch_bounds__(kBlock) k_apply_soa(DMesh m, DTab t, const T* __restrict__ adv, double alpha,
-                                                      double adt, const TS* __restrict__ x,
-                                                      const TS* __restrict__ w, TS* __restrict__ out,
-                                                      double* __restrict__ part) {
+// Value held by the other lane of an adjacent lane pair (2i <-> 2i+1), via a
+// DPP quad permutation [1,0,3,2]: a VALU operation, so unlike a bpermute it
+// does not wait on outstanding scalar loads.  Both lanes of a pair must be
+// active.
+__device__ __forceinline__ double pair_swap(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0xB1, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Per-cell data of the Step I operator are stored in tiles of 32 cells
+// (one wave of the two-threads-per-cell kernels): entry j of cell e sits at
+// ((e/32)*nj + j)*32 + e%32.  A wave then reads 256 contiguous bytes per
+// entry and one contiguous block overall, which keeps the number of DRAM
+// streams small.  Arrays hold ceil(nc/32)*32 cells.
+__device__ __forceinline__ long tile_idx(long e, int j, int nj) { return ((e >> 5) * nj + j) * 32 + (e & 31); }
+
+// Per-cell volume matrix of the Step I form, for the Q* of a stage:
+//   V[s][s'] = -sum_q w_q phi_s(q) (Q*(q) . grad phi_s'(q)) det J
+// (the volume term -(Q*.grad x, w) of eq. (f_impl) acts on each velocity
+// component alike), entry s*NS + s' in tiles.  One thread per (cell, row s).
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_step1_matrix(DMesh m, DTab t, const double* __restrict__ Qs,
+                                                         double* __restrict__ V) {
   using D = Dims<K>;
-  constexpr int NS = D::NS, NQC = D::NQC, NQF = D::NQF;
-  // the neighbour's trace table is indexed by the neighbour's local facet and
-  // orientation, which differ between lanes: stage it in LDS
-  __shared__ T sFBu[3 * NQF * NS];
-  for (int i = threadIdx.x; i < 3 * NQF * NS; i += blockDim.x) sFBu[i] = (T)t.FBu[i];
-  __syncthreads();
+  constexpr int NS = D::NS, NU = D::NU, NQC = D::NQC;
   const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long nc = m.nc;
-  const int e = (int)(tid >> 1);
-  const int c = (int)(tid & 1);
-  double d1 = 0.0, d2 = 0.0, d3 = 0.0;
-  if (e < nc) {
-    T xv[NS], y[NS];
+  if (tid >= nc * NS) return;
+  const int e = (int)(tid % nc), s = (int)(tid / nc);
+  double q[NU], row[NS];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) { xv[s] = (T)x[(long)(c * NS + s) * nc + e]; y[s] = (T)0; }
-    for (int qq = 0; qq < NQC; ++qq) {
-      const T a0 = adv[(long)(0 * NQC + qq) * nc + e], a1 = adv[(long)(1 * NQC + qq) * nc + e];
-      T dx = (T)0, dy = (T)0;
+  for (int i = 0; i < NU; ++i) q[i] = Qs[(long)e * NU + i];
 #pragma unroll
-      for (int s = 0; s < NS; ++s) { dx += (T)t.Gux[qq * NS + s] * xv[s]; dy += (T)t.Guy[qq * NS + s] * xv[s]; }
-      const T v = a0 * dx + a1 * dy;
+  for (int i = 0; i < NS; ++i) row[i] = 0.0;
+  const double det = m.geo[D_DET * nc + e];
+  const double i00 = det * m.geo[D_IJ00 * nc + e], i01 = det * m.geo[D_IJ01 * nc + e];
+  const double i10 = det * m.geo[D_IJ10 * nc + e], i11 = det * m.geo[D_IJ11 * nc + e];
+  for (int qq = 0; qq < NQC; ++qq) {
+    double qx = 0.0, qy = 0.0;
 #pragma unroll
-      for (int s = 0; s < NS; ++s) y[s] -= (T)t.Bu[qq * NS + s] * v;
+    for (int i = 0; i < NS; ++i) {
+      qx += t.Bu[qq * NS + i] * q[i];
+      qy += t.Bu[qq * NS + i] * q[NS + i];
     }
-    const double det = m.geo[D_DET * nc + e];
+    const double w = -t.cw[qq] * t.Bu[qq * NS + s];
+    const double a0 = w * (i00 * qx + i01 * qy), a1 = w * (i10 * qx + i11 * qy);
 #pragma unroll
-    for (int f = 0; f < 3; ++f) {
-      const int nb = m.cf_nb[f * nc + e];
-      const T nx = (T)m.geo[(D_NX0 + 2 * f) * nc + e], ny = (T)m.geo[(D_NY0 + 2 * f) * nc + e];
-      const T nc_ = c ? ny : nx;
-      int fn = 0, rev = 0;
-      T xn[NS];
-      if (nb >= 0) {
-        fn = m.cf_nbf[f * nc + e];
-        rev = m.cf_flip[f * nc + e] != m.cf_flip[fn * nc + nb];
+    for (int i = 0; i < NS; ++i) row[i] += a0 * t.Gux[qq * NS + i] + a1 * t.Guy[qq * NS + i];
+  }
 #pragma unroll
-        for (int s = 0; s < NS; ++s) xn[s] = (T)x[(long)(c * NS + s) * nc + nb];
+  for (int i = 0; i < NS; ++i) V[tile_idx(e, s * NS + i, NS * NS)] = row[i];
+}
+
+// Upwind weights of the Step I facet term at the facet points, for the Q*
+// of a stage: beta = w_q h (Q*.n/2 - delta_up |Q*.n|) on interior facets,
+// 0 on walls, entry f*NQF + q in tiles.  One thread per (cell, facet).
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_step1_beta(DMesh m, DTab t, const double* __restrict__ Qs,
+                                                       double delta_up, double* __restrict__ beta) {
+  using D = Dims<K>;
+  constexpr int NS = D::NS, NU = D::NU, NQF = D::NQF;
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nc = m.nc;
+  if (tid >= 3 * nc) return;
+  const int e = (int)(tid % nc), f = (int)(tid / nc);
+  const bool inner = m.cf_nb[f * nc + e] >= 0;
+  const double nx = m.geo[(D_NX0 + 2 * f) * nc + e], ny = m.geo[(D_NY0 + 2 * f) * nc + e];
+  const double h = m.geo[(D_H0 + f) * nc + e];
+  for (int qq = 0; qq < NQF; ++qq) {
+    double vx = 0.0, vy = 0.0;
+    for (int s = 0; s < NS; ++s) {
+      const double b = t.FBu[(f * NQF + qq) * NS + s];
+      vx += b * Qs[(long)e * NU + s];
+      vy += b * Qs[(long)e * NU + NS + s];
+    }
+    const double qn = vx * nx + vy * ny;
+    beta[tile_idx(e, f * NQF + qq, 3 * NQF)] = inner ? t.fw[qq] * h * (0.5 * qn - delta_up * fabs(qn)) : 0.0;
+  }
+}
+
+// The Step I form f_im(w, x; Q*) of eq. (f_impl) for one cell e and one
+// velocity component c on structure-of-arrays data x[(c*NS + s)*nc + e]:
+// the volume term through the cell matrix V, and per facet the upwinded
+// advective jump term beta(q) [[x]] (beta = w_q h (Q*.n/2 - delta_up
+// |Q*.n|) at the facet points, precomputed per stage in tiles, entry
+// f*NQF + q, zero on walls) and the normal-jump penalty
+// alpha ([[x]].n)(w.n).  Two threads per cell (lanes 2i, 2i+1, one per
+// component) exchange their components of the jump with pair_swap.  y
+// receives the result in reference scaling (the caller multiplies by
+// adt/det).  The neighbour's input value at structure-of-arrays index idx
+// is nb(idx); sFBu is the facet trace table staged in LDS.
+template <int K, typename NbVal>
+__device__ __forceinline__ void step1_core(const DMesh& m, const DTab& t, const double* sFBu,
+                                           const double* __restrict__ V, const double* __restrict__ beta, long nc,
+                                           int e, int c, double alpha, const double (&xv)[Dims<K>::NS],
+                                           double (&y)[Dims<K>::NS], const NbVal& nb) {
+  using D = Dims<K>;
+  constexpr int NS = D::NS, NQF = D::NQF;
+  // volume: the two lanes of a cell split the rows of V (lane c takes rows
+  // 2r + c) and apply them to both components, so that every lane loads
+  // distinct entries; the partner's results come back through pair_swap
+  {
+    double xo[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) xo[i] = pair_swap(xv[i]);
+#pragma unroll
+    for (int r = 0; r < (NS + 1) / 2; ++r) {
+      const int s = 2 * r + c < NS ? 2 * r + c : NS - 1;
+      double am = 0.0, ao = 0.0;
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        const double v = V[tile_idx(e, s * NS + i, NS * NS)];
+        am += v * xv[i];
+        ao += v * xo[i];
+      }
+      const double recv = pair_swap(ao);
+      if (2 * r + 1 < NS) {
+        y[2 * r] = c ? recv : am;
+        y[2 * r + 1] = c ? am : recv;
       } else {
-#pragma unroll
-        for (int s = 0; s < NS; ++s) xn[s] = (T)0;
-      }
-      for (int qq = 0; qq < NQF; ++qq) {
-        const int qn = rev ? NQF - 1 - qq : qq;
-        T j = (T)0, jn_ = (T)0;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-          j += (T)t.FBu[(f * NQF + qq) * NS + s] * xv[s];
-          jn_ += sFBu[(fn * NQF + qn) * NS + s] * xn[s];
-        }
-        j -= jn_;
-        const T jo = __shfl_xor(j, 1, 64);
-        const T jdotn = c ? (jo * nx + j * ny) : (j * nx + jo * ny);
-        const T beta = adv[(long)(2 * NQC + f * NQF + qq) * nc + e];
-        const T con = beta * j - (T)(alpha * t.fw[qq]) * jdotn * nc_;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) y[s] += (T)t.FBu[(f * NQF + qq) * NS + s] * con;
+        y[2 * r] = c ? recv : am;
       }
     }
-    const T sc = (T)(adt / det);
+  }
+  int nbx[3];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) nbx[f] = m.cf_nbx[f * nc + e];
+#pragma unroll 1
+  for (int f = 0; f < 3; ++f) {
+    const int en = nbx[f] >= 0 ? nbx[f] >> 3 : -1;
+    const int fn = nbx[f] >= 0 ? (nbx[f] >> 1) & 3 : 0;
+    const int rev = nbx[f] >= 0 ? nbx[f] & 1 : 0;
+    const double nx = m.geo[(D_NX0 + 2 * f) * nc + e], ny = m.geo[(D_NY0 + 2 * f) * nc + e];
+    const double ncomp = c ? ny : nx;
+    double xn[NS], bq[NQF];
+#pragma unroll
+    for (int qq = 0; qq < NQF; ++qq) bq[qq] = beta[tile_idx(e, f * NQF + qq, 3 * NQF)];
+    if (en >= 0) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) xn[s] = nb((long)(c * NS + s) * nc + en);
+    } else {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) xn[s] = 0.0;
+    }
+#pragma unroll
+    for (int qq = 0; qq < NQF; ++qq) {
+      const int qn = rev ? NQF - 1 - qq : qq;
+      double j = 0.0, jn = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        j += t.FBu[(f * NQF + qq) * NS + s] * xv[s];
+        jn += sFBu[(fn * NQF + qn) * NS + s] * xn[s];
+      }
+      j -= jn;
+      const double jo = pair_swap(j);
+      const double jdotn = c ? (jo * nx + j * ny) : (j * nx + jo * ny);
+      const double con = bq[qq] * j - alpha * t.fw[qq] * jdotn * ncomp;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) y[s] += t.FBu[(f * NQF + qq) * NS + s] * con;
+    }
+  }
+}
+
+// Waves per SIMD the Step I operator kernels are compiled for (bounds their
+// registers, and with them how many loads the compiler keeps in flight).
+#ifndef HDG_STEP1_WAVES
+#define HDG_STEP1_WAVES 2
+#endif
+constexpr int kStep1Waves = HDG_STEP1_WAVES;
+
+// Stage the facet trace table in LDS: the neighbour's table row is indexed
+// by the neighbour's local facet and orientation, which differ between lanes.
+template <int K>
+__device__ __forceinline__ void stage_fbu(const DTab& t, double* sFBu) {
+  constexpr int N = 3 * Dims<K>::NQF * Dims<K>::NS;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) sFBu[i] = t.FBu[i];
+  __syncthreads();
+}
+
+// out = x - (adt/det) f_im(., x; Q*): the mass-scaled Step I operator on
+// structure-of-arrays vectors (two threads per cell), with per-block
+// partial sums (nb = gridDim.x sets of partials at part + i*nb):
+//   DOT 0: none;  DOT 1: w.out;  DOT 2: out.x, out.out, w.x, w.out.
+// In BiCGStab, DOT 1 gives rh.v for v = A p and DOT 2 gives t.s, t.t, rh.s,
+// rh.t for t = A s.
+template <int K, int DOT>
+__global__ void __launch_bounds__(kBlock, kStep1Waves) k_apply_soa(DMesh m, DTab t, const double* __restrict__ V,
+                                                                   const double* __restrict__ beta, double alpha,
+                                                                   double adt, const double* __restrict__ x,
+                                                                   const double* __restrict__ w,
+                                                                   double* __restrict__ out,
+                                                                   double* __restrict__ part) {
+  using D = Dims<K>;
+  constexpr int NS = D::NS;
+  __shared__ double sFBu[3 * D::NQF * NS];
+  stage_fbu<K>(t, sFBu);
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nc = m.nc;
+  const int e = (int)(tid >> 1), c = (int)(tid & 1);
+  double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+  if (e < nc) {
+    double xv[NS], y[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) xv[s] = x[(long)(c * NS + s) * nc + e];
+    step1_core<K>(m, t, sFBu, V, beta, nc, e, c, alpha, xv, y, [&](long i) { return x[i]; });
+    const double sc = adt / m.geo[D_DET * nc + e];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const long idx = (long)(c * NS + s) * nc + e;
-      const T o = xv[s] - sc * y[s];
-      out[idx] = (TS)o;
-      if (DOT == 1) d1 += (double)w[idx] * (double)o;
+      const double o = xv[s] - sc * y[s];
+      out[idx] = o;
+      if (DOT == 1) d0 += w[idx] * o;
       if (DOT == 2) {
-        d1 += (double)o * (double)xv[s];
-        d2 += (double)o * (double)o;
-        d3 += (double)xv[s] * (double)xv[s];
+        const double wv = w[idx];
+        d0 += o * xv[s];
+        d1 += o * o;
+        d2 += wv * xv[s];
+        d3 += wv * o;
       }
     }
   }
   if (DOT >= 1) {
-    const double s1 = block_sum(d1);
-    if (threadIdx.x == 0) part[blockIdx.x] = s1;
+    d0 = block_sum(d0);
+    if (threadIdx.x == 0) part[blockIdx.x] = d0;
   }
   if (DOT == 2) {
-    const double s2 = block_sum(d2);
-    if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = s2;
-    const double s3 = block_sum(d3);
-    if (threadIdx.x == 0) part[2 * gridDim.x + blockIdx.x] = s3;
+    const int nb = gridDim.x;
+    d1 = block_sum(d1);
+    d2 = block_sum(d2);
+    d3 = block_sum(d3);
+    if (threadIdx.x == 0) {
+      part[nb + blockIdx.x] = d1;
+      part[2 * nb + blockIdx.x] = d2;
+      part[3 * nb + blockIdx.x] = d3;
+    }
   }
 }
 
-// AoS [cell][2 ns] <-> SoA [(c ns + s) nc + cell]; scale multiplies by 1/det^pw
-template <int K, typename T>
-__global__ void k_to_soa(DMesh m, int inv_det, const double* __restrict__ x, T* __restrict__ y) {
+// Sum of np partials in a fixed order, returned to every thread of the block.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int np) {
+  __shared__ double r;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) v += part[i];
+  v = block_sum(v);
+  if (threadIdx.x == 0) r = v;
+  __syncthreads();
+  return r;
+}
+
+// BiCGStab on the mass-scaled Step I operator A.  Per iteration, with the
+// scalars of the iteration in the slot sc (layout BiCGSlot):
+//   v = A p                 k_apply_soa<DOT 1>: partials of rh.v
+//   s = r - alpha v         k_bicg_s: every block finishes rh.v itself
+//                           (alpha = rho / rh.v), block 0 records it
+//   t = A s                 k_apply_soa<DOT 2>: partials of t.s, t.t, rh.s, rh.t
+//   x += alpha p + omega s, r = s - omega t, p = r + beta (p - omega v)
+//                           k_bicg_xrp: every block finishes the four sums
+//                           (omega, beta), block 0 records them and opens the
+//                           next slot; partials of r.r
+// Both vector kernels run on a fixed grid of kRedBlocks blocks, so the
+// redundant finishes read few partials in total.
+__global__ void __launch_bounds__(kBlock) k_bicg_s(long n, int np, const double* __restrict__ part,
+                                                   double* __restrict__ sc, const double* __restrict__ R,
+                                                   const double* __restrict__ Vv, double* __restrict__ S) {
+  const double rv = sum_partials(part, np);
+  const bool ok = rv != 0.0 && rv == rv;
+  const double al = ok ? sc[BS_RHO] / rv : 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    S[i] = R[i] - al * Vv[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc[BS_RV] = rv;
+    sc[BS_ALPHA] = al;
+    if (!ok) sc[BS_FLAG] = 1.0;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_bicg_xrp(long n, int np, const double* __restrict__ part2,
+                                                     double* __restrict__ sc, const double* __restrict__ S,
+                                                     const double* __restrict__ Tv, const double* __restrict__ Vv,
+                                                     double* __restrict__ X, double* __restrict__ R,
+                                                     double* __restrict__ P, double* __restrict__ part) {
+  // omega = t.s / t.t, rho_next = rh.s - omega rh.t (= rh.r_next),
+  // beta = (rho_next / rho)(alpha / omega)
+  const double ts = sum_partials(part2, np);
+  const double tt = sum_partials(part2 + np, np);
+  const double rs = sum_partials(part2 + 2 * np, np);
+  const double rt = sum_partials(part2 + 3 * np, np);
+  const double al = sc[BS_ALPHA], rho = sc[BS_RHO];
+  const bool okw = tt > 0.0 && ts != 0.0 && ts == ts;
+  const double om = okw ? ts / tt : 0.0;
+  const double rho_next = rs - om * rt;
+  const bool okb = okw && rho != 0.0 && rho_next == rho_next;
+  const double be = okb ? (rho_next / rho) * (al / om) : 0.0;
+  double rr = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double p = P[i], s = S[i];
+    X[i] += al * p + om * s;
+    const double r = s - om * Tv[i];
+    R[i] = r;
+    rr += r * r;
+    P[i] = r + be * (p - om * Vv[i]);
+  }
+  rr = block_sum(rr);
+  if (threadIdx.x == 0) part[blockIdx.x] = rr;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc[BS_TS] = ts;
+    sc[BS_TT] = tt;
+    sc[BS_OMEGA] = om;
+    sc[BS_BETA] = be;
+    if (!okb) sc[BS_FLAG] = 1.0;
+    sc[BS_STRIDE + BS_RHO] = rho_next;
+    sc[BS_STRIDE + BS_FLAG] = 0.0;
+  }
+}
+
+// Slot 0 of a (re)start: no previous coefficients; rho is set by the caller.
+__global__ void k_bicg_init(double* __restrict__ sc) {
+  if (threadIdx.x < BS_STRIDE && threadIdx.x != BS_RHO) sc[threadIdx.x] = 0.0;
+}
+
+// AoS [cell][2 ns] <-> SoA [(c ns + s) nc + cell]; inv_det = 1 also divides by det J
+template <int K>
+__global__ void k_to_soa(DMesh m, int inv_det, const double* __restrict__ x, double* __restrict__ y) {
   constexpr int NU = Dims<K>::NU;
   const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= (long)m.nc * NU) return;
   const long e = tid % m.nc, i = tid / m.nc;
   const double sc = inv_det ? 1.0 / m.geo[D_DET * (long)m.nc + e] : 1.0;
-  y[tid] = (T)(sc * x[e * NU + i]);
+  y[tid] = sc * x[e * NU + i];
 }
-template <int K, typename T>
-__global__ void k_to_aos(DMesh m, const T* __restrict__ x, double* __restrict__ y) {
+template <int K>
+__global__ void k_to_aos(DMesh m, const double* __restrict__ x, double* __restrict__ y) {
   constexpr int NU = Dims<K>::NU;
   const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= (long)m.nc * NU) return;
   const long e = tid / NU, i = tid % NU;
-  y[tid] = (double)x[i * m.nc + e];
-}
-template <typename T>
-__global__ void k_convert(long n, const double* __restrict__ x, T* __restrict__ y) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = (T)x[i];
+  y[tid] = x[i * m.nc + e];
 }
 
 // ===================================================================== a6
@@ -1018,12 +1235,11 @@ __global__ void k_dense_mv(int n, const double* __restrict__ M, const double* __
   y[i] = acc;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_dot(long n, const T* __restrict__ a, const T* __restrict__ b,
+__global__ void __launch_bounds__(kBlock) k_dot(long n, const double* __restrict__ a, const double* __restrict__ b,
                                                 double* __restrict__ part) {
   double v = 0.0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-    v += (double)a[i] * (double)(b ? b[i] : a[i]);
+    v += a[i] * (b ? b[i] : a[i]);
   v = block_sum(v);
   if (threadIdx.x == 0) part[blockIdx.x] = v;
 }
@@ -1066,15 +1282,6 @@ __global__ void __launch_bounds__(kBlock) k_finish_mean(const double* __restrict
 }
 
 // out[j] = sum_{i < np} part[j * np + i] for j < nsets
-__global__ void __launch_bounds__(kBlock) k_finish_sets(const double* __restrict__ part, int np, int nsets,
-                                                        double* __restrict__ out) {
-  for (int j = 0; j < nsets; ++j) {
-    double v = 0.0;
-    for (int i = threadIdx.x; i < np; i += blockDim.x) v += part[(long)j * np + i];
-    v = block_sum(v);
-    if (threadIdx.x == 0) out[j] = v;
-  }
-}
 
 __global__ void __launch_bounds__(kBlock) k_finish2(const double* __restrict__ part2, double* __restrict__ out2) {
   double v = 0.0, w = 0.0;
@@ -1084,20 +1291,17 @@ __global__ void __launch_bounds__(kBlock) k_finish2(const double* __restrict__ p
   if (threadIdx.x == 0) { out2[0] = v; out2[1] = w; }
 }
 
-template <typename T>
-__global__ void k_axpby(long n, double a, const T* __restrict__ x, double b, T* __restrict__ y) {
+__global__ void k_axpby(long n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = (T)(a * (double)x[i] + (b != 0.0 ? b * (double)y[i] : 0.0));
+  if (i < n) y[i] = a * x[i] + (b != 0.0 ? b * y[i] : 0.0);
 }
-template <typename T>
-__global__ void k_copy(long n, const T* __restrict__ x, T* __restrict__ y) {
+__global__ void k_copy(long n, const double* __restrict__ x, double* __restrict__ y) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = x[i];
 }
-template <typename T>
-__global__ void k_fill(long n, double v, T* __restrict__ y) {
+__global__ void k_fill(long n, double v, double* __restrict__ y) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = (T)v;
+  if (i < n) y[i] = v;
 }
 // remove the constant-trace component: g_F,0 -= sum / nF
 __global__ void k_project_const(int nF, int nf, const double* __restrict__ sum, double* __restrict__ g) {
@@ -1125,57 +1329,6 @@ __global__ void k_pcg_direction(long n, const double* __restrict__ rzn, const do
                                 const double* __restrict__ z, double* __restrict__ p) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = z[i] + (rzn[0] / rzo[0]) * p[i];
-}
-
-// BiCGStab scalars, 8 per iteration i: [0] rho_i = rhat.r_i, [1] rhat.v_i
-// (r_i.r_i until the iteration overwrites it), [2] t.s, [3] t.t, [4] s.s
-// alpha and omega fall back to 0 on an exact breakdown; the host then restarts
-__device__ __forceinline__ double bicg_alpha(const double* sc, int i) {
-  return sc[8 * i + 1] != 0.0 ? sc[8 * i] / sc[8 * i + 1] : 0.0;
-}
-// omega = t.s / t.t (local minimal residual)
-__device__ __forceinline__ double bicg_omega(const double* sc, int i) {
-  return sc[8 * i + 3] > 0.0 ? sc[8 * i + 2] / sc[8 * i + 3] : 0.0;
-}
-
-template <typename T>
-__global__ void k_bicg_p(long n, const double* __restrict__ sc, int it, const T* __restrict__ r,
-                         const T* __restrict__ v, T* __restrict__ p) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (it == 0) { p[i] = r[i]; return; }
-  const double om = bicg_omega(sc, it - 1);
-  // a vanished omega or rho leaves beta = 0 (steepest-descent direction) until the host restarts
-  const double rho_old = sc[8 * (it - 1)];
-  const double beta = (fabs(om) > 1e-30 && rho_old != 0.0) ? (sc[8 * it] / rho_old) * (bicg_alpha(sc, it - 1) / om) : 0.0;
-  p[i] = (T)((double)r[i] + beta * ((double)p[i] - om * (double)v[i]));
-}
-
-template <typename T>
-__global__ void k_bicg_s(long n, const double* __restrict__ sc, int it, const T* __restrict__ r,
-                         const T* __restrict__ v, T* __restrict__ s) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) s[i] = (T)((double)r[i] - bicg_alpha(sc, it) * (double)v[i]);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_bicg_xr(long n, const double* __restrict__ sc, int it,
-                                                    const T* __restrict__ p, const T* __restrict__ s,
-                                                    const T* __restrict__ t, T* __restrict__ x,
-                                                    T* __restrict__ r, const T* __restrict__ rhat,
-                                                    double* __restrict__ part2) {
-  const double al = bicg_alpha(sc, it), om = bicg_omega(sc, it);
-  double a = 0.0, b = 0.0;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    x[i] = (T)((double)x[i] + al * (double)p[i] + om * (double)s[i]);
-    const T ri = (T)((double)s[i] - om * (double)t[i]);
-    r[i] = ri;
-    a += (double)rhat[i] * (double)ri;
-    b += (double)ri * (double)ri;
-  }
-  a = block_sum(a);
-  b = block_sum(b);
-  if (threadIdx.x == 0) { part2[blockIdx.x] = a; part2[kRedBlocks + blockIdx.x] = b; }
 }
 
 // ----------------------------------------------------------------- IDR(s)
@@ -1322,35 +1475,38 @@ void launch_apply(int k, hipStream_t st, int mode, DMesh m, DTab t, const double
     HDG_DISPATCH(k, (k_apply<KK, 2><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, adv, alpha, adt, x, r, p, lam, out)));
   }
 }
-template <typename TS, typename T>
-void launch_apply_soa(int k, hipStream_t st, int dot, DMesh m, DTab t, const T* adv, double alpha, double adt,
-                      const TS* x, const TS* w, TS* out, double* part) {
+void launch_step1_matrix(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, double* V,
+                         double* beta) {
+  HDG_DISPATCH(k, (k_step1_matrix<KK><<<nblocks((long)m.nc * Dims<KK>::NS), kBlock, 0, st>>>(m, t, Qs, V)));
+  HDG_DISPATCH(k, (k_step1_beta<KK><<<nblocks(3L * m.nc), kBlock, 0, st>>>(m, t, Qs, delta_up, beta)));
+}
+void launch_apply_soa(int k, hipStream_t st, int dot, DMesh m, DTab t, const double* V, const double* beta,
+                      double alpha, double adt, const double* x, const double* w, double* out, double* part) {
   const int nb = nblocks(2L * m.nc);
   if (dot == 0) {
-    HDG_DISPATCH(k, (k_apply_soa<KK, 0, TS, T><<<nb, kBlock, 0, st>>>(m, t, adv, alpha, adt, x, w, out, part)));
+    HDG_DISPATCH(k, (k_apply_soa<KK, 0><<<nb, kBlock, 0, st>>>(m, t, V, beta, alpha, adt, x, w, out, part)));
   } else if (dot == 1) {
-    HDG_DISPATCH(k, (k_apply_soa<KK, 1, TS, T><<<nb, kBlock, 0, st>>>(m, t, adv, alpha, adt, x, w, out, part)));
+    HDG_DISPATCH(k, (k_apply_soa<KK, 1><<<nb, kBlock, 0, st>>>(m, t, V, beta, alpha, adt, x, w, out, part)));
   } else {
-    HDG_DISPATCH(k, (k_apply_soa<KK, 2, TS, T><<<nb, kBlock, 0, st>>>(m, t, adv, alpha, adt, x, w, out, part)));
+    HDG_DISPATCH(k, (k_apply_soa<KK, 2><<<nb, kBlock, 0, st>>>(m, t, V, beta, alpha, adt, x, w, out, part)));
   }
 }
-template void launch_apply_soa<double, double>(int, hipStream_t, int, DMesh, DTab, const double*, double, double,
-                                               const double*, const double*, double*, double*);
-template void launch_apply_soa<double, float>(int, hipStream_t, int, DMesh, DTab, const float*, double, double,
-                                              const double*, const double*, double*, double*);
 int apply_soa_blocks(long nc) { return nblocks(2L * nc); }
-template <typename T>
-void launch_to_soa(int k, hipStream_t st, DMesh m, int inv_det, const double* x, T* y) {
-  HDG_DISPATCH(k, (k_to_soa<KK, T><<<nblocks((long)m.nc * Dims<KK>::NU), kBlock, 0, st>>>(m, inv_det, x, y)));
+void launch_bicg_s(hipStream_t st, long n, long nc, const double* part, double* sc, const double* r, const double* v,
+                   double* s) {
+  k_bicg_s<<<kRedBlocks, kBlock, 0, st>>>(n, nblocks(2L * nc), part, sc, r, v, s);
 }
-template <typename T>
-void launch_to_aos(int k, hipStream_t st, DMesh m, const T* x, double* y) {
-  HDG_DISPATCH(k, (k_to_aos<KK, T><<<nblocks((long)m.nc * Dims<KK>::NU), kBlock, 0, st>>>(m, x, y)));
+void launch_bicg_xrp(hipStream_t st, long n, long nc, const double* part2, double* sc, const double* s,
+                     const double* tv, const double* v, double* x, double* r, double* p, double* part) {
+  k_bicg_xrp<<<kRedBlocks, kBlock, 0, st>>>(n, nblocks(2L * nc), part2, sc, s, tv, v, x, r, p, part);
 }
-template void launch_to_soa<double>(int, hipStream_t, DMesh, int, const double*, double*);
-template void launch_to_soa<float>(int, hipStream_t, DMesh, int, const double*, float*);
-template void launch_to_aos<double>(int, hipStream_t, DMesh, const double*, double*);
-template void launch_to_aos<float>(int, hipStream_t, DMesh, const float*, double*);
+void launch_bicg_init(hipStream_t st, double* sc) { k_bicg_init<<<1, 64, 0, st>>>(sc); }
+void launch_to_soa(int k, hipStream_t st, DMesh m, int inv_det, const double* x, double* y) {
+  HDG_DISPATCH(k, (k_to_soa<KK><<<nblocks((long)m.nc * Dims<KK>::NU), kBlock, 0, st>>>(m, inv_det, x, y)));
+}
+void launch_to_aos(int k, hipStream_t st, DMesh m, const double* x, double* y) {
+  HDG_DISPATCH(k, (k_to_aos<KK><<<nblocks((long)m.nc * Dims<KK>::NU), kBlock, 0, st>>>(m, x, y)));
+}
 void launch_div(int k, hipStream_t st, DMesh m, DTab t, const double* F, double scale, double* out) {
   HDG_DISPATCH(k, (k_div<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, F, scale, out)));
 }
@@ -1381,10 +1537,7 @@ void launch_dense_mv(hipStream_t st, int n, const double* M, const double* x, do
   k_dense_mv<<<nblocks(n), kBlock, 0, st>>>(n, M, x, y);
 }
 void launch_dot(hipStream_t st, long n, const double* a, const double* b, double* part) {
-  k_dot<double><<<kRedBlocks, kBlock, 0, st>>>(n, a, b, part);
-}
-void launch_dot(hipStream_t st, long n, const float* a, const float* b, double* part) {
-  k_dot<float><<<kRedBlocks, kBlock, 0, st>>>(n, a, b, part);
+  k_dot<<<kRedBlocks, kBlock, 0, st>>>(n, a, b, part);
 }
 void launch_dot_sub(hipStream_t st, long n, int stride, int off, const double* a, double* part) {
   k_dot_sub<<<kRedBlocks, kBlock, 0, st>>>(n, stride, off, a, part);
@@ -1396,22 +1549,12 @@ void launch_finish_mean(hipStream_t st, const double* part, int nparts, double a
   k_finish_mean<<<1, kBlock, 0, st>>>(part, nparts, area, out);
 }
 void launch_axpby(hipStream_t st, long n, double a, const double* x, double b, double* y) {
-  k_axpby<double><<<nblocks(n), kBlock, 0, st>>>(n, a, x, b, y);
-}
-void launch_axpby(hipStream_t st, long n, double a, const float* x, double b, float* y) {
-  k_axpby<float><<<nblocks(n), kBlock, 0, st>>>(n, a, x, b, y);
+  k_axpby<<<nblocks(n), kBlock, 0, st>>>(n, a, x, b, y);
 }
 void launch_copy(hipStream_t st, long n, const double* x, double* y) {
-  k_copy<double><<<nblocks(n), kBlock, 0, st>>>(n, x, y);
+  k_copy<<<nblocks(n), kBlock, 0, st>>>(n, x, y);
 }
-void launch_copy(hipStream_t st, long n, const float* x, float* y) {
-  k_copy<float><<<nblocks(n), kBlock, 0, st>>>(n, x, y);
-}
-void launch_fill(hipStream_t st, long n, double v, double* y) { k_fill<double><<<nblocks(n), kBlock, 0, st>>>(n, v, y); }
-void launch_fill(hipStream_t st, long n, double v, float* y) { k_fill<float><<<nblocks(n), kBlock, 0, st>>>(n, v, y); }
-void launch_convert(hipStream_t st, long n, const double* x, float* y) {
-  k_convert<float><<<nblocks(n), kBlock, 0, st>>>(n, x, y);
-}
+void launch_fill(hipStream_t st, long n, double v, double* y) { k_fill<<<nblocks(n), kBlock, 0, st>>>(n, v, y); }
 void launch_project_const(hipStream_t st, int nF, int nf, const double* sum, double* g) {
   k_project_const<<<nblocks(nF), kBlock, 0, st>>>(nF, nf, sum, g);
 }
@@ -1422,34 +1565,10 @@ void launch_pcg_update(hipStream_t st, long n, const double* rz, const double* p
 void launch_pcg_direction(hipStream_t st, long n, const double* rzn, const double* rzo, const double* z, double* p) {
   k_pcg_direction<<<nblocks(n), kBlock, 0, st>>>(n, rzn, rzo, z, p);
 }
-template <typename T>
-void launch_bicg_p(hipStream_t st, long n, const double* sc, int it, const T* r, const T* v, T* p) {
-  k_bicg_p<T><<<nblocks(n), kBlock, 0, st>>>(n, sc, it, r, v, p);
-}
-template <typename T>
-void launch_bicg_s(hipStream_t st, long n, const double* sc, int it, const T* r, const T* v, T* s) {
-  k_bicg_s<T><<<nblocks(n), kBlock, 0, st>>>(n, sc, it, r, v, s);
-}
-template <typename T>
-void launch_bicg_xr(hipStream_t st, long n, const double* sc, int it, const T* p, const T* s, const T* t, T* x,
-                    T* r, const T* rhat, double* part2) {
-  k_bicg_xr<T><<<kRedBlocks, kBlock, 0, st>>>(n, sc, it, p, s, t, x, r, rhat, part2);
-}
-template void launch_bicg_p<double>(hipStream_t, long, const double*, int, const double*, const double*, double*);
-template void launch_bicg_p<float>(hipStream_t, long, const double*, int, const float*, const float*, float*);
-template void launch_bicg_s<double>(hipStream_t, long, const double*, int, const double*, const double*, double*);
-template void launch_bicg_s<float>(hipStream_t, long, const double*, int, const float*, const float*, float*);
-template void launch_bicg_xr<double>(hipStream_t, long, const double*, int, const double*, const double*,
-                                     const double*, double*, double*, const double*, double*);
-template void launch_bicg_xr<float>(hipStream_t, long, const double*, int, const float*, const float*,
-                                    const float*, float*, float*, const float*, double*);
 void launch_dot2(hipStream_t st, long n, const double* a, const double* b, const double* c, double* part2) {
   k_dot2<<<kRedBlocks, kBlock, 0, st>>>(n, a, b, c, part2);
 }
 void launch_finish2(hipStream_t st, const double* part2, double* out2) { k_finish2<<<1, kBlock, 0, st>>>(part2, out2); }
-void launch_finish_sets(hipStream_t st, const double* part, int np, int nsets, double* out) {
-  k_finish_sets<<<1, kBlock, 0, st>>>(part, np, nsets, out);
-}
 void launch_idr_u(hipStream_t st, long n, int k, int s, IdrCoef c, double om, const double* r, const double* G,
                   double* U) {
   k_idr_u<<<nblocks(n), kBlock, 0, st>>>(n, k, s, c, om, r, G, U);

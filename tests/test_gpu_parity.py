@@ -94,7 +94,13 @@ def test_a4_momentum_residual(n, k, pert):
     assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
-@pytest.mark.parametrize("n,k,pert", OPS)
+# Step I runs as fused launches whose inner products finish in the last block
+# to arrive: meshes with several blocks per launch (2 threads per cell, 256
+# per block) check that the partials of all blocks are collected
+STEP1 = OPS + [(24, 3, 0.1), (40, 1, 0.1), (16, 4, 0.1)]
+
+
+@pytest.mark.parametrize("n,k,pert", STEP1)
 def test_a5_tentative_velocity(n, k, pert):
     import scipy.sparse.linalg as spla
     torch = torch_or_skip()
@@ -106,10 +112,15 @@ def test_a5_tentative_velocity(n, k, pert):
     Qs = d.bdm_project(d.l2_project_velocity(lambda x, y: hi.streamfunction_velocity(par, x, y)))
     rhs = rng.standard_normal(d.nQ)
     adt = 0.01
-    ref = spla.splu((d.mass() - adt * d.advection(Qs)).tocsc()).solve(rhs)
+    A = (d.mass() - adt * d.advection(Qs)).tocsc()
+    ref = spla.splu(A).solve(rhs)
     ctx = context(X, C, degree=k, rtol_velocity=1e-13)
     got = host(ctx.tentative_velocity(adt, dev(torch, Qs), dev(torch, rhs)))
-    assert rel_l2_cells(d, got, ref, d.nu) < 1e-11
+    # the solver stops on the mass-scaled residual; the forward error adds the
+    # conditioning of the operator, which grows with the mesh
+    minv = 1.0 / d.mass().diagonal()
+    assert np.linalg.norm(minv * (A @ got - rhs)) <= 1e-11 * np.linalg.norm(minv * rhs)
+    assert rel_l2_cells(d, got, ref, d.nu) < (1e-11 if n <= 4 else 1e-9)
 
 
 @pytest.mark.parametrize("n,k,pert", OPS)
