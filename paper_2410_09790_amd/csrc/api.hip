@@ -201,6 +201,12 @@ struct hdg_ctx {
   double t_trace = 0.0, t_velocity = 0.0, t_other = 0.0;
   int max_pcg_bicg_seen = 0;
   bool not_converged = false;
+  // an iteration cap was reached: the result is kept and flagged; the first
+  // such event of a call is reported through hdg_last_error
+  void cap_reached(const std::string& what) {
+    if (!not_converged) err = what;
+    not_converged = true;
+  }
 
   template <class T>
   T* dalloc(size_t n) {
@@ -231,6 +237,7 @@ struct hdg_ctx {
   hdg::TraceOp& trace_op(double c);
   void build_mg(hdg::TraceOp& op);
   void precond(hdg::TraceOp& op, const double* r, double* z);
+  void project_null(double* v);
   void mg_apply(hdg::TraceOp& op, const double* r, double* z);
   void vcycle(hdg::TraceOp& op, int l);
   int pcg(hdg::TraceOp& op, const double* g, double* x);
@@ -478,9 +485,22 @@ void hdg_ctx::mg_apply(TraceOp& op, const double* r, double* z) {
   launch_jacobi_sweep(k, st, nF, op.vals, op.cols, op.Dinv, om, r, t1, z);
 }
 
+// Remove from a trace vector its component along the null vector of the
+// condensed operator (the constant trace: e_0 = 1 on every facet).
+void hdg_ctx::project_null(double* v) {
+  double* sum = scal + 3 * (prm.max_it_trace + 4);
+  launch_dot_sub(st, hm.nF, nf, 0, v, part);
+  launch_finish(st, part, kRedBlocks, sum);
+  launch_project_const(st, (int)hm.nF, nf, sum, v);
+}
+
+// z = B r; the block-Jacobi parts of B do not preserve orthogonality to the
+// null vector, so z is projected back: otherwise the iterate drifts along
+// the null vector, its norm grows and the attainable residual with it.
 void hdg_ctx::precond(TraceOp& op, const double* r, double* z) {
   if (op.mg) mg_apply(op, r, z);
   else launch_blockdiag(k, st, (int)hm.nF, op.Dinv, r, z);
+  project_null(z);
   KCHK();
 }
 
@@ -520,7 +540,8 @@ int hdg_ctx::pcg(TraceOp& op, const double* gin, double* x) {
     launch_finish(st, part, kRedBlocks, rz + it + 1);
     launch_pcg_direction(st, n, rz + it + 1, rz + it, pz, pp);
   }
-  not_converged = true;
+  cap_reached("PCG on the trace system: " + std::to_string(maxit) + " iterations without reaching rtol_trace (relative residual " +
+              std::to_string(std::sqrt(read_scalar(rr + maxit - 1)) / gnorm) + ")");
   return maxit;
 }
 
@@ -533,10 +554,8 @@ void hdg_ctx::solve_trace(double c, const double* Fw, const double* Fpsi, const 
     launch_rhs_condense(k, st, dm, dt, c, prm.tau, op.Pinv, Fw, Fpsi, ycell);
     launch_gather_rhs(k, st, dm, ycell, Fmu, g);
   }
-  // remove the component along the null vector (constant trace = e_0 on every facet)
-  launch_dot_sub(st, hm.nF, nf, 0, g, part);
-  launch_finish(st, part, kRedBlocks, scal + 3 * (prm.max_it_trace + 4));
-  launch_project_const(st, (int)hm.nF, nf, scal + 3 * (prm.max_it_trace + 4), g);
+  // compatible right-hand side: no component along the null vector
+  project_null(g);
   KCHK();
   const int its = pcg(op, g, lout);
   pcg_iters.push_back(its);
@@ -635,7 +654,9 @@ int hdg_ctx::bicgstab(double adt, const double* b_aos, double* x_aos) {
       if (!(rr == rr)) throw SolverBreakdown("BiCGStab breakdown (NaN residual); the result is invalid");
       if (std::sqrt(rr) <= rtol * bnorm) break;
       if (it >= maxit) {
-        not_converged = true;
+        cap_reached("BiCGStab (Step I): " + std::to_string(maxit) + " iterations without reaching rtol_velocity "
+                    "(relative residual " + std::to_string(std::sqrt(rr) / bnorm) + ", " +
+                    std::to_string(restarts) + " restarts)");
         break;
       }
       bool flag = false;
@@ -759,7 +780,9 @@ int hdg_ctx::idrs(double adt, const double* b, double* x) {
     if (!(normr == normr)) throw SolverBreakdown("IDR(s) breakdown (NaN residual)");
     ++it;
   }
-  if (normr > tol) not_converged = true;
+  if (normr > tol)
+    cap_reached("IDR(s) (Step I): " + std::to_string(it) + " iterations without reaching rtol_velocity (relative "
+                "residual " + std::to_string(normr / bnorm) + ")");
   return it;
 }
 
@@ -966,6 +989,7 @@ int hdg_cell_points(const hdg_ctx* ctx, double* xy) {
 int hdg_set_velocity_from_points(hdg_ctx* ctx, const double* qvals) {
   if (!ctx || !qvals) return HDG_ERR_INVALID_ARG;
   ctx->not_converged = false;
+  ctx->err.clear();
   API_BEGIN
   launch_project(ctx->k, ctx->st, ctx->dm, ctx->dt, qvals, ctx->Q);
   KCHK();
@@ -977,6 +1001,7 @@ int hdg_set_velocity_from_points(hdg_ctx* ctx, const double* qvals) {
 int hdg_set_state(hdg_ctx* ctx, const double* Qv, const double* pv, const double* lv) {
   if (!ctx || !Qv || !pv || !lv) return HDG_ERR_INVALID_ARG;
   ctx->not_converged = false;
+  ctx->err.clear();
   API_BEGIN
   launch_copy(ctx->st, ctx->nQ, Qv, ctx->Q);
   launch_copy(ctx->st, ctx->nP, pv, ctx->p);
@@ -992,6 +1017,7 @@ int hdg_get_state(const hdg_ctx* cctx, double* Qv, double* pv, double* lv) {
   if (!ctx) return HDG_ERR_INVALID_ARG;
   if (!ctx->have_state) { ctx->err = "no state set"; return HDG_ERR_BAD_STATE; }
   ctx->not_converged = false;
+  ctx->err.clear();
   API_BEGIN
   if (Qv) launch_copy(ctx->st, ctx->nQ, ctx->Q, Qv);
   if (pv) launch_copy(ctx->st, ctx->nP, ctx->p, pv);
@@ -1005,6 +1031,7 @@ int hdg_advance(hdg_ctx* ctx, double dtv, int nsteps) {
   if (!ctx || !(dtv > 0) || nsteps < 0) return HDG_ERR_INVALID_ARG;
   if (!ctx->have_state) { ctx->err = "no state set"; return HDG_ERR_BAD_STATE; }
   ctx->not_converged = false;
+  ctx->err.clear();
   API_BEGIN
   for (int n = 0; n < nsteps; ++n) ctx->step(dtv);
   API_END(ctx)
@@ -1014,6 +1041,7 @@ int hdg_solve_trace(hdg_ctx* ctx, double c, const double* Fw, const double* Fpsi
                     double* pv, double* lv) {
   if (!ctx || !(c > 0) || !U || !pv || !lv) return HDG_ERR_INVALID_ARG;
   ctx->not_converged = false;
+  ctx->err.clear();
   API_BEGIN
   ctx->solve_trace(c, Fw, Fpsi, Fmu, U, pv, lv);
   API_END(ctx)
@@ -1022,6 +1050,7 @@ int hdg_solve_trace(hdg_ctx* ctx, double c, const double* Fw, const double* Fpsi
 int hdg_trace_matvec(hdg_ctx* ctx, double c, const double* x, double* y) {
   if (!ctx || !(c > 0) || !x || !y) return HDG_ERR_INVALID_ARG;
   ctx->not_converged = false;
+  ctx->err.clear();
   API_BEGIN
   TraceOp& op = ctx->trace_op(c);
   launch_spmv(ctx->k, ctx->st, (int)ctx->hm.nF, op.vals, op.cols, x, y);
@@ -1033,6 +1062,7 @@ int hdg_trace_matvec(hdg_ctx* ctx, double c, const double* x, double* y) {
 int hdg_bdm_project(hdg_ctx* ctx, const double* Qv, double* Qsv) {
   if (!ctx || !Qv || !Qsv) return HDG_ERR_INVALID_ARG;
   ctx->not_converged = false;
+  ctx->err.clear();
   API_BEGIN
   launch_bdm(ctx->k, ctx->st, ctx->dm, ctx->dt, Qv, Qsv);
   KCHK();
@@ -1043,6 +1073,7 @@ int hdg_bdm_project(hdg_ctx* ctx, const double* Qv, double* Qsv) {
 int hdg_weak_divergence(hdg_ctx* ctx, const double* F, double* out) {
   if (!ctx || !F || !out) return HDG_ERR_INVALID_ARG;
   ctx->not_converged = false;
+  ctx->err.clear();
   API_BEGIN
   launch_div(ctx->k, ctx->st, ctx->dm, ctx->dt, F, 1.0, out);
   KCHK();
@@ -1054,6 +1085,7 @@ int hdg_momentum_residual(hdg_ctx* ctx, double adt, const double* r, const doubl
                           const double* pv, const double* lv, double* out) {
   if (!ctx || !r || !Qsv || !Qv || !pv || !lv || !out) return HDG_ERR_INVALID_ARG;
   ctx->not_converged = false;
+  ctx->err.clear();
   API_BEGIN
   launch_prep_adv(ctx->k, ctx->st, ctx->dm, ctx->dt, Qsv, ctx->prm.delta_up, ctx->adv);
   launch_apply(ctx->k, ctx->st, 2, ctx->dm, ctx->dt, ctx->adv, ctx->prm.alpha, adt, Qv, r, pv, lv, out);
@@ -1065,6 +1097,7 @@ int hdg_momentum_residual(hdg_ctx* ctx, double adt, const double* r, const doubl
 int hdg_tentative_velocity(hdg_ctx* ctx, double adt, const double* Qsv, const double* rhs, double* Qbar) {
   if (!ctx || !Qsv || !rhs || !Qbar) return HDG_ERR_INVALID_ARG;
   ctx->not_converged = false;
+  ctx->err.clear();
   API_BEGIN
   ctx->prepare_step1(Qsv);
   // mass-scaled right-hand side rhs / det: the residual kernel with Q = p = lam = 0
@@ -1085,6 +1118,7 @@ int hdg_tentative_velocity(hdg_ctx* ctx, double adt, const double* Qsv, const do
 int hdg_reconstruct_pressure(hdg_ctx* ctx, const double* Qv, double* pv, double* lv) {
   if (!ctx || !Qv || !pv || !lv) return HDG_ERR_INVALID_ARG;
   ctx->not_converged = false;
+  ctx->err.clear();
   API_BEGIN
   ctx->reconstruct(Qv, pv, lv);
   API_END(ctx)
@@ -1093,6 +1127,7 @@ int hdg_reconstruct_pressure(hdg_ctx* ctx, const double* Qv, double* pv, double*
 int hdg_profile(hdg_ctx* ctx, int enable) {
   if (!ctx) return HDG_ERR_INVALID_ARG;
   ctx->not_converged = false;
+  ctx->err.clear();
   API_BEGIN
   ctx->sync();
   ctx->prof.reset();
