@@ -166,11 +166,13 @@ int hdg_tentative_velocity(hdg_ctx* ctx, double adt, const double* Qstar, const 
  * mixed problem with psi-data Div(psi, (Q.grad_h)Q); returns (p, lam). */
 int hdg_reconstruct_pressure(hdg_ctx* ctx, const double* Q, double* p, double* lam);
 
-/* enable != 0: from now on time the main kernel classes (Step I operator,
- * residual, trace SpMV, smoother sweeps, AMG levels, condensation, RHS
- * condensation, back-substitution, BDM, weak divergence, reconstruction
- * data) with HIP events on the context stream; counters are reset.  The
- * sums appear under "kernels" in hdg_get_info.  enable == 0 stops timing. */
+/* enable = N > 0: from now on time every N-th launch of each main kernel
+ * class (Step I operator, residual, trace SpMV, smoother sweeps, AMG levels,
+ * condensation, RHS condensation, back-substitution, BDM, weak divergence,
+ * reconstruction data, Krylov vector updates) with HIP events on the context
+ * stream; counters are reset.  hdg_get_info reports per class under
+ * "kernels": all launches, the number timed and their summed milliseconds.
+ * enable <= 0 stops timing. */
 int hdg_profile(hdg_ctx* ctx, int enable);
 
 /* JSON with sizes, iteration counts of the last calls, timings. */

@@ -100,7 +100,9 @@ struct TraceOp {
   double *cb = nullptr, *cx = nullptr;  // coarsest rhs / solution
 };
 
-// Optional per-kernel-class timing with HIP events on the context stream.
+// Optional per-kernel-class timing with HIP events on the context stream:
+// every `every`-th launch of a class is bracketed by two events (sampling
+// keeps the cost of the event records out of the timed work).
 enum KClass { KC_APPLY_OP = 0, KC_APPLY_RES, KC_TRACE_SPMV, KC_SMOOTH, KC_AMG, KC_CONDENSE, KC_RHS, KC_BACKSUB,
               KC_BDM, KC_DIV, KC_RECON, KC_VECTOR, kNumKClass };
 static const char* kKClassName[kNumKClass] = {"apply_step1_operator", "apply_residual", "trace_spmv",
@@ -110,12 +112,15 @@ static const char* kKClassName[kNumKClass] = {"apply_step1_operator", "apply_res
 
 struct Profiler {
   bool on = false;
+  int every = 1;
   hipStream_t st = nullptr;
   std::vector<hipEvent_t> pool;
   struct Pending { int cls; hipEvent_t a, b; };
   std::vector<Pending> pending;
-  double ms[kNumKClass] = {};
+  double ms[kNumKClass] = {};   // summed over the timed launches
   long launches[kNumKClass] = {};
+  long timed[kNumKClass] = {};
+  bool sample(int cls) { return on && launches[cls]++ % every == 0; }
   hipEvent_t get() {
     if (pool.empty()) {
       hipEvent_t e;
@@ -130,14 +135,14 @@ struct Profiler {
     for (auto& p : pending) {
       float t = 0.f;
       if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) ms[p.cls] += t;
-      launches[p.cls] += 1;
+      timed[p.cls] += 1;
       pool.push_back(p.a);
       pool.push_back(p.b);
     }
     pending.clear();
   }
   void reset() {
-    for (int i = 0; i < kNumKClass; ++i) { ms[i] = 0.0; launches[i] = 0; }
+    for (int i = 0; i < kNumKClass; ++i) { ms[i] = 0.0; launches[i] = 0; timed[i] = 0; }
   }
   ~Profiler() {
     for (auto& p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
@@ -150,10 +155,10 @@ struct Timed {
   int cls;
   hipEvent_t a = nullptr;
   Timed(Profiler& p, int c) : pr(p), cls(c) {
-    if (pr.on) { a = pr.get(); (void)hipEventRecord(a, pr.st); }
+    if (pr.sample(cls)) { a = pr.get(); (void)hipEventRecord(a, pr.st); }
   }
   ~Timed() {
-    if (pr.on && a) {
+    if (a) {
       hipEvent_t b = pr.get();
       (void)hipEventRecord(b, pr.st);
       pr.pending.push_back({cls, a, b});
@@ -1131,7 +1136,8 @@ int hdg_profile(hdg_ctx* ctx, int enable) {
   API_BEGIN
   ctx->sync();
   ctx->prof.reset();
-  ctx->prof.on = enable != 0;
+  ctx->prof.on = enable > 0;
+  ctx->prof.every = enable > 0 ? enable : 1;
   API_END(ctx)
 }
 
@@ -1156,7 +1162,8 @@ int hdg_get_info(const hdg_ctx* ctx, char* buf, size_t cap) {
                   ",\"seconds_velocity\":" + std::to_string(ctx->t_velocity) + ",\"kernels\":{";
   for (int i = 0; i < kNumKClass; ++i) {
     s += std::string(i ? "," : "") + "\"" + kKClassName[i] + "\":{\"launches\":" +
-         std::to_string(ctx->prof.launches[i]) + ",\"ms\":" + std::to_string(ctx->prof.ms[i]) + "}";
+         std::to_string(ctx->prof.launches[i]) + ",\"timed\":" + std::to_string(ctx->prof.timed[i]) +
+         ",\"ms\":" + std::to_string(ctx->prof.ms[i]) + "}";
   }
   s += "}}";
   std::snprintf(buf, cap, "%s", s.c_str());

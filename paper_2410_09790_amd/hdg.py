@@ -225,8 +225,9 @@ class Context:
         self._check(self._lib.hdg_reconstruct_pressure(self._h, _ptr(Q), _ptr(p), _ptr(lam)))
         return p, lam
 
-    def profile(self, enable: bool):
-        self._check(self._lib.hdg_profile(self._h, int(bool(enable))))
+    def profile(self, every: int):
+        """Time every `every`-th launch of each kernel class (0: stop timing)."""
+        self._check(self._lib.hdg_profile(self._h, int(every)))
 
     def info(self) -> dict:
         buf = ctypes.create_string_buffer(1 << 16)
