@@ -14,6 +14,11 @@ the final projection and the pressure reconstruction.
 Metric: trace DOF-IMEX-stages per second = N_trace * (s-1) * steps / wall time,
 with the state resident on the device before the timed region starts.
 
+The line also carries "mixed": the same workload with the per-stage Step I
+cell matrices stored in FP32 (FP64 arithmetic, FP64 Richardson residual and
+trace solves), its throughput and the relative L2 difference of its final
+state from the FP64 run's.
+
 Output: one JSON line on stdout (everything else goes to stderr).
 """
 from __future__ import annotations
@@ -115,6 +120,36 @@ def cpu_baseline(max_seconds: float = 30.0):
                       f"{el:.1f} s, one thread (SuperLU direct solves)"}
 
 
+def mixed_run(hdg, hi, torch, w, X, C, args, ref_ctx):
+    """The same workload with the Step I cell matrices stored in FP32 (FP64
+    arithmetic, FP64 Richardson residual and trace solves): throughput and the
+    relative L2 difference of the final state from the FP64 run above (which
+    has taken the same warm-up and timed steps from the same initial state)."""
+    mctx = hdg.Context(X, C, degree=w["k"], imex=w["scheme"], n_richardson=w["n_richardson"],
+                       trace_solver=w["trace_solver"], rtol_trace=w["rtol_trace"],
+                       rtol_velocity=w["rtol_velocity"], precision="mixed")
+    par = hi.stream_function_params(w["seed"])
+    xy = mctx.cell_points()
+    mctx.set_velocity_from_points(hi.streamfunction_velocity(par, xy[..., 0], xy[..., 1]))
+    mctx.advance(w["dt"], args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mctx.advance(w["dt"], args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # uniform mesh: equal det J in every cell, so 2-norms are L2 norms
+    diffs = {}
+    for name, a, b in zip(("Q", "p", "lambda"), mctx.get_state(), ref_ctx.get_state()):
+        diffs[name] = float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+    value = mctx.nT * 2 * args.steps / el
+    log(f"mixed: {args.steps} steps {el:.3f} s, {1e3 * el / args.steps:.1f} ms/step, rel. L2 diff vs FP64 {diffs}")
+    mctx.close()
+    return {"value": value, "ms_per_step": 1e3 * el / args.steps,
+            "precision": "FP32 storage of the per-stage Step I cell matrices; FP64 arithmetic, Krylov "
+                         "recurrences, Richardson residual and trace solves",
+            "rel_l2_diff_vs_fp64": diffs, "speedup_vs_fp64": None}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +159,7 @@ def main():
     ap.add_argument("--k", type=int, default=WORKLOAD["k"], help="degree (experiments only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with events")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision run")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -214,6 +250,9 @@ def main():
                         "frac": round(ach / FP64_PEAK_TFLOPS, 4), "traffic": measured_traffic(dom), "kernel": dom,
                         "algorithmic_flops_per_launch": flops, "avg_launch_us": round(avg_s * 1e6, 2),
                         "share_of_step": round(timed[dom]["est_ms"] * 1e-3 / el, 3)}
+    mixed = None
+    if not args.no_mixed:
+        mixed = mixed_run(hdg, hi, torch, w, X, C, args, ctx)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -238,7 +277,10 @@ def main():
                    "velocity_iterations": bicg, "velocity_solves": nvel},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "mixed": mixed,
     }
+    if mixed is not None:
+        mixed["speedup_vs_fp64"] = round(mixed["value"] / value, 3)
     print(json.dumps(out), flush=True)
 
 

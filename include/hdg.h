@@ -65,9 +65,15 @@ typedef enum {
 typedef enum { HDG_IMEX_EULER = 0, HDG_ARS222 = 1, HDG_ARS233 = 2 } hdg_imex_scheme;
 typedef enum { HDG_TRACE_JACOBI_PCG = 0, HDG_TRACE_MG_PCG = 1 } hdg_trace_solver;
 typedef enum { HDG_PRESSURE_RECONSTRUCT = 0, HDG_PRESSURE_FIRST_ORDER = 1 } hdg_pressure_update;
-/* HDG_MIXED is reserved: hdg_create returns HDG_ERR_UNSUPPORTED for it in
- * this build (FP32 arithmetic in the dominant Step I solve makes BiCGStab
- * diverge on this advection-dominated operator). */
+/* HDG_MIXED: the per-stage cell matrices of the Step I operator (the
+ * dominant HBM stream of the tentative-velocity solve, Algorithm 2 Step I)
+ * are stored in FP32; the operator still computes in FP64, and every
+ * Krylov recurrence, inner product, the Richardson residual (which uses the
+ * FP64 form f_im) and the trace solves stay FP64.  The Step I solve is then
+ * exact for an operator within ~1e-7 (relative) of the FP64 one; the
+ * Richardson iteration corrects with the FP64 residual, and a step differs
+ * from the FP64 step by ~1e-7 relative.  FP32 operator arithmetic is not
+ * offered: it makes BiCGStab stall or diverge on this operator. */
 typedef enum { HDG_FP64 = 0, HDG_MIXED = 1 } hdg_precision;
 
 typedef struct hdg_ctx hdg_ctx;

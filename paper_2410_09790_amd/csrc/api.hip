@@ -254,13 +254,17 @@ struct hdg_ctx {
            *v = nullptr;
   };
   KrylovBuf kd;
-  // per-stage Step I data of the current Q*: cell volume matrices and facet
-  // upwind weights (tiles of 32 cells) for the structure-of-arrays operator,
-  // and the advection data of the cell-major residual kernels
-  double *vk = nullptr, *vbeta = nullptr;
+  // per-stage Step I data of the current Q*: cell volume matrices (FP32 in
+  // the mixed-precision mode) and facet upwind weights (tiles of 32 cells)
+  // for the structure-of-arrays operator, and the advection data of the
+  // cell-major residual kernels (FP64 in both modes: the Richardson residual
+  // is the accuracy reference)
+  void* vk = nullptr;
+  bool vk32 = false;
+  double* vbeta = nullptr;
   void prepare_step1(const double* Qstar) {
     hdg::launch_prep_adv(k, st, dm, dt, Qstar, prm.delta_up, adv);
-    hdg::launch_step1_matrix(k, st, dm, dt, Qstar, prm.delta_up, vk, vbeta);
+    hdg::launch_step1_matrix(k, st, dm, dt, Qstar, prm.delta_up, vk, vk32, vbeta);
   }
   int bicgstab(double adt, const double* b, double* x);
   int idrs(double adt, const double* b, double* x);
@@ -332,7 +336,8 @@ void hdg_ctx::setup() {
   t1 = dalloc<double>(nT); t2 = dalloc<double>(nT); t3 = dalloc<double>(nT);
   for (double** v : {&kd.b, &kd.x, &kd.r, &kd.rh, &kd.s, &kd.t, &kd.p, &kd.v}) *v = dalloc<double>(nQ);
   const long nc32 = (nc + 31) / 32 * 32;
-  vk = dalloc<double>((long)ns * ns * nc32);
+  vk32 = prm.precision == HDG_MIXED;
+  vk = vk32 ? (void*)dalloc<float>((long)ns * ns * nc32) : (void*)dalloc<double>((long)ns * ns * nc32);
   vbeta = dalloc<double>(3L * nqf * nc32);
   br = dalloc<double>(nQ); bt = dalloc<double>(nQ);
   adv = dalloc<double>((long)nc * (2 * nqc + 3 * nqf));
@@ -579,8 +584,9 @@ void hdg_ctx::solve_trace(double c, const double* Fw, const double* Fpsi, const 
 }
 
 // BiCGStab on the mass-scaled Step I operator  x - (adt/det) f_im(x) = b,
-// all in FP64 (with FP32 operator arithmetic BiCGStab stalls or diverges on
-// this advection-dominated operator).  An iteration is four launches: v = A p
+// with FP64 arithmetic (FP32 operator arithmetic makes BiCGStab stall or
+// diverge on this advection-dominated operator; the mixed mode only stores
+// the cell matrices in FP32).  An iteration is four launches: v = A p
 // (with partials of rh.v), s = r - alpha v (alpha finished there), t = A s
 // (with partials of t.s, t.t, rh.s, rh.t), and the x, r, p updates (omega
 // and beta finished there, partials of r.r).  Coefficients stay in device memory, so the host only
@@ -614,7 +620,7 @@ int hdg_ctx::bicgstab(double adt, const double* b_aos, double* x_aos) {
       } else {  // true residual of the current iterate
         {
           Timed tm(prof, KC_APPLY_OP);
-          launch_apply_soa(k, st, 0, dm, dt, vk, beta, prm.alpha, adt, B.x, nullptr, B.t, nullptr);
+          launch_apply_soa(k, st, 0, dm, dt, vk, vk32, beta, prm.alpha, adt, B.x, nullptr, B.t, nullptr);
         }
         launch_copy(st, n, B.b, B.r);
         launch_axpby(st, n, -1.0, B.t, 1.0, B.r);
@@ -632,7 +638,7 @@ int hdg_ctx::bicgstab(double adt, const double* b_aos, double* x_aos) {
     double* sc = bsc + (long)BS_STRIDE * j;
     {
       Timed tm(prof, KC_APPLY_OP);
-      launch_apply_soa(k, st, 1, dm, dt, vk, beta, prm.alpha, adt, B.p, B.rh, B.v, part);
+      launch_apply_soa(k, st, 1, dm, dt, vk, vk32, beta, prm.alpha, adt, B.p, B.rh, B.v, part);
     }
     {
       Timed tm(prof, KC_VECTOR);
@@ -640,7 +646,7 @@ int hdg_ctx::bicgstab(double adt, const double* b_aos, double* x_aos) {
     }
     {
       Timed tm(prof, KC_APPLY_OP);
-      launch_apply_soa(k, st, 2, dm, dt, vk, beta, prm.alpha, adt, B.s, B.rh, B.t, kpart);
+      launch_apply_soa(k, st, 2, dm, dt, vk, vk32, beta, prm.alpha, adt, B.s, B.rh, B.t, kpart);
     }
     {
       Timed tm(prof, KC_VECTOR);
@@ -927,11 +933,7 @@ int hdg_create(int64_t nv, const double* coords, int64_t nc, const int32_t* cell
     g_create_error = "invalid parameter";
     return HDG_ERR_INVALID_ARG;
   }
-  if (prm->precision == HDG_MIXED) {
-    g_create_error = "mixed precision is not available in this build: FP32 arithmetic in the Step I operator "
-                     "destabilises BiCGStab on this advection-dominated system";
-    return HDG_ERR_UNSUPPORTED;
-  }
+
   auto ctx = std::make_unique<hdg_ctx>();
   ctx->prm = *prm;
   ctx->k = prm->degree;

@@ -78,13 +78,14 @@ void launch_apply(int k, hipStream_t st, int mode, DMesh m, DTab t, const double
 // Per-stage data of the Step I operator for advecting velocity Qs (AoS): the
 // per-cell volume matrices V (ns*ns entries) and the facet upwind weights
 // beta (3*nq_facet entries), both in tiles of 32 cells (entry j of cell e at
-// ((e/32)*nj + j)*32 + e%32; arrays hold ceil(nc/32)*32 cells)
-void launch_step1_matrix(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, double* V,
+// ((e/32)*nj + j)*32 + e%32; arrays hold ceil(nc/32)*32 cells).  V is FP32
+// when v32, else FP64; beta is FP64.
+void launch_step1_matrix(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, void* V, bool v32,
                          double* beta);
 // Step I operator on structure-of-arrays vectors (2 threads per cell):
 // out = x - (adt/det) f_im(x), with partial sums (apply_soa_blocks(nc) per set):
 // dot 0 none; dot 1 w.out; dot 2 out.x, out.out, w.x, w.out
-void launch_apply_soa(int k, hipStream_t st, int dot, DMesh m, DTab t, const double* V, const double* beta,
+void launch_apply_soa(int k, hipStream_t st, int dot, DMesh m, DTab t, const void* V, bool v32, const double* beta,
                       double alpha, double adt, const double* x, const double* w, double* out, double* part);
 int apply_soa_blocks(long nc);
 // BiCGStab pieces (slot sc of BS_STRIDE scalars):

@@ -667,10 +667,12 @@ __device__ __forceinline__ long tile_idx(long e, int j, int nj) { return ((e >> 
 // Per-cell volume matrix of the Step I form, for the Q* of a stage:
 //   V[s][s'] = -sum_q w_q phi_s(q) (Q*(q) . grad phi_s'(q)) det J
 // (the volume term -(Q*.grad x, w) of eq. (f_impl) acts on each velocity
-// component alike), entry s*NS + s' in tiles.  One thread per (cell, row s).
-template <int K>
+// component alike), entry s*NS + s' in tiles.  TV is the storage type: FP64,
+// or FP32 in the mixed-precision mode (the operator still computes in FP64).
+// One thread per (cell, row s).
+template <int K, typename TV>
 __global__ void __launch_bounds__(kBlock) k_step1_matrix(DMesh m, DTab t, const double* __restrict__ Qs,
-                                                         double* __restrict__ V) {
+                                                         TV* __restrict__ V) {
   using D = Dims<K>;
   constexpr int NS = D::NS, NU = D::NU, NQC = D::NQC;
   const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -698,7 +700,7 @@ __global__ void __launch_bounds__(kBlock) k_step1_matrix(DMesh m, DTab t, const 
     for (int i = 0; i < NS; ++i) row[i] += a0 * t.Gux[qq * NS + i] + a1 * t.Guy[qq * NS + i];
   }
 #pragma unroll
-  for (int i = 0; i < NS; ++i) V[tile_idx(e, s * NS + i, NS * NS)] = row[i];
+  for (int i = 0; i < NS; ++i) V[tile_idx(e, s * NS + i, NS * NS)] = (TV)row[i];
 }
 
 // Upwind weights of the Step I facet term at the facet points, for the Q*
@@ -739,9 +741,9 @@ __global__ void __launch_bounds__(kBlock) k_step1_beta(DMesh m, DTab t, const do
 // receives the result in reference scaling (the caller multiplies by
 // adt/det).  The neighbour's input value at structure-of-arrays index idx
 // is nb(idx); sFBu is the facet trace table staged in LDS.
-template <int K, typename NbVal>
+template <int K, typename TV, typename NbVal>
 __device__ __forceinline__ void step1_core(const DMesh& m, const DTab& t, const double* sFBu,
-                                           const double* __restrict__ V, const double* __restrict__ beta, long nc,
+                                           const TV* __restrict__ V, const double* __restrict__ beta, long nc,
                                            int e, int c, double alpha, const double (&xv)[Dims<K>::NS],
                                            double (&y)[Dims<K>::NS], const NbVal& nb) {
   using D = Dims<K>;
@@ -759,7 +761,7 @@ __device__ __forceinline__ void step1_core(const DMesh& m, const DTab& t, const 
       double am = 0.0, ao = 0.0;
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
-        const double v = V[tile_idx(e, s * NS + i, NS * NS)];
+        const double v = (double)V[tile_idx(e, s * NS + i, NS * NS)];
         am += v * xv[i];
         ao += v * xo[i];
       }
@@ -833,8 +835,8 @@ __device__ __forceinline__ void stage_fbu(const DTab& t, double* sFBu) {
 //   DOT 0: none;  DOT 1: w.out;  DOT 2: out.x, out.out, w.x, w.out.
 // In BiCGStab, DOT 1 gives rh.v for v = A p and DOT 2 gives t.s, t.t, rh.s,
 // rh.t for t = A s.
-template <int K, int DOT>
-__global__ void __launch_bounds__(kBlock, kStep1Waves) k_apply_soa(DMesh m, DTab t, const double* __restrict__ V,
+template <int K, int DOT, typename TV>
+__global__ void __launch_bounds__(kBlock, kStep1Waves) k_apply_soa(DMesh m, DTab t, const TV* __restrict__ V,
                                                                    const double* __restrict__ beta, double alpha,
                                                                    double adt, const double* __restrict__ x,
                                                                    const double* __restrict__ w,
@@ -852,7 +854,7 @@ __global__ void __launch_bounds__(kBlock, kStep1Waves) k_apply_soa(DMesh m, DTab
     double xv[NS], y[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) xv[s] = x[(long)(c * NS + s) * nc + e];
-    step1_core<K>(m, t, sFBu, V, beta, nc, e, c, alpha, xv, y, [&](long i) { return x[i]; });
+    step1_core<K, TV>(m, t, sFBu, V, beta, nc, e, c, alpha, xv, y, [&](long i) { return x[i]; });
     const double sc = adt / m.geo[D_DET * nc + e];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -1475,21 +1477,32 @@ void launch_apply(int k, hipStream_t st, int mode, DMesh m, DTab t, const double
     HDG_DISPATCH(k, (k_apply<KK, 2><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, adv, alpha, adt, x, r, p, lam, out)));
   }
 }
-void launch_step1_matrix(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, double* V,
+void launch_step1_matrix(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, void* V, bool v32,
                          double* beta) {
-  HDG_DISPATCH(k, (k_step1_matrix<KK><<<nblocks((long)m.nc * Dims<KK>::NS), kBlock, 0, st>>>(m, t, Qs, V)));
+  const int nb = nblocks((long)m.nc * (k + 2) * (k + 3) / 2);
+  if (v32) {
+    HDG_DISPATCH(k, (k_step1_matrix<KK, float><<<nb, kBlock, 0, st>>>(m, t, Qs, (float*)V)));
+  } else {
+    HDG_DISPATCH(k, (k_step1_matrix<KK, double><<<nb, kBlock, 0, st>>>(m, t, Qs, (double*)V)));
+  }
   HDG_DISPATCH(k, (k_step1_beta<KK><<<nblocks(3L * m.nc), kBlock, 0, st>>>(m, t, Qs, delta_up, beta)));
 }
-void launch_apply_soa(int k, hipStream_t st, int dot, DMesh m, DTab t, const double* V, const double* beta,
-                      double alpha, double adt, const double* x, const double* w, double* out, double* part) {
+template <typename TV>
+static void apply_soa_t(int k, hipStream_t st, int dot, DMesh m, DTab t, const TV* V, const double* beta,
+                        double alpha, double adt, const double* x, const double* w, double* out, double* part) {
   const int nb = nblocks(2L * m.nc);
   if (dot == 0) {
-    HDG_DISPATCH(k, (k_apply_soa<KK, 0><<<nb, kBlock, 0, st>>>(m, t, V, beta, alpha, adt, x, w, out, part)));
+    HDG_DISPATCH(k, (k_apply_soa<KK, 0, TV><<<nb, kBlock, 0, st>>>(m, t, V, beta, alpha, adt, x, w, out, part)));
   } else if (dot == 1) {
-    HDG_DISPATCH(k, (k_apply_soa<KK, 1><<<nb, kBlock, 0, st>>>(m, t, V, beta, alpha, adt, x, w, out, part)));
+    HDG_DISPATCH(k, (k_apply_soa<KK, 1, TV><<<nb, kBlock, 0, st>>>(m, t, V, beta, alpha, adt, x, w, out, part)));
   } else {
-    HDG_DISPATCH(k, (k_apply_soa<KK, 2><<<nb, kBlock, 0, st>>>(m, t, V, beta, alpha, adt, x, w, out, part)));
+    HDG_DISPATCH(k, (k_apply_soa<KK, 2, TV><<<nb, kBlock, 0, st>>>(m, t, V, beta, alpha, adt, x, w, out, part)));
   }
+}
+void launch_apply_soa(int k, hipStream_t st, int dot, DMesh m, DTab t, const void* V, bool v32, const double* beta,
+                      double alpha, double adt, const double* x, const double* w, double* out, double* part) {
+  if (v32) apply_soa_t(k, st, dot, m, t, (const float*)V, beta, alpha, adt, x, w, out, part);
+  else apply_soa_t(k, st, dot, m, t, (const double*)V, beta, alpha, adt, x, w, out, part);
 }
 int apply_soa_blocks(long nc) { return nblocks(2L * nc); }
 void launch_bicg_s(hipStream_t st, long n, long nc, const double* part, double* sc, const double* r, const double* v,

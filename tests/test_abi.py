@@ -54,14 +54,17 @@ def test_default_params_and_create_errors(lib_path):
     assert b"degree" in lib.hdg_last_error(None)
 
 
-def test_mixed_precision_is_rejected_on_the_host(lib_path):
+def test_precision_parameter_is_checked_on_the_host(lib_path):
     from paper_2410_09790_amd import hdg
     lib = hdg.load_library()
-    p = hdg.default_params(precision="mixed")
+    assert hdg.default_params(precision="mixed").precision == 1
+    p = hdg.default_params()
+    assert p.precision == 0
+    p.precision = 2
     h = ctypes.c_void_p()
     st = lib.hdg_create(3, None, 1, None, ctypes.byref(p), None, ctypes.byref(h))
-    assert st == 6 and not h.value
-    assert b"mixed" in lib.hdg_last_error(None)
+    assert st == 1 and not h.value
+    assert b"invalid parameter" in lib.hdg_last_error(None)
 
 
 def test_clockwise_mesh_is_rejected_on_the_host(lib_path):
