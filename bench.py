@@ -15,9 +15,10 @@ Metric: trace DOF-IMEX-stages per second = N_trace * (s-1) * steps / wall time,
 with the state resident on the device before the timed region starts.
 
 The line also carries "mixed": the same workload with the per-stage Step I
-cell matrices stored in FP32 (FP64 arithmetic, FP64 Richardson residual and
-trace solves), its throughput and the relative L2 difference of its final
-state from the FP64 run's.
+cell matrices stored in FP32 and the Step I solves stopped at 1e-6 (FP64
+arithmetic, trace solves and Richardson residual, the Richardson loop acting
+as iterative refinement), its throughput and the relative L2 difference of
+its final state from the FP64 run's.
 
 Output: one JSON line on stdout (everything else goes to stderr).
 """
@@ -48,6 +49,7 @@ MEASURED_TRAFFIC = {
     "apply_step1_operator": {"kernels_sha256": "cde038ae4be98acb", "bytes_per_launch": 499.7e6},
 }
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
+MIXED_RTOL_VELOCITY = 1e-6  # Step I tolerance of the mixed-precision run
 PROFILE_EVERY = 15           # event-time one launch in 15 of each kernel class (odd: launches alternate)
 
 
@@ -121,13 +123,16 @@ def cpu_baseline(max_seconds: float = 30.0):
 
 
 def mixed_run(hdg, hi, torch, w, X, C, args, ref_ctx):
-    """The same workload with the Step I cell matrices stored in FP32 (FP64
-    arithmetic, FP64 Richardson residual and trace solves): throughput and the
-    relative L2 difference of the final state from the FP64 run above (which
-    has taken the same warm-up and timed steps from the same initial state)."""
+    """The same workload in the mixed-precision mode: the Step I cell matrices
+    stored in FP32 and the Step I solves stopped at MIXED_RTOL_VELOCITY (an
+    operator that is only FP32-accurate gains nothing from a tighter solve);
+    FP64 arithmetic, Krylov recurrences, trace solves and Richardson residual,
+    so the Richardson loop refines each stage.  Reports the throughput and
+    the relative L2 difference of the final state from the FP64 run above
+    (same warm-up and timed steps from the same initial state)."""
     mctx = hdg.Context(X, C, degree=w["k"], imex=w["scheme"], n_richardson=w["n_richardson"],
                        trace_solver=w["trace_solver"], rtol_trace=w["rtol_trace"],
-                       rtol_velocity=w["rtol_velocity"], precision="mixed")
+                       rtol_velocity=MIXED_RTOL_VELOCITY, precision="mixed")
     par = hi.stream_function_params(w["seed"])
     xy = mctx.cell_points()
     mctx.set_velocity_from_points(hi.streamfunction_velocity(par, xy[..., 0], xy[..., 1]))
@@ -145,8 +150,9 @@ def mixed_run(hdg, hi, torch, w, X, C, args, ref_ctx):
     log(f"mixed: {args.steps} steps {el:.3f} s, {1e3 * el / args.steps:.1f} ms/step, rel. L2 diff vs FP64 {diffs}")
     mctx.close()
     return {"value": value, "ms_per_step": 1e3 * el / args.steps,
-            "precision": "FP32 storage of the per-stage Step I cell matrices; FP64 arithmetic, Krylov "
-                         "recurrences, Richardson residual and trace solves",
+            "precision": "FP32 storage of the per-stage Step I cell matrices, Step I rtol "
+                         f"{MIXED_RTOL_VELOCITY:g}; FP64 arithmetic, Krylov recurrences, trace solves and "
+                         "Richardson residual",
             "rel_l2_diff_vs_fp64": diffs, "speedup_vs_fp64": None}
 
 

@@ -159,7 +159,8 @@ def test_initial_state(n, k):
     assert rel_l2_trace(d, host(lg), lam) < 1e-10
 
 
-def _run_both(n, k, nsteps, dt, tab, scheme, nR, pert=0.0, solver="mg_pcg", seed=0, precision="fp64"):
+def _run_both(n, k, nsteps, dt, tab, scheme, nR, pert=0.0, solver="mg_pcg", seed=0, precision="fp64",
+              rtol_velocity=1e-13):
     X, C = mesh(n, pert)
     d = Discretisation(X, C, k)
     par = hi.stream_function_params(seed)
@@ -167,7 +168,7 @@ def _run_both(n, k, nsteps, dt, tab, scheme, nR, pert=0.0, solver="mg_pcg", seed
     Q, p, lam = st.initial_state(lambda x, y: hi.streamfunction_velocity(par, x, y))
     Q, p, lam = st.run(Q, p, lam, 0.0, nsteps)
     ctx = context(X, C, degree=k, imex=scheme, n_richardson=nR, trace_solver=solver, rtol_trace=1e-13,
-                  rtol_velocity=1e-13, precision=precision)
+                  rtol_velocity=rtol_velocity, precision=precision)
     _initial(ctx, par)
     ctx.advance(dt, nsteps)
     Qg, pg, lg = ctx.get_state()
@@ -206,11 +207,13 @@ def test_degree3_mg_parity():
 
 
 
-# Mixed precision (FP32 storage of the per-stage Step I cell matrices, FP64
-# arithmetic, FP64 Richardson residual): within 1e-6 of the FP64 oracle.
+# Mixed precision as the benchmark runs it (FP32 storage of the per-stage
+# Step I cell matrices, Step I solves stopped at 1e-6, FP64 arithmetic and
+# FP64 Richardson residual): within 1e-6 of the FP64 oracle.
 def test_mixed_config1_parity():
     torch_or_skip()
-    d, ref, got, _ = _run_both(16, 1, 10, 1e-3, ars222(), "ars222", 3, solver="jacobi_pcg", precision="mixed")
+    d, ref, got, _ = _run_both(16, 1, 10, 1e-3, ars222(), "ars222", 3, solver="jacobi_pcg", precision="mixed",
+                               rtol_velocity=1e-6)
     assert rel_l2_cells(d, got[0], ref[0], d.nu) < 1e-6
     assert rel_l2_cells(d, got[1], ref[1], d.npp) < 1e-6
     assert rel_l2_trace(d, got[2], ref[2]) < 1e-6
@@ -218,7 +221,8 @@ def test_mixed_config1_parity():
 
 def test_mixed_degree3_parity():
     torch_or_skip()
-    d, ref, got, _ = _run_both(8, 3, 3, 1e-3, ars222(), "ars222", 3, pert=0.1, precision="mixed")
+    d, ref, got, _ = _run_both(8, 3, 3, 1e-3, ars222(), "ars222", 3, pert=0.1, precision="mixed",
+                               rtol_velocity=1e-6)
     assert rel_l2_cells(d, got[0], ref[0], d.nu) < 1e-6
     assert rel_l2_cells(d, got[1], ref[1], d.npp) < 1e-6
     assert rel_l2_trace(d, got[2], ref[2]) < 1e-6
