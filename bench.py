@@ -15,7 +15,7 @@ Metric: trace DOF-IMEX-stages per second = N_trace * (s-1) * steps / wall time,
 with the state resident on the device before the timed region starts.
 
 The line also carries "mixed": the same workload with the per-stage Step I
-cell matrices stored in FP32 and the Step I solves stopped at 1e-6 (FP64
+cell matrices stored in FP32 and the Step I solves stopped at 1e-5 (FP64
 arithmetic, trace solves and Richardson residual, the Richardson loop acting
 as iterative refinement), its throughput and the relative L2 difference of
 its final state from the FP64 run's.
@@ -49,7 +49,7 @@ MEASURED_TRAFFIC = {
     "apply_step1_operator": {"kernels_sha256": "cde038ae4be98acb", "bytes_per_launch": 499.7e6},
 }
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
-MIXED_RTOL_VELOCITY = 1e-6  # Step I tolerance of the mixed-precision run
+MIXED_RTOL_VELOCITY = 1e-5  # Step I tolerance of the mixed-precision run
 PROFILE_EVERY = 15           # event-time one launch in 15 of each kernel class (odd: launches alternate)
 
 

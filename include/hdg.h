@@ -72,9 +72,9 @@ typedef enum { HDG_PRESSURE_RECONSTRUCT = 0, HDG_PRESSURE_FIRST_ORDER = 1 } hdg_
  * FP64 form f_im) and the trace solves stay FP64.  Step I then solves a
  * system within ~1e-7 (relative) of the FP64 one, and the Richardson
  * iteration of Algorithm 2 refines the stage with the FP64 residual, so a
- * looser Step I tolerance (rtol_velocity = 1e-6, say) is the natural
- * companion of this mode; on the 256 x 256, k = 3 workload such steps stay
- * within 1e-10 of the FP64 steps at rtol_velocity = 1e-10.  FP32 operator
+ * looser Step I tolerance is the natural companion of this mode; on the
+ * 256 x 256, k = 3 workload four steps at rtol_velocity = 1e-5 stay within
+ * 2e-9 of the FP64 steps at rtol_velocity = 1e-10.  FP32 operator
  * arithmetic is not offered: it makes BiCGStab stall or diverge on this
  * operator. */
 typedef enum { HDG_FP64 = 0, HDG_MIXED = 1 } hdg_precision;

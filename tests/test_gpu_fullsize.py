@@ -164,7 +164,7 @@ def test_full_steps_properties(setup):
 
 def test_full_mixed_vs_fp64_step():
     """Mixed precision as the benchmark runs it (FP32 storage of the Step I
-    cell matrices, Step I solves stopped at 1e-6) against the FP64 path on one
+    cell matrices, Step I solves stopped at 1e-5) against the FP64 path on one
     benchmark step: within 1e-6 (the FP64 path itself is held to the oracle by
     the tests above and the small-mesh parity tests)."""
     torch = torch_or_skip()
@@ -173,7 +173,7 @@ def test_full_mixed_vs_fp64_step():
     out = {}
     for prec in ("fp64", "mixed"):
         ctx = context(X, C, degree=K, imex="ars222", n_richardson=3, trace_solver="mg_pcg", rtol_trace=1e-12,
-                      rtol_velocity=1e-10 if prec == "fp64" else 1e-6, precision=prec)
+                      rtol_velocity=1e-10 if prec == "fp64" else 1e-5, precision=prec)
         xy = ctx.cell_points()
         ctx.set_velocity_from_points(hi.streamfunction_velocity(par, xy[..., 0], xy[..., 1]))
         ctx.advance(DT, 1)

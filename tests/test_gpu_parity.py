@@ -208,12 +208,12 @@ def test_degree3_mg_parity():
 
 
 # Mixed precision as the benchmark runs it (FP32 storage of the per-stage
-# Step I cell matrices, Step I solves stopped at 1e-6, FP64 arithmetic and
+# Step I cell matrices, Step I solves stopped at 1e-5, FP64 arithmetic and
 # FP64 Richardson residual): within 1e-6 of the FP64 oracle.
 def test_mixed_config1_parity():
     torch_or_skip()
     d, ref, got, _ = _run_both(16, 1, 10, 1e-3, ars222(), "ars222", 3, solver="jacobi_pcg", precision="mixed",
-                               rtol_velocity=1e-6)
+                               rtol_velocity=1e-5)
     assert rel_l2_cells(d, got[0], ref[0], d.nu) < 1e-6
     assert rel_l2_cells(d, got[1], ref[1], d.npp) < 1e-6
     assert rel_l2_trace(d, got[2], ref[2]) < 1e-6
@@ -222,7 +222,27 @@ def test_mixed_config1_parity():
 def test_mixed_degree3_parity():
     torch_or_skip()
     d, ref, got, _ = _run_both(8, 3, 3, 1e-3, ars222(), "ars222", 3, pert=0.1, precision="mixed",
-                               rtol_velocity=1e-6)
+                               rtol_velocity=1e-5)
     assert rel_l2_cells(d, got[0], ref[0], d.nu) < 1e-6
     assert rel_l2_cells(d, got[1], ref[1], d.npp) < 1e-6
     assert rel_l2_trace(d, got[2], ref[2]) < 1e-6
+
+
+def test_mixed_vs_fp64_twenty_steps():
+    """Error growth over the benchmark's horizon: 20 steps on the 64 x 64 mesh,
+    k = 3, mixed (Step I at 1e-5 on the FP32-stored operator) against FP64
+    (Step I at 1e-10), both on the GPU; the FP64 path is held to the oracle
+    by the tests above."""
+    torch = torch_or_skip()
+    X, C = mesh(64)
+    par = hi.stream_function_params(0)
+    out = {}
+    for prec, rtv in (("fp64", 1e-10), ("mixed", 1e-5)):
+        ctx = context(X, C, degree=3, imex="ars222", n_richardson=3, trace_solver="mg_pcg", rtol_trace=1e-12,
+                      rtol_velocity=rtv, precision=prec)
+        _initial(ctx, par)
+        ctx.advance(1e-3, 20)
+        out[prec] = [host(t) for t in ctx.get_state()]
+        ctx.close()
+    for a, b in zip(out["mixed"], out["fp64"]):
+        assert np.linalg.norm(a - b) <= 1e-6 * np.linalg.norm(b)
