@@ -20,6 +20,9 @@ arithmetic, trace solves and Richardson residual, the Richardson loop acting
 as iterative refinement), its throughput and the relative L2 difference of
 its final state from the FP64 run's.
 
+"latency" gives p50/p99 per-call latencies of hdg_advance (one step) and
+hdg_solve_trace on the small 16 x 16, k = 1 workload.
+
 Output: one JSON line on stdout (everything else goes to stderr).
 """
 from __future__ import annotations
@@ -156,6 +159,46 @@ def mixed_run(hdg, hi, torch, w, X, C, args, ref_ctx):
             "rel_l2_diff_vs_fp64": diffs, "speedup_vs_fp64": None}
 
 
+def latency_run(hdg, hi, torch, ncalls: int = 100):
+    """Per-call latency distributions on the small parity workload (16 x 16
+    mesh, k = 1, ARS(2,2,2), dt = 1e-3, n_R = 3, facet-block-Jacobi PCG at
+    1e-12, Step I at 1e-10, FP64): hdg_advance of one step, and
+    hdg_solve_trace with c = gamma dt on seeded data, each call synchronous,
+    after 5 warm-up calls."""
+    import numpy as np
+    X, C = hi.unit_square_mesh(16)
+    ctx = hdg.Context(X, C, degree=1, imex="ars222", n_richardson=3, trace_solver="jacobi_pcg", rtol_trace=1e-12,
+                      rtol_velocity=1e-10)
+    par = hi.stream_function_params(0)
+    xy = ctx.cell_points()
+    ctx.set_velocity_from_points(hi.streamfunction_velocity(par, xy[..., 0], xy[..., 1]))
+
+    def dist(fn):
+        for _ in range(5):
+            fn()
+        ts = []
+        for _ in range(ncalls):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(1e3 * (time.perf_counter() - t0))
+        ts = np.array(ts)
+        return {"p50": round(float(np.percentile(ts, 50)), 3), "p99": round(float(np.percentile(ts, 99)), 3),
+                "mean": round(float(ts.mean()), 3), "calls": ncalls}
+
+    adv = dist(lambda: ctx.advance(1e-3, 1))
+    rng = np.random.default_rng(7)
+    Fpsi = torch.as_tensor(rng.standard_normal(ctx.nP)).cuda()
+    Fmu = torch.as_tensor(rng.standard_normal(ctx.nT)).cuda()
+    c = (1.0 - 2.0 ** -0.5) * 1e-3
+    tr = dist(lambda: ctx.solve_trace(c, None, Fpsi, Fmu))
+    ctx.close()
+    log(f"latency (16x16, k=1): advance one step p50 {adv['p50']} ms p99 {adv['p99']} ms; "
+        f"solve_trace p50 {tr['p50']} ms p99 {tr['p99']} ms")
+    return {"workload": "unit_square_16x16_k1_ars222 (512 cells, 1600 trace DOFs), FP64, facet-block-Jacobi PCG",
+            "advance_one_step_ms": adv, "solve_trace_ms": tr}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +209,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with events")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision run")
+    ap.add_argument("--no-latency", action="store_true", help="skip the per-call latency distributions")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -259,6 +303,9 @@ def main():
     mixed = None
     if not args.no_mixed:
         mixed = mixed_run(hdg, hi, torch, w, X, C, args, ctx)
+    latency = None
+    if not args.no_latency:
+        latency = latency_run(hdg, hi, torch)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -284,6 +331,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "mixed": mixed,
+        "latency": latency,
     }
     if mixed is not None:
         mixed["speedup_vs_fp64"] = round(mixed["value"] / value, 3)

@@ -144,7 +144,8 @@ int hdg_advance(hdg_ctx* ctx, double dt, int nsteps);
  *   (U, w) - c g(w, p, lam) = Fw(w),  Gamma(psi, mu, U, p, lam) = Fpsi(psi) + Fmu(mu)
  * for all (w, psi, mu); g and Gamma as in Section "Hybridisation".  The data
  * must satisfy Fpsi(1) = Fmu(1) (the component violating it is removed);
- * (p, lam) is normalised to int p = 0.  c > 0. */
+ * (p, lam) is normalised to int p = 0.  c > 0.  A null Fw, Fpsi or Fmu
+ * stands for zero data. */
 int hdg_solve_trace(hdg_ctx* ctx, double c, const double* Fw, const double* Fpsi,
                     const double* Fmu, double* U, double* p, double* lam);
 
