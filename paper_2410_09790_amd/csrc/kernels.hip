@@ -820,6 +820,17 @@ __device__ __forceinline__ void step1_core(const DMesh& m, const DTab& t, const 
 #endif
 constexpr int kStep1Waves = HDG_STEP1_WAVES;
 
+// Workgroups are dealt to the eight XCDs in turn (workgroup i to XCD i % 8),
+// and each XCD has its own L2.  The Step I operator reads the input vector
+// at neighbour cells, which sit a few workgroups away; renumbering so that
+// each XCD takes one contiguous eighth of the cells keeps those reads in the
+// same L2.  A bijection of [0, gridDim.x) onto itself.
+__device__ __forceinline__ int xcd_block() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int q = nb >> 3, r = nb & 7, x = b & 7, j = b >> 3;
+  return x < r ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
+}
+
 // Stage the facet trace table in LDS: the neighbour's table row is indexed
 // by the neighbour's local facet and orientation, which differ between lanes.
 template <int K>
@@ -846,7 +857,8 @@ __global__ void __launch_bounds__(kBlock, kStep1Waves) k_apply_soa(DMesh m, DTab
   constexpr int NS = D::NS;
   __shared__ double sFBu[3 * D::NQF * NS];
   stage_fbu<K>(t, sFBu);
-  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int blk = xcd_block();
+  const long tid = (long)blk * blockDim.x + threadIdx.x;
   const long nc = m.nc;
   const int e = (int)(tid >> 1), c = (int)(tid & 1);
   double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
@@ -873,7 +885,7 @@ __global__ void __launch_bounds__(kBlock, kStep1Waves) k_apply_soa(DMesh m, DTab
   }
   if (DOT >= 1) {
     d0 = block_sum(d0);
-    if (threadIdx.x == 0) part[blockIdx.x] = d0;
+    if (threadIdx.x == 0) part[blk] = d0;
   }
   if (DOT == 2) {
     const int nb = gridDim.x;
@@ -881,9 +893,9 @@ __global__ void __launch_bounds__(kBlock, kStep1Waves) k_apply_soa(DMesh m, DTab
     d2 = block_sum(d2);
     d3 = block_sum(d3);
     if (threadIdx.x == 0) {
-      part[nb + blockIdx.x] = d1;
-      part[2 * nb + blockIdx.x] = d2;
-      part[3 * nb + blockIdx.x] = d3;
+      part[nb + blk] = d1;
+      part[2 * nb + blk] = d2;
+      part[3 * nb + blk] = d3;
     }
   }
 }
