@@ -516,6 +516,8 @@ void hdg_ctx::precond(TraceOp& op, const double* r, double* z) {
 
 // preconditioned CG on S x = g (g orthogonal to the constant trace), x0 = 0
 int hdg_ctx::pcg(TraceOp& op, const double* gin, double* x) {
+  constexpr int kCheck = 4;
+  static_assert(kCheck <= kPinned, "pinned buffer holds kCheck residuals");
   const long n = nT;
   const int nF = (int)hm.nF;
   const int maxit = prm.max_it_trace;
@@ -542,9 +544,19 @@ int hdg_ctx::pcg(TraceOp& op, const double* gin, double* x) {
     launch_pcg_update(st, n, rz + it, pqv + it, pp, pq, x, pr, part);
     launch_finish(st, part, kRedBlocks, rr + it);
     KCHK();
-    const double res = std::sqrt(read_scalar(rr + it));
-    if (!(res == res)) throw SolverBreakdown("PCG breakdown (NaN residual)");
-    if (res <= prm.rtol_trace * gnorm) return it + 1;
+    // the residual norms stay on the device; the host reads the last kCheck
+    // of them at once (a converged solve runs at most kCheck - 1 extra
+    // iterations, which only improve x)
+    if ((it + 1) % kCheck == 0 || it + 1 == maxit) {
+      const int c0 = it + 1 - ((it + 1) % kCheck == 0 ? kCheck : (it + 1) % kCheck);
+      HIPCHK(hipMemcpyAsync(h_pinned, rr + c0, (size_t)(it + 1 - c0) * sizeof(double), hipMemcpyDeviceToHost, st));
+      sync();
+      for (int i = 0; i <= it - c0; ++i) {
+        const double res = std::sqrt(h_pinned[i]);
+        if (!(res == res)) throw SolverBreakdown("PCG breakdown (NaN residual)");
+        if (res <= prm.rtol_trace * gnorm) return it + 1;
+      }
+    }
     precond(op, pr, pz);
     launch_dot(st, n, pr, pz, part);
     launch_finish(st, part, kRedBlocks, rz + it + 1);

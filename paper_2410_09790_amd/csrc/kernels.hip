@@ -1327,7 +1327,8 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(long n, const double* __r
                                                        const double* __restrict__ p, const double* __restrict__ q,
                                                        double* __restrict__ x, double* __restrict__ r,
                                                        double* __restrict__ part) {
-  const double alpha = rz[0] / pq[0];
+  // a vanished p.q (converged to an exact zero residual) leaves x and r as they are
+  const double alpha = pq[0] != 0.0 ? rz[0] / pq[0] : 0.0;
   double v = 0.0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     x[i] += alpha * p[i];
@@ -1342,7 +1343,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(long n, const double* __r
 __global__ void k_pcg_direction(long n, const double* __restrict__ rzn, const double* __restrict__ rzo,
                                 const double* __restrict__ z, double* __restrict__ p) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = z[i] + (rzn[0] / rzo[0]) * p[i];
+  if (i < n) p[i] = z[i] + (rzo[0] != 0.0 ? rzn[0] / rzo[0] : 0.0) * p[i];
 }
 
 // ----------------------------------------------------------------- IDR(s)
