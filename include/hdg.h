@@ -62,7 +62,18 @@ typedef enum {
   HDG_ERR_UNSUPPORTED = 6    /* feature outside this build (3D, degree > 4, ...) */
 } hdg_status;
 
-typedef enum { HDG_IMEX_EULER = 0, HDG_ARS222 = 1, HDG_ARS233 = 2 } hdg_imex_scheme;
+/* IMEX schemes (Appendix A): IMEX Euler as printed; ARS(2,2,2) and ARS(2,3,3)
+ * of Ascher, Ruuth and Spiteri (cited, not printed); SSP2(3,3,2) and
+ * SSP3(4,3,3) as printed, whose implicit first stage is placed after an
+ * explicit stage 0 (Q_0 = Q^n) to fit the paper's form a^im_{i,0} = 0:
+ * s = 4 and 5, i.e. 3 and 4 implicit stages per step. */
+typedef enum {
+  HDG_IMEX_EULER = 0,
+  HDG_ARS222 = 1,
+  HDG_ARS233 = 2,
+  HDG_SSP2_332 = 3,
+  HDG_SSP3_433 = 4
+} hdg_imex_scheme;
 typedef enum { HDG_TRACE_JACOBI_PCG = 0, HDG_TRACE_MG_PCG = 1 } hdg_trace_solver;
 typedef enum { HDG_PRESSURE_RECONSTRUCT = 0, HDG_PRESSURE_FIRST_ORDER = 1 } hdg_pressure_update;
 /* HDG_MIXED: the per-stage cell matrices of the Step I operator (the

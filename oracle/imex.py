@@ -1,10 +1,12 @@
 """IMEX-HDG time stepping (oracle side; test infrastructure).
 
 * Butcher tableaux in the paper's form (Appendix A): s stages, implicit
-  tableau with a zero first column (a^im_{i,0} = b^im_0 = 0).  IMEX Euler is
-  printed in the paper.  ARS(2,2,2) and ARS(2,3,3) are the Ascher-Ruuth-
-  Spiteri schemes the paper cites; their coefficients are not printed there and
-  are pinned by the IMEX order conditions in the tests.
+  tableau with a zero first column (a^im_{i,0} = b^im_0 = 0).  IMEX Euler,
+  SSP2(3,3,2) and SSP3(4,3,3) are printed in the paper (the SSP ones with an
+  implicit first stage, placed after an explicit stage 0).  ARS(2,2,2) and
+  ARS(2,3,3) are the Ascher-Ruuth-Spiteri schemes the paper cites; their
+  coefficients are not printed there.  All are pinned by the order conditions
+  in the tests.
 * ``stage_residual`` / ``final_residual``: eqs. (imex_residual) and
   (final_residual), the recursion that replaces f_im(Q_j) by
   (M Q_j - r_j) / a_jj.
@@ -70,7 +72,37 @@ def ars233() -> Tableau:
                    np.array([0.0, 0.5, 0.5]))
 
 
-TABLEAUX = {"imex_euler": imex_euler, "ars222": ars222, "ars233": ars233}
+def _pad_explicit_stage0(name, Ae, be, Ai, bi) -> Tableau:
+    """The paper's SSP tableaux (Appendix A) start with an implicit stage,
+    against its form a^im_{i,0} = b^im_0 = 0.  Reading: an explicit stage 0
+    (Q_0 = Q^n) goes in front and the printed tableau becomes rows and
+    columns 1..s-1, so every printed implicit stage is solved."""
+    m = Ae.shape[0]
+    pad = lambda A: np.pad(A, ((1, 0), (1, 0)))
+    return Tableau(name, pad(Ae), np.concatenate([[0.0], be]), pad(Ai), np.concatenate([[0.0], bi]))
+
+
+def ssp2_332() -> Tableau:
+    """SSP2(3,3,2) as printed (Appendix A); the printed abscissae (0, 1, 1/2)
+    are not the row sums of the printed explicit tableau, which are used."""
+    h, t = 0.5, 1.0 / 3.0
+    Ae = np.array([[0.0, 0.0, 0.0], [h, 0.0, 0.0], [h, h, 0.0]])
+    Ai = np.array([[0.25, 0.0, 0.0], [0.0, 0.25, 0.0], [t, t, t]])
+    return _pad_explicit_stage0("ssp2_332", Ae, np.array([t, t, t]), Ai, np.array([t, t, t]))
+
+
+def ssp3_433() -> Tableau:
+    """SSP3(4,3,3) as printed (Appendix A)."""
+    a, b, e = 0.24169426078821, 0.06042356519705, 0.12915286960590
+    d = 0.5 - a - b - e
+    Ae = np.array([[0.0, 0.0, 0.0, 0.0], [0.0, 0.0, 0.0, 0.0], [0.0, 1.0, 0.0, 0.0], [0.0, 0.25, 0.25, 0.0]])
+    Ai = np.array([[a, 0.0, 0.0, 0.0], [-a, a, 0.0, 0.0], [0.0, 1.0 - a, a, 0.0], [b, e, d, a]])
+    w = np.array([0.0, 1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0])
+    return _pad_explicit_stage0("ssp3_433", Ae, w, Ai, w)
+
+
+TABLEAUX = {"imex_euler": imex_euler, "ars222": ars222, "ars233": ars233, "ssp2_332": ssp2_332,
+            "ssp3_433": ssp3_433}
 
 
 def stage_residual(tab: Tableau, i: int, MQn, MQ, r, fex, dt):

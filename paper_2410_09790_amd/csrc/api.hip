@@ -47,9 +47,10 @@ struct SolverBreakdown : std::runtime_error {
   } while (0)
 #define KCHK() HIPCHK(hipGetLastError())
 
+constexpr int kMaxStages = 5;
 struct Tableau {
   int s;
-  double Aex[3][3], bex[3], Aim[3][3], bim[3];
+  double Aex[kMaxStages][kMaxStages], bex[kMaxStages], Aim[kMaxStages][kMaxStages], bim[kMaxStages];
 };
 
 static Tableau make_tableau(int which) {
@@ -72,6 +73,37 @@ static Tableau make_tableau(int which) {
     t.bex[1] = 0.5; t.bex[2] = 0.5;
     t.Aim[1][1] = g; t.Aim[2][1] = 1.0 - 2.0 * g; t.Aim[2][2] = g;
     t.bim[1] = 0.5; t.bim[2] = 0.5;
+  } else if (which == HDG_SSP2_332 || which == HDG_SSP3_433) {
+    // The paper's SSP tableaux (Appendix A) have an implicit first stage; in
+    // the paper's form (a^im_{i,0} = 0) they take an explicit stage 0 with
+    // Q_0 = Q^n in front, so every printed implicit stage is solved and the
+    // printed tableau becomes rows 1..s-1 / columns 1..s-1.  SSP2's printed
+    // abscissae are replaced by the row sums (0, 1/2, 1).
+    const bool ssp2 = which == HDG_SSP2_332;
+    const int m = ssp2 ? 3 : 4;  // printed stages
+    double Ae[4][4] = {}, be[4] = {}, Ai[4][4] = {}, bi[4] = {};
+    if (ssp2) {
+      Ae[1][0] = 0.5; Ae[2][0] = 0.5; Ae[2][1] = 0.5;
+      be[0] = be[1] = be[2] = 1.0 / 3.0;
+      Ai[0][0] = 0.25; Ai[1][1] = 0.25; Ai[2][0] = Ai[2][1] = Ai[2][2] = 1.0 / 3.0;
+      bi[0] = bi[1] = bi[2] = 1.0 / 3.0;
+    } else {
+      const double al = 0.24169426078821, be_ = 0.06042356519705, et = 0.12915286960590;
+      Ae[2][1] = 1.0; Ae[3][1] = 0.25; Ae[3][2] = 0.25;
+      be[1] = be[2] = 1.0 / 6.0; be[3] = 2.0 / 3.0;
+      Ai[0][0] = al; Ai[1][0] = -al; Ai[1][1] = al; Ai[2][1] = 1.0 - al; Ai[2][2] = al;
+      Ai[3][0] = be_; Ai[3][1] = et; Ai[3][2] = 0.5 - al - be_ - et; Ai[3][3] = al;
+      bi[1] = bi[2] = 1.0 / 6.0; bi[3] = 2.0 / 3.0;
+    }
+    t.s = m + 1;
+    for (int i = 0; i < m; ++i) {
+      t.bex[i + 1] = be[i];
+      t.bim[i + 1] = bi[i];
+      for (int j = 0; j < m; ++j) {
+        t.Aex[i + 1][j + 1] = Ae[i][j];
+        t.Aim[i + 1][j + 1] = Ai[i][j];
+      }
+    }
   } else {
     throw ArgError("unknown IMEX scheme");
   }
@@ -191,11 +223,11 @@ struct hdg_ctx {
   double *adv = nullptr, *Qs = nullptr, *dr = nullptr, *Qbar = nullptr, *dQ = nullptr, *dp = nullptr, *dl = nullptr,
          *fpsi = nullptr, *Ut = nullptr;
   double *Q = nullptr, *p = nullptr, *lam = nullptr;
-  double* stQ[3] = {nullptr, nullptr, nullptr};
-  double* stP[3] = {nullptr, nullptr, nullptr};
-  double* stL[3] = {nullptr, nullptr, nullptr};
-  double* stR[3] = {nullptr, nullptr, nullptr};
-  double* stMQ[3] = {nullptr, nullptr, nullptr};
+  double* stQ[hdg::kMaxStages] = {};
+  double* stP[hdg::kMaxStages] = {};
+  double* stL[hdg::kMaxStages] = {};
+  double* stR[hdg::kMaxStages] = {};
+  double* stMQ[hdg::kMaxStages] = {};
   static constexpr int kPinned = 512;
   double* h_pinned = nullptr;
   bool have_state = false;
@@ -344,7 +376,7 @@ void hdg_ctx::setup() {
   Qs = dalloc<double>(nQ); dr = dalloc<double>(nQ); Qbar = dalloc<double>(nQ); dQ = dalloc<double>(nQ);
   dp = dalloc<double>(nP); dl = dalloc<double>(nT); fpsi = dalloc<double>(nP); Ut = dalloc<double>(nQ);
   Q = dalloc<double>(nQ); p = dalloc<double>(nP); lam = dalloc<double>(nT);
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < make_tableau(prm.imex).s; ++i) {
     stQ[i] = dalloc<double>(nQ); stP[i] = dalloc<double>(nP); stL[i] = dalloc<double>(nT);
     stR[i] = dalloc<double>(nQ); stMQ[i] = dalloc<double>(nQ);
   }
@@ -939,7 +971,7 @@ int hdg_create(int64_t nv, const double* coords, int64_t nc, const int32_t* cell
   }
   if (prm->tau <= 0 || prm->alpha < 0 || prm->delta_up < 0 || prm->n_richardson < 1 || prm->max_it_trace < 1 ||
       prm->max_it_velocity < 1 || !(prm->rtol_trace > 0) || !(prm->rtol_velocity > 0) || prm->imex < 0 ||
-      prm->imex > 2 || prm->trace_solver < 0 || prm->trace_solver > 1 || prm->pressure_update < 0 ||
+      prm->imex > 4 || prm->trace_solver < 0 || prm->trace_solver > 1 || prm->pressure_update < 0 ||
       prm->pressure_update > 1 || prm->idr_s < 0 || prm->idr_s > kIdrMax ||
       prm->precision < 0 || prm->precision > 1) {
     g_create_error = "invalid parameter";

@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhdg.so")
 
-IMEX = {"imex_euler": 0, "ars222": 1, "ars233": 2}
+IMEX = {"imex_euler": 0, "ars222": 1, "ars233": 2, "ssp2_332": 3, "ssp3_433": 4}
 TRACE_SOLVER = {"jacobi_pcg": 0, "mg_pcg": 1}
 PRESSURE = {"reconstruct": 0, "first_order": 1}
 PRECISION = {"fp64": 0, "mixed": 1}

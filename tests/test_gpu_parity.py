@@ -9,7 +9,7 @@ import pytest
 import hdg_inputs as hi
 from oracle.forms import Discretisation
 from oracle.hdg import HDGSolver, monolithic_matrix
-from oracle.imex import IMEXHDG, ars222, ars233, imex_euler
+from oracle.imex import IMEXHDG, ars222, ars233, imex_euler, ssp2_332, ssp3_433
 
 from gpu_util import compatible_rhs, context, dev, host, mesh, rel_l2_cells, rel_l2_trace, torch_or_skip
 
@@ -175,8 +175,10 @@ def _run_both(n, k, nsteps, dt, tab, scheme, nR, pert=0.0, solver="mg_pcg", seed
     return d, (Q, p, lam), tuple(host(t) for t in (Qg, pg, lg)), ctx
 
 
-@pytest.mark.parametrize("scheme,tab", [("imex_euler", imex_euler), ("ars222", ars222), ("ars233", ars233)])
+@pytest.mark.parametrize("scheme,tab", [("imex_euler", imex_euler), ("ars222", ars222), ("ars233", ars233),
+                                        ("ssp2_332", ssp2_332), ("ssp3_433", ssp3_433)])
 def test_step_small(scheme, tab):
+    """Two steps with n_R = 2 (the paper's setting) on a perturbed 4x4 mesh, k = 2."""
     torch_or_skip()
     d, ref, got, _ = _run_both(4, 2, 2, 5e-3, tab(), scheme, 2, pert=0.15)
     assert rel_l2_cells(d, got[0], ref[0], d.nu) < 1e-10

@@ -47,7 +47,30 @@ def test_p9_order_conditions(name, order):
             assert abs(b @ A @ c - 1 / 6) < 1e-15
 
 
-@pytest.mark.parametrize("name,order", [("imex_euler", 1), ("ars222", 2), ("ars233", 3)])
+@pytest.mark.parametrize("name,order", [("ssp2_332", 2), ("ssp3_433", 3)])
+def test_p9_ssp_order_conditions(name, order):
+    """The paper's SSP tableaux in its form (explicit stage 0 in front): the
+    classical conditions of each tableau and the coupling conditions up to the
+    scheme's order, with the different explicit and implicit abscissae.  The
+    printed coefficients carry 14 digits, hence the tolerance."""
+    tab = TABLEAUX[name]()
+    Ae, be, ce, Ai, bi, ci = _conds(tab)
+    assert np.allclose(np.triu(Ae), 0) and np.allclose(Ai[:, 0], 0) and bi[0] == 0
+    assert np.allclose(Ai[0], 0) and np.all(np.diag(Ai)[1:] > 0)
+    tol = 1e-13
+    assert abs(be.sum() - 1) < tol and abs(bi.sum() - 1) < tol
+    for b, c in itertools.product((be, bi), (ce, ci)):
+        assert abs(b @ c - 0.5) < tol
+    third = [abs(b @ c**2 - 1 / 3) for b, c in itertools.product((be, bi), (ce, ci))]
+    third += [abs(b @ A @ c - 1 / 6) for b, A, c in itertools.product((be, bi), (Ae, Ai), (ce, ci))]
+    if order >= 3:
+        assert max(third) < tol
+    else:
+        assert max(third) > 1e-3  # SSP2(3,3,2) is exactly second order
+
+
+@pytest.mark.parametrize("name,order", [("imex_euler", 1), ("ars222", 2), ("ars233", 3), ("ssp2_332", 2),
+                                        ("ssp3_433", 3)])
 def test_p9_scalar_ode_order(name, order):
     """y' = lam y + g(t), lam implicit, g explicit; exact y = 1 + sin t."""
     tab = TABLEAUX[name]()
