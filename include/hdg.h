@@ -139,9 +139,31 @@ int hdg_sizes(const hdg_ctx* ctx, int64_t* out, int n);
  * passes the values to hdg_set_velocity_from_points. */
 int hdg_cell_points(const hdg_ctx* ctx, double* xy);
 
+/* Physical coordinates of the facet quadrature points seen from each cell,
+ * HOST buffer [ncells][3][nq_facet][2] (local facet f of a cell joins its
+ * vertices (1,2), (0,2), (0,1) for f = 0, 1, 2; the number of facet points is
+ * ceil((3k+4)/2)).  Used to pass a forcing to hdg_set_forcing. */
+int hdg_facet_points(const hdg_ctx* ctx, double* xy);
+
+/* Forcing f(x, t) = exp(-decay t) f0(x) of the momentum equation (eq.
+ * f_expl, explicit in the IMEX stages; the form of the paper's Taylor-Green
+ * forcing, eq. taylor_green_Q0_f).  cell_vals: f0 at the cell quadrature
+ * points [ncells][nq][2], facet_vals: f0 at the facet points
+ * [ncells][3][nq_facet][2], both DEVICE buffers, copied.  The forcing enters
+ * the stage and final residuals (eqs. imex_residual, final_residual) and
+ * the pressure reconstruction (f_p = -f + (Q.grad)Q, wall data -<mu, n.f>),
+ * so set it before hdg_set_velocity_from_points.  cell_vals == NULL removes
+ * the forcing. */
+int hdg_set_forcing(hdg_ctx* ctx, const double* cell_vals, const double* facet_vals, double decay);
+
+/* Time of the state (0 after hdg_create; hdg_advance adds dt per step).  It
+ * only matters with a forcing. */
+int hdg_set_time(hdg_ctx* ctx, double t);
+double hdg_get_time(const hdg_ctx* ctx);
+
 /* Initial state (the paper leaves it open): Q = cell-wise L2 projection of
  * the given point values [ncells][nq][2] with the cell rule; (p, lam) from
- * the pressure reconstruction of Q. */
+ * the pressure reconstruction of Q (with the forcing at the current time). */
 int hdg_set_velocity_from_points(hdg_ctx* ctx, const double* qvals);
 
 int hdg_set_state(hdg_ctx* ctx, const double* Q, const double* p, const double* lam);

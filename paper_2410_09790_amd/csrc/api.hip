@@ -53,6 +53,13 @@ struct Tableau {
   double Aex[kMaxStages][kMaxStages], bex[kMaxStages], Aim[kMaxStages][kMaxStages], bim[kMaxStages];
 };
 
+// explicit abscissa c_j = sum_l a^ex_jl
+static double abscissa(const Tableau& t, int j) {
+  double c = 0.0;
+  for (int l = 0; l < t.s; ++l) c += t.Aex[j][l];
+  return c;
+}
+
 static Tableau make_tableau(int which) {
   Tableau t{};
   if (which == HDG_IMEX_EULER) {
@@ -305,6 +312,12 @@ struct hdg_ctx {
   }
   double *iP = nullptr, *iG = nullptr, *iU = nullptr, *ired = nullptr;
   void reconstruct(const double* Qin, double* pout, double* lout);
+  // forcing f(x, t) = exp(-f_decay t) f0(x) (eq. f_expl): f0 as a dual vector,
+  // at the cell and facet points, and its wall data; time of the state
+  double time = 0.0, f_decay = 0.0;
+  double *f_dual = nullptr, *f_cell = nullptr, *f_fac = nullptr, *f_wall = nullptr, *f_tmp = nullptr;
+  bool forced = false;
+  double f_scale(double tt) const { return std::exp(-f_decay * tt); }
   void richardson(double adt, const double* r, double* Q, double* p, double* lam);
   void step(double dt);
 };
@@ -841,13 +854,18 @@ int hdg_ctx::idrs(double adt, const double* b, double* x) {
   return it;
 }
 
+// Pressure reconstruction at the current time (eq.
+// (pressure_reconstruction_compact)): psi-data Div_c(psi, (Q.grad)Q - f) and,
+// with forcing, wall data -<mu, n.f>.
 void hdg_ctx::reconstruct(const double* Qin, double* pout, double* lout) {
+  const double fs = forced ? f_scale(time) : 0.0;
   {
     Timed tm(prof, KC_RECON);
-    launch_recon_rhs(k, st, dm, dt, Qin, fpsi);
+    launch_recon_rhs(k, st, dm, dt, Qin, forced ? f_cell : nullptr, forced ? f_fac : nullptr, fs, fpsi);
+    if (forced) launch_axpby(st, nT, fs, f_wall, 0.0, f_tmp);
     KCHK();
   }
-  solve_trace(1.0, nullptr, fpsi, nullptr, Ut, pout, lout);
+  solve_trace(1.0, nullptr, fpsi, forced ? f_tmp : nullptr, Ut, pout, lout);
 }
 
 // Algorithm 2 for one stage: (Q, p, lam) hold the iterate on entry and exit
@@ -890,12 +908,17 @@ void hdg_ctx::step(double dtv) {
   launch_copy(st, nP, p, stP[0]);
   launch_copy(st, nT, lam, stL[0]);
   for (int i = 1; i < s; ++i) {
-    // stage residual r_i (forcing is zero)
+    // stage residual r_i, eq. (imex_residual)
     launch_copy(st, nQ, MQn, stR[i]);
     for (int j = 1; j < i; ++j) {
       const double w = tab.Aim[i][j] / tab.Aim[j][j];
       launch_axpby(st, nQ, w, stMQ[j], 1.0, stR[i]);
       launch_axpby(st, nQ, -w, stR[j], 1.0, stR[i]);
+    }
+    if (forced) {  // dt sum_{j<i} a^ex_ij f^ex(t + c_j dt)
+      double w = 0.0;
+      for (int j = 0; j < i; ++j) w += tab.Aex[i][j] * f_scale(time + abscissa(tab, j) * dtv);
+      launch_axpby(st, nQ, dtv * w, f_dual, 1.0, stR[i]);
     }
     {
       Timed tm(prof, KC_BDM);
@@ -917,7 +940,13 @@ void hdg_ctx::step(double dtv) {
     launch_axpby(st, nQ, w, stMQ[i], 1.0, rn);
     launch_axpby(st, nQ, -w, stR[i], 1.0, rn);
   }
+  if (forced) {  // dt sum_j b^ex_j f^ex(t + c_j dt), eq. (final_residual)
+    double w = 0.0;
+    for (int j = 0; j < s; ++j) w += tab.bex[j] * f_scale(time + abscissa(tab, j) * dtv);
+    launch_axpby(st, nQ, dtv * w, f_dual, 1.0, rn);
+  }
   KCHK();
+  time += dtv;  // the final projection and the reconstruction belong to t^{n+1}
   solve_trace(dtv * tab.bim[s - 1], rn, nullptr, nullptr, Q, dp, dl);
   if (prm.pressure_update == HDG_PRESSURE_RECONSTRUCT) {
     reconstruct(Q, p, lam);
@@ -1036,6 +1065,65 @@ int hdg_cell_points(const hdg_ctx* ctx, double* xy) {
   }
   return HDG_OK;
 }
+
+int hdg_facet_points(const hdg_ctx* ctx, double* xy) {
+  if (!ctx || !xy) return HDG_ERR_INVALID_ARG;
+  const auto& m = ctx->hm;
+  const auto& t = ctx->rt;
+  for (int64_t e = 0; e < m.nc; ++e) {
+    const double* v0 = &m.coords[2 * m.cells[3 * e]];
+    const double* v1 = &m.coords[2 * m.cells[3 * e + 1]];
+    const double* v2 = &m.coords[2 * m.cells[3 * e + 2]];
+    for (int f = 0; f < 3; ++f)
+      for (int q = 0; q < t.nqf; ++q) {
+        double a, b;  // the reference point of the facet trace tables
+        hdg::facet_point(f, t.fq_s[q], a, b);
+        const int64_t i = ((e * 3 + f) * t.nqf + q) * 2;
+        xy[i] = v0[0] + (v1[0] - v0[0]) * a + (v2[0] - v0[0]) * b;
+        xy[i + 1] = v0[1] + (v1[1] - v0[1]) * a + (v2[1] - v0[1]) * b;
+      }
+  }
+  return HDG_OK;
+}
+
+int hdg_set_forcing(hdg_ctx* ctx, const double* cell_vals, const double* facet_vals, double decay) {
+  if (!ctx || (cell_vals && !facet_vals) || !(decay == decay)) return HDG_ERR_INVALID_ARG;
+  ctx->not_converged = false;
+  ctx->err.clear();
+  API_BEGIN
+  if (!cell_vals) {
+    ctx->forced = false;
+  } else {
+    const long nc = ctx->hm.nc;
+    if (!ctx->f_dual) {
+      ctx->f_dual = ctx->dalloc<double>(ctx->nQ);
+      ctx->f_cell = ctx->dalloc<double>(nc * ctx->nqc * 2);
+      ctx->f_fac = ctx->dalloc<double>(nc * 3 * ctx->nqf * 2);
+      ctx->f_wall = ctx->dalloc<double>(ctx->nT);
+      ctx->f_tmp = ctx->dalloc<double>(ctx->nT);
+    }
+    HIPCHK(hipMemcpyAsync(ctx->f_cell, cell_vals, nc * ctx->nqc * 2 * sizeof(double), hipMemcpyDeviceToDevice,
+                          ctx->st));
+    HIPCHK(hipMemcpyAsync(ctx->f_fac, facet_vals, nc * 3 * ctx->nqf * 2 * sizeof(double), hipMemcpyDeviceToDevice,
+                          ctx->st));
+    launch_point_dual(ctx->k, ctx->st, ctx->dm, ctx->dt, ctx->f_cell, ctx->f_dual);
+    launch_fill(ctx->st, ctx->nT, 0.0, ctx->f_wall);
+    launch_wall_flux(ctx->k, ctx->st, ctx->dm, ctx->dt, ctx->f_fac, ctx->f_wall);
+    KCHK();
+    ctx->f_decay = decay;
+    ctx->forced = true;
+  }
+  ctx->sync();
+  API_END(ctx)
+}
+
+int hdg_set_time(hdg_ctx* ctx, double t) {
+  if (!ctx || !(t == t)) return HDG_ERR_INVALID_ARG;
+  ctx->time = t;
+  return HDG_OK;
+}
+
+double hdg_get_time(const hdg_ctx* ctx) { return ctx ? ctx->time : 0.0; }
 
 int hdg_set_velocity_from_points(hdg_ctx* ctx, const double* qvals) {
   if (!ctx || !qvals) return HDG_ERR_INVALID_ARG;

@@ -103,7 +103,13 @@ void launch_to_soa(int k, hipStream_t st, DMesh m, int inv_det, const double* x,
 void launch_to_aos(int k, hipStream_t st, DMesh m, const double* x, double* y);
 void launch_div(int k, hipStream_t st, DMesh m, DTab t, const double* F, double scale, double* out);
 void launch_bdm(int k, hipStream_t st, DMesh m, DTab t, const double* Q, double* Qs);
-void launch_recon_rhs(int k, hipStream_t st, DMesh m, DTab t, const double* Q, double* out);
+// f_p data of the pressure reconstruction: (Q.grad)Q - fsc f, f at the cell
+// and facet points (null: no forcing)
+void launch_recon_rhs(int k, hipStream_t st, DMesh m, DTab t, const double* Q, const double* fcell,
+                      const double* ffac, double fsc, double* out);
+// forcing: dual vector of cell point values; wall data -<mu, n.f> of facet point values (interior 0 untouched)
+void launch_point_dual(int k, hipStream_t st, DMesh m, DTab t, const double* vals, double* out);
+void launch_wall_flux(int k, hipStream_t st, DMesh m, DTab t, const double* vals, double* out);
 void launch_project(int k, hipStream_t st, DMesh m, DTab t, const double* vals, double* Q);
 void launch_mass(int k, hipStream_t st, DMesh m, double s, const double* x, double* y);
 void launch_shift_mean(int k, hipStream_t st, DMesh m, const double* mean, double* p, double* lam);

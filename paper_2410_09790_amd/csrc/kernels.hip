@@ -1122,6 +1122,8 @@ __global__ void __launch_bounds__(kBlock) k_bdm(DMesh m, DTab t, const double* _
 // psi-data of the pressure reconstruction: Div(psi, f_p), f_p = (Q.grad_h)Q
 template <int K>
 __global__ void __launch_bounds__(kBlock) k_recon_rhs(DMesh m, DTab t, const double* __restrict__ Q,
+                                                      const double* __restrict__ fcell,
+                                                      const double* __restrict__ ffac, double fsc,
                                                       double* __restrict__ out) {
   using D = Dims<K>;
   constexpr int NS = D::NS, NU = D::NU, NP = D::NP, NQC = D::NQC, NQF = D::NQF;
@@ -1152,6 +1154,10 @@ __global__ void __launch_bounds__(kBlock) k_recon_rhs(DMesh m, DTab t, const dou
   for (int qq = 0; qq < NQC; ++qq) {
     double fx, fy;
     conv(t.Bu + qq * NS, t.Gux + qq * NS, t.Guy + qq * NS, qv, g.ij, fx, fy);
+    if (fcell) {  // f_p = (Q.grad)Q - f
+      fx -= fsc * fcell[((long)e * NQC + qq) * 2];
+      fy -= fsc * fcell[((long)e * NQC + qq) * 2 + 1];
+    }
     const double w = t.cw[qq] * g.det;
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
@@ -1177,6 +1183,11 @@ __global__ void __launch_bounds__(kBlock) k_recon_rhs(DMesh m, DTab t, const dou
       double fx, fy, gx, gy;
       conv(t.FBu + (f * NQF + qq) * NS, t.FGux + (f * NQF + qq) * NS, t.FGuy + (f * NQF + qq) * NS, qv, g.ij, fx, fy);
       conv(t.FBu + (fn * NQF + qn) * NS, t.FGux + (fn * NQF + qn) * NS, t.FGuy + (fn * NQF + qn) * NS, xn, ijn, gx, gy);
+      if (ffac) {  // f is continuous: the same point value on both sides
+        const long fi = (((long)e * 3 + f) * NQF + qq) * 2;
+        fx -= fsc * ffac[fi]; gx -= fsc * ffac[fi];
+        fy -= fsc * ffac[fi + 1]; gy -= fsc * ffac[fi + 1];
+      }
       const double flux = 0.5 * t.fw[qq] * g.h[f] * ((fx + gx) * g.n[f][0] + (fy + gy) * g.n[f][1]);
 #pragma unroll
       for (int i = 0; i < NP; ++i) o[i] += t.FBp[(f * NQF + qq) * NP + i] * flux;
@@ -1217,6 +1228,49 @@ __global__ void k_mass(DMesh m, double s, const double* __restrict__ x, double* 
   if (tid >= (long)m.nc * NU) return;
   const int e = (int)(tid / NU);
   y[tid] = s * m.geo[D_DET * (long)m.nc + e] * x[tid];
+}
+
+// ====================================================== forcing (eq. f_expl)
+// Dual vector (f, w) of a field given at the cell quadrature points
+// (vals[(e*NQC + q)*2 + c]), AoS [cell][c*NS + s].
+template <int K>
+__global__ void k_point_dual(DMesh m, DTab t, const double* __restrict__ vals, double* __restrict__ out) {
+  using D = Dims<K>;
+  constexpr int NS = D::NS, NU = D::NU, NQC = D::NQC;
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (long)m.nc * NU) return;
+  const long e = tid / NU;
+  const int i = (int)(tid % NU), c = i / NS, s = i % NS;
+  double acc = 0.0;
+  for (int q = 0; q < NQC; ++q) acc += t.cw[q] * t.Bu[q * NS + s] * vals[(e * NQC + q) * 2 + c];
+  out[tid] = m.geo[D_DET * (long)m.nc + e] * acc;
+}
+
+// Wall data of the pressure reconstruction for a field f given at the facet
+// points (vals[((e*3 + f)*NQF + q)*2 + c], the cell's local parametrisation):
+// out(mu) = -<mu, n.f> on wall facets, 0 on interior facets.  One thread per
+// (cell, local facet).
+template <int K>
+__global__ void k_wall_flux(DMesh m, DTab t, const double* __restrict__ vals, double* __restrict__ out) {
+  using D = Dims<K>;
+  constexpr int NF = D::NF, NQF = D::NQF;
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nc = m.nc;
+  if (tid >= 3 * nc) return;
+  const long e = tid % nc;
+  const int f = (int)(tid / nc);
+  if (m.cf_nb[f * nc + e] >= 0) return;
+  const int F = m.cf_facet[f * nc + e], flip = m.cf_flip[f * nc + e];
+  const double nx = m.geo[(D_NX0 + 2 * f) * nc + e], ny = m.geo[(D_NY0 + 2 * f) * nc + e];
+  const double h = m.geo[(D_H0 + f) * nc + e];
+  for (int mm = 0; mm < NF; ++mm) {
+    double acc = 0.0;
+    for (int q = 0; q < NQF; ++q) {
+      const long vi = ((e * 3 + f) * NQF + q) * 2;
+      acc += t.fw[q] * t.MU[q * NF + mm] * (nx * vals[vi] + ny * vals[vi + 1]);
+    }
+    out[(long)F * NF + mm] = -sgn(flip, mm) * h * acc;
+  }
 }
 
 // ================================================================ generic
@@ -1539,8 +1593,15 @@ void launch_div(int k, hipStream_t st, DMesh m, DTab t, const double* F, double 
 void launch_bdm(int k, hipStream_t st, DMesh m, DTab t, const double* Q, double* Qs) {
   HDG_DISPATCH(k, (k_bdm<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, Q, Qs)));
 }
-void launch_recon_rhs(int k, hipStream_t st, DMesh m, DTab t, const double* Q, double* out) {
-  HDG_DISPATCH(k, (k_recon_rhs<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, Q, out)));
+void launch_recon_rhs(int k, hipStream_t st, DMesh m, DTab t, const double* Q, const double* fcell,
+                      const double* ffac, double fsc, double* out) {
+  HDG_DISPATCH(k, (k_recon_rhs<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, Q, fcell, ffac, fsc, out)));
+}
+void launch_point_dual(int k, hipStream_t st, DMesh m, DTab t, const double* vals, double* out) {
+  HDG_DISPATCH(k, (k_point_dual<KK><<<nblocks((long)m.nc * Dims<KK>::NU), kBlock, 0, st>>>(m, t, vals, out)));
+}
+void launch_wall_flux(int k, hipStream_t st, DMesh m, DTab t, const double* vals, double* out) {
+  HDG_DISPATCH(k, (k_wall_flux<KK><<<nblocks(3L * m.nc), kBlock, 0, st>>>(m, t, vals, out)));
 }
 void launch_project(int k, hipStream_t st, DMesh m, DTab t, const double* vals, double* Q) {
   HDG_DISPATCH(k, (k_project<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, vals, Q)));

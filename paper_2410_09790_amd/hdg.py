@@ -24,7 +24,7 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NOT_CO
 
 EXPORTS = [
     "hdg_default_params", "hdg_create", "hdg_destroy", "hdg_last_error", "hdg_sizes", "hdg_cell_points",
-    "hdg_set_velocity_from_points", "hdg_set_state", "hdg_get_state", "hdg_advance", "hdg_solve_trace",
+    "hdg_facet_points", "hdg_set_forcing", "hdg_set_time", "hdg_get_time", "hdg_set_velocity_from_points", "hdg_set_state", "hdg_get_state", "hdg_advance", "hdg_solve_trace",
     "hdg_trace_matvec", "hdg_bdm_project", "hdg_weak_divergence", "hdg_momentum_residual",
     "hdg_tentative_velocity", "hdg_reconstruct_pressure", "hdg_profile", "hdg_get_info",
 ]
@@ -74,6 +74,10 @@ def load_library(path: str = LIB_PATH):
         "hdg_last_error": (ctypes.c_char_p, [P]),
         "hdg_sizes": (I, [P, P, I]),
         "hdg_cell_points": (I, [P, P]),
+        "hdg_facet_points": (I, [P, P]),
+        "hdg_set_forcing": (I, [P, P, P, D]),
+        "hdg_set_time": (I, [P, D]),
+        "hdg_get_time": (D, [P]),
         "hdg_set_velocity_from_points": (I, [P, P]),
         "hdg_set_state": (I, [P, P, P, P]),
         "hdg_get_state": (I, [P, P, P, P]),
@@ -170,6 +174,31 @@ class Context:
         xy = np.empty((self.ncells, self.nq_cell, 2))
         self._check(self._lib.hdg_cell_points(self._h, xy.ctypes.data_as(ctypes.c_void_p)))
         return xy
+
+    def facet_points(self) -> np.ndarray:
+        nqf = (3 * self.degree + 5) // 2
+        xy = np.empty((self.ncells, 3, nqf, 2))
+        self._check(self._lib.hdg_facet_points(self._h, xy.ctypes.data_as(ctypes.c_void_p)))
+        return xy
+
+    def set_forcing(self, cell_values, facet_values, decay: float):
+        """f(x, t) = exp(-decay t) f0(x), f0 given at cell_points() and facet_points();
+        None removes the forcing."""
+        if cell_values is None:
+            self._check(self._lib.hdg_set_forcing(self._h, None, None, float(decay)))
+            return
+        import torch
+        cv = torch.as_tensor(np.ascontiguousarray(cell_values, dtype=np.float64)).to(self.device)
+        fv = torch.as_tensor(np.ascontiguousarray(facet_values, dtype=np.float64)).to(self.device)
+        self._check(self._lib.hdg_set_forcing(self._h, _ptr(cv), _ptr(fv), float(decay)))
+
+    @property
+    def time(self) -> float:
+        return float(self._lib.hdg_get_time(self._h))
+
+    @time.setter
+    def time(self, t: float):
+        self._check(self._lib.hdg_set_time(self._h, float(t)))
 
     def set_velocity_from_points(self, values):
         import torch
