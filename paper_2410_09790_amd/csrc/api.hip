@@ -714,7 +714,7 @@ int hdg_ctx::bicgstab(double adt, const double* b_aos, double* x_aos) {
     ++j;
     if (j - jc == kCheck || it >= maxit) {
       const int cnt = j - jc;
-      launch_finish(st, part, kRedBlocks, sc + BS_RR);
+      launch_finish(st, part, kVecBlocks, sc + BS_RR);
       HIPCHK(hipMemcpyAsync(h_pinned, bsc + (long)BS_STRIDE * jc, (size_t)BS_STRIDE * cnt * sizeof(double),
                             hipMemcpyDeviceToHost, st));
       sync();

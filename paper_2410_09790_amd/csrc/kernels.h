@@ -43,6 +43,11 @@ struct IdrCoef {
   double v[kIdrMax];
 };
 constexpr int kRedBlocks = 1024;  // fixed grid for deterministic reductions
+// Grid of the BiCGStab vector kernels (k_bicg_s, k_bicg_xrp): every block
+// finishes the inner products of the preceding operator launch itself, so
+// fewer, fuller blocks read fewer partials in total; k_bicg_xrp leaves
+// kVecBlocks partials of r.r.
+constexpr int kVecBlocks = 512;
 
 // Device scalars of one BiCGStab iteration (BS_STRIDE doubles per slot).
 enum BiCGSlot {
@@ -93,7 +98,7 @@ int apply_soa_blocks(long nc);
 //   s = r - alpha v, alpha from those partials: launch_bicg_s
 //   t = A s: launch_apply_soa dot 2 with rh (partials in part2)
 //   x, r, p updates, omega and beta from part2, partials of r.r
-//   (kRedBlocks of them) in part: launch_bicg_xrp
+//   (kVecBlocks of them) in part: launch_bicg_xrp
 void launch_bicg_s(hipStream_t st, long n, long nc, const double* part, double* sc, const double* r, const double* v,
                    double* s);
 void launch_bicg_xrp(hipStream_t st, long n, long nc, const double* part2, double* sc, const double* s,

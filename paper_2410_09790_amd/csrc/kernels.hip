@@ -921,7 +921,7 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
 //                           k_bicg_xrp: every block finishes the four sums
 //                           (omega, beta), block 0 records them and opens the
 //                           next slot; partials of r.r
-// Both vector kernels run on a fixed grid of kRedBlocks blocks, so the
+// Both vector kernels run on a fixed grid of kVecBlocks blocks, so the
 // redundant finishes read few partials in total.
 __global__ void __launch_bounds__(kBlock) k_bicg_s(long n, int np, const double* __restrict__ part,
                                                    double* __restrict__ sc, const double* __restrict__ R,
@@ -929,8 +929,15 @@ __global__ void __launch_bounds__(kBlock) k_bicg_s(long n, int np, const double*
   const double rv = sum_partials(part, np);
   const bool ok = rv != 0.0 && rv == rv;
   const double al = ok ? sc[BS_RHO] / rv : 0.0;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-    S[i] = R[i] - al * Vv[i];
+  // n is even (2 ns doubles per cell and component pair): 16-byte accesses
+  const long n2 = n >> 1;
+  const double2* R2 = reinterpret_cast<const double2*>(R);
+  const double2* V2 = reinterpret_cast<const double2*>(Vv);
+  double2* S2 = reinterpret_cast<double2*>(S);
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (long)gridDim.x * blockDim.x) {
+    const double2 r = R2[i], v = V2[i];
+    S2[i] = make_double2(r.x - al * v.x, r.y - al * v.y);
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc[BS_RV] = rv;
     sc[BS_ALPHA] = al;
@@ -956,13 +963,18 @@ __global__ void __launch_bounds__(kBlock) k_bicg_xrp(long n, int np, const doubl
   const bool okb = okw && rho != 0.0 && rho_next == rho_next;
   const double be = okb ? (rho_next / rho) * (al / om) : 0.0;
   double rr = 0.0;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const double p = P[i], s = S[i];
-    X[i] += al * p + om * s;
-    const double r = s - om * Tv[i];
-    R[i] = r;
-    rr += r * r;
-    P[i] = r + be * (p - om * Vv[i]);
+  const long n2 = n >> 1;  // n is even: 16-byte accesses
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (long)gridDim.x * blockDim.x) {
+    const double2 p = reinterpret_cast<const double2*>(P)[i], s = reinterpret_cast<const double2*>(S)[i];
+    const double2 t = reinterpret_cast<const double2*>(Tv)[i], v = reinterpret_cast<const double2*>(Vv)[i];
+    double2 x = reinterpret_cast<const double2*>(X)[i];
+    x.x += al * p.x + om * s.x;
+    x.y += al * p.y + om * s.y;
+    reinterpret_cast<double2*>(X)[i] = x;
+    const double2 r = make_double2(s.x - om * t.x, s.y - om * t.y);
+    reinterpret_cast<double2*>(R)[i] = r;
+    rr += r.x * r.x + r.y * r.y;
+    reinterpret_cast<double2*>(P)[i] = make_double2(r.x + be * (p.x - om * v.x), r.y + be * (p.y - om * v.y));
   }
   rr = block_sum(rr);
   if (threadIdx.x == 0) part[blockIdx.x] = rr;
@@ -1574,11 +1586,11 @@ void launch_apply_soa(int k, hipStream_t st, int dot, DMesh m, DTab t, const voi
 int apply_soa_blocks(long nc) { return nblocks(2L * nc); }
 void launch_bicg_s(hipStream_t st, long n, long nc, const double* part, double* sc, const double* r, const double* v,
                    double* s) {
-  k_bicg_s<<<kRedBlocks, kBlock, 0, st>>>(n, nblocks(2L * nc), part, sc, r, v, s);
+  k_bicg_s<<<kVecBlocks, kBlock, 0, st>>>(n, nblocks(2L * nc), part, sc, r, v, s);
 }
 void launch_bicg_xrp(hipStream_t st, long n, long nc, const double* part2, double* sc, const double* s,
                      const double* tv, const double* v, double* x, double* r, double* p, double* part) {
-  k_bicg_xrp<<<kRedBlocks, kBlock, 0, st>>>(n, nblocks(2L * nc), part2, sc, s, tv, v, x, r, p, part);
+  k_bicg_xrp<<<kVecBlocks, kBlock, 0, st>>>(n, nblocks(2L * nc), part2, sc, s, tv, v, x, r, p, part);
 }
 void launch_bicg_init(hipStream_t st, double* sc) { k_bicg_init<<<1, 64, 0, st>>>(sc); }
 void launch_to_soa(int k, hipStream_t st, DMesh m, int inv_det, const double* x, double* y) {
