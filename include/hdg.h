@@ -109,11 +109,14 @@ typedef struct {
   int pressure_update;   /* hdg_pressure_update */
   int idr_s;             /* Step I Krylov method: IDR(s) with this s (1..8), or 0 = BiCGStab */
   int precision;         /* hdg_precision */
+  int use_graphs;        /* 1: the Krylov iteration blocks (PCG: 4 iterations, BiCGStab: 8)
+                            are captured once as HIP graphs and replayed; 0: launched one by
+                            one.  Results are the same.  Ignored while profiling is on. */
 } hdg_params;
 
 /* Fill p with the defaults: k=1, tau=alpha=delta_up=1, ARS(2,2,2), n_R=3,
  * MG-PCG, rtol 1e-12 for both solvers, caps 5000 / 20000, reconstruction,
- * BiCGStab for Step I, FP64. */
+ * BiCGStab for Step I, FP64, graph replay on. */
 void hdg_default_params(hdg_params* p);
 
 /* Create a context on the current HIP device.  coords: host [nv][2];

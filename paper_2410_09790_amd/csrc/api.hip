@@ -137,6 +137,7 @@ struct TraceOp {
   int ncoarse = 0;
   double* coarse_pinv = nullptr;
   double *cb = nullptr, *cx = nullptr;  // coarsest rhs / solution
+  hipGraphExec_t pcg_block = nullptr;    // captured block of PCG iterations
 };
 
 // Optional per-kernel-class timing with HIP events on the context stream:
@@ -285,6 +286,9 @@ struct hdg_ctx {
   void mg_apply(hdg::TraceOp& op, const double* r, double* z);
   void vcycle(hdg::TraceOp& op, int l);
   int pcg(hdg::TraceOp& op, const double* g, double* x);
+  static constexpr int kPcgBlock = 4;  // PCG iterations per captured block
+  void pcg_block(hdg::TraceOp& op);
+  double* px = nullptr;                // PCG iterate (fixed address for the captured block)
   void solve_trace(double c, const double* Fw, const double* Fpsi, const double* Fmu, double* U, double* p,
                    double* lam);
   // BiCGStab vectors, structure-of-arrays
@@ -306,6 +310,14 @@ struct hdg_ctx {
     hdg::launch_step1_matrix(k, st, dm, dt, Qstar, prm.delta_up, vk, vk32, vbeta);
   }
   int bicgstab(double adt, const double* b, double* x);
+  static constexpr int kBicgBlock = 8;  // BiCGStab iterations per captured block
+  void bicgstab_block(double adt);
+  std::map<double, hipGraphExec_t> bicg_graphs;  // captured blocks per adt
+  // Graph capture runs on a private stream (capture is not possible on the
+  // legacy null stream a caller may pass); the graphs are launched on st.
+  hipStream_t cap_st = nullptr;
+  template <class Body>
+  hipGraphExec_t capture(Body&& body);
   int idrs(double adt, const double* b, double* x);
   int velocity_solve(double adt, const double* b, double* x) {
     return prm.idr_s > 0 ? idrs(adt, b, x) : bicgstab(adt, b, x);
@@ -375,10 +387,10 @@ void hdg_ctx::setup() {
   part2 = dalloc<double>(2 * kRedBlocks);
   const int mt = prm.max_it_trace + 4, mv = prm.max_it_velocity + 4;
   scal = dalloc<double>(3 * mt + 16);
-  bsc = dalloc<double>((long)BS_STRIDE * (mv + 2));
+  bsc = dalloc<double>((long)BS_STRIDE * std::max(mv + 2, kBicgBlock + 2));
   kpart = dalloc<double>(4L * apply_soa_blocks(nc) + 16);
   pr = dalloc<double>(nT); pz = dalloc<double>(nT); pp = dalloc<double>(nT); pq = dalloc<double>(nT);
-  t1 = dalloc<double>(nT); t2 = dalloc<double>(nT); t3 = dalloc<double>(nT);
+  t1 = dalloc<double>(nT); t2 = dalloc<double>(nT); t3 = dalloc<double>(nT); px = dalloc<double>(nT);
   for (double** v : {&kd.b, &kd.x, &kd.r, &kd.rh, &kd.s, &kd.t, &kd.p, &kd.v}) *v = dalloc<double>(nQ);
   const long nc32 = (nc + 31) / 32 * 32;
   vk32 = prm.precision == HDG_MIXED;
@@ -559,57 +571,81 @@ void hdg_ctx::precond(TraceOp& op, const double* r, double* z) {
   KCHK();
 }
 
-// preconditioned CG on S x = g (g orthogonal to the constant trace), x0 = 0
-int hdg_ctx::pcg(TraceOp& op, const double* gin, double* x) {
-  constexpr int kCheck = 4;
-  static_assert(kCheck <= kPinned, "pinned buffer holds kCheck residuals");
+// Preconditioned CG on S x = g (g orthogonal to the constant trace), x0 = 0,
+// in blocks of kPcgBlock iterations.  A block is the same sequence of
+// launches every time (its scalars live in a ring that the block rotates
+// first), so it is captured once per operator as a HIP graph and replayed;
+// the host then reads the block's residual norms (a converged solve runs
+// at most kPcgBlock - 1 extra iterations, which only improve x).  With
+// kernel timing on, the block runs eagerly so that its launches are timed.
+void hdg_ctx::pcg_block(TraceOp& op) {
   const long n = nT;
   const int nF = (int)hm.nF;
-  const int maxit = prm.max_it_trace;
-  double* rz = scal;               // [maxit+2]
-  double* pqv = scal + (maxit + 4);  // [maxit+1]
-  double* rr = scal + 2 * (maxit + 4);
-  launch_fill(st, n, 0.0, x);
-  launch_copy(st, n, gin, pr);
-  launch_dot(st, n, pr, nullptr, part);
-  launch_finish(st, part, kRedBlocks, rr + maxit + 2);
-  const double gnorm = std::sqrt(read_scalar(rr + maxit + 2));
-  if (gnorm == 0.0) return 0;
-  precond(op, pr, pz);
-  launch_dot(st, n, pr, pz, part);
-  launch_finish(st, part, kRedBlocks, rz);
-  launch_copy(st, n, pz, pp);
-  for (int it = 0; it < maxit; ++it) {
+  double* rz = scal;  // ring: rz[0..kPcgBlock], pq[0..kPcgBlock), rr[0..kPcgBlock)
+  double* pqv = scal + kPcgBlock + 1;
+  double* rr = scal + 2 * kPcgBlock + 1;
+  launch_copy(st, 1, rz + kPcgBlock, rz);
+  for (int b = 0; b < kPcgBlock; ++b) {
     {
       Timed tm(prof, KC_TRACE_SPMV);
       launch_spmv(k, st, nF, op.vals, op.cols, pp, pq);
     }
     launch_dot(st, n, pp, pq, part);
-    launch_finish(st, part, kRedBlocks, pqv + it);
-    launch_pcg_update(st, n, rz + it, pqv + it, pp, pq, x, pr, part);
-    launch_finish(st, part, kRedBlocks, rr + it);
-    KCHK();
-    // the residual norms stay on the device; the host reads the last kCheck
-    // of them at once (a converged solve runs at most kCheck - 1 extra
-    // iterations, which only improve x)
-    if ((it + 1) % kCheck == 0 || it + 1 == maxit) {
-      const int c0 = it + 1 - ((it + 1) % kCheck == 0 ? kCheck : (it + 1) % kCheck);
-      HIPCHK(hipMemcpyAsync(h_pinned, rr + c0, (size_t)(it + 1 - c0) * sizeof(double), hipMemcpyDeviceToHost, st));
-      sync();
-      for (int i = 0; i <= it - c0; ++i) {
-        const double res = std::sqrt(h_pinned[i]);
-        if (!(res == res)) throw SolverBreakdown("PCG breakdown (NaN residual)");
-        if (res <= prm.rtol_trace * gnorm) return it + 1;
-      }
-    }
+    launch_finish(st, part, kRedBlocks, pqv + b);
+    launch_pcg_update(st, n, rz + b, pqv + b, pp, pq, px, pr, part);
+    launch_finish(st, part, kRedBlocks, rr + b);
     precond(op, pr, pz);
     launch_dot(st, n, pr, pz, part);
-    launch_finish(st, part, kRedBlocks, rz + it + 1);
-    launch_pcg_direction(st, n, rz + it + 1, rz + it, pz, pp);
+    launch_finish(st, part, kRedBlocks, rz + b + 1);
+    launch_pcg_direction(st, n, rz + b + 1, rz + b, pz, pp);
   }
-  cap_reached("PCG on the trace system: " + std::to_string(maxit) + " iterations without reaching rtol_trace (relative residual " +
-              std::to_string(std::sqrt(read_scalar(rr + maxit - 1)) / gnorm) + ")");
-  return maxit;
+  KCHK();
+}
+
+int hdg_ctx::pcg(TraceOp& op, const double* gin, double* x) {
+  static_assert(kPcgBlock <= kPinned, "pinned buffer holds a block of residuals");
+  const long n = nT;
+  const int maxit = prm.max_it_trace;
+  double* rz = scal;
+  double* rr = scal + 2 * kPcgBlock + 1;
+  double* gsq = scal + 3 * kPcgBlock + 2;
+  launch_fill(st, n, 0.0, px);
+  launch_copy(st, n, gin, pr);
+  launch_dot(st, n, pr, nullptr, part);
+  launch_finish(st, part, kRedBlocks, gsq);
+  const double gnorm = std::sqrt(read_scalar(gsq));
+  if (gnorm == 0.0) {
+    launch_fill(st, n, 0.0, x);
+    return 0;
+  }
+  precond(op, pr, pz);
+  launch_dot(st, n, pr, pz, part);
+  launch_finish(st, part, kRedBlocks, rz + kPcgBlock);  // the block rotates it to rz[0]
+  launch_copy(st, n, pz, pp);
+  KCHK();
+  const bool graphs = prm.use_graphs && !prof.on;
+  if (graphs && !op.pcg_block) op.pcg_block = capture([&] { pcg_block(op); });
+  double res = 0.0;
+  int it = 0;
+  while (it < maxit) {
+    if (graphs) HIPCHK(hipGraphLaunch(op.pcg_block, st));
+    else pcg_block(op);
+    HIPCHK(hipMemcpyAsync(h_pinned, rr, kPcgBlock * sizeof(double), hipMemcpyDeviceToHost, st));
+    sync();
+    for (int b = 0; b < kPcgBlock; ++b) {
+      res = std::sqrt(h_pinned[b]);
+      if (!(res == res)) throw SolverBreakdown("PCG breakdown (NaN residual)");
+      if (res <= prm.rtol_trace * gnorm) {
+        launch_copy(st, n, px, x);
+        return it + kPcgBlock;
+      }
+    }
+    it += kPcgBlock;
+  }
+  launch_copy(st, n, px, x);
+  cap_reached("PCG on the trace system: " + std::to_string(it) + " iterations without reaching rtol_trace (relative residual " +
+              std::to_string(res / gnorm) + ")");
+  return it;
 }
 
 void hdg_ctx::solve_trace(double c, const double* Fw, const double* Fpsi, const double* Fmu, double* U, double* pout,
@@ -646,18 +682,75 @@ void hdg_ctx::solve_trace(double c, const double* Fw, const double* Fpsi, const 
 // the cell matrices in FP32).  An iteration is four launches: v = A p
 // (with partials of rh.v), s = r - alpha v (alpha finished there), t = A s
 // (with partials of t.s, t.t, rh.s, rh.t), and the x, r, p updates (omega
-// and beta finished there, partials of r.r).  Coefficients stay in device memory, so the host only
-// enqueues; every kCheck iterations it reads the slots back: the residual
-// r.r of the current iterate, NaNs and breakdown flags.  A breakdown (zero
-// divisor) restarts from the current iterate with the true residual.
+// and beta finished there, partials of r.r).  Coefficients stay in device
+// memory; the host reads a block's slots back after every kBicgBlock
+// iterations: the residual r.r of the current iterate, NaNs and breakdown
+// flags.  A breakdown (zero divisor) restarts from the current iterate with
+// the true residual.
+// Records the launches body() issues on the context stream into a graph
+// and instantiates it.  Nothing runs during capture.
+template <class Body>
+hipGraphExec_t hdg_ctx::capture(Body&& body) {
+  if (!cap_st) HIPCHK(hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking));
+  hipStream_t keep = st;
+  hipGraph_t gr = nullptr;
+  HIPCHK(hipStreamBeginCapture(cap_st, hipStreamCaptureModeThreadLocal));
+  st = cap_st;
+  try {
+    body();
+  } catch (...) {
+    st = keep;
+    if (hipStreamEndCapture(cap_st, &gr) == hipSuccess && gr) (void)hipGraphDestroy(gr);
+    throw;
+  }
+  st = keep;
+  HIPCHK(hipStreamEndCapture(cap_st, &gr));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(gr);
+  HIPCHK(e);
+  return exec;
+}
+
+// One block of kBicgBlock iterations on the slot ring bsc[0..kBicgBlock]:
+// the block first moves the opening slot (kBicgBlock) to slot 0, iteration
+// b uses slot b and opens slot b + 1, and the block ends with r.r of its
+// last iterate in slot kBicgBlock - 1.  The same launches every time, so
+// the block is captured once per adt as a HIP graph and replayed.
+void hdg_ctx::bicgstab_block(double adt) {
+  KrylovBuf& B = kd;
+  const long n = nQ;
+  launch_copy(st, BS_STRIDE, bsc + (long)BS_STRIDE * kBicgBlock, bsc);
+  for (int b = 0; b < kBicgBlock; ++b) {
+    double* sc = bsc + (long)BS_STRIDE * b;
+    {
+      Timed tm(prof, KC_APPLY_OP);
+      launch_apply_soa(k, st, 1, dm, dt, vk, vk32, vbeta, prm.alpha, adt, B.p, B.rh, B.v, part);
+    }
+    {
+      Timed tm(prof, KC_VECTOR);
+      launch_bicg_s(st, n, hm.nc, part, sc, B.r, B.v, B.s);
+    }
+    {
+      Timed tm(prof, KC_APPLY_OP);
+      launch_apply_soa(k, st, 2, dm, dt, vk, vk32, vbeta, prm.alpha, adt, B.s, B.rh, B.t, kpart);
+    }
+    {
+      Timed tm(prof, KC_VECTOR);
+      launch_bicg_xrp(st, n, hm.nc, kpart, sc, B.s, B.t, B.v, B.x, B.r, B.p, part);
+    }
+  }
+  launch_finish(st, part, kVecBlocks, bsc + (long)BS_STRIDE * (kBicgBlock - 1) + BS_RR);
+  KCHK();
+}
+
 int hdg_ctx::bicgstab(double adt, const double* b_aos, double* x_aos) {
   KrylovBuf& B = kd;
-  constexpr int kCheck = 8;
-  static_assert(BS_STRIDE * kCheck <= kPinned, "pinned buffer holds kCheck slots");
+  static_assert(BS_STRIDE * kBicgBlock <= kPinned, "pinned buffer holds a block of slots");
   const long n = nQ;
   const int maxit = prm.max_it_velocity;
   const double rtol = prm.rtol_velocity;
-  const double* beta = vbeta;
+  double* open = bsc + (long)BS_STRIDE * kBicgBlock;  // slot opening the next block
   launch_to_soa(k, st, dm, 0, b_aos, B.b);
   launch_dot(st, n, B.b, nullptr, part);
   launch_finish(st, part, kRedBlocks, bsc);
@@ -667,8 +760,17 @@ int hdg_ctx::bicgstab(double adt, const double* b_aos, double* x_aos) {
     launch_fill(st, nQ, 0.0, x_aos);
     return 0;
   }
+  const bool graphs = prm.use_graphs && !prof.on;
+  hipGraphExec_t* exec = nullptr;
+  if (graphs) {
+    if (bicg_graphs.size() >= 16 && !bicg_graphs.count(adt)) {  // time step changes: drop the old ones
+      for (auto& g : bicg_graphs) (void)hipGraphExecDestroy(g.second);
+      bicg_graphs.clear();
+    }
+    exec = &bicg_graphs[adt];
+  }
   launch_fill(st, n, 0.0, B.x);
-  int it = 0, j = 0, jc = 0, restarts = 0;
+  int it = 0, restarts = 0;
   bool restart = true;
   while (true) {
     if (restart) {
@@ -677,7 +779,7 @@ int hdg_ctx::bicgstab(double adt, const double* b_aos, double* x_aos) {
       } else {  // true residual of the current iterate
         {
           Timed tm(prof, KC_APPLY_OP);
-          launch_apply_soa(k, st, 0, dm, dt, vk, vk32, beta, prm.alpha, adt, B.x, nullptr, B.t, nullptr);
+          launch_apply_soa(k, st, 0, dm, dt, vk, vk32, vbeta, prm.alpha, adt, B.x, nullptr, B.t, nullptr);
         }
         launch_copy(st, n, B.b, B.r);
         launch_axpby(st, n, -1.0, B.t, 1.0, B.r);
@@ -686,52 +788,33 @@ int hdg_ctx::bicgstab(double adt, const double* b_aos, double* x_aos) {
       }
       launch_copy(st, n, B.r, B.p);
       launch_copy(st, n, B.r, B.rh);
-      launch_bicg_init(st, bsc);
+      launch_bicg_init(st, open);
       launch_dot(st, n, B.rh, nullptr, part);
-      launch_finish(st, part, kRedBlocks, bsc + BS_RHO);
-      j = jc = 0;
+      launch_finish(st, part, kRedBlocks, open + BS_RHO);
+      KCHK();
       restart = false;
     }
-    double* sc = bsc + (long)BS_STRIDE * j;
-    {
-      Timed tm(prof, KC_APPLY_OP);
-      launch_apply_soa(k, st, 1, dm, dt, vk, vk32, beta, prm.alpha, adt, B.p, B.rh, B.v, part);
+    if (graphs) {
+      if (!*exec) *exec = capture([&] { bicgstab_block(adt); });
+      HIPCHK(hipGraphLaunch(*exec, st));
+    } else {
+      bicgstab_block(adt);
     }
-    {
-      Timed tm(prof, KC_VECTOR);
-      launch_bicg_s(st, n, hm.nc, part, sc, B.r, B.v, B.s);
+    it += kBicgBlock;
+    HIPCHK(hipMemcpyAsync(h_pinned, bsc, (size_t)BS_STRIDE * kBicgBlock * sizeof(double), hipMemcpyDeviceToHost, st));
+    sync();
+    const double rr = h_pinned[BS_STRIDE * (kBicgBlock - 1) + BS_RR];
+    if (!(rr == rr)) throw SolverBreakdown("BiCGStab breakdown (NaN residual); the result is invalid");
+    if (std::sqrt(rr) <= rtol * bnorm) break;
+    if (it >= maxit) {
+      cap_reached("BiCGStab (Step I): " + std::to_string(it) + " iterations without reaching rtol_velocity "
+                  "(relative residual " + std::to_string(std::sqrt(rr) / bnorm) + ", " +
+                  std::to_string(restarts) + " restarts)");
+      break;
     }
-    {
-      Timed tm(prof, KC_APPLY_OP);
-      launch_apply_soa(k, st, 2, dm, dt, vk, vk32, beta, prm.alpha, adt, B.s, B.rh, B.t, kpart);
-    }
-    {
-      Timed tm(prof, KC_VECTOR);
-      launch_bicg_xrp(st, n, hm.nc, kpart, sc, B.s, B.t, B.v, B.x, B.r, B.p, part);
-    }
-    KCHK();
-    ++it;
-    ++j;
-    if (j - jc == kCheck || it >= maxit) {
-      const int cnt = j - jc;
-      launch_finish(st, part, kVecBlocks, sc + BS_RR);
-      HIPCHK(hipMemcpyAsync(h_pinned, bsc + (long)BS_STRIDE * jc, (size_t)BS_STRIDE * cnt * sizeof(double),
-                            hipMemcpyDeviceToHost, st));
-      sync();
-      const double rr = h_pinned[BS_STRIDE * (cnt - 1) + BS_RR];
-      if (!(rr == rr)) throw SolverBreakdown("BiCGStab breakdown (NaN residual); the result is invalid");
-      if (std::sqrt(rr) <= rtol * bnorm) break;
-      if (it >= maxit) {
-        cap_reached("BiCGStab (Step I): " + std::to_string(maxit) + " iterations without reaching rtol_velocity "
-                    "(relative residual " + std::to_string(std::sqrt(rr) / bnorm) + ", " +
-                    std::to_string(restarts) + " restarts)");
-        break;
-      }
-      bool flag = false;
-      for (int i = 0; i < cnt; ++i) flag |= h_pinned[BS_STRIDE * i + BS_FLAG] != 0.0;
-      jc = j;
-      if (flag) restart = true;
-    }
+    bool flag = false;
+    for (int b = 0; b < kBicgBlock; ++b) flag |= h_pinned[BS_STRIDE * b + BS_FLAG] != 0.0;
+    if (flag) restart = true;
   }
   launch_to_aos(k, st, dm, B.x, x_aos);
   KCHK();
@@ -988,6 +1071,7 @@ void hdg_default_params(hdg_params* p) {
   p->pressure_update = HDG_PRESSURE_RECONSTRUCT;
   p->idr_s = 0;
   p->precision = HDG_FP64;
+  p->use_graphs = 1;
 }
 
 int hdg_create(int64_t nv, const double* coords, int64_t nc, const int32_t* cells, const hdg_params* prm,
@@ -1002,7 +1086,7 @@ int hdg_create(int64_t nv, const double* coords, int64_t nc, const int32_t* cell
       prm->max_it_velocity < 1 || !(prm->rtol_trace > 0) || !(prm->rtol_velocity > 0) || prm->imex < 0 ||
       prm->imex > 4 || prm->trace_solver < 0 || prm->trace_solver > 1 || prm->pressure_update < 0 ||
       prm->pressure_update > 1 || prm->idr_s < 0 || prm->idr_s > kIdrMax ||
-      prm->precision < 0 || prm->precision > 1) {
+      prm->precision < 0 || prm->precision > 1 || prm->use_graphs < 0 || prm->use_graphs > 1) {
     g_create_error = "invalid parameter";
     return HDG_ERR_INVALID_ARG;
   }
@@ -1032,6 +1116,10 @@ int hdg_create(int64_t nv, const double* coords, int64_t nc, const int32_t* cell
 void hdg_destroy(hdg_ctx* ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->st);
+  for (auto& kv : ctx->ops)
+    if (kv.second->pcg_block) (void)hipGraphExecDestroy(kv.second->pcg_block);
+  for (auto& g : ctx->bicg_graphs) (void)hipGraphExecDestroy(g.second);
+  if (ctx->cap_st) (void)hipStreamDestroy(ctx->cap_st);
   for (void* p : ctx->allocs) (void)hipFree(p);
   if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
   delete ctx;

@@ -46,6 +46,7 @@ class Params(ctypes.Structure):
         ("pressure_update", ctypes.c_int),
         ("idr_s", ctypes.c_int),
         ("precision", ctypes.c_int),
+        ("use_graphs", ctypes.c_int),
     ]
 
 

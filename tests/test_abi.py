@@ -79,3 +79,36 @@ def test_clockwise_mesh_is_rejected_on_the_host(lib_path):
                         ctypes.byref(p), None, ctypes.byref(h))
     assert st == 1 and not h.value
     assert b"counter-clockwise" in lib.hdg_last_error(None)
+
+
+def test_graph_parameter_is_checked_on_the_host(lib_path):
+    from paper_2410_09790_amd import hdg
+    lib = hdg.load_library()
+    assert hdg.default_params().use_graphs == 1
+    assert hdg.default_params(use_graphs=0).use_graphs == 0
+    p = hdg.default_params()
+    p.use_graphs = 2
+    h = ctypes.c_void_p()
+    st = lib.hdg_create(3, None, 1, None, ctypes.byref(p), None, ctypes.byref(h))
+    assert st == 1 and not h.value
+    assert b"invalid parameter" in lib.hdg_last_error(None)
+
+
+def test_params_struct_layout_matches_the_header(tmp_path):
+    """The ctypes mirror of hdg_params has the C compiler's size and offsets."""
+    import shutil
+    import subprocess
+    from paper_2410_09790_amd import hdg
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    names = [f[0] for f in hdg.Params._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"hdg.h\"\nint main(void) {\n"
+                   "  printf(\"%zu\\n\", sizeof(hdg_params));\n"
+                   + "".join(f"  printf(\"%zu\\n\", offsetof(hdg_params, {n}));\n" for n in names)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert out[0] == ctypes.sizeof(hdg.Params)
+    assert out[1:] == [getattr(hdg.Params, n).offset for n in names]
