@@ -19,6 +19,10 @@ into n x n squares, each split into two right-angled triangles):
 * Taylor-Green vortex (Section "Taylor Green vortex"): velocity and forcing
   as printed; the pressure is the mean-zero field that satisfies the momentum
   equation (the printed pressure does not).
+* double-layer shear flow (Section "Double-layer shear flow"): the periodic
+  square [0, 2 pi]^2 on the same n x n split-square mesh with the right/top
+  vertices identified with the left/bottom ones, and the printed initial
+  velocity with rho = pi/15, delta = 0.05.
 """
 from __future__ import annotations
 
@@ -32,6 +36,10 @@ __all__ = [
     "taylor_green_forcing",
     "taylor_green_pressure",
     "random_mesh_perturbation",
+    "periodic_square_mesh",
+    "shear_layer_velocity",
+    "steady_vortex_velocity",
+    "steady_vortex_pressure",
 ]
 
 
@@ -68,6 +76,52 @@ def random_mesh_perturbation(coords: np.ndarray, n: int, amplitude: float, seed:
     )
     out[interior] += amplitude / n * rng.uniform(-1.0, 1.0, size=(int(interior.sum()), 2))
     return out
+
+
+def periodic_square_mesh(n: int, length: float = 2.0 * np.pi, amplitude: float = 0.0, seed: int = 0):
+    """Doubly periodic mesh of [0, length]^2.
+
+    Returns (coords, cells, vertex_rep): the unit_square_mesh connectivity
+    scaled by length, and for every vertex the vertex it is identified with
+    (vertices on the right and top edges map to their copies on the left and
+    bottom edges, the other vertices to themselves).  With amplitude > 0 each
+    class of identified vertices moves by one seeded offset (a fraction of the
+    spacing length/n), applied to all its copies, so the mesh stays periodic.
+    n >= 3 keeps the facets of the periodic mesh distinct.
+    """
+    if n < 3:
+        raise ValueError("periodic meshes need n >= 3")
+    coords, cells = unit_square_mesh(n)
+    coords = coords * length
+    i, j = np.meshgrid(np.arange(n + 1), np.arange(n + 1), indexing="xy")
+    i, j = i.ravel(), j.ravel()
+    rep = ((j % n) * (n + 1) + (i % n)).astype(np.int32)
+    if amplitude:
+        rng = np.random.default_rng(seed)
+        off = amplitude * length / n * rng.uniform(-1.0, 1.0, size=(n * n, 2))
+        coords = coords + off[(j % n) * n + (i % n)]
+    return coords, cells, rep
+
+
+def shear_layer_velocity(x, y, rho: float = np.pi / 15.0, delta: float = 0.05):
+    """Initial velocity of the double-layer shear flow on [0, 2 pi]^2 (Section
+    "Double-layer shear flow"): tanh profiles of width rho about y = pi/2 and
+    y = 3 pi/2, plus a transverse perturbation delta sin(x); y is taken
+    modulo 2 pi."""
+    y = np.mod(y, 2.0 * np.pi)
+    qx = np.where(y <= np.pi, np.tanh((y - 0.5 * np.pi) / rho), np.tanh((1.5 * np.pi - y) / rho))
+    return np.stack([qx, delta * np.sin(x)], axis=-1)
+
+
+def steady_vortex_velocity(x, y):
+    """A steady Euler solution on the 2 pi-periodic square (the Taylor-Green
+    cell pattern without decay): u = (sin x cos y, -cos x sin y)."""
+    return np.stack([np.sin(x) * np.cos(y), -np.cos(x) * np.sin(y)], axis=-1)
+
+
+def steady_vortex_pressure(x, y):
+    """Pressure of steady_vortex_velocity, (cos 2x + cos 2y)/4 (mean zero)."""
+    return 0.25 * (np.cos(2.0 * x) + np.cos(2.0 * y))
 
 
 def stream_function_params(seed: int, nterms: int = 4):

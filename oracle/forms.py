@@ -81,9 +81,8 @@ class Discretisation:
         self.ft = t
         self.mu = legendre01(k, t)          # trace basis (nqf, nf)
         self.nu_bdm = legendre01(k + 1, t)  # BDM facet moments (nqf, k+2)
-        X = mesh.facet_points(t)            # (nF, nqf, 2)
         Fcf = mesh.cell_facets             # (nc, 3)
-        self.cf_x = X[Fcf]                  # (nc, 3, nqf, 2)
+        self.cf_x = mesh.cell_facet_points(t)  # (nc, 3, nqf, 2), each cell's own geometry
         self.cf_w = wt[None, None, :] * mesh.hF[Fcf][:, :, None]
         Kidx = np.repeat(np.arange(nc), 3 * t.size).reshape(nc, 3, t.size)
         ref = mesh.to_reference(Kidx, self.cf_x)  # (nc, 3, nqf, 2)

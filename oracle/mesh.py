@@ -6,6 +6,12 @@ Conventions that are part of the documented data layout:
   by the cell array, is x = v0 + (v1 - v0) xi + (v2 - v0) eta;
 * facets are the distinct vertex pairs (lo, hi), lo < hi, numbered in
   lexicographic order of (lo, hi); the trace parameter t runs from lo to hi.
+* periodic meshes: an optional vertex_rep array names, for every vertex,
+  the vertex it is identified with (itself if none).  Topology (facets,
+  neighbours, the facet parameter direction) uses the classes of identified
+  vertices, numbered by the rank of their representative; geometry uses
+  every cell's own vertex coordinates.  Without vertex_rep the classes are
+  the vertices themselves.
 
 The notation follows Section "Notation": for an interior facet the cell with
 the smaller id is K+ and the other K-; h_F is the facet length.
@@ -19,7 +25,7 @@ LOCAL_EDGES = ((1, 2), (0, 2), (0, 1))
 
 
 class Mesh:
-    def __init__(self, coords, cells):
+    def __init__(self, coords, cells, vertex_rep=None):
         coords = np.asarray(coords, dtype=np.float64)
         cells = np.asarray(cells, dtype=np.int64)
         if coords.ndim != 2 or coords.shape[1] != 2 or cells.ndim != 2 or cells.shape[1] != 3:
@@ -28,12 +34,25 @@ class Mesh:
         self.cells = cells
         self.ncells = cells.shape[0]
         nc = self.ncells
+        nv = coords.shape[0]
+        if vertex_rep is None:
+            vclass = np.arange(nv, dtype=np.int64)
+        else:
+            rep = np.asarray(vertex_rep, dtype=np.int64)
+            if rep.shape != (nv,) or rep.min() < 0 or rep.max() >= nv:
+                raise ValueError("vertex_rep must map every vertex to a vertex")
+            _, vclass = np.unique(rep, return_inverse=True)
+        self.periodic = vertex_rep is not None
+        self.vclass = vclass
+        self.tcells = tc = vclass[cells]  # cells in topological vertex ids
 
         # --- facets ---------------------------------------------------------
         pairs = np.empty((nc, 3, 2), dtype=np.int64)
         for f, (a, b) in enumerate(LOCAL_EDGES):
-            pairs[:, f, 0] = np.minimum(cells[:, a], cells[:, b])
-            pairs[:, f, 1] = np.maximum(cells[:, a], cells[:, b])
+            if np.any(tc[:, a] == tc[:, b]):
+                raise ValueError("a cell edge joins identified vertices")
+            pairs[:, f, 0] = np.minimum(tc[:, a], tc[:, b])
+            pairs[:, f, 1] = np.maximum(tc[:, a], tc[:, b])
         flat = pairs.reshape(-1, 2)
         facets, inverse = np.unique(flat, axis=0, return_inverse=True)
         self.facets = facets  # (nf, 2) = (lo, hi)
@@ -83,15 +102,31 @@ class Mesh:
             n[out < 0] *= -1.0
             self.normal[:, f] = n
             self.hF_cell[:, f] = ln
-        self.hF = np.linalg.norm(coords[facets[:, 1]] - coords[facets[:, 0]], axis=1)
+        # facet length as seen from K+; both sides of an identified facet must agree
+        self.hF = self.hF_cell[fc[:, 0], fc[:, 1]]
+        Ii = np.nonzero(self.interior)[0]
+        if np.any(np.abs(self.hF_cell[fc[Ii, 2], fc[Ii, 3]] - self.hF[Ii]) > 1e-12 * self.hF[Ii]):
+            raise ValueError("the two sides of a facet differ in length")
 
     def to_reference(self, K, x):
         """Reference coordinates of physical points x (..., 2) in cells K (broadcast)."""
         d = x - self.v0[K]
         return np.einsum("...ad,...d->...a", self.invJ[K], d)
 
+    def cell_facet_points(self, t):
+        """Physical points x(t) on every local facet of every cell, t running
+        from the facet's lo to its hi vertex; shape (nc, 3, nt, 2)."""
+        t = np.asarray(t, dtype=np.float64)
+        out = np.empty((self.ncells, 3, t.size, 2))
+        for f, (a, b) in enumerate(LOCAL_EDGES):
+            va, vb = self.coords[self.cells[:, a]], self.coords[self.cells[:, b]]
+            fwd = (self.tcells[:, a] < self.tcells[:, b])[:, None]
+            xlo, xhi = np.where(fwd, va, vb), np.where(fwd, vb, va)
+            out[:, f] = xlo[:, None, :] + t[None, :, None] * (xhi - xlo)[:, None, :]
+        return out
+
     def facet_points(self, t):
-        """Physical points x(t) on every facet, t from lo to hi; shape (nf, nt, 2)."""
-        xlo = self.coords[self.facets[:, 0]]
-        xhi = self.coords[self.facets[:, 1]]
-        return xlo[:, None, :] + np.asarray(t)[None, :, None] * (xhi - xlo)[:, None, :]
+        """Physical points x(t) on every facet as seen from K+, t from lo to hi;
+        shape (nf, nt, 2)."""
+        fc = self.facet_cells
+        return self.cell_facet_points(t)[fc[:, 0], fc[:, 1]]
