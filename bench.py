@@ -199,6 +199,47 @@ def latency_run(hdg, hi, torch, ncalls: int = 100):
             "advance_one_step_ms": adv, "solve_trace_ms": tr}
 
 
+def shear_layer_run(hdg, hi, torch, nsteps: int = 5):
+    """The paper's double-layer shear flow (Section "Double-layer shear flow")
+    at its largest tabulated size: [0, 2 pi]^2 periodic, 64 x 64 squares,
+    k = 3, SSP3(4,3,3), dt = 0.04, n_R = 2, the paper's tolerances (trace
+    1e-12, Step I 1e-10), FP64; one warm-up step, then nsteps timed steps
+    with the state resident on the device."""
+    import numpy as np
+    n, k, dt = 64, 3, 0.04
+    X, C, rep = hi.periodic_square_mesh(n)
+    ctx = hdg.Context(X, C, vertex_rep=rep, degree=k, imex="ssp3_433", n_richardson=2, rtol_trace=1e-12,
+                      rtol_velocity=1e-10)
+    xy = ctx.cell_points()
+    ctx.set_velocity_from_points(hi.shear_layer_velocity(xy[..., 0], xy[..., 1]))
+    ctx.advance(dt, 1)
+    torch.cuda.synchronize()
+    i0 = ctx.info()
+    t0 = time.perf_counter()
+    ctx.advance(dt, nsteps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    i1 = ctx.info()
+    Q = ctx.get_state()[0].cpu().numpy().reshape(ctx.ncells, -1)
+    det = (L_SHEAR / n) ** 2  # det J of every cell of the uniform mesh; the velocity mass matrix is det J times I
+    ke = 0.5 * det * float(np.sum(Q * Q))
+    nT = ctx.nT
+    ctx.close()
+    stages = 3  # implicit stages of SSP3(4,3,3)
+    its = {key: i1[key] - i0[key] for key in ("pcg_iterations_total", "trace_solves", "velocity_iterations_total",
+                                              "velocity_solves")}
+    log(f"shear layer (64x64 periodic, k=3, SSP3(4,3,3)): {1e3 * el / nsteps:.1f} ms/step over {nsteps} steps; {its}")
+    return {"workload": "periodic_2pi_64x64_k3_ssp3_433 (8192 cells, 49152 trace DOFs), dt=0.04, n_R=2, FP64",
+            "ms_per_step": 1e3 * el / nsteps, "steps": nsteps, "value": nT * stages * nsteps / el,
+            "unit": "trace-DOF-stages/s", "kinetic_energy_after": ke, "iterations": its,
+            "paper_s_per_step": 52.16,
+            "paper_note": "the paper's shear-layer table, SSP3(4,3,3), k=3, 64x64: 52.16 s per step on its "
+                          "own (CPU) hardware; context, not a target"}
+
+
+L_SHEAR = 2.0 * 3.141592653589793
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,6 +251,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with events")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision run")
     ap.add_argument("--no-latency", action="store_true", help="skip the per-call latency distributions")
+    ap.add_argument("--no-shear", action="store_true", help="skip the periodic shear-layer run")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -306,6 +348,9 @@ def main():
     latency = None
     if not args.no_latency:
         latency = latency_run(hdg, hi, torch)
+    shear = None
+    if not args.no_shear:
+        shear = shear_layer_run(hdg, hi, torch)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -332,6 +377,7 @@ def main():
         "cpu_baseline": cpu,
         "mixed": mixed,
         "latency": latency,
+        "shear_layer": shear,
     }
     if mixed is not None:
         mixed["speedup_vs_fp64"] = round(mixed["value"] / value, 3)

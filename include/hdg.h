@@ -5,7 +5,8 @@
  * hybridised DG discretisation and IMEX Runge-Kutta time stepping of
  * Mueller, "A Higher-order Hybridisable Discontinuous Galerkin IMEX method
  * for the incompressible Euler equations" (arXiv:2410.09790):
- *   - problem: eqs. (incompressible_euler_momentum/constraint), n.Q = 0 walls;
+ *   - problem: eqs. (incompressible_euler_momentum/constraint), n.Q = 0 on
+ *     walls, or periodic identification (Section "Double-layer shear flow");
  *   - spaces: V_Q = [DG_{k+1}]^2, V_p = DG_k with int p = 0, V_trace = P_k on
  *     the facets (Section "Discontinuous Galerkin spaces", "Hybridisation");
  *   - one time step: Algorithm 1, each implicit stage solved by Algorithm 2
@@ -14,7 +15,8 @@
  *     the pressure reconstruction: static condensation onto the trace,
  *     multigrid-preconditioned CG on the trace system, back-substitution
  *     (Section "Solvers and preconditioners").
- * Only two-dimensional triangle meshes are supported; the forcing f is zero.
+ * Only two-dimensional triangle meshes are supported; the forcing f is zero
+ * unless hdg_set_forcing supplies one.
  *
  * Data layout (all state and right-hand-side arrays):
  *   Q[cell][c*ns + s]  velocity, component c in {x, y}, ns = (k+2)(k+3)/2;
@@ -28,7 +30,9 @@
  *     degree i+j, then by i ascending.
  *   Facets: the distinct vertex pairs (lo, hi), lo < hi, numbered in
  *   lexicographic order; facet basis mu_m(t) = sqrt(2m+1) P_m(2t-1) with t
- *   running from vertex lo (t=0) to vertex hi (t=1).
+ *   running from vertex lo (t=0) to vertex hi (t=1).  On a periodic mesh
+ *   (hdg_create_periodic) lo and hi are topological vertex ids: the classes
+ *   of identified vertices, numbered by the rank of their representative.
  *   A dual vector (a right-hand side F_w(w) = sum_i F_i w_i) uses the same
  *   index as the unknown it tests.
  *
@@ -63,10 +67,12 @@ typedef enum {
 } hdg_status;
 
 /* IMEX schemes (Appendix A): IMEX Euler as printed; ARS(2,2,2) and ARS(2,3,3)
- * of Ascher, Ruuth and Spiteri (cited, not printed); SSP2(3,3,2) and
- * SSP3(4,3,3) as printed, whose implicit first stage is placed after an
- * explicit stage 0 (Q_0 = Q^n) to fit the paper's form a^im_{i,0} = 0:
- * s = 4 and 5, i.e. 3 and 4 implicit stages per step. */
+ * of Ascher, Ruuth and Spiteri (cited, not printed); SSP3(4,3,3) as printed,
+ * read through Algorithm 1 (stage 0 = Q^n, the unused first implicit column
+ * dropped: s = 4, 3 implicit stages per step); SSP2(3,3,2) as printed with
+ * an explicit stage 0 in front of its implicit first stage (s = 4, 3
+ * implicit stages), since dropping its first implicit column would lose the
+ * weight b^im_0 = 1/3. */
 typedef enum {
   HDG_IMEX_EULER = 0,
   HDG_ARS222 = 1,
@@ -102,7 +108,10 @@ typedef struct {
   int imex;              /* hdg_imex_scheme */
   int n_richardson;      /* n_R of Algorithm 2 */
   int trace_solver;      /* hdg_trace_solver */
-  double rtol_trace;     /* PCG: ||g - S lam||_2 <= rtol ||g||_2 */
+  double rtol_trace;     /* PCG: ||g - S lam||_2 <= rtol ||g||_2 (the residual's component along
+                            the constant trace left out); a residual that stalls within 100 rtol
+                            (the round-off floor of an ill-conditioned S) also ends the solve,
+                            counted as pcg_floor_stops in hdg_get_info */
   double rtol_velocity;  /* Step I: same criterion on the mass-scaled system */
   int max_it_trace;
   int max_it_velocity;
@@ -126,6 +135,19 @@ void hdg_default_params(hdg_params* p);
  * UNSUPPORTED (degree), OUT_OF_MEMORY, DEVICE. */
 int hdg_create(int64_t nv, const double* coords, int64_t nc, const int32_t* cells,
                const hdg_params* prm, void* stream, hdg_ctx** out);
+
+/* Create a context on a periodic mesh (Section "Double-layer shear flow":
+ * periodic boundary conditions in both directions).  vertex_rep: host [nv],
+ * the vertex each vertex is identified with (itself if none); vertices with
+ * the same representative are one topological vertex, so the cells on both
+ * sides of a period share facets and every facet is interior.  Geometry uses
+ * each cell's own coordinates, so a cell may reach across the period.  The
+ * two placements of an identified facet must have the same length (else
+ * INVALID_ARG), and no cell edge may join two identified vertices (a
+ * periodic split-square mesh needs at least 3 x 3 squares).  vertex_rep =
+ * NULL gives hdg_create.  Other arguments and errors as for hdg_create. */
+int hdg_create_periodic(int64_t nv, const double* coords, int64_t nc, const int32_t* cells,
+                        const int32_t* vertex_rep, const hdg_params* prm, void* stream, hdg_ctx** out);
 void hdg_destroy(hdg_ctx* ctx);
 
 /* Last error message of ctx, or of the last failed hdg_create in this

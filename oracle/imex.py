@@ -2,11 +2,16 @@
 
 * Butcher tableaux in the paper's form (Appendix A): s stages, implicit
   tableau with a zero first column (a^im_{i,0} = b^im_0 = 0).  IMEX Euler,
-  SSP2(3,3,2) and SSP3(4,3,3) are printed in the paper (the SSP ones with an
-  implicit first stage, placed after an explicit stage 0).  ARS(2,2,2) and
-  ARS(2,3,3) are the Ascher-Ruuth-Spiteri schemes the paper cites; their
-  coefficients are not printed there.  All are pinned by the order conditions
-  in the tests.
+  SSP2(3,3,2) and SSP3(4,3,3) are printed in the paper; the SSP ones have
+  nonzero entries in the first implicit column, which Algorithm 1 never
+  uses (Q_0 = Q^n, implicit sums from j = 1).  SSP3(4,3,3) is taken as
+  printed through Algorithm 1 (its dropped first column carries b^im_0 = 0;
+  3 implicit stages, the solve counts of the paper's timing table);
+  SSP2(3,3,2) would lose the implicit weight b^im_0 = 1/3 that way, so its
+  printed stages all become implicit stages after an explicit stage 0.
+  ARS(2,2,2) and ARS(2,3,3) are the Ascher-Ruuth-Spiteri schemes the paper
+  cites; their coefficients are not printed there.  All are pinned by order
+  conditions in the tests.
 * ``stage_residual`` / ``final_residual``: eqs. (imex_residual) and
   (final_residual), the recursion that replaces f_im(Q_j) by
   (M Q_j - r_j) / a_jj.
@@ -92,13 +97,17 @@ def ssp2_332() -> Tableau:
 
 
 def ssp3_433() -> Tableau:
-    """SSP3(4,3,3) as printed (Appendix A)."""
+    """SSP3(4,3,3) as printed (Appendix A), read through Algorithm 1: s = 4,
+    stage 0 is Q^n, and the printed first implicit column (alpha, -alpha, 0,
+    beta), which Algorithm 1 does not use, is left out (its weight b^im_0 is
+    zero).  Stages 1..3 are implicit with diagonal alpha."""
     a, b, e = 0.24169426078821, 0.06042356519705, 0.12915286960590
     d = 0.5 - a - b - e
     Ae = np.array([[0.0, 0.0, 0.0, 0.0], [0.0, 0.0, 0.0, 0.0], [0.0, 1.0, 0.0, 0.0], [0.0, 0.25, 0.25, 0.0]])
     Ai = np.array([[a, 0.0, 0.0, 0.0], [-a, a, 0.0, 0.0], [0.0, 1.0 - a, a, 0.0], [b, e, d, a]])
     w = np.array([0.0, 1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0])
-    return _pad_explicit_stage0("ssp3_433", Ae, w, Ai, w)
+    Ai[:, 0] = 0.0  # unused by Algorithm 1
+    return Tableau("ssp3_433", Ae, w, Ai, w)
 
 
 TABLEAUX = {"imex_euler": imex_euler, "ars222": ars222, "ars233": ars233, "ssp2_332": ssp2_332,

@@ -65,6 +65,7 @@ inline void facet_point(int f, double s, double& xi, double& eta) {
 // ------------------------------------------------------------------- mesh
 struct HostMesh {
   int64_t nv = 0, nc = 0, nF = 0;
+  int64_t nvt = 0;                  // topological vertices (classes of identified vertices)
   std::vector<double> coords;       // [nv][2]
   std::vector<int32_t> cells;       // [nc][3]
   std::vector<int32_t> facet_lo, facet_hi;
@@ -80,7 +81,8 @@ enum GeoField { G_DET = 0, G_IJ00, G_IJ01, G_IJ10, G_IJ11, G_NX0, G_NY0, G_NX1, 
                 G_H0, G_H1, G_H2, G_J00, G_J01, G_J10, G_J11, kGeo };
 
 // returns empty string on success, else an error message
-std::string build_mesh(int64_t nv, const double* coords, int64_t nc, const int32_t* cells, HostMesh& m);
+std::string build_mesh(int64_t nv, const double* coords, int64_t nc, const int32_t* cells,
+                       const int32_t* vertex_rep, HostMesh& m);
 
 // ------------------------------------------------------------ AMG (host)
 struct Csr {

@@ -137,8 +137,10 @@ void launch_fill(hipStream_t st, long n, double v, double* y);
 void launch_project_const(hipStream_t st, int nF, int nf, const double* sum, double* g);
 
 // Krylov helpers with device scalars
-void launch_pcg_update(hipStream_t st, long n, const double* rz, const double* pq, const double* p, const double* q,
-                       double* x, double* r, double* part_rr);
+void launch_pcg_update(hipStream_t st, long n, int nf, const double* rz, const double* pq, const double* p,
+                       const double* q, double* x, double* r, double* part_rr);
+// sum(part[0..n)) - sum(part[n..2n))^2 / nnull  (residual norm^2 without its null-vector part)
+void launch_finish_proj(hipStream_t st, const double* part, int nparts, double nnull, double* out);
 void launch_pcg_direction(hipStream_t st, long n, const double* rz_new, const double* rz_old, const double* z, double* p);
 void launch_dot2(hipStream_t st, long n, const double* a, const double* b, const double* c, double* part2);
 void launch_finish2(hipStream_t st, const double* part2, double* out2);

@@ -1389,21 +1389,44 @@ __global__ void k_project_const(int nF, int nf, const double* __restrict__ sum, 
   if (F < nF) g[(long)F * nf] -= sum[0] / (double)nF;
 }
 
-__global__ void __launch_bounds__(kBlock) k_pcg_update(long n, const double* __restrict__ rz, const double* __restrict__ pq,
-                                                       const double* __restrict__ p, const double* __restrict__ q,
-                                                       double* __restrict__ x, double* __restrict__ r,
-                                                       double* __restrict__ part) {
+// Also returns, per block, the partial sums of the residual's coefficients
+// along the trace null vector (coefficient 0 of every facet, stride nf):
+// round-off of S along that vector accumulates there, and the convergence
+// test leaves it out.
+__global__ void __launch_bounds__(kBlock) k_pcg_update(long n, int nf, const double* __restrict__ rz,
+                                                       const double* __restrict__ pq, const double* __restrict__ p,
+                                                       const double* __restrict__ q, double* __restrict__ x,
+                                                       double* __restrict__ r, double* __restrict__ part) {
   // a vanished p.q (converged to an exact zero residual) leaves x and r as they are
   const double alpha = pq[0] != 0.0 ? rz[0] / pq[0] : 0.0;
-  double v = 0.0;
+  double v = 0.0, s = 0.0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     x[i] += alpha * p[i];
     const double ri = r[i] - alpha * q[i];
     r[i] = ri;
     v += ri * ri;
+    if (i % nf == 0) s += ri;
   }
   v = block_sum(v);
-  if (threadIdx.x == 0) part[blockIdx.x] = v;
+  s = block_sum(s);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = v;
+    part[gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// out = sum(part[0..np)) - sum(part[np..2np))^2 / nnull: the squared norm of
+// the residual with its null-vector component removed (|v|^2 = nnull)
+__global__ void __launch_bounds__(kBlock) k_finish_proj(const double* __restrict__ part, int np, double nnull,
+                                                        double* __restrict__ out) {
+  double v = 0.0, s = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    v += part[i];
+    s += part[np + i];
+  }
+  v = block_sum(v);
+  s = block_sum(s);
+  if (threadIdx.x == 0) out[0] = fmax(v - s * s / nnull, 0.0);
 }
 
 __global__ void k_pcg_direction(long n, const double* __restrict__ rzn, const double* __restrict__ rzo,
@@ -1657,9 +1680,12 @@ void launch_fill(hipStream_t st, long n, double v, double* y) { k_fill<<<nblocks
 void launch_project_const(hipStream_t st, int nF, int nf, const double* sum, double* g) {
   k_project_const<<<nblocks(nF), kBlock, 0, st>>>(nF, nf, sum, g);
 }
-void launch_pcg_update(hipStream_t st, long n, const double* rz, const double* pq, const double* p, const double* q,
-                       double* x, double* r, double* part_rr) {
-  k_pcg_update<<<kRedBlocks, kBlock, 0, st>>>(n, rz, pq, p, q, x, r, part_rr);
+void launch_pcg_update(hipStream_t st, long n, int nf, const double* rz, const double* pq, const double* p,
+                       const double* q, double* x, double* r, double* part_rr) {
+  k_pcg_update<<<kRedBlocks, kBlock, 0, st>>>(n, nf, rz, pq, p, q, x, r, part_rr);
+}
+void launch_finish_proj(hipStream_t st, const double* part, int nparts, double nnull, double* out) {
+  k_finish_proj<<<1, kBlock, 0, st>>>(part, nparts, nnull, out);
 }
 void launch_pcg_direction(hipStream_t st, long n, const double* rzn, const double* rzo, const double* z, double* p) {
   k_pcg_direction<<<nblocks(n), kBlock, 0, st>>>(n, rzn, rzo, z, p);

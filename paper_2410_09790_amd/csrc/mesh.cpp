@@ -3,6 +3,9 @@
 //
 // Facet numbering (part of the data layout): distinct vertex pairs (lo, hi),
 // lo < hi, in lexicographic order; the trace parameter runs from lo to hi.
+// On a periodic mesh the pairs are taken over classes of identified vertices
+// (vertices with the same representative), numbered by the rank of the
+// representative; geometry always uses each cell's own vertex coordinates.
 // Local facet f of a cell is the edge opposite local vertex f, with local
 // parameter running from local vertex FA[f] to FB[f].
 //
@@ -21,7 +24,8 @@
 
 namespace hdg {
 
-std::string build_mesh(int64_t nv, const double* coords, int64_t nc, const int32_t* cells, HostMesh& m) {
+std::string build_mesh(int64_t nv, const double* coords, int64_t nc, const int32_t* cells,
+                       const int32_t* vertex_rep, HostMesh& m) {
   if (nv < 3 || nc < 1 || !coords || !cells) return "empty mesh";
   if (nv > INT32_MAX / 2 || nc > INT32_MAX / 4) return "mesh too large for 32-bit indices";
   m.nv = nv;
@@ -30,15 +34,36 @@ std::string build_mesh(int64_t nv, const double* coords, int64_t nc, const int32
   m.cells.assign(cells, cells + 3 * nc);
   for (int64_t i = 0; i < 3 * nc; ++i)
     if (cells[i] < 0 || cells[i] >= nv) return "cell vertex index out of range";
+  // topological vertex ids: rank of each vertex's representative
+  std::vector<int32_t> topo(nv);
+  if (vertex_rep) {
+    std::vector<int32_t> rank(nv, 0);
+    for (int64_t v = 0; v < nv; ++v) {
+      if (vertex_rep[v] < 0 || vertex_rep[v] >= nv) return "vertex_rep entry out of range";
+      rank[vertex_rep[v]] = 1;
+    }
+    int32_t r = 0;
+    for (int64_t v = 0; v < nv; ++v) {
+      const int32_t used = rank[v];
+      rank[v] = r;
+      r += used;
+    }
+    for (int64_t v = 0; v < nv; ++v) topo[v] = rank[vertex_rep[v]];
+    m.nvt = r;
+  } else {
+    std::iota(topo.begin(), topo.end(), 0);
+    m.nvt = nv;
+  }
+  const int64_t nvt = m.nvt;
   struct Ent { int64_t key; int32_t cell, f; };
   std::vector<Ent> ents(3 * nc);
   m.cf_flip.assign(3 * nc, 0);
   for (int64_t K = 0; K < nc; ++K)
     for (int f = 0; f < 3; ++f) {
-      int32_t a = cells[3 * K + FA[f]], b = cells[3 * K + FB[f]];
-      if (a == b) return "degenerate cell";
+      int32_t a = topo[cells[3 * K + FA[f]]], b = topo[cells[3 * K + FB[f]]];
+      if (a == b) return vertex_rep ? "a cell edge joins identified vertices" : "degenerate cell";
       int64_t lo = std::min(a, b), hi = std::max(a, b);
-      ents[3 * K + f] = {lo * nv + hi, (int32_t)K, f};
+      ents[3 * K + f] = {lo * nvt + hi, (int32_t)K, f};
       m.cf_flip[f * nc + K] = a > b ? 1 : 0;
     }
   std::sort(ents.begin(), ents.end(), [](const Ent& x, const Ent& y) {
@@ -54,8 +79,8 @@ std::string build_mesh(int64_t nv, const double* coords, int64_t nc, const int32
     while (j < ents.size() && ents[j].key == ents[i].key) ++j;
     if (j - i > 2) return "non-manifold facet";
     int32_t F = (int32_t)m.facet_lo.size();
-    m.facet_lo.push_back((int32_t)(ents[i].key / nv));
-    m.facet_hi.push_back((int32_t)(ents[i].key % nv));
+    m.facet_lo.push_back((int32_t)(ents[i].key / nvt));
+    m.facet_hi.push_back((int32_t)(ents[i].key % nvt));
     fcp.push_back(ents[i].cell); ffp.push_back(ents[i].f);
     m.cf_facet[ents[i].f * nc + ents[i].cell] = F;
     if (j - i == 2) {
@@ -94,6 +119,13 @@ std::string build_mesh(int64_t nv, const double* coords, int64_t nc, const int32
       if (nx * (x[a] - x[f]) + ny * (y[a] - y[f]) < 0) { nx = -nx; ny = -ny; }
       G(G_NX0 + 2 * f, K) = nx; G(G_NY0 + 2 * f, K) = ny; G(G_H0 + f, K) = len;
     }
+  }
+  // both sides of a facet (two placements of it on a periodic mesh) must match
+  for (int64_t F = 0; F < m.nF; ++F) {
+    const int32_t Km = m.fc_cell[m.nF + F];
+    if (Km < 0) continue;
+    const double hp = G(G_H0 + m.fc_f[F], m.fc_cell[F]), hm = G(G_H0 + m.fc_f[m.nF + F], Km);
+    if (std::fabs(hp - hm) > 1e-12 * hp) return "the two sides of facet " + std::to_string(F) + " differ in length";
   }
   return "";
 }

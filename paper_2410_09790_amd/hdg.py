@@ -23,7 +23,7 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NOT_CO
           6: "UNSUPPORTED"}
 
 EXPORTS = [
-    "hdg_default_params", "hdg_create", "hdg_destroy", "hdg_last_error", "hdg_sizes", "hdg_cell_points",
+    "hdg_default_params", "hdg_create", "hdg_create_periodic", "hdg_destroy", "hdg_last_error", "hdg_sizes", "hdg_cell_points",
     "hdg_facet_points", "hdg_set_forcing", "hdg_set_time", "hdg_get_time", "hdg_set_velocity_from_points", "hdg_set_state", "hdg_get_state", "hdg_advance", "hdg_solve_trace",
     "hdg_trace_matvec", "hdg_bdm_project", "hdg_weak_divergence", "hdg_momentum_residual",
     "hdg_tentative_velocity", "hdg_reconstruct_pressure", "hdg_profile", "hdg_get_info",
@@ -71,6 +71,7 @@ def load_library(path: str = LIB_PATH):
     sig = {
         "hdg_default_params": (None, [ctypes.POINTER(Params)]),
         "hdg_create": (I, [I64, P, I64, P, ctypes.POINTER(Params), P, ctypes.POINTER(P)]),
+        "hdg_create_periodic": (I, [I64, P, I64, P, P, ctypes.POINTER(Params), P, ctypes.POINTER(P)]),
         "hdg_destroy": (None, [P]),
         "hdg_last_error": (ctypes.c_char_p, [P]),
         "hdg_sizes": (I, [P, P, I]),
@@ -130,20 +131,24 @@ def _ptr(t):
 class Context:
     """One HDG-IMEX instance on the current CUDA (HIP) device."""
 
-    def __init__(self, coords, cells, stream=None, **params):
+    def __init__(self, coords, cells, stream=None, vertex_rep=None, **params):
         import torch
         self._lib = load_library()
         coords = np.ascontiguousarray(coords, dtype=np.float64)
         cells = np.ascontiguousarray(cells, dtype=np.int32)
+        rep = None if vertex_rep is None else np.ascontiguousarray(vertex_rep, dtype=np.int32)
+        if rep is not None and rep.shape != (coords.shape[0],):
+            raise ValueError("vertex_rep needs one entry per vertex")
         self.params = default_params(**params)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
         self.device = stream.device
         h = ctypes.c_void_p()
-        st = self._lib.hdg_create(coords.shape[0], coords.ctypes.data_as(ctypes.c_void_p), cells.shape[0],
-                                  cells.ctypes.data_as(ctypes.c_void_p), ctypes.byref(self.params),
-                                  ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        st = self._lib.hdg_create_periodic(
+            coords.shape[0], coords.ctypes.data_as(ctypes.c_void_p), cells.shape[0],
+            cells.ctypes.data_as(ctypes.c_void_p), None if rep is None else rep.ctypes.data_as(ctypes.c_void_p),
+            ctypes.byref(self.params), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
         if st != 0:
             raise HDGError(st, self._lib.hdg_last_error(None).decode())
         self._h = h

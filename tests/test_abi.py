@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -112,3 +113,40 @@ def test_params_struct_layout_matches_the_header(tmp_path):
     out = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
     assert out[0] == ctypes.sizeof(hdg.Params)
     assert out[1:] == [getattr(hdg.Params, n).offset for n in names]
+
+
+def _create_periodic(lib, X, C, rep):
+    from paper_2410_09790_amd import hdg
+    import numpy as np
+    p = hdg.default_params()
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    C = np.ascontiguousarray(C, dtype=np.int32)
+    rep = np.ascontiguousarray(rep, dtype=np.int32)
+    h = ctypes.c_void_p()
+    st = lib.hdg_create_periodic(X.shape[0], X.ctypes.data_as(ctypes.c_void_p), C.shape[0],
+                                 C.ctypes.data_as(ctypes.c_void_p), rep.ctypes.data_as(ctypes.c_void_p),
+                                 ctypes.byref(p), None, ctypes.byref(h))
+    return st, h
+
+
+def test_bad_periodic_meshes_are_rejected_on_the_host(lib_path):
+    """Mesh errors are found before any device work (no GPU needed)."""
+    import hdg_inputs as hi
+    from paper_2410_09790_amd import hdg
+    lib = hdg.load_library()
+    X, C, rep = hi.periodic_square_mesh(3)
+    bad = rep.copy()
+    bad[5] = X.shape[0]  # out of range
+    st, h = _create_periodic(lib, X, C, bad)
+    assert st == 1 and not h.value and b"vertex_rep" in lib.hdg_last_error(None)
+    # 2 x 2 squares: two edges of a row become one facet of four cells
+    X2, C2 = hi.unit_square_mesh(2)
+    i, j = np.meshgrid(np.arange(3), np.arange(3), indexing="xy")
+    rep2 = ((j.ravel() % 2) * 3 + (i.ravel() % 2)).astype(np.int32)
+    st, h = _create_periodic(lib, X2, C2, rep2)
+    assert st == 1 and not h.value and b"non-manifold" in lib.hdg_last_error(None)
+    # a right-edge vertex moved without its left copy: identified facets differ in length
+    X3 = X.copy()
+    X3[2 * 4 - 1, 0] += 0.1  # vertex (3, 1)
+    st, h = _create_periodic(lib, X3, C, rep)
+    assert st == 1 and not h.value and b"differ in length" in lib.hdg_last_error(None)

@@ -3,8 +3,9 @@
 
 * one forced configuration against the oracle, element by element;
 * the convergence study of Section "Convergence" on the GPU: T = 1, n_t = n
-  time steps on the n x n grid (Table "stepsizes"), IMEX Euler with k = 1 and
-  SSP2(3,3,2) with k = 2 (pairings of the paper's experiments), n_R = 2; the
+  time steps on the n x n grid (Table "stepsizes"), IMEX Euler with k = 1,
+  SSP2(3,3,2) with k = 2 and SSP3(4,3,3) with k = 3 (pairings of the
+  paper's experiments), n_R = 2; the
   velocity and pressure errors must fall at least at the rate h^k the paper
   reports.
 """
@@ -59,11 +60,8 @@ def _errors(d, Q, p, t):
     return eq, ep
 
 
-# SSP3(4,3,3) with k = 3 is left out: in the reading of its printed tableau
-# used here (an explicit stage 0 in front) the oracle and the GPU agree, but
-# the Taylor-Green error does not fall under refinement with n_R = 2 (nor 4),
-# unlike the paper's figure, so that reading is probably not the paper's.
-@pytest.mark.parametrize("scheme,k,ns", [("imex_euler", 1, (4, 8, 16, 32)), ("ssp2_332", 2, (4, 8, 16))])
+@pytest.mark.parametrize("scheme,k,ns", [("imex_euler", 1, (4, 8, 16, 32)), ("ssp2_332", 2, (4, 8, 16)),
+                                         ("ssp3_433", 3, (4, 8, 16))])
 def test_convergence(scheme, k, ns):
     torch_or_skip()
     T = 1.0
