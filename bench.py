@@ -240,6 +240,135 @@ def shear_layer_run(hdg, hi, torch, nsteps: int = 5):
 L_SHEAR = 2.0 * 3.141592653589793
 
 
+def batched_run(hdg, hi, torch, ninst: int = 4):
+    """A bounded sample of the batched workload: instances j = 0..ninst-1 with
+    n = integers(32, 257), k = integers(1, 5) drawn from default_rng(j) and
+    the seed-j stream-function data; ARS(2,2,2), dt = 1e-3, n_R = 3, MG-PCG,
+    the paper's tolerances.  One untimed warm-up step (operator builds, graph
+    capture), then one timed step of every instance one after another (FP64),
+    one timed step of all of them as one hdg_batch on distinct streams (FP64),
+    and the same with FP32 cell-matrix storage (Step I rtol 1e-5).  The mixed
+    states after two steps are compared with the FP64 states after two."""
+    import numpy as np
+    specs = []
+    for j in range(ninst):
+        n, k, par = hi.batched_instance(j)
+        specs.append((par, n, k))
+
+    def make(n, k, par, stream, **kw):
+        X, C = hi.unit_square_mesh(n)
+        ctx = hdg.Context(X, C, stream=stream, degree=k, imex="ars222", n_richardson=3, rtol_trace=1e-12, **kw)
+        xy = ctx.cell_points()
+        ctx.set_velocity_from_points(hi.streamfunction_velocity(par, xy[..., 0], xy[..., 1]))
+        return ctx
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    dt = 1e-3
+    streams = [torch.cuda.Stream() for _ in specs]
+    f64 = [make(n, k, par, s, rtol_velocity=1e-10) for (par, n, k), s in zip(specs, streams)]
+    work = sum(c.nT * 2 for c in f64)  # trace DOF-stages of one step of every instance
+    bf = hdg.Batch(f64)
+    bf.advance(dt, 1)  # warm-up
+    t_seq = timed(lambda: [c.advance(dt, 1) for c in f64])
+    ref = [tuple(t.cpu().numpy() for t in c.get_state()) for c in f64]
+    t_bat = timed(lambda: bf.advance(dt, 1))
+    bf.close()
+    for c in f64:
+        c.close()
+    mstreams = [torch.cuda.Stream() for _ in specs]
+    mx = [make(n, k, par, s, rtol_velocity=MIXED_RTOL_VELOCITY, precision="mixed")
+          for (par, n, k), s in zip(specs, mstreams)]
+    bm = hdg.Batch(mx)
+    bm.advance(dt, 1)  # warm-up
+    t_mix = timed(lambda: bm.advance(dt, 1))
+    diff = 0.0
+    for c, (Q, p, lam) in zip(mx, ref):
+        Qm, pm, lm = (t.cpu().numpy() for t in c.get_state())
+        diff = max(diff, float(np.linalg.norm(Qm - Q) / np.linalg.norm(Q)),
+                   float(np.linalg.norm(pm - p) / np.linalg.norm(p)), float(np.linalg.norm(lm - lam) / np.linalg.norm(lam)))
+    bm.close()
+    for c in mx:
+        c.close()
+    out = {"workload": "batched sample: instances " + ", ".join(f"{n}x{n} k={k}" for _, n, k in specs) +
+                       " (draws j = 0..%d of the batched recipe), ARS(2,2,2), dt=1e-3, n_R=3, one step each" % (ninst - 1),
+           "unit": "trace-DOF-stages/s",
+           "fp64_one_at_a_time": work / t_seq, "fp64_batched": work / t_bat, "mixed_batched": work / t_mix,
+           "mixed_max_rel_l2_diff_vs_fp64": diff,
+           "seconds": {"fp64_one_at_a_time": t_seq, "fp64_batched": t_bat, "mixed_batched": t_mix}}
+    log(f"batched: one-at-a-time FP64 {work / t_seq:.4g}, batched FP64 {work / t_bat:.4g}, batched mixed "
+        f"{work / t_mix:.4g} trace-DOF-stages/s; mixed vs FP64 {diff:.2e}")
+    return out
+
+
+def serving_run(hdg, hi, torch, njobs: int = 16, nmax: int = 48, steps: int = 10, rho: float = 0.8):
+    """A bounded sample of the serving workload: jobs j = 0..njobs-1 with
+    n = round(exp(U(ln 16, ln 512))) clipped to nmax and k = integers(1, 5)
+    from default_rng(10000 + j), steps time steps of ARS(2,2,2) each
+    (dt = 1e-3, n_R = 3, Jacobi-PCG below 32 x 32, else MG-PCG; FP64).  Each job
+    first runs alone (one at a time); then the jobs arrive with exponential
+    gaps from default_rng(999) at rate rho / mean alone time and are served
+    by the continuous-batching loop (admission by footprint, 8 slots,
+    budget 32 GiB).  The one-at-a-time FIFO baseline under the same arrivals
+    follows from the alone times."""
+    import threading
+    import numpy as np
+    from paper_2410_09790_amd import serve
+    jobs = []
+    for j in range(njobs):
+        n, k, par = hi.serving_job(j)
+        n = min(n, nmax)
+        X, C = hi.unit_square_mesh(n)
+        solver = "jacobi_pcg" if n < 32 else "mg_pcg"
+        vel = (lambda par_: lambda x, y: hi.streamfunction_velocity(par_, x, y))(par)
+        jobs.append(serve.Job(X, C, vel, 1e-3, steps,
+                              dict(degree=k, imex="ars222", n_richardson=3, trace_solver=solver, rtol_trace=1e-12,
+                                   rtol_velocity=1e-10), name=f"{n}x{n} k={k}"))
+    alone = [serve.run_alone(job) for job in jobs]
+    service = np.array([a[0] for a in alone])
+    arrivals = hi.serving_arrivals(service.mean() / rho, njobs)
+    # FIFO one at a time under the same arrivals
+    fin, fifo_lat = 0.0, []
+    for a_j, s_j in zip(arrivals, service):
+        fin = max(fin, a_j) + s_j
+        fifo_lat.append(fin - a_j)
+    work = sum(a[2] * steps * 2 for a in alone)
+    srv = serve.Server(32 << 30, slots=8)
+
+    def feed():
+        t0 = srv.now()
+        for a_j, job in zip(arrivals, jobs):
+            wait = a_j - (srv.now() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            srv.submit(job)
+
+    th = threading.Thread(target=feed)
+    th.start()
+    th.join()
+    srv.drain(timeout=600)
+    res = srv.results
+    same = all(r.error is None and all(np.array_equal(x, y) for x, y in zip(r.state, a[1])) for r, a in zip(res, alone))
+    lat = [r.latency for r in res]
+    makespan = max(r.end for r in res) - min(r.arrival for r in res)
+    out = {"workload": f"serving sample: {njobs} jobs of the serving recipe, n clipped to {nmax}, {steps} ARS(2,2,2) "
+                       f"steps each, Poisson arrivals at rho={rho} of the mean alone service time",
+           "jobs": [j.name for j in jobs],
+           "served": {"latency_s": serve.percentiles(lat), "throughput": work / makespan, "max_active": srv.max_active,
+                      "max_in_use_bytes": srv.max_in_use},
+           "fifo_one_at_a_time": {"latency_s": serve.percentiles(fifo_lat), "throughput": work / (fin - arrivals[0])},
+           "unit": "trace-DOF-stages/s", "results_identical_to_alone": bool(same)}
+    log(f"serving: p50/p99 latency {out['served']['latency_s']} s served vs {out['fifo_one_at_a_time']['latency_s']} s "
+        f"FIFO; throughput {out['served']['throughput']:.4g} vs {out['fifo_one_at_a_time']['throughput']:.4g}; "
+        f"identical to alone: {same}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,6 +381,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision run")
     ap.add_argument("--no-latency", action="store_true", help="skip the per-call latency distributions")
     ap.add_argument("--no-shear", action="store_true", help="skip the periodic shear-layer run")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-instances sample")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving sample")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -351,6 +482,12 @@ def main():
     shear = None
     if not args.no_shear:
         shear = shear_layer_run(hdg, hi, torch)
+    batched = None
+    if not args.no_batched:
+        batched = batched_run(hdg, hi, torch)
+    serving = None
+    if not args.no_serving:
+        serving = serving_run(hdg, hi, torch)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -378,6 +515,8 @@ def main():
         "mixed": mixed,
         "latency": latency,
         "shear_layer": shear,
+        "batched": batched,
+        "serving": serving,
     }
     if mixed is not None:
         mixed["speedup_vs_fp64"] = round(mixed["value"] / value, 3)

@@ -19,6 +19,8 @@ into n x n squares, each split into two right-angled triangles):
 * Taylor-Green vortex (Section "Taylor Green vortex"): velocity and forcing
   as printed; the pressure is the mean-zero field that satisfies the momentum
   equation (the printed pressure does not).
+* batched and serving workloads (independent instances on one GPU): the
+  draws of batched_instance / serving_job / serving_arrivals below.
 * double-layer shear flow (Section "Double-layer shear flow"): the periodic
   square [0, 2 pi]^2 on the same n x n split-square mesh with the right/top
   vertices identified with the left/bottom ones, and the printed initial
@@ -40,6 +42,10 @@ __all__ = [
     "shear_layer_velocity",
     "steady_vortex_velocity",
     "steady_vortex_pressure",
+    "stream_function_params_from",
+    "batched_instance",
+    "serving_job",
+    "serving_arrivals",
 ]
 
 
@@ -126,7 +132,12 @@ def steady_vortex_pressure(x, y):
 
 def stream_function_params(seed: int, nterms: int = 4):
     """Amplitudes and wavenumbers of the seeded stream function."""
-    rng = np.random.default_rng(seed)
+    return stream_function_params_from(np.random.default_rng(seed), nterms)
+
+
+def stream_function_params_from(rng, nterms: int = 4):
+    """The stream-function terms drawn from an existing generator (in the
+    order amplitude, x wavenumber, y wavenumber per term)."""
     amp = np.empty(nterms)
     kx = np.empty(nterms, dtype=np.int64)
     ky = np.empty(nterms, dtype=np.int64)
@@ -135,6 +146,33 @@ def stream_function_params(seed: int, nterms: int = 4):
         kx[m] = rng.integers(1, 4)
         ky[m] = rng.integers(1, 4)
     return amp, kx, ky
+
+
+def batched_instance(j: int):
+    """Instance j of the batched workload: default_rng(j) draws, in this
+    order, n = integers(32, 257), k = integers(1, 5), then the 4 terms of
+    the stream-function initial data.  Returns (n, k, params)."""
+    rng = np.random.default_rng(j)
+    n = int(rng.integers(32, 257))
+    k = int(rng.integers(1, 5))
+    return n, k, stream_function_params_from(rng)
+
+
+def serving_job(j: int):
+    """Job j of the serving workload: default_rng(10000 + j) draws
+    n = round(exp(U(ln 16, ln 512))), k = integers(1, 5), then the 4
+    stream-function terms.  Returns (n, k, params)."""
+    rng = np.random.default_rng(10000 + j)
+    n = int(round(np.exp(rng.uniform(np.log(16), np.log(512)))))
+    k = int(rng.integers(1, 5))
+    return n, k, stream_function_params_from(rng)
+
+
+def serving_arrivals(mean_gap: float, njobs: int):
+    """Arrival times of the serving workload: 0, then exponential gaps of the
+    given mean from default_rng(999)."""
+    gaps = np.random.default_rng(999).exponential(mean_gap, size=njobs)
+    return np.concatenate([[0.0], np.cumsum(gaps[1:])])
 
 
 def streamfunction_velocity(params, x: np.ndarray, y: np.ndarray):

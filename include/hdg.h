@@ -97,6 +97,7 @@ typedef enum { HDG_PRESSURE_RECONSTRUCT = 0, HDG_PRESSURE_FIRST_ORDER = 1 } hdg_
 typedef enum { HDG_FP64 = 0, HDG_MIXED = 1 } hdg_precision;
 
 typedef struct hdg_ctx hdg_ctx;
+typedef struct hdg_batch hdg_batch;
 
 /* Discretisation and solver parameters.  Paper values (Section "Setup"):
  * tau = alpha = delta_up = 1; the paper uses n_R = 2 Richardson iterations. */
@@ -243,8 +244,39 @@ int hdg_reconstruct_pressure(hdg_ctx* ctx, const double* Q, double* p, double* l
  * enable <= 0 stops timing. */
 int hdg_profile(hdg_ctx* ctx, int enable);
 
-/* JSON with sizes, iteration counts of the last calls, timings. */
+/* JSON with sizes, iteration counts of the last calls, timings, and the
+ * device memory held (device_bytes) and the largest short-lived buffer
+ * (device_transient_bytes, the condensation scratch of a trace-operator
+ * build). */
 int hdg_get_info(const hdg_ctx* ctx, char* buf, size_t cap);
+
+/* ---------------------------------------------------------------- serving
+ * Independent instances (many meshes, degrees, time steps) share one GPU.
+ * For admission control, hdg_footprint_bytes estimates, on the host and
+ * without touching the device, the device memory a context created from the
+ * same arguments holds after its first hdg_advance(dt, .) (one trace
+ * operator per distinct c of the scheme: the stage coefficients a_ii dt,
+ * b^im_{s-1} dt and 1), plus the condensation scratch of an operator build.
+ * It covers the forcing-free configuration; hdg_set_forcing adds
+ * 8 (n_u + 2 nq_cell + 6 nq_facet) bytes per cell and 16 bytes per trace
+ * unknown.  Mesh errors are
+ * reported as by hdg_create (INVALID_ARG, message via hdg_last_error(NULL)). */
+int hdg_footprint_bytes(int64_t nv, const double* coords, int64_t nc, const int32_t* cells,
+                        const int32_t* vertex_rep, const hdg_params* prm, double dt, int64_t* bytes);
+
+/* A batch is a non-owning view of n distinct contexts (none NULL); the
+ * contexts must outlive it and must not be used elsewhere during
+ * hdg_batch_advance.  hdg_batch_advance(b, dt[n], nsteps[n], status[n])
+ * advances member i by nsteps[i] steps of dt[i], running the members on up
+ * to 16 host threads: members on distinct HIP streams overlap on the
+ * device, members sharing a stream are serialised by it.  Each member's
+ * result is bit for bit that of a lone hdg_advance.  status (optional)
+ * receives each member's hdg_status (details via hdg_last_error(member));
+ * the return value is the first non-OK member status, else HDG_OK. */
+int hdg_batch_create(int n, hdg_ctx* const* members, hdg_batch** out);
+int hdg_batch_size(const hdg_batch* b);
+int hdg_batch_advance(hdg_batch* b, const double* dt, const int* nsteps, int* status);
+void hdg_batch_destroy(hdg_batch* b);
 
 #ifdef __cplusplus
 }

@@ -9,6 +9,8 @@
 //   pressure reconstruction               -> Ctx::reconstruct
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -16,7 +18,9 @@
 #include <map>
 #include <memory>
 #include <stdexcept>
+#include <set>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/hdg.h"
@@ -220,6 +224,9 @@ struct hdg_ctx {
   long nQ = 0, nP = 0, nT = 0;
   double area = 0.0;
   std::vector<void*> allocs;
+  int device = 0;              // HIP device current at creation
+  size_t dev_bytes = 0;        // device memory held (every dalloc)
+  size_t dev_transient = 0;    // largest short-lived allocation (trace-operator assembly)
   std::map<double, std::unique_ptr<hdg::TraceOp>> ops;
   // work vectors
   double *ycell = nullptr, *g = nullptr, *part = nullptr, *part2 = nullptr, *scal = nullptr;
@@ -262,6 +269,7 @@ struct hdg_ctx {
     hipError_t e = hipMalloc(&p, n * sizeof(T));
     if (e != hipSuccess) throw hdg::OomError("hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
     allocs.push_back(p);
+    dev_bytes += n * sizeof(T);
     return static_cast<T*>(p);
   }
   template <class T>
@@ -421,6 +429,7 @@ TraceOp& hdg_ctx::trace_op(double c) {
   op->Pinv = dalloc<double>(nc * np * np);
   double* SK = nullptr;
   HIPCHK(hipMalloc(&SK, sizeof(double) * nc * nlam * nlam));
+  dev_transient = std::max(dev_transient, sizeof(double) * nc * nlam * nlam);
   op->vals = dalloc<double>(5 * nF * nf * nf);
   op->cols = dalloc<int>(5 * nF);
   op->Dinv = dalloc<double>(nF * nf * nf);
@@ -1065,6 +1074,52 @@ void hdg_ctx::step(double dtv) {
 }
 
 // ======================================================================= ABI
+
+// Device bytes a context holds after its first step, from the allocations
+// made in setup(), per trace operator (one per distinct c: the stage
+// coefficients a_ii dt, the final b^im_{s-1} dt and the reconstruction's
+// c = 1) and by the multigrid hierarchy (P1 coarse operator and its
+// aggregation levels, estimated as 2x the first level).  The transient
+// condensation buffer of an operator build is reported separately.
+static void estimate_footprint(const hdg::HostMesh& m, const hdg::RefTables& rt, const hdg_params& prm, double dtv,
+                               int64_t* held, int64_t* transient) {
+  const double nc = (double)m.nc, nF = (double)m.nF, nvt = (double)m.nvt;
+  const double ns = rt.ns, np = rt.np, nf = rt.nf, nqc = rt.nqc, nqf = rt.nqf;
+  const double nu = 2 * ns, nlam = 3 * nf, nc32 = std::ceil(nc / 32.0) * 32.0;
+  const double nQ = nc * nu, nP = nc * np, nT = nF * nf;
+  const Tableau tab = make_tableau(prm.imex);
+  const double s = tab.s;
+  const double blocks = (double)apply_soa_blocks((long)m.nc);
+  double b = 0.0;
+  // mesh (geometry, connectivity, packed neighbours) and reference tables
+  b += 8.0 * kDGeo * nc + 4.0 * 5 * 3 * nc + 4.0 * 4 * nF;
+  for (const std::vector<double>* v : {&rt.Bu, &rt.Gux, &rt.Guy, &rt.Bp, &rt.Gpx, &rt.Gpy, &rt.cq_w, &rt.FBu, &rt.FGux,
+                                       &rt.FGuy, &rt.FBp, &rt.fq_w, &rt.MU, &rt.NUB, &rt.Dx, &rt.Dy, &rt.Rx, &rt.Ry,
+                                       &rt.Chat, &rt.That, &rt.Ehat, &rt.CC, &rt.KDD, &rt.CD, &rt.BDMinv, &rt.NED})
+    b += 8.0 * v->size();
+  // work vectors: cell duals, trace vectors, Krylov and stage vectors
+  b += 8.0 * (nc * nlam + nT * (11 + s) + nQ * (18 + 2 * s) + nP * (3 + s));
+  b += 8.0 * ((double)kRedBlocks * kIdrMax + 2.0 * kRedBlocks + 3.0 * (prm.max_it_trace + 4) + 16 +
+              (double)BS_STRIDE * std::max(prm.max_it_velocity + 6, 10) + 2 * (4 * blocks + 16));
+  // Step I data: cell matrices, upwind weights, residual-kernel advection data
+  b += ns * ns * nc32 * (prm.precision == HDG_MIXED ? 4.0 : 8.0) + 8.0 * 3 * nqf * nc32 + 8.0 * nc * (2 * nqc + 3 * nqf);
+  if (prm.idr_s > 0) b += 8.0 * (3.0 * prm.idr_s * nQ + kIdrMax + 8);
+  // trace operators
+  std::set<double> cs = {1.0, tab.bim[tab.s - 1] * dtv};
+  for (int i = 1; i < tab.s; ++i) cs.insert(tab.Aim[i][i] * dtv);
+  double op = 8.0 * (nc * np * np + 5 * nF * nf * nf + nF * nf * nf) + 4.0 * 5 * nF;
+  if (prm.trace_solver == HDG_TRACE_MG_PCG) {
+    const double transfer = 2 * (4.0 * (nT + 1) + 12.0 * 4 * nF);        // P1 prolongation and restriction
+    const double level0 = 12.0 * 9 * nvt + 4.0 * nvt + 2 * (12.0 * 3 * nvt + 4.0 * nvt) + 8.0 * 5 * nvt;
+    double nco = nvt;  // coarsest level: aggregates of about six P1 vertices until at most 200 remain
+    while (nco > 200) nco = std::ceil(nco / 6.0);
+    op += transfer + 2.0 * level0 + 8.0 * nco * (nco + 2);
+  }
+  b += cs.size() * op;
+  *held = (int64_t)(1.02 * b) + 65536;  // margin for the small buffers not itemised here
+  *transient = (int64_t)(8.0 * nc * nlam * nlam);
+}
+
 #define API_BEGIN try {
 #define API_END(ctxp)                                                   \
   }                                                                     \
@@ -1123,6 +1178,7 @@ int hdg_create_periodic(int64_t nv, const double* coords, int64_t nc, const int3
   ctx->st = (hipStream_t)stream;
   std::string e = build_mesh(nv, coords, nc, cells, vertex_rep, ctx->hm);
   if (!e.empty()) { g_create_error = e; return HDG_ERR_INVALID_ARG; }
+  if (hipGetDevice(&ctx->device) != hipSuccess) { g_create_error = "no HIP device"; return HDG_ERR_DEVICE; }
   try {
     build_reference(ctx->k, ctx->rt);
     ctx->setup();
@@ -1405,6 +1461,8 @@ int hdg_get_info(const hdg_ctx* ctx, char* buf, size_t cap) {
                   ",\"velocity_iterations_total\":" + std::to_string(ctx->total_bicg) +
                   ",\"bicgstab_restarts\":" + std::to_string(ctx->bicg_restarts) +
                   ",\"pcg_floor_stops\":" + std::to_string(ctx->pcg_floor_stops) +
+                  ",\"device_bytes\":" + std::to_string(ctx->dev_bytes) +
+                  ",\"device_transient_bytes\":" + std::to_string(ctx->dev_transient) +
                   ",\"pcg_iterations_last\":" + last(ctx->pcg_iters, 16) +
                   ",\"velocity_iterations_last\":" + last(ctx->bicg_iters, 16) +
                   ",\"seconds_trace\":" + std::to_string(ctx->t_trace) +
@@ -1418,5 +1476,93 @@ int hdg_get_info(const hdg_ctx* ctx, char* buf, size_t cap) {
   std::snprintf(buf, cap, "%s", s.c_str());
   return s.size() < cap ? HDG_OK : HDG_ERR_INVALID_ARG;
 }
+
+
+int hdg_footprint_bytes(int64_t nv, const double* coords, int64_t nc, const int32_t* cells, const int32_t* vertex_rep,
+                        const hdg_params* prm, double dt, int64_t* bytes) {
+  if (!prm || !bytes || !(dt > 0)) { g_create_error = "null argument or dt <= 0"; return HDG_ERR_INVALID_ARG; }
+  if (prm->degree < 1 || prm->degree > kMaxDegree) { g_create_error = "degree must be in 1..4"; return HDG_ERR_UNSUPPORTED; }
+  if (prm->imex < 0 || prm->imex > 4) { g_create_error = "invalid parameter"; return HDG_ERR_INVALID_ARG; }
+  try {
+    hdg::HostMesh m;
+    std::string e = build_mesh(nv, coords, nc, cells, vertex_rep, m);
+    if (!e.empty()) { g_create_error = e; return HDG_ERR_INVALID_ARG; }
+    hdg::RefTables rt;
+    build_reference(prm->degree, rt);
+    int64_t held = 0, transient = 0;
+    estimate_footprint(m, rt, *prm, dt, &held, &transient);
+    *bytes = held + transient;
+  } catch (const std::exception& ex) {
+    g_create_error = ex.what();
+    return HDG_ERR_INVALID_ARG;
+  }
+  return HDG_OK;
+}
+
+}  // extern "C"
+
+// A batch is a non-owning list of distinct contexts.  Advancing it runs
+// every member's hdg_advance on a pool of host threads (at most 16, one
+// member at a time per thread), so members on distinct streams overlap on
+// the device; each member's arithmetic is exactly that of a lone call.
+struct hdg_batch {
+  std::vector<hdg_ctx*> members;
+};
+
+extern "C" {
+
+int hdg_batch_create(int n, hdg_ctx* const* members, hdg_batch** out) {
+  if (!out || n < 1 || !members) { g_create_error = "null argument or empty batch"; return HDG_ERR_INVALID_ARG; }
+  *out = nullptr;
+  std::set<hdg_ctx*> seen;
+  for (int i = 0; i < n; ++i) {
+    if (!members[i] || !seen.insert(members[i]).second) {
+      g_create_error = "batch members must be distinct, non-null contexts";
+      return HDG_ERR_INVALID_ARG;
+    }
+  }
+  auto b = new (std::nothrow) hdg_batch;
+  if (!b) { g_create_error = "out of host memory"; return HDG_ERR_OUT_OF_MEMORY; }
+  b->members.assign(members, members + n);
+  *out = b;
+  return HDG_OK;
+}
+
+int hdg_batch_size(const hdg_batch* b) { return b ? (int)b->members.size() : 0; }
+
+int hdg_batch_advance(hdg_batch* b, const double* dt, const int* nsteps, int* status) {
+  if (!b || !dt || !nsteps) return HDG_ERR_INVALID_ARG;
+  const int n = (int)b->members.size();
+  std::vector<int> st(n, HDG_OK);
+  std::atomic<int> next{0};
+  auto work = [&] {
+    for (int i = next.fetch_add(1); i < n; i = next.fetch_add(1)) {
+      hdg_ctx* c = b->members[i];
+      if (hipSetDevice(c->device) != hipSuccess) {
+        c->err = "hipSetDevice failed";
+        st[i] = HDG_ERR_DEVICE;
+        continue;
+      }
+      st[i] = hdg_advance(c, dt[i], nsteps[i]);
+    }
+  };
+  const int nthreads = std::min(n, 16);
+  std::vector<std::thread> pool;
+  try {
+    for (int t = 1; t < nthreads; ++t) pool.emplace_back(work);
+  } catch (const std::exception&) {
+    // fewer threads: the calling thread and those started share the members
+  }
+  work();
+  for (auto& t : pool) t.join();
+  int worst = HDG_OK;
+  for (int i = 0; i < n; ++i) {
+    if (status) status[i] = st[i];
+    if (worst == HDG_OK && st[i] != HDG_OK) worst = st[i];
+  }
+  return worst;
+}
+
+void hdg_batch_destroy(hdg_batch* b) { delete b; }
 
 }  // extern "C"

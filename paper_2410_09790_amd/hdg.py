@@ -23,7 +23,8 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NOT_CO
           6: "UNSUPPORTED"}
 
 EXPORTS = [
-    "hdg_default_params", "hdg_create", "hdg_create_periodic", "hdg_destroy", "hdg_last_error", "hdg_sizes", "hdg_cell_points",
+    "hdg_default_params", "hdg_create", "hdg_create_periodic", "hdg_destroy", "hdg_footprint_bytes",
+    "hdg_batch_create", "hdg_batch_size", "hdg_batch_advance", "hdg_batch_destroy", "hdg_last_error", "hdg_sizes", "hdg_cell_points",
     "hdg_facet_points", "hdg_set_forcing", "hdg_set_time", "hdg_get_time", "hdg_set_velocity_from_points", "hdg_set_state", "hdg_get_state", "hdg_advance", "hdg_solve_trace",
     "hdg_trace_matvec", "hdg_bdm_project", "hdg_weak_divergence", "hdg_momentum_residual",
     "hdg_tentative_velocity", "hdg_reconstruct_pressure", "hdg_profile", "hdg_get_info",
@@ -72,6 +73,11 @@ def load_library(path: str = LIB_PATH):
         "hdg_default_params": (None, [ctypes.POINTER(Params)]),
         "hdg_create": (I, [I64, P, I64, P, ctypes.POINTER(Params), P, ctypes.POINTER(P)]),
         "hdg_create_periodic": (I, [I64, P, I64, P, P, ctypes.POINTER(Params), P, ctypes.POINTER(P)]),
+        "hdg_footprint_bytes": (I, [I64, P, I64, P, P, ctypes.POINTER(Params), D, ctypes.POINTER(I64)]),
+        "hdg_batch_create": (I, [I, P, ctypes.POINTER(P)]),
+        "hdg_batch_size": (I, [P]),
+        "hdg_batch_advance": (I, [P, P, P, P]),
+        "hdg_batch_destroy": (None, [P]),
         "hdg_destroy": (None, [P]),
         "hdg_last_error": (ctypes.c_char_p, [P]),
         "hdg_sizes": (I, [P, P, I]),
@@ -268,3 +274,63 @@ class Context:
         buf = ctypes.create_string_buffer(1 << 16)
         self._check(self._lib.hdg_get_info(self._h, buf, len(buf)))
         return json.loads(buf.value.decode())
+
+
+def footprint_bytes(coords, cells, dt: float, vertex_rep=None, **params) -> int:
+    """Device bytes a Context with these arguments holds after its first
+    advance(dt, .), plus its transient assembly scratch (host-side estimate,
+    no device work): the admission figure of the serving loop."""
+    lib = load_library()
+    coords = np.ascontiguousarray(coords, dtype=np.float64)
+    cells = np.ascontiguousarray(cells, dtype=np.int32)
+    rep = None if vertex_rep is None else np.ascontiguousarray(vertex_rep, dtype=np.int32)
+    p = default_params(**params)
+    out = ctypes.c_int64()
+    st = lib.hdg_footprint_bytes(coords.shape[0], coords.ctypes.data_as(ctypes.c_void_p), cells.shape[0],
+                                 cells.ctypes.data_as(ctypes.c_void_p),
+                                 None if rep is None else rep.ctypes.data_as(ctypes.c_void_p), ctypes.byref(p),
+                                 float(dt), ctypes.byref(out))
+    if st != 0:
+        raise HDGError(st, lib.hdg_last_error(None).decode())
+    return int(out.value)
+
+
+class Batch:
+    """Non-owning group of distinct Contexts advanced together: hdg_batch_advance
+    runs the members on host threads, so members on distinct streams overlap
+    on the device."""
+
+    def __init__(self, contexts):
+        self._lib = load_library()
+        self.contexts = list(contexts)
+        arr = (ctypes.c_void_p * len(self.contexts))(*[c._h.value for c in self.contexts])
+        h = ctypes.c_void_p()
+        st = self._lib.hdg_batch_create(len(self.contexts), arr, ctypes.byref(h))
+        if st != 0:
+            raise HDGError(st, self._lib.hdg_last_error(None).decode())
+        self._h = h
+
+    def advance(self, dt, nsteps):
+        """dt, nsteps: one value per member (or scalars).  Raises on the first
+        failed member; returns the per-member statuses."""
+        n = len(self.contexts)
+        dts = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, dtype=np.float64), (n,)))
+        nst = np.ascontiguousarray(np.broadcast_to(np.asarray(nsteps, dtype=np.int32), (n,)))
+        status = np.zeros(n, dtype=np.int32)
+        st = self._lib.hdg_batch_advance(self._h, dts.ctypes.data_as(ctypes.c_void_p),
+                                         nst.ctypes.data_as(ctypes.c_void_p), status.ctypes.data_as(ctypes.c_void_p))
+        if st != 0:
+            bad = int(np.nonzero(status)[0][0])
+            raise HDGError(st, f"member {bad}: " + self._lib.hdg_last_error(self.contexts[bad]._h).decode())
+        return status
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hdg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -150,3 +150,21 @@ def test_bad_periodic_meshes_are_rejected_on_the_host(lib_path):
     X3[2 * 4 - 1, 0] += 0.1  # vertex (3, 1)
     st, h = _create_periodic(lib, X3, C, rep)
     assert st == 1 and not h.value and b"differ in length" in lib.hdg_last_error(None)
+
+
+def test_footprint_estimate_runs_on_the_host(lib_path):
+    """hdg_footprint_bytes needs no device: it grows with the mesh and the
+    degree, FP32 cell-matrix storage lowers it, and bad meshes are refused."""
+    import hdg_inputs as hi
+    from paper_2410_09790_amd import hdg
+    X, C = hi.unit_square_mesh(16)
+    X2, C2 = hi.unit_square_mesh(32)
+    f1 = hdg.footprint_bytes(X, C, 1e-3, degree=1)
+    f2 = hdg.footprint_bytes(X2, C2, 1e-3, degree=1)
+    f3 = hdg.footprint_bytes(X2, C2, 1e-3, degree=3)
+    f3m = hdg.footprint_bytes(X2, C2, 1e-3, degree=3, precision="mixed")
+    assert 0 < f1 < f2 < f3 and f3m < f3
+    Xp, Cp, rep = hi.periodic_square_mesh(8)
+    assert hdg.footprint_bytes(Xp, Cp, 0.04, vertex_rep=rep, degree=2, imex="ssp3_433") > 0
+    with pytest.raises(hdg.HDGError):
+        hdg.footprint_bytes(X, C[:, ::-1], 1e-3)  # clockwise cells
