@@ -192,11 +192,46 @@ double hdg_get_time(const hdg_ctx* ctx);
  * the pressure reconstruction of Q (with the forcing at the current time). */
 int hdg_set_velocity_from_points(hdg_ctx* ctx, const double* qvals);
 
+/* State exchange in the layout above (device pointers; get_state accepts
+ * NULL for fields not wanted).  During a step in progress (see
+ * hdg_advance_stages) get_state returns the state of the last completed
+ * step; set_state, set_velocity_from_points and hdg_set_time abandon the
+ * step in progress. */
 int hdg_set_state(hdg_ctx* ctx, const double* Q, const double* p, const double* lam);
 int hdg_get_state(const hdg_ctx* ctx, double* Q, double* p, double* lam);
 
-/* Algorithm 1: nsteps IMEX-HDG steps of size dt from the current state. */
+/* Algorithm 1: nsteps IMEX-HDG steps of size dt from the current state.
+ * BAD_STATE while a step started by hdg_advance_stages is unfinished. */
 int hdg_advance(hdg_ctx* ctx, double dt, int nsteps);
+
+/* Stage granularity of Algorithm 1 for schedulers that interleave jobs:
+ * runs the next nstages implicit stages (each a full Algorithm 2 solve),
+ * starting a step of size dt when none is in progress; the final projection
+ * and the pressure reconstruction run right after the last stage of a step
+ * (so a step of an s-stage scheme takes s - 1 stages).  Any chunking gives
+ * results bit for bit equal to hdg_advance.  INVALID_ARG if a step is in
+ * progress with another dt.  hdg_pending_stage: the next stage of the step
+ * in progress (1..s-1), 0 if none, -1 for NULL. */
+int hdg_advance_stages(hdg_ctx* ctx, double dt, int nstages);
+int hdg_pending_stage(const hdg_ctx* ctx);
+
+/* Basis-free export: the velocity and pressure polynomials of every cell at
+ * npts (1..1024) points given in reference coordinates (xi, eta) (host
+ * [npts][2], the same for every cell; the cell map is the one of the data
+ * layout; points outside the reference triangle extrapolate).  Q_out:
+ * device [ncells][npts][2], p_out: device [ncells][npts]; either may be
+ * NULL (not both).  Allocates a basis table of 8 * 1024 * (n_u/2 + n_p)
+ * bytes on first use. */
+int hdg_eval_points(hdg_ctx* ctx, const double* xy_ref, int npts, double* Q_out, double* p_out);
+
+/* Host-side mesh of the square [0, length]^2 cut into n x n squares, each
+ * split along its "/" diagonal (the paper's test meshes): vertex (i, j) has
+ * id j (n+1) + i at (i, j) length / n; square (i, j) gives the cells
+ * (v00, v10, v11) and (v00, v11, v01), ids 2 (j n + i) and 2 (j n + i) + 1.
+ * coords: [(n+1)^2][2], cells: [2 n^2][3], vertex_rep: [(n+1)^2] or NULL
+ * when periodic = 0 (then the identity); with periodic = 1 (n >= 3) the right
+ * and top vertices map to their left and bottom copies (hdg_create_periodic). */
+int hdg_mesh_square(int n, double length, int periodic, double* coords, int32_t* cells, int32_t* vertex_rep);
 
 /* One hybridised mixed solve (paper, Section "Solvers and preconditioners"):
  * find (U, p, lam) with

@@ -30,6 +30,7 @@
 namespace hdg {
 
 static thread_local std::string g_create_error;
+constexpr int kMaxEvalPoints = 1024;
 
 struct HipError : std::runtime_error {
   explicit HipError(const std::string& s) : std::runtime_error(s) {}
@@ -342,6 +343,12 @@ struct hdg_ctx {
   double f_scale(double tt) const { return std::exp(-f_decay * tt); }
   void richardson(double adt, const double* r, double* Q, double* p, double* lam);
   void step(double dt);
+  int pend_stage = 0;     // next implicit stage of a step in progress (0: none)
+  double* eval_tab = nullptr;  // basis values at hdg_eval_points' points
+  double pend_dt = 0.0;   // its time step
+  void begin_step(double dt);
+  void stage_once();
+  void finish_step();
 };
 
 using namespace hdg;
@@ -1012,15 +1019,32 @@ void hdg_ctx::richardson(double adt, const double* r, double* Qv, double* pv, do
 }
 
 // Algorithm 1
+// One step of Algorithm 1 is begin_step, stages 1..s-1 and finish_step; the
+// pieces keep their state in the stage arrays, so hdg_advance_stages can stop
+// between stages.  Q, p, lam change only in finish_step.
 void hdg_ctx::step(double dtv) {
-  const Tableau tab = make_tableau(prm.imex);
-  const int s = tab.s;
+  begin_step(dtv);
+  while (pend_stage != 0) stage_once();
+}
+
+void hdg_ctx::begin_step(double dtv) {
   double* MQn = stMQ[0];
   launch_mass(k, st, dm, 1.0, Q, MQn);
   launch_copy(st, nQ, Q, stQ[0]);
   launch_copy(st, nP, p, stP[0]);
   launch_copy(st, nT, lam, stL[0]);
-  for (int i = 1; i < s; ++i) {
+  pend_stage = 1;
+  pend_dt = dtv;
+}
+
+// implicit stage pend_stage; after the last one, the final projection
+void hdg_ctx::stage_once() {
+  const Tableau tab = make_tableau(prm.imex);
+  const int s = tab.s;
+  const double dtv = pend_dt;
+  const int i = pend_stage;
+  double* MQn = stMQ[0];
+  {
     // stage residual r_i, eq. (imex_residual)
     launch_copy(st, nQ, MQn, stR[i]);
     for (int j = 1; j < i; ++j) {
@@ -1045,6 +1069,15 @@ void hdg_ctx::step(double dtv) {
     richardson(tab.Aim[i][i] * dtv, stR[i], stQ[i], stP[i], stL[i]);
     launch_mass(k, st, dm, 1.0, stQ[i], stMQ[i]);
   }
+  if (++pend_stage == s) finish_step();
+}
+
+void hdg_ctx::finish_step() {
+  const Tableau tab = make_tableau(prm.imex);
+  const int s = tab.s;
+  const double dtv = pend_dt;
+  double* MQn = stMQ[0];
+  pend_stage = 0;  // Q, p, lam are overwritten from here on
   // final residual and projection
   double* rn = dr;
   launch_copy(st, nQ, MQn, rn);
@@ -1290,6 +1323,7 @@ int hdg_set_forcing(hdg_ctx* ctx, const double* cell_vals, const double* facet_v
 int hdg_set_time(hdg_ctx* ctx, double t) {
   if (!ctx || !(t == t)) return HDG_ERR_INVALID_ARG;
   ctx->time = t;
+  ctx->pend_stage = 0;  // a step in progress is abandoned
   return HDG_OK;
 }
 
@@ -1299,6 +1333,7 @@ int hdg_set_velocity_from_points(hdg_ctx* ctx, const double* qvals) {
   if (!ctx || !qvals) return HDG_ERR_INVALID_ARG;
   ctx->not_converged = false;
   ctx->err.clear();
+  ctx->pend_stage = 0;  // a step in progress is abandoned
   API_BEGIN
   launch_project(ctx->k, ctx->st, ctx->dm, ctx->dt, qvals, ctx->Q);
   KCHK();
@@ -1311,6 +1346,7 @@ int hdg_set_state(hdg_ctx* ctx, const double* Qv, const double* pv, const double
   if (!ctx || !Qv || !pv || !lv) return HDG_ERR_INVALID_ARG;
   ctx->not_converged = false;
   ctx->err.clear();
+  ctx->pend_stage = 0;  // a step in progress is abandoned
   API_BEGIN
   launch_copy(ctx->st, ctx->nQ, Qv, ctx->Q);
   launch_copy(ctx->st, ctx->nP, pv, ctx->p);
@@ -1339,11 +1375,89 @@ int hdg_get_state(const hdg_ctx* cctx, double* Qv, double* pv, double* lv) {
 int hdg_advance(hdg_ctx* ctx, double dtv, int nsteps) {
   if (!ctx || !(dtv > 0) || nsteps < 0) return HDG_ERR_INVALID_ARG;
   if (!ctx->have_state) { ctx->err = "no state set"; return HDG_ERR_BAD_STATE; }
+  if (ctx->pend_stage != 0) {
+    ctx->err = "a step is in progress (hdg_advance_stages): finish it first";
+    return HDG_ERR_BAD_STATE;
+  }
   ctx->not_converged = false;
   ctx->err.clear();
   API_BEGIN
-  for (int n = 0; n < nsteps; ++n) ctx->step(dtv);
+  try {
+    for (int n = 0; n < nsteps; ++n) ctx->step(dtv);
+  } catch (...) {
+    ctx->pend_stage = 0;
+    throw;
+  }
   API_END(ctx)
+}
+
+int hdg_advance_stages(hdg_ctx* ctx, double dtv, int nstages) {
+  if (!ctx || !(dtv > 0) || nstages < 0) return HDG_ERR_INVALID_ARG;
+  if (!ctx->have_state) { ctx->err = "no state set"; return HDG_ERR_BAD_STATE; }
+  if (ctx->pend_stage != 0 && dtv != ctx->pend_dt) {
+    ctx->err = "the step in progress has another dt";
+    return HDG_ERR_INVALID_ARG;
+  }
+  ctx->not_converged = false;
+  ctx->err.clear();
+  API_BEGIN
+  try {
+    for (int n = 0; n < nstages; ++n) {
+      if (ctx->pend_stage == 0) ctx->begin_step(dtv);
+      ctx->stage_once();
+    }
+    ctx->sync();
+  } catch (...) {
+    ctx->pend_stage = 0;
+    throw;
+  }
+  API_END(ctx)
+}
+
+int hdg_pending_stage(const hdg_ctx* ctx) { return ctx ? ctx->pend_stage : -1; }
+
+int hdg_eval_points(hdg_ctx* ctx, const double* xy_ref, int npts, double* Qo, double* po) {
+  if (!ctx || !xy_ref || npts < 1 || npts > kMaxEvalPoints || (!Qo && !po)) return HDG_ERR_INVALID_ARG;
+  if (!ctx->have_state) { ctx->err = "no state set"; return HDG_ERR_BAD_STATE; }
+  ctx->not_converged = false;
+  ctx->err.clear();
+  API_BEGIN
+  const int ns = ctx->ns, np = ctx->np;
+  std::vector<double> bu((size_t)npts * ns), bp((size_t)npts * np);
+  for (int q = 0; q < npts; ++q) {
+    dubiner_eval(ctx->k + 1, xy_ref[2 * q], xy_ref[2 * q + 1], &bu[(size_t)q * ns], nullptr, nullptr);
+    dubiner_eval(ctx->k, xy_ref[2 * q], xy_ref[2 * q + 1], &bp[(size_t)q * np], nullptr, nullptr);
+  }
+  if (!ctx->eval_tab) ctx->eval_tab = ctx->dalloc<double>((size_t)kMaxEvalPoints * (ns + np));
+  HIPCHK(hipMemcpyAsync(ctx->eval_tab, bu.data(), bu.size() * sizeof(double), hipMemcpyHostToDevice, ctx->st));
+  HIPCHK(hipMemcpyAsync(ctx->eval_tab + bu.size(), bp.data(), bp.size() * sizeof(double), hipMemcpyHostToDevice,
+                        ctx->st));
+  launch_eval_points(ctx->st, ctx->hm.nc, npts, ns, np, ctx->eval_tab, ctx->eval_tab + bu.size(), ctx->Q, ctx->p, Qo,
+                     po);
+  KCHK();
+  ctx->sync();
+  API_END(ctx)
+}
+
+int hdg_mesh_square(int n, double length, int periodic, double* coords, int32_t* cells, int32_t* vertex_rep) {
+  if (n < 1 || !(length > 0) || !coords || !cells || (periodic && (!vertex_rep || n < 3))) return HDG_ERR_INVALID_ARG;
+  const int64_t m = n + 1;
+  if ((int64_t)n * n * 2 > INT32_MAX / 3) return HDG_ERR_INVALID_ARG;
+  for (int64_t j = 0; j < m; ++j)
+    for (int64_t i = 0; i < m; ++i) {
+      const int64_t v = j * m + i;
+      coords[2 * v] = length * (double)i / n;
+      coords[2 * v + 1] = length * (double)j / n;
+      if (vertex_rep) vertex_rep[v] = periodic ? (int32_t)((j % n) * m + (i % n)) : (int32_t)v;
+    }
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t i = 0; i < n; ++i) {
+      const int32_t v00 = (int32_t)(j * m + i), v10 = v00 + 1, v01 = (int32_t)(v00 + m), v11 = v01 + 1;
+      int32_t* c = cells + 6 * (j * n + i);
+      c[0] = v00; c[1] = v10; c[2] = v11;  // below the "/" diagonal
+      c[3] = v00; c[4] = v11; c[5] = v01;  // above it
+    }
+  return HDG_OK;
 }
 
 int hdg_solve_trace(hdg_ctx* ctx, double c, const double* Fw, const double* Fpsi, const double* Fmu, double* U,
@@ -1462,6 +1576,7 @@ int hdg_get_info(const hdg_ctx* ctx, char* buf, size_t cap) {
                   ",\"bicgstab_restarts\":" + std::to_string(ctx->bicg_restarts) +
                   ",\"pcg_floor_stops\":" + std::to_string(ctx->pcg_floor_stops) +
                   ",\"device_bytes\":" + std::to_string(ctx->dev_bytes) +
+                  ",\"pending_stage\":" + std::to_string(ctx->pend_stage) +
                   ",\"device_transient_bytes\":" + std::to_string(ctx->dev_transient) +
                   ",\"pcg_iterations_last\":" + last(ctx->pcg_iters, 16) +
                   ",\"velocity_iterations_last\":" + last(ctx->bicg_iters, 16) +

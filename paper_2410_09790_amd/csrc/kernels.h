@@ -135,6 +135,9 @@ void launch_axpby(hipStream_t st, long n, double a, const double* x, double b, d
 void launch_copy(hipStream_t st, long n, const double* x, double* y);
 void launch_fill(hipStream_t st, long n, double v, double* y);
 void launch_project_const(hipStream_t st, int nF, int nf, const double* sum, double* g);
+// Qo[cell][pt][2], po[cell][pt] from the velocity / pressure bases at the points (either output may be null)
+void launch_eval_points(hipStream_t st, long nc, int npts, int ns, int np, const double* BU, const double* BP,
+                        const double* Q, const double* p, double* Qo, double* po);
 
 // Krylov helpers with device scalars
 void launch_pcg_update(hipStream_t st, long n, int nf, const double* rz, const double* pq, const double* p,

@@ -1677,6 +1677,40 @@ void launch_copy(hipStream_t st, long n, const double* x, double* y) {
   k_copy<<<nblocks(n), kBlock, 0, st>>>(n, x, y);
 }
 void launch_fill(hipStream_t st, long n, double v, double* y) { k_fill<<<nblocks(n), kBlock, 0, st>>>(n, v, y); }
+// Point values of the cell polynomials: thread per (cell, point); BU, BP are
+// the velocity and pressure bases at the points ([npts][ns], [npts][np]).
+__global__ void k_eval_points(long nc, int npts, int ns, int np, const double* __restrict__ BU,
+                              const double* __restrict__ BP, const double* __restrict__ Q,
+                              const double* __restrict__ p, double* __restrict__ Qo, double* __restrict__ po) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nc * npts) return;
+  const long e = i / npts;
+  const int q = (int)(i - e * npts);
+  if (Qo) {
+    const double* Qe = Q + e * 2 * ns;
+    double ux = 0.0, uy = 0.0;
+    for (int s = 0; s < ns; ++s) {
+      const double b = BU[q * ns + s];
+      ux += b * Qe[s];
+      uy += b * Qe[ns + s];
+    }
+    Qo[2 * i] = ux;
+    Qo[2 * i + 1] = uy;
+  }
+  if (po) {
+    const double* pe = p + e * np;
+    double v = 0.0;
+    for (int s = 0; s < np; ++s) v += BP[q * np + s] * pe[s];
+    po[i] = v;
+  }
+}
+
+void launch_eval_points(hipStream_t st, long nc, int npts, int ns, int np, const double* BU, const double* BP,
+                        const double* Q, const double* p, double* Qo, double* po) {
+  const long n = nc * npts;
+  k_eval_points<<<(int)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(nc, npts, ns, np, BU, BP, Q, p, Qo, po);
+}
+
 void launch_project_const(hipStream_t st, int nF, int nf, const double* sum, double* g) {
   k_project_const<<<nblocks(nF), kBlock, 0, st>>>(nF, nf, sum, g);
 }

@@ -24,7 +24,8 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NOT_CO
 
 EXPORTS = [
     "hdg_default_params", "hdg_create", "hdg_create_periodic", "hdg_destroy", "hdg_footprint_bytes",
-    "hdg_batch_create", "hdg_batch_size", "hdg_batch_advance", "hdg_batch_destroy", "hdg_last_error", "hdg_sizes", "hdg_cell_points",
+    "hdg_batch_create", "hdg_batch_size", "hdg_batch_advance", "hdg_batch_destroy", "hdg_advance_stages",
+    "hdg_pending_stage", "hdg_eval_points", "hdg_mesh_square", "hdg_last_error", "hdg_sizes", "hdg_cell_points",
     "hdg_facet_points", "hdg_set_forcing", "hdg_set_time", "hdg_get_time", "hdg_set_velocity_from_points", "hdg_set_state", "hdg_get_state", "hdg_advance", "hdg_solve_trace",
     "hdg_trace_matvec", "hdg_bdm_project", "hdg_weak_divergence", "hdg_momentum_residual",
     "hdg_tentative_velocity", "hdg_reconstruct_pressure", "hdg_profile", "hdg_get_info",
@@ -78,6 +79,10 @@ def load_library(path: str = LIB_PATH):
         "hdg_batch_size": (I, [P]),
         "hdg_batch_advance": (I, [P, P, P, P]),
         "hdg_batch_destroy": (None, [P]),
+        "hdg_advance_stages": (I, [P, D, I]),
+        "hdg_pending_stage": (I, [P]),
+        "hdg_eval_points": (I, [P, P, I, P, P]),
+        "hdg_mesh_square": (I, [I, D, I, P, P, P]),
         "hdg_destroy": (None, [P]),
         "hdg_last_error": (ctypes.c_char_p, [P]),
         "hdg_sizes": (I, [P, P, I]),
@@ -228,6 +233,22 @@ class Context:
     def advance(self, dt: float, nsteps: int):
         self._check(self._lib.hdg_advance(self._h, float(dt), int(nsteps)))
 
+    def advance_stages(self, dt: float, nstages: int):
+        self._check(self._lib.hdg_advance_stages(self._h, float(dt), int(nstages)))
+
+    @property
+    def pending_stage(self) -> int:
+        return int(self._lib.hdg_pending_stage(self._h))
+
+    def eval_points(self, xy_ref):
+        """Velocity (ncells, npts, 2) and pressure (ncells, npts) at reference points."""
+        pts = np.ascontiguousarray(xy_ref, dtype=np.float64).reshape(-1, 2)
+        Qo = self._empty(self.ncells * pts.shape[0] * 2)
+        po = self._empty(self.ncells * pts.shape[0])
+        self._check(self._lib.hdg_eval_points(self._h, pts.ctypes.data_as(ctypes.c_void_p), pts.shape[0], _ptr(Qo),
+                                              _ptr(po)))
+        return Qo.view(self.ncells, pts.shape[0], 2), po.view(self.ncells, pts.shape[0])
+
     # ------------------------------------------------------- path pieces
     def solve_trace(self, c, Fw=None, Fpsi=None, Fmu=None):
         U, p, lam = self._empty(self.nQ), self._empty(self.nP), self._empty(self.nT)
@@ -334,3 +355,16 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def mesh_square(n: int, length: float = 1.0, periodic: bool = False):
+    """The library's split-square mesh of [0, length]^2: (coords, cells, vertex_rep)."""
+    lib = load_library()
+    coords = np.empty(((n + 1) ** 2, 2), dtype=np.float64)
+    cells = np.empty((2 * n * n, 3), dtype=np.int32)
+    rep = np.empty((n + 1) ** 2, dtype=np.int32)
+    st = lib.hdg_mesh_square(int(n), float(length), int(bool(periodic)), coords.ctypes.data_as(ctypes.c_void_p),
+                             cells.ctypes.data_as(ctypes.c_void_p), rep.ctypes.data_as(ctypes.c_void_p))
+    if st != 0:
+        raise HDGError(st, "invalid mesh size")
+    return coords, cells, rep

@@ -168,3 +168,21 @@ def test_footprint_estimate_runs_on_the_host(lib_path):
     assert hdg.footprint_bytes(Xp, Cp, 0.04, vertex_rep=rep, degree=2, imex="ssp3_433") > 0
     with pytest.raises(hdg.HDGError):
         hdg.footprint_bytes(X, C[:, ::-1], 1e-3)  # clockwise cells
+
+
+@pytest.mark.parametrize("n,periodic", [(1, False), (5, False), (4, True)])
+def test_library_mesh_follows_the_documented_recipe(lib_path, n, periodic):
+    """hdg_mesh_square (host only) gives the documented split-square mesh,
+    the same arrays as the seeded input module."""
+    import hdg_inputs as hi
+    from paper_2410_09790_amd import hdg
+    X, C, rep = hdg.mesh_square(n, 2.0 * np.pi if periodic else 1.0, periodic)
+    if periodic:
+        Xr, Cr, repr_ = hi.periodic_square_mesh(n)
+        assert np.array_equal(rep, repr_)
+    else:
+        Xr, Cr = hi.unit_square_mesh(n)
+        assert np.array_equal(rep, np.arange((n + 1) ** 2))
+    assert np.allclose(X, Xr, rtol=0, atol=1e-14) and np.array_equal(C, Cr)
+    with pytest.raises(hdg.HDGError):
+        hdg.mesh_square(2, 1.0, True)
