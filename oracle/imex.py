@@ -229,6 +229,7 @@ class IMEXHDG:
         else:
             pn, ln = self.hdg1.normalise(ps_[-1] + dp, ls_[-1] + dl)
         self.last_final = (dp, dl)
+        self.last_stages = Qs_  # stage velocities Q_0 = Q^n, ..., Q_{s-1} (the tracer transport uses them)
         return Qn, pn, ln
 
     def run(self, Q, p, lam, t0, nsteps, callback=None):
