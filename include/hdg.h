@@ -215,6 +215,26 @@ int hdg_advance(hdg_ctx* ctx, double dt, int nsteps);
 int hdg_advance_stages(hdg_ctx* ctx, double dt, int nstages);
 int hdg_pending_stage(const hdg_ctx* ctx);
 
+/* Passive tracer (Appendix "DG tracer advection"): a scalar q in DG_k
+ * (layout and basis of the pressure, q[cell][s]) advected explicitly with
+ * the IMEX scheme's explicit tableau by U = P_CG(Q_j), the L2 projection of
+ * the stage velocities onto continuous CG_{k+1}; the transport form is
+ * (q, div(chi U)) minus the upwind flux <q^up [[chi U.n]]> on interior
+ * facets (walls carry no term, as printed), and the final update sums the
+ * explicit weights b^ex_j over every stage j = 0..s-1 (printed from j = 1,
+ * which would freeze q for IMEX Euler).  hdg_set_tracer: L2 projection of
+ * the values at the cell points (device [ncells][nq_cell]; NULL switches
+ * the tracer off); hdg_advance then transports it.  hdg_get_tracer: device
+ * [ncells][n_p].  hdg_cg_project: U = P_CG(Q) in the layout of Q (device);
+ * hdg_tracer_rate: out = M^-1 a(., q, P_CG(Q)) (device, tracer layout).
+ * The CG space (a nodal basis on equispaced points, its mass matrix and
+ * maps) is set up on first use; it is solved by Jacobi-PCG to a relative
+ * residual of 1e-14. */
+int hdg_set_tracer(hdg_ctx* ctx, const double* q_at_points);
+int hdg_get_tracer(const hdg_ctx* ctx, double* q);
+int hdg_cg_project(hdg_ctx* ctx, const double* Q, double* U);
+int hdg_tracer_rate(hdg_ctx* ctx, const double* Q, const double* q, double* out);
+
 /* Basis-free export: the velocity and pressure polynomials of every cell at
  * npts (1..1024) points given in reference coordinates (xi, eta) (host
  * [npts][2], the same for every cell; the cell map is the one of the data

@@ -343,6 +343,25 @@ struct hdg_ctx {
   double f_scale(double tt) const { return std::exp(-f_decay * tt); }
   void richardson(double adt, const double* r, double* Q, double* p, double* lam);
   void step(double dt);
+  // passive tracer (Appendix "DG tracer advection"): q in DG_k advected by
+  // P_CG(Q_j) with the explicit tableau; the CG_{k+1} space is set up on
+  // first use
+  bool tracer_on = false;
+  double *trq = nullptr, *trq_tmp = nullptr, *Ucg = nullptr;
+  double* trR[hdg::kMaxStages] = {};
+  struct Cg {
+    bool ready = false;
+    int N = 0;
+    int *l2g = nullptr, *gptr = nullptr, *ginc = nullptr;
+    double *T = nullptr, *dinv = nullptr, *b = nullptr, *u = nullptr, *r = nullptr, *z = nullptr, *p = nullptr,
+           *w = nullptr, *sc = nullptr;
+    hdg::DCsr M{};
+    int last_its = 0;
+  } cg;
+  void cg_setup();
+  void cg_project(const double* Qin, double* Uout);
+  void tracer_alloc();
+  void tracer_step(double dtv);
   int pend_stage = 0;     // next implicit stage of a step in progress (0: none)
   double* eval_tab = nullptr;  // basis values at hdg_eval_points' points
   double pend_dt = 0.0;   // its time step
@@ -1077,7 +1096,8 @@ void hdg_ctx::finish_step() {
   const int s = tab.s;
   const double dtv = pend_dt;
   double* MQn = stMQ[0];
-  pend_stage = 0;  // Q, p, lam are overwritten from here on
+  pend_stage = 0;  // Q, p, lam (and the tracer) are overwritten from here on
+  if (tracer_on) tracer_step(dtv);
   // final residual and projection
   double* rn = dr;
   launch_copy(st, nQ, MQn, rn);
@@ -1104,6 +1124,191 @@ void hdg_ctx::finish_step() {
     KCHK();
   }
   sync();
+}
+
+
+// ------------------------------------------------------------------ tracer
+// CG_{k+1}: nodal Lagrange basis on the equispaced points of the reference
+// triangle (vertices, then the m-1 inner points of each local edge from its
+// first to its second vertex, then the inner points), glued along the
+// topological vertices and facets; inner edge points are numbered along the
+// facet parameter (lower topological vertex first).
+void hdg_ctx::cg_setup() {
+  if (cg.ready) return;
+  const int m = k + 1;
+  const long nc = hm.nc, nF = hm.nF, nvt = hm.nvt;
+  const int nint = (m - 1) * (m - 2) / 2;
+  std::vector<double> px, py;
+  const double V[3][2] = {{0.0, 0.0}, {1.0, 0.0}, {0.0, 1.0}};
+  for (int v = 0; v < 3; ++v) { px.push_back(V[v][0]); py.push_back(V[v][1]); }
+  for (int f = 0; f < 3; ++f)
+    for (int r = 1; r < m; ++r) {
+      px.push_back(V[FA[f]][0] + (V[FB[f]][0] - V[FA[f]][0]) * r / m);
+      py.push_back(V[FA[f]][1] + (V[FB[f]][1] - V[FA[f]][1]) * r / m);
+    }
+  for (int j = 1; j < m; ++j)
+    for (int i = 1; i < m - j; ++i) { px.push_back((double)i / m); py.push_back((double)j / m); }
+  if ((int)px.size() != ns) throw std::runtime_error("CG node count mismatch");
+  // T = Vn^-1, Vn[a][s] = phi_s(node a): Gauss-Jordan with partial pivoting
+  std::vector<double> A((size_t)ns * ns), T((size_t)ns * ns, 0.0);
+  for (int a = 0; a < ns; ++a) dubiner_eval(m, px[a], py[a], &A[(size_t)a * ns], nullptr, nullptr);
+  for (int i = 0; i < ns; ++i) T[(size_t)i * ns + i] = 1.0;
+  for (int c = 0; c < ns; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < ns; ++r)
+      if (std::fabs(A[(size_t)r * ns + c]) > std::fabs(A[(size_t)piv * ns + c])) piv = r;
+    for (int j = 0; j < ns; ++j) {
+      std::swap(A[(size_t)c * ns + j], A[(size_t)piv * ns + j]);
+      std::swap(T[(size_t)c * ns + j], T[(size_t)piv * ns + j]);
+    }
+    const double d = A[(size_t)c * ns + c];
+    for (int j = 0; j < ns; ++j) { A[(size_t)c * ns + j] /= d; T[(size_t)c * ns + j] /= d; }
+    for (int r = 0; r < ns; ++r) {
+      if (r == c) continue;
+      const double f = A[(size_t)r * ns + c];
+      if (f == 0.0) continue;
+      for (int j = 0; j < ns; ++j) { A[(size_t)r * ns + j] -= f * A[(size_t)c * ns + j]; T[(size_t)r * ns + j] -= f * T[(size_t)c * ns + j]; }
+    }
+  }
+  // T now holds Vn^-1 with rows indexed by s and columns by the node a
+  const long N = nvt + nF * (m - 1) + nc * nint;
+  if (N > INT32_MAX / 2) throw ArgError("CG space too large");
+  std::vector<int32_t> l2g((size_t)nc * ns);
+  for (long e = 0; e < nc; ++e) {
+    int a = 0;
+    for (int v = 0; v < 3; ++v) l2g[e * ns + a++] = hm.vtopo[hm.cells[3 * e + v]];
+    for (int f = 0; f < 3; ++f) {
+      const long F = hm.cf_facet[f * nc + e];
+      const bool flip = hm.cf_flip[f * nc + e] != 0;
+      for (int r = 0; r < m - 1; ++r) l2g[e * ns + a++] = (int32_t)(nvt + F * (m - 1) + (flip ? m - 2 - r : r));
+    }
+    for (int c = 0; c < nint; ++c) l2g[e * ns + a++] = (int32_t)(nvt + nF * (m - 1) + e * nint + c);
+  }
+  // mass matrix: M_K = det_K T^T T (the Dubiner mass is det_K I)
+  std::vector<double> G((size_t)ns * ns, 0.0);
+  for (int x = 0; x < ns; ++x)
+    for (int y = 0; y < ns; ++y)
+      for (int s = 0; s < ns; ++s) G[(size_t)x * ns + y] += T[(size_t)s * ns + x] * T[(size_t)s * ns + y];
+  std::vector<std::pair<int64_t, double>> trip;
+  trip.reserve((size_t)nc * ns * ns);
+  for (long e = 0; e < nc; ++e) {
+    const double det = hm.geo[(size_t)G_DET * nc + e];
+    for (int x = 0; x < ns; ++x)
+      for (int y = 0; y < ns; ++y)
+        trip.push_back({(int64_t)l2g[e * ns + x] * N + l2g[e * ns + y], det * G[(size_t)x * ns + y]});
+  }
+  std::sort(trip.begin(), trip.end(), [](const auto& u, const auto& v) { return u.first < v.first; });
+  Csr M;
+  M.nrows = M.ncols = N;
+  M.ptr.assign(N + 1, 0);
+  for (size_t i = 0; i < trip.size();) {
+    size_t j = i;
+    double v = 0.0;
+    while (j < trip.size() && trip[j].first == trip[i].first) v += trip[j++].second;
+    const int64_t row = trip[i].first / N, col = trip[i].first % N;
+    M.idx.push_back((int32_t)col);
+    M.val.push_back(v);
+    M.ptr[row + 1]++;
+    i = j;
+  }
+  for (long r = 0; r < N; ++r) M.ptr[r + 1] += M.ptr[r];
+  std::vector<double> dinv(N, 0.0);
+  for (long r = 0; r < N; ++r)
+    for (int32_t q = M.ptr[r]; q < M.ptr[r + 1]; ++q)
+      if (M.idx[q] == r) dinv[r] = 1.0 / M.val[q];
+  // incidences of each unknown, for the gathered right-hand side
+  std::vector<int32_t> gptr(N + 1, 0), ginc((size_t)nc * ns);
+  for (size_t i = 0; i < l2g.size(); ++i) gptr[l2g[i] + 1]++;
+  for (long r = 0; r < N; ++r) gptr[r + 1] += gptr[r];
+  {
+    std::vector<int32_t> pos(gptr.begin(), gptr.end() - 1);
+    for (size_t i = 0; i < l2g.size(); ++i) ginc[pos[l2g[i]]++] = (int32_t)i;
+  }
+  cg.N = (int)N;
+  cg.l2g = upload(l2g);
+  cg.gptr = upload(gptr);
+  cg.ginc = upload(ginc);
+  cg.T = upload(T);
+  cg.M.n = (int)N;
+  cg.M.ptr = upload(M.ptr);
+  cg.M.idx = upload(M.idx);
+  cg.M.val = upload(M.val);
+  cg.dinv = upload(dinv);
+  for (double** v : {&cg.b, &cg.u, &cg.r, &cg.z, &cg.p, &cg.w}) *v = dalloc<double>(N);
+  cg.sc = dalloc<double>(4);
+  sync();
+  cg.ready = true;
+}
+
+// Uout = P_CG(Qin): per component, Jacobi-PCG on the CG mass matrix to a
+// relative residual of 1e-14, then the nodal values back to Dubiner form.
+void hdg_ctx::cg_project(const double* Qin, double* Uout) {
+  cg_setup();
+  const long N = cg.N;
+  for (int comp = 0; comp < 2; ++comp) {
+    launch_cg_rhs(st, cg.N, cg.gptr, cg.ginc, ns, cg.T, dm, Qin, comp, cg.b);
+    launch_fill(st, N, 0.0, cg.u);
+    launch_copy(st, N, cg.b, cg.r);
+    launch_csr_jacobi(st, cg.M, cg.dinv, 1.0, cg.r, nullptr, cg.z);
+    launch_copy(st, N, cg.z, cg.p);
+    launch_dot(st, N, cg.b, nullptr, part);
+    launch_finish(st, part, kRedBlocks, cg.sc);
+    const double bn = std::sqrt(read_scalar(cg.sc));
+    launch_dot(st, N, cg.r, cg.z, part);
+    launch_finish(st, part, kRedBlocks, cg.sc);
+    double rz = read_scalar(cg.sc);
+    int it = 0;
+    for (; bn > 0.0 && it < 1000; ++it) {
+      launch_csr_spmv(st, cg.M, cg.p, cg.w, 0.0);
+      launch_dot(st, N, cg.p, cg.w, part);
+      launch_finish(st, part, kRedBlocks, cg.sc);
+      const double pw = read_scalar(cg.sc);
+      if (!(pw > 0.0)) break;
+      const double alpha = rz / pw;
+      launch_axpby(st, N, alpha, cg.p, 1.0, cg.u);
+      launch_axpby(st, N, -alpha, cg.w, 1.0, cg.r);
+      launch_dot(st, N, cg.r, nullptr, part);
+      launch_finish(st, part, kRedBlocks, cg.sc);
+      if (std::sqrt(read_scalar(cg.sc)) <= 1e-14 * bn) { ++it; break; }
+      launch_csr_jacobi(st, cg.M, cg.dinv, 1.0, cg.r, nullptr, cg.z);
+      launch_dot(st, N, cg.r, cg.z, part);
+      launch_finish(st, part, kRedBlocks, cg.sc);
+      const double rzn = read_scalar(cg.sc);
+      launch_axpby(st, N, 1.0, cg.z, rzn / rz, cg.p);
+      rz = rzn;
+    }
+    cg.last_its = it;
+    launch_cg_to_dg(st, hm.nc, ns, cg.T, cg.l2g, cg.u, comp, Uout);
+  }
+  KCHK();
+}
+
+void hdg_ctx::tracer_alloc() {
+  if (trq) return;
+  trq = dalloc<double>(nP);
+  trq_tmp = dalloc<double>(nP);
+  Ucg = dalloc<double>(nQ);
+  for (int i = 0; i < make_tableau(prm.imex).s; ++i) trR[i] = dalloc<double>(nP);
+}
+
+// eqs. (advection_update_stages), (advection_update_final): stage tracer
+// values with the explicit tableau and the stage velocities Q_j of this step
+void hdg_ctx::tracer_step(double dtv) {
+  const Tableau tab = make_tableau(prm.imex);
+  const int s = tab.s;
+  for (int j = 0; j < s; ++j) {
+    bool needed = tab.bex[j] != 0.0;
+    for (int i = j + 1; i < s; ++i) needed = needed || tab.Aex[i][j] != 0.0;
+    if (!needed) continue;
+    launch_copy(st, nP, trq, trq_tmp);
+    for (int i = 0; i < j; ++i)
+      if (tab.Aex[j][i] != 0.0) launch_axpby(st, nP, dtv * tab.Aex[j][i], trR[i], 1.0, trq_tmp);
+    cg_project(stQ[j], Ucg);
+    launch_tracer_rate(k, st, dm, dt, Ucg, trq_tmp, trR[j]);
+  }
+  for (int j = 0; j < s; ++j)
+    if (tab.bex[j] != 0.0) launch_axpby(st, nP, dtv * tab.bex[j], trR[j], 1.0, trq);
+  KCHK();
 }
 
 // ======================================================================= ABI
@@ -1415,6 +1620,60 @@ int hdg_advance_stages(hdg_ctx* ctx, double dtv, int nstages) {
 }
 
 int hdg_pending_stage(const hdg_ctx* ctx) { return ctx ? ctx->pend_stage : -1; }
+
+int hdg_set_tracer(hdg_ctx* ctx, const double* qvals) {
+  if (!ctx) return HDG_ERR_INVALID_ARG;
+  ctx->not_converged = false;
+  ctx->err.clear();
+  API_BEGIN
+  if (!qvals) {
+    ctx->tracer_on = false;
+  } else {
+    ctx->tracer_alloc();
+    launch_project_scalar(ctx->k, ctx->st, ctx->dm, ctx->dt, qvals, ctx->trq);
+    KCHK();
+    ctx->tracer_on = true;
+  }
+  ctx->sync();
+  API_END(ctx)
+}
+
+int hdg_get_tracer(const hdg_ctx* cctx, double* q) {
+  hdg_ctx* ctx = const_cast<hdg_ctx*>(cctx);
+  if (!ctx || !q) return HDG_ERR_INVALID_ARG;
+  if (!ctx->tracer_on) { ctx->err = "no tracer set"; return HDG_ERR_BAD_STATE; }
+  ctx->not_converged = false;
+  ctx->err.clear();
+  API_BEGIN
+  launch_copy(ctx->st, ctx->nP, ctx->trq, q);
+  KCHK();
+  ctx->sync();
+  API_END(ctx)
+}
+
+int hdg_cg_project(hdg_ctx* ctx, const double* Qv, double* Ucg) {
+  if (!ctx || !Qv || !Ucg) return HDG_ERR_INVALID_ARG;
+  ctx->not_converged = false;
+  ctx->err.clear();
+  API_BEGIN
+  ctx->cg_project(Qv, Ucg);
+  ctx->sync();
+  API_END(ctx)
+}
+
+int hdg_tracer_rate(hdg_ctx* ctx, const double* Qv, const double* q, double* out) {
+  if (!ctx || !Qv || !q || !out) return HDG_ERR_INVALID_ARG;
+  ctx->not_converged = false;
+  ctx->err.clear();
+  API_BEGIN
+  ctx->tracer_alloc();
+  ctx->cg_project(Qv, ctx->Ucg);
+  launch_tracer_rate(ctx->k, ctx->st, ctx->dm, ctx->dt, ctx->Ucg, q, out);
+  KCHK();
+  ctx->sync();
+  API_END(ctx)
+}
+
 
 int hdg_eval_points(hdg_ctx* ctx, const double* xy_ref, int npts, double* Qo, double* po) {
   if (!ctx || !xy_ref || npts < 1 || npts > kMaxEvalPoints || (!Qo && !po)) return HDG_ERR_INVALID_ARG;

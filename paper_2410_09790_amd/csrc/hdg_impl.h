@@ -66,6 +66,7 @@ inline void facet_point(int f, double s, double& xi, double& eta) {
 struct HostMesh {
   int64_t nv = 0, nc = 0, nF = 0;
   int64_t nvt = 0;                  // topological vertices (classes of identified vertices)
+  std::vector<int32_t> vtopo;       // [nv] topological id of each vertex
   std::vector<double> coords;       // [nv][2]
   std::vector<int32_t> cells;       // [nc][3]
   std::vector<int32_t> facet_lo, facet_hi;

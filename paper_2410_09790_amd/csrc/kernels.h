@@ -135,6 +135,13 @@ void launch_axpby(hipStream_t st, long n, double a, const double* x, double b, d
 void launch_copy(hipStream_t st, long n, const double* x, double* y);
 void launch_fill(hipStream_t st, long n, double v, double* y);
 void launch_project_const(hipStream_t st, int nF, int nf, const double* sum, double* g);
+// passive tracer: CG_{k+1} projection pieces and the DG transport rate M^-1 a(., q, U)
+void launch_cg_rhs(hipStream_t st, int N, const int* ptr, const int* inc, int ns, const double* T, DMesh m,
+                   const double* Q, int comp, double* b);
+void launch_cg_to_dg(hipStream_t st, long nc, int ns, const double* T, const int* l2g, const double* u, int comp,
+                     double* U);
+void launch_project_scalar(int k, hipStream_t st, DMesh m, DTab t, const double* vals, double* q);
+void launch_tracer_rate(int k, hipStream_t st, DMesh m, DTab t, const double* U, const double* q, double* out);
 // Qo[cell][pt][2], po[cell][pt] from the velocity / pressure bases at the points (either output may be null)
 void launch_eval_points(hipStream_t st, long nc, int npts, int ns, int np, const double* BU, const double* BP,
                         const double* Q, const double* p, double* Qo, double* po);

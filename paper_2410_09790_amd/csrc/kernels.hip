@@ -1638,6 +1638,154 @@ void launch_point_dual(int k, hipStream_t st, DMesh m, DTab t, const double* val
 void launch_wall_flux(int k, hipStream_t st, DMesh m, DTab t, const double* vals, double* out) {
   HDG_DISPATCH(k, (k_wall_flux<KK><<<nblocks(3L * m.nc), kBlock, 0, st>>>(m, t, vals, out)));
 }
+// ===================================================================== tracer
+// Passive tracer (Appendix "DG tracer advection"): q in DG_k (the pressure
+// basis), advected by U = P_CG(Q), the L2 projection of the velocity onto
+// continuous CG_{k+1}.  The CG space is nodal Lagrange on equispaced points;
+// T maps a cell's nodal values to its Dubiner coefficients (L_a =
+// sum_s T[s][a] phi_s), l2g its nodes to global CG unknowns.
+
+// b[d] = (L_d, Q_comp): sum over the (cell, node) incidences of unknown d of
+// det * sum_s T[s][a] Q[cell][comp][s] (the Dubiner mass is det * I).
+__global__ void k_cg_rhs(int N, const int* __restrict__ ptr, const int* __restrict__ inc, int ns,
+                         const double* __restrict__ T, const double* __restrict__ geo, int nc,
+                         const double* __restrict__ Q, int comp, double* __restrict__ b) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= N) return;
+  double acc = 0.0;
+  for (int p = ptr[d]; p < ptr[d + 1]; ++p) {
+    const int e = inc[p] / ns, a = inc[p] - e * ns;
+    const double* Qe = Q + ((long)e * 2 + comp) * ns;
+    double v = 0.0;
+    for (int s = 0; s < ns; ++s) v += T[s * ns + a] * Qe[s];
+    acc += geo[D_DET * (long)nc + e] * v;
+  }
+  b[d] = acc;
+}
+
+// U[cell][comp][s] = sum_a T[s][a] u[l2g[cell][a]]
+__global__ void k_cg_to_dg(long nc, int ns, const double* __restrict__ T, const int* __restrict__ l2g,
+                           const double* __restrict__ u, int comp, double* __restrict__ U) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nc * ns) return;
+  const long e = i / ns;
+  const int s = (int)(i - e * ns);
+  double v = 0.0;
+  for (int a = 0; a < ns; ++a) v += T[s * ns + a] * u[l2g[e * ns + a]];
+  U[(e * 2 + comp) * ns + s] = v;
+}
+
+// L2 projection of point values onto the tracer space (orthonormal basis:
+// coefficient s = sum_q w_q phi_s(x_q) v_q)
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_project_scalar(DMesh m, DTab t, const double* __restrict__ vals,
+                                                           double* __restrict__ q) {
+  using D = Dims<K>;
+  constexpr int NP = D::NP, NQC = D::NQC;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m.nc) return;
+  double o[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) o[i] = 0.0;
+  for (int qq = 0; qq < NQC; ++qq) {
+    const double v = t.cw[qq] * vals[(long)e * NQC + qq];
+#pragma unroll
+    for (int s = 0; s < NP; ++s) o[s] += t.Bp[qq * NP + s] * v;
+  }
+#pragma unroll
+  for (int i = 0; i < NP; ++i) q[(long)e * NP + i] = o[i];
+}
+
+// out = M^-1 a(., q, U): volume (q, div(chi U)) and, on interior facets,
+// -<q^up [[chi U.n]]> with q^up from the side U.n points away from.
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_tracer_rate(DMesh m, DTab t, const double* __restrict__ U,
+                                                        const double* __restrict__ q, double* __restrict__ out) {
+  using D = Dims<K>;
+  constexpr int NS = D::NS, NP = D::NP, NQC = D::NQC, NQF = D::NQF;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m.nc) return;
+  const long nc = m.nc;
+  const CellGeo g = load_geo(m, e);
+  double uc[2 * NS], qv[NP], o[NP];
+#pragma unroll
+  for (int i = 0; i < 2 * NS; ++i) uc[i] = U[(long)e * 2 * NS + i];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    qv[i] = q[(long)e * NP + i];
+    o[i] = 0.0;
+  }
+  for (int qq = 0; qq < NQC; ++qq) {
+    double ux = 0.0, uy = 0.0, dxx = 0.0, dxe = 0.0, dyx = 0.0, dye = 0.0, qval = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const double b = t.Bu[qq * NS + s], gx = t.Gux[qq * NS + s], gy = t.Guy[qq * NS + s];
+      ux += b * uc[s];
+      uy += b * uc[NS + s];
+      dxx += gx * uc[s];       // d Ux / d xi
+      dxe += gy * uc[s];       // d Ux / d eta
+      dyx += gx * uc[NS + s];  // d Uy / d xi
+      dye += gy * uc[NS + s];
+    }
+#pragma unroll
+    for (int s = 0; s < NP; ++s) qval += t.Bp[qq * NP + s] * qv[s];
+    // physical derivative d/dx_d = sum_a d/dxi_a ij[a][d]
+    const double div = g.ij[0][0] * dxx + g.ij[1][0] * dxe + g.ij[0][1] * dyx + g.ij[1][1] * dye;
+    const double a0 = g.ij[0][0] * ux + g.ij[0][1] * uy;  // sum_d ij[0][d] U_d
+    const double a1 = g.ij[1][0] * ux + g.ij[1][1] * uy;
+    const double w = t.cw[qq] * g.det * qval;
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+      o[i] += w * (t.Gpx[qq * NP + i] * a0 + t.Gpy[qq * NP + i] * a1 + t.Bp[qq * NP + i] * div);
+  }
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const int nb = m.cf_nb[f * nc + e];
+    if (nb < 0) continue;  // walls carry no term
+    const int fn = m.cf_nbf[f * nc + e];
+    const int rev = m.cf_flip[f * nc + e] != m.cf_flip[fn * nc + nb];
+    double qn[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) qn[i] = q[(long)nb * NP + i];
+    for (int qq = 0; qq < NQF; ++qq) {
+      const int qm = rev ? NQF - 1 - qq : qq;
+      double ux = 0.0, uy = 0.0, qo = 0.0, qb = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const double b = t.FBu[(f * NQF + qq) * NS + s];
+        ux += b * uc[s];
+        uy += b * uc[NS + s];
+      }
+#pragma unroll
+      for (int s = 0; s < NP; ++s) {
+        qo += t.FBp[(f * NQF + qq) * NP + s] * qv[s];
+        qb += t.FBp[(fn * NQF + qm) * NP + s] * qn[s];
+      }
+      const double un = ux * g.n[f][0] + uy * g.n[f][1];
+      const double flux = t.fw[qq] * g.h[f] * un * (un >= 0.0 ? qo : qb);
+#pragma unroll
+      for (int i = 0; i < NP; ++i) o[i] -= t.FBp[(f * NQF + qq) * NP + i] * flux;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NP; ++i) out[(long)e * NP + i] = o[i] / g.det;
+}
+
+void launch_cg_rhs(hipStream_t st, int N, const int* ptr, const int* inc, int ns, const double* T, DMesh m,
+                   const double* Q, int comp, double* b) {
+  k_cg_rhs<<<nblocks(N), kBlock, 0, st>>>(N, ptr, inc, ns, T, m.geo, m.nc, Q, comp, b);
+}
+void launch_cg_to_dg(hipStream_t st, long nc, int ns, const double* T, const int* l2g, const double* u, int comp,
+                     double* U) {
+  k_cg_to_dg<<<nblocks(nc * ns), kBlock, 0, st>>>(nc, ns, T, l2g, u, comp, U);
+}
+void launch_project_scalar(int k, hipStream_t st, DMesh m, DTab t, const double* vals, double* q) {
+  HDG_DISPATCH(k, (k_project_scalar<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, vals, q)));
+}
+void launch_tracer_rate(int k, hipStream_t st, DMesh m, DTab t, const double* U, const double* q, double* out) {
+  HDG_DISPATCH(k, (k_tracer_rate<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, U, q, out)));
+}
+
 void launch_project(int k, hipStream_t st, DMesh m, DTab t, const double* vals, double* Q) {
   HDG_DISPATCH(k, (k_project<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, vals, Q)));
 }

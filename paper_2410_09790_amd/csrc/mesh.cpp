@@ -55,6 +55,7 @@ std::string build_mesh(int64_t nv, const double* coords, int64_t nc, const int32
     m.nvt = nv;
   }
   const int64_t nvt = m.nvt;
+  m.vtopo = topo;
   struct Ent { int64_t key; int32_t cell, f; };
   std::vector<Ent> ents(3 * nc);
   m.cf_flip.assign(3 * nc, 0);

@@ -25,7 +25,8 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NOT_CO
 EXPORTS = [
     "hdg_default_params", "hdg_create", "hdg_create_periodic", "hdg_destroy", "hdg_footprint_bytes",
     "hdg_batch_create", "hdg_batch_size", "hdg_batch_advance", "hdg_batch_destroy", "hdg_advance_stages",
-    "hdg_pending_stage", "hdg_eval_points", "hdg_mesh_square", "hdg_last_error", "hdg_sizes", "hdg_cell_points",
+    "hdg_pending_stage", "hdg_eval_points", "hdg_mesh_square", "hdg_set_tracer", "hdg_get_tracer",
+    "hdg_cg_project", "hdg_tracer_rate", "hdg_last_error", "hdg_sizes", "hdg_cell_points",
     "hdg_facet_points", "hdg_set_forcing", "hdg_set_time", "hdg_get_time", "hdg_set_velocity_from_points", "hdg_set_state", "hdg_get_state", "hdg_advance", "hdg_solve_trace",
     "hdg_trace_matvec", "hdg_bdm_project", "hdg_weak_divergence", "hdg_momentum_residual",
     "hdg_tentative_velocity", "hdg_reconstruct_pressure", "hdg_profile", "hdg_get_info",
@@ -83,6 +84,10 @@ def load_library(path: str = LIB_PATH):
         "hdg_pending_stage": (I, [P]),
         "hdg_eval_points": (I, [P, P, I, P, P]),
         "hdg_mesh_square": (I, [I, D, I, P, P, P]),
+        "hdg_set_tracer": (I, [P, P]),
+        "hdg_get_tracer": (I, [P, P]),
+        "hdg_cg_project": (I, [P, P, P]),
+        "hdg_tracer_rate": (I, [P, P, P, P]),
         "hdg_destroy": (None, [P]),
         "hdg_last_error": (ctypes.c_char_p, [P]),
         "hdg_sizes": (I, [P, P, I]),
@@ -239,6 +244,30 @@ class Context:
     @property
     def pending_stage(self) -> int:
         return int(self._lib.hdg_pending_stage(self._h))
+
+    def set_tracer(self, values):
+        """Tracer from its values at cell_points() (ncells, nq_cell); None switches it off."""
+        import torch
+        if values is None:
+            self._check(self._lib.hdg_set_tracer(self._h, None))
+            return
+        v = torch.as_tensor(np.ascontiguousarray(values, dtype=np.float64)).to(self.device)
+        self._check(self._lib.hdg_set_tracer(self._h, _ptr(v)))
+
+    def get_tracer(self):
+        q = self._empty(self.nP)
+        self._check(self._lib.hdg_get_tracer(self._h, _ptr(q)))
+        return q
+
+    def cg_project(self, Q):
+        U = self._empty(self.nQ)
+        self._check(self._lib.hdg_cg_project(self._h, _ptr(Q), _ptr(U)))
+        return U
+
+    def tracer_rate(self, Q, q):
+        out = self._empty(self.nP)
+        self._check(self._lib.hdg_tracer_rate(self._h, _ptr(Q), _ptr(q), _ptr(out)))
+        return out
 
     def eval_points(self, xy_ref):
         """Velocity (ncells, npts, 2) and pressure (ncells, npts) at reference points."""
