@@ -252,6 +252,9 @@ struct hdg_ctx {
   long total_pcg = 0, total_bicg = 0, n_trace_solves = 0, n_velocity_solves = 0, bicg_restarts = 0;
   long pcg_floor_stops = 0;  // trace solves ended at the round-off floor (within kPcgFloor * rtol)
   static constexpr int kPcgFlatBlocks = 3;
+  static constexpr long kSmallTrace = 24576;  // trace unknowns up to which Jacobi-PCG runs in one workgroup
+  double* small_info = nullptr;
+  int pcg_small(hdg::TraceOp& op, const double* gin, double gnorm, double* x);
   static constexpr double kPcgFloor = 100.0;
   double t_trace = 0.0, t_velocity = 0.0, t_other = 0.0;
   int max_pcg_bicg_seen = 0;
@@ -427,6 +430,7 @@ void hdg_ctx::setup() {
   kpart = dalloc<double>(4L * apply_soa_blocks(nc) + 16);
   pr = dalloc<double>(nT); pz = dalloc<double>(nT); pp = dalloc<double>(nT); pq = dalloc<double>(nT);
   t1 = dalloc<double>(nT); t2 = dalloc<double>(nT); t3 = dalloc<double>(nT); px = dalloc<double>(nT);
+  small_info = dalloc<double>(4);
   for (double** v : {&kd.b, &kd.x, &kd.r, &kd.rh, &kd.s, &kd.t, &kd.p, &kd.v}) *v = dalloc<double>(nQ);
   const long nc32 = (nc + 31) / 32 * 32;
   vk32 = prm.precision == HDG_MIXED;
@@ -684,6 +688,7 @@ int hdg_ctx::pcg(TraceOp& op, const double* gin, double* x) {
     launch_fill(st, n, 0.0, x);
     return 0;
   }
+  if (!op.mg && n <= kSmallTrace) return pcg_small(op, gin, gnorm, x);
   precond(op, pr, pz);
   launch_dot(st, n, pr, pz, part);
   launch_finish(st, part, kRedBlocks, rz + kPcgBlock);  // the block rotates it to rz[0]
@@ -727,6 +732,31 @@ int hdg_ctx::pcg(TraceOp& op, const double* gin, double* x) {
   cap_reached("PCG on the trace system: " + std::to_string(it) + " iterations without reaching rtol_trace (relative residual " +
               sci(res / gnorm) + ")");
   return it;
+}
+
+// Small facet-block-Jacobi systems: the whole solve in one single-workgroup
+// launch (launch and synchronisation latency, not bandwidth, bound the
+// multi-launch iteration there).  Same stopping rules as pcg().
+int hdg_ctx::pcg_small(TraceOp& op, const double* gin, double gnorm, double* x) {
+  const double tol = prm.rtol_trace * gnorm, flo = kPcgFloor * prm.rtol_trace * gnorm;
+  launch_pcg_small(k, st, (int)hm.nF, op.vals, op.cols, op.Dinv, gin, px, pr, pz, pp, pq, prm.max_it_trace, tol * tol,
+                   flo * flo, kPcgFlatBlocks, small_info);
+  KCHK();
+  HIPCHK(hipMemcpyAsync(h_pinned, small_info, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+  sync();
+  const int its = (int)h_pinned[0];
+  const double res = std::sqrt(h_pinned[1]);
+  if (!(res == res)) throw SolverBreakdown("PCG breakdown (NaN residual)");
+  launch_copy(st, nT, px, x);
+  if (h_pinned[3] == 0.0) {
+    if (h_pinned[2] != 0.0) {
+      ++pcg_floor_stops;
+    } else {
+      cap_reached("PCG on the trace system: " + std::to_string(its) + " iterations without reaching rtol_trace "
+                  "(relative residual " + sci(res / gnorm) + ")");
+    }
+  }
+  return its;
 }
 
 void hdg_ctx::solve_trace(double c, const double* Fw, const double* Fpsi, const double* Fmu, double* U, double* pout,

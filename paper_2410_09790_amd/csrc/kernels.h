@@ -135,6 +135,11 @@ void launch_axpby(hipStream_t st, long n, double a, const double* x, double b, d
 void launch_copy(hipStream_t st, long n, const double* x, double* y);
 void launch_fill(hipStream_t st, long n, double v, double* y);
 void launch_project_const(hipStream_t st, int nF, int nf, const double* sum, double* g);
+// facet-block-Jacobi PCG of a small trace system in one workgroup (one launch per solve);
+// info[4]: iterations, squared projected residual, floor stop, converged
+void launch_pcg_small(int k, hipStream_t st, int nF, const double* vals, const int* cols, const double* Dinv,
+                      const double* g, double* x, double* r, double* z, double* p, double* q, int maxit, double tol2,
+                      double floor2, int flat_blocks, double* info);
 // passive tracer: CG_{k+1} projection pieces and the DG transport rate M^-1 a(., q, U)
 void launch_cg_rhs(hipStream_t st, int N, const int* ptr, const int* inc, int ns, const double* T, DMesh m,
                    const double* Q, int comp, double* b);

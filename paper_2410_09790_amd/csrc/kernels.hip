@@ -1786,6 +1786,142 @@ void launch_tracer_rate(int k, hipStream_t st, DMesh m, DTab t, const double* U,
   HDG_DISPATCH(k, (k_tracer_rate<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, U, q, out)));
 }
 
+
+// ------------------------------------------------------------------ small PCG
+// Facet-block-Jacobi PCG on a small trace system in one workgroup: every
+// iteration (S p, the updates, the block-Jacobi preconditioner with the
+// null-vector projection, the new direction) runs between workgroup
+// barriers, so a solve is one launch instead of a dozen per iteration.  The
+// arithmetic is that of the multi-launch path (projected residual norm, the
+// same round-off-floor stop); only the summation order of the inner
+// products differs.  info: iterations, final squared residual (null
+// component removed), floor stop, converged.
+constexpr int kSmallBlock = 1024;
+
+__device__ __forceinline__ void small_reduce(double* v, int nv, double* sh) {
+  // sh: shared scratch of 3 * (kSmallBlock / 64) doubles; all threads get the sums
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int c = 0; c < nv; ++c) {
+    double x = v[c];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    if (lane == 0) sh[c * (kSmallBlock / 64) + w] = x;
+  }
+  __syncthreads();
+  for (int c = 0; c < nv; ++c) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < kSmallBlock / 64; ++i) s += sh[c * (kSmallBlock / 64) + i];
+    v[c] = s;
+  }
+  __syncthreads();
+}
+
+template <int K>
+__global__ void __launch_bounds__(kSmallBlock) k_pcg_small(int nF, const double* __restrict__ vals,
+                                                           const int* __restrict__ cols, const double* __restrict__ Dinv,
+                                                           const double* __restrict__ g, double* __restrict__ x,
+                                                           double* __restrict__ r, double* __restrict__ z,
+                                                           double* __restrict__ p, double* __restrict__ q, int maxit,
+                                                           double tol2, double floor2, int flat_blocks,
+                                                           double* __restrict__ info) {
+  constexpr int NF = K + 1;
+  __shared__ double sh[3 * (kSmallBlock / 64)];
+  const int n = nF * NF;
+  const int tid = threadIdx.x;
+  const double nnull = (double)nF;
+  // z = Dinv r projected; returns (sum r.z, sum z_0, sum r_0) reduced
+  auto precond = [&](double* red) {
+    double rz = 0.0, s0 = 0.0, r0 = 0.0;
+    for (int F = tid; F < nF; F += kSmallBlock) {
+      double rv[NF];
+#pragma unroll
+      for (int j = 0; j < NF; ++j) rv[j] = r[(long)F * NF + j];
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < NF; ++j) v += Dinv[(long)(i * NF + j) * nF + F] * rv[j];
+        z[(long)F * NF + i] = v;
+        rz += v * rv[i];
+      }
+      s0 += z[(long)F * NF];
+      r0 += rv[0];
+    }
+    red[0] = rz; red[1] = s0; red[2] = r0;
+    small_reduce(red, 3, sh);
+  };
+  for (int i = tid; i < n; i += kSmallBlock) {
+    x[i] = 0.0;
+    r[i] = g[i];
+  }
+  __syncthreads();
+  double red[3];
+  precond(red);
+  double mean = red[1] / nnull;
+  double rz = red[0] - mean * red[2];
+  for (int i = tid; i < n; i += kSmallBlock) p[i] = z[i] - ((i % NF) == 0 ? mean : 0.0);
+  __syncthreads();
+  double rr = 0.0, best = 1e300, low = 1e300;
+  int it = 0, flat = 0, conv = 0, floor_stop = 0;
+  while (it < maxit) {
+    // q = S p and p.q
+    double pq = 0.0;
+    for (int row = tid; row < n; row += kSmallBlock) {
+      const int F = row / NF, i = row - F * NF;
+      double acc = 0.0;
+#pragma unroll
+      for (int s = 0; s < 5; ++s) {
+        const int col = cols[s * nF + F];
+#pragma unroll
+        for (int j = 0; j < NF; ++j) acc += vals[((long)(s * NF + i) * NF + j) * nF + F] * p[(long)col * NF + j];
+      }
+      q[row] = acc;
+      pq += p[row] * acc;
+    }
+    small_reduce(&pq, 1, sh);
+    const double alpha = pq != 0.0 ? rz / pq : 0.0;
+    double u[2] = {0.0, 0.0};
+    for (int row = tid; row < n; row += kSmallBlock) {
+      x[row] += alpha * p[row];
+      const double rv = r[row] - alpha * q[row];
+      r[row] = rv;
+      u[0] += rv * rv;
+      if (row % NF == 0) u[1] += rv;
+    }
+    small_reduce(u, 2, sh);
+    rr = fmax(u[0] - u[1] * u[1] / nnull, 0.0);
+    ++it;
+    if (rr <= tol2) { conv = 1; break; }
+    low = fmin(low, rr);
+    if (it % 4 == 0) {  // blocks of four iterations, as the multi-launch path checks
+      if (low < 0.25 * best) { best = low; flat = 0; }
+      else if (++flat >= flat_blocks && best <= floor2) { floor_stop = 1; break; }
+      low = 1e300;
+    }
+    precond(red);
+    mean = red[1] / nnull;
+    const double rzn = red[0] - mean * red[2];
+    const double beta = rz != 0.0 ? rzn / rz : 0.0;
+    rz = rzn;
+    for (int i = tid; i < n; i += kSmallBlock) p[i] = z[i] - ((i % NF) == 0 ? mean : 0.0) + beta * p[i];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    info[0] = it;
+    info[1] = rr;
+    info[2] = floor_stop;
+    info[3] = conv;
+  }
+}
+
+void launch_pcg_small(int k, hipStream_t st, int nF, const double* vals, const int* cols, const double* Dinv,
+                      const double* g, double* x, double* r, double* z, double* p, double* q, int maxit, double tol2,
+                      double floor2, int flat_blocks, double* info) {
+  HDG_DISPATCH(k, (k_pcg_small<KK><<<1, kSmallBlock, 0, st>>>(nF, vals, cols, Dinv, g, x, r, z, p, q, maxit, tol2,
+                                                              floor2, flat_blocks, info)));
+}
+
 void launch_project(int k, hipStream_t st, DMesh m, DTab t, const double* vals, double* Q) {
   HDG_DISPATCH(k, (k_project<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, vals, Q)));
 }
