@@ -1817,16 +1817,25 @@ __device__ __forceinline__ void small_reduce(double* v, int nv, double* sh) {
   __syncthreads();
 }
 
-template <int K>
+// Up to kSmallLds unknowns the work vectors r, z, p, q live in LDS
+// (4 x 1920 doubles = 60 KiB); beyond that in global memory.
+constexpr int kSmallLds = 1920;
+
+template <int K, bool LDS>
 __global__ void __launch_bounds__(kSmallBlock) k_pcg_small(int nF, const double* __restrict__ vals,
                                                            const int* __restrict__ cols, const double* __restrict__ Dinv,
                                                            const double* __restrict__ g, double* __restrict__ x,
-                                                           double* __restrict__ r, double* __restrict__ z,
-                                                           double* __restrict__ p, double* __restrict__ q, int maxit,
+                                                           double* __restrict__ rg, double* __restrict__ zg,
+                                                           double* __restrict__ pg, double* __restrict__ qg, int maxit,
                                                            double tol2, double floor2, int flat_blocks,
                                                            double* __restrict__ info) {
   constexpr int NF = K + 1;
   __shared__ double sh[3 * (kSmallBlock / 64)];
+  __shared__ double sv[LDS ? 4 : 1][LDS ? kSmallLds : 1];
+  double* r = LDS ? sv[0] : rg;
+  double* z = LDS ? sv[1] : zg;
+  double* p = LDS ? sv[2] : pg;
+  double* q = LDS ? sv[3] : qg;
   const int n = nF * NF;
   const int tid = threadIdx.x;
   const double nnull = (double)nF;
@@ -1918,8 +1927,13 @@ __global__ void __launch_bounds__(kSmallBlock) k_pcg_small(int nF, const double*
 void launch_pcg_small(int k, hipStream_t st, int nF, const double* vals, const int* cols, const double* Dinv,
                       const double* g, double* x, double* r, double* z, double* p, double* q, int maxit, double tol2,
                       double floor2, int flat_blocks, double* info) {
-  HDG_DISPATCH(k, (k_pcg_small<KK><<<1, kSmallBlock, 0, st>>>(nF, vals, cols, Dinv, g, x, r, z, p, q, maxit, tol2,
-                                                              floor2, flat_blocks, info)));
+  if ((long)nF * (k + 1) <= kSmallLds) {
+    HDG_DISPATCH(k, (k_pcg_small<KK, true><<<1, kSmallBlock, 0, st>>>(nF, vals, cols, Dinv, g, x, r, z, p, q, maxit,
+                                                                      tol2, floor2, flat_blocks, info)));
+  } else {
+    HDG_DISPATCH(k, (k_pcg_small<KK, false><<<1, kSmallBlock, 0, st>>>(nF, vals, cols, Dinv, g, x, r, z, p, q, maxit,
+                                                                       tol2, floor2, flat_blocks, info)));
+  }
 }
 
 void launch_project(int k, hipStream_t st, DMesh m, DTab t, const double* vals, double* Q) {
