@@ -286,8 +286,10 @@ int hdg_momentum_residual(hdg_ctx* ctx, double adt, const double* r, const doubl
 int hdg_tentative_velocity(hdg_ctx* ctx, double adt, const double* Qstar, const double* rhs,
                            double* Qbar);
 
-/* Pressure reconstruction (Section "Pressure reconstruction", f = 0): the
- * mixed problem with psi-data Div(psi, (Q.grad_h)Q); returns (p, lam). */
+/* Pressure reconstruction (Section "Pressure reconstruction"): the mixed
+ * problem with psi-data Div(psi, f_p), f_p = -f + (Q.grad_h)Q, and, with a
+ * forcing set, the wall data -<mu n.f>, f taken at the context's time;
+ * returns (p, lam) with int p = 0. */
 int hdg_reconstruct_pressure(hdg_ctx* ctx, const double* Q, double* p, double* lam);
 
 /* enable = N > 0: from now on time every N-th launch of each main kernel
