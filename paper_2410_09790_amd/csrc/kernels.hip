@@ -750,7 +750,10 @@ __device__ __forceinline__ void step1_core(const DMesh& m, const DTab& t, const 
   constexpr int NS = D::NS, NQF = D::NQF;
   // volume: the two lanes of a cell split the rows of V (lane c takes rows
   // 2r + c) and apply them to both components, so that every lane loads
-  // distinct entries; the partner's results come back through pair_swap
+  // distinct entries; the partner's results come back through pair_swap.
+  // V and the upwind weights are read once per application: non-temporal
+  // loads keep them from evicting the velocity vectors (read again by the
+  // neighbouring cells) from the caches.
   {
     double xo[NS];
 #pragma unroll
@@ -761,7 +764,7 @@ __device__ __forceinline__ void step1_core(const DMesh& m, const DTab& t, const 
       double am = 0.0, ao = 0.0;
 #pragma unroll
       for (int i = 0; i < NS; ++i) {
-        const double v = (double)V[tile_idx(e, s * NS + i, NS * NS)];
+        const double v = (double)__builtin_nontemporal_load(&V[tile_idx(e, s * NS + i, NS * NS)]);
         am += v * xv[i];
         ao += v * xo[i];
       }
@@ -786,7 +789,7 @@ __device__ __forceinline__ void step1_core(const DMesh& m, const DTab& t, const 
     const double ncomp = c ? ny : nx;
     double xn[NS], bq[NQF];
 #pragma unroll
-    for (int qq = 0; qq < NQF; ++qq) bq[qq] = beta[tile_idx(e, f * NQF + qq, 3 * NQF)];
+    for (int qq = 0; qq < NQF; ++qq) bq[qq] = __builtin_nontemporal_load(&beta[tile_idx(e, f * NQF + qq, 3 * NQF)]);
     if (en >= 0) {
 #pragma unroll
       for (int s = 0; s < NS; ++s) xn[s] = nb((long)(c * NS + s) * nc + en);
