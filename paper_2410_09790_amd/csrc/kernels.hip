@@ -1802,7 +1802,7 @@ void launch_tracer_rate(int k, hipStream_t st, DMesh m, DTab t, const double* U,
 constexpr int kSmallBlock = 1024;
 
 __device__ __forceinline__ void small_reduce(double* v, int nv, double* sh) {
-  // sh: shared scratch of 3 * (kSmallBlock / 64) doubles; all threads get the sums
+  // sh: shared scratch of nv * (kSmallBlock / 64) doubles; all threads get the sums
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int c = 0; c < nv; ++c) {
     double x = v[c];
@@ -1833,76 +1833,88 @@ __global__ void __launch_bounds__(kSmallBlock) k_pcg_small(int nF, const double*
                                                            double tol2, double floor2, int flat_blocks,
                                                            double* __restrict__ info) {
   constexpr int NF = K + 1;
-  __shared__ double sh[3 * (kSmallBlock / 64)];
+  __shared__ double sh[4 * (kSmallBlock / 64)];
   __shared__ double sv[LDS ? 4 : 1][LDS ? kSmallLds : 1];
   double* r = LDS ? sv[0] : rg;
   double* z = LDS ? sv[1] : zg;
   double* p = LDS ? sv[2] : pg;
   double* q = LDS ? sv[3] : qg;
-  const int n = nF * NF;
   const int tid = threadIdx.x;
   const double nnull = (double)nF;
-  // z = Dinv r projected; returns (sum r.z, sum z_0, sum r_0) reduced
-  auto precond = [&](double* red) {
-    double rz = 0.0, s0 = 0.0, r0 = 0.0;
-    for (int F = tid; F < nF; F += kSmallBlock) {
-      double rv[NF];
+  // Every pass below maps a thread to whole facets, so q, r and z of a facet
+  // are written and read by the same thread and only p (read across facets
+  // by S p) needs a barrier between passes.
+  // z_F = Dinv_F r_F; red = (r.r, sum r_0, r.z, sum z_0)
+  auto precond_facet = [&](int F, double* red) {
+    double rv[NF];
 #pragma unroll
-      for (int j = 0; j < NF; ++j) rv[j] = r[(long)F * NF + j];
+    for (int j = 0; j < NF; ++j) rv[j] = r[F * NF + j];
 #pragma unroll
-      for (int i = 0; i < NF; ++i) {
-        double v = 0.0;
+    for (int i = 0; i < NF; ++i) {
+      double v = 0.0;
 #pragma unroll
-        for (int j = 0; j < NF; ++j) v += Dinv[(long)(i * NF + j) * nF + F] * rv[j];
-        z[(long)F * NF + i] = v;
-        rz += v * rv[i];
-      }
-      s0 += z[(long)F * NF];
-      r0 += rv[0];
+      for (int j = 0; j < NF; ++j) v += Dinv[(long)(i * NF + j) * nF + F] * rv[j];
+      z[F * NF + i] = v;
+      red[0] += rv[i] * rv[i];
+      red[2] += rv[i] * v;
     }
-    red[0] = rz; red[1] = s0; red[2] = r0;
-    small_reduce(red, 3, sh);
+    red[1] += rv[0];
+    red[3] += z[F * NF];
   };
-  for (int i = tid; i < n; i += kSmallBlock) {
-    x[i] = 0.0;
-    r[i] = g[i];
+  double red[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int F = tid; F < nF; F += kSmallBlock) {
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      x[(long)F * NF + i] = 0.0;
+      r[F * NF + i] = g[(long)F * NF + i];
+    }
+    precond_facet(F, red);
   }
-  __syncthreads();
-  double red[3];
-  precond(red);
-  double mean = red[1] / nnull;
-  double rz = red[0] - mean * red[2];
-  for (int i = tid; i < n; i += kSmallBlock) p[i] = z[i] - ((i % NF) == 0 ? mean : 0.0);
+  small_reduce(red, 4, sh);
+  double mean = red[3] / nnull;
+  double rz = red[2] - mean * red[1];
+  for (int F = tid; F < nF; F += kSmallBlock)
+#pragma unroll
+    for (int i = 0; i < NF; ++i) p[F * NF + i] = z[F * NF + i] - (i == 0 ? mean : 0.0);
   __syncthreads();
   double rr = 0.0, best = 1e300, low = 1e300;
   int it = 0, flat = 0, conv = 0, floor_stop = 0;
   while (it < maxit) {
     // q = S p and p.q
     double pq = 0.0;
-    for (int row = tid; row < n; row += kSmallBlock) {
-      const int F = row / NF, i = row - F * NF;
-      double acc = 0.0;
+    for (int F = tid; F < nF; F += kSmallBlock) {
+      double pc[5][NF];
 #pragma unroll
       for (int s = 0; s < 5; ++s) {
         const int col = cols[s * nF + F];
 #pragma unroll
-        for (int j = 0; j < NF; ++j) acc += vals[((long)(s * NF + i) * NF + j) * nF + F] * p[(long)col * NF + j];
+        for (int j = 0; j < NF; ++j) pc[s][j] = p[col * NF + j];
       }
-      q[row] = acc;
-      pq += p[row] * acc;
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        double acc = 0.0;
+#pragma unroll
+        for (int s = 0; s < 5; ++s)
+#pragma unroll
+          for (int j = 0; j < NF; ++j) acc += vals[((long)(s * NF + i) * NF + j) * nF + F] * pc[s][j];
+        q[F * NF + i] = acc;
+        pq += p[F * NF + i] * acc;
+      }
     }
     small_reduce(&pq, 1, sh);
     const double alpha = pq != 0.0 ? rz / pq : 0.0;
-    double u[2] = {0.0, 0.0};
-    for (int row = tid; row < n; row += kSmallBlock) {
-      x[row] += alpha * p[row];
-      const double rv = r[row] - alpha * q[row];
-      r[row] = rv;
-      u[0] += rv * rv;
-      if (row % NF == 0) u[1] += rv;
+    // x, r updates and the preconditioner, facet by facet
+    red[0] = red[1] = red[2] = red[3] = 0.0;
+    for (int F = tid; F < nF; F += kSmallBlock) {
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        x[(long)F * NF + i] += alpha * p[F * NF + i];
+        r[F * NF + i] -= alpha * q[F * NF + i];
+      }
+      precond_facet(F, red);
     }
-    small_reduce(u, 2, sh);
-    rr = fmax(u[0] - u[1] * u[1] / nnull, 0.0);
+    small_reduce(red, 4, sh);
+    rr = fmax(red[0] - red[1] * red[1] / nnull, 0.0);
     ++it;
     if (rr <= tol2) { conv = 1; break; }
     low = fmin(low, rr);
@@ -1911,12 +1923,13 @@ __global__ void __launch_bounds__(kSmallBlock) k_pcg_small(int nF, const double*
       else if (++flat >= flat_blocks && best <= floor2) { floor_stop = 1; break; }
       low = 1e300;
     }
-    precond(red);
-    mean = red[1] / nnull;
-    const double rzn = red[0] - mean * red[2];
+    mean = red[3] / nnull;
+    const double rzn = red[2] - mean * red[1];
     const double beta = rz != 0.0 ? rzn / rz : 0.0;
     rz = rzn;
-    for (int i = tid; i < n; i += kSmallBlock) p[i] = z[i] - ((i % NF) == 0 ? mean : 0.0) + beta * p[i];
+    for (int F = tid; F < nF; F += kSmallBlock)
+#pragma unroll
+      for (int i = 0; i < NF; ++i) p[F * NF + i] = z[F * NF + i] - (i == 0 ? mean : 0.0) + beta * p[F * NF + i];
     __syncthreads();
   }
   if (tid == 0) {
