@@ -1,0 +1,92 @@
+"""Edge cases of the GPU path through the C ABI.
+
+* the smallest mesh (one square, two cells: a single interior facet) and the
+  highest degree (k = 4) step in agreement with the oracle;
+* zero data gives exact zeros (trace solve, Step I, a zero state stays zero);
+* zero steps change nothing, and calls out of order are refused.
+"""
+import numpy as np
+import pytest
+
+import hdg_inputs as hi
+from oracle.forms import Discretisation
+from oracle.imex import IMEXHDG, ars222, ssp3_433
+
+from gpu_util import context, dev, host, mesh, rel_l2_cells, rel_l2_trace, torch_or_skip
+
+pytestmark = pytest.mark.gpu
+
+
+def _both(n, k, tab, scheme, nsteps, dt, pert=0.0, seed=0, solver="mg_pcg"):
+    X, C = mesh(n, pert)
+    d = Discretisation(X, C, k)
+    par = hi.stream_function_params(seed)
+    vel = lambda x, y: hi.streamfunction_velocity(par, x, y)
+    st = IMEXHDG(d, dt, tab, 2)
+    Q, p, lam = st.initial_state(vel)
+    Q, p, lam = st.run(Q, p, lam, 0.0, nsteps)
+    ctx = context(X, C, degree=k, imex=scheme, n_richardson=2, trace_solver=solver, rtol_trace=1e-13,
+                  rtol_velocity=1e-13)
+    xy = ctx.cell_points()
+    ctx.set_velocity_from_points(vel(xy[..., 0], xy[..., 1]))
+    ctx.advance(dt, nsteps)
+    return d, (Q, p, lam), [host(t) for t in ctx.get_state()], ctx
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_one_square_mesh(k):
+    torch_or_skip()
+    d, ref, got, ctx = _both(1, k, ars222(), "ars222", 2, 1e-2, solver="jacobi_pcg")
+    assert ctx.ncells == 2 and ctx.nfacets == 5
+    assert rel_l2_cells(d, got[0], ref[0], d.nu) < 1e-10
+    assert rel_l2_cells(d, got[1], ref[1], d.npp) < 1e-9
+    assert rel_l2_trace(d, got[2], ref[2]) < 1e-9
+
+
+@pytest.mark.parametrize("scheme,tab", [("ars222", ars222), ("ssp3_433", ssp3_433)])
+def test_highest_degree_steps(scheme, tab):
+    torch_or_skip()
+    d, ref, got, _ = _both(3, 4, tab(), scheme, 2, 5e-3, pert=0.2, seed=4)
+    assert rel_l2_cells(d, got[0], ref[0], d.nu) < 1e-10
+    assert rel_l2_cells(d, got[1], ref[1], d.npp) < 1e-9
+    assert rel_l2_trace(d, got[2], ref[2]) < 1e-9
+
+
+@pytest.mark.parametrize("solver", ["jacobi_pcg", "mg_pcg"])
+def test_zero_data_gives_zeros(solver):
+    torch = torch_or_skip()
+    X, C = mesh(6, 0.1)
+    ctx = context(X, C, degree=2, trace_solver=solver)
+    U, p, lam = (host(t) for t in ctx.solve_trace(0.3))  # null data means zero
+    assert not U.any() and not p.any() and not lam.any()
+    Qs = dev(torch, np.random.default_rng(1).standard_normal(ctx.nQ))
+    Qbar = host(ctx.tentative_velocity(1e-3, Qs, dev(torch, np.zeros(ctx.nQ))))
+    assert not Qbar.any()
+    z = [dev(torch, np.zeros(n)) for n in (ctx.nQ, ctx.nP, ctx.nT)]
+    ctx.set_state(*z)
+    ctx.advance(1e-3, 2)
+    for t in ctx.get_state():
+        assert not host(t).any()
+
+
+def test_zero_steps_and_call_order():
+    torch = torch_or_skip()
+    from paper_2410_09790_amd import hdg
+    X, C = mesh(4, 0.1)
+    ctx = context(X, C, degree=1)
+    with pytest.raises(hdg.HDGError, match="BAD_STATE"):
+        ctx.advance(1e-3, 1)  # no state yet
+    with pytest.raises(hdg.HDGError, match="BAD_STATE"):
+        ctx.get_state()
+    par = hi.stream_function_params(2)
+    xy = ctx.cell_points()
+    ctx.set_velocity_from_points(hi.streamfunction_velocity(par, xy[..., 0], xy[..., 1]))
+    before = [host(t) for t in ctx.get_state()]
+    ctx.advance(1e-3, 0)
+    after = [host(t) for t in ctx.get_state()]
+    for x, y in zip(before, after):
+        assert np.array_equal(x, y)
+    with pytest.raises(hdg.HDGError, match="INVALID_ARG"):
+        ctx.advance(-1e-3, 1)
+    with pytest.raises(hdg.HDGError, match="BAD_STATE"):
+        ctx.get_tracer()  # no tracer set
