@@ -240,15 +240,16 @@ def shear_layer_run(hdg, hi, torch, nsteps: int = 5):
 L_SHEAR = 2.0 * 3.141592653589793
 
 
-def batched_run(hdg, hi, torch, ninst: int = 4):
+def batched_run(hdg, hi, torch, ninst: int = 4, steps: int = 1):
     """A bounded sample of the batched workload: instances j = 0..ninst-1 with
     n = integers(32, 257), k = integers(1, 5) drawn from default_rng(j) and
     the seed-j stream-function data; ARS(2,2,2), dt = 1e-3, n_R = 3, MG-PCG,
     the paper's tolerances.  One untimed warm-up step (operator builds, graph
-    capture), then one timed step of every instance one after another (FP64),
-    one timed step of all of them as one hdg_batch on distinct streams (FP64),
-    and the same with FP32 cell-matrix storage (Step I rtol 1e-5).  The mixed
-    states after two steps are compared with the FP64 states after two."""
+    capture), then `steps` timed steps of every instance one after another
+    (FP64), `steps` timed steps of all of them as one hdg_batch on distinct
+    streams (FP64), and the same with FP32 cell-matrix storage (Step I rtol
+    1e-5).  The mixed states after 1 + steps steps are compared with the FP64
+    states after as many."""
     import numpy as np
     specs = []
     for j in range(ninst):
@@ -271,13 +272,32 @@ def batched_run(hdg, hi, torch, ninst: int = 4):
 
     dt = 1e-3
     streams = [torch.cuda.Stream() for _ in specs]
-    f64 = [make(n, k, par, s, rtol_velocity=1e-10) for (par, n, k), s in zip(specs, streams)]
-    work = sum(c.nT * 2 for c in f64)  # trace DOF-stages of one step of every instance
+    f64 = []
+    for (par, n, k), s in zip(specs, streams):
+        f64.append(make(n, k, par, s, rtol_velocity=1e-10))
+        if len(f64) % 8 == 0:
+            log(f"batched: {len(f64)} of {len(specs)} FP64 instances set up")
+    work = sum(c.nT * 2 for c in f64) * steps  # trace DOF-stages of `steps` steps of every instance
     bf = hdg.Batch(f64)
     bf.advance(dt, 1)  # warm-up
-    t_seq = timed(lambda: [c.advance(dt, 1) for c in f64])
+    log("batched: FP64 warm-up step done")
+
+    def one_by_one():
+        for i, c in enumerate(f64):
+            c.advance(dt, steps)
+            if (i + 1) % 8 == 0:
+                log(f"batched: {i + 1} of {len(f64)} instances advanced one at a time")
+
+    t_seq = timed(one_by_one)
     ref = [tuple(t.cpu().numpy() for t in c.get_state()) for c in f64]
-    t_bat = timed(lambda: bf.advance(dt, 1))
+    def batch_steps(b, what):
+        for i in range(steps):  # one step per call: a progress line per step
+            b.advance(dt, 1)
+            if steps > 1:
+                log(f"batched: {what} step {i + 1} of {steps}")
+
+    t_bat = timed(lambda: batch_steps(bf, "FP64"))
+    log(f"batched: FP64 one at a time {t_seq:.1f} s, as one batch {t_bat:.1f} s")
     bf.close()
     for c in f64:
         c.close()
@@ -286,7 +306,8 @@ def batched_run(hdg, hi, torch, ninst: int = 4):
           for (par, n, k), s in zip(specs, mstreams)]
     bm = hdg.Batch(mx)
     bm.advance(dt, 1)  # warm-up
-    t_mix = timed(lambda: bm.advance(dt, 1))
+    log("batched: mixed warm-up step done")
+    t_mix = timed(lambda: batch_steps(bm, "mixed"))
     diff = 0.0
     for c, (Q, p, lam) in zip(mx, ref):
         Qm, pm, lm = (t.cpu().numpy() for t in c.get_state())
@@ -296,7 +317,8 @@ def batched_run(hdg, hi, torch, ninst: int = 4):
     for c in mx:
         c.close()
     out = {"workload": "batched sample: instances " + ", ".join(f"{n}x{n} k={k}" for _, n, k in specs) +
-                       " (draws j = 0..%d of the batched recipe), ARS(2,2,2), dt=1e-3, n_R=3, one step each" % (ninst - 1),
+                       " (draws j = 0..%d of the batched recipe), ARS(2,2,2), dt=1e-3, n_R=3, %d timed step(s) each"
+                       % (ninst - 1, steps),
            "unit": "trace-DOF-stages/s",
            "fp64_one_at_a_time": work / t_seq, "fp64_batched": work / t_bat, "mixed_batched": work / t_mix,
            "mixed_max_rel_l2_diff_vs_fp64": diff,
@@ -383,6 +405,10 @@ def main():
     ap.add_argument("--no-shear", action="store_true", help="skip the periodic shear-layer run")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-instances sample")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sample")
+    ap.add_argument("--batched-instances", type=int, default=4, help="instances of the batched sample (recipe: 64)")
+    ap.add_argument("--batched-steps", type=int, default=1, help="timed steps of the batched sample (recipe: 10)")
+    ap.add_argument("--serving-jobs", type=int, default=16, help="jobs of the serving sample (recipe: 200)")
+    ap.add_argument("--serving-nmax", type=int, default=48, help="mesh size cap of the serving sample (recipe: 512)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -484,10 +510,10 @@ def main():
         shear = shear_layer_run(hdg, hi, torch)
     batched = None
     if not args.no_batched:
-        batched = batched_run(hdg, hi, torch)
+        batched = batched_run(hdg, hi, torch, args.batched_instances, args.batched_steps)
     serving = None
     if not args.no_serving:
-        serving = serving_run(hdg, hi, torch)
+        serving = serving_run(hdg, hi, torch, args.serving_jobs, args.serving_nmax)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
