@@ -255,7 +255,7 @@ struct hdg_ctx {
   static constexpr long kSmallTrace = 24576;  // trace unknowns up to which Jacobi-PCG runs in one workgroup
   double* small_info = nullptr;
   int pcg_small(hdg::TraceOp& op, const double* gin, double gnorm, double* x);
-  static constexpr double kPcgFloor = 100.0;
+  static constexpr double kPcgFloor = 1e4;
   double t_trace = 0.0, t_velocity = 0.0, t_other = 0.0;
   int max_pcg_bicg_seen = 0;
   bool not_converged = false;
@@ -715,8 +715,9 @@ int hdg_ctx::pcg(TraceOp& op, const double* gin, double* x) {
     }
     it += kPcgBlock;
     // Round-off floor: with rtol near eps times the condition number of S
-    // (1e-12 against ~3e4 at 64 x 64, c = 1) the recursion can stop
-    // improving just above rtol on smooth data.  A residual that has not
+    // (1e-12 against ~3e4 at 64 x 64, k = 3, c = 1, and more at higher k and
+    // finer meshes) the recursion can stop improving above rtol on smooth
+    // data.  A residual that has not
     // halved over kPcgFlatBlocks blocks while within kPcgFloor * rtol is
     // accepted (and counted) instead of running to the cap.
     if (low < 0.5 * best) {
