@@ -245,13 +245,16 @@ int hdg_tracer_rate(hdg_ctx* ctx, const double* Q, const double* q, double* out)
 int hdg_eval_points(hdg_ctx* ctx, const double* xy_ref, int npts, double* Q_out, double* p_out);
 
 /* Host-side mesh of the square [0, length]^2 cut into n x n squares, each
- * split along its "/" diagonal (the paper's test meshes): vertex (i, j) has
- * id j (n+1) + i at (i, j) length / n; square (i, j) gives the cells
- * (v00, v10, v11) and (v00, v11, v01), ids 2 (j n + i) and 2 (j n + i) + 1.
- * coords: [(n+1)^2][2], cells: [2 n^2][3], vertex_rep: [(n+1)^2] or NULL
- * when periodic = 0 (then the identity); with periodic = 1 (n >= 3) the right
- * and top vertices map to their left and bottom copies (hdg_create_periodic). */
-int hdg_mesh_square(int n, double length, int periodic, double* coords, int32_t* cells, int32_t* vertex_rep);
+ * split along a diagonal (the paper's test meshes): vertex (i, j) has id
+ * j (n+1) + i at (i, j) length / n; square (i, j) gives the cells with ids
+ * 2 (j n + i) and 2 (j n + i) + 1: (v00, v10, v11) and (v00, v11, v01) for
+ * diagonal = 0 (the "/" diagonal), (v00, v10, v01) and (v10, v11, v01) for
+ * diagonal = 1 ("\"), all counter-clockwise.  coords: [(n+1)^2][2], cells:
+ * [2 n^2][3], vertex_rep: [(n+1)^2] or NULL when periodic = 0 (then the
+ * identity); with periodic = 1 (n >= 3) the right and top vertices map to
+ * their left and bottom copies (hdg_create_periodic). */
+int hdg_mesh_square(int n, double length, int diagonal, int periodic, double* coords, int32_t* cells,
+                    int32_t* vertex_rep);
 
 /* One hybridised mixed solve (paper, Section "Solvers and preconditioners"):
  * find (U, p, lam) with

@@ -1729,8 +1729,11 @@ int hdg_eval_points(hdg_ctx* ctx, const double* xy_ref, int npts, double* Qo, do
   API_END(ctx)
 }
 
-int hdg_mesh_square(int n, double length, int periodic, double* coords, int32_t* cells, int32_t* vertex_rep) {
-  if (n < 1 || !(length > 0) || !coords || !cells || (periodic && (!vertex_rep || n < 3))) return HDG_ERR_INVALID_ARG;
+int hdg_mesh_square(int n, double length, int diagonal, int periodic, double* coords, int32_t* cells,
+                    int32_t* vertex_rep) {
+  if (n < 1 || !(length > 0) || !coords || !cells || (periodic && (!vertex_rep || n < 3)) || diagonal < 0 ||
+      diagonal > 1)
+    return HDG_ERR_INVALID_ARG;
   const int64_t m = n + 1;
   if ((int64_t)n * n * 2 > INT32_MAX / 3) return HDG_ERR_INVALID_ARG;
   for (int64_t j = 0; j < m; ++j)
@@ -1744,8 +1747,13 @@ int hdg_mesh_square(int n, double length, int periodic, double* coords, int32_t*
     for (int64_t i = 0; i < n; ++i) {
       const int32_t v00 = (int32_t)(j * m + i), v10 = v00 + 1, v01 = (int32_t)(v00 + m), v11 = v01 + 1;
       int32_t* c = cells + 6 * (j * n + i);
-      c[0] = v00; c[1] = v10; c[2] = v11;  // below the "/" diagonal
-      c[3] = v00; c[4] = v11; c[5] = v01;  // above it
+      if (diagonal == 0) {
+        c[0] = v00; c[1] = v10; c[2] = v11;  // below the "/" diagonal
+        c[3] = v00; c[4] = v11; c[5] = v01;  // above it
+      } else {
+        c[0] = v00; c[1] = v10; c[2] = v01;  // below the "\" diagonal
+        c[3] = v10; c[4] = v11; c[5] = v01;  // above it
+      }
     }
   return HDG_OK;
 }

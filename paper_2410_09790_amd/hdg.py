@@ -83,7 +83,7 @@ def load_library(path: str = LIB_PATH):
         "hdg_advance_stages": (I, [P, D, I]),
         "hdg_pending_stage": (I, [P]),
         "hdg_eval_points": (I, [P, P, I, P, P]),
-        "hdg_mesh_square": (I, [I, D, I, P, P, P]),
+        "hdg_mesh_square": (I, [I, D, I, I, P, P, P]),
         "hdg_set_tracer": (I, [P, P]),
         "hdg_get_tracer": (I, [P, P]),
         "hdg_cg_project": (I, [P, P, P]),
@@ -386,14 +386,16 @@ class Batch:
             pass
 
 
-def mesh_square(n: int, length: float = 1.0, periodic: bool = False):
-    """The library's split-square mesh of [0, length]^2: (coords, cells, vertex_rep)."""
+def mesh_square(n: int, length: float = 1.0, periodic: bool = False, diagonal: int = 0):
+    """The library's split-square mesh of [0, length]^2 (diagonal 0: "/", 1: "\\"):
+    (coords, cells, vertex_rep)."""
     lib = load_library()
     coords = np.empty(((n + 1) ** 2, 2), dtype=np.float64)
     cells = np.empty((2 * n * n, 3), dtype=np.int32)
     rep = np.empty((n + 1) ** 2, dtype=np.int32)
-    st = lib.hdg_mesh_square(int(n), float(length), int(bool(periodic)), coords.ctypes.data_as(ctypes.c_void_p),
-                             cells.ctypes.data_as(ctypes.c_void_p), rep.ctypes.data_as(ctypes.c_void_p))
+    st = lib.hdg_mesh_square(int(n), float(length), int(diagonal), int(bool(periodic)),
+                             coords.ctypes.data_as(ctypes.c_void_p), cells.ctypes.data_as(ctypes.c_void_p),
+                             rep.ctypes.data_as(ctypes.c_void_p))
     if st != 0:
         raise HDGError(st, "invalid mesh size")
     return coords, cells, rep

@@ -186,3 +186,18 @@ def test_library_mesh_follows_the_documented_recipe(lib_path, n, periodic):
     assert np.allclose(X, Xr, rtol=0, atol=1e-14) and np.array_equal(C, Cr)
     with pytest.raises(hdg.HDGError):
         hdg.mesh_square(2, 1.0, True)
+
+
+def test_library_mesh_other_diagonal(lib_path):
+    """The "\\" split: same vertices, counter-clockwise cells, the same facet
+    count; the host mesh check (via hdg_footprint_bytes) accepts it."""
+    from paper_2410_09790_amd import hdg
+    X, C, _ = hdg.mesh_square(5, 1.0, diagonal=1)
+    X0, C0, _ = hdg.mesh_square(5, 1.0)
+    assert np.array_equal(X, X0) and not np.array_equal(C, C0)
+    v = X[C]
+    det = (v[:, 1, 0] - v[:, 0, 0]) * (v[:, 2, 1] - v[:, 0, 1]) - (v[:, 2, 0] - v[:, 0, 0]) * (v[:, 1, 1] - v[:, 0, 1])
+    assert (det > 0).all() and np.allclose(det, (1 / 5) ** 2)
+    assert hdg.footprint_bytes(X, C, 1e-3, degree=2) > 0
+    Xp, Cp, rep = hdg.mesh_square(4, 2.0, periodic=True, diagonal=1)
+    assert hdg.footprint_bytes(Xp, Cp, 1e-3, vertex_rep=rep, degree=1) > 0

@@ -90,3 +90,28 @@ def test_zero_steps_and_call_order():
         ctx.advance(-1e-3, 1)
     with pytest.raises(hdg.HDGError, match="BAD_STATE"):
         ctx.get_tracer()  # no tracer set
+
+
+def test_other_diagonal_steps():
+    """Meshes split along the other diagonal (hdg_mesh_square, diagonal = 1):
+    two steps against the oracle on the walled and on the periodic square."""
+    torch_or_skip()
+    from paper_2410_09790_amd import hdg
+    from oracle.mesh import Mesh
+    par = hi.stream_function_params(6)
+    for periodic in (False, True):
+        X, C, rep = hdg.mesh_square(4, 2.0 * np.pi if periodic else 1.0, periodic, diagonal=1)
+        vel = hi.shear_layer_velocity if periodic else (lambda x, y: hi.streamfunction_velocity(par, x, y))
+        d = Discretisation(Mesh(X, C, rep if periodic else None), None, 2)
+        st = IMEXHDG(d, 1e-2, ars222(), 2)
+        Q, p, lam = st.initial_state(vel)
+        Q, p, lam = st.run(Q, p, lam, 0.0, 2)
+        ctx = context(X, C, vertex_rep=rep if periodic else None, degree=2, imex="ars222", n_richardson=2,
+                      rtol_trace=1e-13, rtol_velocity=1e-13)
+        xy = ctx.cell_points()
+        ctx.set_velocity_from_points(vel(xy[..., 0], xy[..., 1]))
+        ctx.advance(1e-2, 2)
+        got = [host(t) for t in ctx.get_state()]
+        assert rel_l2_cells(d, got[0], Q, d.nu) < 1e-10
+        assert rel_l2_cells(d, got[1], p, d.npp) < 1e-9
+        assert rel_l2_trace(d, got[2], lam) < 1e-9
