@@ -1919,7 +1919,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_pcg_small(int nF, const double*
     if (rr <= tol2) { conv = 1; break; }
     low = fmin(low, rr);
     if (it % 4 == 0) {  // blocks of four iterations, as the multi-launch path checks
-      if (low < 0.25 * best) { best = low; flat = 0; }
+      if (low < 0.9801 * best) { best = low; flat = 0; }  // squared norms: 1 % per block
       else if (++flat >= flat_blocks && best <= floor2) { floor_stop = 1; break; }
       low = 1e300;
     }

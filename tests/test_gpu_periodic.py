@@ -127,6 +127,6 @@ def test_trace_solve_round_off_floor_is_accepted():
         out.append((host(ctx.get_state()[1]), info))
         ctx.close()
     (p12, i12), (p10, i10) = out
-    assert i12["pcg_floor_stops"] >= 1 and i12["pcg_iterations_last"][-1] < 100
+    assert i12["pcg_floor_stops"] >= 1 and i12["pcg_iterations_last"][-1] < 200  # floor reached by ~20, then a 100-iteration window
     assert i10["pcg_floor_stops"] == 0
     assert np.linalg.norm(p12 - p10) <= 1e-8 * np.linalg.norm(p10)
