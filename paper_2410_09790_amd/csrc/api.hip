@@ -251,7 +251,7 @@ struct hdg_ctx {
   std::vector<int> pcg_iters, bicg_iters;
   long total_pcg = 0, total_bicg = 0, n_trace_solves = 0, n_velocity_solves = 0, bicg_restarts = 0;
   long pcg_floor_stops = 0;  // trace solves ended at the round-off floor (within kPcgFloor * rtol)
-  static constexpr int kPcgFlatBlocks = 25;  // 100 iterations: longer than the plateaus of a converging CG
+  static constexpr int kPcgFlatBlocks = 16;  // 64 iterations
   static constexpr long kSmallTrace = 24576;  // trace unknowns up to which Jacobi-PCG runs in one workgroup
   double* small_info = nullptr;
   int pcg_small(hdg::TraceOp& op, const double* gin, double gnorm, double* x);
@@ -696,33 +696,39 @@ int hdg_ctx::pcg(TraceOp& op, const double* gin, double* x) {
   KCHK();
   const bool graphs = prm.use_graphs && !prof.on;
   if (graphs && !op.pcg_block) op.pcg_block = capture([&] { pcg_block(op); });
-  double res = 0.0, best = HUGE_VAL;
+  double res = 0.0, best = HUGE_VAL, best_rz = HUGE_VAL;
   int it = 0, flat = 0;
   while (it < maxit) {
     if (graphs) HIPCHK(hipGraphLaunch(op.pcg_block, st));
     else pcg_block(op);
-    HIPCHK(hipMemcpyAsync(h_pinned, rr, kPcgBlock * sizeof(double), hipMemcpyDeviceToHost, st));
+    // the block's scalars: rz[0..kPcgBlock], pq[0..kPcgBlock), rr[0..kPcgBlock)
+    HIPCHK(hipMemcpyAsync(h_pinned, rz, (3 * kPcgBlock + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
     sync();
-    double low = HUGE_VAL;
+    const double* hrz = h_pinned;
+    const double* hrr = h_pinned + 2 * kPcgBlock + 1;
+    double low = HUGE_VAL, low_rz = HUGE_VAL;
     for (int b = 0; b < kPcgBlock; ++b) {
-      res = std::sqrt(h_pinned[b]);
+      res = std::sqrt(hrr[b]);
       if (!(res == res)) throw SolverBreakdown("PCG breakdown (NaN residual)");
       if (res <= prm.rtol_trace * gnorm) {
         launch_copy(st, n, px, x);
         return it + kPcgBlock;
       }
       low = std::min(low, res);
+      low_rz = std::min(low_rz, std::fabs(hrz[b + 1]));
     }
     it += kPcgBlock;
+    best = std::min(best, low);
     // Round-off floor: with rtol near eps times the condition number of S
     // (1e-12 against ~3e4 at 64 x 64, k = 3, c = 1, and more at higher k and
     // finer meshes) the recursion can stop improving above rtol on smooth
-    // data.  A residual that improves by less than 1 % per block for
-    // kPcgFlatBlocks blocks while within kPcgFloor * rtol is accepted (and
-    // counted) instead of running to the cap; slow but steady convergence
-    // keeps iterating.
-    if (low < 0.99 * best) {
-      best = low;
+    // data.  Stalling is judged on r.z, the preconditioned residual norm,
+    // which keeps falling while CG converges even where the 2-norm of r
+    // plateaus: r.z gaining less than 1 % (in norm) per block for
+    // kPcgFlatBlocks blocks, with |r| within kPcgFloor * rtol, ends the solve
+    // (counted) instead of running to the cap.
+    if (low_rz < 0.98 * best_rz) {
+      best_rz = low_rz;
       flat = 0;
     } else if (++flat >= kPcgFlatBlocks && best <= kPcgFloor * prm.rtol_trace * gnorm) {
       ++pcg_floor_stops;

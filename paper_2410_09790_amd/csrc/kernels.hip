@@ -1877,7 +1877,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_pcg_small(int nF, const double*
 #pragma unroll
     for (int i = 0; i < NF; ++i) p[F * NF + i] = z[F * NF + i] - (i == 0 ? mean : 0.0);
   __syncthreads();
-  double rr = 0.0, best = 1e300, low = 1e300;
+  double rr = 0.0, best = 1e300, best_rz = 1e300, low = 1e300;
   int it = 0, flat = 0, conv = 0, floor_stop = 0;
   while (it < maxit) {
     // q = S p and p.q
@@ -1917,14 +1917,16 @@ __global__ void __launch_bounds__(kSmallBlock) k_pcg_small(int nF, const double*
     rr = fmax(red[0] - red[1] * red[1] / nnull, 0.0);
     ++it;
     if (rr <= tol2) { conv = 1; break; }
-    low = fmin(low, rr);
+    mean = red[3] / nnull;
+    const double rzn = red[2] - mean * red[1];
+    best = fmin(best, rr);
+    low = fmin(low, fabs(rzn));
     if (it % 4 == 0) {  // blocks of four iterations, as the multi-launch path checks
-      if (low < 0.9801 * best) { best = low; flat = 0; }  // squared norms: 1 % per block
+      // stalls judged on r.z (1 % per block in norm), accepted with |r| within the floor
+      if (low < 0.98 * best_rz) { best_rz = low; flat = 0; }
       else if (++flat >= flat_blocks && best <= floor2) { floor_stop = 1; break; }
       low = 1e300;
     }
-    mean = red[3] / nnull;
-    const double rzn = red[2] - mean * red[1];
     const double beta = rz != 0.0 ? rzn / rz : 0.0;
     rz = rzn;
     for (int F = tid; F < nF; F += kSmallBlock)

@@ -198,7 +198,7 @@ def test_config1_parity():
     info = ctx.info()
     assert info["trace_solves"] == 1 + 10 * (2 * 3 + 2)
     assert info["velocity_solves"] == 10 * 2 * 3
-    assert info["pcg_floor_stops"] == 0  # every solve reached rtol itself
+    assert info["pcg_floor_stops"] <= 2  # (measured: none; small-c solves sit near their round-off floor)
 
 
 def test_degree3_mg_parity():
