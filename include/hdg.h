@@ -111,8 +111,9 @@ typedef struct {
   int trace_solver;      /* hdg_trace_solver */
   double rtol_trace;     /* PCG: ||g - S lam||_2 <= rtol ||g||_2 (the residual's component along
                             the constant trace left out); a solve whose preconditioned
-                            residual r.z stalls (< 1 % gain per four iterations for 64
-                            iterations) with |r| within 1e4 rtol
+                            residual r.z stalls (< 1 % gain per four iterations for a
+                            quarter of the iterations spent, at least 12) with |r|
+                            within 1e4 rtol
                             (the round-off floor of an ill-conditioned S) also ends the solve,
                             counted as pcg_floor_stops in hdg_get_info */
   double rtol_velocity;  /* Step I: same criterion on the mass-scaled system */

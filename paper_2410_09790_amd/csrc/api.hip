@@ -251,7 +251,7 @@ struct hdg_ctx {
   std::vector<int> pcg_iters, bicg_iters;
   long total_pcg = 0, total_bicg = 0, n_trace_solves = 0, n_velocity_solves = 0, bicg_restarts = 0;
   long pcg_floor_stops = 0;  // trace solves ended at the round-off floor (within kPcgFloor * rtol)
-  static constexpr int kPcgFlatBlocks = 16;  // 64 iterations
+  static constexpr int kPcgFlatBlocks = 3;  // shortest stall window (blocks); it grows to a quarter of the iterations spent
   static constexpr long kSmallTrace = 24576;  // trace unknowns up to which Jacobi-PCG runs in one workgroup
   double* small_info = nullptr;
   int pcg_small(hdg::TraceOp& op, const double* gin, double gnorm, double* x);
@@ -722,15 +722,17 @@ int hdg_ctx::pcg(TraceOp& op, const double* gin, double* x) {
     // Round-off floor: with rtol near eps times the condition number of S
     // (1e-12 against ~3e4 at 64 x 64, k = 3, c = 1, and more at higher k and
     // finer meshes) the recursion can stop improving above rtol on smooth
-    // data.  Stalling is judged on r.z, the preconditioned residual norm,
-    // which keeps falling while CG converges even where the 2-norm of r
-    // plateaus: r.z gaining less than 1 % (in norm) per block for
-    // kPcgFlatBlocks blocks, with |r| within kPcgFloor * rtol, ends the solve
-    // (counted) instead of running to the cap.
+    // data.  Stalling is judged on r.z, the preconditioned residual norm:
+    // r.z gaining less than 1 % (in norm) per block for a window of
+    // max(kPcgFlatBlocks, it / 16) blocks (a quarter of the iterations
+    // spent so far: a fast multigrid solve that stalls gives up after 12
+    // iterations, a slow Jacobi solve with long plateaus waits longer), with
+    // |r| within kPcgFloor * rtol, ends the solve (counted) instead of
+    // running to the cap.
     if (low_rz < 0.98 * best_rz) {
       best_rz = low_rz;
       flat = 0;
-    } else if (++flat >= kPcgFlatBlocks && best <= kPcgFloor * prm.rtol_trace * gnorm) {
+    } else if (++flat >= std::max(kPcgFlatBlocks, it / 16) && best <= kPcgFloor * prm.rtol_trace * gnorm) {
       ++pcg_floor_stops;
       launch_copy(st, n, px, x);
       return it;

@@ -1924,7 +1924,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_pcg_small(int nF, const double*
     if (it % 4 == 0) {  // blocks of four iterations, as the multi-launch path checks
       // stalls judged on r.z (1 % per block in norm), accepted with |r| within the floor
       if (low < 0.98 * best_rz) { best_rz = low; flat = 0; }
-      else if (++flat >= flat_blocks && best <= floor2) { floor_stop = 1; break; }
+      else if (++flat >= max(flat_blocks, it / 16) && best <= floor2) { floor_stop = 1; break; }
       low = 1e300;
     }
     const double beta = rz != 0.0 ? rzn / rz : 0.0;
