@@ -860,7 +860,8 @@ int hdg_ctx::bicgstab(double adt, const double* b_aos, double* x_aos) {
   hipGraphExec_t* exec = nullptr;
   if (graphs) {
     if (bicg_graphs.size() >= 16 && !bicg_graphs.count(adt)) {  // time step changes: drop the old ones
-      for (auto& g : bicg_graphs) (void)hipGraphExecDestroy(g.second);
+      for (auto& g : bicg_graphs)
+        if (g.second) (void)hipGraphExecDestroy(g.second);
       bicg_graphs.clear();
     }
     exec = &bicg_graphs[adt];
@@ -1478,7 +1479,8 @@ void hdg_destroy(hdg_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->st);
   for (auto& kv : ctx->ops)
     if (kv.second->pcg_block) (void)hipGraphExecDestroy(kv.second->pcg_block);
-  for (auto& g : ctx->bicg_graphs) (void)hipGraphExecDestroy(g.second);
+  for (auto& g : ctx->bicg_graphs)
+    if (g.second) (void)hipGraphExecDestroy(g.second);
   if (ctx->cap_st) (void)hipStreamDestroy(ctx->cap_st);
   for (void* p : ctx->allocs) (void)hipFree(p);
   if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
