@@ -111,3 +111,42 @@ def test_serving_same_alone_and_in_the_mix():
     big = serve.Job(*mesh(16), _sf(0), 1e-3, 1, dict(degree=4))
     r = serve.Server(fps[0] // 2, slots=1).submit(big)
     assert r.error is not None and "budget" in r.error
+
+
+def test_batch_of_mixed_features():
+    """A batch mixing a walled degree-4 member, a periodic shear-layer member
+    with SSP3(4,3,3) and a member carrying a tracer: each equals its lone run."""
+    torch = torch_or_skip()
+    from paper_2410_09790_amd import hdg
+
+    def members(streams):
+        X, C = mesh(5, 0.1, 2)
+        a = context(X, C, stream=streams[0], degree=4, imex="ars222", n_richardson=2)
+        xy = a.cell_points()
+        a.set_velocity_from_points(_sf(2)(xy[..., 0], xy[..., 1]))
+        Xp, Cp, rep = hi.periodic_square_mesh(6)
+        b = context(Xp, Cp, stream=streams[1], vertex_rep=rep, degree=2, imex="ssp3_433", n_richardson=2)
+        xy = b.cell_points()
+        b.set_velocity_from_points(hi.shear_layer_velocity(xy[..., 0], xy[..., 1]))
+        X3, C3 = mesh(6, 0.1, 3)
+        c = context(X3, C3, stream=streams[2], degree=2, imex="ssp2_332", n_richardson=2)
+        xy = c.cell_points()
+        c.set_velocity_from_points(_sf(3)(xy[..., 0], xy[..., 1]))
+        c.set_tracer(np.sin(3.0 * xy[..., 0]) * np.cos(2.0 * xy[..., 1]))
+        return [a, b, c]
+
+    dts = [1e-3, 0.04, 5e-3]
+    alone = members([None, None, None])
+    for ctx, dt in zip(alone, dts):
+        ctx.advance(dt, 2)
+    ref = [[host(t) for t in ctx.get_state()] for ctx in alone]
+    ref_q = host(alone[2].get_tracer())
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    mixed = members(streams)
+    b = hdg.Batch(mixed)
+    assert (b.advance(dts, 2) == 0).all()
+    for ctx, want in zip(mixed, ref):
+        for x, y in zip([host(t) for t in ctx.get_state()], want):
+            assert np.array_equal(x, y)
+    assert np.array_equal(host(mixed[2].get_tracer()), ref_q)
+    b.close()
