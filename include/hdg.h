@@ -125,11 +125,18 @@ typedef struct {
   int use_graphs;        /* 1: the Krylov iteration blocks (PCG: 4 iterations, BiCGStab: 8)
                             are captured once as HIP graphs and replayed; 0: launched one by
                             one.  Results are the same.  Ignored while profiling is on. */
+  int step1_block;       /* launch shape of the Step I operator: threads per workgroup, 64, 128
+                            or 256 (two threads per cell).  The partial sums of the Krylov
+                            inner products follow the workgroups, so results differ between
+                            shapes in the last bits only; one shape always gives the same bits. */
+  int step1_xcd;         /* 1: each of the eight XCDs (own L2) takes a contiguous eighth of the
+                            cells; 0: the hardware's round-robin order of workgroups */
 } hdg_params;
 
 /* Fill p with the defaults: k=1, tau=alpha=delta_up=1, ARS(2,2,2), n_R=3,
  * MG-PCG, rtol 1e-12 for both solvers, caps 5000 / 20000, reconstruction,
- * BiCGStab for Step I, FP64, graph replay on. */
+ * BiCGStab for Step I, FP64, graph replay on, Step I operator in workgroups
+ * of 256 threads in XCD order. */
 void hdg_default_params(hdg_params* p);
 
 /* Create a context on the current HIP device.  coords: host [nv][2];

@@ -215,6 +215,7 @@ struct Timed {
 struct hdg_ctx {
   hdg::Profiler prof;
   hdg_params prm{};
+  hdg::Step1Launch s1{256, 1};  // launch shape of the Step I operator (from prm)
   int k = 1;
   hipStream_t st = nullptr;
   hdg::HostMesh hm;
@@ -422,12 +423,12 @@ void hdg_ctx::setup() {
   // work
   ycell = dalloc<double>(nc * nlam);
   g = dalloc<double>(nT);
-  part = dalloc<double>(std::max<long>((long)kRedBlocks * kIdrMax, 4L * apply_soa_blocks(nc) + 16));
+  part = dalloc<double>(std::max<long>((long)kRedBlocks * kIdrMax, 4L * apply_soa_blocks(nc, s1.block) + 16));
   part2 = dalloc<double>(2 * kRedBlocks);
   const int mt = prm.max_it_trace + 4, mv = prm.max_it_velocity + 4;
   scal = dalloc<double>(3 * mt + 16);
   bsc = dalloc<double>((long)BS_STRIDE * std::max(mv + 2, kBicgBlock + 2));
-  kpart = dalloc<double>(4L * apply_soa_blocks(nc) + 16);
+  kpart = dalloc<double>(4L * apply_soa_blocks(nc, s1.block) + 16);
   pr = dalloc<double>(nT); pz = dalloc<double>(nT); pp = dalloc<double>(nT); pq = dalloc<double>(nT);
   t1 = dalloc<double>(nT); t2 = dalloc<double>(nT); t3 = dalloc<double>(nT); px = dalloc<double>(nT);
   small_info = dalloc<double>(4);
@@ -677,7 +678,7 @@ int hdg_ctx::pcg(TraceOp& op, const double* gin, double* x) {
   const long n = nT;
   const int maxit = prm.max_it_trace;
   double* rz = scal;
-  double* rr = scal + 2 * kPcgBlock + 1;
+  // the squared residual norms of a block follow at scal + 2 * kPcgBlock + 1
   double* gsq = scal + 3 * kPcgBlock + 2;
   launch_fill(st, n, 0.0, px);
   launch_copy(st, n, gin, pr);
@@ -821,19 +822,19 @@ void hdg_ctx::bicgstab_block(double adt) {
     double* sc = bsc + (long)BS_STRIDE * b;
     {
       Timed tm(prof, KC_APPLY_OP);
-      launch_apply_soa(k, st, 1, dm, dt, vk, vk32, vbeta, prm.alpha, adt, B.p, B.rh, B.v, part);
+      launch_apply_soa(k, st, s1, 1, dm, dt, vk, vk32, vbeta, prm.alpha, adt, B.p, B.rh, B.v, part);
     }
     {
       Timed tm(prof, KC_VECTOR);
-      launch_bicg_s(st, n, hm.nc, part, sc, B.r, B.v, B.s);
+      launch_bicg_s(st, n, apply_soa_blocks(hm.nc, s1.block), part, sc, B.r, B.v, B.s);
     }
     {
       Timed tm(prof, KC_APPLY_OP);
-      launch_apply_soa(k, st, 2, dm, dt, vk, vk32, vbeta, prm.alpha, adt, B.s, B.rh, B.t, kpart);
+      launch_apply_soa(k, st, s1, 2, dm, dt, vk, vk32, vbeta, prm.alpha, adt, B.s, B.rh, B.t, kpart);
     }
     {
       Timed tm(prof, KC_VECTOR);
-      launch_bicg_xrp(st, n, hm.nc, kpart, sc, B.s, B.t, B.v, B.x, B.r, B.p, part);
+      launch_bicg_xrp(st, n, apply_soa_blocks(hm.nc, s1.block), kpart, sc, B.s, B.t, B.v, B.x, B.r, B.p, part);
     }
   }
   launch_finish(st, part, kVecBlocks, bsc + (long)BS_STRIDE * (kBicgBlock - 1) + BS_RR);
@@ -876,7 +877,7 @@ int hdg_ctx::bicgstab(double adt, const double* b_aos, double* x_aos) {
       } else {  // true residual of the current iterate
         {
           Timed tm(prof, KC_APPLY_OP);
-          launch_apply_soa(k, st, 0, dm, dt, vk, vk32, vbeta, prm.alpha, adt, B.x, nullptr, B.t, nullptr);
+          launch_apply_soa(k, st, s1, 0, dm, dt, vk, vk32, vbeta, prm.alpha, adt, B.x, nullptr, B.t, nullptr);
         }
         launch_copy(st, n, B.b, B.r);
         launch_axpby(st, n, -1.0, B.t, 1.0, B.r);
@@ -1368,7 +1369,7 @@ static void estimate_footprint(const hdg::HostMesh& m, const hdg::RefTables& rt,
   const double nQ = nc * nu, nP = nc * np, nT = nF * nf;
   const Tableau tab = make_tableau(prm.imex);
   const double s = tab.s;
-  const double blocks = (double)apply_soa_blocks((long)m.nc);
+  const double blocks = (double)apply_soa_blocks((long)m.nc, prm.step1_block);
   double b = 0.0;
   // mesh (geometry, connectivity, packed neighbours) and reference tables
   b += 8.0 * kDGeo * nc + 4.0 * 5 * 3 * nc + 4.0 * 4 * nF;
@@ -1427,6 +1428,8 @@ void hdg_default_params(hdg_params* p) {
   p->idr_s = 0;
   p->precision = HDG_FP64;
   p->use_graphs = 1;
+  p->step1_block = 256;
+  p->step1_xcd = 1;
 }
 
 int hdg_create(int64_t nv, const double* coords, int64_t nc, const int32_t* cells, const hdg_params* prm,
@@ -1446,13 +1449,16 @@ int hdg_create_periodic(int64_t nv, const double* coords, int64_t nc, const int3
       prm->max_it_velocity < 1 || !(prm->rtol_trace > 0) || !(prm->rtol_velocity > 0) || prm->imex < 0 ||
       prm->imex > 4 || prm->trace_solver < 0 || prm->trace_solver > 1 || prm->pressure_update < 0 ||
       prm->pressure_update > 1 || prm->idr_s < 0 || prm->idr_s > kIdrMax ||
-      prm->precision < 0 || prm->precision > 1 || prm->use_graphs < 0 || prm->use_graphs > 1) {
+      prm->precision < 0 || prm->precision > 1 || prm->use_graphs < 0 || prm->use_graphs > 1 ||
+      (prm->step1_block != 64 && prm->step1_block != 128 && prm->step1_block != 256) || prm->step1_xcd < 0 ||
+      prm->step1_xcd > 1) {
     g_create_error = "invalid parameter";
     return HDG_ERR_INVALID_ARG;
   }
 
   auto ctx = std::make_unique<hdg_ctx>();
   ctx->prm = *prm;
+  ctx->s1 = {prm->step1_block, prm->step1_xcd};
   ctx->k = prm->degree;
   ctx->st = (hipStream_t)stream;
   std::string e = build_mesh(nv, coords, nc, cells, vertex_rep, ctx->hm);
@@ -1886,6 +1892,8 @@ int hdg_get_info(const hdg_ctx* ctx, char* buf, size_t cap) {
                   ",\"pcg_floor_stops\":" + std::to_string(ctx->pcg_floor_stops) +
                   ",\"device_bytes\":" + std::to_string(ctx->dev_bytes) +
                   ",\"pending_stage\":" + std::to_string(ctx->pend_stage) +
+                  ",\"step1_block\":" + std::to_string(ctx->s1.block) +
+                  ",\"step1_xcd\":" + std::to_string(ctx->s1.xcd) +
                   ",\"device_transient_bytes\":" + std::to_string(ctx->dev_transient) +
                   ",\"pcg_iterations_last\":" + last(ctx->pcg_iters, 16) +
                   ",\"velocity_iterations_last\":" + last(ctx->bicg_iters, 16) +
@@ -1906,7 +1914,11 @@ int hdg_footprint_bytes(int64_t nv, const double* coords, int64_t nc, const int3
                         const hdg_params* prm, double dt, int64_t* bytes) {
   if (!prm || !bytes || !(dt > 0)) { g_create_error = "null argument or dt <= 0"; return HDG_ERR_INVALID_ARG; }
   if (prm->degree < 1 || prm->degree > kMaxDegree) { g_create_error = "degree must be in 1..4"; return HDG_ERR_UNSUPPORTED; }
-  if (prm->imex < 0 || prm->imex > 4) { g_create_error = "invalid parameter"; return HDG_ERR_INVALID_ARG; }
+  if (prm->imex < 0 || prm->imex > 4 ||
+      (prm->step1_block != 64 && prm->step1_block != 128 && prm->step1_block != 256)) {
+    g_create_error = "invalid parameter";
+    return HDG_ERR_INVALID_ARG;
+  }
   try {
     hdg::HostMesh m;
     std::string e = build_mesh(nv, coords, nc, cells, vertex_rep, m);

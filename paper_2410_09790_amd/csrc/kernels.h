@@ -87,21 +87,29 @@ void launch_apply(int k, hipStream_t st, int mode, DMesh m, DTab t, const double
 // when v32, else FP64; beta is FP64.
 void launch_step1_matrix(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, void* V, bool v32,
                          double* beta);
+// Launch shape of the Step I operator: threads per workgroup (64, 128 or
+// 256; two threads per cell) and the workgroup-to-XCD order (1: each XCD
+// takes a contiguous eighth of the cells, 0: hardware order).
+struct Step1Launch {
+  int block;
+  int xcd;
+};
 // Step I operator on structure-of-arrays vectors (2 threads per cell):
-// out = x - (adt/det) f_im(x), with partial sums (apply_soa_blocks(nc) per set):
-// dot 0 none; dot 1 w.out; dot 2 out.x, out.out, w.x, w.out
-void launch_apply_soa(int k, hipStream_t st, int dot, DMesh m, DTab t, const void* V, bool v32, const double* beta,
-                      double alpha, double adt, const double* x, const double* w, double* out, double* part);
-int apply_soa_blocks(long nc);
+// out = x - (adt/det) f_im(x), with partial sums (apply_soa_blocks(nc, block)
+// per set): dot 0 none; dot 1 w.out; dot 2 out.x, out.out, w.x, w.out
+void launch_apply_soa(int k, hipStream_t st, Step1Launch ln, int dot, DMesh m, DTab t, const void* V, bool v32,
+                      const double* beta, double alpha, double adt, const double* x, const double* w, double* out,
+                      double* part);
+int apply_soa_blocks(long nc, int block);
 // BiCGStab pieces (slot sc of BS_STRIDE scalars):
-//   v = A p: launch_apply_soa dot 1 with rh (partials in part)
+//   v = A p: launch_apply_soa dot 1 with rh (np partials in part)
 //   s = r - alpha v, alpha from those partials: launch_bicg_s
-//   t = A s: launch_apply_soa dot 2 with rh (partials in part2)
+//   t = A s: launch_apply_soa dot 2 with rh (4 sets of np partials in part2)
 //   x, r, p updates, omega and beta from part2, partials of r.r
 //   (kVecBlocks of them) in part: launch_bicg_xrp
-void launch_bicg_s(hipStream_t st, long n, long nc, const double* part, double* sc, const double* r, const double* v,
+void launch_bicg_s(hipStream_t st, long n, int np, const double* part, double* sc, const double* r, const double* v,
                    double* s);
-void launch_bicg_xrp(hipStream_t st, long n, long nc, const double* part2, double* sc, const double* s,
+void launch_bicg_xrp(hipStream_t st, long n, int np, const double* part2, double* sc, const double* s,
                      const double* tv, const double* v, double* x, double* r, double* p, double* part);
 void launch_bicg_init(hipStream_t st, double* sc);  // zero a slot except BS_RHO
 void launch_to_soa(int k, hipStream_t st, DMesh m, int inv_det, const double* x, double* y);

@@ -51,21 +51,27 @@ __device__ __forceinline__ CellGeo load_geo(const DMesh& m, int e) {
 
 __device__ __forceinline__ double sgn(int flip, int m) { return (flip && (m & 1)) ? -1.0 : 1.0; }
 
-__device__ __forceinline__ double block_sum(double v) {
+template <int BS>
+__device__ __forceinline__ double block_sum_n(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  __shared__ double s[kBlock / 64];
-  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) s[w] = v;
-  __syncthreads();
-  double r = 0.0;
-  if (threadIdx.x == 0) {
+  if constexpr (BS == 64) {
+    return v;  // one wavefront: lane 0 holds the sum
+  } else {
+    __shared__ double s[BS / 64];
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) s[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
 #pragma unroll
-    for (int i = 0; i < kBlock / 64; ++i) r += s[i];
+      for (int i = 0; i < BS / 64; ++i) r += s[i];
+    }
+    return r;
   }
-  return r;
 }
+__device__ __forceinline__ double block_sum(double v) { return block_sum_n<kBlock>(v); }
 
 static inline int nblocks(long n) { return (int)((n + kBlock - 1) / kBlock); }
 
@@ -848,20 +854,22 @@ __device__ __forceinline__ void stage_fbu(const DTab& t, double* sFBu) {
 // partial sums (nb = gridDim.x sets of partials at part + i*nb):
 //   DOT 0: none;  DOT 1: w.out;  DOT 2: out.x, out.out, w.x, w.out.
 // In BiCGStab, DOT 1 gives rh.v for v = A p and DOT 2 gives t.s, t.t, rh.s,
-// rh.t for t = A s.
-template <int K, int DOT, typename TV>
-__global__ void __launch_bounds__(kBlock, kStep1Waves) k_apply_soa(DMesh m, DTab t, const TV* __restrict__ V,
-                                                                   const double* __restrict__ beta, double alpha,
-                                                                   double adt, const double* __restrict__ x,
-                                                                   const double* __restrict__ w,
-                                                                   double* __restrict__ out,
-                                                                   double* __restrict__ part) {
+// rh.t for t = A s.  BS threads per workgroup (64, 128 or 256); xcd = 1 deals
+// the cells to the XCDs in contiguous eighths (xcd_block), 0 keeps the
+// hardware order.
+template <int K, int DOT, typename TV, int BS>
+__global__ void __launch_bounds__(BS, kStep1Waves) k_apply_soa(DMesh m, DTab t, const TV* __restrict__ V,
+                                                               const double* __restrict__ beta, double alpha,
+                                                               double adt, const double* __restrict__ x,
+                                                               const double* __restrict__ w,
+                                                               double* __restrict__ out,
+                                                               double* __restrict__ part, int xcd) {
   using D = Dims<K>;
   constexpr int NS = D::NS;
   __shared__ double sFBu[3 * D::NQF * NS];
   stage_fbu<K>(t, sFBu);
-  const int blk = xcd_block();
-  const long tid = (long)blk * blockDim.x + threadIdx.x;
+  const int blk = xcd ? xcd_block() : (int)blockIdx.x;
+  const long tid = (long)blk * BS + threadIdx.x;
   const long nc = m.nc;
   const int e = (int)(tid >> 1), c = (int)(tid & 1);
   double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
@@ -887,14 +895,14 @@ __global__ void __launch_bounds__(kBlock, kStep1Waves) k_apply_soa(DMesh m, DTab
     }
   }
   if (DOT >= 1) {
-    d0 = block_sum(d0);
+    d0 = block_sum_n<BS>(d0);
     if (threadIdx.x == 0) part[blk] = d0;
   }
   if (DOT == 2) {
     const int nb = gridDim.x;
-    d1 = block_sum(d1);
-    d2 = block_sum(d2);
-    d3 = block_sum(d3);
+    d1 = block_sum_n<BS>(d1);
+    d2 = block_sum_n<BS>(d2);
+    d3 = block_sum_n<BS>(d3);
     if (threadIdx.x == 0) {
       part[nb + blk] = d1;
       part[2 * nb + blk] = d2;
@@ -1592,31 +1600,43 @@ void launch_step1_matrix(int k, hipStream_t st, DMesh m, DTab t, const double* Q
   }
   HDG_DISPATCH(k, (k_step1_beta<KK><<<nblocks(3L * m.nc), kBlock, 0, st>>>(m, t, Qs, delta_up, beta)));
 }
-template <typename TV>
-static void apply_soa_t(int k, hipStream_t st, int dot, DMesh m, DTab t, const TV* V, const double* beta,
+template <int DOT, typename TV, int BS>
+static void apply_soa_bs(int k, hipStream_t st, DMesh m, DTab t, const TV* V, const double* beta, double alpha,
+                         double adt, const double* x, const double* w, double* out, double* part, int xcd) {
+  const int nb = apply_soa_blocks(m.nc, BS);
+  HDG_DISPATCH(k, (k_apply_soa<KK, DOT, TV, BS><<<nb, BS, 0, st>>>(m, t, V, beta, alpha, adt, x, w, out, part, xcd)));
+}
+template <int DOT, typename TV>
+static void apply_soa_d(int k, hipStream_t st, Step1Launch ln, DMesh m, DTab t, const TV* V, const double* beta,
                         double alpha, double adt, const double* x, const double* w, double* out, double* part) {
-  const int nb = nblocks(2L * m.nc);
-  if (dot == 0) {
-    HDG_DISPATCH(k, (k_apply_soa<KK, 0, TV><<<nb, kBlock, 0, st>>>(m, t, V, beta, alpha, adt, x, w, out, part)));
-  } else if (dot == 1) {
-    HDG_DISPATCH(k, (k_apply_soa<KK, 1, TV><<<nb, kBlock, 0, st>>>(m, t, V, beta, alpha, adt, x, w, out, part)));
-  } else {
-    HDG_DISPATCH(k, (k_apply_soa<KK, 2, TV><<<nb, kBlock, 0, st>>>(m, t, V, beta, alpha, adt, x, w, out, part)));
+  switch (ln.block) {
+    case 64: apply_soa_bs<DOT, TV, 64>(k, st, m, t, V, beta, alpha, adt, x, w, out, part, ln.xcd); break;
+    case 128: apply_soa_bs<DOT, TV, 128>(k, st, m, t, V, beta, alpha, adt, x, w, out, part, ln.xcd); break;
+    default: apply_soa_bs<DOT, TV, 256>(k, st, m, t, V, beta, alpha, adt, x, w, out, part, ln.xcd); break;
   }
 }
-void launch_apply_soa(int k, hipStream_t st, int dot, DMesh m, DTab t, const void* V, bool v32, const double* beta,
-                      double alpha, double adt, const double* x, const double* w, double* out, double* part) {
-  if (v32) apply_soa_t(k, st, dot, m, t, (const float*)V, beta, alpha, adt, x, w, out, part);
-  else apply_soa_t(k, st, dot, m, t, (const double*)V, beta, alpha, adt, x, w, out, part);
+template <typename TV>
+static void apply_soa_t(int k, hipStream_t st, Step1Launch ln, int dot, DMesh m, DTab t, const TV* V,
+                        const double* beta, double alpha, double adt, const double* x, const double* w, double* out,
+                        double* part) {
+  if (dot == 0) apply_soa_d<0, TV>(k, st, ln, m, t, V, beta, alpha, adt, x, w, out, part);
+  else if (dot == 1) apply_soa_d<1, TV>(k, st, ln, m, t, V, beta, alpha, adt, x, w, out, part);
+  else apply_soa_d<2, TV>(k, st, ln, m, t, V, beta, alpha, adt, x, w, out, part);
 }
-int apply_soa_blocks(long nc) { return nblocks(2L * nc); }
-void launch_bicg_s(hipStream_t st, long n, long nc, const double* part, double* sc, const double* r, const double* v,
+void launch_apply_soa(int k, hipStream_t st, Step1Launch ln, int dot, DMesh m, DTab t, const void* V, bool v32,
+                      const double* beta, double alpha, double adt, const double* x, const double* w, double* out,
+                      double* part) {
+  if (v32) apply_soa_t(k, st, ln, dot, m, t, (const float*)V, beta, alpha, adt, x, w, out, part);
+  else apply_soa_t(k, st, ln, dot, m, t, (const double*)V, beta, alpha, adt, x, w, out, part);
+}
+int apply_soa_blocks(long nc, int block) { return (int)((2L * nc + block - 1) / block); }
+void launch_bicg_s(hipStream_t st, long n, int np, const double* part, double* sc, const double* r, const double* v,
                    double* s) {
-  k_bicg_s<<<kVecBlocks, kBlock, 0, st>>>(n, nblocks(2L * nc), part, sc, r, v, s);
+  k_bicg_s<<<kVecBlocks, kBlock, 0, st>>>(n, np, part, sc, r, v, s);
 }
-void launch_bicg_xrp(hipStream_t st, long n, long nc, const double* part2, double* sc, const double* s,
+void launch_bicg_xrp(hipStream_t st, long n, int np, const double* part2, double* sc, const double* s,
                      const double* tv, const double* v, double* x, double* r, double* p, double* part) {
-  k_bicg_xrp<<<kVecBlocks, kBlock, 0, st>>>(n, nblocks(2L * nc), part2, sc, s, tv, v, x, r, p, part);
+  k_bicg_xrp<<<kVecBlocks, kBlock, 0, st>>>(n, np, part2, sc, s, tv, v, x, r, p, part);
 }
 void launch_bicg_init(hipStream_t st, double* sc) { k_bicg_init<<<1, 64, 0, st>>>(sc); }
 void launch_to_soa(int k, hipStream_t st, DMesh m, int inv_det, const double* x, double* y) {

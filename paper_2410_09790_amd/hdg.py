@@ -2,7 +2,10 @@
 
 Argument marshalling only: every numerical step runs in the HIP library.
 torch supplies device memory (float64 CUDA tensors) and the HIP stream.
-Loading fails loudly when the library has not been built.
+Loading fails loudly when the library has not been built.  Unless the caller
+sets it, the launch shape of the Step I operator is taken from the table that
+autotune.py measures (launch_table.json beside this file; library default
+when it is absent).
 """
 from __future__ import annotations
 
@@ -14,6 +17,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhdg.so")
+# launch shapes of the Step I operator measured by autotune.py
+LAUNCH_TABLE = os.path.join(_HERE, "launch_table.json")
 
 IMEX = {"imex_euler": 0, "ars222": 1, "ars233": 2, "ssp2_332": 3, "ssp3_433": 4}
 TRACE_SOLVER = {"jacobi_pcg": 0, "mg_pcg": 1}
@@ -50,6 +55,8 @@ class Params(ctypes.Structure):
         ("idr_s", ctypes.c_int),
         ("precision", ctypes.c_int),
         ("use_graphs", ctypes.c_int),
+        ("step1_block", ctypes.c_int),
+        ("step1_xcd", ctypes.c_int),
     ]
 
 
@@ -135,6 +142,33 @@ def default_params(**kw) -> Params:
     return p
 
 
+_launch_cache: dict = {}
+
+
+def tuned_launch(degree: int, ncells: int, path: str = LAUNCH_TABLE):
+    """{"step1_block", "step1_xcd"} that autotune.py measured fastest for this
+    degree at the tabulated mesh nearest to ncells (in log scale), or {} when
+    the table is missing or holds no entry for the degree."""
+    if path not in _launch_cache:
+        try:
+            with open(path) as f:
+                _launch_cache[path] = json.load(f)["entries"]
+        except FileNotFoundError:
+            _launch_cache[path] = []
+    rows = [r for r in _launch_cache[path] if r["degree"] == int(degree)]
+    if not rows:
+        return {}
+    best = min(rows, key=lambda r: abs(np.log(r["ncells"]) - np.log(max(int(ncells), 1))))
+    return {"step1_block": int(best["step1_block"]), "step1_xcd": int(best["step1_xcd"])}
+
+
+def _with_launch(params: dict, ncells: int) -> dict:
+    """params with the tuned Step I launch shape filled in unless given."""
+    if "step1_block" in params or "step1_xcd" in params:
+        return params
+    return {**params, **tuned_launch(params.get("degree", 1), ncells)}
+
+
 def _ptr(t):
     import torch
     if t is None:
@@ -155,7 +189,7 @@ class Context:
         rep = None if vertex_rep is None else np.ascontiguousarray(vertex_rep, dtype=np.int32)
         if rep is not None and rep.shape != (coords.shape[0],):
             raise ValueError("vertex_rep needs one entry per vertex")
-        self.params = default_params(**params)
+        self.params = default_params(**_with_launch(params, cells.shape[0]))
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -334,7 +368,7 @@ def footprint_bytes(coords, cells, dt: float, vertex_rep=None, **params) -> int:
     coords = np.ascontiguousarray(coords, dtype=np.float64)
     cells = np.ascontiguousarray(cells, dtype=np.int32)
     rep = None if vertex_rep is None else np.ascontiguousarray(vertex_rep, dtype=np.int32)
-    p = default_params(**params)
+    p = default_params(**_with_launch(params, cells.shape[0]))
     out = ctypes.c_int64()
     st = lib.hdg_footprint_bytes(coords.shape[0], coords.ctypes.data_as(ctypes.c_void_p), cells.shape[0],
                                  cells.ctypes.data_as(ctypes.c_void_p),

@@ -95,6 +95,45 @@ def test_graph_parameter_is_checked_on_the_host(lib_path):
     assert b"invalid parameter" in lib.hdg_last_error(None)
 
 
+def test_step1_launch_shape_is_checked_on_the_host(lib_path):
+    from paper_2410_09790_amd import hdg
+    lib = hdg.load_library()
+    p = hdg.default_params()
+    assert (p.step1_block, p.step1_xcd) == (256, 1)
+    h = ctypes.c_void_p()
+    for block, xcd in ((96, 1), (512, 1), (0, 1), (64, 2), (128, -1)):
+        p = hdg.default_params(step1_block=block, step1_xcd=xcd)
+        st = lib.hdg_create(3, None, 1, None, ctypes.byref(p), None, ctypes.byref(h))
+        assert st == 1 and not h.value
+        assert b"invalid parameter" in lib.hdg_last_error(None)
+
+
+def test_tuned_launch_table_lookup(tmp_path):
+    """The binding takes the tabulated shape of the nearest mesh size (log
+    scale) for the degree; an explicit shape or a missing table leaves the
+    library default."""
+    import json
+    from paper_2410_09790_amd import hdg
+    path = str(tmp_path / "t.json")
+    rows = [{"degree": 2, "ncells": 512, "step1_block": 64, "step1_xcd": 0},
+            {"degree": 2, "ncells": 131072, "step1_block": 256, "step1_xcd": 1},
+            {"degree": 3, "ncells": 512, "step1_block": 128, "step1_xcd": 1}]
+    with open(path, "w") as f:
+        json.dump({"entries": rows}, f)
+    assert hdg.tuned_launch(2, 600, path) == {"step1_block": 64, "step1_xcd": 0}
+    assert hdg.tuned_launch(2, 8000, path) == {"step1_block": 64, "step1_xcd": 0}  # log midpoint 8192
+    assert hdg.tuned_launch(2, 8400, path) == {"step1_block": 256, "step1_xcd": 1}
+    assert hdg.tuned_launch(3, 10 ** 6, path) == {"step1_block": 128, "step1_xcd": 1}
+    assert hdg.tuned_launch(4, 512, path) == {}
+    assert hdg.tuned_launch(1, 512, str(tmp_path / "none.json")) == {}
+    # the committed table covers every degree with valid shapes
+    if os.path.exists(hdg.LAUNCH_TABLE):
+        with open(hdg.LAUNCH_TABLE) as f:
+            tab = json.load(f)["entries"]
+        assert sorted({r["degree"] for r in tab}) == [1, 2, 3, 4]
+        assert all(r["step1_block"] in (64, 128, 256) and r["step1_xcd"] in (0, 1) for r in tab)
+
+
 def test_params_struct_layout_matches_the_header(tmp_path):
     """The ctypes mirror of hdg_params has the C compiler's size and offsets."""
     import shutil
