@@ -49,7 +49,7 @@ KERNELS_SRC = os.path.join(ROOT, "paper_2410_09790_amd", "csrc", "kernels.hip")
 # counter passes (each scaled by the counts of a 256 MiB copy), valid only for
 # the kernel source they were taken on (sha256 prefix of kernels.hip)
 MEASURED_TRAFFIC = {
-    "apply_step1_operator": {"kernels_sha256": "8efc47d6fc78e01f", "bytes_per_launch": 381.8e6},
+    "apply_step1_operator": {"kernels_sha256": "cfee42fcd5d16a30", "bytes_per_launch": 383.7e6},
 }
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
 MIXED_RTOL_VELOCITY = 1e-5  # Step I tolerance of the mixed-precision run
@@ -391,6 +391,25 @@ def serving_run(hdg, hi, torch, njobs: int = 16, nmax: int = 48, steps: int = 10
     return out
 
 
+def copy_bandwidth(torch, mib: int = 2048, reps: int = 5) -> float:
+    """GB/s (bytes read + written) of a plain device-to-device copy of mib MiB,
+    larger than the last-level cache: what a streaming kernel reaches on this
+    device, reported beside the published peak."""
+    src = torch.ones(mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbs = 2.0 * src.numel() * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -493,6 +512,11 @@ def main():
                         "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom), "kernel": dom,
                         "algorithmic_bytes_per_launch": nbytes, "avg_launch_us": round(avg_s * 1e6, 2),
                         "share_of_step": round(timed[dom]["est_ms"] * 1e-3 / el, 3)}
+            copy = copy_bandwidth(torch)
+            roofline["device_copy_GBps"] = round(copy, 1)
+            roofline["frac_of_device_copy"] = round(ach / copy, 4)
+            log(f"plain device copy (2 GiB): {copy:.0f} GB/s read + written; the dominant kernel reaches "
+                f"{ach / copy:.2f} of it")
         else:
             ach = flops / avg_s / 1e12
             roofline = {"bound": "alu", "achieved": round(ach, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",

@@ -264,27 +264,33 @@ __global__ void __launch_bounds__(kBlock) k_assemble(DMesh m, const double* __re
 }
 
 // ===================================================================== a8
-// Trace SpMV, one thread per (facet, row): the five blocks of a facet row are
-// stored slot-major, then row, then column, with the facet index fastest.
+// Trace SpMV, one thread per facet and all NF rows of its block row: the five
+// blocks of a facet row are stored slot-major, then row, then column, with
+// the facet index fastest, so every value load is coalesced across the
+// wavefront, and each thread writes its NF results as one contiguous run.
 template <int K>
 __global__ void __launch_bounds__(kBlock) k_spmv(int nF, const double* __restrict__ vals, const int* __restrict__ cols,
                                                  const double* __restrict__ x, const double* __restrict__ b,
                                                  double* __restrict__ y) {
   constexpr int NF = K + 1;
-  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= (long)nF * NF) return;
-  const int F = (int)(tid % nF);
-  const int i = (int)(tid / nF);
-  double acc = 0.0;
+  const int F = blockIdx.x * blockDim.x + threadIdx.x;
+  if (F >= nF) return;
+  double acc[NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) acc[i] = 0.0;
 #pragma unroll
   for (int s = 0; s < 5; ++s) {
     const int col = cols[s * nF + F];
-    const double* xc = x + (long)col * NF;
+    double xc[NF];
 #pragma unroll
-    for (int j = 0; j < NF; ++j) acc += vals[((long)(s * NF + i) * NF + j) * nF + F] * xc[j];
+    for (int j = 0; j < NF; ++j) xc[j] = x[(long)col * NF + j];
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+#pragma unroll
+      for (int j = 0; j < NF; ++j) acc[i] += vals[((long)(s * NF + i) * NF + j) * nF + F] * xc[j];
   }
-  if (b) y[(long)F * NF + i] = b[(long)F * NF + i] - acc;
-  else y[(long)F * NF + i] = acc;
+#pragma unroll
+  for (int i = 0; i < NF; ++i) y[(long)F * NF + i] = b ? b[(long)F * NF + i] - acc[i] : acc[i];
 }
 
 // damped block-Jacobi sweep: xout = xin + omega Dinv (b - S xin); xin == nullptr means xin = 0
@@ -1552,11 +1558,11 @@ void launch_assemble(int k, hipStream_t st, DMesh m, const double* SK, double* v
   HDG_DISPATCH(k, (k_assemble<KK><<<nblocks(m.nF), kBlock, 0, st>>>(m, SK, vals, cols, Dinv)));
 }
 void launch_spmv(int k, hipStream_t st, int nF, const double* vals, const int* cols, const double* x, double* y) {
-  HDG_DISPATCH(k, (k_spmv<KK><<<nblocks((long)nF * (k + 1)), kBlock, 0, st>>>(nF, vals, cols, x, nullptr, y)));
+  HDG_DISPATCH(k, (k_spmv<KK><<<nblocks(nF), kBlock, 0, st>>>(nF, vals, cols, x, nullptr, y)));
 }
 void launch_residual(int k, hipStream_t st, int nF, const double* vals, const int* cols, const double* b,
                      const double* x, double* r) {
-  HDG_DISPATCH(k, (k_spmv<KK><<<nblocks((long)nF * (k + 1)), kBlock, 0, st>>>(nF, vals, cols, x, b, r)));
+  HDG_DISPATCH(k, (k_spmv<KK><<<nblocks(nF), kBlock, 0, st>>>(nF, vals, cols, x, b, r)));
 }
 void launch_jacobi_sweep(int k, hipStream_t st, int nF, const double* vals, const int* cols, const double* Dinv,
                          double omega, const double* b, const double* xin, double* xout) {
