@@ -676,6 +676,19 @@ __device__ __forceinline__ double pair_swap(double v) {
 // streams small.  Arrays hold ceil(nc/32)*32 cells.
 __device__ __forceinline__ long tile_idx(long e, int j, int nj) { return ((e >> 5) * nj + j) * 32 + (e & 31); }
 
+// FP32 cell matrices (mixed mode) are stored in pairs of adjacent entries of a
+// row, so that one 8-byte load per lane brings two of them (the same bytes per
+// load instruction as FP64): row s of cell e holds NPR = ceil(NS/2) pairs
+// (the last one padded with a zero when NS is odd), pair pi of row s at
+// vpair_idx(e, s, pi) in units of pairs, in tiles of 32 cells.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+template <int K>
+struct VPairs {
+  static constexpr int NS = Dims<K>::NS;
+  static constexpr int NPR = (NS + 1) / 2;
+  __device__ static long idx(long e, int s, int pi) { return ((e >> 5) * (long)(NS * NPR) + s * NPR + pi) * 32 + (e & 31); }
+};
+
 // Per-cell volume matrix of the Step I form, for the Q* of a stage:
 //   V[s][s'] = -sum_q w_q phi_s(q) (Q*(q) . grad phi_s'(q)) det J
 // (the volume term -(Q*.grad x, w) of eq. (f_impl) acts on each velocity
@@ -711,8 +724,19 @@ __global__ void __launch_bounds__(kBlock) k_step1_matrix(DMesh m, DTab t, const 
 #pragma unroll
     for (int i = 0; i < NS; ++i) row[i] += a0 * t.Gux[qq * NS + i] + a1 * t.Guy[qq * NS + i];
   }
+  if constexpr (sizeof(TV) == 4) {
+    f32x2* V2 = reinterpret_cast<f32x2*>(V);
 #pragma unroll
-  for (int i = 0; i < NS; ++i) V[tile_idx(e, s * NS + i, NS * NS)] = (TV)row[i];
+    for (int pi = 0; pi < VPairs<K>::NPR; ++pi) {
+      f32x2 v;
+      v.x = (float)row[2 * pi];
+      v.y = 2 * pi + 1 < NS ? (float)row[2 * pi + 1] : 0.0f;
+      V2[VPairs<K>::idx(e, s, pi)] = v;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) V[tile_idx(e, s * NS + i, NS * NS)] = (TV)row[i];
+  }
 }
 
 // Upwind weights of the Step I facet term at the facet points, for the Q*
@@ -774,11 +798,25 @@ __device__ __forceinline__ void step1_core(const DMesh& m, const DTab& t, const 
     for (int r = 0; r < (NS + 1) / 2; ++r) {
       const int s = 2 * r + c < NS ? 2 * r + c : NS - 1;
       double am = 0.0, ao = 0.0;
+      if constexpr (sizeof(TV) == 4) {
+        const f32x2* V2 = reinterpret_cast<const f32x2*>(V);
 #pragma unroll
-      for (int i = 0; i < NS; ++i) {
-        const double v = (double)__builtin_nontemporal_load(&V[tile_idx(e, s * NS + i, NS * NS)]);
-        am += v * xv[i];
-        ao += v * xo[i];
+        for (int pi = 0; pi < VPairs<K>::NPR; ++pi) {
+          const f32x2 v = __builtin_nontemporal_load(&V2[VPairs<K>::idx(e, s, pi)]);
+          am += (double)v.x * xv[2 * pi];
+          ao += (double)v.x * xo[2 * pi];
+          if (2 * pi + 1 < NS) {
+            am += (double)v.y * xv[2 * pi + 1];
+            ao += (double)v.y * xo[2 * pi + 1];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          const double v = (double)__builtin_nontemporal_load(&V[tile_idx(e, s * NS + i, NS * NS)]);
+          am += v * xv[i];
+          ao += v * xo[i];
+        }
       }
       const double recv = pair_swap(ao);
       if (2 * r + 1 < NS) {
