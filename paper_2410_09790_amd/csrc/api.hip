@@ -435,8 +435,7 @@ void hdg_ctx::setup() {
   for (double** v : {&kd.b, &kd.x, &kd.r, &kd.rh, &kd.s, &kd.t, &kd.p, &kd.v}) *v = dalloc<double>(nQ);
   const long nc32 = (nc + 31) / 32 * 32;
   vk32 = prm.precision == HDG_MIXED;
-  // FP32 rows are stored in pairs, padded to an even length
-  vk = vk32 ? (void*)dalloc<float>((long)ns * ((ns + 1) / 2 * 2) * nc32) : (void*)dalloc<double>((long)ns * ns * nc32);
+  vk = vk32 ? (void*)dalloc<float>((long)ns * ns * nc32) : (void*)dalloc<double>((long)ns * ns * nc32);
   vbeta = dalloc<double>(3L * nqf * nc32);
   br = dalloc<double>(nQ); bt = dalloc<double>(nQ);
   adv = dalloc<double>((long)nc * (2 * nqc + 3 * nqf));
@@ -1383,7 +1382,7 @@ static void estimate_footprint(const hdg::HostMesh& m, const hdg::RefTables& rt,
   b += 8.0 * ((double)kRedBlocks * kIdrMax + 2.0 * kRedBlocks + 3.0 * (prm.max_it_trace + 4) + 16 +
               (double)BS_STRIDE * std::max(prm.max_it_velocity + 6, 10) + 2 * (4 * blocks + 16));
   // Step I data: cell matrices, upwind weights, residual-kernel advection data
-  b += (prm.precision == HDG_MIXED ? 4.0 * ns * (std::ceil(ns / 2.0) * 2.0) : 8.0 * ns * ns) * nc32 + 8.0 * 3 * nqf * nc32 + 8.0 * nc * (2 * nqc + 3 * nqf);
+  b += ns * ns * nc32 * (prm.precision == HDG_MIXED ? 4.0 : 8.0) + 8.0 * 3 * nqf * nc32 + 8.0 * nc * (2 * nqc + 3 * nqf);
   if (prm.idr_s > 0) b += 8.0 * (3.0 * prm.idr_s * nQ + kIdrMax + 8);
   // trace operators
   std::set<double> cs = {1.0, tab.bim[tab.s - 1] * dtv};

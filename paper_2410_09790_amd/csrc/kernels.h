@@ -81,12 +81,13 @@ void launch_prep_adv(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, d
 void launch_apply(int k, hipStream_t st, int mode, DMesh m, DTab t, const double* adv, double alpha, double adt,
                   const double* x, const double* r, const double* p, const double* lam, double* out);
 // Per-stage data of the Step I operator for advecting velocity Qs (AoS): the
-// per-cell volume matrices V (ns*ns entries) and the facet upwind weights
-// beta (3*nq_facet entries), both in tiles of 32 cells (entry j of cell e at
-// ((e/32)*nj + j)*32 + e%32; arrays hold ceil(nc/32)*32 cells).  V is FP64
-// in that layout, or FP32 when v32, then with each row stored as
-// ceil(ns/2) pairs of adjacent entries (zero-padded) and the pairs tiled the
-// same way (ns*ceil(ns/2)*2 floats per cell); beta is FP64.
+// per-cell volume matrices V (ns*ns entries, FP32 when v32, else FP64) and the
+// facet upwind weights beta (3*nq_facet FP64 entries), in tiles of 32 cells
+// (arrays hold ceil(nc/32)*32 cells).  beta: entry j of cell e at
+// ((e/32)*nj + j)*32 + e%32.  V: each row as floor(ns/2) pairs of adjacent
+// entries tiled that way (pair pi of row s as entry s*floor(ns/2) + pi, in
+// units of pairs), then, for odd ns, the last entry of every row tiled as
+// entry s of a second array that follows all pairs.
 void launch_step1_matrix(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, void* V, bool v32,
                          double* beta);
 // Launch shape of the Step I operator: threads per workgroup (64, 128 or

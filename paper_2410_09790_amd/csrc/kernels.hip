@@ -676,17 +676,23 @@ __device__ __forceinline__ double pair_swap(double v) {
 // streams small.  Arrays hold ceil(nc/32)*32 cells.
 __device__ __forceinline__ long tile_idx(long e, int j, int nj) { return ((e >> 5) * nj + j) * 32 + (e & 31); }
 
-// FP32 cell matrices (mixed mode) are stored in pairs of adjacent entries of a
-// row, so that one 8-byte load per lane brings two of them (the same bytes per
-// load instruction as FP64): row s of cell e holds NPR = ceil(NS/2) pairs
-// (the last one padded with a zero when NS is odd), pair pi of row s at
-// vpair_idx(e, s, pi) in units of pairs, in tiles of 32 cells.
+// The cell matrices are stored as pairs of adjacent row entries, so that one
+// load per lane brings two of them (16 bytes in FP64, 8 in FP32): row s of
+// cell e holds NP2 = floor(NS/2) pairs, pair pi of row s at
+// pair(e, s, pi) in units of pairs, in tiles of 32 cells; when NS is odd the
+// last entry of every row follows all pairs, at tail(nc) + tile_idx(e, s, NS)
+// in units of entries.  The array holds ceil(nc/32)*32*NS*NS entries either way.
 typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <typename TV> struct Pair2;
+template <> struct Pair2<float> { using T = f32x2; };
+template <> struct Pair2<double> { using T = f64x2; };
 template <int K>
 struct VPairs {
   static constexpr int NS = Dims<K>::NS;
-  static constexpr int NPR = (NS + 1) / 2;
-  __device__ static long idx(long e, int s, int pi) { return ((e >> 5) * (long)(NS * NPR) + s * NPR + pi) * 32 + (e & 31); }
+  static constexpr int NP2 = NS / 2;
+  __device__ static long pair(long e, int s, int pi) { return ((e >> 5) * (long)(NS * NP2) + s * NP2 + pi) * 32 + (e & 31); }
+  __device__ static long tail(long nc) { return ((nc + 31) >> 5) * 32 * (long)NS * (2 * NP2); }
 };
 
 // Per-cell volume matrix of the Step I form, for the Q* of a stage:
@@ -724,19 +730,16 @@ __global__ void __launch_bounds__(kBlock) k_step1_matrix(DMesh m, DTab t, const 
 #pragma unroll
     for (int i = 0; i < NS; ++i) row[i] += a0 * t.Gux[qq * NS + i] + a1 * t.Guy[qq * NS + i];
   }
-  if constexpr (sizeof(TV) == 4) {
-    f32x2* V2 = reinterpret_cast<f32x2*>(V);
+  using TV2 = typename Pair2<TV>::T;
+  TV2* V2 = reinterpret_cast<TV2*>(V);
 #pragma unroll
-    for (int pi = 0; pi < VPairs<K>::NPR; ++pi) {
-      f32x2 v;
-      v.x = (float)row[2 * pi];
-      v.y = 2 * pi + 1 < NS ? (float)row[2 * pi + 1] : 0.0f;
-      V2[VPairs<K>::idx(e, s, pi)] = v;
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < NS; ++i) V[tile_idx(e, s * NS + i, NS * NS)] = (TV)row[i];
+  for (int pi = 0; pi < VPairs<K>::NP2; ++pi) {
+    TV2 v;
+    v.x = (TV)row[2 * pi];
+    v.y = (TV)row[2 * pi + 1];
+    V2[VPairs<K>::pair(e, s, pi)] = v;
   }
+  if constexpr (NS & 1) V[VPairs<K>::tail(nc) + tile_idx(e, s, NS)] = (TV)row[NS - 1];
 }
 
 // Upwind weights of the Step I facet term at the facet points, for the Q*
@@ -791,6 +794,8 @@ __device__ __forceinline__ void step1_core(const DMesh& m, const DTab& t, const 
   // loads keep them from evicting the velocity vectors (read again by the
   // neighbouring cells) from the caches.
   {
+    using TV2 = typename Pair2<TV>::T;
+    const long vtail = VPairs<K>::tail(nc);
     double xo[NS];
 #pragma unroll
     for (int i = 0; i < NS; ++i) xo[i] = pair_swap(xv[i]);
@@ -798,25 +803,19 @@ __device__ __forceinline__ void step1_core(const DMesh& m, const DTab& t, const 
     for (int r = 0; r < (NS + 1) / 2; ++r) {
       const int s = 2 * r + c < NS ? 2 * r + c : NS - 1;
       double am = 0.0, ao = 0.0;
-      if constexpr (sizeof(TV) == 4) {
-        const f32x2* V2 = reinterpret_cast<const f32x2*>(V);
+      const TV2* V2 = reinterpret_cast<const TV2*>(V);
 #pragma unroll
-        for (int pi = 0; pi < VPairs<K>::NPR; ++pi) {
-          const f32x2 v = __builtin_nontemporal_load(&V2[VPairs<K>::idx(e, s, pi)]);
-          am += (double)v.x * xv[2 * pi];
-          ao += (double)v.x * xo[2 * pi];
-          if (2 * pi + 1 < NS) {
-            am += (double)v.y * xv[2 * pi + 1];
-            ao += (double)v.y * xo[2 * pi + 1];
-          }
-        }
-      } else {
-#pragma unroll
-        for (int i = 0; i < NS; ++i) {
-          const double v = (double)__builtin_nontemporal_load(&V[tile_idx(e, s * NS + i, NS * NS)]);
-          am += v * xv[i];
-          ao += v * xo[i];
-        }
+      for (int pi = 0; pi < VPairs<K>::NP2; ++pi) {
+        const TV2 v = __builtin_nontemporal_load(&V2[VPairs<K>::pair(e, s, pi)]);
+        am += (double)v.x * xv[2 * pi];
+        ao += (double)v.x * xo[2 * pi];
+        am += (double)v.y * xv[2 * pi + 1];
+        ao += (double)v.y * xo[2 * pi + 1];
+      }
+      if constexpr (NS & 1) {
+        const double v = (double)__builtin_nontemporal_load(&V[vtail + tile_idx(e, s, NS)]);
+        am += v * xv[NS - 1];
+        ao += v * xo[NS - 1];
       }
       const double recv = pair_swap(ao);
       if (2 * r + 1 < NS) {
