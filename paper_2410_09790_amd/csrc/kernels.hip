@@ -1884,10 +1884,15 @@ __device__ __forceinline__ void small_reduce(double* v, int nv, double* sh) {
 }
 
 // Up to kSmallLds unknowns the work vectors r, z, p, q live in LDS
-// (4 x 1920 doubles = 60 KiB); beyond that in global memory.
+// (4 x 1920 doubles = 60 KiB); beyond that in global memory.  With REG (one
+// facet per thread at most, degree 1) each thread also keeps its facet's
+// neighbour list and preconditioner block in registers for the whole solve,
+// so that no load of an iteration waits on another global load (the operator
+// values are still loaded every iteration, independently: kept in registers
+// too they would spill); the arithmetic is the same.
 constexpr int kSmallLds = 1920;
 
-template <int K, bool LDS>
+template <int K, bool LDS, bool REG = false>
 __global__ void __launch_bounds__(kSmallBlock) k_pcg_small(int nF, const double* __restrict__ vals,
                                                            const int* __restrict__ cols, const double* __restrict__ Dinv,
                                                            const double* __restrict__ g, double* __restrict__ x,
@@ -1904,6 +1909,19 @@ __global__ void __launch_bounds__(kSmallBlock) k_pcg_small(int nF, const double*
   double* q = LDS ? sv[3] : qg;
   const int tid = threadIdx.x;
   const double nnull = (double)nF;
+  static_assert(!REG || (K == 1 && LDS), "register caching is for degree 1 with LDS vectors");
+  constexpr int NR = REG ? NF : 1;
+  double rD[NR][NR];
+  int rc[REG ? 5 : 1];
+  if constexpr (REG) {
+    const int F = tid < nF ? tid : 0;
+#pragma unroll
+    for (int s = 0; s < 5; ++s) rc[s] = cols[s * nF + F];
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+#pragma unroll
+      for (int j = 0; j < NF; ++j) rD[i][j] = Dinv[(long)(i * NF + j) * nF + F];
+  }
   // Every pass below maps a thread to whole facets, so q, r and z of a facet
   // are written and read by the same thread and only p (read across facets
   // by S p) needs a barrier between passes.
@@ -1916,7 +1934,10 @@ __global__ void __launch_bounds__(kSmallBlock) k_pcg_small(int nF, const double*
     for (int i = 0; i < NF; ++i) {
       double v = 0.0;
 #pragma unroll
-      for (int j = 0; j < NF; ++j) v += Dinv[(long)(i * NF + j) * nF + F] * rv[j];
+      for (int j = 0; j < NF; ++j) {
+        if constexpr (REG) v += rD[i][j] * rv[j];
+        else v += Dinv[(long)(i * NF + j) * nF + F] * rv[j];
+      }
       z[F * NF + i] = v;
       red[0] += rv[i] * rv[i];
       red[2] += rv[i] * v;
@@ -1949,7 +1970,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_pcg_small(int nF, const double*
       double pc[5][NF];
 #pragma unroll
       for (int s = 0; s < 5; ++s) {
-        const int col = cols[s * nF + F];
+        const int col = REG ? rc[REG ? s : 0] : cols[s * nF + F];
 #pragma unroll
         for (int j = 0; j < NF; ++j) pc[s][j] = p[col * NF + j];
       }
@@ -2008,7 +2029,10 @@ __global__ void __launch_bounds__(kSmallBlock) k_pcg_small(int nF, const double*
 void launch_pcg_small(int k, hipStream_t st, int nF, const double* vals, const int* cols, const double* Dinv,
                       const double* g, double* x, double* r, double* z, double* p, double* q, int maxit, double tol2,
                       double floor2, int flat_blocks, double* info) {
-  if ((long)nF * (k + 1) <= kSmallLds) {
+  if (k == 1 && nF <= kSmallBlock && (long)nF * 2 <= kSmallLds) {
+    k_pcg_small<1, true, true><<<1, kSmallBlock, 0, st>>>(nF, vals, cols, Dinv, g, x, r, z, p, q, maxit, tol2, floor2,
+                                                         flat_blocks, info);
+  } else if ((long)nF * (k + 1) <= kSmallLds) {
     HDG_DISPATCH(k, (k_pcg_small<KK, true><<<1, kSmallBlock, 0, st>>>(nF, vals, cols, Dinv, g, x, r, z, p, q, maxit,
                                                                       tol2, floor2, flat_blocks, info)));
   } else {
