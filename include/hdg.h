@@ -314,7 +314,9 @@ int hdg_reconstruct_pressure(hdg_ctx* ctx, const double* Q, double* p, double* l
  * enable <= 0 stops timing. */
 int hdg_profile(hdg_ctx* ctx, int enable);
 
-/* JSON with sizes, iteration counts of the last calls, timings, and the
+/* JSON with sizes, iteration counts (totals since creation over every trace
+ * and Step I solve, whether from hdg_advance or the single-step entry points,
+ * and those of the last 16 solves), timings, the Step I launch shape, and the
  * device memory held (device_bytes) and the largest short-lived buffer
  * (device_transient_bytes, the condensation scratch of a trace-operator
  * build). */

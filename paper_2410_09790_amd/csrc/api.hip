@@ -1849,6 +1849,8 @@ int hdg_tentative_velocity(hdg_ctx* ctx, double adt, const double* Qsv, const do
   KCHK();
   int its = ctx->velocity_solve(adt, ctx->dr, Qbar);
   ctx->bicg_iters.push_back(its);
+  ctx->total_bicg += its;
+  ++ctx->n_velocity_solves;
   ctx->sync();
   API_END(ctx)
 }
