@@ -428,6 +428,8 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=1, help="timed steps of the batched sample (recipe: 10)")
     ap.add_argument("--serving-jobs", type=int, default=16, help="jobs of the serving sample (recipe: 200)")
     ap.add_argument("--serving-nmax", type=int, default=48, help="mesh size cap of the serving sample (recipe: 512)")
+    ap.add_argument("--serving-rho", type=float, default=0.8,
+                    help="offered load of the serving sample: arrival rate x mean alone service time (recipe: 0.5, 0.8)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -537,7 +539,7 @@ def main():
         batched = batched_run(hdg, hi, torch, args.batched_instances, args.batched_steps)
     serving = None
     if not args.no_serving:
-        serving = serving_run(hdg, hi, torch, args.serving_jobs, args.serving_nmax)
+        serving = serving_run(hdg, hi, torch, args.serving_jobs, args.serving_nmax, rho=args.serving_rho)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
