@@ -1864,6 +1864,9 @@ void launch_tracer_rate(int k, hipStream_t st, DMesh m, DTab t, const double* U,
 // component removed), floor stop, converged.
 constexpr int kSmallBlock = 1024;
 
+// No barrier follows the final reads of sh: a caller alternates two scratch
+// areas between consecutive reductions, so the barrier inside the next
+// reduction orders those reads before sh is written again.
 __device__ __forceinline__ void small_reduce(double* v, int nv, double* sh) {
   // sh: shared scratch of nv * (kSmallBlock / 64) doubles; all threads get the sums
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1880,7 +1883,6 @@ __device__ __forceinline__ void small_reduce(double* v, int nv, double* sh) {
     for (int i = 0; i < kSmallBlock / 64; ++i) s += sh[c * (kSmallBlock / 64) + i];
     v[c] = s;
   }
-  __syncthreads();
 }
 
 // Up to kSmallLds unknowns the work vectors r, z, p, q live in LDS
@@ -1901,7 +1903,9 @@ __global__ void __launch_bounds__(kSmallBlock) k_pcg_small(int nF, const double*
                                                            double tol2, double floor2, int flat_blocks,
                                                            double* __restrict__ info) {
   constexpr int NF = K + 1;
-  __shared__ double sh[4 * (kSmallBlock / 64)];
+  // reduction scratch: shq for p.q, shr for the four sums of the update pass
+  // (alternating areas; see small_reduce)
+  __shared__ double shq[kSmallBlock / 64], shr[4 * (kSmallBlock / 64)];
   __shared__ double sv[LDS ? 4 : 1][LDS ? kSmallLds : 1];
   double* r = LDS ? sv[0] : rg;
   double* z = LDS ? sv[1] : zg;
@@ -1954,7 +1958,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_pcg_small(int nF, const double*
     }
     precond_facet(F, red);
   }
-  small_reduce(red, 4, sh);
+  small_reduce(red, 4, shr);
   double mean = red[3] / nnull;
   double rz = red[2] - mean * red[1];
   for (int F = tid; F < nF; F += kSmallBlock)
@@ -1985,7 +1989,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_pcg_small(int nF, const double*
         pq += p[F * NF + i] * acc;
       }
     }
-    small_reduce(&pq, 1, sh);
+    small_reduce(&pq, 1, shq);
     const double alpha = pq != 0.0 ? rz / pq : 0.0;
     // x, r updates and the preconditioner, facet by facet
     red[0] = red[1] = red[2] = red[3] = 0.0;
@@ -1997,7 +2001,7 @@ __global__ void __launch_bounds__(kSmallBlock) k_pcg_small(int nF, const double*
       }
       precond_facet(F, red);
     }
-    small_reduce(red, 4, sh);
+    small_reduce(red, 4, shr);
     rr = fmax(red[0] - red[1] * red[1] / nnull, 0.0);
     ++it;
     if (rr <= tol2) { conv = 1; break; }
