@@ -1861,12 +1861,11 @@ void launch_tracer_rate(int k, hipStream_t st, DMesh m, DTab t, const double* U,
 // arithmetic is that of the multi-launch path (projected residual norm, the
 // same round-off-floor stop); only the summation order of the inner
 // products differs.  info: iterations, final squared residual (null
-// component removed), floor stop, converged.  Workgroup size: 512 threads
-// when the vectors fit in LDS (fewer waves make each barrier cheaper: on
-// 1600 unknowns a solve took 3.9 ms against 4.8 ms with 1024 threads and
-// 4.0 ms with 256), 1024 when they live in global memory.
-constexpr int kSmallBlock = 1024;
-constexpr int kSmallBlockLds = 512;
+// component removed), floor stop, converged.  Workgroup size 512: fewer
+// waves make each barrier cheaper (on 1600 unknowns a solve took 3.9 ms
+// against 4.8 ms with 1024 threads and 4.0 ms with 256; on 9408 unknowns,
+// vectors in global memory, 27.9 against 31.6 ms with 1024).
+constexpr int kSmallBlock = 512;
 
 // No barrier follows the final reads of sh: a caller alternates two scratch
 // areas between consecutive reductions, so the barrier inside the next
@@ -2038,17 +2037,17 @@ __global__ void __launch_bounds__(BS) k_pcg_small(int nF, const double* __restri
 void launch_pcg_small(int k, hipStream_t st, int nF, const double* vals, const int* cols, const double* Dinv,
                       const double* g, double* x, double* r, double* z, double* p, double* q, int maxit, double tol2,
                       double floor2, int flat_blocks, double* info) {
-  constexpr int BL = kSmallBlockLds, BG = kSmallBlock;
+  constexpr int BS = kSmallBlock;
   if ((long)nF * (k + 1) <= kSmallLds) {
-    if (k == 1 && nF <= BL) {
-      k_pcg_small<1, true, true, BL><<<1, BL, 0, st>>>(nF, vals, cols, Dinv, g, x, r, z, p, q, maxit, tol2, floor2,
+    if (k == 1 && nF <= BS) {
+      k_pcg_small<1, true, true, BS><<<1, BS, 0, st>>>(nF, vals, cols, Dinv, g, x, r, z, p, q, maxit, tol2, floor2,
                                                        flat_blocks, info);
     } else {
-      HDG_DISPATCH(k, (k_pcg_small<KK, true, false, BL><<<1, BL, 0, st>>>(nF, vals, cols, Dinv, g, x, r, z, p, q,
+      HDG_DISPATCH(k, (k_pcg_small<KK, true, false, BS><<<1, BS, 0, st>>>(nF, vals, cols, Dinv, g, x, r, z, p, q,
                                                                            maxit, tol2, floor2, flat_blocks, info)));
     }
   } else {
-    HDG_DISPATCH(k, (k_pcg_small<KK, false, false, BG><<<1, BG, 0, st>>>(nF, vals, cols, Dinv, g, x, r, z, p, q,
+    HDG_DISPATCH(k, (k_pcg_small<KK, false, false, BS><<<1, BS, 0, st>>>(nF, vals, cols, Dinv, g, x, r, z, p, q,
                                                                           maxit, tol2, floor2, flat_blocks, info)));
   }
 }
