@@ -740,6 +740,12 @@ int hdg_ctx::pcg(TraceOp& op, const double* gin, double* x) {
     }
   }
   launch_copy(st, n, px, x);
+  // at the cap with |r| within the floor band: the same round-off floor,
+  // reached by a residual that kept wobbling by more than the stall margin
+  if (res <= kPcgFloor * prm.rtol_trace * gnorm) {
+    ++pcg_floor_stops;
+    return it;
+  }
   cap_reached("PCG on the trace system: " + std::to_string(it) + " iterations without reaching rtol_trace (relative residual " +
               sci(res / gnorm) + ")");
   return it;
@@ -760,7 +766,7 @@ int hdg_ctx::pcg_small(TraceOp& op, const double* gin, double gnorm, double* x) 
   if (!(res == res)) throw SolverBreakdown("PCG breakdown (NaN residual)");
   launch_copy(st, nT, px, x);
   if (h_pinned[3] == 0.0) {
-    if (h_pinned[2] != 0.0) {
+    if (h_pinned[2] != 0.0 || res <= flo) {  // stalled, or at the cap, within the floor band
       ++pcg_floor_stops;
     } else {
       cap_reached("PCG on the trace system: " + std::to_string(its) + " iterations without reaching rtol_trace "
