@@ -115,8 +115,10 @@ typedef struct {
                             quarter of the iterations spent, at least 12) with |r|
                             within 1e4 rtol
                             (the round-off floor of an ill-conditioned S) also ends the solve,
-                            counted as pcg_floor_stops in hdg_get_info; so does reaching
-                            max_it_trace with |r| within that band (else NOT_CONVERGED) */
+                            counted as pcg_floor_stops in hdg_get_info; so do, in the
+                            multigrid path, |r| setting no new 1 % low over the same window
+                            within that band, and reaching max_it_trace with |r| within it
+                            (else NOT_CONVERGED) */
   double rtol_velocity;  /* Step I: same criterion on the mass-scaled system */
   int max_it_trace;
   int max_it_velocity;

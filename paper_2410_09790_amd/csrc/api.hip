@@ -697,8 +697,8 @@ int hdg_ctx::pcg(TraceOp& op, const double* gin, double* x) {
   KCHK();
   const bool graphs = prm.use_graphs && !prof.on;
   if (graphs && !op.pcg_block) op.pcg_block = capture([&] { pcg_block(op); });
-  double res = 0.0, best = HUGE_VAL, best_rz = HUGE_VAL;
-  int it = 0, flat = 0;
+  double res = 0.0, best = HUGE_VAL, best_rz = HUGE_VAL, best_r = HUGE_VAL;
+  int it = 0, flat = 0, flat_r = 0;
   while (it < maxit) {
     if (graphs) HIPCHK(hipGraphLaunch(op.pcg_block, st));
     else pcg_block(op);
@@ -720,6 +720,12 @@ int hdg_ctx::pcg(TraceOp& op, const double* gin, double* x) {
     }
     it += kPcgBlock;
     best = std::min(best, low);
+    if (low < 0.98 * best_r) {
+      best_r = low;
+      flat_r = 0;
+    } else {
+      ++flat_r;
+    }
     // Round-off floor: with rtol near eps times the condition number of S
     // (1e-12 against ~3e4 at 64 x 64, k = 3, c = 1, and more at higher k and
     // finer meshes) the recursion can stop improving above rtol on smooth
@@ -729,11 +735,18 @@ int hdg_ctx::pcg(TraceOp& op, const double* gin, double* x) {
     // spent so far: a fast multigrid solve that stalls gives up after 12
     // iterations, a slow Jacobi solve with long plateaus waits longer), with
     // |r| within kPcgFloor * rtol, ends the solve (counted) instead of
-    // running to the cap.
+    // running to the cap.  So does |r| itself setting no new 2 % low for
+    // that window inside the band (a multigrid solve whose r.z keeps
+    // wobbling to new lows while |r| sits at the floor).
+    const int window = std::max(kPcgFlatBlocks, it / 16);
+    const bool in_band = best <= kPcgFloor * prm.rtol_trace * gnorm;
     if (low_rz < 0.98 * best_rz) {
       best_rz = low_rz;
       flat = 0;
-    } else if (++flat >= std::max(kPcgFlatBlocks, it / 16) && best <= kPcgFloor * prm.rtol_trace * gnorm) {
+    } else {
+      ++flat;
+    }
+    if (in_band && (flat >= window || flat_r >= window)) {
       ++pcg_floor_stops;
       launch_copy(st, n, px, x);
       return it;
