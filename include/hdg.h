@@ -116,7 +116,7 @@ typedef struct {
                             within 1e4 rtol
                             (the round-off floor of an ill-conditioned S) also ends the solve,
                             counted as pcg_floor_stops in hdg_get_info; so do, in the
-                            multigrid path, |r| setting no new 1 % low over the same window
+                            multigrid path, |r| setting no new 2 % low over the same window
                             within that band, and reaching max_it_trace with |r| within it
                             (else NOT_CONVERGED) */
   double rtol_velocity;  /* Step I: same criterion on the mass-scaled system */
