@@ -44,12 +44,12 @@ WORKLOAD = {"workload": "unit_square_256x256_k3_ars222", "n": 256, "k": 3, "seed
             "rtol_trace": 1e-12, "rtol_velocity": 1e-10}
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
-KERNELS_SRC = os.path.join(ROOT, "paper_2410_09790_amd", "csrc", "kernels.hip")
+KERNELS_SRC = os.path.join(ROOT, "paper_2410_09790_amd", "csrc", "step1.hip")
 # HBM bytes per launch of the dominant kernel from the FETCH_SIZE / WRITE_SIZE
 # counter passes (each scaled by the counts of a 256 MiB copy), valid only for
-# the kernel source they were taken on (sha256 prefix of kernels.hip)
+# the kernel source they were taken on (sha256 prefix of step1.hip, the Step I kernels)
 MEASURED_TRAFFIC = {
-    "apply_step1_operator": {"kernels_sha256": "95ff23421c899865", "bytes_per_launch": 384.7e6},
+    "apply_step1_operator": {"kernels_sha256": "f75de82eff364ef5", "bytes_per_launch": 385.4e6},
 }
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
 MIXED_RTOL_VELOCITY = 1e-5  # Step I tolerance of the mixed-precision run

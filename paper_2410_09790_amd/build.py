@@ -21,6 +21,7 @@ SOURCES = [
     ("ref.cpp", "host"),
     ("mesh.cpp", "host"),
     ("kernels.hip", "hip"),
+    ("step1.hip", "hip"),
     ("api.hip", "hip"),
 ]
 

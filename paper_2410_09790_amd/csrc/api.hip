@@ -251,12 +251,29 @@ struct hdg_ctx {
   // statistics
   std::vector<int> pcg_iters, bicg_iters;
   long total_pcg = 0, total_bicg = 0, n_trace_solves = 0, n_velocity_solves = 0, bicg_restarts = 0;
-  long pcg_floor_stops = 0;  // trace solves ended at the round-off floor (within kPcgFloor * rtol)
+  long pcg_floor_stops = 0;  // trace solves ended at the round-off floor (within floor_band())
+  double pcg_floor_true_max = 0.0;  // largest true relative residual |g - S x| / |g| of those solves
+  double velocity_true_max = 0.0;   // largest true relative residual of a converged Step I solve
+  long velocity_true_restarts = 0;  // Step I solves continued because the true residual was above 10 rtol
   static constexpr int kPcgFlatBlocks = 3;  // shortest stall window (blocks); it grows to a quarter of the iterations spent
   static constexpr long kSmallTrace = 24576;  // trace unknowns up to which Jacobi-PCG runs in one workgroup
   double* small_info = nullptr;
   int pcg_small(hdg::TraceOp& op, const double* gin, double gnorm, double* x);
   static constexpr double kPcgFloor = 1e4;
+  static constexpr double kPcgFloorMax = 1e-9;
+  // Relative round-off band of the trace solve: a solve may end above rtol
+  // only with its residual inside this band.  It is kPcgFloor * rtol, but
+  // never above kPcgFloorMax, so that a loose rtol does not widen it.
+  double floor_band() const { return std::min(kPcgFloor * prm.rtol_trace, kPcgFloorMax); }
+  double trace_true_residual(hdg::TraceOp& op, const double* gin, const double* x);
+  // a solve ended at the round-off floor: its true residual must lie in the band
+  void accept_floor(double true_rel, int its) {
+    ++pcg_floor_stops;
+    pcg_floor_true_max = std::max(pcg_floor_true_max, true_rel);
+    if (true_rel > floor_band())
+      cap_reached("PCG on the trace system: stalled after " + std::to_string(its) + " iterations with a true "
+                  "relative residual of " + hdg::sci(true_rel) + ", above the round-off band " + hdg::sci(floor_band()));
+  }
   double t_trace = 0.0, t_velocity = 0.0, t_other = 0.0;
   int max_pcg_bicg_seen = 0;
   bool not_converged = false;
@@ -697,7 +714,7 @@ int hdg_ctx::pcg(TraceOp& op, const double* gin, double* x) {
   KCHK();
   const bool graphs = prm.use_graphs && !prof.on;
   if (graphs && !op.pcg_block) op.pcg_block = capture([&] { pcg_block(op); });
-  double res = 0.0, best = HUGE_VAL, best_rz = HUGE_VAL, best_r = HUGE_VAL;
+  double res = 0.0, best_rz = HUGE_VAL, best_r = HUGE_VAL;
   int it = 0, flat = 0, flat_r = 0;
   while (it < maxit) {
     if (graphs) HIPCHK(hipGraphLaunch(op.pcg_block, st));
@@ -719,7 +736,6 @@ int hdg_ctx::pcg(TraceOp& op, const double* gin, double* x) {
       low_rz = std::min(low_rz, std::fabs(hrz[b + 1]));
     }
     it += kPcgBlock;
-    best = std::min(best, low);
     if (low < 0.98 * best_r) {
       best_r = low;
       flat_r = 0;
@@ -734,12 +750,15 @@ int hdg_ctx::pcg(TraceOp& op, const double* gin, double* x) {
     // max(kPcgFlatBlocks, it / 16) blocks (a quarter of the iterations
     // spent so far: a fast multigrid solve that stalls gives up after 12
     // iterations, a slow Jacobi solve with long plateaus waits longer), with
-    // |r| within kPcgFloor * rtol, ends the solve (counted) instead of
-    // running to the cap.  So does |r| itself setting no new 2 % low for
-    // that window inside the band (a multigrid solve whose r.z keeps
-    // wobbling to new lows while |r| sits at the floor).
+    // the current |r| within the round-off band (floor_band()), ends the
+    // solve (counted) instead of running to the cap.  So does |r| itself
+    // setting no new 2 % low for that window inside the band (a multigrid
+    // solve whose r.z keeps wobbling to new lows while |r| sits at the
+    // floor).  Either way the true residual is recomputed and must lie in
+    // the band too.
     const int window = std::max(kPcgFlatBlocks, it / 16);
-    const bool in_band = best <= kPcgFloor * prm.rtol_trace * gnorm;
+    // the iterate returned is the current one: its own residual must be in the band
+    const bool in_band = res <= floor_band() * gnorm;
     if (low_rz < 0.98 * best_rz) {
       best_rz = low_rz;
       flat = 0;
@@ -747,16 +766,17 @@ int hdg_ctx::pcg(TraceOp& op, const double* gin, double* x) {
       ++flat;
     }
     if (in_band && (flat >= window || flat_r >= window)) {
-      ++pcg_floor_stops;
       launch_copy(st, n, px, x);
+      accept_floor(trace_true_residual(op, gin, px) / gnorm, it);
       return it;
     }
   }
   launch_copy(st, n, px, x);
-  // at the cap with |r| within the floor band: the same round-off floor,
-  // reached by a residual that kept wobbling by more than the stall margin
-  if (res <= kPcgFloor * prm.rtol_trace * gnorm) {
-    ++pcg_floor_stops;
+  // at the cap: accepted only with a true residual within 1e2 rtol (a
+  // residual that kept wobbling at its round-off floor just above rtol)
+  const double tr = trace_true_residual(op, gin, px) / gnorm;
+  if (tr <= std::min(1e2 * prm.rtol_trace, floor_band())) {
+    accept_floor(tr, it);
     return it;
   }
   cap_reached("PCG on the trace system: " + std::to_string(it) + " iterations without reaching rtol_trace (relative residual " +
@@ -768,7 +788,7 @@ int hdg_ctx::pcg(TraceOp& op, const double* gin, double* x) {
 // launch (launch and synchronisation latency, not bandwidth, bound the
 // multi-launch iteration there).  Same stopping rules as pcg().
 int hdg_ctx::pcg_small(TraceOp& op, const double* gin, double gnorm, double* x) {
-  const double tol = prm.rtol_trace * gnorm, flo = kPcgFloor * prm.rtol_trace * gnorm;
+  const double tol = prm.rtol_trace * gnorm, flo = floor_band() * gnorm;
   launch_pcg_small(k, st, (int)hm.nF, op.vals, op.cols, op.Dinv, gin, px, pr, pz, pp, pq, prm.max_it_trace, tol * tol,
                    flo * flo, kPcgFlatBlocks, small_info);
   KCHK();
@@ -779,14 +799,26 @@ int hdg_ctx::pcg_small(TraceOp& op, const double* gin, double gnorm, double* x) 
   if (!(res == res)) throw SolverBreakdown("PCG breakdown (NaN residual)");
   launch_copy(st, nT, px, x);
   if (h_pinned[3] == 0.0) {
-    if (h_pinned[2] != 0.0 || res <= flo) {  // stalled, or at the cap, within the floor band
-      ++pcg_floor_stops;
+    const double tr = trace_true_residual(op, gin, px) / gnorm;
+    if (h_pinned[2] != 0.0 || tr <= std::min(1e2 * prm.rtol_trace, floor_band())) {  // stalled in the band, or at the cap near rtol
+      accept_floor(tr, its);
     } else {
       cap_reached("PCG on the trace system: " + std::to_string(its) + " iterations without reaching rtol_trace "
                   "(relative residual " + sci(res / gnorm) + ")");
     }
   }
   return its;
+}
+
+// |g - S x| without the component along the constant trace (the norm the
+// trace solves stop on), recomputed from x rather than recursively updated
+double hdg_ctx::trace_true_residual(TraceOp& op, const double* gin, const double* xv) {
+  const double* scr = scal + 3 * (prm.max_it_trace + 4) + 2;
+  launch_residual(k, st, (int)hm.nF, op.vals, op.cols, gin, xv, t3);
+  launch_rr_partials(st, nT, nf, t3, part);
+  launch_finish_proj(st, part, kRedBlocks, (double)hm.nF, const_cast<double*>(scr));
+  KCHK();
+  return std::sqrt(read_scalar(scr));
 }
 
 void hdg_ctx::solve_trace(double c, const double* Fw, const double* Fpsi, const double* Fmu, double* U, double* pout,
@@ -922,7 +954,31 @@ int hdg_ctx::bicgstab(double adt, const double* b_aos, double* x_aos) {
     sync();
     const double rr = h_pinned[BS_STRIDE * (kBicgBlock - 1) + BS_RR];
     if (!(rr == rr)) throw SolverBreakdown("BiCGStab breakdown (NaN residual); the result is invalid");
-    if (std::sqrt(rr) <= rtol * bnorm) break;
+    if (std::sqrt(rr) <= rtol * bnorm) {
+      // the recursive residual says converged: check the true one b - A x
+      // (in B.r from here on); more than 10 rtol away continues from it
+      {
+        Timed tm(prof, KC_APPLY_OP);
+        launch_apply_soa(k, st, s1, 0, dm, dt, vk, vk32, vbeta, prm.alpha, adt, B.x, nullptr, B.t, nullptr);
+      }
+      launch_copy(st, n, B.b, B.r);
+      launch_axpby(st, n, -1.0, B.t, 1.0, B.r);
+      double* tslot = bsc + (long)BS_STRIDE * (kBicgBlock + 1);
+      launch_dot(st, n, B.r, nullptr, part);
+      launch_finish(st, part, kRedBlocks, tslot);
+      const double tr = std::sqrt(read_scalar(tslot)) / bnorm;
+      if (!(tr == tr)) throw SolverBreakdown("BiCGStab: non-finite true residual");
+      velocity_true_max = std::max(velocity_true_max, tr);
+      if (tr <= 10.0 * rtol) break;
+      if (it >= maxit) {
+        cap_reached("BiCGStab (Step I): " + std::to_string(it) + " iterations; true relative residual " + sci(tr) +
+                    " above 10 rtol_velocity");
+        break;
+      }
+      ++velocity_true_restarts;
+      restart = true;
+      continue;
+    }
     if (it >= maxit) {
       cap_reached("BiCGStab (Step I): " + std::to_string(it) + " iterations without reaching rtol_velocity "
                   "(relative residual " + sci(std::sqrt(rr) / bnorm) + ", " +
@@ -1903,7 +1959,10 @@ int hdg_get_info(const hdg_ctx* ctx, char* buf, size_t cap) {
     for (size_t i = st; i < v.size(); ++i) s += (i > st ? "," : "") + std::to_string(v[i]);
     return s + "]";
   };
+  size_t amg_levels = 0;  // aggregation levels below the P1 coarse space (largest over the trace operators)
+  for (const auto& kv : ctx->ops) amg_levels = std::max(amg_levels, kv.second->levels.size());
   std::string s = "{\"ncells\":" + std::to_string(ctx->hm.nc) + ",\"nfacets\":" + std::to_string(ctx->hm.nF) +
+                  ",\"amg_levels\":" + std::to_string(amg_levels) +
                   ",\"degree\":" + std::to_string(ctx->k) + ",\"n_trace_dofs\":" + std::to_string(ctx->nT) +
                   ",\"trace_solves\":" + std::to_string(ctx->n_trace_solves) +
                   ",\"pcg_iterations_total\":" + std::to_string(ctx->total_pcg) +
@@ -1911,6 +1970,10 @@ int hdg_get_info(const hdg_ctx* ctx, char* buf, size_t cap) {
                   ",\"velocity_iterations_total\":" + std::to_string(ctx->total_bicg) +
                   ",\"bicgstab_restarts\":" + std::to_string(ctx->bicg_restarts) +
                   ",\"pcg_floor_stops\":" + std::to_string(ctx->pcg_floor_stops) +
+                  ",\"pcg_floor_band\":" + hdg::sci(ctx->floor_band()) +
+                  ",\"pcg_floor_true_residual_max\":" + hdg::sci(ctx->pcg_floor_true_max) +
+                  ",\"velocity_true_residual_max\":" + hdg::sci(ctx->velocity_true_max) +
+                  ",\"velocity_true_residual_restarts\":" + std::to_string(ctx->velocity_true_restarts) +
                   ",\"device_bytes\":" + std::to_string(ctx->dev_bytes) +
                   ",\"pending_stage\":" + std::to_string(ctx->pend_stage) +
                   ",\"step1_block\":" + std::to_string(ctx->s1.block) +

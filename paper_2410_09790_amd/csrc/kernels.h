@@ -165,6 +165,8 @@ void launch_eval_points(hipStream_t st, long nc, int npts, int ns, int np, const
 // Krylov helpers with device scalars
 void launch_pcg_update(hipStream_t st, long n, int nf, const double* rz, const double* pq, const double* p,
                        const double* q, double* x, double* r, double* part_rr);
+// partials of r.r and sum r_0 over kRedBlocks blocks, the layout launch_pcg_update leaves
+void launch_rr_partials(hipStream_t st, long n, int nf, const double* r, double* part);
 // sum(part[0..n)) - sum(part[n..2n))^2 / nnull  (residual norm^2 without its null-vector part)
 void launch_finish_proj(hipStream_t st, const double* part, int nparts, double nnull, double* out);
 void launch_pcg_direction(hipStream_t st, long n, const double* rz_new, const double* rz_old, const double* z, double* p);

@@ -112,9 +112,9 @@ def test_other_diagonal_steps():
         ctx.set_velocity_from_points(vel(xy[..., 0], xy[..., 1]))
         ctx.advance(1e-2, 2)
         got = [host(t) for t in ctx.get_state()]
-        assert rel_l2_cells(d, got[0], Q, d.nu) < 1e-10
-        assert rel_l2_cells(d, got[1], p, d.npp) < 1e-9
-        assert rel_l2_trace(d, got[2], lam) < 1e-9
+        errs = (rel_l2_cells(d, got[0], Q, d.nu), rel_l2_cells(d, got[1], p, d.npp), rel_l2_trace(d, got[2], lam))
+        print(f"diagonal 1, periodic {periodic}: rel L2 Q {errs[0]:.2e} p {errs[1]:.2e} lam {errs[2]:.2e}")
+        assert max(errs) < 1e-10, errs
 
 
 def test_high_degree_reconstruction_stalls_are_accepted():
@@ -156,6 +156,10 @@ def test_multigrid_reconstruction_at_the_floor_ends_early():
         out.append((host(ctx.get_state()[1]), ctx.info()))
         ctx.close()
     (p12, i12), (p9, i9) = out
-    assert i12["pcg_iterations_last"][-1] <= 200
+    print("1e-12 solve:", i12["pcg_iterations_last"], i12["pcg_floor_stops"], i12["pcg_floor_true_residual_max"])
+    assert i12["pcg_floor_stops"] >= 1
+    assert i12["pcg_iterations_last"][-1] <= 64  # measured: about 40
+    # the stopped solve's recomputed residual lies in the round-off band
+    assert 0.0 < i12["pcg_floor_true_residual_max"] <= i12["pcg_floor_band"]
     assert i9["pcg_floor_stops"] == 0
-    assert np.linalg.norm(p12 - p9) <= 1e-7 * np.linalg.norm(p9)
+    assert np.linalg.norm(p12 - p9) <= 1e-8 * np.linalg.norm(p9)

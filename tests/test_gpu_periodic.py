@@ -69,9 +69,9 @@ def test_periodic_shear_layer_steps(scheme, k, n, nR):
     ctx.set_velocity_from_points(_shear(xy[..., 0], xy[..., 1]))
     ctx.advance(dt, nsteps)
     Qg, pg, lg = (host(t) for t in ctx.get_state())
-    assert rel_l2_cells(d, Qg, Q, d.nu) < 1e-10
-    assert rel_l2_cells(d, pg, p, d.npp) < 1e-9
-    assert rel_l2_trace(d, lg, lam) < 1e-9
+    errs = (rel_l2_cells(d, Qg, Q, d.nu), rel_l2_cells(d, pg, p, d.npp), rel_l2_trace(d, lg, lam))
+    print(f"{scheme} k={k} n={n}: rel L2 Q {errs[0]:.2e} p {errs[1]:.2e} lam {errs[2]:.2e}")
+    assert max(errs) < 1e-10, errs
 
 
 def test_uniform_flow_stays_steady_at_size():
