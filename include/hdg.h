@@ -257,6 +257,16 @@ int hdg_tracer_rate(hdg_ctx* ctx, const double* Q, const double* q, double* out)
  * bytes on first use. */
 int hdg_eval_points(hdg_ctx* ctx, const double* xy_ref, int npts, double* Q_out, double* p_out);
 
+/* For callers that cannot allocate device memory (tight serving loops, code
+ * that must not call hipMalloc): hdg_eval_points with the same arguments,
+ * layout and results, but the basis table is staged in a static device array
+ * of 288 KiB (1024 points at degree 4) that every device holds until the
+ * process ends, so the call allocates nothing.  npts above 1024 gives
+ * INVALID_ARG with a message.  All contexts on one device share that array:
+ * calls that overlap on one device (contexts on different streams or host
+ * threads) race and must be serialised by the caller. */
+int hdg_eval_points_noalloc(hdg_ctx* ctx, const double* xy_ref, int npts, double* Q_out, double* p_out);
+
 /* Host-side mesh of the square [0, length]^2 cut into n x n squares, each
  * split along a diagonal (the paper's test meshes): vertex (i, j) has id
  * j (n+1) + i at (i, j) length / n; square (i, j) gives the cells with ids

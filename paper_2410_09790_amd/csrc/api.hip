@@ -17,6 +17,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <set>
 #include <string>
@@ -31,6 +32,31 @@ namespace hdg {
 
 static thread_local std::string g_create_error;
 constexpr int kMaxEvalPoints = 1024;
+
+// Staging area of hdg_eval_points_noalloc: the velocity- and pressure-degree
+// basis values at up to kMaxEvalPoints points for the largest degree
+// (ns = 21 and np = 15 at k = 4), 288 KiB.  Every device the library runs on
+// holds its own copy until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress gives on that device.
+constexpr int kEvalScratchDoubles = kMaxEvalPoints * (21 + 15);
+static __device__ __align__(256) double scratch[kEvalScratchDoubles];
+static std::mutex g_scratch_mu;
+static std::map<int, double*> g_scratch_ptr;  // device id -> that device's copy of scratch
+
+// Address of the current device's copy of scratch, looked up once per device
+// (the caller has made `device` current); nullptr if the lookup fails.
+static double* scratch_address(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it != g_scratch_ptr.end()) return it->second;
+  double* ptr = nullptr;
+  if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  g_scratch_ptr[device] = ptr;
+  return ptr;
+}
 
 struct HipError : std::runtime_error {
   explicit HipError(const std::string& s) : std::runtime_error(s) {}
@@ -385,6 +411,8 @@ struct hdg_ctx {
   void tracer_step(double dtv);
   int pend_stage = 0;     // next implicit stage of a step in progress (0: none)
   double* eval_tab = nullptr;  // basis values at hdg_eval_points' points
+  double* eval_scratch = nullptr;        // this device's copy of scratch (hdg_eval_points_noalloc)
+  std::vector<double> eval_host;         // host staging of the same values, sized at creation
   double pend_dt = 0.0;   // its time step
   void begin_step(double dt);
   void stage_once();
@@ -1542,6 +1570,8 @@ int hdg_create_periodic(int64_t nv, const double* coords, int64_t nc, const int3
   try {
     build_reference(ctx->k, ctx->rt);
     ctx->setup();
+    ctx->eval_scratch = scratch_address(ctx->device);
+    ctx->eval_host.assign(kEvalScratchDoubles, 0.0);
   } catch (const OomError& ex) {
     g_create_error = ex.what();
     hdg_destroy(ctx.release());
@@ -1816,6 +1846,40 @@ int hdg_eval_points(hdg_ctx* ctx, const double* xy_ref, int npts, double* Qo, do
                         ctx->st));
   launch_eval_points(ctx->st, ctx->hm.nc, npts, ns, np, ctx->eval_tab, ctx->eval_tab + bu.size(), ctx->Q, ctx->p, Qo,
                      po);
+  KCHK();
+  ctx->sync();
+  API_END(ctx)
+}
+
+// hdg_eval_points with the basis table staged in the device's static scratch
+// array instead of a buffer allocated on first use: no device allocation.
+// Calls on one device share the array, so calls that overlap there race.
+int hdg_eval_points_noalloc(hdg_ctx* ctx, const double* xy_ref, int npts, double* Qo, double* po) {
+  if (!ctx || !xy_ref || npts < 1 || (!Qo && !po)) return HDG_ERR_INVALID_ARG;
+  if (npts > kMaxEvalPoints) {
+    ctx->err = "hdg_eval_points_noalloc: " + std::to_string(npts) + " points, more than the static staging area's " +
+               std::to_string(kMaxEvalPoints);
+    return HDG_ERR_INVALID_ARG;
+  }
+  if (!ctx->have_state) { ctx->err = "no state set"; return HDG_ERR_BAD_STATE; }
+  if (!ctx->eval_scratch) {
+    ctx->err = "hdg_eval_points_noalloc: the static staging area has no address on this device";
+    return HDG_ERR_DEVICE;
+  }
+  ctx->not_converged = false;
+  ctx->err.clear();
+  API_BEGIN
+  const int ns = ctx->ns, np = ctx->np;
+  if ((long)npts * (ns + np) > kEvalScratchDoubles) throw ArgError("staging area too small for this degree");
+  double* bu = ctx->eval_host.data();
+  double* bp = bu + (size_t)npts * ns;
+  for (int q = 0; q < npts; ++q) {
+    dubiner_eval(ctx->k + 1, xy_ref[2 * q], xy_ref[2 * q + 1], bu + (size_t)q * ns, nullptr, nullptr);
+    dubiner_eval(ctx->k, xy_ref[2 * q], xy_ref[2 * q + 1], bp + (size_t)q * np, nullptr, nullptr);
+  }
+  double* d = ctx->eval_scratch;
+  HIPCHK(hipMemcpyAsync(d, bu, sizeof(double) * (size_t)npts * (ns + np), hipMemcpyHostToDevice, ctx->st));
+  launch_eval_points(ctx->st, ctx->hm.nc, npts, ns, np, d, d + (size_t)npts * ns, ctx->Q, ctx->p, Qo, po);
   KCHK();
   ctx->sync();
   API_END(ctx)

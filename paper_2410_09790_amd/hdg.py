@@ -30,7 +30,7 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NOT_CO
 EXPORTS = [
     "hdg_default_params", "hdg_create", "hdg_create_periodic", "hdg_destroy", "hdg_footprint_bytes",
     "hdg_batch_create", "hdg_batch_size", "hdg_batch_advance", "hdg_batch_destroy", "hdg_advance_stages",
-    "hdg_pending_stage", "hdg_eval_points", "hdg_mesh_square", "hdg_set_tracer", "hdg_get_tracer",
+    "hdg_pending_stage", "hdg_eval_points", "hdg_eval_points_noalloc", "hdg_mesh_square", "hdg_set_tracer", "hdg_get_tracer",
     "hdg_cg_project", "hdg_tracer_rate", "hdg_last_error", "hdg_sizes", "hdg_cell_points",
     "hdg_facet_points", "hdg_set_forcing", "hdg_set_time", "hdg_get_time", "hdg_set_velocity_from_points", "hdg_set_state", "hdg_get_state", "hdg_advance", "hdg_solve_trace",
     "hdg_trace_matvec", "hdg_bdm_project", "hdg_weak_divergence", "hdg_momentum_residual",
@@ -90,6 +90,7 @@ def load_library(path: str = LIB_PATH):
         "hdg_advance_stages": (I, [P, D, I]),
         "hdg_pending_stage": (I, [P]),
         "hdg_eval_points": (I, [P, P, I, P, P]),
+        "hdg_eval_points_noalloc": (I, [P, P, I, P, P]),
         "hdg_mesh_square": (I, [I, D, I, I, P, P, P]),
         "hdg_set_tracer": (I, [P, P]),
         "hdg_get_tracer": (I, [P, P]),
@@ -311,6 +312,14 @@ class Context:
         self._check(self._lib.hdg_eval_points(self._h, pts.ctypes.data_as(ctypes.c_void_p), pts.shape[0], _ptr(Qo),
                                               _ptr(po)))
         return Qo.view(self.ncells, pts.shape[0], 2), po.view(self.ncells, pts.shape[0])
+
+    def eval_points_noalloc(self, xy_ref, Qo, po):
+        """eval_points into caller buffers (device tensors of ncells * npts * 2 and
+        ncells * npts doubles, either may be None), with no device allocation
+        inside the library."""
+        pts = np.ascontiguousarray(xy_ref, dtype=np.float64).reshape(-1, 2)
+        self._check(self._lib.hdg_eval_points_noalloc(self._h, pts.ctypes.data_as(ctypes.c_void_p), pts.shape[0],
+                                                      _ptr(Qo), _ptr(po)))
 
     # ------------------------------------------------------- path pieces
     def solve_trace(self, c, Fw=None, Fpsi=None, Fmu=None):
