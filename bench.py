@@ -44,12 +44,20 @@ WORKLOAD = {"workload": "unit_square_256x256_k3_ars222", "n": 256, "k": 3, "seed
             "rtol_trace": 1e-12, "rtol_velocity": 1e-10}
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
-KERNELS_SRC = os.path.join(ROOT, "paper_2410_09790_amd", "csrc", "step1.hip")
-# HBM bytes per launch of the dominant kernel from the FETCH_SIZE / WRITE_SIZE
-# counter passes (each scaled by the counts of a 256 MiB copy), valid only for
-# the kernel source they were taken on (sha256 prefix of step1.hip, the Step I kernels)
+CSRC = os.path.join(ROOT, "paper_2410_09790_amd", "csrc")
+# HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes (each
+# scaled by the counts of a 256 MiB copy), valid only for the kernel code
+# they were taken on: the sha256 prefix of the listed functions' source text
+# (the kernel and the device functions it calls), so an edit elsewhere in the
+# file leaves a record valid and an edit of the kernel voids it
 MEASURED_TRAFFIC = {
-    "apply_step1_operator": {"kernels_sha256": "f75de82eff364ef5", "bytes_per_launch": 385.4e6},
+    "apply_step1_operator": {"src": "step1.hip", "funcs": ["pair_swap", "tile_idx", "VPairs", "step1_core",
+                                                           "xcd_block", "stage_fbu", "k_apply_soa"],
+                             "sha256": "3c0c5c4a232c8b2b", "bytes_per_launch": 404.1e6},
+    "step1_precond_apply": {"src": "step1.hip", "funcs": ["PcLayout", "PcApplyShape", "k_pc_apply"],
+                            "sha256": "f95d7160166a152f", "bytes_per_launch": 1674.6e6},
+    "trace_spmv": {"src": "kernels.hip", "funcs": ["k_spmv"], "sha256": "96d7545c27858460", "bytes_per_launch": 159.0e6},
+    "trace_spmv_512": {"src": "kernels.hip", "funcs": ["k_spmv"], "sha256": "96d7545c27858460", "bytes_per_launch": 627.0e6},
 }
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
 MIXED_RTOL_VELOCITY = 1e-5  # Step I tolerance of the mixed-precision run
@@ -60,7 +68,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_cost(kernel: str, k: int, nc: int, nF: int):
+def algorithmic_cost(kernel: str, k: int, nc: int, nF: int, nF_int: int | None = None):
     """(bytes, flops) that one launch of `kernel` must move / execute at minimum.
 
     apply_step1_operator (mass-scaled Step I operator on structure-of-arrays
@@ -73,13 +81,24 @@ def algorithmic_cost(kernel: str, k: int, nc: int, nF: int):
     (own trace, neighbour trace, projection) plus ~10 for the jump and flux.
     trace_spmv (facet-block ELL, FP64): per facet row 5 blocks of (k+1)^2
     values, 5 int32 column ids, reads x and writes y ((k+1) doubles each).
+    step1_precond_apply (facet-patch Schwarz of the Step I operator): per
+    interior facet the FP16 inverse of its 2 nu x 2 nu block (nu = 2 ns),
+    read as two halves by the two cells, plus per cell the input and output
+    vectors (nu doubles each) and 3 int32 neighbour entries.  nF_int: the
+    interior facets (default nF).
     """
     ns = (k + 2) * (k + 3) // 2
     nqf = (3 * k + 5) // 2
     nf = k + 1
+    nu = 2 * ns
     if kernel == "apply_step1_operator":
         nbytes = nc * (8 * (ns * ns + 3 * nqf + 7 + 3 * 2 * ns) + 4 * 9)
         flops = nc * 2 * (2 * ns * ns + 3 * nqf * (6 * ns + 10) + 2 * ns)
+        return nbytes, flops
+    if kernel == "step1_precond_apply":
+        ni = nF if nF_int is None else nF_int
+        nbytes = ni * (2 * nu) ** 2 * 2 + nc * (2 * 8 * nu + 4 * 3)
+        flops = ni * 2 * 2 * nu * nu * 2
         return nbytes, flops
     if kernel == "trace_spmv":
         nbytes = nF * (8 * 5 * nf * nf + 4 * 5 + 8 * 2 * nf)
@@ -88,20 +107,75 @@ def algorithmic_cost(kernel: str, k: int, nc: int, nF: int):
     return None, None
 
 
-def measured_traffic(kernel: str):
+def method_bytes(kernel: str, k: int, nc: int):
+    """Bytes per launch of the Step I operator if it read only what the method
+    itself defines per cell: the input, output and inner-product vectors
+    (3 x 2 ns doubles), Q* (2 ns doubles), det J and the three normals
+    (7 doubles) and 9 int32 connectivity entries; the per-stage cell matrices
+    and upwind weights the kernel streams are a design choice on top."""
+    if kernel != "apply_step1_operator":
+        return None
+    ns = (k + 2) * (k + 3) // 2
+    return nc * (8 * (4 * 2 * ns + 7) + 4 * 9)
+
+
+def function_source(text: str, name: str) -> str:
+    """Source text of the function or struct `name` (its declaration line
+    through the brace that closes its body, template line included)."""
+    import re
+    m = re.search(r"^[^\n]*\b(?:struct\s+)?" + re.escape(name) + r"\b[^;\n]*(?:\(|\{|$)", text, re.M)
+    while m is not None:
+        start = text.rfind("\n", 0, m.start()) + 1
+        line = text[start:text.find("\n", m.start())]
+        if not line.lstrip().startswith(("//", "return", "if", "for")) and ("(" in line or "struct" in line):
+            break
+        m = re.search(r"^[^\n]*\b" + re.escape(name) + r"\b[^;\n]*(?:\(|\{|$)", text[m.end():], re.M)
+        if m is None:
+            break
+        m = re.search(re.escape(m.group(0)), text)
+    if m is None:
+        raise KeyError(name)
+    start = text.rfind("\n", 0, m.start()) + 1
+    prev = text.rfind("\n", 0, start - 1) + 1
+    if text[prev:start].lstrip().startswith("template"):
+        start = prev
+    i = text.index("{", m.start())
+    depth = 0
+    for j in range(i, len(text)):
+        if text[j] == "{":
+            depth += 1
+        elif text[j] == "}":
+            depth -= 1
+            if depth == 0:
+                return text[start:j + 1]
+    raise ValueError(name)
+
+
+def kernel_sha(rec: dict) -> str:
     import hashlib
+    with open(os.path.join(CSRC, rec["src"])) as fh:
+        text = fh.read()
+    h = hashlib.sha256()
+    for name in rec["funcs"]:
+        h.update(function_source(text, name).encode())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
     rec = MEASURED_TRAFFIC.get(kernel)
     if rec is None:
         return None
-    with open(KERNELS_SRC, "rb") as fh:
-        sha = hashlib.sha256(fh.read()).hexdigest()[:16]
-    return rec["bytes_per_launch"] if sha == rec["kernels_sha256"] else None
+    return rec["bytes_per_launch"] if kernel_sha(rec) == rec["sha256"] else None
 
 
-def cpu_baseline(max_seconds: float = 30.0):
-    """The oracle (NumPy/SciPy, FP64, one thread) on a bounded sample: one step of
-    the same scheme, degree, dt, n_R and seed on the 32 x 32 mesh."""
-    from threadpoolctl import threadpool_limits
+def cpu_baseline():
+    """The oracle (NumPy/SciPy, FP64) on a bounded sample: one step of the same
+    scheme, degree, dt, n_R and seed on the 32 x 32 mesh, timed once with the
+    BLAS thread pools at one thread and once at their default size (all the
+    cores the process may use).  The value is the sample's own throughput in
+    trace DOF-stages/s (the better of the two), not an extrapolation to the
+    256 x 256 mesh: the oracle's direct solves grow faster than the mesh."""
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     import numpy as np
 
@@ -109,20 +183,61 @@ def cpu_baseline(max_seconds: float = 30.0):
     from oracle.forms import Discretisation
     from oracle.imex import IMEXHDG, ars222
     n = 32
-    with threadpool_limits(limits=1):
-        X, C = hi.unit_square_mesh(n)
-        d = Discretisation(X, C, WORKLOAD["k"])
-        st = IMEXHDG(d, WORKLOAD["dt"], ars222(), WORKLOAD["n_richardson"])
-        par = hi.stream_function_params(WORKLOAD["seed"])
-        Q, p, lam = st.initial_state(lambda x, y: hi.streamfunction_velocity(par, x, y))
-        t0 = time.perf_counter()
-        Q, p, lam = st.step(Q, p, lam, 0.0)
-        el = time.perf_counter() - t0
-    assert np.all(np.isfinite(Q))
-    value = d.nT * (ars222().s - 1) / el
-    return {"value": value, "unit": "trace-DOF-stages/s", "cores": 1, "kind": "oracle",
-            "sample": f"one ARS(2,2,2) step, k=3, dt=1e-3, n_R=3, seed 0 on the 32x32 mesh ({d.nT} trace DOFs), "
-                      f"{el:.1f} s, one thread (SuperLU direct solves)"}
+    X, C = hi.unit_square_mesh(n)
+    par = hi.stream_function_params(WORKLOAD["seed"])
+    runs = {}
+    for label, limit in (("one_thread", 1), ("all_threads", None)):
+        with threadpool_limits(limits=limit):
+            threads = max([pool.get("num_threads", 1) for pool in threadpool_info()] or [1])
+            d = Discretisation(X, C, WORKLOAD["k"])
+            st = IMEXHDG(d, WORKLOAD["dt"], ars222(), WORKLOAD["n_richardson"])
+            Q, p, lam = st.initial_state(lambda x, y: hi.streamfunction_velocity(par, x, y))
+            t0 = time.perf_counter()
+            Q, p, lam = st.step(Q, p, lam, 0.0)
+            el = time.perf_counter() - t0
+        assert np.all(np.isfinite(Q))
+        runs[label] = {"threads": threads, "seconds": round(el, 2), "value": d.nT * (ars222().s - 1) / el}
+        log(f"cpu baseline ({label}, {threads} threads): {el:.1f} s for one step")
+    best = max(runs, key=lambda r: runs[r]["value"])
+    return {"value": runs[best]["value"], "unit": "trace-DOF-stages/s", "cores": runs[best]["threads"],
+            "kind": "oracle",
+            "sample": f"one ARS(2,2,2) step, k=3, dt=1e-3, n_R=3, seed 0 on the 32x32 mesh ({d.nT} trace DOFs, "
+                      "SuperLU direct solves); the value is this sample's own throughput, not extrapolated to "
+                      "the 256x256 mesh",
+            "runs": runs, "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
+def trace_operator_run(hdg, hi, torch, n: int = 512, k: int = 3, calls: int = 40):
+    """The assembled trace operator (the SpMV of every PCG iteration) on a mesh
+    whose operator does not fit the 256 MB last-level cache: 512 x 512, k = 3
+    (inside the serving recipe's range), c = gamma dt.  Each of `calls`
+    applications is event-timed; algorithmic bytes as in algorithmic_cost."""
+    import numpy as np
+    X, C = hi.unit_square_mesh(n)
+    ctx = hdg.Context(X, C, degree=k, trace_solver="jacobi_pcg", step1_precond=0)
+    c = (1.0 - 2.0 ** -0.5) * 1e-3
+    x = torch.as_tensor(np.random.default_rng(3).standard_normal(ctx.nT)).cuda()
+    ctx.trace_matvec(c, x)  # builds the operator
+    ctx.trace_matvec(c, x)
+    ctx.profile(1)
+    for _ in range(calls):
+        ctx.trace_matvec(c, x)
+    kv = ctx.info()["kernels"]["trace_spmv"]
+    ctx.profile(0)
+    nbytes, _ = algorithmic_cost("trace_spmv", k, ctx.ncells, ctx.nfacets)
+    avg = kv["ms"] / kv["timed"] * 1e-3
+    gbs = nbytes / avg / 1e9
+    out = {"workload": f"unit_square_{n}x{n}_k{k} trace operator, c = gamma dt ({ctx.nT} trace DOFs, "
+                       f"{nbytes / 1e6:.1f} MB per application, FP64)",
+           "avg_launch_us": round(avg * 1e6, 2), "launches": kv["timed"], "algorithmic_bytes_per_launch": nbytes,
+           "achieved_GBps": round(gbs, 1), "peak": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4),
+           "traffic": MEASURED_TRAFFIC.get("trace_spmv_512", {}).get("bytes_per_launch")
+           if measured_traffic("trace_spmv_512") else None}
+    log(f"trace operator {n}x{n} k={k}: {avg * 1e6:.1f} us per application, {gbs:.0f} GB/s "
+        f"({gbs / HBM_PEAK_GBS:.3f} of peak)")
+    ctx.close()
+    return out
 
 
 def mixed_run(hdg, hi, torch, w, X, C, args, ref_ctx):
@@ -152,11 +267,32 @@ def mixed_run(hdg, hi, torch, w, X, C, args, ref_ctx):
     value = mctx.nT * 2 * args.steps / el
     log(f"mixed: {args.steps} steps {el:.3f} s, {1e3 * el / args.steps:.1f} ms/step, rel. L2 diff vs FP64 {diffs}")
     mctx.close()
+    # the equal-tolerance FP64 leg: FP64 storage with the same Step I rtol, so
+    # that the ratio measures the precision alone
+    fctx = hdg.Context(X, C, degree=w["k"], imex=w["scheme"], n_richardson=w["n_richardson"],
+                       trace_solver=w["trace_solver"], rtol_trace=w["rtol_trace"],
+                       rtol_velocity=MIXED_RTOL_VELOCITY, precision="fp64")
+    fctx.set_velocity_from_points(hi.streamfunction_velocity(par, xy[..., 0], xy[..., 1]))
+    fctx.advance(w["dt"], args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fctx.advance(w["dt"], args.steps)
+    torch.cuda.synchronize()
+    el64 = time.perf_counter() - t0
+    diffs64 = {}
+    for name, a, b in zip(("Q", "p", "lambda"), fctx.get_state(), ref_ctx.get_state()):
+        diffs64[name] = float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+    fctx.close()
+    value64 = ref_ctx.nT * 2 * args.steps / el64
+    log(f"FP64 at the mixed run's Step I rtol: {1e3 * el64 / args.steps:.1f} ms/step, diff vs FP64 {diffs64}")
     return {"value": value, "ms_per_step": 1e3 * el / args.steps,
             "precision": "FP32 storage of the per-stage Step I cell matrices, Step I rtol "
                          f"{MIXED_RTOL_VELOCITY:g}; FP64 arithmetic, Krylov recurrences, trace solves and "
                          "Richardson residual",
-            "rel_l2_diff_vs_fp64": diffs, "speedup_vs_fp64": None}
+            "rel_l2_diff_vs_fp64": diffs, "speedup_vs_fp64": None,
+            "fp64_same_rtol": {"value": value64, "ms_per_step": 1e3 * el64 / args.steps,
+                               "rel_l2_diff_vs_fp64": diffs64},
+            "speedup_precision_only": round(value / value64, 3)}
 
 
 def latency_run(hdg, hi, torch, ncalls: int = 100):
@@ -424,6 +560,7 @@ def main():
     ap.add_argument("--no-shear", action="store_true", help="skip the periodic shear-layer run")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-instances sample")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sample")
+    ap.add_argument("--no-trace-op", action="store_true", help="skip the out-of-cache trace-operator leg")
     ap.add_argument("--batched-instances", type=int, default=4, help="instances of the batched sample (recipe: 64)")
     ap.add_argument("--batched-steps", type=int, default=1, help="timed steps of the batched sample (recipe: 10)")
     ap.add_argument("--serving-jobs", type=int, default=16, help="jobs of the serving sample (recipe: 200)")
@@ -486,6 +623,7 @@ def main():
     assert bool(torch.isfinite(Q).all()), "non-finite velocity"
     stages = 2
     value = ctx.nT * stages * args.steps / el
+    vel_last = info["velocity_iterations_last"]
     pcg = info["pcg_iterations_total"] - before["pcg_iterations_total"]
     bicg = info["velocity_iterations_total"] - before["velocity_iterations_total"]
     nsolves = info["trace_solves"] - before["trace_solves"]
@@ -503,9 +641,23 @@ def main():
             f"~{kv['est_ms']:9.1f} ms in total")
     roofline = None
     timed = {n_: kv for n_, kv in kernels.items() if algorithmic_cost(n_, 1, 1, 1)[0] is not None}
+    nF_int = ctx.nfacets - 4 * w["n"]  # the n x n square has 4 n wall facets
+    # every kernel class with a cost model, with its roofline figures
+    per_kernel = {}
+    for n_, kv in timed.items():
+        nb_, fl_ = algorithmic_cost(n_, w["k"], ctx.ncells, ctx.nfacets, nF_int)
+        gbs = nb_ / (kv["avg_us"] * 1e-6) / 1e9
+        per_kernel[n_] = {"avg_launch_us": round(kv["avg_us"], 2), "launches": kv["launches"],
+                          "algorithmic_bytes_per_launch": nb_, "achieved_GBps": round(gbs, 1),
+                          "frac": round(gbs / HBM_PEAK_GBS, 4), "share_of_step": round(kv["est_ms"] * 1e-3 / el, 3),
+                          "traffic": measured_traffic(n_)}
+        mb = method_bytes(n_, w["k"], ctx.ncells)
+        if mb is not None:
+            per_kernel[n_]["method_bytes_per_launch"] = mb
+            per_kernel[n_]["frac_method_bytes"] = round(mb / (kv["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
     if timed:
         dom = max(timed, key=lambda n_: timed[n_]["est_ms"])
-        nbytes, flops = algorithmic_cost(dom, w["k"], ctx.ncells, ctx.nfacets)
+        nbytes, flops = algorithmic_cost(dom, w["k"], ctx.ncells, ctx.nfacets, nF_int)
         avg_s = timed[dom]["avg_us"] * 1e-6
         t_mem, t_alu = nbytes / (HBM_PEAK_GBS * 1e9), flops / (FP64_PEAK_TFLOPS * 1e12)
         if t_mem >= t_alu:
@@ -517,6 +669,7 @@ def main():
             copy = copy_bandwidth(torch)
             roofline["device_copy_GBps"] = round(copy, 1)
             roofline["frac_of_device_copy"] = round(ach / copy, 4)
+            roofline["kernels"] = per_kernel
             log(f"plain device copy (2 GiB): {copy:.0f} GB/s read + written; the dominant kernel reaches "
                 f"{ach / copy:.2f} of it")
         else:
@@ -540,6 +693,9 @@ def main():
     serving = None
     if not args.no_serving:
         serving = serving_run(hdg, hi, torch, args.serving_jobs, args.serving_nmax, rho=args.serving_rho)
+    trace_op = None
+    if not args.no_trace_op:
+        trace_op = trace_operator_run(hdg, hi, torch)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -560,8 +716,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["workload"], "cells": ctx.ncells, "trace_dofs": ctx.nT, "degree": w["k"],
                    "imex": w["scheme"], "dt": w["dt"], "n_richardson": w["n_richardson"],
-                   "trace_solver": w["trace_solver"], "pcg_iterations": pcg, "trace_solves": nsolves,
-                   "velocity_iterations": bicg, "velocity_solves": nvel},
+                   "trace_solver": w["trace_solver"], "rtol_trace": w["rtol_trace"],
+                   "rtol_velocity": w["rtol_velocity"], "step1_precond": info.get("step1_precond"),
+                   "pcg_iterations": pcg, "trace_solves": nsolves,
+                   "pcg_iterations_per_solve": round(pcg / max(nsolves, 1), 1),
+                   "velocity_iterations": bicg, "velocity_solves": nvel,
+                   "velocity_iterations_per_solve": round(bicg / max(nvel, 1), 1),
+                   "velocity_iterations_last": vel_last,
+                   "bicgstab_restarts": info["bicgstab_restarts"] - before["bicgstab_restarts"],
+                   "velocity_true_residual_max": info["velocity_true_residual_max"],
+                   "pcg_floor_stops": info["pcg_floor_stops"] - before["pcg_floor_stops"],
+                   "pcg_floor_true_residual_max": info["pcg_floor_true_residual_max"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "mixed": mixed,
@@ -569,6 +734,7 @@ def main():
         "shear_layer": shear,
         "batched": batched,
         "serving": serving,
+        "trace_operator_out_of_cache": trace_op,
     }
     if mixed is not None:
         mixed["speedup_vs_fp64"] = round(mixed["value"] / value, 3)

@@ -134,12 +134,23 @@ typedef struct {
                             shapes in the last bits only; one shape always gives the same bits. */
   int step1_xcd;         /* 1: each of the eight XCDs (own L2) takes a contiguous eighth of the
                             cells; 0: the hardware's round-robin order of workgroups */
+  int step1_precond;     /* Step I preconditioner (BiCGStab; ignored with idr_s > 0; right
+                            preconditioning, so the
+                            stopping residual is that of the unpreconditioned system): 1 =
+                            additive Schwarz over facet patches (per interior facet, the block
+                            of the operator on its two cells, inverted per stage in FP64 and
+                            stored in FP16, which changes the convergence, not the solution);
+                            0 = none.  The patches contain the normal-continuous fields on
+                            which the penalty term alpha h^-1 <[Q.n][w.n]> of eq. (f_impl)
+                            vanishes, so the iteration count does not grow with that term's
+                            weight adt/h^2 as it does for cell blocks.  Device memory: 8 nu^2 +
+                            12 nu^2 bytes per cell (nu = (k+2)(k+3)). */
 } hdg_params;
 
 /* Fill p with the defaults: k=1, tau=alpha=delta_up=1, ARS(2,2,2), n_R=3,
  * MG-PCG, rtol 1e-12 for both solvers, caps 5000 / 20000, reconstruction,
- * BiCGStab for Step I, FP64, graph replay on, Step I operator in workgroups
- * of 256 threads in XCD order. */
+ * BiCGStab for Step I with the facet-patch preconditioner, FP64, graph
+ * replay on, Step I operator in workgroups of 256 threads in XCD order. */
 void hdg_default_params(hdg_params* p);
 
 /* Create a context on the current HIP device.  coords: host [nv][2];
@@ -311,6 +322,15 @@ int hdg_momentum_residual(hdg_ctx* ctx, double adt, const double* r, const doubl
 /* Algorithm 2, Step I: solve (Qbar, w) - adt f_im(w, Qbar, Qstar) = rhs(w). */
 int hdg_tentative_velocity(hdg_ctx* ctx, double adt, const double* Qstar, const double* rhs,
                            double* Qbar);
+
+/* The Step I preconditioner (step1_precond = 1) for the operator of
+ * hdg_tentative_velocity in its mass-scaled form A = I - adt M^-1 f_im(., .;
+ * Q*): z = sum over interior facets F of R_F^T A_F^{-1} R_F r, with A_F the
+ * block of A on the unknowns of the two cells of F (couplings through other
+ * facets dropped) and R_F the restriction to them.  r and z in the layout
+ * of Q.  UNSUPPORTED when the context has the preconditioner off (also on a
+ * mesh with a cell that touches no interior facet). */
+int hdg_step1_precond(hdg_ctx* ctx, double adt, const double* Qstar, const double* r, double* z);
 
 /* Pressure reconstruction (Section "Pressure reconstruction"): the mixed
  * problem with psi-data Div(psi, f_p), f_p = -f + (Q.grad_h)Q, and, with a

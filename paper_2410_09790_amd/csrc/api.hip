@@ -174,11 +174,11 @@ struct TraceOp {
 // every `every`-th launch of a class is bracketed by two events (sampling
 // keeps the cost of the event records out of the timed work).
 enum KClass { KC_APPLY_OP = 0, KC_APPLY_RES, KC_TRACE_SPMV, KC_SMOOTH, KC_AMG, KC_CONDENSE, KC_RHS, KC_BACKSUB,
-              KC_BDM, KC_DIV, KC_RECON, KC_VECTOR, kNumKClass };
+              KC_BDM, KC_DIV, KC_RECON, KC_VECTOR, KC_PC_APPLY, KC_PC_BUILD, kNumKClass };
 static const char* kKClassName[kNumKClass] = {"apply_step1_operator", "apply_residual", "trace_spmv",
                                               "trace_jacobi_sweep", "amg_coarse", "condense_assemble",
                                               "rhs_condense", "backsub", "bdm", "weak_div", "recon_rhs",
-                                              "krylov_vector"};
+                                              "krylov_vector", "step1_precond_apply", "step1_precond_build"};
 
 struct Profiler {
   bool on = false;
@@ -353,6 +353,7 @@ struct hdg_ctx {
   struct KrylovBuf {
     double *b = nullptr, *x = nullptr, *r = nullptr, *rh = nullptr, *s = nullptr, *t = nullptr, *p = nullptr,
            *v = nullptr;
+    double *ph = nullptr, *sh = nullptr;  // preconditioned directions (right preconditioning)
   };
   KrylovBuf kd;
   // per-stage Step I data of the current Q*: cell volume matrices (FP32 in
@@ -366,6 +367,30 @@ struct hdg_ctx {
   void prepare_step1(const double* Qstar) {
     hdg::launch_prep_adv(k, st, dm, dt, Qstar, prm.delta_up, adv);
     hdg::launch_step1_matrix(k, st, dm, dt, Qstar, prm.delta_up, vk, vk32, vbeta);
+    vk_qs = Qstar;
+    ++vk_gen;
+  }
+  // Step I preconditioner (facet-patch additive Schwarz): built for the Q*
+  // and adt of the current stage on the first solve that needs it
+  const double* vk_qs = nullptr;  // Q* the Step I data were prepared for
+  long vk_gen = 0, pc_gen = -1;   // generation of the Step I data / of the preconditioner
+  double pc_adt = 0.0;
+  bool pc_on = false;
+  double* pcD = nullptr;          // cell blocks (FP64 scratch of the build)
+  void* pcB = nullptr;            // patch inverses (FP16)
+  long pc_builds = 0;
+  void pc_prepare(double adt) {
+    if (!pc_on || (pc_gen == vk_gen && pc_adt == adt)) return;
+    hdg::Timed tm(prof, hdg::KC_PC_BUILD);
+    hdg::launch_pc_build(k, st, dm, dt, vk_qs, prm.delta_up, prm.alpha, adt, pcD, pcB);
+    KCHK();
+    pc_gen = vk_gen;
+    pc_adt = adt;
+    ++pc_builds;
+  }
+  void pc_apply(const double* r, double* z) {
+    hdg::Timed tm(prof, hdg::KC_PC_APPLY);
+    hdg::launch_pc_apply(k, st, dm, pcB, r, z);
   }
   int bicgstab(double adt, const double* b, double* x);
   static constexpr int kBicgBlock = 8;  // BiCGStab iterations per captured block
@@ -478,6 +503,17 @@ void hdg_ctx::setup() {
   t1 = dalloc<double>(nT); t2 = dalloc<double>(nT); t3 = dalloc<double>(nT); px = dalloc<double>(nT);
   small_info = dalloc<double>(4);
   for (double** v : {&kd.b, &kd.x, &kd.r, &kd.rh, &kd.s, &kd.t, &kd.p, &kd.v}) *v = dalloc<double>(nQ);
+  // the facet-patch preconditioner needs every cell on an interior facet
+  // (else a cell would receive no correction)
+  pc_on = prm.step1_precond == 1 && prm.idr_s == 0;
+  for (long e = 0; pc_on && e < nc; ++e)
+    pc_on = hm.cf_nb[e] >= 0 || hm.cf_nb[nc + e] >= 0 || hm.cf_nb[2 * nc + e] >= 0;
+  if (pc_on) {
+    kd.ph = dalloc<double>(nQ);
+    kd.sh = dalloc<double>(nQ);
+    pcD = dalloc<double>(nc * nu * nu);
+    pcB = dalloc<uint16_t>(pc_entries(k, nc));
+  }
   const long nc32 = (nc + 31) / 32 * 32;
   vk32 = prm.precision == HDG_MIXED;
   vk = vk32 ? (void*)dalloc<float>((long)ns * ns * nc32) : (void*)dalloc<double>((long)ns * ns * nc32);
@@ -897,23 +933,31 @@ void hdg_ctx::bicgstab_block(double adt) {
   KrylovBuf& B = kd;
   const long n = nQ;
   launch_copy(st, BS_STRIDE, bsc + (long)BS_STRIDE * kBicgBlock, bsc);
+  // right preconditioning: the operator acts on ph = B p and sh = B s, the
+  // residual stays that of the unpreconditioned system
+  const double* ph = pc_on ? B.ph : B.p;
+  const double* sh = pc_on ? B.sh : B.s;
   for (int b = 0; b < kBicgBlock; ++b) {
     double* sc = bsc + (long)BS_STRIDE * b;
+    if (pc_on) pc_apply(B.p, B.ph);
     {
       Timed tm(prof, KC_APPLY_OP);
-      launch_apply_soa(k, st, s1, 1, dm, dt, vk, vk32, vbeta, prm.alpha, adt, B.p, B.rh, B.v, part);
+      launch_apply_soa(k, st, s1, 1, dm, dt, vk, vk32, vbeta, prm.alpha, adt, ph, B.rh, B.v, part);
     }
     {
       Timed tm(prof, KC_VECTOR);
       launch_bicg_s(st, n, apply_soa_blocks(hm.nc, s1.block), part, sc, B.r, B.v, B.s);
     }
+    if (pc_on) pc_apply(B.s, B.sh);
     {
       Timed tm(prof, KC_APPLY_OP);
-      launch_apply_soa(k, st, s1, 2, dm, dt, vk, vk32, vbeta, prm.alpha, adt, B.s, B.rh, B.t, kpart);
+      launch_apply_soa(k, st, s1, pc_on ? 3 : 2, dm, dt, vk, vk32, vbeta, prm.alpha, adt, sh, B.rh, B.t, kpart,
+                       B.s);
     }
     {
       Timed tm(prof, KC_VECTOR);
-      launch_bicg_xrp(st, n, apply_soa_blocks(hm.nc, s1.block), kpart, sc, B.s, B.t, B.v, B.x, B.r, B.p, part);
+      launch_bicg_xrp(st, n, apply_soa_blocks(hm.nc, s1.block), kpart, sc, B.s, B.t, B.v, ph, sh, B.x, B.r, B.p,
+                      part);
     }
   }
   launch_finish(st, part, kVecBlocks, bsc + (long)BS_STRIDE * (kBicgBlock - 1) + BS_RR);
@@ -936,6 +980,7 @@ int hdg_ctx::bicgstab(double adt, const double* b_aos, double* x_aos) {
     launch_fill(st, nQ, 0.0, x_aos);
     return 0;
   }
+  pc_prepare(adt);
   const bool graphs = prm.use_graphs && !prof.on;
   hipGraphExec_t* exec = nullptr;
   if (graphs) {
@@ -1487,6 +1532,8 @@ static void estimate_footprint(const hdg::HostMesh& m, const hdg::RefTables& rt,
   // Step I data: cell matrices, upwind weights, residual-kernel advection data
   b += ns * ns * nc32 * (prm.precision == HDG_MIXED ? 4.0 : 8.0) + 8.0 * 3 * nqf * nc32 + 8.0 * nc * (2 * nqc + 3 * nqf);
   if (prm.idr_s > 0) b += 8.0 * (3.0 * prm.idr_s * nQ + kIdrMax + 8);
+  // Step I preconditioner: two direction vectors, the cell blocks and the patch inverses
+  if (prm.step1_precond == 1 && prm.idr_s == 0) b += 8.0 * (2 * nQ + nc * nu * nu) + 2.0 * (double)pc_entries(rt.k, (long)m.nc);
   // trace operators
   std::set<double> cs = {1.0, tab.bim[tab.s - 1] * dtv};
   for (int i = 1; i < tab.s; ++i) cs.insert(tab.Aim[i][i] * dtv);
@@ -1533,6 +1580,7 @@ void hdg_default_params(hdg_params* p) {
   p->use_graphs = 1;
   p->step1_block = 256;
   p->step1_xcd = 1;
+  p->step1_precond = 1;
 }
 
 int hdg_create(int64_t nv, const double* coords, int64_t nc, const int32_t* cells, const hdg_params* prm,
@@ -1554,7 +1602,7 @@ int hdg_create_periodic(int64_t nv, const double* coords, int64_t nc, const int3
       prm->pressure_update > 1 || prm->idr_s < 0 || prm->idr_s > kIdrMax ||
       prm->precision < 0 || prm->precision > 1 || prm->use_graphs < 0 || prm->use_graphs > 1 ||
       (prm->step1_block != 64 && prm->step1_block != 128 && prm->step1_block != 256) || prm->step1_xcd < 0 ||
-      prm->step1_xcd > 1) {
+      prm->step1_xcd > 1 || prm->step1_precond < 0 || prm->step1_precond > 1) {
     g_create_error = "invalid parameter";
     return HDG_ERR_INVALID_ARG;
   }
@@ -1930,7 +1978,10 @@ int hdg_trace_matvec(hdg_ctx* ctx, double c, const double* x, double* y) {
   ctx->err.clear();
   API_BEGIN
   TraceOp& op = ctx->trace_op(c);
-  launch_spmv(ctx->k, ctx->st, (int)ctx->hm.nF, op.vals, op.cols, x, y);
+  {
+    Timed tm(ctx->prof, KC_TRACE_SPMV);
+    launch_spmv(ctx->k, ctx->st, (int)ctx->hm.nF, op.vals, op.cols, x, y);
+  }
   KCHK();
   ctx->sync();
   API_END(ctx)
@@ -1994,6 +2045,22 @@ int hdg_tentative_velocity(hdg_ctx* ctx, double adt, const double* Qsv, const do
   API_END(ctx)
 }
 
+int hdg_step1_precond(hdg_ctx* ctx, double adt, const double* Qsv, const double* r, double* z) {
+  if (!ctx || !(adt > 0) || !Qsv || !r || !z) return HDG_ERR_INVALID_ARG;
+  if (!ctx->pc_on) { ctx->err = "the Step I preconditioner is off for this context"; return HDG_ERR_UNSUPPORTED; }
+  ctx->not_converged = false;
+  ctx->err.clear();
+  API_BEGIN
+  ctx->prepare_step1(Qsv);
+  ctx->pc_prepare(adt);
+  launch_to_soa(ctx->k, ctx->st, ctx->dm, 0, r, ctx->kd.b);
+  ctx->pc_apply(ctx->kd.b, ctx->kd.x);
+  launch_to_aos(ctx->k, ctx->st, ctx->dm, ctx->kd.x, z);
+  KCHK();
+  ctx->sync();
+  API_END(ctx)
+}
+
 int hdg_reconstruct_pressure(hdg_ctx* ctx, const double* Qv, double* pv, double* lv) {
   if (!ctx || !Qv || !pv || !lv) return HDG_ERR_INVALID_ARG;
   ctx->not_converged = false;
@@ -2042,6 +2109,8 @@ int hdg_get_info(const hdg_ctx* ctx, char* buf, size_t cap) {
                   ",\"pending_stage\":" + std::to_string(ctx->pend_stage) +
                   ",\"step1_block\":" + std::to_string(ctx->s1.block) +
                   ",\"step1_xcd\":" + std::to_string(ctx->s1.xcd) +
+                  ",\"step1_precond\":" + std::to_string(ctx->pc_on ? 1 : 0) +
+                  ",\"step1_precond_builds\":" + std::to_string(ctx->pc_builds) +
                   ",\"device_transient_bytes\":" + std::to_string(ctx->dev_transient) +
                   ",\"pcg_iterations_last\":" + last(ctx->pcg_iters, 16) +
                   ",\"velocity_iterations_last\":" + last(ctx->bicg_iters, 16) +

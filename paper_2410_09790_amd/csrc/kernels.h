@@ -100,9 +100,11 @@ struct Step1Launch {
 // Step I operator on structure-of-arrays vectors (2 threads per cell):
 // out = x - (adt/det) f_im(x), with partial sums (apply_soa_blocks(nc, block)
 // per set): dot 0 none; dot 1 w.out; dot 2 out.x, out.out, w.x, w.out
+// (dot 3: as dot 2 with the dots taken against sd instead of x: out.sd,
+// out.out, w.sd, w.out; sd is ignored otherwise)
 void launch_apply_soa(int k, hipStream_t st, Step1Launch ln, int dot, DMesh m, DTab t, const void* V, bool v32,
                       const double* beta, double alpha, double adt, const double* x, const double* w, double* out,
-                      double* part);
+                      double* part, const double* sd = nullptr);
 int apply_soa_blocks(long nc, int block);
 // BiCGStab pieces (slot sc of BS_STRIDE scalars):
 //   v = A p: launch_apply_soa dot 1 with rh (np partials in part)
@@ -113,8 +115,18 @@ int apply_soa_blocks(long nc, int block);
 void launch_bicg_s(hipStream_t st, long n, int np, const double* part, double* sc, const double* r, const double* v,
                    double* s);
 void launch_bicg_xrp(hipStream_t st, long n, int np, const double* part2, double* sc, const double* s,
-                     const double* tv, const double* v, double* x, double* r, double* p, double* part);
+                     const double* tv, const double* v, const double* ph, const double* sh, double* x, double* r,
+                     double* p, double* part);
 void launch_bicg_init(hipStream_t st, double* sc);  // zero a slot except BS_RHO
+// Step I preconditioner: additive Schwarz over facet patches (two cells per
+// interior facet) of the mass-scaled Step I operator.  launch_pc_build forms
+// the patch inverses for the Q* and adt of a stage (D: scratch of
+// nc * nu * nu doubles; Binv: pc_entries(k, nc) FP16 entries); launch_pc_apply
+// gives z = B r on structure-of-arrays vectors.
+void launch_pc_build(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, double alpha,
+                     double adt, double* D, void* Binv);
+void launch_pc_apply(int k, hipStream_t st, DMesh m, const void* Binv, const double* r, double* z);
+long pc_entries(int k, long nc);
 void launch_to_soa(int k, hipStream_t st, DMesh m, int inv_det, const double* x, double* y);
 void launch_to_aos(int k, hipStream_t st, DMesh m, const double* x, double* y);
 void launch_div(int k, hipStream_t st, DMesh m, DTab t, const double* F, double scale, double* out);

@@ -244,7 +244,9 @@ __device__ __forceinline__ void stage_fbu(const DTab& t, double* sFBu) {
 // out = x - (adt/det) f_im(., x; Q*): the mass-scaled Step I operator on
 // structure-of-arrays vectors (two threads per cell), with per-block
 // partial sums (nb = gridDim.x sets of partials at part + i*nb):
-//   DOT 0: none;  DOT 1: w.out;  DOT 2: out.x, out.out, w.x, w.out.
+//   DOT 0: none;  DOT 1: w.out;  DOT 2: out.x, out.out, w.x, w.out;
+//   DOT 3: out.sd, out.out, w.sd, w.out (sd: the unpreconditioned vector
+//   whose preconditioned image is x).
 // In BiCGStab, DOT 1 gives rh.v for v = A p and DOT 2 gives t.s, t.t, rh.s,
 // rh.t for t = A s.  BS threads per workgroup (64, 128 or 256); xcd = 1 deals
 // the cells to the XCDs in contiguous eighths (xcd_block), 0 keeps the
@@ -254,6 +256,7 @@ __global__ void __launch_bounds__(BS, kStep1Waves) k_apply_soa(DMesh m, DTab t, 
                                                                const double* __restrict__ beta, double alpha,
                                                                double adt, const double* __restrict__ x,
                                                                const double* __restrict__ w,
+                                                               const double* __restrict__ sd,
                                                                double* __restrict__ out,
                                                                double* __restrict__ part, int xcd) {
   using D = Dims<K>;
@@ -277,11 +280,12 @@ __global__ void __launch_bounds__(BS, kStep1Waves) k_apply_soa(DMesh m, DTab t, 
       const double o = xv[s] - sc * y[s];
       out[idx] = o;
       if (DOT == 1) d0 += w[idx] * o;
-      if (DOT == 2) {
+      if (DOT >= 2) {
         const double wv = w[idx];
-        d0 += o * xv[s];
+        const double sv = DOT == 3 ? sd[idx] : xv[s];
+        d0 += o * sv;
         d1 += o * o;
-        d2 += wv * xv[s];
+        d2 += wv * sv;
         d3 += wv * o;
       }
     }
@@ -290,7 +294,7 @@ __global__ void __launch_bounds__(BS, kStep1Waves) k_apply_soa(DMesh m, DTab t, 
     d0 = block_sum_n<BS>(d0);
     if (threadIdx.x == 0) part[blk] = d0;
   }
-  if (DOT == 2) {
+  if (DOT >= 2) {
     const int nb = gridDim.x;
     d1 = block_sum_n<BS>(d1);
     d2 = block_sum_n<BS>(d2);
@@ -351,6 +355,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_s(long n, int np, const double*
 __global__ void __launch_bounds__(kBlock) k_bicg_xrp(long n, int np, const double* __restrict__ part2,
                                                      double* __restrict__ sc, const double* __restrict__ S,
                                                      const double* __restrict__ Tv, const double* __restrict__ Vv,
+                                                     const double* __restrict__ PH, const double* __restrict__ SH,
                                                      double* __restrict__ X, double* __restrict__ R,
                                                      double* __restrict__ P, double* __restrict__ part) {
   // omega = t.s / t.t, rho_next = rh.s - omega rh.t (= rh.r_next),
@@ -370,9 +375,11 @@ __global__ void __launch_bounds__(kBlock) k_bicg_xrp(long n, int np, const doubl
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (long)gridDim.x * blockDim.x) {
     const double2 p = reinterpret_cast<const double2*>(P)[i], s = reinterpret_cast<const double2*>(S)[i];
     const double2 t = reinterpret_cast<const double2*>(Tv)[i], v = reinterpret_cast<const double2*>(Vv)[i];
+    // the iterate moves along the preconditioned directions (PH = P, SH = S without a preconditioner)
+    const double2 ph = reinterpret_cast<const double2*>(PH)[i], sh = reinterpret_cast<const double2*>(SH)[i];
     double2 x = reinterpret_cast<const double2*>(X)[i];
-    x.x += al * p.x + om * s.x;
-    x.y += al * p.y + om * s.y;
+    x.x += al * ph.x + om * sh.x;
+    x.y += al * ph.y + om * sh.y;
     reinterpret_cast<double2*>(X)[i] = x;
     const double2 r = make_double2(s.x - om * t.x, s.y - om * t.y);
     reinterpret_cast<double2*>(R)[i] = r;
@@ -416,6 +423,306 @@ __global__ void k_to_aos(DMesh m, const double* __restrict__ x, double* __restri
   y[tid] = x[i * m.nc + e];
 }
 
+// ======================================================= Step I preconditioner
+// Additive Schwarz over facet patches, B r = sum_F R_F^T A_F^{-1} R_F r: for
+// every interior facet F with cells K+ and K-, A_F is the block of the
+// mass-scaled Step I operator on the 2 NU unknowns of the two cells (both
+// cell blocks and their coupling through F; couplings through the other
+// facets are left out).  The interior-penalty term alpha h^-1 <[Q.n][w.n]> of
+// eq. (f_impl) carries the factor adt/h^2 against the mass term, and it
+// vanishes exactly on fields whose normal component is continuous.  Those
+// fields are spanned by functions that live on one cell or on the two cells
+// of one facet, so every patch holds its share of them and the
+// preconditioned operator stays well conditioned however strong the penalty
+// is; single-cell blocks (block Jacobi) hold no such function across a
+// facet and lose that property.
+//
+// Storage: per (cell e, local facet f) the NU rows of A_F^{-1} that belong
+// to e, with the columns of e first and those of the neighbour after them,
+// as quads of adjacent columns in tiles of 32 cells (quad jq of row i at
+// ((((e/32)*3 + f)*NU + i)*NS + jq)*32 + e%32, NS = 2 NU / 4 quads per
+// row), in FP16: one 8-byte load per lane brings four entries.  Slots of
+// wall facets are never read.  Precision: the entries are bounded (the
+// symmetric part of A_F is at least the identity up to the divergence of Q*,
+// so |A_F^{-1}| <~ 1), and FP16 keeps them to 5e-4 relative; a preconditioner
+// that accurate converges like the exact one, and the solution does not
+// depend on it.  The conversion saturates, so no entry can become infinite.
+using pc_t = _Float16;
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+template <int K>
+struct PcLayout {
+  static constexpr int NU = Dims<K>::NU, NQ = Dims<K>::NS;  // 2 NU = 4 NQ
+  __device__ static long quad(long e, int f, int i, int jq) {
+    return ((((e >> 5) * 3 + f) * (long)NU + i) * NQ + jq) * 32 + (e & 31);
+  }
+};
+__device__ __forceinline__ pc_t pc_store(double v) {
+  const double lim = 65504.0;  // largest finite FP16
+  return (pc_t)(v > lim ? lim : (v < -lim ? -lim : v));
+}
+
+// Own-cell block of the mass-scaled Step I operator, row i = (c, s) of cell
+// e: D[e][i][j] = delta_ij - (adt/det) (volume term + the own-side facet
+// terms of all three facets), FP64, row-major per cell.  The same terms, in
+// the same form, as step1_core with the neighbour's values set to zero.  One
+// thread per (cell, row).
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_pc_cellblock(DMesh m, DTab t, const double* __restrict__ Qs,
+                                                         double delta_up, double alpha, double adt,
+                                                         double* __restrict__ D) {
+  using Dm = Dims<K>;
+  constexpr int NS = Dm::NS, NU = Dm::NU, NQC = Dm::NQC, NQF = Dm::NQF;
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nc = m.nc;
+  if (tid >= nc * NU) return;
+  const int e = (int)(tid % nc), i = (int)(tid / nc);
+  const int c = i / NS, s = i % NS;
+  // vc: the terms acting on component c alone (volume, upwind), indexed by
+  // s'; pen: the normal-jump penalty, indexed by (c', s')
+  double q[NU], vc[NS], pen[NU];
+#pragma unroll
+  for (int a = 0; a < NU; ++a) { q[a] = Qs[(long)e * NU + a]; pen[a] = 0.0; }
+#pragma unroll
+  for (int a = 0; a < NS; ++a) vc[a] = 0.0;
+  const double det = m.geo[D_DET * nc + e];
+  const double i00 = det * m.geo[D_IJ00 * nc + e], i01 = det * m.geo[D_IJ01 * nc + e];
+  const double i10 = det * m.geo[D_IJ10 * nc + e], i11 = det * m.geo[D_IJ11 * nc + e];
+  // volume: -(phi_s, Q*.grad phi_s') det J
+  for (int qq = 0; qq < NQC; ++qq) {
+    double qx = 0.0, qy = 0.0;
+#pragma unroll
+    for (int a = 0; a < NS; ++a) { qx += t.Bu[qq * NS + a] * q[a]; qy += t.Bu[qq * NS + a] * q[NS + a]; }
+    const double w = -t.cw[qq] * t.Bu[qq * NS + s];
+    const double a0 = w * (i00 * qx + i01 * qy), a1 = w * (i10 * qx + i11 * qy);
+#pragma unroll
+    for (int a = 0; a < NS; ++a) vc[a] += a0 * t.Gux[qq * NS + a] + a1 * t.Guy[qq * NS + a];
+  }
+  // own side of each facet: phi_s phi_s' (beta delta_cc' - alpha w_q n_c n_c')
+#pragma unroll 1
+  for (int f = 0; f < 3; ++f) {
+    const bool inner = m.cf_nbx[f * nc + e] >= 0;
+    const double nx = m.geo[(D_NX0 + 2 * f) * nc + e], ny = m.geo[(D_NY0 + 2 * f) * nc + e];
+    const double h = m.geo[(D_H0 + f) * nc + e];
+    const double ncomp = c ? ny : nx;
+    for (int qq = 0; qq < NQF; ++qq) {
+      double vx = 0.0, vy = 0.0;
+#pragma unroll
+      for (int a = 0; a < NS; ++a) {
+        const double b = t.FBu[(f * NQF + qq) * NS + a];
+        vx += b * q[a];
+        vy += b * q[NS + a];
+      }
+      const double qn = vx * nx + vy * ny;
+      const double beta = inner ? t.fw[qq] * h * (0.5 * qn - delta_up * fabs(qn)) : 0.0;
+      const double ps = t.FBu[(f * NQF + qq) * NS + s];
+      const double pw = alpha * t.fw[qq] * ncomp;
+#pragma unroll
+      for (int a = 0; a < NS; ++a) {
+        const double b = ps * t.FBu[(f * NQF + qq) * NS + a];
+        vc[a] += b * beta;
+        pen[a] -= b * pw * nx;
+        pen[NS + a] -= b * pw * ny;
+      }
+    }
+  }
+  const double sc = adt / det;
+#pragma unroll
+  for (int j = 0; j < NU; ++j) {
+    const double own = j < NS ? (c == 0 ? vc[j % NS] : 0.0) : (c == 1 ? vc[j % NS] : 0.0);
+    D[((long)e * NU + i) * NU + j] = (i == j ? 1.0 : 0.0) - sc * (own + pen[j]);
+  }
+}
+
+// Threads of the patch kernel: NC column slots (64 per wave) times NH row
+// parts.  At k >= 3 a column of 2 NU rows would not fit in registers, so it
+// is split between two waves, one per cell of the patch.
+template <int K>
+struct PcPatchShape {
+  static constexpr int N = 2 * Dims<K>::NU;
+  static constexpr int NH = N > 40 ? 2 : 1;
+  static constexpr int NC = (N + 63) / 64 * 64;
+  static constexpr int HN = N / NH;  // rows per thread
+  static constexpr int NT = NC * NH;
+};
+
+// One workgroup per facet: assemble A_F of an interior facet column by column
+// (thread (j, h) holds rows [h HN, (h+1) HN) of column j in registers), invert
+// it by Gauss-Jordan elimination without pivoting (the symmetric part of A_F
+// is positive definite: mass plus the dissipative penalty and upwind terms,
+// the advective part being skew up to the own-side flux
+// (1/2 - delta_up)|Q*.n| <= 0 on the cut facets), and store each cell's rows
+// of the inverse as described above.  Wall facets return at once.
+template <int K>
+__global__ void __launch_bounds__(PcPatchShape<K>::NT) k_pc_patch(DMesh m, DTab t, const double* __restrict__ Qs,
+                                                                  double delta_up, double alpha, double adt,
+                                                                  const double* __restrict__ D,
+                                                                  pc_t* __restrict__ Binv) {
+  using Dm = Dims<K>;
+  using Sh = PcPatchShape<K>;
+  constexpr int NS = Dm::NS, NU = Dm::NU, NQF = Dm::NQF, N = Sh::N, NH = Sh::NH, HN = Sh::HN, NC = Sh::NC;
+  const int F = blockIdx.x;
+  const long nc = m.nc;
+  const int Km = m.fc_cell[m.nF + F];
+  if (Km < 0) return;  // wall facet: no patch (uniform over the workgroup)
+  const int Kp = m.fc_cell[F];
+  const int fp = m.fc_f[F], fm = m.fc_f[m.nF + F];
+  const int rev = (m.cf_nbx[fp * nc + Kp] & 1);
+  // side 0 = K+, side 1 = K- (selects, not arrays: an array indexed by a
+  // runtime side would live in scratch memory)
+  auto cell = [&](int side) { return side ? Km : Kp; };
+  auto lf = [&](int side) { return side ? fm : fp; };
+  __shared__ double sbeta[2][NQF];
+  __shared__ double scol[2][N], srow[2][NC];
+  const int j = threadIdx.x % NC, h = threadIdx.x / NC;
+  // upwind weights of both sides at their own facet points (side 0 = K+)
+  if (threadIdx.x < 2 * NQF) {
+    const int side = threadIdx.x / NQF, qq = threadIdx.x % NQF;
+    const int e = cell(side), f = lf(side);
+    const double nx = m.geo[(D_NX0 + 2 * f) * nc + e], ny = m.geo[(D_NY0 + 2 * f) * nc + e];
+    const double hf = m.geo[(D_H0 + f) * nc + e];
+    double vx = 0.0, vy = 0.0;
+    for (int a = 0; a < NS; ++a) {
+      const double b = t.FBu[(f * NQF + qq) * NS + a];
+      vx += b * Qs[(long)e * NU + a];
+      vy += b * Qs[(long)e * NU + NS + a];
+    }
+    const double qn = vx * nx + vy * ny;
+    sbeta[side][qq] = t.fw[qq] * hf * (0.5 * qn - delta_up * fabs(qn));
+  }
+  __syncthreads();
+  const int jc = j < N ? j : 0;          // idle lanes build a copy of column 0 and discard it
+  const int sj = jc / NU, jj = jc % NU;  // column side and unknown (c', s') on that side
+  const int cj = jj / NS, s2 = jj % NS;
+  // row r of the patch on side rs: the cell block when rs == sj, else the
+  // coupling of the row cell (side rs) to the column cell through F
+  auto entry = [&](int rs, int rr) -> double {
+    if (rs == sj) return D[((long)cell(sj) * NU + rr) * NU + jj];
+    const int eo = cell(rs), fo = lf(rs), fcol = lf(sj);
+    const double nx = m.geo[(D_NX0 + 2 * fo) * nc + eo], ny = m.geo[(D_NY0 + 2 * fo) * nc + eo];
+    const int cr = rr / NS, sr = rr % NS;
+    const double ncr = cr ? ny : nx, ncj = cj ? ny : nx;
+    double v = 0.0;
+    for (int qq = 0; qq < NQF; ++qq) {
+      const double coef = (cr == cj ? sbeta[rs][qq] : 0.0) - alpha * t.fw[qq] * ncr * ncj;
+      v += t.FBu[(fo * NQF + qq) * NS + sr] * t.FBu[(fcol * NQF + (rev ? NQF - 1 - qq : qq)) * NS + s2] * coef;
+    }
+    return adt / m.geo[D_DET * nc + eo] * v;
+  };
+  // the block is assembled in LDS (a loop that is not unrolled, so the
+  // assembly's table loads do not crowd the registers), then each thread
+  // takes its part of a column into registers
+  __shared__ double sA[N][N + 1];
+  if (j < N) {
+#pragma unroll 1
+    for (int r = 0; r < HN; ++r) {
+      const int gr = h * HN + r;  // patch row (h is uniform per wave)
+      sA[gr][j] = entry(gr / NU, gr % NU);
+    }
+  }
+  __syncthreads();
+  double col[HN];
+#pragma unroll
+  for (int r = 0; r < HN; ++r) col[r] = sA[h * HN + r][jc];
+  // in-place Gauss-Jordan inversion; the pivot column and the pivot row go
+  // through LDS (two buffers each, so the next pivot's writes need no
+  // second barrier)
+  // (the pivot loop is not unrolled: the pivot's row is picked out of the
+  // registers by selects, never by a runtime index)
+#pragma unroll 1
+  for (int p = 0; p < N; ++p) {
+    double* cp = scol[p & 1];
+    double* rp = srow[p & 1];
+    const int hp = p / HN, lp = p % HN;
+    if (j == p) {
+#pragma unroll
+      for (int r = 0; r < HN; ++r) cp[h * HN + r] = col[r];
+    }
+    if (h == hp) {
+      double v = 0.0;
+#pragma unroll
+      for (int r = 0; r < HN; ++r) v = r == lp ? col[r] : v;
+      rp[j] = v;
+    }
+    __syncthreads();
+    const double d = 1.0 / cp[p];
+    if (j == p) {
+#pragma unroll
+      for (int r = 0; r < HN; ++r) col[r] = (h == hp && r == lp) ? d : -cp[h * HN + r] * d;
+    } else {
+      const double a = rp[j] * d;
+#pragma unroll
+      for (int r = 0; r < HN; ++r) col[r] = (h == hp && r == lp) ? a : col[r] - cp[h * HN + r] * a;
+    }
+  }
+  if (j >= N) return;
+  // rows of column j of the inverse: rows of K+ keep the column order (own,
+  // then neighbour); rows of K- see K- as own and K+ as neighbour
+#pragma unroll
+  for (int r = 0; r < HN; ++r) {
+    const int gr = h * HN + r, side = gr / NU, rr = gr % NU;
+    const int jb = side == 0 ? j : (j >= NU ? j - NU : j + NU);
+    Binv[4 * PcLayout<K>::quad(cell(side), lf(side), rr, jb >> 2) + (jb & 3)] = pc_store(col[r]);
+  }
+}
+
+// z = B r on structure-of-arrays vectors: thread (cell e, rows i in group g)
+// sums over the cell's interior facets the rows of A_F^{-1} applied to
+// (r_e, r_neighbour); no scatter, so no atomics, and a fixed order.
+template <int K>
+struct PcApplyShape {
+  static constexpr int NU = Dims<K>::NU;
+  static constexpr int G = K == 1 ? 2 : (K == 2 ? 4 : 6);  // row groups per cell
+  static constexpr int RG = NU / G;
+  static_assert(RG * G == NU, "rows split evenly");
+};
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_pc_apply(DMesh m, const pc_t* __restrict__ Binv,
+                                                     const double* __restrict__ r, double* __restrict__ z) {
+  using Sh = PcApplyShape<K>;
+  constexpr int NU = Dims<K>::NU, NQ = PcLayout<K>::NQ, G = Sh::G, RG = Sh::RG;
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nc = m.nc;
+  const long tile = tid / (G * 32);
+  const int rem = (int)(tid % (G * 32));
+  const int g = rem >> 5;
+  const long e = tile * 32 + (rem & 31);
+  if (e >= nc) return;
+  double acc[RG];
+#pragma unroll
+  for (int a = 0; a < RG; ++a) acc[a] = 0.0;
+  double ro[NU];
+#pragma unroll
+  for (int a = 0; a < NU; ++a) ro[a] = r[(long)a * nc + e];
+  const f16x4* B4 = reinterpret_cast<const f16x4*>(Binv);
+#pragma unroll 1
+  for (int f = 0; f < 3; ++f) {
+    const int nbx = m.cf_nbx[f * nc + e];
+    if (nbx < 0) continue;
+    const long en = nbx >> 3;
+    double rn[NU];
+#pragma unroll
+    for (int a = 0; a < NU; ++a) rn[a] = r[(long)a * nc + en];
+#pragma unroll
+    for (int a = 0; a < RG; ++a) {
+      const int i = g * RG + a;
+      double v = 0.0;
+#pragma unroll
+      for (int jq = 0; jq < NQ; ++jq) {
+        const f16x4 b = __builtin_nontemporal_load(&B4[PcLayout<K>::quad(e, f, i, jq)]);
+        const double bv[4] = {(double)b.x, (double)b.y, (double)b.z, (double)b.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int jx = 4 * jq + u;
+          v += bv[u] * (jx < NU ? ro[jx] : rn[jx - NU]);
+        }
+      }
+      acc[a] += v;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < RG; ++a) z[(long)(g * RG + a) * nc + e] = acc[a];
+}
+
 // ============================================================== launchers
 void launch_step1_matrix(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, void* V, bool v32,
                          double* beta) {
@@ -429,32 +736,36 @@ void launch_step1_matrix(int k, hipStream_t st, DMesh m, DTab t, const double* Q
 }
 template <int DOT, typename TV, int BS>
 static void apply_soa_bs(int k, hipStream_t st, DMesh m, DTab t, const TV* V, const double* beta, double alpha,
-                         double adt, const double* x, const double* w, double* out, double* part, int xcd) {
+                         double adt, const double* x, const double* w, const double* sd, double* out, double* part,
+                         int xcd) {
   const int nb = apply_soa_blocks(m.nc, BS);
-  HDG_DISPATCH(k, (k_apply_soa<KK, DOT, TV, BS><<<nb, BS, 0, st>>>(m, t, V, beta, alpha, adt, x, w, out, part, xcd)));
+  HDG_DISPATCH(k, (k_apply_soa<KK, DOT, TV, BS><<<nb, BS, 0, st>>>(m, t, V, beta, alpha, adt, x, w, sd, out, part,
+                                                                   xcd)));
 }
 template <int DOT, typename TV>
 static void apply_soa_d(int k, hipStream_t st, Step1Launch ln, DMesh m, DTab t, const TV* V, const double* beta,
-                        double alpha, double adt, const double* x, const double* w, double* out, double* part) {
+                        double alpha, double adt, const double* x, const double* w, const double* sd, double* out,
+                        double* part) {
   switch (ln.block) {
-    case 64: apply_soa_bs<DOT, TV, 64>(k, st, m, t, V, beta, alpha, adt, x, w, out, part, ln.xcd); break;
-    case 128: apply_soa_bs<DOT, TV, 128>(k, st, m, t, V, beta, alpha, adt, x, w, out, part, ln.xcd); break;
-    default: apply_soa_bs<DOT, TV, 256>(k, st, m, t, V, beta, alpha, adt, x, w, out, part, ln.xcd); break;
+    case 64: apply_soa_bs<DOT, TV, 64>(k, st, m, t, V, beta, alpha, adt, x, w, sd, out, part, ln.xcd); break;
+    case 128: apply_soa_bs<DOT, TV, 128>(k, st, m, t, V, beta, alpha, adt, x, w, sd, out, part, ln.xcd); break;
+    default: apply_soa_bs<DOT, TV, 256>(k, st, m, t, V, beta, alpha, adt, x, w, sd, out, part, ln.xcd); break;
   }
 }
 template <typename TV>
 static void apply_soa_t(int k, hipStream_t st, Step1Launch ln, int dot, DMesh m, DTab t, const TV* V,
-                        const double* beta, double alpha, double adt, const double* x, const double* w, double* out,
-                        double* part) {
-  if (dot == 0) apply_soa_d<0, TV>(k, st, ln, m, t, V, beta, alpha, adt, x, w, out, part);
-  else if (dot == 1) apply_soa_d<1, TV>(k, st, ln, m, t, V, beta, alpha, adt, x, w, out, part);
-  else apply_soa_d<2, TV>(k, st, ln, m, t, V, beta, alpha, adt, x, w, out, part);
+                        const double* beta, double alpha, double adt, const double* x, const double* w,
+                        const double* sd, double* out, double* part) {
+  if (dot == 0) apply_soa_d<0, TV>(k, st, ln, m, t, V, beta, alpha, adt, x, w, sd, out, part);
+  else if (dot == 1) apply_soa_d<1, TV>(k, st, ln, m, t, V, beta, alpha, adt, x, w, sd, out, part);
+  else if (dot == 2) apply_soa_d<2, TV>(k, st, ln, m, t, V, beta, alpha, adt, x, w, sd, out, part);
+  else apply_soa_d<3, TV>(k, st, ln, m, t, V, beta, alpha, adt, x, w, sd, out, part);
 }
 void launch_apply_soa(int k, hipStream_t st, Step1Launch ln, int dot, DMesh m, DTab t, const void* V, bool v32,
                       const double* beta, double alpha, double adt, const double* x, const double* w, double* out,
-                      double* part) {
-  if (v32) apply_soa_t(k, st, ln, dot, m, t, (const float*)V, beta, alpha, adt, x, w, out, part);
-  else apply_soa_t(k, st, ln, dot, m, t, (const double*)V, beta, alpha, adt, x, w, out, part);
+                      double* part, const double* sd) {
+  if (v32) apply_soa_t(k, st, ln, dot, m, t, (const float*)V, beta, alpha, adt, x, w, sd, out, part);
+  else apply_soa_t(k, st, ln, dot, m, t, (const double*)V, beta, alpha, adt, x, w, sd, out, part);
 }
 int apply_soa_blocks(long nc, int block) { return (int)((2L * nc + block - 1) / block); }
 void launch_bicg_s(hipStream_t st, long n, int np, const double* part, double* sc, const double* r, const double* v,
@@ -462,8 +773,9 @@ void launch_bicg_s(hipStream_t st, long n, int np, const double* part, double* s
   k_bicg_s<<<kVecBlocks, kBlock, 0, st>>>(n, np, part, sc, r, v, s);
 }
 void launch_bicg_xrp(hipStream_t st, long n, int np, const double* part2, double* sc, const double* s,
-                     const double* tv, const double* v, double* x, double* r, double* p, double* part) {
-  k_bicg_xrp<<<kVecBlocks, kBlock, 0, st>>>(n, np, part2, sc, s, tv, v, x, r, p, part);
+                     const double* tv, const double* v, const double* ph, const double* sh, double* x, double* r,
+                     double* p, double* part) {
+  k_bicg_xrp<<<kVecBlocks, kBlock, 0, st>>>(n, np, part2, sc, s, tv, v, ph, sh, x, r, p, part);
 }
 void launch_bicg_init(hipStream_t st, double* sc) { k_bicg_init<<<1, 64, 0, st>>>(sc); }
 void launch_to_soa(int k, hipStream_t st, DMesh m, int inv_det, const double* x, double* y) {
@@ -471,5 +783,24 @@ void launch_to_soa(int k, hipStream_t st, DMesh m, int inv_det, const double* x,
 }
 void launch_to_aos(int k, hipStream_t st, DMesh m, const double* x, double* y) {
   HDG_DISPATCH(k, (k_to_aos<KK><<<nblocks((long)m.nc * Dims<KK>::NU), kBlock, 0, st>>>(m, x, y)));
+}
+// Facet-patch preconditioner of the Step I operator for the Q* and adt of a
+// stage: cell blocks (D, FP64 scratch of nc*NU*NU doubles) then the patch
+// inverses (Binv, pc_entries(k, nc) = ceil(nc/32)*32*3*NU*2NU entries of FP16).
+void launch_pc_build(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, double alpha,
+                     double adt, double* D, void* Binv) {
+  HDG_DISPATCH(k, (k_pc_cellblock<KK><<<nblocks((long)m.nc * Dims<KK>::NU), kBlock, 0, st>>>(m, t, Qs, delta_up,
+                                                                                              alpha, adt, D)));
+  HDG_DISPATCH(k, (k_pc_patch<KK><<<m.nF, PcPatchShape<KK>::NT, 0, st>>>(m, t, Qs, delta_up, alpha, adt, D,
+                                                                         (pc_t*)Binv)));
+}
+void launch_pc_apply(int k, hipStream_t st, DMesh m, const void* Binv, const double* r, double* z) {
+  HDG_DISPATCH(k, (k_pc_apply<KK><<<nblocks((long)(m.nc + 31) / 32 * 32 * PcApplyShape<KK>::G), kBlock, 0, st>>>(
+                      m, (const pc_t*)Binv, r, z)));
+}
+// per (cell, facet) slot: NU rows of 2 NU entries (own cell, then neighbour)
+long pc_entries(int k, long nc) {
+  const long nu = (long)(k + 2) * (k + 3);
+  return (nc + 31) / 32 * 32 * 3 * nu * 2 * nu;
 }
 }  // namespace hdg

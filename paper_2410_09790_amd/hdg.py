@@ -34,7 +34,7 @@ EXPORTS = [
     "hdg_cg_project", "hdg_tracer_rate", "hdg_last_error", "hdg_sizes", "hdg_cell_points",
     "hdg_facet_points", "hdg_set_forcing", "hdg_set_time", "hdg_get_time", "hdg_set_velocity_from_points", "hdg_set_state", "hdg_get_state", "hdg_advance", "hdg_solve_trace",
     "hdg_trace_matvec", "hdg_bdm_project", "hdg_weak_divergence", "hdg_momentum_residual",
-    "hdg_tentative_velocity", "hdg_reconstruct_pressure", "hdg_profile", "hdg_get_info",
+    "hdg_tentative_velocity", "hdg_step1_precond", "hdg_reconstruct_pressure", "hdg_profile", "hdg_get_info",
 ]
 
 
@@ -57,6 +57,7 @@ class Params(ctypes.Structure):
         ("use_graphs", ctypes.c_int),
         ("step1_block", ctypes.c_int),
         ("step1_xcd", ctypes.c_int),
+        ("step1_precond", ctypes.c_int),
     ]
 
 
@@ -114,6 +115,7 @@ def load_library(path: str = LIB_PATH):
         "hdg_weak_divergence": (I, [P, P, P]),
         "hdg_momentum_residual": (I, [P, D, P, P, P, P, P, P]),
         "hdg_tentative_velocity": (I, [P, D, P, P, P]),
+        "hdg_step1_precond": (I, [P, D, P, P, P]),
         "hdg_reconstruct_pressure": (I, [P, P, P, P]),
         "hdg_profile": (I, [P, I]),
         "hdg_get_info": (I, [P, ctypes.c_char_p, ctypes.c_size_t]),
@@ -352,6 +354,12 @@ class Context:
     def tentative_velocity(self, adt, Qstar, rhs):
         out = self._empty(self.nQ)
         self._check(self._lib.hdg_tentative_velocity(self._h, float(adt), _ptr(Qstar), _ptr(rhs), _ptr(out)))
+        return out
+
+    def step1_precond(self, adt, Qstar, r):
+        """z = B r, the facet-patch preconditioner of the mass-scaled Step I operator."""
+        out = self._empty(self.nQ)
+        self._check(self._lib.hdg_step1_precond(self._h, float(adt), _ptr(Qstar), _ptr(r), _ptr(out)))
         return out
 
     def reconstruct_pressure(self, Q):

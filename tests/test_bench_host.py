@@ -34,18 +34,40 @@ def test_algorithmic_bytes_of_the_operators():
 
 def test_recorded_traffic_is_tied_to_the_kernel_source(monkeypatch):
     import bench
-    with open(bench.KERNELS_SRC, "rb") as fh:
-        sha = hashlib.sha256(fh.read()).hexdigest()[:16]
     rec = dict(bench.MEASURED_TRAFFIC["apply_step1_operator"])
-    monkeypatch.setitem(bench.MEASURED_TRAFFIC, "apply_step1_operator", {**rec, "kernels_sha256": sha})
+    sha = bench.kernel_sha(rec)
+    monkeypatch.setitem(bench.MEASURED_TRAFFIC, "apply_step1_operator", {**rec, "sha256": sha})
     assert bench.measured_traffic("apply_step1_operator") == rec["bytes_per_launch"]
-    monkeypatch.setitem(bench.MEASURED_TRAFFIC, "apply_step1_operator", {**rec, "kernels_sha256": "0" * 16})
+    monkeypatch.setitem(bench.MEASURED_TRAFFIC, "apply_step1_operator", {**rec, "sha256": "0" * 16})
     assert bench.measured_traffic("apply_step1_operator") is None
-    assert bench.measured_traffic("trace_spmv") is None
+    assert bench.measured_traffic("no_such_kernel") is None
 
 
 def test_recorded_traffic_matches_the_committed_kernels():
-    """The committed record was taken on the committed kernel source, so the
+    """Every committed record was taken on the committed kernel source, so the
     bench line carries it (a kernel change must come with fresh counters)."""
     import bench
-    assert bench.measured_traffic("apply_step1_operator") is not None
+    for name in bench.MEASURED_TRAFFIC:
+        assert bench.measured_traffic(name) is not None, name
+
+
+def test_kernel_source_extraction():
+    """The hash covers exactly the named functions: their text starts at the
+    template line and ends with the closing brace of the body."""
+    import bench
+    with open(bench.os.path.join(bench.CSRC, "kernels.hip")) as fh:
+        text = fh.read()
+    src = bench.function_source(text, "k_spmv")
+    assert src.startswith("template <int K>\n__global__") and src.rstrip().endswith("}")
+    assert src.count("{") == src.count("}")
+    assert "k_jacobi" not in src
+
+
+def test_preconditioner_bytes():
+    import bench
+    # 256 x 256, k = 3: 196096 interior facets, each a 60 x 60 FP16 inverse
+    nbytes, _ = bench.algorithmic_cost("step1_precond_apply", 3, 131072, 197120, 196096)
+    assert nbytes == 196096 * 2 * 30 * 60 * 2 + 131072 * (2 * 8 * 30 + 12)
+    # the operator on the method's own data: 4 vectors of 30 doubles (input,
+    # output, inner-product vector, Q*), 7 geometry doubles, 9 int32 entries
+    assert bench.method_bytes("apply_step1_operator", 3, 131072) == 131072 * (8 * (120 + 7) + 36)
