@@ -95,6 +95,18 @@ typedef enum { HDG_PRESSURE_RECONSTRUCT = 0, HDG_PRESSURE_FIRST_ORDER = 1 } hdg_
  * arithmetic is not offered: it makes BiCGStab stall or diverge on this
  * operator. */
 typedef enum { HDG_FP64 = 0, HDG_MIXED = 1 } hdg_precision;
+/* Step II of Algorithm 2.  PRINTED (reading A): the mixed solve of eq.
+ * (pressure_increment) with c = 1, psi-data -Div(psi, Qbar)/(a_ii dt) and
+ * the update of Step III; its fixed point satisfies the stage momentum
+ * equation but not the constraint Gamma(Q_i, p_i, lam_i) = 0 of eq.
+ * (imex_implicit_solve_constraint), which only the final projection of
+ * Algorithm 1 enforces.  STAGE_SOLVE (reading B): the mixed solve of the
+ * stage operator itself (c = a_ii dt) with w-data (Qbar, w) and constraint
+ * data -Gamma(psi, mu, Q, p, lam) of the iterate, whose solution is added to
+ * the iterate: a fixed point solves eqs. (imex_implicit_solve) and
+ * (imex_implicit_solve_constraint) exactly, and the iteration converges to
+ * that monolithic stage solution as n_R grows. */
+typedef enum { HDG_STEP2_PRINTED = 0, HDG_STEP2_STAGE_SOLVE = 1 } hdg_step2_reading;
 
 typedef struct hdg_ctx hdg_ctx;
 typedef struct hdg_batch hdg_batch;
@@ -110,16 +122,20 @@ typedef struct {
   int n_richardson;      /* n_R of Algorithm 2 */
   int trace_solver;      /* hdg_trace_solver */
   double rtol_trace;     /* PCG: ||g - S lam||_2 <= rtol ||g||_2 (the residual's component along
-                            the constant trace left out); a solve whose preconditioned
-                            residual r.z stalls (< 1 % gain per four iterations for a
-                            quarter of the iterations spent, at least 12) with |r|
-                            within 1e4 rtol
-                            (the round-off floor of an ill-conditioned S) also ends the solve,
-                            counted as pcg_floor_stops in hdg_get_info; so do, in the
-                            multigrid path, |r| setting no new 2 % low over the same window
-                            within that band, and reaching max_it_trace with |r| within it
-                            (else NOT_CONVERGED) */
-  double rtol_velocity;  /* Step I: same criterion on the mass-scaled system */
+                            the constant trace left out).  Round-off band: min(1e4 rtol, 1e-9)
+                            relative.  A solve whose preconditioned residual r.z stalls (< 1 %
+                            gain per four iterations for a quarter of the iterations spent, at
+                            least 12) with the current |r| inside the band (the round-off floor
+                            of an ill-conditioned S) also ends, counted as pcg_floor_stops in
+                            hdg_get_info; so does, in the multigrid path, |r| setting no new 2 %
+                            low over the same window inside the band.  The true residual g - S lam
+                            of such a stop is recomputed (pcg_floor_true_residual_max) and must
+                            lie in the band, else NOT_CONVERGED.  At max_it_trace: NOT_CONVERGED
+                            unless the true residual is within min(1e2 rtol, band). */
+  double rtol_velocity;  /* Step I: same criterion on the mass-scaled system; when BiCGStab's
+                            recursive residual reaches it, the true residual is recomputed and
+                            the solve continues from it unless it is within 10 rtol
+                            (velocity_true_residual_max, velocity_true_residual_restarts) */
   int max_it_trace;
   int max_it_velocity;
   int pressure_update;   /* hdg_pressure_update */
@@ -145,6 +161,7 @@ typedef struct {
                             vanishes, so the iteration count does not grow with that term's
                             weight adt/h^2 as it does for cell blocks.  Device memory: 8 nu^2 +
                             12 nu^2 bytes per cell (nu = (k+2)(k+3)). */
+  int step2_reading;     /* hdg_step2_reading */
 } hdg_params;
 
 /* Fill p with the defaults: k=1, tau=alpha=delta_up=1, ARS(2,2,2), n_R=3,
@@ -331,6 +348,13 @@ int hdg_tentative_velocity(hdg_ctx* ctx, double adt, const double* Qstar, const 
  * of Q.  UNSUPPORTED when the context has the preconditioner off (also on a
  * mesh with a cell that touches no interior facet). */
 int hdg_step1_precond(hdg_ctx* ctx, double adt, const double* Qstar, const double* r, double* z);
+
+/* The constraint residual Gamma(psi, mu, Q, p, lam) of Section
+ * "Hybridisation" (the second line of the hybridised system) as dual
+ * vectors: Fpsi in the layout of p, Fmu in the layout of lam.  p or lam may
+ * be NULL (zero). */
+int hdg_constraint_residual(hdg_ctx* ctx, const double* Q, const double* p, const double* lam, double* Fpsi,
+                            double* Fmu);
 
 /* Pressure reconstruction (Section "Pressure reconstruction"): the mixed
  * problem with psi-data Div(psi, f_p), f_p = -f + (Q.grad_h)Q, and, with a

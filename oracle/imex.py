@@ -18,7 +18,15 @@
 * ``IMEXHDG.richardson``: Algorithm 2 (Steps I-III), with the weak divergence
   as the right-hand side of the psi-equation of Step II (the printed Step II
   puts it on the w-line with swapped test functions; the mixed-Poisson reading
-  delta Q + grad p = 0, div delta Q = b fixes it to the psi-equation).
+  delta Q + grad p = 0, div delta Q = b fixes it to the psi-equation).  This
+  is reading A of Step II.  Reading B (``step2_reading="B"``) replaces Step II
+  and Step III by the mixed solve of the stage's own operator H_{a_ii dt}
+  with w-data (Qbar, w) and constraint data -Gamma(psi, mu, Q, p, lambda) of
+  the current iterate, then adds its solution (U, dp, dlambda) to the iterate:
+  a fixed point has U = 0, so Qbar = 0, delta r = 0 and Gamma = 0, which are
+  eqs. (imex_implicit_solve) and (imex_implicit_solve_constraint); the printed
+  Step II uses H_1 and no constraint residual, so its fixed point is only
+  close to the stage solution.
 * ``IMEXHDG.step``: Algorithm 1; the final projection uses c = dt b^im_{s-1}
   (Algorithm 1 prints b^im, eq. (Q_nplus1_equation) prints b^ex; b^ex_{s-1}
   vanishes for the schemes used, which would make the system singular).
@@ -141,7 +149,7 @@ def final_residual(tab: Tableau, MQn, MQ, r, fex, dt):
 
 class IMEXHDG:
     def __init__(self, disc, dt: float, tableau: Tableau, n_richardson: int = 3,
-                 forcing=None, pressure_update: str = "reconstruct"):
+                 forcing=None, pressure_update: str = "reconstruct", step2_reading: str = "A"):
         self.disc = disc
         self.dt = float(dt)
         self.tab = tableau
@@ -150,6 +158,10 @@ class IMEXHDG:
         if pressure_update not in ("reconstruct", "first_order"):
             raise ValueError(pressure_update)
         self.pressure_update = pressure_update
+        if step2_reading not in ("A", "B"):
+            raise ValueError(step2_reading)
+        self.step2_reading = step2_reading
+        self._stage_solvers = {}  # reading B: H_c per stage coefficient c = a_ii dt
         self.M = disc.mass()
         self.ops = disc.static_operators()
         self.hdg1 = HDGSolver(disc, 1.0)
@@ -196,9 +208,16 @@ class IMEXHDG:
         for _ in range(self.nR):
             dr = r_i - self.M @ Q + adt * (A @ Q + d.g(p, lam))
             Qbar = lu.solve(dr)                                  # Step I
-            Fpsi = -d.div_c(Qbar) / adt
-            dQ, dp, dl = self.hdg1.solve(zQ, Fpsi, zT)            # Step II
-            Q = Q + Qbar + adt * dQ                               # Step III
+            if self.step2_reading == "A":
+                Fpsi = -d.div_c(Qbar) / adt
+                dQ, dp, dl = self.hdg1.solve(zQ, Fpsi, zT)        # Step II
+                Q = Q + Qbar + adt * dQ                           # Step III
+            else:
+                if adt not in self._stage_solvers:
+                    self._stage_solvers[adt] = HDGSolver(d, adt)
+                gpsi, gmu = d.gamma(Q, p, lam)
+                dQ, dp, dl = self._stage_solvers[adt].solve(self.M @ Qbar, -gpsi, -gmu)
+                Q = Q + dQ
             p = p + dp
             lam = lam + dl
             self.log.append(dict(dr=float(np.linalg.norm(dr)), Qbar=float(np.linalg.norm(Qbar))))

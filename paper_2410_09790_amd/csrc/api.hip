@@ -264,6 +264,7 @@ struct hdg_ctx {
   double* kpart = nullptr;               // partials of t = A s (4 sets)
   double *adv = nullptr, *Qs = nullptr, *dr = nullptr, *Qbar = nullptr, *dQ = nullptr, *dp = nullptr, *dl = nullptr,
          *fpsi = nullptr, *Ut = nullptr;
+  double* fmu = nullptr;  // trace data of a mixed solve (reading B of Step II)
   double *Q = nullptr, *p = nullptr, *lam = nullptr;
   double* stQ[hdg::kMaxStages] = {};
   double* stP[hdg::kMaxStages] = {};
@@ -522,6 +523,7 @@ void hdg_ctx::setup() {
   adv = dalloc<double>((long)nc * (2 * nqc + 3 * nqf));
   Qs = dalloc<double>(nQ); dr = dalloc<double>(nQ); Qbar = dalloc<double>(nQ); dQ = dalloc<double>(nQ);
   dp = dalloc<double>(nP); dl = dalloc<double>(nT); fpsi = dalloc<double>(nP); Ut = dalloc<double>(nQ);
+  fmu = dalloc<double>(nT);
   Q = dalloc<double>(nQ); p = dalloc<double>(nP); lam = dalloc<double>(nT);
   for (int i = 0; i < make_tableau(prm.imex).s; ++i) {
     stQ[i] = dalloc<double>(nQ); stP[i] = dalloc<double>(nP); stL[i] = dalloc<double>(nT);
@@ -1210,17 +1212,28 @@ void hdg_ctx::richardson(double adt, const double* r, double* Qv, double* pv, do
     bicg_iters.push_back(its);
     total_bicg += its;
     ++n_velocity_solves;
-    {
+    if (prm.step2_reading == HDG_STEP2_PRINTED) {
       Timed tm(prof, KC_DIV);
       launch_div(k, st, dm, dt, Qbar, -1.0 / adt, fpsi);  // Step II data
       KCHK();
     }
     sync();
     t_velocity += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    solve_trace(1.0, nullptr, fpsi, nullptr, dQ, dp, dl);
-    // Step III
-    launch_axpby(st, nQ, 1.0, Qbar, 1.0, Qv);
-    launch_axpby(st, nQ, adt, dQ, 1.0, Qv);
+    if (prm.step2_reading == HDG_STEP2_PRINTED) {
+      solve_trace(1.0, nullptr, fpsi, nullptr, dQ, dp, dl);
+      // Step III
+      launch_axpby(st, nQ, 1.0, Qbar, 1.0, Qv);
+      launch_axpby(st, nQ, adt, dQ, 1.0, Qv);
+    } else {
+      // reading B: the mixed solve of the stage operator H_adt with w-data
+      // (Qbar, w) and the iterate's constraint residual -Gamma(Q, p, lam),
+      // whose solution is added to the iterate
+      launch_mass(k, st, dm, 1.0, Qbar, Ut);
+      launch_gamma(k, st, dm, dt, prm.tau, -1.0, Qv, pv, lv, fpsi, ycell, fmu);
+      KCHK();
+      solve_trace(adt, Ut, fpsi, fmu, dQ, dp, dl);
+      launch_axpby(st, nQ, 1.0, dQ, 1.0, Qv);
+    }
     launch_axpby(st, nP, 1.0, dp, 1.0, pv);
     launch_axpby(st, nT, 1.0, dl, 1.0, lv);
     KCHK();
@@ -1526,7 +1539,7 @@ static void estimate_footprint(const hdg::HostMesh& m, const hdg::RefTables& rt,
                                        &rt.Chat, &rt.That, &rt.Ehat, &rt.CC, &rt.KDD, &rt.CD, &rt.BDMinv, &rt.NED})
     b += 8.0 * v->size();
   // work vectors: cell duals, trace vectors, Krylov and stage vectors
-  b += 8.0 * (nc * nlam + nT * (11 + s) + nQ * (18 + 2 * s) + nP * (3 + s));
+  b += 8.0 * (nc * nlam + nT * (12 + s) + nQ * (18 + 2 * s) + nP * (3 + s));
   b += 8.0 * ((double)kRedBlocks * kIdrMax + 2.0 * kRedBlocks + 3.0 * (prm.max_it_trace + 4) + 16 +
               (double)BS_STRIDE * std::max(prm.max_it_velocity + 6, 10) + 2 * (4 * blocks + 16));
   // Step I data: cell matrices, upwind weights, residual-kernel advection data
@@ -1581,6 +1594,7 @@ void hdg_default_params(hdg_params* p) {
   p->step1_block = 256;
   p->step1_xcd = 1;
   p->step1_precond = 1;
+  p->step2_reading = HDG_STEP2_PRINTED;
 }
 
 int hdg_create(int64_t nv, const double* coords, int64_t nc, const int32_t* cells, const hdg_params* prm,
@@ -1602,7 +1616,8 @@ int hdg_create_periodic(int64_t nv, const double* coords, int64_t nc, const int3
       prm->pressure_update > 1 || prm->idr_s < 0 || prm->idr_s > kIdrMax ||
       prm->precision < 0 || prm->precision > 1 || prm->use_graphs < 0 || prm->use_graphs > 1 ||
       (prm->step1_block != 64 && prm->step1_block != 128 && prm->step1_block != 256) || prm->step1_xcd < 0 ||
-      prm->step1_xcd > 1 || prm->step1_precond < 0 || prm->step1_precond > 1) {
+      prm->step1_xcd > 1 || prm->step1_precond < 0 || prm->step1_precond > 1 || prm->step2_reading < 0 ||
+      prm->step2_reading > 1) {
     g_create_error = "invalid parameter";
     return HDG_ERR_INVALID_ARG;
   }
@@ -2061,6 +2076,18 @@ int hdg_step1_precond(hdg_ctx* ctx, double adt, const double* Qsv, const double*
   API_END(ctx)
 }
 
+int hdg_constraint_residual(hdg_ctx* ctx, const double* Qv, const double* pv, const double* lv, double* Fpsi,
+                            double* Fmu) {
+  if (!ctx || !Qv || !Fpsi || !Fmu) return HDG_ERR_INVALID_ARG;
+  ctx->not_converged = false;
+  ctx->err.clear();
+  API_BEGIN
+  launch_gamma(ctx->k, ctx->st, ctx->dm, ctx->dt, ctx->prm.tau, 1.0, Qv, pv, lv, Fpsi, ctx->ycell, Fmu);
+  KCHK();
+  ctx->sync();
+  API_END(ctx)
+}
+
 int hdg_reconstruct_pressure(hdg_ctx* ctx, const double* Qv, double* pv, double* lv) {
   if (!ctx || !Qv || !pv || !lv) return HDG_ERR_INVALID_ARG;
   ctx->not_converged = false;
@@ -2110,6 +2137,7 @@ int hdg_get_info(const hdg_ctx* ctx, char* buf, size_t cap) {
                   ",\"step1_block\":" + std::to_string(ctx->s1.block) +
                   ",\"step1_xcd\":" + std::to_string(ctx->s1.xcd) +
                   ",\"step1_precond\":" + std::to_string(ctx->pc_on ? 1 : 0) +
+                  ",\"step2_reading\":" + std::to_string(ctx->prm.step2_reading) +
                   ",\"step1_precond_builds\":" + std::to_string(ctx->pc_builds) +
                   ",\"device_transient_bytes\":" + std::to_string(ctx->dev_transient) +
                   ",\"pcg_iterations_last\":" + last(ctx->pcg_iters, 16) +

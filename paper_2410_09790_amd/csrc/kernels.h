@@ -74,6 +74,10 @@ void launch_rhs_condense(int k, hipStream_t st, DMesh m, DTab t, double c, doubl
 void launch_gather_rhs(int k, hipStream_t st, DMesh m, const double* ycell, const double* Fmu, double* g);
 void launch_backsub(int k, hipStream_t st, DMesh m, DTab t, double c, double tau, const double* Pinv,
                     const double* Fw, const double* Fpsi, const double* lam, double* U, double* p, double* part);
+// scale * Gamma(psi, mu, Q, P, lam) as dual vectors: gpsi [nc][np] and gmu [nF][nf]
+// (ycell: scratch of nc * 3 * nf doubles); P or lam may be null (zero)
+void launch_gamma(int k, hipStream_t st, DMesh m, DTab t, double tau, double scale, const double* Q, const double* P,
+                  const double* lam, double* gpsi, double* ycell, double* gmu);
 void launch_prep_adv(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, double* adv);
 // mode 0: out = x - (adt/det) f_im(x)          (mass-scaled Step I operator)
 // mode 1: out = (r - det x + adt (f_im(x) + g(p, lam))) / det  (mass-scaled residual)

@@ -444,6 +444,76 @@ __global__ void k_shift_mean(DMesh m, const double* __restrict__ mean, double* _
   if (tid < m.nF && lam) lam[tid * NF] -= mv;
 }
 
+// Constraint residual Gamma(psi, mu, Q, p, lam) of Section "Hybridisation"
+// (the second line of the hybridised system) as dual vectors, times scale:
+//   psi part, per cell:  (psi, div Q)_K + <tau (p - lam), psi>_dK
+//   mu part, per (cell, local facet): <Q.n_K + tau (p - lam), mu>_F from
+//   this cell's side, written to ycell in the layout k_gather_rhs sums over
+//   the facet's cells.
+// With the reference blocks: D Q + T p - E^T lam and C Q + E p - F lam.
+// P or lam may be null (zero).
+template <int K>
+__global__ void __launch_bounds__(kBlock) k_gamma(DMesh m, DTab t, double tau, double scale,
+                                                  const double* __restrict__ Q, const double* __restrict__ P,
+                                                  const double* __restrict__ lam, double* __restrict__ gpsi,
+                                                  double* __restrict__ ycell) {
+  using D = Dims<K>;
+  constexpr int NS = D::NS, NP = D::NP, NF = D::NF, NU = D::NU;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m.nc) return;
+  const long nc = m.nc;
+  const CellGeo g = load_geo(m, e);
+  double q[NU], p[NP], ps[NP];
+#pragma unroll
+  for (int i = 0; i < NU; ++i) q[i] = Q[(long)e * NU + i];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) p[i] = P ? P[(long)e * NP + i] : 0.0;
+  // (psi_i, div Q)_K = det sum_s (Dhat_x[i][s] u0_s + Dhat_y[i][s] u1_s), u_a = sum_c iJ[a][c] Q_c
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    double v = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const double u0 = g.ij[0][0] * q[s] + g.ij[0][1] * q[NS + s];
+      const double u1 = g.ij[1][0] * q[s] + g.ij[1][1] * q[NS + s];
+      v += t.Dx[i * NS + s] * u0 + t.Dy[i * NS + s] * u1;
+    }
+    ps[i] = g.det * v;
+  }
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const int F = m.cf_facet[f * nc + e];
+    const int flip = m.cf_flip[f * nc + e];
+    const double h = g.h[f];
+    double l[NF];
+#pragma unroll
+    for (int mm = 0; mm < NF; ++mm) l[mm] = lam ? lam[(long)F * NF + mm] : 0.0;
+    // psi part: tau h (That p - Ehat^T sgn lam)
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      double v = 0.0;
+#pragma unroll
+      for (int j = 0; j < NP; ++j) v += t.That[(f * NP + i) * NP + j] * p[j];
+#pragma unroll
+      for (int mm = 0; mm < NF; ++mm) v -= t.Ehat[(f * NF + mm) * NP + i] * sgn(flip, mm) * l[mm];
+      ps[i] += tau * h * v;
+    }
+    // mu part from this side: h sgn (Chat (Q.n) + tau Ehat p) - tau h lam
+#pragma unroll
+    for (int mm = 0; mm < NF; ++mm) {
+      double cq = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) cq += t.Chat[(f * NF + mm) * NS + s] * (g.n[f][0] * q[s] + g.n[f][1] * q[NS + s]);
+      double ep = 0.0;
+#pragma unroll
+      for (int j = 0; j < NP; ++j) ep += t.Ehat[(f * NF + mm) * NP + j] * p[j];
+      ycell[(long)(f * NF + mm) * nc + e] = scale * (h * sgn(flip, mm) * (cq + tau * ep) - tau * h * l[mm]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NP; ++i) gpsi[(long)e * NP + i] = scale * ps[i];
+}
+
 // ================================================================ a4, a5
 // Per-stage advection data from Q*: weighted reference-direction velocities
 // at the cell points and the facet weights (1/2 qn - delta |qn|) w h at the
@@ -1160,6 +1230,11 @@ void launch_backsub(int k, hipStream_t st, DMesh m, DTab t, double c, double tau
                     const double* Fw, const double* Fpsi, const double* lam, double* U, double* p, double* part) {
   // one partial sum per block: part holds ceil(nc / kBlock) entries
   HDG_DISPATCH(k, (k_backsub<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, c, tau, Pinv, Fw, Fpsi, lam, U, p, part)));
+}
+void launch_gamma(int k, hipStream_t st, DMesh m, DTab t, double tau, double scale, const double* Q, const double* P,
+                  const double* lam, double* gpsi, double* ycell, double* gmu) {
+  HDG_DISPATCH(k, (k_gamma<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, tau, scale, Q, P, lam, gpsi, ycell)));
+  HDG_DISPATCH(k, (k_gather_rhs<KK><<<nblocks((long)m.nF * (KK + 1)), kBlock, 0, st>>>(m, ycell, nullptr, gmu)));
 }
 void launch_prep_adv(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, double* adv) {
   HDG_DISPATCH(k, (k_prep_adv<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, Qs, delta_up, adv)));

@@ -24,6 +24,7 @@ IMEX = {"imex_euler": 0, "ars222": 1, "ars233": 2, "ssp2_332": 3, "ssp3_433": 4}
 TRACE_SOLVER = {"jacobi_pcg": 0, "mg_pcg": 1}
 PRESSURE = {"reconstruct": 0, "first_order": 1}
 PRECISION = {"fp64": 0, "mixed": 1}
+STEP2 = {"A": 0, "printed": 0, "B": 1, "stage_solve": 1}
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NOT_CONVERGED", 5: "BAD_STATE",
           6: "UNSUPPORTED"}
 
@@ -34,7 +35,7 @@ EXPORTS = [
     "hdg_cg_project", "hdg_tracer_rate", "hdg_last_error", "hdg_sizes", "hdg_cell_points",
     "hdg_facet_points", "hdg_set_forcing", "hdg_set_time", "hdg_get_time", "hdg_set_velocity_from_points", "hdg_set_state", "hdg_get_state", "hdg_advance", "hdg_solve_trace",
     "hdg_trace_matvec", "hdg_bdm_project", "hdg_weak_divergence", "hdg_momentum_residual",
-    "hdg_tentative_velocity", "hdg_step1_precond", "hdg_reconstruct_pressure", "hdg_profile", "hdg_get_info",
+    "hdg_tentative_velocity", "hdg_step1_precond", "hdg_constraint_residual", "hdg_reconstruct_pressure", "hdg_profile", "hdg_get_info",
 ]
 
 
@@ -58,6 +59,7 @@ class Params(ctypes.Structure):
         ("step1_block", ctypes.c_int),
         ("step1_xcd", ctypes.c_int),
         ("step1_precond", ctypes.c_int),
+        ("step2_reading", ctypes.c_int),
     ]
 
 
@@ -116,6 +118,7 @@ def load_library(path: str = LIB_PATH):
         "hdg_momentum_residual": (I, [P, D, P, P, P, P, P, P]),
         "hdg_tentative_velocity": (I, [P, D, P, P, P]),
         "hdg_step1_precond": (I, [P, D, P, P, P]),
+        "hdg_constraint_residual": (I, [P, P, P, P, P, P]),
         "hdg_reconstruct_pressure": (I, [P, P, P, P]),
         "hdg_profile": (I, [P, I]),
         "hdg_get_info": (I, [P, ctypes.c_char_p, ctypes.c_size_t]),
@@ -141,6 +144,8 @@ def default_params(**kw) -> Params:
             val = PRESSURE[val]
         elif key == "precision" and isinstance(val, str):
             val = PRECISION[val]
+        elif key == "step2_reading" and isinstance(val, str):
+            val = STEP2[val]
         setattr(p, key, val)
     return p
 
@@ -361,6 +366,12 @@ class Context:
         out = self._empty(self.nQ)
         self._check(self._lib.hdg_step1_precond(self._h, float(adt), _ptr(Qstar), _ptr(r), _ptr(out)))
         return out
+
+    def constraint_residual(self, Q, p=None, lam=None):
+        """Gamma(psi, mu, Q, p, lam) as dual vectors (Fpsi, Fmu)."""
+        Fpsi, Fmu = self._empty(self.nP), self._empty(self.nT)
+        self._check(self._lib.hdg_constraint_residual(self._h, _ptr(Q), _ptr(p), _ptr(lam), _ptr(Fpsi), _ptr(Fmu)))
+        return Fpsi, Fmu
 
     def reconstruct_pressure(self, Q):
         p, lam = self._empty(self.nP), self._empty(self.nT)

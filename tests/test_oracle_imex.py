@@ -195,3 +195,79 @@ def test_p12_pressure_reconstruction_of_exact_velocity(k):
         errs.append(_tg_errors(d, Q, p, 0.0)[1])
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert rates.min() > k + 0.5, rates
+
+
+def _stage_problem(n, k, dt, seed=2, amp=3.0):
+    """A stage of ARS(2,2,2) on a perturbed n x n mesh: the data of Algorithm 2
+    and the monolithic solution of eqs. (imex_implicit_solve) and
+    (imex_implicit_solve_constraint), by a dense least-squares solve of the
+    full (Q, p, lambda) system (its null space is the constant (p, lambda))."""
+    import scipy.sparse as sp
+    X, C = hi.unit_square_mesh(n)
+    X = hi.random_mesh_perturbation(X, n, 0.1, 1)
+    d = Discretisation(X, C, k)
+    par = hi.stream_function_params(seed)
+    Q0 = d.l2_project_velocity(lambda x, y: amp * hi.streamfunction_velocity(par, x, y))
+    st = IMEXHDG(d, dt, ars222(), 1)
+    p0, l0 = st.reconstruct(Q0, 0.0)
+    Qs = d.bdm_project(Q0)
+    a = ars222().Aim[1, 1]
+    adt = a * dt
+    r = d.mass() @ Q0
+    s = d.static_operators()
+    A = d.mass() - adt * d.advection(Qs)
+    H = sp.bmat([[A, -adt * s["Gp"], -adt * s["Gl"]], [s["Dv"], s["Tpp"], s["Tpl"]],
+                 [s["Cl"], s["Elp"], s["Fll"]]]).toarray()
+    x = np.linalg.lstsq(H, np.concatenate([r, np.zeros(d.nP + d.nT)]), rcond=None)[0]
+    return d, (r, a, Qs, Q0, p0, l0), x[:d.nQ]
+
+
+@pytest.mark.parametrize("n,k", [(3, 1), (2, 2)])
+def test_p14_reading_b_converges_to_the_monolithic_stage_solve(n, k):
+    """P14: with Step II read as the mixed solve of the stage operator H_{a dt}
+    with the constraint residual of the iterate (reading B), the Richardson
+    iterates converge to the monolithic solution of the stage equations as
+    n_R grows, and the limit satisfies the constraint Gamma = 0; the printed
+    Step II (reading A) settles elsewhere: it never removes the constraint
+    residual of the iterate."""
+    d, (r, a, Qs, Q0, p0, l0), Qm = _stage_problem(n, k, 5e-3)
+    errs = {}
+    for reading in ("A", "B"):
+        errs[reading] = []
+        for nR in (2, 8, 32):
+            st = IMEXHDG(d, 5e-3, ars222(), nR, step2_reading=reading)
+            Q, p, lam = st.richardson(r, a, Qs, Q0, p0, l0)
+            errs[reading].append(np.linalg.norm(Q - Qm) / np.linalg.norm(Qm))
+            if reading == "B" and nR == 32:
+                gpsi, gmu = d.gamma(Q, p, lam)
+                scale = np.linalg.norm(np.concatenate(d.gamma(Q, 0 * p, 0 * lam)))
+                assert np.linalg.norm(np.concatenate([gpsi, gmu])) <= 1e-10 * scale
+    eb, ea = errs["B"], errs["A"]
+    assert eb[0] > eb[1] > eb[2] and eb[2] < 1e-9, eb
+    assert min(ea) > 1e-3, ea          # a different fixed point
+    assert abs(ea[2] - ea[1]) < 1e-3 * ea[2]  # ... which reading A does reach
+
+
+def test_reading_b_step_is_a_step():
+    """Reading B on whole steps: the final projection leaves Gamma(Q^{n+1}) = 0
+    (P10) and the zero state stays zero (P13)."""
+    X, C = hi.unit_square_mesh(3)
+    d = Discretisation(X, C, 2)
+    par = hi.stream_function_params(0)
+    st = IMEXHDG(d, 1e-3, ars222(), 2, step2_reading="B")
+    Q, p, lam = st.initial_state(lambda x, y: hi.streamfunction_velocity(par, x, y))
+    Q1, p1, l1 = st.step(Q, p, lam, 0.0)
+    dp, dl = st.last_final
+    gpsi, gmu = d.gamma(Q1, dp, dl)
+    assert np.linalg.norm(np.concatenate([gpsi, gmu])) <= 1e-11 * np.linalg.norm(d.mass() @ Q1)
+    z = np.zeros(d.nQ)
+    Qz, pz, lz = st.step(z, np.zeros(d.nP), np.zeros(d.nT), 0.0)
+    assert np.abs(Qz).max() == 0.0 and np.abs(pz).max() == 0.0
+    # The readings give different steps: the state's (p, lambda) come from the
+    # pressure reconstruction, which does not make Gamma(Q, p, lambda) vanish
+    # (Gamma holds tau (p - lambda) terms), and reading B removes that
+    # residual in its first iteration while reading A never sees it.
+    st_a = IMEXHDG(d, 1e-3, ars222(), 2)
+    Qa, _, _ = st_a.step(Q, p, lam, 0.0)
+    assert np.linalg.norm(np.concatenate(d.gamma(Q, p, lam))) > 1e-3 * np.linalg.norm(d.mass() @ Q)
+    assert np.linalg.norm(Qa - Q1) > 1e-6 * np.linalg.norm(Q1)
