@@ -1316,7 +1316,18 @@ void hdg_ctx::finish_step() {
   }
   KCHK();
   time += dtv;  // the final projection and the reconstruction belong to t^{n+1}
-  solve_trace(dtv * tab.bim[s - 1], rn, nullptr, nullptr, Q, dp, dl);
+  // Final projection (Algorithm 1, eq. (final_update)) in increment form:
+  // with Q^{n+1} = Q_{s-1} + dQ, H_c(Q^{n+1}, dp, dl) = (r^{n+1}, 0, 0) is
+  // H_c(dQ, dp, dl) = (r^{n+1} - M Q_{s-1}, -Gamma(Q_{s-1}, 0, 0)), the same
+  // system in exact arithmetic; the trace solve's error then scales with the
+  // increment rather than with the state.
+  launch_mass(k, st, dm, -1.0, stQ[s - 1], Ut);
+  launch_axpby(st, nQ, 1.0, Ut, 1.0, rn);
+  launch_gamma(k, st, dm, dt, prm.tau, -1.0, stQ[s - 1], nullptr, nullptr, fpsi, ycell, fmu);
+  KCHK();
+  solve_trace(dtv * tab.bim[s - 1], rn, fpsi, fmu, dQ, dp, dl);
+  launch_copy(st, nQ, stQ[s - 1], Q);
+  launch_axpby(st, nQ, 1.0, dQ, 1.0, Q);
   if (prm.pressure_update == HDG_PRESSURE_RECONSTRUCT) {
     reconstruct(Q, p, lam);
   } else {
