@@ -241,13 +241,14 @@ def trace_operator_run(hdg, hi, torch, n: int = 512, k: int = 3, calls: int = 40
 
 
 def mixed_run(hdg, hi, torch, w, X, C, args, ref_ctx):
-    """The same workload in the mixed-precision mode: the Step I cell matrices
-    stored in FP32 and the Step I solves stopped at MIXED_RTOL_VELOCITY (an
-    operator that is only FP32-accurate gains nothing from a tighter solve);
-    FP64 arithmetic, Krylov recurrences, trace solves and Richardson residual,
-    so the Richardson loop refines each stage.  Reports the throughput and
-    the relative L2 difference of the final state from the FP64 run above
-    (same warm-up and timed steps from the same initial state)."""
+    """The same workload in the mixed-precision mode: the Step I solve in FP32
+    (vectors, cell data, arithmetic) stopped at MIXED_RTOL_VELOCITY, the FP64
+    Richardson residual refining each stage, FP64 trace solves.  Reports the
+    throughput and the relative L2 difference of the final state from the
+    FP64 run above (same warm-up and timed steps from the same initial
+    state), and the FP64 path at the same Step I tolerance (the
+    equal-tolerance baseline, so that the ratio measures the precision
+    alone)."""
     mctx = hdg.Context(X, C, degree=w["k"], imex=w["scheme"], n_richardson=w["n_richardson"],
                        trace_solver=w["trace_solver"], rtol_trace=w["rtol_trace"],
                        rtol_velocity=MIXED_RTOL_VELOCITY, precision="mixed")
@@ -286,9 +287,10 @@ def mixed_run(hdg, hi, torch, w, X, C, args, ref_ctx):
     value64 = ref_ctx.nT * 2 * args.steps / el64
     log(f"FP64 at the mixed run's Step I rtol: {1e3 * el64 / args.steps:.1f} ms/step, diff vs FP64 {diffs64}")
     return {"value": value, "ms_per_step": 1e3 * el / args.steps,
-            "precision": "FP32 storage of the per-stage Step I cell matrices, Step I rtol "
-                         f"{MIXED_RTOL_VELOCITY:g}; FP64 arithmetic, Krylov recurrences, trace solves and "
-                         "Richardson residual",
+            "precision": f"Step I in FP32 (Krylov vectors, cell matrices, upwind weights, arithmetic; FP64 inner "
+                         f"products) stopped at rtol {MIXED_RTOL_VELOCITY:g}; FP64 Richardson residual (which refines "
+                         "each stage), trace solves, increment-form final projection and pressure reconstruction; "
+                         "the Step I preconditioner is FP16-stored in both modes",
             "rel_l2_diff_vs_fp64": diffs, "speedup_vs_fp64": None,
             "fp64_same_rtol": {"value": value64, "ms_per_step": 1e3 * el64 / args.steps,
                                "rel_l2_diff_vs_fp64": diffs64},
@@ -464,16 +466,19 @@ def batched_run(hdg, hi, torch, ninst: int = 4, steps: int = 1):
     return out
 
 
-def serving_run(hdg, hi, torch, njobs: int = 16, nmax: int = 48, steps: int = 10, rho: float = 0.8):
-    """A bounded sample of the serving workload: jobs j = 0..njobs-1 with
-    n = round(exp(U(ln 16, ln 512))) clipped to nmax and k = integers(1, 5)
-    from default_rng(10000 + j), steps time steps of ARS(2,2,2) each
-    (dt = 1e-3, n_R = 3, Jacobi-PCG below 32 x 32, else MG-PCG; FP64).  Each job
-    first runs alone (one at a time); then the jobs arrive with exponential
-    gaps from default_rng(999) at rate rho / mean alone time and are served
-    by the continuous-batching loop (admission by footprint, 8 slots,
-    budget 32 GiB).  The one-at-a-time FIFO baseline under the same arrivals
-    follows from the alone times."""
+def serving_run(hdg, hi, torch, njobs: int = 16, nmax: int = 48, steps: int = 10, rhos=(0.5, 0.8),
+                workers=(1, 2)):
+    """A sample of the serving workload: jobs j = 0..njobs-1 with
+    n = round(exp(U(ln 16, ln 512))) (clipped to nmax when nmax < 512) and
+    k = integers(1, 5) from default_rng(10000 + j), `steps` ARS(2,2,2) steps
+    each (dt = 1e-3, n_R = 3, Jacobi-PCG below 32 x 32, else MG-PCG; FP64 at
+    the paper's tolerances).  Each job first runs alone (service time and
+    reference state); then, for each offered load rho, the jobs arrive with
+    exponential gaps from default_rng(999) at rate rho / mean alone time, and
+    are run twice under the same arrivals: one at a time in arrival order
+    (FIFO, measured) and by the stage-granular shortest-remaining-work server
+    (admission by footprint) with each worker-thread count in `workers`.
+    Latency = arrival to completion."""
     import threading
     import numpy as np
     from paper_2410_09790_amd import serve
@@ -487,43 +492,63 @@ def serving_run(hdg, hi, torch, njobs: int = 16, nmax: int = 48, steps: int = 10
         jobs.append(serve.Job(X, C, vel, 1e-3, steps,
                               dict(degree=k, imex="ars222", n_richardson=3, trace_solver=solver, rtol_trace=1e-12,
                                    rtol_velocity=1e-10), name=f"{n}x{n} k={k}"))
-    alone = [serve.run_alone(job) for job in jobs]
+    alone = []
+    for i, job in enumerate(jobs):
+        alone.append(serve.run_alone(job))
+        log(f"serving: job {i} ({job.name}) alone {alone[-1][0]:.2f} s")
     service = np.array([a[0] for a in alone])
-    arrivals = hi.serving_arrivals(service.mean() / rho, njobs)
-    # FIFO one at a time under the same arrivals
-    fin, fifo_lat = 0.0, []
-    for a_j, s_j in zip(arrivals, service):
-        fin = max(fin, a_j) + s_j
-        fifo_lat.append(fin - a_j)
     work = sum(a[2] * steps * 2 for a in alone)
-    srv = serve.Server(32 << 30, slots=8)
+    out = {"workload": f"serving sample: jobs 0..{njobs - 1} of the serving recipe" +
+                       (f", n clipped to {nmax}" if nmax < 512 else " (n not clipped)") +
+                       f", {steps} ARS(2,2,2) steps each, Poisson arrivals at offered load rho (arrival rate x mean "
+                       f"alone service time); FP64, paper tolerances",
+           "jobs": [j.name for j in jobs], "alone_s": [round(float(x), 3) for x in service],
+           "unit": "trace-DOF-stages/s", "server": "stage-granular shortest remaining work",
+           "loads": {}}
+    for rho in rhos:
+        arrivals = hi.serving_arrivals(service.mean() / rho, njobs)
+        fifo = serve.run_fifo(jobs, arrivals,
+                              progress=lambda i, r: log(f"serving rho={rho}: FIFO job {i - 1} done at {r[2]:.1f} s"))
+        fifo_lat = [e - a for a, _, e in fifo]
+        fifo_span = max(e for _, _, e in fifo) - arrivals[0]
+        log(f"serving rho={rho}: FIFO p50/p99 {serve.percentiles(fifo_lat)} s")
+        load = {"fifo_one_at_a_time_measured": {"latency_s": serve.percentiles(fifo_lat),
+                                                "mean_latency_s": float(np.mean(fifo_lat)),
+                                                "throughput": work / fifo_span}}
+        for nw in workers:
+            pol = ["srpt"] if nw == 1 else None  # default: srpt + fifo workers
+            srv = serve.Server(64 << 30, workers=nw, policies=pol)
 
-    def feed():
-        t0 = srv.now()
-        for a_j, job in zip(arrivals, jobs):
-            wait = a_j - (srv.now() - t0)
-            if wait > 0:
-                time.sleep(wait)
-            srv.submit(job)
+            def feed():
+                t0 = srv.now()
+                for a_j, job in zip(arrivals, jobs):
+                    wait = a_j - (srv.now() - t0)
+                    if wait > 0:
+                        time.sleep(wait)
+                    srv.submit(job)
 
-    th = threading.Thread(target=feed)
-    th.start()
-    th.join()
-    srv.drain(timeout=600)
-    res = srv.results
-    same = all(r.error is None and all(np.array_equal(x, y) for x, y in zip(r.state, a[1])) for r, a in zip(res, alone))
-    lat = [r.latency for r in res]
-    makespan = max(r.end for r in res) - min(r.arrival for r in res)
-    out = {"workload": f"serving sample: {njobs} jobs of the serving recipe, n clipped to {nmax}, {steps} ARS(2,2,2) "
-                       f"steps each, Poisson arrivals at rho={rho} of the mean alone service time",
-           "jobs": [j.name for j in jobs],
-           "served": {"latency_s": serve.percentiles(lat), "throughput": work / makespan, "max_active": srv.max_active,
-                      "max_in_use_bytes": srv.max_in_use},
-           "fifo_one_at_a_time": {"latency_s": serve.percentiles(fifo_lat), "throughput": work / (fin - arrivals[0])},
-           "unit": "trace-DOF-stages/s", "results_identical_to_alone": bool(same)}
-    log(f"serving: p50/p99 latency {out['served']['latency_s']} s served vs {out['fifo_one_at_a_time']['latency_s']} s "
-        f"FIFO; throughput {out['served']['throughput']:.4g} vs {out['fifo_one_at_a_time']['throughput']:.4g}; "
-        f"identical to alone: {same}")
+            th = threading.Thread(target=feed)
+            th.start()
+            th.join()
+            while True:
+                try:
+                    srv.drain(timeout=30)
+                    break
+                except TimeoutError:  # a progress line every 30 s
+                    log(f"serving rho={rho}, {nw} workers: {sum(r.end > 0 for r in srv.results)} of {njobs} done")
+            res = srv.results
+            same = all(r.error is None and all(np.array_equal(x, y) for x, y in zip(r.state, a[1]))
+                       for r, a in zip(res, alone))
+            lat = [r.latency for r in res]
+            makespan = max(r.end for r in res) - min(r.arrival for r in res)
+            load[f"served_{nw}_workers"] = {"policies": srv.policies,
+                "latency_s": serve.percentiles(lat), "mean_latency_s": float(np.mean(lat)),
+                "throughput": work / makespan, "max_active": srv.max_active, "max_in_use_bytes": srv.max_in_use,
+                "results_identical_to_alone": bool(same)}
+            log(f"serving rho={rho}, {nw} workers: served p50/p99 {serve.percentiles(lat)} s, mean "
+                f"{np.mean(lat):.3f} s, throughput {work / makespan:.4g}; FIFO {serve.percentiles(fifo_lat)} s, mean "
+                f"{np.mean(fifo_lat):.3f} s, {work / fifo_span:.4g}; identical to alone: {same}")
+        out["loads"][str(rho)] = load
     return out
 
 
@@ -565,8 +590,13 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=1, help="timed steps of the batched sample (recipe: 10)")
     ap.add_argument("--serving-jobs", type=int, default=16, help="jobs of the serving sample (recipe: 200)")
     ap.add_argument("--serving-nmax", type=int, default=48, help="mesh size cap of the serving sample (recipe: 512)")
-    ap.add_argument("--serving-rho", type=float, default=0.8,
-                    help="offered load of the serving sample: arrival rate x mean alone service time (recipe: 0.5, 0.8)")
+    ap.add_argument("--serving-rho", type=float, nargs="+", default=[0.5, 0.8],
+                    help="offered loads of the serving sample: arrival rate x mean alone service time (recipe: 0.5, 0.8)")
+    ap.add_argument("--serving-steps", type=int, default=10, help="steps per serving job (recipe: 20)")
+    ap.add_argument("--serving-workers", type=int, nargs="+", default=[1, 2],
+                    help="worker-thread counts of the serving loop to measure")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving sample and print it as the JSON line (a separate measurement)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -581,6 +611,11 @@ def main():
     from paper_2410_09790_amd import hdg
 
     torch.cuda.set_device(0)
+    if args.serving_only:
+        serving = serving_run(hdg, hi, torch, args.serving_jobs, args.serving_nmax, args.serving_steps,
+                              tuple(args.serving_rho), tuple(args.serving_workers))
+        print(json.dumps({"metric": "serving job latency p50/p99 (s) and throughput", "serving": serving}), flush=True)
+        return
     if args.copy_probe:
         # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE counters
         # calibrate the byte counters of the HDG kernels
@@ -692,7 +727,8 @@ def main():
         batched = batched_run(hdg, hi, torch, args.batched_instances, args.batched_steps)
     serving = None
     if not args.no_serving:
-        serving = serving_run(hdg, hi, torch, args.serving_jobs, args.serving_nmax, rho=args.serving_rho)
+        serving = serving_run(hdg, hi, torch, args.serving_jobs, args.serving_nmax, args.serving_steps,
+                              tuple(args.serving_rho), tuple(args.serving_workers))
     trace_op = None
     if not args.no_trace_op:
         trace_op = trace_operator_run(hdg, hi, torch)

@@ -82,18 +82,14 @@ typedef enum {
 } hdg_imex_scheme;
 typedef enum { HDG_TRACE_JACOBI_PCG = 0, HDG_TRACE_MG_PCG = 1 } hdg_trace_solver;
 typedef enum { HDG_PRESSURE_RECONSTRUCT = 0, HDG_PRESSURE_FIRST_ORDER = 1 } hdg_pressure_update;
-/* HDG_MIXED: the per-stage cell matrices of the Step I operator (the
- * dominant HBM stream of the tentative-velocity solve, Algorithm 2 Step I)
- * are stored in FP32; the operator still computes in FP64, and every
- * Krylov recurrence, inner product, the Richardson residual (which uses the
- * FP64 form f_im) and the trace solves stay FP64.  Step I then solves a
- * system within ~1e-7 (relative) of the FP64 one, and the Richardson
- * iteration of Algorithm 2 refines the stage with the FP64 residual, so a
- * looser Step I tolerance is the natural companion of this mode; on the
- * 256 x 256, k = 3 workload four steps at rtol_velocity = 1e-5 stay within
- * 2e-9 of the FP64 steps at rtol_velocity = 1e-10.  FP32 operator
- * arithmetic is not offered: it makes BiCGStab stall or diverge on this
- * operator. */
+/* HDG_MIXED: the tentative-velocity solve (Algorithm 2, Step I) runs in
+ * FP32: Krylov vectors, the per-stage cell matrices and upwind weights, and
+ * the operator's arithmetic; its inner products accumulate in FP64, and it
+ * stops at max(rtol_velocity, 1e-6) (FP32 cannot go tighter).  Everything
+ * else stays FP64: the Richardson residual of Algorithm 2 (eq. (f_impl) in
+ * FP64), which refines each stage, the trace solves, the final projection
+ * (in increment form) and the pressure reconstruction.  The Step I
+ * preconditioner is the same FP16-stored Schwarz method in both modes. */
 typedef enum { HDG_FP64 = 0, HDG_MIXED = 1 } hdg_precision;
 /* Step II of Algorithm 2.  PRINTED (reading A): the mixed solve of eq.
  * (pressure_increment) with c = 1, psi-data -Div(psi, Qbar)/(a_ii dt) and

@@ -351,11 +351,15 @@ struct hdg_ctx {
   void solve_trace(double c, const double* Fw, const double* Fpsi, const double* Fmu, double* U, double* p,
                    double* lam);
   // BiCGStab vectors, structure-of-arrays
+  // structure-of-arrays Krylov vectors of the Step I solve, FP64 or, in the
+  // mixed-precision mode (kx32), FP32
   struct KrylovBuf {
-    double *b = nullptr, *x = nullptr, *r = nullptr, *rh = nullptr, *s = nullptr, *t = nullptr, *p = nullptr,
-           *v = nullptr;
-    double *ph = nullptr, *sh = nullptr;  // preconditioned directions (right preconditioning)
+    void *b = nullptr, *x = nullptr, *r = nullptr, *rh = nullptr, *s = nullptr, *t = nullptr, *p = nullptr,
+         *v = nullptr;
+    void *ph = nullptr, *sh = nullptr;  // preconditioned directions (right preconditioning)
   };
+  bool kx32 = false;  // FP32 Step I: vectors, upwind weights, cell matrices and arithmetic
+  static constexpr double kMixedRtolFloor = 1e-6;
   KrylovBuf kd;
   // per-stage Step I data of the current Q*: cell volume matrices (FP32 in
   // the mixed-precision mode) and facet upwind weights (tiles of 32 cells)
@@ -364,10 +368,10 @@ struct hdg_ctx {
   // is the accuracy reference)
   void* vk = nullptr;
   bool vk32 = false;
-  double* vbeta = nullptr;
+  void* vbeta = nullptr;  // upwind weights, FP32 when kx32
   void prepare_step1(const double* Qstar) {
     hdg::launch_prep_adv(k, st, dm, dt, Qstar, prm.delta_up, adv);
-    hdg::launch_step1_matrix(k, st, dm, dt, Qstar, prm.delta_up, vk, vk32, vbeta);
+    hdg::launch_step1_matrix(k, st, dm, dt, Qstar, prm.delta_up, vk, vk32, vbeta, kx32);
     vk_qs = Qstar;
     ++vk_gen;
   }
@@ -389,9 +393,9 @@ struct hdg_ctx {
     pc_adt = adt;
     ++pc_builds;
   }
-  void pc_apply(const double* r, double* z) {
+  void pc_apply(const void* r, void* z) {
     hdg::Timed tm(prof, hdg::KC_PC_APPLY);
-    hdg::launch_pc_apply(k, st, dm, pcB, r, z);
+    hdg::launch_pc_apply(k, st, dm, pcB, r, z, kx32);
   }
   int bicgstab(double adt, const double* b, double* x);
   static constexpr int kBicgBlock = 8;  // BiCGStab iterations per captured block
@@ -503,22 +507,24 @@ void hdg_ctx::setup() {
   pr = dalloc<double>(nT); pz = dalloc<double>(nT); pp = dalloc<double>(nT); pq = dalloc<double>(nT);
   t1 = dalloc<double>(nT); t2 = dalloc<double>(nT); t3 = dalloc<double>(nT); px = dalloc<double>(nT);
   small_info = dalloc<double>(4);
-  for (double** v : {&kd.b, &kd.x, &kd.r, &kd.rh, &kd.s, &kd.t, &kd.p, &kd.v}) *v = dalloc<double>(nQ);
+  kx32 = prm.precision == HDG_MIXED;
+  auto kvec = [&]() -> void* { return kx32 ? (void*)dalloc<float>(nQ) : (void*)dalloc<double>(nQ); };
+  for (void** v : {&kd.b, &kd.x, &kd.r, &kd.rh, &kd.s, &kd.t, &kd.p, &kd.v}) *v = kvec();
   // the facet-patch preconditioner needs every cell on an interior facet
   // (else a cell would receive no correction)
   pc_on = prm.step1_precond == 1 && prm.idr_s == 0;
   for (long e = 0; pc_on && e < nc; ++e)
     pc_on = hm.cf_nb[e] >= 0 || hm.cf_nb[nc + e] >= 0 || hm.cf_nb[2 * nc + e] >= 0;
   if (pc_on) {
-    kd.ph = dalloc<double>(nQ);
-    kd.sh = dalloc<double>(nQ);
+    kd.ph = kvec();
+    kd.sh = kvec();
     pcD = dalloc<double>(nc * nu * nu);
     pcB = dalloc<uint16_t>(pc_entries(k, nc));
   }
   const long nc32 = (nc + 31) / 32 * 32;
   vk32 = prm.precision == HDG_MIXED;
   vk = vk32 ? (void*)dalloc<float>((long)ns * ns * nc32) : (void*)dalloc<double>((long)ns * ns * nc32);
-  vbeta = dalloc<double>(3L * nqf * nc32);
+  vbeta = kx32 ? (void*)dalloc<float>(3L * nqf * nc32) : (void*)dalloc<double>(3L * nqf * nc32);
   br = dalloc<double>(nQ); bt = dalloc<double>(nQ);
   adv = dalloc<double>((long)nc * (2 * nqc + 3 * nqf));
   Qs = dalloc<double>(nQ); dr = dalloc<double>(nQ); Qbar = dalloc<double>(nQ); dQ = dalloc<double>(nQ);
@@ -937,29 +943,29 @@ void hdg_ctx::bicgstab_block(double adt) {
   launch_copy(st, BS_STRIDE, bsc + (long)BS_STRIDE * kBicgBlock, bsc);
   // right preconditioning: the operator acts on ph = B p and sh = B s, the
   // residual stays that of the unpreconditioned system
-  const double* ph = pc_on ? B.ph : B.p;
-  const double* sh = pc_on ? B.sh : B.s;
+  const void* ph = pc_on ? B.ph : B.p;
+  const void* sh = pc_on ? B.sh : B.s;
   for (int b = 0; b < kBicgBlock; ++b) {
     double* sc = bsc + (long)BS_STRIDE * b;
     if (pc_on) pc_apply(B.p, B.ph);
     {
       Timed tm(prof, KC_APPLY_OP);
-      launch_apply_soa(k, st, s1, 1, dm, dt, vk, vk32, vbeta, prm.alpha, adt, ph, B.rh, B.v, part);
+      launch_apply_soa(k, st, s1, 1, dm, dt, vk, vk32, vbeta, prm.alpha, adt, ph, B.rh, B.v, part, nullptr, kx32);
     }
     {
       Timed tm(prof, KC_VECTOR);
-      launch_bicg_s(st, n, apply_soa_blocks(hm.nc, s1.block), part, sc, B.r, B.v, B.s);
+      launch_bicg_s(st, n, apply_soa_blocks(hm.nc, s1.block), part, sc, B.r, B.v, B.s, kx32);
     }
     if (pc_on) pc_apply(B.s, B.sh);
     {
       Timed tm(prof, KC_APPLY_OP);
       launch_apply_soa(k, st, s1, pc_on ? 3 : 2, dm, dt, vk, vk32, vbeta, prm.alpha, adt, sh, B.rh, B.t, kpart,
-                       B.s);
+                       B.s, kx32);
     }
     {
       Timed tm(prof, KC_VECTOR);
       launch_bicg_xrp(st, n, apply_soa_blocks(hm.nc, s1.block), kpart, sc, B.s, B.t, B.v, ph, sh, B.x, B.r, B.p,
-                      part);
+                      part, kx32);
     }
   }
   launch_finish(st, part, kVecBlocks, bsc + (long)BS_STRIDE * (kBicgBlock - 1) + BS_RR);
@@ -971,10 +977,13 @@ int hdg_ctx::bicgstab(double adt, const double* b_aos, double* x_aos) {
   static_assert(BS_STRIDE * kBicgBlock <= kPinned, "pinned buffer holds a block of slots");
   const long n = nQ;
   const int maxit = prm.max_it_velocity;
-  const double rtol = prm.rtol_velocity;
+  // FP32 arithmetic cannot reach the tolerances of FP64: the mixed mode's
+  // Step I stops no tighter than kMixedRtolFloor (the FP64 Richardson
+  // residual of Algorithm 2 refines the stage)
+  const double rtol = kx32 ? std::max(prm.rtol_velocity, kMixedRtolFloor) : prm.rtol_velocity;
   double* open = bsc + (long)BS_STRIDE * kBicgBlock;  // slot opening the next block
-  launch_to_soa(k, st, dm, 0, b_aos, B.b);
-  launch_dot(st, n, B.b, nullptr, part);
+  launch_to_soa(k, st, dm, 0, b_aos, B.b, kx32);
+  launch_vdot(st, n, B.b, nullptr, part, kx32);
   launch_finish(st, part, kRedBlocks, bsc);
   const double bnorm = std::sqrt(read_scalar(bsc));
   if (!(bnorm == bnorm)) throw SolverBreakdown("BiCGStab: non-finite right-hand side");
@@ -993,27 +1002,28 @@ int hdg_ctx::bicgstab(double adt, const double* b_aos, double* x_aos) {
     }
     exec = &bicg_graphs[adt];
   }
-  launch_fill(st, n, 0.0, B.x);
+  launch_vfill(st, n, 0.0, B.x, kx32);
   int it = 0, restarts = 0;
   bool restart = true;
   while (true) {
     if (restart) {
       if (it == 0) {
-        launch_copy(st, n, B.b, B.r);
+        launch_vcopy(st, n, B.b, B.r, kx32);
       } else {  // true residual of the current iterate
         {
           Timed tm(prof, KC_APPLY_OP);
-          launch_apply_soa(k, st, s1, 0, dm, dt, vk, vk32, vbeta, prm.alpha, adt, B.x, nullptr, B.t, nullptr);
+          launch_apply_soa(k, st, s1, 0, dm, dt, vk, vk32, vbeta, prm.alpha, adt, B.x, nullptr, B.t, nullptr,
+                           nullptr, kx32);
         }
-        launch_copy(st, n, B.b, B.r);
-        launch_axpby(st, n, -1.0, B.t, 1.0, B.r);
+        launch_vcopy(st, n, B.b, B.r, kx32);
+        launch_vaxpby(st, n, -1.0, B.t, 1.0, B.r, kx32);
         ++bicg_restarts;
         if (++restarts > 50) throw SolverBreakdown("BiCGStab: too many restarts");
       }
-      launch_copy(st, n, B.r, B.p);
-      launch_copy(st, n, B.r, B.rh);
+      launch_vcopy(st, n, B.r, B.p, kx32);
+      launch_vcopy(st, n, B.r, B.rh, kx32);
       launch_bicg_init(st, open);
-      launch_dot(st, n, B.rh, nullptr, part);
+      launch_vdot(st, n, B.rh, nullptr, part, kx32);
       launch_finish(st, part, kRedBlocks, open + BS_RHO);
       KCHK();
       restart = false;
@@ -1034,12 +1044,13 @@ int hdg_ctx::bicgstab(double adt, const double* b_aos, double* x_aos) {
       // (in B.r from here on); more than 10 rtol away continues from it
       {
         Timed tm(prof, KC_APPLY_OP);
-        launch_apply_soa(k, st, s1, 0, dm, dt, vk, vk32, vbeta, prm.alpha, adt, B.x, nullptr, B.t, nullptr);
+        launch_apply_soa(k, st, s1, 0, dm, dt, vk, vk32, vbeta, prm.alpha, adt, B.x, nullptr, B.t, nullptr,
+                         nullptr, kx32);
       }
-      launch_copy(st, n, B.b, B.r);
-      launch_axpby(st, n, -1.0, B.t, 1.0, B.r);
+      launch_vcopy(st, n, B.b, B.r, kx32);
+      launch_vaxpby(st, n, -1.0, B.t, 1.0, B.r, kx32);
       double* tslot = bsc + (long)BS_STRIDE * (kBicgBlock + 1);
-      launch_dot(st, n, B.r, nullptr, part);
+      launch_vdot(st, n, B.r, nullptr, part, kx32);
       launch_finish(st, part, kRedBlocks, tslot);
       const double tr = std::sqrt(read_scalar(tslot)) / bnorm;
       if (!(tr == tr)) throw SolverBreakdown("BiCGStab: non-finite true residual");
@@ -1064,7 +1075,7 @@ int hdg_ctx::bicgstab(double adt, const double* b_aos, double* x_aos) {
     for (int b = 0; b < kBicgBlock; ++b) flag |= h_pinned[BS_STRIDE * b + BS_FLAG] != 0.0;
     if (flag) restart = true;
   }
-  launch_to_aos(k, st, dm, B.x, x_aos);
+  launch_to_aos(k, st, dm, B.x, x_aos, kx32);
   KCHK();
   return it;
 }
@@ -1551,13 +1562,16 @@ static void estimate_footprint(const hdg::HostMesh& m, const hdg::RefTables& rt,
     b += 8.0 * v->size();
   // work vectors: cell duals, trace vectors, Krylov and stage vectors
   b += 8.0 * (nc * nlam + nT * (12 + s) + nQ * (18 + 2 * s) + nP * (3 + s));
+  const bool x32 = prm.precision == HDG_MIXED;  // the 8 Step I Krylov vectors in FP32
+  if (x32) b -= 4.0 * 8 * nQ;
   b += 8.0 * ((double)kRedBlocks * kIdrMax + 2.0 * kRedBlocks + 3.0 * (prm.max_it_trace + 4) + 16 +
               (double)BS_STRIDE * std::max(prm.max_it_velocity + 6, 10) + 2 * (4 * blocks + 16));
   // Step I data: cell matrices, upwind weights, residual-kernel advection data
-  b += ns * ns * nc32 * (prm.precision == HDG_MIXED ? 4.0 : 8.0) + 8.0 * 3 * nqf * nc32 + 8.0 * nc * (2 * nqc + 3 * nqf);
+  b += ns * ns * nc32 * (x32 ? 4.0 : 8.0) + (x32 ? 4.0 : 8.0) * 3 * nqf * nc32 + 8.0 * nc * (2 * nqc + 3 * nqf);
   if (prm.idr_s > 0) b += 8.0 * (3.0 * prm.idr_s * nQ + kIdrMax + 8);
   // Step I preconditioner: two direction vectors, the cell blocks and the patch inverses
-  if (prm.step1_precond == 1 && prm.idr_s == 0) b += 8.0 * (2 * nQ + nc * nu * nu) + 2.0 * (double)pc_entries(rt.k, (long)m.nc);
+  if (prm.step1_precond == 1 && prm.idr_s == 0)
+    b += (x32 ? 4.0 : 8.0) * 2 * nQ + 8.0 * nc * nu * nu + 2.0 * (double)pc_entries(rt.k, (long)m.nc);
   // trace operators
   std::set<double> cs = {1.0, tab.bim[tab.s - 1] * dtv};
   for (int i = 1; i < tab.s; ++i) cs.insert(tab.Aim[i][i] * dtv);
@@ -2079,9 +2093,9 @@ int hdg_step1_precond(hdg_ctx* ctx, double adt, const double* Qsv, const double*
   API_BEGIN
   ctx->prepare_step1(Qsv);
   ctx->pc_prepare(adt);
-  launch_to_soa(ctx->k, ctx->st, ctx->dm, 0, r, ctx->kd.b);
+  launch_to_soa(ctx->k, ctx->st, ctx->dm, 0, r, ctx->kd.b, ctx->kx32);
   ctx->pc_apply(ctx->kd.b, ctx->kd.x);
-  launch_to_aos(ctx->k, ctx->st, ctx->dm, ctx->kd.x, z);
+  launch_to_aos(ctx->k, ctx->st, ctx->dm, ctx->kd.x, z, ctx->kx32);
   KCHK();
   ctx->sync();
   API_END(ctx)

@@ -92,8 +92,9 @@ void launch_apply(int k, hipStream_t st, int mode, DMesh m, DTab t, const double
 // entries tiled that way (pair pi of row s as entry s*floor(ns/2) + pi, in
 // units of pairs), then, for odd ns, the last entry of every row tiled as
 // entry s of a second array that follows all pairs.
+// (beta FP32 when b32, else FP64)
 void launch_step1_matrix(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, void* V, bool v32,
-                         double* beta);
+                         void* beta, bool b32);
 // Launch shape of the Step I operator: threads per workgroup (64, 128 or
 // 256; two threads per cell) and the workgroup-to-XCD order (1: each XCD
 // takes a contiguous eighth of the cells, 0: hardware order).
@@ -105,10 +106,12 @@ struct Step1Launch {
 // out = x - (adt/det) f_im(x), with partial sums (apply_soa_blocks(nc, block)
 // per set): dot 0 none; dot 1 w.out; dot 2 out.x, out.out, w.x, w.out
 // (dot 3: as dot 2 with the dots taken against sd instead of x: out.sd,
-// out.out, w.sd, w.out; sd is ignored otherwise)
+// out.out, w.sd, w.out; sd is ignored otherwise).  x32: FP32 vectors, beta
+// and arithmetic (V FP32); else FP64 vectors, beta and arithmetic (V FP32
+// when v32).  Inner products accumulate in FP64 either way.
 void launch_apply_soa(int k, hipStream_t st, Step1Launch ln, int dot, DMesh m, DTab t, const void* V, bool v32,
-                      const double* beta, double alpha, double adt, const double* x, const double* w, double* out,
-                      double* part, const double* sd = nullptr);
+                      const void* beta, double alpha, double adt, const void* x, const void* w, void* out,
+                      double* part, const void* sd, bool x32);
 int apply_soa_blocks(long nc, int block);
 // BiCGStab pieces (slot sc of BS_STRIDE scalars):
 //   v = A p: launch_apply_soa dot 1 with rh (np partials in part)
@@ -116,11 +119,11 @@ int apply_soa_blocks(long nc, int block);
 //   t = A s: launch_apply_soa dot 2 with rh (4 sets of np partials in part2)
 //   x, r, p updates, omega and beta from part2, partials of r.r
 //   (kVecBlocks of them) in part: launch_bicg_xrp
-void launch_bicg_s(hipStream_t st, long n, int np, const double* part, double* sc, const double* r, const double* v,
-                   double* s);
-void launch_bicg_xrp(hipStream_t st, long n, int np, const double* part2, double* sc, const double* s,
-                     const double* tv, const double* v, const double* ph, const double* sh, double* x, double* r,
-                     double* p, double* part);
+void launch_bicg_s(hipStream_t st, long n, int np, const double* part, double* sc, const void* r, const void* v,
+                   void* s, bool x32);
+void launch_bicg_xrp(hipStream_t st, long n, int np, const double* part2, double* sc, const void* s, const void* tv,
+                     const void* v, const void* ph, const void* sh, void* x, void* r, void* p, double* part,
+                     bool x32);
 void launch_bicg_init(hipStream_t st, double* sc);  // zero a slot except BS_RHO
 // Step I preconditioner: additive Schwarz over facet patches (two cells per
 // interior facet) of the mass-scaled Step I operator.  launch_pc_build forms
@@ -129,10 +132,16 @@ void launch_bicg_init(hipStream_t st, double* sc);  // zero a slot except BS_RHO
 // gives z = B r on structure-of-arrays vectors.
 void launch_pc_build(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, double alpha,
                      double adt, double* D, void* Binv);
-void launch_pc_apply(int k, hipStream_t st, DMesh m, const void* Binv, const double* r, double* z);
+void launch_pc_apply(int k, hipStream_t st, DMesh m, const void* Binv, const void* r, void* z, bool x32);
 long pc_entries(int k, long nc);
-void launch_to_soa(int k, hipStream_t st, DMesh m, int inv_det, const double* x, double* y);
-void launch_to_aos(int k, hipStream_t st, DMesh m, const double* x, double* y);
+void launch_to_soa(int k, hipStream_t st, DMesh m, int inv_det, const double* x, void* y, bool x32);
+void launch_to_aos(int k, hipStream_t st, DMesh m, const void* x, double* y, bool x32);
+// Step I vectors in either type (x32: FP32): copy, fill, a x + b y, and FP64
+// partials of a.b (b null: a.a) over kRedBlocks blocks for launch_finish
+void launch_vcopy(hipStream_t st, long n, const void* x, void* y, bool x32);
+void launch_vfill(hipStream_t st, long n, double v, void* y, bool x32);
+void launch_vaxpby(hipStream_t st, long n, double a, const void* x, double b, void* y, bool x32);
+void launch_vdot(hipStream_t st, long n, const void* a, const void* b, double* part, bool x32);
 void launch_div(int k, hipStream_t st, DMesh m, DTab t, const double* F, double scale, double* out);
 void launch_bdm(int k, hipStream_t st, DMesh m, DTab t, const double* Q, double* Qs);
 // f_p data of the pressure reconstruction: (Q.grad)Q - fsc f, f at the cell

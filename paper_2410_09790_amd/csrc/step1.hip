@@ -17,6 +17,9 @@ __device__ __forceinline__ double pair_swap(double v) {
   const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0xB1, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
+__device__ __forceinline__ float pair_swap(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
 
 // Per-cell data of the Step I operator are stored in tiles of 32 cells
 // (one wave of the two-threads-per-cell kernels): entry j of cell e sits at
@@ -93,10 +96,11 @@ __global__ void __launch_bounds__(kBlock) k_step1_matrix(DMesh m, DTab t, const 
 
 // Upwind weights of the Step I facet term at the facet points, for the Q*
 // of a stage: beta = w_q h (Q*.n/2 - delta_up |Q*.n|) on interior facets,
-// 0 on walls, entry f*NQF + q in tiles.  One thread per (cell, facet).
-template <int K>
+// 0 on walls, entry f*NQF + q in tiles, stored as TB (the operator's
+// arithmetic type).  One thread per (cell, facet).
+template <int K, typename TB>
 __global__ void __launch_bounds__(kBlock) k_step1_beta(DMesh m, DTab t, const double* __restrict__ Qs,
-                                                       double delta_up, double* __restrict__ beta) {
+                                                       double delta_up, TB* __restrict__ beta) {
   using D = Dims<K>;
   constexpr int NS = D::NS, NU = D::NU, NQF = D::NQF;
   const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -114,7 +118,7 @@ __global__ void __launch_bounds__(kBlock) k_step1_beta(DMesh m, DTab t, const do
       vy += b * Qs[(long)e * NU + NS + s];
     }
     const double qn = vx * nx + vy * ny;
-    beta[tile_idx(e, f * NQF + qq, 3 * NQF)] = inner ? t.fw[qq] * h * (0.5 * qn - delta_up * fabs(qn)) : 0.0;
+    beta[tile_idx(e, f * NQF + qq, 3 * NQF)] = (TB)(inner ? t.fw[qq] * h * (0.5 * qn - delta_up * fabs(qn)) : 0.0);
   }
 }
 
@@ -128,12 +132,14 @@ __global__ void __launch_bounds__(kBlock) k_step1_beta(DMesh m, DTab t, const do
 // component) exchange their components of the jump with pair_swap.  y
 // receives the result in reference scaling (the caller multiplies by
 // adt/det).  The neighbour's input value at structure-of-arrays index idx
-// is nb(idx); sFBu is the facet trace table staged in LDS.
-template <int K, typename TV, typename NbVal>
-__device__ __forceinline__ void step1_core(const DMesh& m, const DTab& t, const double* sFBu,
-                                           const TV* __restrict__ V, const double* __restrict__ beta, long nc,
-                                           int e, int c, double alpha, const double (&xv)[Dims<K>::NS],
-                                           double (&y)[Dims<K>::NS], const NbVal& nb) {
+// is nb(idx); sFBu is the facet trace table staged in LDS.  TC is the
+// arithmetic type (FP64, or FP32 in the mixed-precision mode), TV the
+// storage type of the cell matrices.
+template <int K, typename TV, typename TC, typename NbVal>
+__device__ __forceinline__ void step1_core(const DMesh& m, const DTab& t, const TC* sFBu,
+                                           const TV* __restrict__ V, const TC* __restrict__ beta, long nc,
+                                           int e, int c, TC alpha, const TC (&xv)[Dims<K>::NS],
+                                           TC (&y)[Dims<K>::NS], const NbVal& nb) {
   using D = Dims<K>;
   constexpr int NS = D::NS, NQF = D::NQF;
   // volume: the two lanes of a cell split the rows of V (lane c takes rows
@@ -145,28 +151,28 @@ __device__ __forceinline__ void step1_core(const DMesh& m, const DTab& t, const 
   {
     using TV2 = typename Pair2<TV>::T;
     const long vtail = VPairs<K>::tail(nc);
-    double xo[NS];
+    TC xo[NS];
 #pragma unroll
     for (int i = 0; i < NS; ++i) xo[i] = pair_swap(xv[i]);
 #pragma unroll
     for (int r = 0; r < (NS + 1) / 2; ++r) {
       const int s = 2 * r + c < NS ? 2 * r + c : NS - 1;
-      double am = 0.0, ao = 0.0;
+      TC am = 0, ao = 0;
       const TV2* V2 = reinterpret_cast<const TV2*>(V);
 #pragma unroll
       for (int pi = 0; pi < VPairs<K>::NP2; ++pi) {
         const TV2 v = __builtin_nontemporal_load(&V2[VPairs<K>::pair(e, s, pi)]);
-        am += (double)v.x * xv[2 * pi];
-        ao += (double)v.x * xo[2 * pi];
-        am += (double)v.y * xv[2 * pi + 1];
-        ao += (double)v.y * xo[2 * pi + 1];
+        am += (TC)v.x * xv[2 * pi];
+        ao += (TC)v.x * xo[2 * pi];
+        am += (TC)v.y * xv[2 * pi + 1];
+        ao += (TC)v.y * xo[2 * pi + 1];
       }
       if constexpr (NS & 1) {
-        const double v = (double)__builtin_nontemporal_load(&V[vtail + tile_idx(e, s, NS)]);
+        const TC v = (TC)__builtin_nontemporal_load(&V[vtail + tile_idx(e, s, NS)]);
         am += v * xv[NS - 1];
         ao += v * xo[NS - 1];
       }
-      const double recv = pair_swap(ao);
+      const TC recv = pair_swap(ao);
       if (2 * r + 1 < NS) {
         y[2 * r] = c ? recv : am;
         y[2 * r + 1] = c ? am : recv;
@@ -183,9 +189,9 @@ __device__ __forceinline__ void step1_core(const DMesh& m, const DTab& t, const 
     const int en = nbx[f] >= 0 ? nbx[f] >> 3 : -1;
     const int fn = nbx[f] >= 0 ? (nbx[f] >> 1) & 3 : 0;
     const int rev = nbx[f] >= 0 ? nbx[f] & 1 : 0;
-    const double nx = m.geo[(D_NX0 + 2 * f) * nc + e], ny = m.geo[(D_NY0 + 2 * f) * nc + e];
-    const double ncomp = c ? ny : nx;
-    double xn[NS], bq[NQF];
+    const TC nx = (TC)m.geo[(D_NX0 + 2 * f) * nc + e], ny = (TC)m.geo[(D_NY0 + 2 * f) * nc + e];
+    const TC ncomp = c ? ny : nx;
+    TC xn[NS], bq[NQF];
 #pragma unroll
     for (int qq = 0; qq < NQF; ++qq) bq[qq] = __builtin_nontemporal_load(&beta[tile_idx(e, f * NQF + qq, 3 * NQF)]);
     if (en >= 0) {
@@ -193,23 +199,23 @@ __device__ __forceinline__ void step1_core(const DMesh& m, const DTab& t, const 
       for (int s = 0; s < NS; ++s) xn[s] = nb((long)(c * NS + s) * nc + en);
     } else {
 #pragma unroll
-      for (int s = 0; s < NS; ++s) xn[s] = 0.0;
+      for (int s = 0; s < NS; ++s) xn[s] = 0;
     }
 #pragma unroll
     for (int qq = 0; qq < NQF; ++qq) {
       const int qn = rev ? NQF - 1 - qq : qq;
-      double j = 0.0, jn = 0.0;
+      TC j = 0, jn = 0;
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        j += t.FBu[(f * NQF + qq) * NS + s] * xv[s];
+        j += (TC)t.FBu[(f * NQF + qq) * NS + s] * xv[s];
         jn += sFBu[(fn * NQF + qn) * NS + s] * xn[s];
       }
       j -= jn;
-      const double jo = pair_swap(j);
-      const double jdotn = c ? (jo * nx + j * ny) : (j * nx + jo * ny);
-      const double con = bq[qq] * j - alpha * t.fw[qq] * jdotn * ncomp;
+      const TC jo = pair_swap(j);
+      const TC jdotn = c ? (jo * nx + j * ny) : (j * nx + jo * ny);
+      const TC con = bq[qq] * j - alpha * (TC)t.fw[qq] * jdotn * ncomp;
 #pragma unroll
-      for (int s = 0; s < NS; ++s) y[s] += t.FBu[(f * NQF + qq) * NS + s] * con;
+      for (int s = 0; s < NS; ++s) y[s] += (TC)t.FBu[(f * NQF + qq) * NS + s] * con;
     }
   }
 }
@@ -234,10 +240,10 @@ __device__ __forceinline__ int xcd_block() {
 
 // Stage the facet trace table in LDS: the neighbour's table row is indexed
 // by the neighbour's local facet and orientation, which differ between lanes.
-template <int K>
-__device__ __forceinline__ void stage_fbu(const DTab& t, double* sFBu) {
+template <int K, typename TC>
+__device__ __forceinline__ void stage_fbu(const DTab& t, TC* sFBu) {
   constexpr int N = 3 * Dims<K>::NQF * Dims<K>::NS;
-  for (int i = threadIdx.x; i < N; i += blockDim.x) sFBu[i] = t.FBu[i];
+  for (int i = threadIdx.x; i < N; i += blockDim.x) sFBu[i] = (TC)t.FBu[i];
   __syncthreads();
 }
 
@@ -250,39 +256,41 @@ __device__ __forceinline__ void stage_fbu(const DTab& t, double* sFBu) {
 // In BiCGStab, DOT 1 gives rh.v for v = A p and DOT 2 gives t.s, t.t, rh.s,
 // rh.t for t = A s.  BS threads per workgroup (64, 128 or 256); xcd = 1 deals
 // the cells to the XCDs in contiguous eighths (xcd_block), 0 keeps the
-// hardware order.
-template <int K, int DOT, typename TV, int BS>
+// hardware order.  TX: the vectors' type and the arithmetic type (FP64, or
+// FP32 in the mixed-precision mode); the inner products accumulate in FP64.
+template <int K, int DOT, typename TV, int BS, typename TX>
 __global__ void __launch_bounds__(BS, kStep1Waves) k_apply_soa(DMesh m, DTab t, const TV* __restrict__ V,
-                                                               const double* __restrict__ beta, double alpha,
-                                                               double adt, const double* __restrict__ x,
-                                                               const double* __restrict__ w,
-                                                               const double* __restrict__ sd,
-                                                               double* __restrict__ out,
+                                                               const TX* __restrict__ beta, double alpha,
+                                                               double adt, const TX* __restrict__ x,
+                                                               const TX* __restrict__ w,
+                                                               const TX* __restrict__ sd,
+                                                               TX* __restrict__ out,
                                                                double* __restrict__ part, int xcd) {
   using D = Dims<K>;
   constexpr int NS = D::NS;
-  __shared__ double sFBu[3 * D::NQF * NS];
-  stage_fbu<K>(t, sFBu);
+  __shared__ TX sFBu[3 * D::NQF * NS];
+  stage_fbu<K, TX>(t, sFBu);
   const int blk = xcd ? xcd_block() : (int)blockIdx.x;
   const long tid = (long)blk * BS + threadIdx.x;
   const long nc = m.nc;
   const int e = (int)(tid >> 1), c = (int)(tid & 1);
   double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
   if (e < nc) {
-    double xv[NS], y[NS];
+    TX xv[NS], y[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) xv[s] = x[(long)(c * NS + s) * nc + e];
-    step1_core<K, TV>(m, t, sFBu, V, beta, nc, e, c, alpha, xv, y, [&](long i) { return x[i]; });
-    const double sc = adt / m.geo[D_DET * nc + e];
+    step1_core<K, TV, TX>(m, t, sFBu, V, beta, nc, e, c, (TX)alpha, xv, y, [&](long i) { return x[i]; });
+    const TX sc = (TX)(adt / m.geo[D_DET * nc + e]);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const long idx = (long)(c * NS + s) * nc + e;
-      const double o = xv[s] - sc * y[s];
-      out[idx] = o;
-      if (DOT == 1) d0 += w[idx] * o;
+      const TX ot = xv[s] - sc * y[s];
+      out[idx] = ot;
+      const double o = ot;
+      if (DOT == 1) d0 += (double)w[idx] * o;
       if (DOT >= 2) {
         const double wv = w[idx];
-        const double sv = DOT == 3 ? sd[idx] : xv[s];
+        const double sv = DOT == 3 ? (double)sd[idx] : (double)xv[s];
         d0 += o * sv;
         d1 += o * o;
         d2 += wv * sv;
@@ -330,20 +338,30 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
 //                           next slot; partials of r.r
 // Both vector kernels run on a fixed grid of kVecBlocks blocks, so the
 // redundant finishes read few partials in total.
+// Vectors of type TX (FP64, or FP32 in the mixed-precision mode) accessed as
+// pairs (n is even: 2 ns entries per cell and component pair); the
+// coefficients are FP64 and so are the inner-product partials.
+template <typename TX> struct VPair2;
+template <> struct VPair2<double> { using T = f64x2; };
+template <> struct VPair2<float> { using T = f32x2; };
+template <typename TX>
 __global__ void __launch_bounds__(kBlock) k_bicg_s(long n, int np, const double* __restrict__ part,
-                                                   double* __restrict__ sc, const double* __restrict__ R,
-                                                   const double* __restrict__ Vv, double* __restrict__ S) {
+                                                   double* __restrict__ sc, const TX* __restrict__ R,
+                                                   const TX* __restrict__ Vv, TX* __restrict__ S) {
+  using T2 = typename VPair2<TX>::T;
   const double rv = sum_partials(part, np);
   const bool ok = rv != 0.0 && rv == rv;
   const double al = ok ? sc[BS_RHO] / rv : 0.0;
-  // n is even (2 ns doubles per cell and component pair): 16-byte accesses
   const long n2 = n >> 1;
-  const double2* R2 = reinterpret_cast<const double2*>(R);
-  const double2* V2 = reinterpret_cast<const double2*>(Vv);
-  double2* S2 = reinterpret_cast<double2*>(S);
+  const T2* R2 = reinterpret_cast<const T2*>(R);
+  const T2* V2 = reinterpret_cast<const T2*>(Vv);
+  T2* S2 = reinterpret_cast<T2*>(S);
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (long)gridDim.x * blockDim.x) {
-    const double2 r = R2[i], v = V2[i];
-    S2[i] = make_double2(r.x - al * v.x, r.y - al * v.y);
+    const T2 r = R2[i], v = V2[i];
+    T2 o;
+    o.x = (TX)((double)r.x - al * (double)v.x);
+    o.y = (TX)((double)r.y - al * (double)v.y);
+    S2[i] = o;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc[BS_RV] = rv;
@@ -352,12 +370,14 @@ __global__ void __launch_bounds__(kBlock) k_bicg_s(long n, int np, const double*
   }
 }
 
+template <typename TX>
 __global__ void __launch_bounds__(kBlock) k_bicg_xrp(long n, int np, const double* __restrict__ part2,
-                                                     double* __restrict__ sc, const double* __restrict__ S,
-                                                     const double* __restrict__ Tv, const double* __restrict__ Vv,
-                                                     const double* __restrict__ PH, const double* __restrict__ SH,
-                                                     double* __restrict__ X, double* __restrict__ R,
-                                                     double* __restrict__ P, double* __restrict__ part) {
+                                                     double* __restrict__ sc, const TX* __restrict__ S,
+                                                     const TX* __restrict__ Tv, const TX* __restrict__ Vv,
+                                                     const TX* __restrict__ PH, const TX* __restrict__ SH,
+                                                     TX* __restrict__ X, TX* __restrict__ R,
+                                                     TX* __restrict__ P, double* __restrict__ part) {
+  using T2 = typename VPair2<TX>::T;
   // omega = t.s / t.t, rho_next = rh.s - omega rh.t (= rh.r_next),
   // beta = (rho_next / rho)(alpha / omega)
   const double ts = sum_partials(part2, np);
@@ -371,20 +391,25 @@ __global__ void __launch_bounds__(kBlock) k_bicg_xrp(long n, int np, const doubl
   const bool okb = okw && rho != 0.0 && rho_next == rho_next;
   const double be = okb ? (rho_next / rho) * (al / om) : 0.0;
   double rr = 0.0;
-  const long n2 = n >> 1;  // n is even: 16-byte accesses
+  const long n2 = n >> 1;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (long)gridDim.x * blockDim.x) {
-    const double2 p = reinterpret_cast<const double2*>(P)[i], s = reinterpret_cast<const double2*>(S)[i];
-    const double2 t = reinterpret_cast<const double2*>(Tv)[i], v = reinterpret_cast<const double2*>(Vv)[i];
+    const T2 p = reinterpret_cast<const T2*>(P)[i], s = reinterpret_cast<const T2*>(S)[i];
+    const T2 t = reinterpret_cast<const T2*>(Tv)[i], v = reinterpret_cast<const T2*>(Vv)[i];
     // the iterate moves along the preconditioned directions (PH = P, SH = S without a preconditioner)
-    const double2 ph = reinterpret_cast<const double2*>(PH)[i], sh = reinterpret_cast<const double2*>(SH)[i];
-    double2 x = reinterpret_cast<const double2*>(X)[i];
-    x.x += al * ph.x + om * sh.x;
-    x.y += al * ph.y + om * sh.y;
-    reinterpret_cast<double2*>(X)[i] = x;
-    const double2 r = make_double2(s.x - om * t.x, s.y - om * t.y);
-    reinterpret_cast<double2*>(R)[i] = r;
-    rr += r.x * r.x + r.y * r.y;
-    reinterpret_cast<double2*>(P)[i] = make_double2(r.x + be * (p.x - om * v.x), r.y + be * (p.y - om * v.y));
+    const T2 ph = reinterpret_cast<const T2*>(PH)[i], sh = reinterpret_cast<const T2*>(SH)[i];
+    T2 x = reinterpret_cast<const T2*>(X)[i];
+    x.x = (TX)((double)x.x + (al * (double)ph.x + om * (double)sh.x));
+    x.y = (TX)((double)x.y + (al * (double)ph.y + om * (double)sh.y));
+    reinterpret_cast<T2*>(X)[i] = x;
+    T2 r;
+    r.x = (TX)((double)s.x - om * (double)t.x);
+    r.y = (TX)((double)s.y - om * (double)t.y);
+    reinterpret_cast<T2*>(R)[i] = r;
+    rr += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
+    T2 pn;
+    pn.x = (TX)((double)r.x + be * ((double)p.x - om * (double)v.x));
+    pn.y = (TX)((double)r.y + be * ((double)p.y - om * (double)v.y));
+    reinterpret_cast<T2*>(P)[i] = pn;
   }
   rr = block_sum(rr);
   if (threadIdx.x == 0) part[blockIdx.x] = rr;
@@ -405,22 +430,50 @@ __global__ void k_bicg_init(double* __restrict__ sc) {
 }
 
 // AoS [cell][2 ns] <-> SoA [(c ns + s) nc + cell]; inv_det = 1 also divides by det J
-template <int K>
-__global__ void k_to_soa(DMesh m, int inv_det, const double* __restrict__ x, double* __restrict__ y) {
+template <int K, typename TX>
+__global__ void k_to_soa(DMesh m, int inv_det, const double* __restrict__ x, TX* __restrict__ y) {
   constexpr int NU = Dims<K>::NU;
   const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= (long)m.nc * NU) return;
   const long e = tid % m.nc, i = tid / m.nc;
   const double sc = inv_det ? 1.0 / m.geo[D_DET * (long)m.nc + e] : 1.0;
-  y[tid] = sc * x[e * NU + i];
+  y[tid] = (TX)(sc * x[e * NU + i]);
 }
-template <int K>
-__global__ void k_to_aos(DMesh m, const double* __restrict__ x, double* __restrict__ y) {
+template <int K, typename TX>
+__global__ void k_to_aos(DMesh m, const TX* __restrict__ x, double* __restrict__ y) {
   constexpr int NU = Dims<K>::NU;
   const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= (long)m.nc * NU) return;
   const long e = tid / NU, i = tid % NU;
-  y[tid] = x[i * m.nc + e];
+  y[tid] = (double)x[i * m.nc + e];
+}
+
+// Generic vector pieces of the Step I solve in either vector type: y = x,
+// y = v, y = a x + b y, and FP64 partial sums of a.b (b null: a.a) over
+// kRedBlocks blocks.
+template <typename TX>
+__global__ void k_vcopy(long n, const TX* __restrict__ x, TX* __restrict__ y) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i];
+}
+template <typename TX>
+__global__ void k_vfill(long n, double v, TX* __restrict__ y) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (TX)v;
+}
+template <typename TX>
+__global__ void k_vaxpby(long n, double a, const TX* __restrict__ x, double b, TX* __restrict__ y) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (TX)(a * (double)x[i] + b * (double)y[i]);
+}
+template <typename TX>
+__global__ void __launch_bounds__(kBlock) k_vdot(long n, const TX* __restrict__ a, const TX* __restrict__ b,
+                                                 double* __restrict__ part) {
+  double v = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    v += (double)a[i] * (double)(b ? b[i] : a[i]);
+  v = block_sum(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
 }
 
 // ======================================================= Step I preconditioner
@@ -675,9 +728,9 @@ struct PcApplyShape {
   static constexpr int RG = NU / G;
   static_assert(RG * G == NU, "rows split evenly");
 };
-template <int K>
+template <int K, typename TX>
 __global__ void __launch_bounds__(kBlock) k_pc_apply(DMesh m, const pc_t* __restrict__ Binv,
-                                                     const double* __restrict__ r, double* __restrict__ z) {
+                                                     const TX* __restrict__ r, TX* __restrict__ z) {
   using Sh = PcApplyShape<K>;
   constexpr int NU = Dims<K>::NU, NQ = PcLayout<K>::NQ, G = Sh::G, RG = Sh::RG;
   const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -720,69 +773,108 @@ __global__ void __launch_bounds__(kBlock) k_pc_apply(DMesh m, const pc_t* __rest
     }
   }
 #pragma unroll
-  for (int a = 0; a < RG; ++a) z[(long)(g * RG + a) * nc + e] = acc[a];
+  for (int a = 0; a < RG; ++a) z[(long)(g * RG + a) * nc + e] = (TX)acc[a];
 }
 
 // ============================================================== launchers
 void launch_step1_matrix(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, void* V, bool v32,
-                         double* beta) {
+                         void* beta, bool b32) {
   const int nb = nblocks((long)m.nc * (k + 2) * (k + 3) / 2);
   if (v32) {
     HDG_DISPATCH(k, (k_step1_matrix<KK, float><<<nb, kBlock, 0, st>>>(m, t, Qs, (float*)V)));
   } else {
     HDG_DISPATCH(k, (k_step1_matrix<KK, double><<<nb, kBlock, 0, st>>>(m, t, Qs, (double*)V)));
   }
-  HDG_DISPATCH(k, (k_step1_beta<KK><<<nblocks(3L * m.nc), kBlock, 0, st>>>(m, t, Qs, delta_up, beta)));
-}
-template <int DOT, typename TV, int BS>
-static void apply_soa_bs(int k, hipStream_t st, DMesh m, DTab t, const TV* V, const double* beta, double alpha,
-                         double adt, const double* x, const double* w, const double* sd, double* out, double* part,
-                         int xcd) {
-  const int nb = apply_soa_blocks(m.nc, BS);
-  HDG_DISPATCH(k, (k_apply_soa<KK, DOT, TV, BS><<<nb, BS, 0, st>>>(m, t, V, beta, alpha, adt, x, w, sd, out, part,
-                                                                   xcd)));
-}
-template <int DOT, typename TV>
-static void apply_soa_d(int k, hipStream_t st, Step1Launch ln, DMesh m, DTab t, const TV* V, const double* beta,
-                        double alpha, double adt, const double* x, const double* w, const double* sd, double* out,
-                        double* part) {
-  switch (ln.block) {
-    case 64: apply_soa_bs<DOT, TV, 64>(k, st, m, t, V, beta, alpha, adt, x, w, sd, out, part, ln.xcd); break;
-    case 128: apply_soa_bs<DOT, TV, 128>(k, st, m, t, V, beta, alpha, adt, x, w, sd, out, part, ln.xcd); break;
-    default: apply_soa_bs<DOT, TV, 256>(k, st, m, t, V, beta, alpha, adt, x, w, sd, out, part, ln.xcd); break;
+  if (b32) {
+    HDG_DISPATCH(k, (k_step1_beta<KK, float><<<nblocks(3L * m.nc), kBlock, 0, st>>>(m, t, Qs, delta_up, (float*)beta)));
+  } else {
+    HDG_DISPATCH(k, (k_step1_beta<KK, double><<<nblocks(3L * m.nc), kBlock, 0, st>>>(m, t, Qs, delta_up,
+                                                                                    (double*)beta)));
   }
 }
-template <typename TV>
-static void apply_soa_t(int k, hipStream_t st, Step1Launch ln, int dot, DMesh m, DTab t, const TV* V,
-                        const double* beta, double alpha, double adt, const double* x, const double* w,
-                        const double* sd, double* out, double* part) {
-  if (dot == 0) apply_soa_d<0, TV>(k, st, ln, m, t, V, beta, alpha, adt, x, w, sd, out, part);
-  else if (dot == 1) apply_soa_d<1, TV>(k, st, ln, m, t, V, beta, alpha, adt, x, w, sd, out, part);
-  else if (dot == 2) apply_soa_d<2, TV>(k, st, ln, m, t, V, beta, alpha, adt, x, w, sd, out, part);
-  else apply_soa_d<3, TV>(k, st, ln, m, t, V, beta, alpha, adt, x, w, sd, out, part);
+template <int DOT, typename TV, typename TX, int BS>
+static void apply_soa_bs(int k, hipStream_t st, DMesh m, DTab t, const TV* V, const TX* beta, double alpha,
+                         double adt, const TX* x, const TX* w, const TX* sd, TX* out, double* part, int xcd) {
+  const int nb = apply_soa_blocks(m.nc, BS);
+  HDG_DISPATCH(k, (k_apply_soa<KK, DOT, TV, BS, TX><<<nb, BS, 0, st>>>(m, t, V, beta, alpha, adt, x, w, sd, out,
+                                                                       part, xcd)));
+}
+template <int DOT, typename TV, typename TX>
+static void apply_soa_d(int k, hipStream_t st, Step1Launch ln, DMesh m, DTab t, const TV* V, const TX* beta,
+                        double alpha, double adt, const TX* x, const TX* w, const TX* sd, TX* out, double* part) {
+  switch (ln.block) {
+    case 64: apply_soa_bs<DOT, TV, TX, 64>(k, st, m, t, V, beta, alpha, adt, x, w, sd, out, part, ln.xcd); break;
+    case 128: apply_soa_bs<DOT, TV, TX, 128>(k, st, m, t, V, beta, alpha, adt, x, w, sd, out, part, ln.xcd); break;
+    default: apply_soa_bs<DOT, TV, TX, 256>(k, st, m, t, V, beta, alpha, adt, x, w, sd, out, part, ln.xcd); break;
+  }
+}
+template <typename TV, typename TX>
+static void apply_soa_t(int k, hipStream_t st, Step1Launch ln, int dot, DMesh m, DTab t, const TV* V, const TX* beta,
+                        double alpha, double adt, const TX* x, const TX* w, const TX* sd, TX* out, double* part) {
+  if (dot == 0) apply_soa_d<0, TV, TX>(k, st, ln, m, t, V, beta, alpha, adt, x, w, sd, out, part);
+  else if (dot == 1) apply_soa_d<1, TV, TX>(k, st, ln, m, t, V, beta, alpha, adt, x, w, sd, out, part);
+  else if (dot == 2) apply_soa_d<2, TV, TX>(k, st, ln, m, t, V, beta, alpha, adt, x, w, sd, out, part);
+  else apply_soa_d<3, TV, TX>(k, st, ln, m, t, V, beta, alpha, adt, x, w, sd, out, part);
 }
 void launch_apply_soa(int k, hipStream_t st, Step1Launch ln, int dot, DMesh m, DTab t, const void* V, bool v32,
-                      const double* beta, double alpha, double adt, const double* x, const double* w, double* out,
-                      double* part, const double* sd) {
-  if (v32) apply_soa_t(k, st, ln, dot, m, t, (const float*)V, beta, alpha, adt, x, w, sd, out, part);
-  else apply_soa_t(k, st, ln, dot, m, t, (const double*)V, beta, alpha, adt, x, w, sd, out, part);
+                      const void* beta, double alpha, double adt, const void* x, const void* w, void* out,
+                      double* part, const void* sd, bool x32) {
+  if (x32) {  // FP32 vectors and arithmetic (the cell matrices are FP32 too)
+    apply_soa_t(k, st, ln, dot, m, t, (const float*)V, (const float*)beta, alpha, adt, (const float*)x,
+                (const float*)w, (const float*)sd, (float*)out, part);
+  } else if (v32) {
+    apply_soa_t(k, st, ln, dot, m, t, (const float*)V, (const double*)beta, alpha, adt, (const double*)x,
+                (const double*)w, (const double*)sd, (double*)out, part);
+  } else {
+    apply_soa_t(k, st, ln, dot, m, t, (const double*)V, (const double*)beta, alpha, adt, (const double*)x,
+                (const double*)w, (const double*)sd, (double*)out, part);
+  }
 }
 int apply_soa_blocks(long nc, int block) { return (int)((2L * nc + block - 1) / block); }
-void launch_bicg_s(hipStream_t st, long n, int np, const double* part, double* sc, const double* r, const double* v,
-                   double* s) {
-  k_bicg_s<<<kVecBlocks, kBlock, 0, st>>>(n, np, part, sc, r, v, s);
+void launch_bicg_s(hipStream_t st, long n, int np, const double* part, double* sc, const void* r, const void* v,
+                   void* s, bool x32) {
+  if (x32) k_bicg_s<float><<<kVecBlocks, kBlock, 0, st>>>(n, np, part, sc, (const float*)r, (const float*)v, (float*)s);
+  else k_bicg_s<double><<<kVecBlocks, kBlock, 0, st>>>(n, np, part, sc, (const double*)r, (const double*)v, (double*)s);
 }
-void launch_bicg_xrp(hipStream_t st, long n, int np, const double* part2, double* sc, const double* s,
-                     const double* tv, const double* v, const double* ph, const double* sh, double* x, double* r,
-                     double* p, double* part) {
-  k_bicg_xrp<<<kVecBlocks, kBlock, 0, st>>>(n, np, part2, sc, s, tv, v, ph, sh, x, r, p, part);
+void launch_bicg_xrp(hipStream_t st, long n, int np, const double* part2, double* sc, const void* s, const void* tv,
+                     const void* v, const void* ph, const void* sh, void* x, void* r, void* p, double* part,
+                     bool x32) {
+  if (x32) {
+    k_bicg_xrp<float><<<kVecBlocks, kBlock, 0, st>>>(n, np, part2, sc, (const float*)s, (const float*)tv,
+                                                     (const float*)v, (const float*)ph, (const float*)sh, (float*)x,
+                                                     (float*)r, (float*)p, part);
+  } else {
+    k_bicg_xrp<double><<<kVecBlocks, kBlock, 0, st>>>(n, np, part2, sc, (const double*)s, (const double*)tv,
+                                                      (const double*)v, (const double*)ph, (const double*)sh,
+                                                      (double*)x, (double*)r, (double*)p, part);
+  }
 }
 void launch_bicg_init(hipStream_t st, double* sc) { k_bicg_init<<<1, 64, 0, st>>>(sc); }
-void launch_to_soa(int k, hipStream_t st, DMesh m, int inv_det, const double* x, double* y) {
-  HDG_DISPATCH(k, (k_to_soa<KK><<<nblocks((long)m.nc * Dims<KK>::NU), kBlock, 0, st>>>(m, inv_det, x, y)));
+void launch_to_soa(int k, hipStream_t st, DMesh m, int inv_det, const double* x, void* y, bool x32) {
+  const int nb = nblocks((long)m.nc * (k + 2) * (k + 3));
+  if (x32) { HDG_DISPATCH(k, (k_to_soa<KK, float><<<nb, kBlock, 0, st>>>(m, inv_det, x, (float*)y))); }
+  else { HDG_DISPATCH(k, (k_to_soa<KK, double><<<nb, kBlock, 0, st>>>(m, inv_det, x, (double*)y))); }
 }
-void launch_to_aos(int k, hipStream_t st, DMesh m, const double* x, double* y) {
-  HDG_DISPATCH(k, (k_to_aos<KK><<<nblocks((long)m.nc * Dims<KK>::NU), kBlock, 0, st>>>(m, x, y)));
+void launch_to_aos(int k, hipStream_t st, DMesh m, const void* x, double* y, bool x32) {
+  const int nb = nblocks((long)m.nc * (k + 2) * (k + 3));
+  if (x32) { HDG_DISPATCH(k, (k_to_aos<KK, float><<<nb, kBlock, 0, st>>>(m, (const float*)x, y))); }
+  else { HDG_DISPATCH(k, (k_to_aos<KK, double><<<nb, kBlock, 0, st>>>(m, (const double*)x, y))); }
+}
+void launch_vcopy(hipStream_t st, long n, const void* x, void* y, bool x32) {
+  if (x32) k_vcopy<float><<<nblocks(n), kBlock, 0, st>>>(n, (const float*)x, (float*)y);
+  else k_vcopy<double><<<nblocks(n), kBlock, 0, st>>>(n, (const double*)x, (double*)y);
+}
+void launch_vfill(hipStream_t st, long n, double v, void* y, bool x32) {
+  if (x32) k_vfill<float><<<nblocks(n), kBlock, 0, st>>>(n, v, (float*)y);
+  else k_vfill<double><<<nblocks(n), kBlock, 0, st>>>(n, v, (double*)y);
+}
+void launch_vaxpby(hipStream_t st, long n, double a, const void* x, double b, void* y, bool x32) {
+  if (x32) k_vaxpby<float><<<nblocks(n), kBlock, 0, st>>>(n, a, (const float*)x, b, (float*)y);
+  else k_vaxpby<double><<<nblocks(n), kBlock, 0, st>>>(n, a, (const double*)x, b, (double*)y);
+}
+void launch_vdot(hipStream_t st, long n, const void* a, const void* b, double* part, bool x32) {
+  if (x32) k_vdot<float><<<kRedBlocks, kBlock, 0, st>>>(n, (const float*)a, (const float*)b, part);
+  else k_vdot<double><<<kRedBlocks, kBlock, 0, st>>>(n, (const double*)a, (const double*)b, part);
 }
 // Facet-patch preconditioner of the Step I operator for the Q* and adt of a
 // stage: cell blocks (D, FP64 scratch of nc*NU*NU doubles) then the patch
@@ -794,9 +886,14 @@ void launch_pc_build(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, d
   HDG_DISPATCH(k, (k_pc_patch<KK><<<m.nF, PcPatchShape<KK>::NT, 0, st>>>(m, t, Qs, delta_up, alpha, adt, D,
                                                                          (pc_t*)Binv)));
 }
-void launch_pc_apply(int k, hipStream_t st, DMesh m, const void* Binv, const double* r, double* z) {
-  HDG_DISPATCH(k, (k_pc_apply<KK><<<nblocks((long)(m.nc + 31) / 32 * 32 * PcApplyShape<KK>::G), kBlock, 0, st>>>(
-                      m, (const pc_t*)Binv, r, z)));
+void launch_pc_apply(int k, hipStream_t st, DMesh m, const void* Binv, const void* r, void* z, bool x32) {
+  if (x32) {
+    HDG_DISPATCH(k, (k_pc_apply<KK, float><<<nblocks((long)(m.nc + 31) / 32 * 32 * PcApplyShape<KK>::G), kBlock, 0,
+                                             st>>>(m, (const pc_t*)Binv, (const float*)r, (float*)z)));
+  } else {
+    HDG_DISPATCH(k, (k_pc_apply<KK, double><<<nblocks((long)(m.nc + 31) / 32 * 32 * PcApplyShape<KK>::G), kBlock, 0,
+                                              st>>>(m, (const pc_t*)Binv, (const double*)r, (double*)z)));
+  }
 }
 // per (cell, facet) slot: NU rows of 2 NU entries (own cell, then neighbour)
 long pc_entries(int k, long nc) {

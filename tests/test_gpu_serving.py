@@ -8,6 +8,8 @@
   size and degree admitted by footprint overlap on the device, never exceed
   the memory budget, and each result is the same alone and in the mix.
 """
+import time
+
 import numpy as np
 import pytest
 
@@ -98,7 +100,7 @@ def test_serving_same_alone_and_in_the_mix():
     from paper_2410_09790_amd import hdg
     fps = sorted(hdg.footprint_bytes(job.coords, job.cells, job.dt, **job.params) for job in jobs)
     budget = sum(fps[-3:])  # room for about three of the largest at once
-    srv = serve.Server(budget, slots=4)
+    srv = serve.Server(budget, workers=3, slots=4)
     for job in jobs:
         srv.submit(job)
     srv.drain(timeout=120)
@@ -109,8 +111,34 @@ def test_serving_same_alone_and_in_the_mix():
         for x, y in zip(res.state, ref):
             assert np.array_equal(x, y), res.job.name
     big = serve.Job(*mesh(16), _sf(0), 1e-3, 1, dict(degree=4))
-    r = serve.Server(fps[0] // 2, slots=1).submit(big)
+    small = serve.Server(fps[0] // 2, workers=1, slots=1)
+    r = small.submit(big)
     assert r.error is not None and "budget" in r.error
+    small.drain(timeout=10)
+
+
+def test_short_job_overtakes_a_long_one():
+    """Stage-granular shortest-remaining-work: a short job submitted while a
+    long one runs on the only worker finishes first, and both equal their
+    lone runs bit for bit."""
+    torch_or_skip()
+    from paper_2410_09790_amd import serve
+    X, C = mesh(16, 0.1, 1)
+    long_job = serve.Job(X, C, _sf(1), 1e-3, 12, dict(degree=3, imex="ars222", n_richardson=3), name="long")
+    Xs, Cs = mesh(4, 0.1, 2)
+    short_job = serve.Job(Xs, Cs, _sf(2), 1e-3, 2, dict(degree=1, imex="ars222", n_richardson=3), name="short")
+    alone = [serve.run_alone(j)[1] for j in (long_job, short_job)]
+    srv = serve.Server(8 << 30, workers=1, slots=4)
+    r_long = srv.submit(long_job)
+    while r_long.start == 0.0:  # the long job is on the worker
+        time.sleep(0.01)
+    r_short = srv.submit(short_job)
+    srv.drain(timeout=120)
+    assert r_short.end < r_long.end
+    for res, ref in zip((r_long, r_short), alone):
+        assert res.error is None, res.error
+        for x, y in zip(res.state, ref):
+            assert np.array_equal(x, y), res.job.name
 
 
 def test_batch_of_mixed_features():
