@@ -25,6 +25,14 @@ into n x n squares, each split into two right-angled triangles):
   square [0, 2 pi]^2 on the same n x n split-square mesh with the right/top
   vertices identified with the left/bottom ones, and the printed initial
   velocity with rho = pi/15, delta = 0.05.
+* three dimensions (the method is stated for d = 2 and 3; the paper computes
+  in 2D only): the unit cube cut into n^3 cubes of six tetrahedra each (the
+  Kuhn split: every tetrahedron of a cube contains its main diagonal from
+  the corner nearest the origin), and the initial velocity Q = curl A of the
+  vector potential A_c = sum_m a_cm sin(k1 pi x) sin(k2 pi y) sin(k3 pi z),
+  m = 1..4, drawn from default_rng(seed) per component c, per term, in the
+  order a_cm = standard_normal(), then k1, k2, k3 = integers(1, 3).  A
+  vanishes on the walls, so n.Q = 0 there.
 """
 from __future__ import annotations
 
@@ -46,6 +54,10 @@ __all__ = [
     "batched_instance",
     "serving_job",
     "serving_arrivals",
+    "unit_cube_mesh",
+    "random_cube_perturbation",
+    "vector_potential_params",
+    "curl_potential_velocity",
 ]
 
 
@@ -204,3 +216,84 @@ def taylor_green_pressure(x, y, t: float = 0.0, kappa: float = 0.5):
     """Mean-zero pressure that balances (Q.grad)Q for the Taylor-Green velocity."""
     a, b = _tg_angles(np.asarray(x, float), np.asarray(y, float))
     return -0.25 * np.exp(-2.0 * kappa * t) * (np.cos(2.0 * a) + np.cos(2.0 * b))
+
+
+def unit_cube_mesh(n: int):
+    """Kuhn split of [0, 1]^3: returns (coords float64[(n+1)^3, 3], cells
+    int32[6 n^3, 4]).
+
+    Vertex (i, j, l) has id (l*(n+1) + j)*(n+1) + i and coordinates
+    (i, j, l)/n.  Cube (i, j, l) gives the cells 6*((l*n + j)*n + i) + r,
+    r = 0..5, one per permutation (a, b, c) of the axes in lexicographic
+    order: the path corner, corner + e_a, corner + e_a + e_b, corner + 1 along
+    the cube's edges.  Each cell's last two vertices are swapped where needed
+    so that every cell is positively oriented.
+    """
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    m = n + 1
+    g = np.arange(n)
+    I, J, L = np.meshgrid(g, g, g, indexing="ij")
+    I, J, L = (a.transpose(2, 1, 0).ravel() for a in (I, J, L))  # i fastest
+    corner = np.stack([I, J, L], axis=1)
+    vid = lambda p: (p[:, 2] * m + p[:, 1]) * m + p[:, 0]
+    perms = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+    cells = np.empty((n ** 3, 6, 4), dtype=np.int64)
+    for r, perm in enumerate(perms):
+        p = corner.copy()
+        cells[:, r, 0] = vid(p)
+        for s, ax in enumerate(perm):
+            p = p.copy()
+            p[:, ax] += 1
+            cells[:, r, s + 1] = vid(p)
+        # the orientation of a path simplex is the sign of its permutation
+        odd = sum(1 for a in range(3) for b in range(a + 1, 3) if perm[a] > perm[b]) % 2
+        if odd:
+            cells[:, r, [2, 3]] = cells[:, r, [3, 2]]
+    gi, gj, gl = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")
+    coords = np.stack([gi.transpose(2, 1, 0).ravel(), gj.transpose(2, 1, 0).ravel(),
+                       gl.transpose(2, 1, 0).ravel()], axis=1) / n
+    return coords.astype(np.float64), cells.reshape(-1, 4).astype(np.int32)
+
+
+def random_cube_perturbation(coords: np.ndarray, n: int, amplitude: float, seed: int):
+    """Move interior vertices of a unit-cube mesh by a seeded random offset of
+    at most amplitude/n per coordinate (keep amplitude below ~0.15 so that
+    every tetrahedron stays positively oriented); boundary vertices stay put."""
+    rng = np.random.default_rng(seed)
+    out = coords.copy()
+    interior = np.all((coords > 1e-12) & (coords < 1 - 1e-12), axis=1)
+    out[interior] += amplitude / n * rng.uniform(-1.0, 1.0, size=(int(interior.sum()), 3))
+    return out
+
+
+def vector_potential_params(seed: int, nterms: int = 4):
+    """Amplitudes (3, nterms) and wavenumbers (3, nterms, 3) of the seeded
+    vector potential (draw order in the module header)."""
+    rng = np.random.default_rng(seed)
+    amp = np.empty((3, nterms))
+    wav = np.empty((3, nterms, 3), dtype=np.int64)
+    for c in range(3):
+        for t in range(nterms):
+            amp[c, t] = rng.standard_normal()
+            for a in range(3):
+                wav[c, t, a] = rng.integers(1, 3)
+    return amp, wav
+
+
+def curl_potential_velocity(params, x, y, z):
+    """Q = curl A at the points (x, y, z); returns shape x.shape + (3,)."""
+    amp, wav = params
+    X = np.broadcast_arrays(np.asarray(x, float), np.asarray(y, float), np.asarray(z, float))
+    grad = np.zeros(X[0].shape + (3, 3))  # grad[..., c, a] = d A_c / d x_a
+    for c in range(3):
+        for t in range(amp.shape[1]):
+            k = wav[c, t] * np.pi
+            s = [np.sin(k[a] * X[a]) for a in range(3)]
+            co = [np.cos(k[a] * X[a]) for a in range(3)]
+            grad[..., c, 0] += amp[c, t] * k[0] * co[0] * s[1] * s[2]
+            grad[..., c, 1] += amp[c, t] * k[1] * s[0] * co[1] * s[2]
+            grad[..., c, 2] += amp[c, t] * k[2] * s[0] * s[1] * co[2]
+    return np.stack([grad[..., 2, 1] - grad[..., 1, 2],
+                     grad[..., 0, 2] - grad[..., 2, 0],
+                     grad[..., 1, 0] - grad[..., 0, 1]], axis=-1)

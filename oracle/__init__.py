@@ -17,6 +17,9 @@ Module map (each function cites the passage of the paper it follows):
 * ``hdg``        - the hybridised mixed solve: static condensation onto the
                    trace, direct trace solve, back-substitution
                    (Section "Solvers and preconditioners").
+* ``tet``        - tetrahedral meshes, quadrature and bases (d = 3).
+* ``forms3d``    - the same weak forms on tetrahedra, with the 3D BDM
+                   interpolant (first-kind Nedelec interior moments).
 * ``imex``       - Butcher tableaux (Appendix A), the preconditioned Richardson
                    iteration (Algorithm 2), the IMEX-HDG step (Algorithm 1) and
                    the pressure reconstruction (Section "Pressure reconstruction").

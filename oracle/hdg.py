@@ -36,11 +36,13 @@ class HDGSolver:
         b = d.blocks
         mesh = d.mesh
         nc, nu, npp, nf = mesh.ncells, d.nu, d.npp, d.nf
+        nfc = mesh.cell_facets.shape[1]  # facets per cell: 3 (triangles), 4 (tetrahedra)
         nl = nu + npp
         self.nl = nl
         Mk = np.zeros((nc, nu, nu))
-        Mk[:, :d.nsu, :d.nsu] = b["M"]
-        Mk[:, d.nsu:, d.nsu:] = b["M"]
+        for comp in range(nu // d.nsu):
+            sl = slice(comp * d.nsu, (comp + 1) * d.nsu)
+            Mk[:, sl, sl] = b["M"]
         A = np.zeros((nc, nl, nl))
         A[:, :nu, :nu] = Mk
         A[:, :nu, nu:] = -self.c * b["Gp"]
@@ -48,16 +50,16 @@ class HDGSolver:
         A[:, nu:, nu:] = b["Tpp"]
         self.Ainv = np.linalg.inv(A)
         # lambda columns of the cell rows, per local facet: [-c Gl ; Tpl]
-        B = np.zeros((nc, 3, nl, nf))
+        B = np.zeros((nc, nfc, nl, nf))
         B[:, :, :nu, :] = -self.c * b["Gl"]
         B[:, :, nu:, :] = b["Tpl"]
         self.B = B
         # mu rows of the cell unknowns, per local facet: [Cl, Elp] = [-Gl^T, -Tpl^T]
-        L = np.zeros((nc, 3, nf, nl))
+        L = np.zeros((nc, nfc, nf, nl))
         L[:, :, :, :nu] = -np.transpose(b["Gl"], (0, 1, 3, 2))
         L[:, :, :, nu:] = -np.transpose(b["Tpl"], (0, 1, 3, 2))
         self.L = L
-        Sk = np.einsum("kfmi,kij,kgjn->kfgmn", L, self.Ainv, B)  # (nc, 3, 3, nf, nf)
+        Sk = np.einsum("kfmi,kij,kgjn->kfgmn", L, self.Ainv, B)  # (nc, nfc, nfc, nf, nf)
         Fcf = mesh.cell_facets
         rows = (Fcf[:, :, None, None, None] * nf + np.arange(nf)[None, None, None, :, None])
         cols = (Fcf[:, None, :, None, None] * nf + np.arange(nf)[None, None, None, None, :])
@@ -91,7 +93,7 @@ class HDGSolver:
     def back_substitute(self, Fw, Fpsi, lam):
         d = self.disc
         f = self._cell_rhs(Fw, Fpsi)
-        lk = np.asarray(lam).reshape(-1, d.nf)[d.mesh.cell_facets]  # (nc, 3, nf)
+        lk = np.asarray(lam).reshape(-1, d.nf)[d.mesh.cell_facets]  # (nc, nfc, nf)
         f = f - np.einsum("kfin,kfn->ki", self.B, lk)
         x = np.einsum("kij,kj->ki", self.Ainv, f)
         return x[:, :d.nu].reshape(-1), x[:, d.nu:].reshape(-1)

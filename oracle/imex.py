@@ -154,7 +154,7 @@ class IMEXHDG:
         self.dt = float(dt)
         self.tab = tableau
         self.nR = int(n_richardson)
-        self.forcing = forcing  # callable f(x, y, t) -> (..., 2), or None
+        self.forcing = forcing  # callable f(x, y[, z], t) -> (..., d), or None
         if pressure_update not in ("reconstruct", "first_order"):
             raise ValueError(pressure_update)
         self.pressure_update = pressure_update
@@ -172,7 +172,7 @@ class IMEXHDG:
     def forcing_dual(self, t):
         """f^ex(w; t) = (w . f(t))_Omega as a dual vector (eq. f_expl)."""
         d = self.disc
-        vals = self.forcing(d.cx[..., 0], d.cx[..., 1], t)
+        vals = self.forcing(*np.moveaxis(d.cx, -1, 0), t)
         return np.einsum("kq,qi,kqc->kci", d.cw, d.Vu, vals).reshape(-1)
 
     def reconstruct(self, Q, t):
@@ -181,8 +181,8 @@ class IMEXHDG:
         d = self.disc
         cell, fac = d.convection_points(Q)
         if self.forcing is not None:
-            fcell = self.forcing(d.cx[..., 0], d.cx[..., 1], t)
-            ffac = self.forcing(d.cf_x[..., 0], d.cf_x[..., 1], t)
+            fcell = self.forcing(*np.moveaxis(d.cx, -1, 0), t)
+            ffac = self.forcing(*np.moveaxis(d.cf_x, -1, 0), t)
             cell = cell - fcell
             fac = fac - ffac
             Fmu = d.boundary_normal_flux(ffac)
