@@ -53,11 +53,11 @@ CSRC = os.path.join(ROOT, "paper_2410_09790_amd", "csrc")
 MEASURED_TRAFFIC = {
     "apply_step1_operator": {"src": "step1.hip", "funcs": ["pair_swap", "tile_idx", "VPairs", "step1_core",
                                                            "xcd_block", "stage_fbu", "k_apply_soa"],
-                             "sha256": "3c0c5c4a232c8b2b", "bytes_per_launch": 404.1e6},
+                             "sha256": "7ee582c4c3bd27ad", "bytes_per_launch": 403.9e6},
     "step1_precond_apply": {"src": "step1.hip", "funcs": ["PcLayout", "PcApplyShape", "k_pc_apply"],
-                            "sha256": "f95d7160166a152f", "bytes_per_launch": 1674.6e6},
-    "trace_spmv": {"src": "kernels.hip", "funcs": ["k_spmv"], "sha256": "96d7545c27858460", "bytes_per_launch": 159.0e6},
-    "trace_spmv_512": {"src": "kernels.hip", "funcs": ["k_spmv"], "sha256": "96d7545c27858460", "bytes_per_launch": 627.0e6},
+                            "sha256": "6be723b4d110307c", "bytes_per_launch": 1660.3e6},
+    "trace_spmv": {"src": "kernels.hip", "funcs": ["k_spmv"], "sha256": "96d7545c27858460", "bytes_per_launch": 159.1e6},
+    "trace_spmv_512": {"src": "kernels.hip", "funcs": ["k_spmv"], "sha256": "96d7545c27858460", "bytes_per_launch": 627.3e6},
 }
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
 MIXED_RTOL_VELOCITY = 1e-5  # Step I tolerance of the mixed-precision run
@@ -516,8 +516,7 @@ def serving_run(hdg, hi, torch, njobs: int = 16, nmax: int = 48, steps: int = 10
                                                 "mean_latency_s": float(np.mean(fifo_lat)),
                                                 "throughput": work / fifo_span}}
         for nw in workers:
-            pol = ["srpt"] if nw == 1 else None  # default: srpt + fifo workers
-            srv = serve.Server(64 << 30, workers=nw, policies=pol)
+            srv = serve.Server(64 << 30, workers=nw)
 
             def feed():
                 t0 = srv.now()
