@@ -158,6 +158,18 @@ typedef struct {
                             weight adt/h^2 as it does for cell blocks.  Device memory: 8 nu^2 +
                             12 nu^2 bytes per cell (nu = (k+2)(k+3)). */
   int step2_reading;     /* hdg_step2_reading */
+  int dim;               /* 2: triangles (coords [nv][2], cells [nc][3]); 3: tetrahedra (coords
+                            [nv][3], cells [nc][4], positively oriented, degree 1..2, FP64; the
+                            method is stated for d = 2 and 3 in Sections "Discontinuous Galerkin
+                            spaces" and "Hybridisation").  On tetrahedra: local facet f is the
+                            triangle opposite local vertex f; facets are the sorted vertex triples
+                            (lo, mid, hi) in lexicographic order with facet coordinates (s, t) at
+                            x_lo + s (x_mid - x_lo) + t (x_hi - x_lo); bases are the centred
+                            monomials ((d+1)x - 1)^a.. by degree and then descending exponents,
+                            Gram-Schmidt orthonormalised on the reference cell (trace: for twice
+                            the reference triangle's measure).  Not available on tetrahedra:
+                            periodic meshes, forcing, the tracer, point evaluation, the mixed
+                            precision and the Step I preconditioner (step1_precond is ignored). */
 } hdg_params;
 
 /* Fill p with the defaults: k=1, tau=alpha=delta_up=1, ARS(2,2,2), n_R=3,
@@ -166,8 +178,8 @@ typedef struct {
  * replay on, Step I operator in workgroups of 256 threads in XCD order. */
 void hdg_default_params(hdg_params* p);
 
-/* Create a context on the current HIP device.  coords: host [nv][2];
- * cells: host [nc][3] vertex ids, counter-clockwise (det J > 0).  stream:
+/* Create a context on the current HIP device.  coords: host [nv][dim];
+ * cells: host [nc][dim+1] vertex ids, positively oriented (det J > 0).  stream:
  * a hipStream_t (NULL = the null stream).  The mesh is copied.  Errors:
  * INVALID_ARG (bad mesh or parameters; message via hdg_last_error(NULL)),
  * UNSUPPORTED (degree), OUT_OF_MEMORY, DEVICE. */
@@ -302,6 +314,18 @@ int hdg_eval_points_noalloc(hdg_ctx* ctx, const double* xy_ref, int npts, double
  * their left and bottom copies (hdg_create_periodic). */
 int hdg_mesh_square(int n, double length, int diagonal, int periodic, double* coords, int32_t* cells,
                     int32_t* vertex_rep);
+
+/* Host-side mesh of the unit cube cut into n^3 cubes of six tetrahedra
+ * (the Kuhn split, every tetrahedron of a cube contains its diagonal from
+ * the corner nearest the origin; the three-dimensional workload, for the
+ * method as stated for d = 3 in Section "Discontinuous Galerkin spaces"):
+ * vertex (i, j, l) has id (l (n+1) + j)(n+1) + i at (i, j, l)/n; cube
+ * (i, j, l) gives the cells 6 ((l n + j) n + i) + r, r = 0..5, one per
+ * permutation (a, b, c) of the axes in lexicographic order, with vertices
+ * corner, corner + e_a, corner + e_a + e_b, corner + (1, 1, 1) (all /n),
+ * the last two swapped for an odd permutation so that det J > 0.
+ * coords: [(n+1)^3][3], cells: [6 n^3][4] (caller-owned); 1 <= n <= 1024. */
+int hdg_mesh_unit_cube(int n, double* coords, int32_t* cells);
 
 /* One hybridised mixed solve (paper, Section "Solvers and preconditioners"):
  * find (U, p, lam) with

@@ -20,8 +20,10 @@ HIP_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", 
 SOURCES = [
     ("ref.cpp", "host"),
     ("mesh.cpp", "host"),
+    ("tet.cpp", "host"),
     ("kernels.hip", "hip"),
     ("step1.hip", "hip"),
+    ("kernels3.hip", "hip"),
     ("api.hip", "hip"),
 ]
 

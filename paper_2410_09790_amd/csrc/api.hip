@@ -243,9 +243,13 @@ struct hdg_ctx {
   hdg_params prm{};
   hdg::Step1Launch s1{256, 1};  // launch shape of the Step I operator (from prm)
   int k = 1;
+  int dim = 2, nfc = 3;  // tetrahedra: 3, 4
+  int tk = 1;            // key of the trace-operator kernels (k; 10 + k on tetrahedra)
+  int slots = 5;         // facet blocks per trace-operator row (7 on tetrahedra)
   hipStream_t st = nullptr;
   hdg::HostMesh hm;
   hdg::RefTables rt;
+  hdg::RefTables3 rt3;
   hdg::DMesh dm{};
   hdg::DTab dt{};
   int ns = 0, np = 0, nf = 0, nu = 0, nlam = 0, nqc = 0, nqf = 0;
@@ -338,6 +342,9 @@ struct hdg_ctx {
   }
 
   void setup();
+  void setup_tri();
+  void setup_tet();
+  void setup_work();
   hdg::TraceOp& trace_op(double c);
   void build_mg(hdg::TraceOp& op);
   void precond(hdg::TraceOp& op, const double* r, double* z);
@@ -452,11 +459,29 @@ struct hdg_ctx {
 using namespace hdg;
 
 void hdg_ctx::setup() {
-  ns = rt.ns; np = rt.np; nf = rt.nf; nu = 2 * ns; nlam = 3 * nf; nqc = rt.nqc; nqf = rt.nqf;
+  if (dim == 3) {
+    ns = rt3.ns; np = rt3.np; nf = rt3.nf; nu = 3 * ns; nlam = 4 * nf; nqc = rt3.nqc; nqf = rt3.nqf;
+    nfc = 4; tk = 10 + k; slots = 7;
+  } else {
+    ns = rt.ns; np = rt.np; nf = rt.nf; nu = 2 * ns; nlam = 3 * nf; nqc = rt.nqc; nqf = rt.nqf;
+    nfc = 3; tk = k; slots = 5;
+  }
   const long nc = hm.nc, nF = hm.nF;
   nQ = nc * nu; nP = nc * np; nT = nF * nf;
   area = 0.0;
-  for (long e = 0; e < nc; ++e) area += 0.5 * hm.geo[G_DET * nc + e];
+  dm.dim = dim;
+  if (dim == 3) {
+    setup_tet();
+  } else {
+    for (long e = 0; e < nc; ++e) area += 0.5 * hm.geo[G_DET * nc + e];
+    setup_tri();
+  }
+  setup_work();
+}
+
+// triangles: mesh and reference tables
+void hdg_ctx::setup_tri() {
+  const long nc = hm.nc;
   // mesh
   std::vector<double> geo((size_t)kDGeo * nc);
   const int map[kDGeo] = {G_DET, G_IJ00, G_IJ01, G_IJ10, G_IJ11, G_NX0, G_NY0, G_NX1, G_NY1, G_NX2, G_NY2,
@@ -464,7 +489,7 @@ void hdg_ctx::setup() {
   for (int f = 0; f < kDGeo; ++f)
     std::memcpy(&geo[(size_t)f * nc], &hm.geo[(size_t)map[f] * nc], nc * sizeof(double));
   dm.nc = (int)nc;
-  dm.nF = (int)nF;
+  dm.nF = (int)hm.nF;
   dm.geo = upload(geo);
   dm.cf_facet = upload(hm.cf_facet);
   dm.cf_nb = upload(hm.cf_nb);
@@ -495,10 +520,42 @@ void hdg_ctx::setup() {
   dt.Dx = cu(rt.Dx); dt.Dy = cu(rt.Dy); dt.Rx = cu(rt.Rx); dt.Ry = cu(rt.Ry);
   dt.Chat = cu(rt.Chat); dt.That = cu(rt.That); dt.Ehat = cu(rt.Ehat); dt.CC = cu(rt.CC);
   dt.KDD = cu(rt.KDD); dt.CD = cu(rt.CD); dt.BDMinv = cu(rt.BDMinv); dt.NED = cu(rt.NED);
+}
+
+// tetrahedra: mesh and reference tables (geometry fields in the device order)
+void hdg_ctx::setup_tet() {
+  const long nc = hm.nc;
+  for (long e = 0; e < nc; ++e) area += hm.geo[E_DET * nc + e] / 6.0;
+  static_assert((int)kGeo3 == (int)kDGeo3 && (int)E_N == (int)E3_N && (int)E_A == (int)E3_A, "geometry layout");
+  dm.nc = (int)nc;
+  dm.nF = (int)hm.nF;
+  dm.geo = upload(hm.geo);
+  dm.cf_facet = upload(hm.cf_facet);
+  dm.cf_nb = upload(hm.cf_nb);
+  dm.cf_nbf = upload(hm.cf_nbf);
+  dm.cf_flip = upload(hm.cf_flip);
+  dm.cf_nbx = nullptr;
+  dm.fc_cell = upload(hm.fc_cell);
+  dm.fc_f = upload(hm.fc_f);
+  DTab3& t = dt.t3;
+  t.Bu = upload(rt3.Bu); t.dBu = upload(rt3.dBu); t.Bp = upload(rt3.Bp); t.dBp = upload(rt3.dBp);
+  t.cw = upload(rt3.cq_w);
+  t.FBu = upload(rt3.FBu); t.FdBu = upload(rt3.FdBu); t.FBp = upload(rt3.FBp); t.fw = upload(rt3.fq_w);
+  t.MU = upload(rt3.MU); t.NUL = upload(rt3.NUL);
+  t.D = upload(rt3.D); t.R = upload(rt3.R); t.KDD = upload(rt3.KDD); t.That = upload(rt3.That);
+  t.Chat = upload(rt3.Chat); t.Ehat = upload(rt3.Ehat); t.CD = upload(rt3.CD); t.NEDM = upload(rt3.NEDM);
+  t.BDMinv = upload(rt3.BDMinv);
+}
+
+// work vectors (both cell shapes)
+void hdg_ctx::setup_work() {
+  const long nc = hm.nc;
   // work
   ycell = dalloc<double>(nc * nlam);
   g = dalloc<double>(nT);
-  part = dalloc<double>(std::max<long>((long)kRedBlocks * kIdrMax, 4L * apply_soa_blocks(nc, s1.block) + 16));
+  // (tetrahedra: the back-substitution also keeps nc cell integrals behind its partial sums)
+  part = dalloc<double>(std::max<long>((long)kRedBlocks * kIdrMax, 4L * apply_soa_blocks(nc, s1.block) + 16) +
+                        (dim == 3 ? nc : 0));
   part2 = dalloc<double>(2 * kRedBlocks);
   const int mt = prm.max_it_trace + 4, mv = prm.max_it_velocity + 4;
   scal = dalloc<double>(3 * mt + 16);
@@ -512,7 +569,7 @@ void hdg_ctx::setup() {
   for (void** v : {&kd.b, &kd.x, &kd.r, &kd.rh, &kd.s, &kd.t, &kd.p, &kd.v}) *v = kvec();
   // the facet-patch preconditioner needs every cell on an interior facet
   // (else a cell would receive no correction)
-  pc_on = prm.step1_precond == 1 && prm.idr_s == 0;
+  pc_on = prm.step1_precond == 1 && prm.idr_s == 0 && dim == 2;
   for (long e = 0; pc_on && e < nc; ++e)
     pc_on = hm.cf_nb[e] >= 0 || hm.cf_nb[nc + e] >= 0 || hm.cf_nb[2 * nc + e] >= 0;
   if (pc_on) {
@@ -524,9 +581,10 @@ void hdg_ctx::setup() {
   const long nc32 = (nc + 31) / 32 * 32;
   vk32 = prm.precision == HDG_MIXED;
   vk = vk32 ? (void*)dalloc<float>((long)ns * ns * nc32) : (void*)dalloc<double>((long)ns * ns * nc32);
-  vbeta = kx32 ? (void*)dalloc<float>(3L * nqf * nc32) : (void*)dalloc<double>(3L * nqf * nc32);
+  vbeta = kx32 ? (void*)dalloc<float>((long)nfc * nqf * nc32) : (void*)dalloc<double>((long)nfc * nqf * nc32);
   br = dalloc<double>(nQ); bt = dalloc<double>(nQ);
-  adv = dalloc<double>((long)nc * (2 * nqc + 3 * nqf));
+  // residual-kernel advection data (tetrahedra: the cell volume matrices and the facet weights)
+  adv = dalloc<double>(dim == 3 ? (long)nc * (ns * ns + 4 * nqf) : (long)nc * (2 * nqc + 3 * nqf));
   Qs = dalloc<double>(nQ); dr = dalloc<double>(nQ); Qbar = dalloc<double>(nQ); dQ = dalloc<double>(nQ);
   dp = dalloc<double>(nP); dl = dalloc<double>(nT); fpsi = dalloc<double>(nP); Ut = dalloc<double>(nQ);
   fmu = dalloc<double>(nT);
@@ -550,8 +608,8 @@ TraceOp& hdg_ctx::trace_op(double c) {
   double* SK = nullptr;
   HIPCHK(hipMalloc(&SK, sizeof(double) * nc * nlam * nlam));
   dev_transient = std::max(dev_transient, sizeof(double) * nc * nlam * nlam);
-  op->vals = dalloc<double>(5 * nF * nf * nf);
-  op->cols = dalloc<int>(5 * nF);
+  op->vals = dalloc<double>((long)slots * nF * nf * nf);
+  op->cols = dalloc<int>((long)slots * nF);
   op->Dinv = dalloc<double>(nF * nf * nf);
   {
     Timed tm(prof, KC_CONDENSE);
@@ -571,8 +629,8 @@ TraceOp& hdg_ctx::trace_op(double c) {
 // Galerkin P1 coarse operator and AMG hierarchy (host setup, device apply)
 void hdg_ctx::build_mg(TraceOp& op) {
   const long nF = hm.nF;
-  std::vector<double> vals(5 * nF * nf * nf);
-  std::vector<int> cols(5 * nF);
+  std::vector<double> vals((size_t)slots * nF * nf * nf);
+  std::vector<int> cols((size_t)slots * nF);
   HIPCHK(hipMemcpyAsync(vals.data(), op.vals, vals.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(cols.data(), op.cols, cols.size() * sizeof(int), hipMemcpyDeviceToHost, st));
   sync();
@@ -582,7 +640,7 @@ void hdg_ctx::build_mg(TraceOp& op) {
   for (long F = 0; F < nF; ++F)
     for (int i = 0; i < nf; ++i) {
       const long row = F * nf + i;
-      for (int s = 0; s < 5; ++s)
+      for (int s = 0; s < slots; ++s)
         for (int j = 0; j < nf; ++j) {
           double v = vals[((long)(s * nf + i) * nf + j) * nF + F];
           if (v == 0.0) continue;
@@ -595,19 +653,39 @@ void hdg_ctx::build_mg(TraceOp& op) {
   Pt.nrows = nT;
   Pt.ncols = hm.nvt;
   Pt.ptr.assign(nT + 1, 0);
-  const double r3 = 0.5 / std::sqrt(3.0);
-  for (long F = 0; F < nF; ++F)
-    for (int i = 0; i < nf; ++i) {
-      const long row = F * nf + i;
-      if (i == 0) {  // mean of the linear function
-        Pt.idx.push_back(hm.facet_lo[F]); Pt.val.push_back(0.5);
-        Pt.idx.push_back(hm.facet_hi[F]); Pt.val.push_back(0.5);
-      } else if (i == 1) {  // slope in the orthonormal Legendre basis
-        Pt.idx.push_back(hm.facet_lo[F]); Pt.val.push_back(-r3);
-        Pt.idx.push_back(hm.facet_hi[F]); Pt.val.push_back(r3);
-      }
-      Pt.ptr[row + 1] = (int32_t)Pt.idx.size();
+  if (dim == 3) {
+    // the hat functions of the facet's three vertices (1 - s - t, s, t in the
+    // facet's coordinates) projected onto the orthonormal trace basis
+    double proj[3][64] = {};
+    for (int q = 0; q < rt3.nqf; ++q) {
+      const double sq = rt3.fq_s[q], tq = rt3.fq_t[q], w = 2.0 * rt3.fq_w[q];
+      const double hat[3] = {1.0 - sq - tq, sq, tq};
+      for (int v = 0; v < 3; ++v)
+        for (int i = 0; i < nf; ++i) proj[v][i] += w * hat[v] * rt3.MU[(size_t)q * nf + i];
     }
+    for (long F = 0; F < nF; ++F)
+      for (int i = 0; i < nf; ++i) {
+        const long row = F * nf + i;
+        const int32_t vv[3] = {hm.facet_lo[F], hm.facet_mid[F], hm.facet_hi[F]};
+        for (int v = 0; v < 3; ++v)
+          if (std::fabs(proj[v][i]) > 1e-14) { Pt.idx.push_back(vv[v]); Pt.val.push_back(proj[v][i]); }
+        Pt.ptr[row + 1] = (int32_t)Pt.idx.size();
+      }
+  } else {
+    const double r3 = 0.5 / std::sqrt(3.0);
+    for (long F = 0; F < nF; ++F)
+      for (int i = 0; i < nf; ++i) {
+        const long row = F * nf + i;
+        if (i == 0) {  // mean of the linear function
+          Pt.idx.push_back(hm.facet_lo[F]); Pt.val.push_back(0.5);
+          Pt.idx.push_back(hm.facet_hi[F]); Pt.val.push_back(0.5);
+        } else if (i == 1) {  // slope in the orthonormal Legendre basis
+          Pt.idx.push_back(hm.facet_lo[F]); Pt.val.push_back(-r3);
+          Pt.idx.push_back(hm.facet_hi[F]); Pt.val.push_back(r3);
+        }
+        Pt.ptr[row + 1] = (int32_t)Pt.idx.size();
+      }
+  }
   Csr Rt = csr_transpose(Pt);
   Csr Ac = csr_multiply(Rt, csr_multiply(S, Pt));
   AmgHierarchy h;
@@ -669,9 +747,9 @@ void hdg_ctx::mg_apply(TraceOp& op, const double* r, double* z) {
   const double om = 0.7;
   {
     Timed tm(prof, KC_SMOOTH);
-    launch_jacobi_sweep(k, st, nF, op.vals, op.cols, op.Dinv, om, r, nullptr, t1);
-    launch_jacobi_sweep(k, st, nF, op.vals, op.cols, op.Dinv, om, r, t1, t2);
-    launch_residual(k, st, nF, op.vals, op.cols, r, t2, t3);
+    launch_jacobi_sweep(tk, st, nF, op.vals, op.cols, op.Dinv, om, r, nullptr, t1);
+    launch_jacobi_sweep(tk, st, nF, op.vals, op.cols, op.Dinv, om, r, t1, t2);
+    launch_residual(tk, st, nF, op.vals, op.cols, r, t2, t3);
   }
   double* b0 = op.levels.empty() ? op.cb : op.levels[0].b;
   double* x0 = op.levels.empty() ? op.cx : op.levels[0].x;
@@ -679,8 +757,8 @@ void hdg_ctx::mg_apply(TraceOp& op, const double* r, double* z) {
   vcycle(op, 0);
   launch_csr_spmv(st, op.Pt, x0, t2, 1.0);
   Timed tm(prof, KC_SMOOTH);
-  launch_jacobi_sweep(k, st, nF, op.vals, op.cols, op.Dinv, om, r, t2, t1);
-  launch_jacobi_sweep(k, st, nF, op.vals, op.cols, op.Dinv, om, r, t1, z);
+  launch_jacobi_sweep(tk, st, nF, op.vals, op.cols, op.Dinv, om, r, t2, t1);
+  launch_jacobi_sweep(tk, st, nF, op.vals, op.cols, op.Dinv, om, r, t1, z);
 }
 
 // Remove from a trace vector its component along the null vector of the
@@ -697,7 +775,7 @@ void hdg_ctx::project_null(double* v) {
 // the null vector, its norm grows and the attainable residual with it.
 void hdg_ctx::precond(TraceOp& op, const double* r, double* z) {
   if (op.mg) mg_apply(op, r, z);
-  else launch_blockdiag(k, st, (int)hm.nF, op.Dinv, r, z);
+  else launch_blockdiag(tk, st, (int)hm.nF, op.Dinv, r, z);
   project_null(z);
   KCHK();
 }
@@ -748,7 +826,7 @@ void hdg_ctx::pcg_block(TraceOp& op) {
   for (int b = 0; b < kPcgBlock; ++b) {
     {
       Timed tm(prof, KC_TRACE_SPMV);
-      launch_spmv(k, st, nF, op.vals, op.cols, pp, pq);
+      launch_spmv(tk, st, nF, op.vals, op.cols, pp, pq);
     }
     launch_dot(st, n, pp, pq, part);
     launch_finish(st, part, kRedBlocks, pqv + b);
@@ -861,7 +939,7 @@ int hdg_ctx::pcg(TraceOp& op, const double* gin, double* x) {
 // multi-launch iteration there).  Same stopping rules as pcg().
 int hdg_ctx::pcg_small(TraceOp& op, const double* gin, double gnorm, double* x) {
   const double tol = prm.rtol_trace * gnorm, flo = floor_band() * gnorm;
-  launch_pcg_small(k, st, (int)hm.nF, op.vals, op.cols, op.Dinv, gin, px, pr, pz, pp, pq, prm.max_it_trace, tol * tol,
+  launch_pcg_small(tk, st, (int)hm.nF, op.vals, op.cols, op.Dinv, gin, px, pr, pz, pp, pq, prm.max_it_trace, tol * tol,
                    flo * flo, kPcgFlatBlocks, small_info);
   KCHK();
   HIPCHK(hipMemcpyAsync(h_pinned, small_info, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -886,7 +964,7 @@ int hdg_ctx::pcg_small(TraceOp& op, const double* gin, double gnorm, double* x) 
 // trace solves stop on), recomputed from x rather than recursively updated
 double hdg_ctx::trace_true_residual(TraceOp& op, const double* gin, const double* xv) {
   const double* scr = scal + 3 * (prm.max_it_trace + 4) + 2;
-  launch_residual(k, st, (int)hm.nF, op.vals, op.cols, gin, xv, t3);
+  launch_residual(tk, st, (int)hm.nF, op.vals, op.cols, gin, xv, t3);
   launch_rr_partials(st, nT, nf, t3, part);
   launch_finish_proj(st, part, kRedBlocks, (double)hm.nF, const_cast<double*>(scr));
   KCHK();
@@ -1620,6 +1698,7 @@ void hdg_default_params(hdg_params* p) {
   p->step1_xcd = 1;
   p->step1_precond = 1;
   p->step2_reading = HDG_STEP2_PRINTED;
+  p->dim = 2;
 }
 
 int hdg_create(int64_t nv, const double* coords, int64_t nc, const int32_t* cells, const hdg_params* prm,
@@ -1631,8 +1710,13 @@ int hdg_create_periodic(int64_t nv, const double* coords, int64_t nc, const int3
                         const int32_t* vertex_rep, const hdg_params* prm, void* stream, hdg_ctx** out) {
   if (!out || !prm) { g_create_error = "null argument"; return HDG_ERR_INVALID_ARG; }
   *out = nullptr;
-  if (prm->degree < 1 || prm->degree > kMaxDegree) {
-    g_create_error = "degree must be in 1..4";
+  if (prm->dim != 2 && prm->dim != 3) { g_create_error = "dim must be 2 or 3"; return HDG_ERR_INVALID_ARG; }
+  if (prm->degree < 1 || prm->degree > (prm->dim == 3 ? kMaxDegree3 : kMaxDegree)) {
+    g_create_error = prm->dim == 3 ? "degree must be in 1..2 on tetrahedra" : "degree must be in 1..4";
+    return HDG_ERR_UNSUPPORTED;
+  }
+  if (prm->dim == 3 && (vertex_rep || prm->precision != HDG_FP64)) {
+    g_create_error = "tetrahedra: no periodic meshes, FP64 only";
     return HDG_ERR_UNSUPPORTED;
   }
   if (prm->tau <= 0 || prm->alpha < 0 || prm->delta_up < 0 || prm->n_richardson < 1 || prm->max_it_trace < 1 ||
@@ -1652,11 +1736,14 @@ int hdg_create_periodic(int64_t nv, const double* coords, int64_t nc, const int3
   ctx->s1 = {prm->step1_block, prm->step1_xcd};
   ctx->k = prm->degree;
   ctx->st = (hipStream_t)stream;
-  std::string e = build_mesh(nv, coords, nc, cells, vertex_rep, ctx->hm);
+  ctx->dim = prm->dim;
+  std::string e = prm->dim == 3 ? build_mesh3(nv, coords, nc, cells, ctx->hm)
+                                : build_mesh(nv, coords, nc, cells, vertex_rep, ctx->hm);
   if (!e.empty()) { g_create_error = e; return HDG_ERR_INVALID_ARG; }
   if (hipGetDevice(&ctx->device) != hipSuccess) { g_create_error = "no HIP device"; return HDG_ERR_DEVICE; }
   try {
-    build_reference(ctx->k, ctx->rt);
+    if (prm->dim == 3) build_reference3(ctx->k, ctx->rt3);
+    else build_reference(ctx->k, ctx->rt);
     ctx->setup();
     ctx->eval_scratch = scratch_address(ctx->device);
     ctx->eval_host.assign(kEvalScratchDoubles, 0.0);
@@ -1701,6 +1788,21 @@ int hdg_sizes(const hdg_ctx* ctx, int64_t* out, int n) {
 int hdg_cell_points(const hdg_ctx* ctx, double* xy) {
   if (!ctx || !xy) return HDG_ERR_INVALID_ARG;
   const auto& m = ctx->hm;
+  if (ctx->dim == 3) {
+    const auto& t = ctx->rt3;
+    for (int64_t e = 0; e < m.nc; ++e) {
+      const double* v0 = &m.coords[3 * m.cells[4 * e]];
+      for (int q = 0; q < t.nqc; ++q) {
+        const double r[3] = {t.cq_x[q], t.cq_y[q], t.cq_z[q]};
+        for (int a = 0; a < 3; ++a) {
+          double x = v0[a];
+          for (int b = 0; b < 3; ++b) x += m.geo[(size_t)(E_J + 3 * a + b) * m.nc + e] * r[b];
+          xy[(e * t.nqc + q) * 3 + a] = x;
+        }
+      }
+    }
+    return HDG_OK;
+  }
   const auto& t = ctx->rt;
   for (int64_t e = 0; e < m.nc; ++e) {
     const double* v0 = &m.coords[2 * m.cells[3 * e]];
@@ -1718,6 +1820,20 @@ int hdg_cell_points(const hdg_ctx* ctx, double* xy) {
 int hdg_facet_points(const hdg_ctx* ctx, double* xy) {
   if (!ctx || !xy) return HDG_ERR_INVALID_ARG;
   const auto& m = ctx->hm;
+  if (ctx->dim == 3) {  // [nc][4][nq][3], facet f's points in the facet's own order
+    const auto& t = ctx->rt3;
+    for (int64_t e = 0; e < m.nc; ++e)
+      for (int f = 0; f < 4; ++f) {
+        const int64_t F = m.cf_facet[f * m.nc + e];
+        const double* a = &m.coords[3 * m.facet_lo[F]];
+        const double* b = &m.coords[3 * m.facet_mid[F]];
+        const double* c = &m.coords[3 * m.facet_hi[F]];
+        for (int q = 0; q < t.nqf; ++q)
+          for (int d = 0; d < 3; ++d)
+            xy[((e * 4 + f) * t.nqf + q) * 3 + d] = a[d] + t.fq_s[q] * (b[d] - a[d]) + t.fq_t[q] * (c[d] - a[d]);
+      }
+    return HDG_OK;
+  }
   const auto& t = ctx->rt;
   for (int64_t e = 0; e < m.nc; ++e) {
     const double* v0 = &m.coords[2 * m.cells[3 * e]];
@@ -1737,6 +1853,7 @@ int hdg_facet_points(const hdg_ctx* ctx, double* xy) {
 
 int hdg_set_forcing(hdg_ctx* ctx, const double* cell_vals, const double* facet_vals, double decay) {
   if (!ctx || (cell_vals && !facet_vals) || !(decay == decay)) return HDG_ERR_INVALID_ARG;
+  if (ctx->dim == 3 && cell_vals) { ctx->err = "forcing is not available on tetrahedra"; return HDG_ERR_UNSUPPORTED; }
   ctx->not_converged = false;
   ctx->err.clear();
   API_BEGIN
@@ -1864,6 +1981,7 @@ int hdg_pending_stage(const hdg_ctx* ctx) { return ctx ? ctx->pend_stage : -1; }
 
 int hdg_set_tracer(hdg_ctx* ctx, const double* qvals) {
   if (!ctx) return HDG_ERR_INVALID_ARG;
+  if (ctx->dim == 3) { ctx->err = "hdg_set_tracer: triangles only"; return HDG_ERR_UNSUPPORTED; }
   ctx->not_converged = false;
   ctx->err.clear();
   API_BEGIN
@@ -1894,6 +2012,7 @@ int hdg_get_tracer(const hdg_ctx* cctx, double* q) {
 
 int hdg_cg_project(hdg_ctx* ctx, const double* Qv, double* Ucg) {
   if (!ctx || !Qv || !Ucg) return HDG_ERR_INVALID_ARG;
+  if (ctx->dim == 3) { ctx->err = "hdg_cg_project: triangles only"; return HDG_ERR_UNSUPPORTED; }
   ctx->not_converged = false;
   ctx->err.clear();
   API_BEGIN
@@ -1904,6 +2023,7 @@ int hdg_cg_project(hdg_ctx* ctx, const double* Qv, double* Ucg) {
 
 int hdg_tracer_rate(hdg_ctx* ctx, const double* Qv, const double* q, double* out) {
   if (!ctx || !Qv || !q || !out) return HDG_ERR_INVALID_ARG;
+  if (ctx->dim == 3) { ctx->err = "hdg_tracer_rate: triangles only"; return HDG_ERR_UNSUPPORTED; }
   ctx->not_converged = false;
   ctx->err.clear();
   API_BEGIN
@@ -1918,6 +2038,7 @@ int hdg_tracer_rate(hdg_ctx* ctx, const double* Qv, const double* q, double* out
 
 int hdg_eval_points(hdg_ctx* ctx, const double* xy_ref, int npts, double* Qo, double* po) {
   if (!ctx || !xy_ref || npts < 1 || npts > kMaxEvalPoints || (!Qo && !po)) return HDG_ERR_INVALID_ARG;
+  if (ctx->dim == 3) { ctx->err = "hdg_eval_points: triangles only"; return HDG_ERR_UNSUPPORTED; }
   if (!ctx->have_state) { ctx->err = "no state set"; return HDG_ERR_BAD_STATE; }
   ctx->not_converged = false;
   ctx->err.clear();
@@ -1944,6 +2065,7 @@ int hdg_eval_points(hdg_ctx* ctx, const double* xy_ref, int npts, double* Qo, do
 // Calls on one device share the array, so calls that overlap there race.
 int hdg_eval_points_noalloc(hdg_ctx* ctx, const double* xy_ref, int npts, double* Qo, double* po) {
   if (!ctx || !xy_ref || npts < 1 || (!Qo && !po)) return HDG_ERR_INVALID_ARG;
+  if (ctx->dim == 3) { ctx->err = "hdg_eval_points_noalloc: triangles only"; return HDG_ERR_UNSUPPORTED; }
   if (npts > kMaxEvalPoints) {
     ctx->err = "hdg_eval_points_noalloc: " + std::to_string(npts) + " points, more than the static staging area's " +
                std::to_string(kMaxEvalPoints);
@@ -2002,6 +2124,12 @@ int hdg_mesh_square(int n, double length, int diagonal, int periodic, double* co
   return HDG_OK;
 }
 
+int hdg_mesh_unit_cube(int n, double* coords, int32_t* cells) {
+  if (n < 1 || n > 1024 || !coords || !cells) return HDG_ERR_INVALID_ARG;
+  hdg::mesh_unit_cube(n, coords, cells);
+  return HDG_OK;
+}
+
 int hdg_solve_trace(hdg_ctx* ctx, double c, const double* Fw, const double* Fpsi, const double* Fmu, double* U,
                     double* pv, double* lv) {
   if (!ctx || !(c > 0) || !U || !pv || !lv) return HDG_ERR_INVALID_ARG;
@@ -2020,7 +2148,7 @@ int hdg_trace_matvec(hdg_ctx* ctx, double c, const double* x, double* y) {
   TraceOp& op = ctx->trace_op(c);
   {
     Timed tm(ctx->prof, KC_TRACE_SPMV);
-    launch_spmv(ctx->k, ctx->st, (int)ctx->hm.nF, op.vals, op.cols, x, y);
+    launch_spmv(ctx->tk, ctx->st, (int)ctx->hm.nF, op.vals, op.cols, x, y);
   }
   KCHK();
   ctx->sync();
@@ -2183,6 +2311,7 @@ int hdg_get_info(const hdg_ctx* ctx, char* buf, size_t cap) {
 int hdg_footprint_bytes(int64_t nv, const double* coords, int64_t nc, const int32_t* cells, const int32_t* vertex_rep,
                         const hdg_params* prm, double dt, int64_t* bytes) {
   if (!prm || !bytes || !(dt > 0)) { g_create_error = "null argument or dt <= 0"; return HDG_ERR_INVALID_ARG; }
+  if (prm->dim != 2) { g_create_error = "footprint estimate: triangles only"; return HDG_ERR_UNSUPPORTED; }
   if (prm->degree < 1 || prm->degree > kMaxDegree) { g_create_error = "degree must be in 1..4"; return HDG_ERR_UNSUPPORTED; }
   if (prm->imex < 0 || prm->imex > 4 ||
       (prm->step1_block != 64 && prm->step1_block != 128 && prm->step1_block != 256)) {

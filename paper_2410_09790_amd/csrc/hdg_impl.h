@@ -2,6 +2,7 @@
 // the public C ABI; see include/hdg.h for that.
 #pragma once
 
+#include <array>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -62,24 +63,81 @@ inline void facet_point(int f, double s, double& xi, double& eta) {
   else { xi = s; eta = 0.0; }
 }
 
+// ------------------------------------------------------- tetrahedra (d = 3)
+constexpr int kMaxDegree3 = 2;  // pressure/trace degree k supported on tetrahedra
+// local facet f: the triangle opposite local vertex f, local vertices ascending
+constexpr int LF3[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+// orientation p of a local facet: the local positions (into LF3[f]) of the
+// facet's lowest, middle and highest global vertex
+constexpr int PERM3[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+int dim_p3(int m);  // (m+1)(m+2)(m+3)/6
+// reference coordinates of the point (s, t) of local facet f seen in orientation p
+void facet_point3(int f, int p, double s, double t, double* xi);
+
+// Orthonormal basis of P_m on the reference triangle (d = 2) or tetrahedron
+// (d = 3): the centred monomials ((d+1)x - 1)^a ... by degree, then in
+// descending lexicographic order of the exponents, Gram-Schmidt
+// orthonormalised for `scale` times the reference measure.
+struct OrthoSimplexBasis {
+  int m, d, n;
+  std::vector<std::array<int, 3>> exps;
+  std::vector<double> coef;  // [n][n]: function j = sum_l coef[j][l] monomial l
+  OrthoSimplexBasis(int m, int d, double scale = 1.0);
+  void eval_monomials(double x, double y, double z, double* v, double (*dv)[3]) const;
+  void eval(double x, double y, double z, double* v, double* dx, double* dy, double* dz) const;
+};
+
+// Reference tables for one degree k on tetrahedra (row-major).  Facet tables
+// are indexed by fp = 6 f + p (local facet f, orientation p) and evaluated at
+// the facet rule's points in the facet's own coordinates (s, t).
+struct RefTables3 {
+  int k, ns, np, nf, nb, nned, nqc, nqf;
+  std::vector<double> cq_x, cq_y, cq_z, cq_w;    // cell rule, weights sum to 1/6
+  std::vector<double> fq_s, fq_t, fq_w;          // facet rule, weights sum to 1/2
+  std::vector<double> Bu, dBu;                   // [nqc][ns], [3][nqc][ns]
+  std::vector<double> Bp, dBp;                   // [nqc][np], [3][nqc][np]
+  std::vector<double> FBu, FdBu, FBp;            // [24][nqf][ns], [24][3][nqf][ns], [24][nqf][np]
+  std::vector<double> MU;                        // [nqf][nf] trace basis
+  std::vector<double> NUL;                       // [24][nqf][nb] BDM facet-moment basis, cell orientation
+  std::vector<double> D, R;                      // [3][np][ns]: int psi d_a phi, int d_a psi phi
+  std::vector<double> KDD;                       // [3][3][np][np] = D_a D_b^T
+  std::vector<double> That;                      // [4][np][np]  2 sum_q w psi psi on facet f
+  std::vector<double> Chat, Ehat;                // [24][nf][ns], [24][nf][np]
+  std::vector<double> CD;                        // [24][3][nf][np] = Chat D_a^T
+  std::vector<double> NEDM;                      // [nned][3][ns] interior moments of the reference Nedelec basis
+  std::vector<double> BDMinv;                    // [3ns][3ns] inverse of the reference BDM moment matrix
+};
+void build_reference3(int k, RefTables3& t);
+
+// per-cell geometry of a tetrahedron, field-major [field][cell]
+enum GeoField3 { E_DET = 0, E_IJ = 1, E_J = 10, E_N = 19, E_A = 31, kGeo3 = 35 };
+
 // ------------------------------------------------------------------- mesh
 struct HostMesh {
+  int dim = 2, nfc = 3;             // spatial dimension, facets per cell
   int64_t nv = 0, nc = 0, nF = 0;
   int64_t nvt = 0;                  // topological vertices (classes of identified vertices)
   std::vector<int32_t> vtopo;       // [nv] topological id of each vertex
   std::vector<double> coords;       // [nv][2]
   std::vector<int32_t> cells;       // [nc][3]
   std::vector<int32_t> facet_lo, facet_hi;
+  std::vector<int32_t> facet_mid;   // tetrahedra: the middle vertex of each facet
   std::vector<int32_t> cf_facet;    // [3][nc]
   std::vector<int32_t> cf_nb;       // [3][nc]  neighbour cell or -1
   std::vector<int32_t> cf_nbf;      // [3][nc]  neighbour's local facet
   std::vector<int32_t> cf_flip;     // [3][nc]  1 if the local parameter runs hi->lo
+                                    // (tetrahedra: [4][nc] orientation p of the facet)
   std::vector<int32_t> fc_cell;     // [2][nF]  K+, K- (-1 on the boundary)
   std::vector<int32_t> fc_f;        // [2][nF]
   std::vector<double> geo;          // [kGeo][nc]
 };
 enum GeoField { G_DET = 0, G_IJ00, G_IJ01, G_IJ10, G_IJ11, G_NX0, G_NY0, G_NX1, G_NY1, G_NX2, G_NY2,
                 G_H0, G_H1, G_H2, G_J00, G_J01, G_J10, G_J11, kGeo };
+
+// tetrahedral mesh (coords [nv][3], cells [nc][4], positively oriented)
+std::string build_mesh3(int64_t nv, const double* coords, int64_t nc, const int32_t* cells, HostMesh& m);
+// Kuhn split of the unit cube: coords [(n+1)^3][3], cells [6 n^3][4]
+void mesh_unit_cube(int n, double* coords, int32_t* cells);
 
 // returns empty string on success, else an error message
 std::string build_mesh(int64_t nv, const double* coords, int64_t nc, const int32_t* cells,

@@ -11,6 +11,7 @@ enum DGeo { D_DET = 0, D_IJ00, D_IJ01, D_IJ10, D_IJ11, D_NX0, D_NY0, D_NX1, D_NY
 
 struct DMesh {
   int nc, nF;
+  int dim;                 // 2: triangles; 3: tetrahedra (the launchers forward to launch3_*)
   const double* geo;       // [kDGeo][nc]
   const int* cf_facet;     // [3][nc]
   const int* cf_nb;        // [3][nc]
@@ -21,6 +22,20 @@ struct DMesh {
   const int* fc_f;         // [2][nF]
 };
 
+// Tetrahedra (d = 3): per-cell geometry fields [field][cell] (det J, J^{-1}
+// row-major, J row-major, the outward unit normals and areas of the four
+// facets); the DMesh index arrays are [4][nc] and cf_flip holds each local
+// facet's orientation p.
+enum DGeo3 { E3_DET = 0, E3_IJ = 1, E3_J = 10, E3_N = 19, E3_A = 31, kDGeo3 = 35 };
+
+// Reference tables on tetrahedra (global memory; facet tables are indexed by
+// fp = 6 * local facet + orientation).
+struct DTab3 {
+  const double *Bu, *dBu, *Bp, *dBp, *cw;           // cell rule
+  const double *FBu, *FdBu, *FBp, *fw, *MU, *NUL;   // facet rule
+  const double *D, *R, *KDD, *That, *Chat, *Ehat, *CD, *NEDM, *BDMinv;
+};
+
 // Reference tables live in the constant address space: every wave reads the
 // same entry at the same time, so the loads become scalar (s_load) loads.
 typedef const __attribute__((address_space(4))) double* cdptr;
@@ -28,6 +43,7 @@ struct DTab {
   cdptr Bu, Gux, Guy, Bp, Gpx, Gpy, cw;
   cdptr FBu, FGux, FGuy, FBp, fw, MU, NUB;
   cdptr Dx, Dy, Rx, Ry, Chat, That, Ehat, CC, KDD, CD, BDMinv, NED;
+  DTab3 t3;  // tetrahedra
 };
 
 struct DCsr {
@@ -60,6 +76,9 @@ enum BiCGSlot {
   BS_STRIDE = 16
 };
 
+// Trace-operator kernels are keyed by the facet block size and the number of
+// blocks per row: tk = k on triangles (k+1, 5 blocks), tk = 10 + k on
+// tetrahedra ((k+1)(k+2)/2, 7 blocks).
 // launchers (k = degree); all enqueue on `st`
 void launch_condense(int k, hipStream_t st, DMesh m, DTab t, double c, double tau, double* Pinv, double* SK);
 void launch_assemble(int k, hipStream_t st, DMesh m, const double* SK, double* vals, int* cols, double* Dinv);
@@ -204,5 +223,33 @@ void launch_idr_update(hipStream_t st, long n, int k, IdrCoef a, double beta, do
                        double* x, double* part);
 void launch_idr_reduce(hipStream_t st, long n, double om, const double* t, double* r, double* x, double* part);
 void launch_random(hipStream_t st, long n, unsigned long long seed, double* y);
+
+// ------------------------------------------------------------ tetrahedra
+// The same operations on tetrahedral meshes (k = 1, 2); vectors cell-major.
+void launch3_condense(int k, hipStream_t st, DMesh m, DTab3 t, double c, double tau, double* Pinv, double* SK);
+void launch3_assemble(int k, hipStream_t st, DMesh m, const double* SK, double* vals, int* cols, double* Dinv);
+void launch3_rhs_condense(int k, hipStream_t st, DMesh m, DTab3 t, double c, double tau, const double* Pinv,
+                          const double* Fw, const double* Fpsi, double* ycell);
+// cellint: scratch of nc doubles; part: ceil(nc / kBlock) partial sums of int p
+void launch3_backsub(int k, hipStream_t st, DMesh m, DTab3 t, double c, double tau, const double* Pinv,
+                     const double* Fw, const double* Fpsi, const double* lam, double* U, double* p, double* cellint,
+                     double* part);
+void launch3_shift_mean(int k, hipStream_t st, DMesh m, const double* mean, double* p, double* lam);
+// psi part into gpsi, mu part per (cell, local facet) into ycell (gathered by launch_gather_rhs)
+void launch3_gamma(int k, hipStream_t st, DMesh m, DTab3 t, double tau, double scale, const double* Q, const double* P,
+                   const double* lam, double* gpsi, double* ycell);
+void launch3_mass(int k, hipStream_t st, DMesh m, double s, const double* x, double* y);
+// per-stage Step I data: V [nc][ns][ns], beta [nc][4][nq_facet]
+void launch3_prep(int k, hipStream_t st, DMesh m, DTab3 t, const double* Qs, double delta_up, double* V, double* beta);
+// Step I operator (mode 0, with the dot variants of launch_apply_soa over
+// nparts blocks) and residuals (modes 1, 2) as launch_apply describes them
+void launch3_apply(int k, hipStream_t st, int mode, int dot, DMesh m, DTab3 t, const double* V, const double* beta,
+                   double alpha, double adt, const double* x, const double* r, const double* p, const double* lam,
+                   double* out, const double* w, const double* sd, double* part, int nparts);
+void launch3_div(int k, hipStream_t st, DMesh m, DTab3 t, const double* F, double scale, double* out);
+void launch3_bdm(int k, hipStream_t st, DMesh m, DTab3 t, const double* Q, double* Qs);
+void launch3_recon_rhs(int k, hipStream_t st, DMesh m, DTab3 t, const double* Q, double* out);
+// velocity from values at the cell points [nc][nq_cell][3]
+void launch3_project(int k, hipStream_t st, DMesh m, DTab3 t, const double* vals, double* Q);
 
 }  // namespace hdg

@@ -14,6 +14,34 @@
 
 namespace hdg {
 
+// Facet block size and blocks per row of the trace operator, keyed by tk
+// (k on triangles, 10 + k on tetrahedra).
+template <int TK>
+struct TraceDims {
+  static constexpr int NF = TK < 10 ? TK + 1 : (TK - 9) * (TK - 8) / 2;
+  static constexpr int SL = TK < 10 ? 5 : 7;
+};
+
+#define TRACE_DISPATCH(tk, CALL)     \
+  switch (tk) {                      \
+    case 1: { constexpr int KK = 1; CALL; } break; \
+    case 2: { constexpr int KK = 2; CALL; } break; \
+    case 3: { constexpr int KK = 3; CALL; } break; \
+    case 4: { constexpr int KK = 4; CALL; } break; \
+    case 11: { constexpr int KK = 11; CALL; } break; \
+    case 12: { constexpr int KK = 12; CALL; } break; \
+    default: break;                  \
+  }
+
+#define TET_TRACE_DISPATCH(tk, CALL) \
+  switch (tk) {                      \
+    case 11: { constexpr int KK = 11; CALL; } break; \
+    case 12: { constexpr int KK = 12; CALL; } break; \
+    default: break;                  \
+  }
+
+static inline int trace_key(int k, const DMesh& m) { return m.dim == 3 ? 10 + k : k; }
+
 // ===================================================================== a1
 // Local condensation.  With the orthonormal basis the velocity mass matrix is
 // det*I, so the cell problem [[M, -c D^T], [D, T]] reduces to the pressure
@@ -232,13 +260,41 @@ __global__ void __launch_bounds__(kBlock) k_spmv(int nF, const double* __restric
   for (int i = 0; i < NF; ++i) y[(long)F * NF + i] = b ? b[(long)F * NF + i] - acc[i] : acc[i];
 }
 
+// The same product on tetrahedra (tk = 10 + k: (k+1)(k+2)/2 unknowns per
+// facet, 7 blocks per row).
+template <int TK>
+__global__ void __launch_bounds__(kBlock) k_spmv_tet(int nF, const double* __restrict__ vals,
+                                                     const int* __restrict__ cols, const double* __restrict__ x,
+                                                     const double* __restrict__ b, double* __restrict__ y) {
+  constexpr int NF = TraceDims<TK>::NF, SL = TraceDims<TK>::SL;
+  const int F = blockIdx.x * blockDim.x + threadIdx.x;
+  if (F >= nF) return;
+  double acc[NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) acc[i] = 0.0;
+#pragma unroll
+  for (int s = 0; s < SL; ++s) {
+    const int col = cols[s * nF + F];
+    double xc[NF];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) xc[j] = x[(long)col * NF + j];
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+#pragma unroll
+      for (int j = 0; j < NF; ++j) acc[i] += vals[((long)(s * NF + i) * NF + j) * nF + F] * xc[j];
+  }
+#pragma unroll
+  for (int i = 0; i < NF; ++i) y[(long)F * NF + i] = b ? b[(long)F * NF + i] - acc[i] : acc[i];
+}
+
 // damped block-Jacobi sweep: xout = xin + omega Dinv (b - S xin); xin == nullptr means xin = 0
 template <int K>
 __global__ void __launch_bounds__(kBlock) k_jacobi(int nF, const double* __restrict__ vals, const int* __restrict__ cols,
                                                    const double* __restrict__ Dinv, double omega,
                                                    const double* __restrict__ b, const double* __restrict__ xin,
                                                    double* __restrict__ xout) {
-  constexpr int NF = K + 1;
+  constexpr int NF = TraceDims<K>::NF, SL = TraceDims<K>::SL;
+  (void)SL;
   const int F = blockIdx.x * blockDim.x + threadIdx.x;
   if (F >= nF) return;
   double r[NF];
@@ -246,7 +302,7 @@ __global__ void __launch_bounds__(kBlock) k_jacobi(int nF, const double* __restr
   for (int i = 0; i < NF; ++i) r[i] = b[(long)F * NF + i];
   if (xin) {
 #pragma unroll
-    for (int s = 0; s < 5; ++s) {
+    for (int s = 0; s < SL; ++s) {
       const int col = cols[s * nF + F];
       double xc[NF];
 #pragma unroll
@@ -269,7 +325,8 @@ __global__ void __launch_bounds__(kBlock) k_jacobi(int nF, const double* __restr
 template <int K>
 __global__ void __launch_bounds__(kBlock) k_blockdiag(int nF, const double* __restrict__ Dinv,
                                                       const double* __restrict__ x, double* __restrict__ y) {
-  constexpr int NF = K + 1;
+  constexpr int NF = TraceDims<K>::NF, SL = TraceDims<K>::SL;
+  (void)SL;
   const int F = blockIdx.x * blockDim.x + threadIdx.x;
   if (F >= nF) return;
   double xv[NF];
@@ -358,7 +415,8 @@ __global__ void __launch_bounds__(kBlock) k_rhs_condense(DMesh m, DTab t, double
 template <int K>
 __global__ void __launch_bounds__(kBlock) k_gather_rhs(DMesh m, const double* __restrict__ ycell,
                                                        const double* __restrict__ Fmu, double* __restrict__ gout) {
-  constexpr int NF = K + 1;
+  constexpr int NF = TraceDims<K>::NF, SL = TraceDims<K>::SL;
+  (void)SL;
   const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const int nF = m.nF;
   if (tid >= (long)nF * NF) return;
@@ -1200,47 +1258,65 @@ __global__ void k_random(long n, unsigned long long seed, double* __restrict__ y
 // ============================================================== launchers
 
 void launch_condense(int k, hipStream_t st, DMesh m, DTab t, double c, double tau, double* Pinv, double* SK) {
+  if (m.dim == 3) return launch3_condense(k, st, m, t.t3, c, tau, Pinv, SK);
   HDG_DISPATCH(k, (k_condense<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, c, tau, Pinv, SK)));
 }
 void launch_assemble(int k, hipStream_t st, DMesh m, const double* SK, double* vals, int* cols, double* Dinv) {
+  if (m.dim == 3) return launch3_assemble(k, st, m, SK, vals, cols, Dinv);
   HDG_DISPATCH(k, (k_assemble<KK><<<nblocks(m.nF), kBlock, 0, st>>>(m, SK, vals, cols, Dinv)));
 }
 void launch_spmv(int k, hipStream_t st, int nF, const double* vals, const int* cols, const double* x, double* y) {
-  HDG_DISPATCH(k, (k_spmv<KK><<<nblocks(nF), kBlock, 0, st>>>(nF, vals, cols, x, nullptr, y)));
+  if (k > 10) TET_TRACE_DISPATCH(k, (k_spmv_tet<KK><<<nblocks(nF), kBlock, 0, st>>>(nF, vals, cols, x, nullptr, y)))
+  else HDG_DISPATCH(k, (k_spmv<KK><<<nblocks(nF), kBlock, 0, st>>>(nF, vals, cols, x, nullptr, y)));
 }
 void launch_residual(int k, hipStream_t st, int nF, const double* vals, const int* cols, const double* b,
                      const double* x, double* r) {
-  HDG_DISPATCH(k, (k_spmv<KK><<<nblocks(nF), kBlock, 0, st>>>(nF, vals, cols, x, b, r)));
+  if (k > 10) TET_TRACE_DISPATCH(k, (k_spmv_tet<KK><<<nblocks(nF), kBlock, 0, st>>>(nF, vals, cols, x, b, r)))
+  else HDG_DISPATCH(k, (k_spmv<KK><<<nblocks(nF), kBlock, 0, st>>>(nF, vals, cols, x, b, r)));
 }
 void launch_jacobi_sweep(int k, hipStream_t st, int nF, const double* vals, const int* cols, const double* Dinv,
                          double omega, const double* b, const double* xin, double* xout) {
-  HDG_DISPATCH(k, (k_jacobi<KK><<<nblocks(nF), kBlock, 0, st>>>(nF, vals, cols, Dinv, omega, b, xin, xout)));
+  TRACE_DISPATCH(k, (k_jacobi<KK><<<nblocks(nF), kBlock, 0, st>>>(nF, vals, cols, Dinv, omega, b, xin, xout)));
 }
 void launch_blockdiag(int k, hipStream_t st, int nF, const double* Dinv, const double* x, double* y) {
-  HDG_DISPATCH(k, (k_blockdiag<KK><<<nblocks(nF), kBlock, 0, st>>>(nF, Dinv, x, y)));
+  TRACE_DISPATCH(k, (k_blockdiag<KK><<<nblocks(nF), kBlock, 0, st>>>(nF, Dinv, x, y)));
 }
 void launch_rhs_condense(int k, hipStream_t st, DMesh m, DTab t, double c, double tau, const double* Pinv,
                          const double* Fw, const double* Fpsi, double* ycell) {
+  if (m.dim == 3) return launch3_rhs_condense(k, st, m, t.t3, c, tau, Pinv, Fw, Fpsi, ycell);
   HDG_DISPATCH(k, (k_rhs_condense<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, c, tau, Pinv, Fw, Fpsi, ycell)));
 }
 void launch_gather_rhs(int k, hipStream_t st, DMesh m, const double* ycell, const double* Fmu, double* g) {
-  HDG_DISPATCH(k, (k_gather_rhs<KK><<<nblocks((long)m.nF * (k + 1)), kBlock, 0, st>>>(m, ycell, Fmu, g)));
+  TRACE_DISPATCH(trace_key(k, m), (k_gather_rhs<KK><<<nblocks((long)m.nF * TraceDims<KK>::NF), kBlock, 0, st>>>(
+                                        m, ycell, Fmu, g)));
 }
 void launch_backsub(int k, hipStream_t st, DMesh m, DTab t, double c, double tau, const double* Pinv,
                     const double* Fw, const double* Fpsi, const double* lam, double* U, double* p, double* part) {
+  // tetrahedra: the per-cell integrals of p go behind the partial sums in part
+  if (m.dim == 3) return launch3_backsub(k, st, m, t.t3, c, tau, Pinv, Fw, Fpsi, lam, U, p, part + nblocks(m.nc), part);
   // one partial sum per block: part holds ceil(nc / kBlock) entries
   HDG_DISPATCH(k, (k_backsub<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, c, tau, Pinv, Fw, Fpsi, lam, U, p, part)));
 }
 void launch_gamma(int k, hipStream_t st, DMesh m, DTab t, double tau, double scale, const double* Q, const double* P,
                   const double* lam, double* gpsi, double* ycell, double* gmu) {
-  HDG_DISPATCH(k, (k_gamma<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, tau, scale, Q, P, lam, gpsi, ycell)));
-  HDG_DISPATCH(k, (k_gather_rhs<KK><<<nblocks((long)m.nF * (KK + 1)), kBlock, 0, st>>>(m, ycell, nullptr, gmu)));
+  if (m.dim == 3) launch3_gamma(k, st, m, t.t3, tau, scale, Q, P, lam, gpsi, ycell);
+  else HDG_DISPATCH(k, (k_gamma<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, tau, scale, Q, P, lam, gpsi, ycell)));
+  launch_gather_rhs(k, st, m, ycell, nullptr, gmu);
 }
 void launch_prep_adv(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, double* adv) {
+  if (m.dim == 3) {  // adv: V [nc][ns][ns], then beta [nc][4][nq_facet]
+    const long ns = (k + 2) * (k + 3) * (k + 4) / 6;
+    return launch3_prep(k, st, m, t.t3, Qs, delta_up, adv, adv + (long)m.nc * ns * ns);
+  }
   HDG_DISPATCH(k, (k_prep_adv<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, Qs, delta_up, adv)));
 }
 void launch_apply(int k, hipStream_t st, int mode, DMesh m, DTab t, const double* adv, double alpha, double adt,
                   const double* x, const double* r, const double* p, const double* lam, double* out) {
+  if (m.dim == 3) {
+    const long ns = (k + 2) * (k + 3) * (k + 4) / 6;
+    return launch3_apply(k, st, mode, 0, m, t.t3, adv, adv + (long)m.nc * ns * ns, alpha, adt, x, r, p, lam, out,
+                         nullptr, nullptr, nullptr, 0);
+  }
   if (mode == 0) {
     HDG_DISPATCH(k, (k_apply<KK, 0><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, adv, alpha, adt, x, r, p, lam, out)));
   } else if (mode == 1) {
@@ -1250,13 +1326,16 @@ void launch_apply(int k, hipStream_t st, int mode, DMesh m, DTab t, const double
   }
 }
 void launch_div(int k, hipStream_t st, DMesh m, DTab t, const double* F, double scale, double* out) {
+  if (m.dim == 3) return launch3_div(k, st, m, t.t3, F, scale, out);
   HDG_DISPATCH(k, (k_div<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, F, scale, out)));
 }
 void launch_bdm(int k, hipStream_t st, DMesh m, DTab t, const double* Q, double* Qs) {
+  if (m.dim == 3) return launch3_bdm(k, st, m, t.t3, Q, Qs);
   HDG_DISPATCH(k, (k_bdm<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, Q, Qs)));
 }
 void launch_recon_rhs(int k, hipStream_t st, DMesh m, DTab t, const double* Q, const double* fcell,
                       const double* ffac, double fsc, double* out) {
+  if (m.dim == 3) return launch3_recon_rhs(k, st, m, t.t3, Q, out);  // no forcing on tetrahedra
   HDG_DISPATCH(k, (k_recon_rhs<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, Q, fcell, ffac, fsc, out)));
 }
 void launch_point_dual(int k, hipStream_t st, DMesh m, DTab t, const double* vals, double* out) {
@@ -1467,7 +1546,7 @@ __global__ void __launch_bounds__(BS) k_pcg_small(int nF, const double* __restri
                                                            double* __restrict__ pg, double* __restrict__ qg, int maxit,
                                                            double tol2, double floor2, int flat_blocks,
                                                            double* __restrict__ info) {
-  constexpr int NF = K + 1;
+  constexpr int NF = TraceDims<K>::NF, SL = TraceDims<K>::SL;
   // reduction scratch: shq for p.q, shr for the four sums of the update pass
   // (alternating areas; see small_reduce)
   __shared__ double shq[BS / 64], shr[4 * (BS / 64)];
@@ -1481,11 +1560,11 @@ __global__ void __launch_bounds__(BS) k_pcg_small(int nF, const double* __restri
   static_assert(!REG || (K == 1 && LDS), "register caching is for degree 1 with LDS vectors");
   constexpr int NR = REG ? NF : 1;
   double rD[NR][NR];
-  int rc[REG ? 5 : 1];
+  int rc[REG ? SL : 1];
   if constexpr (REG) {
     const int F = tid < nF ? tid : 0;
 #pragma unroll
-    for (int s = 0; s < 5; ++s) rc[s] = cols[s * nF + F];
+    for (int s = 0; s < SL; ++s) rc[s] = cols[s * nF + F];
 #pragma unroll
     for (int i = 0; i < NF; ++i)
 #pragma unroll
@@ -1536,9 +1615,9 @@ __global__ void __launch_bounds__(BS) k_pcg_small(int nF, const double* __restri
     // q = S p and p.q
     double pq = 0.0;
     for (int F = tid; F < nF; F += BS) {
-      double pc[5][NF];
+      double pc[SL][NF];
 #pragma unroll
-      for (int s = 0; s < 5; ++s) {
+      for (int s = 0; s < SL; ++s) {
         const int col = REG ? rc[REG ? s : 0] : cols[s * nF + F];
 #pragma unroll
         for (int j = 0; j < NF; ++j) pc[s][j] = p[col * NF + j];
@@ -1547,7 +1626,7 @@ __global__ void __launch_bounds__(BS) k_pcg_small(int nF, const double* __restri
       for (int i = 0; i < NF; ++i) {
         double acc = 0.0;
 #pragma unroll
-        for (int s = 0; s < 5; ++s)
+        for (int s = 0; s < SL; ++s)
 #pragma unroll
           for (int j = 0; j < NF; ++j) acc += vals[((long)(s * NF + i) * NF + j) * nF + F] * pc[s][j];
         q[F * NF + i] = acc;
@@ -1598,27 +1677,31 @@ void launch_pcg_small(int k, hipStream_t st, int nF, const double* vals, const i
                       const double* g, double* x, double* r, double* z, double* p, double* q, int maxit, double tol2,
                       double floor2, int flat_blocks, double* info) {
   constexpr int BS = kSmallBlock;
-  if ((long)nF * (k + 1) <= kSmallLds) {
+  const int nf = k < 10 ? k + 1 : (k - 9) * (k - 8) / 2;  // k is the trace key here
+  if ((long)nF * nf <= kSmallLds) {
     if (k == 1 && nF <= BS) {
       k_pcg_small<1, true, true, BS><<<1, BS, 0, st>>>(nF, vals, cols, Dinv, g, x, r, z, p, q, maxit, tol2, floor2,
                                                        flat_blocks, info);
     } else {
-      HDG_DISPATCH(k, (k_pcg_small<KK, true, false, BS><<<1, BS, 0, st>>>(nF, vals, cols, Dinv, g, x, r, z, p, q,
+      TRACE_DISPATCH(k, (k_pcg_small<KK, true, false, BS><<<1, BS, 0, st>>>(nF, vals, cols, Dinv, g, x, r, z, p, q,
                                                                            maxit, tol2, floor2, flat_blocks, info)));
     }
   } else {
-    HDG_DISPATCH(k, (k_pcg_small<KK, false, false, BS><<<1, BS, 0, st>>>(nF, vals, cols, Dinv, g, x, r, z, p, q,
+    TRACE_DISPATCH(k, (k_pcg_small<KK, false, false, BS><<<1, BS, 0, st>>>(nF, vals, cols, Dinv, g, x, r, z, p, q,
                                                                           maxit, tol2, floor2, flat_blocks, info)));
   }
 }
 
 void launch_project(int k, hipStream_t st, DMesh m, DTab t, const double* vals, double* Q) {
+  if (m.dim == 3) return launch3_project(k, st, m, t.t3, vals, Q);
   HDG_DISPATCH(k, (k_project<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, vals, Q)));
 }
 void launch_mass(int k, hipStream_t st, DMesh m, double s, const double* x, double* y) {
+  if (m.dim == 3) return launch3_mass(k, st, m, s, x, y);
   HDG_DISPATCH(k, (k_mass<KK><<<nblocks((long)m.nc * Dims<KK>::NU), kBlock, 0, st>>>(m, s, x, y)));
 }
 void launch_shift_mean(int k, hipStream_t st, DMesh m, const double* mean, double* p, double* lam) {
+  if (m.dim == 3) return launch3_shift_mean(k, st, m, mean, p, lam);
   const long n = m.nc > m.nF ? m.nc : m.nF;
   HDG_DISPATCH(k, (k_shift_mean<KK><<<nblocks(n), kBlock, 0, st>>>(m, mean, p, lam)));
 }

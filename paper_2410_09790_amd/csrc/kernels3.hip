@@ -1,0 +1,992 @@
+// gfx950 kernels of the HDG-IMEX library on tetrahedra (d = 3).
+//
+// The forms are those of the triangle kernels (Section 2 of the paper: the
+// mass, f_im of eq. (f_impl), g and Gamma of Section "Hybridisation", the
+// weak divergence, the BDM interpolant), with velocity [P_{k+1}]^3, pressure
+// P_k and trace P_k on triangles.  A cell's local problems are small dense
+// matrices (60 velocity, 10 pressure and 24 trace unknowns at k = 2), so one
+// 64-lane wavefront works on one cell: the lanes split the rows or entries
+// of a local matrix and the cell's data are staged in LDS.  Reference tables
+// are read through the L2; their facet tables are indexed by the local facet
+// and its orientation (fp = 6 f + p), the same for every lane of the wave.
+// Vectors are cell-major ([cell][component][basis]), as in the triangle path.
+// All reductions use a fixed grid and order (bitwise reproducible).
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+#include "kernels.h"
+
+namespace hdg {
+
+template <int K>
+struct Dims3 {
+  static constexpr int NS = (K + 2) * (K + 3) * (K + 4) / 6;
+  static constexpr int NP = (K + 1) * (K + 2) * (K + 3) / 6;
+  static constexpr int NF = (K + 1) * (K + 2) / 2;
+  static constexpr int NB = (K + 2) * (K + 3) / 2;
+  static constexpr int NNED = K * (K + 2) * (K + 3) / 2;
+  static constexpr int NU = 3 * NS;
+  static constexpr int NL = 4 * NF;
+  static constexpr int NQ1 = (3 * K + 4) / 2;
+  static constexpr int NQC = NQ1 * NQ1 * NQ1;
+  static constexpr int NQF1 = (3 * K + 5) / 2;
+  static constexpr int NQF = NQF1 * NQF1;
+};
+
+constexpr int kW3 = 64;  // lanes per cell
+
+struct Geo3 {
+  double det, ij[3][3], n[4][3], a[4];
+};
+
+__device__ __forceinline__ Geo3 load_geo3(const DMesh& m, int e) {
+  Geo3 g;
+  const double* G = m.geo;
+  const long nc = m.nc;
+  g.det = G[(long)E3_DET * nc + e];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) g.ij[a][b] = G[(long)(E3_IJ + 3 * a + b) * nc + e];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g.n[f][c] = G[(long)(E3_N + 3 * f + c) * nc + e];
+    g.a[f] = G[(long)(E3_A + f) * nc + e];
+  }
+  return g;
+}
+
+__device__ __forceinline__ void load_j3(const DMesh& m, int e, double (&J)[3][3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) J[a][b] = m.geo[(long)(E3_J + 3 * a + b) * m.nc + e];
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Gauss-Jordan inverse of an SPD n x n matrix held in LDS as [n][2n]
+// (A | I) by one wave (a 64-thread workgroup): the lanes split the entries
+// of each elimination step; col holds the step's multipliers.
+template <int N>
+__device__ void wave_invert(double (&A)[N][2 * N], double (&col)[N]) {
+  const int lane = threadIdx.x & 63;
+  for (int c = 0; c < N; ++c) {
+    __syncthreads();
+    const double piv = 1.0 / A[c][c];
+    for (int r = lane; r < N; r += 64) col[r] = A[r][c];
+    __syncthreads();
+    for (int j = lane; j < 2 * N; j += 64) A[c][j] *= piv;
+    __syncthreads();
+    for (int idx = lane; idx < N * 2 * N; idx += 64) {
+      const int r = idx / (2 * N), j = idx % (2 * N);
+      if (r != c) A[r][j] -= col[r] * A[c][j];
+    }
+  }
+  __syncthreads();
+}
+
+// ===================================================================== a1
+// Local condensation.  With orthonormal reference bases the velocity mass is
+// det I, so the cell problem reduces to the pressure Schur complement
+//   P = tau sum_f |F_f| That_f + c det sum_ab (iJ iJ^T)_ab KDD_ab,
+// and the cell's trace operator is
+//   S_K = tau |F| I + (c/det) Gl^T Gl - W^T P^{-1} W,
+//   W[i][(f,m)] = -|F_f| (c sum_a nu_fa CD[fp][a][m][i] + tau Ehat[fp][m][i]),
+//   nu_fa = sum_c iJ[a][c] n_f[c],  (Gl^T Gl) = |F_f||F_g| (n_f.n_g) Chat_f Chat_g^T.
+template <int K>
+__global__ void __launch_bounds__(kW3) k3_condense(DMesh m, DTab3 t, double c, double tau, double* __restrict__ Pinv,
+                                                   double* __restrict__ SK) {
+  using D = Dims3<K>;
+  constexpr int NS = D::NS, NP = D::NP, NF = D::NF, NL = D::NL;
+  const int e = blockIdx.x;
+  const int lane = threadIdx.x;
+  const long nc = m.nc;
+  const Geo3 g = load_geo3(m, e);
+  int fpv[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) fpv[f] = 6 * f + m.cf_flip[f * nc + e];
+  __shared__ double A[NP][2 * NP];
+  __shared__ double colb[NP];
+  __shared__ double W[NP][NL];
+  __shared__ double Y[NP][NL];
+  double Gm[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) Gm[a][b] = g.ij[a][0] * g.ij[b][0] + g.ij[a][1] * g.ij[b][1] + g.ij[a][2] * g.ij[b][2];
+  for (int idx = lane; idx < NP * NP; idx += kW3) {
+    const int i = idx / NP, j = idx % NP;
+    double v = 0.0;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) v += g.a[f] * t.That[(f * NP + i) * NP + j];
+    double dd = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) dd += Gm[a][b] * t.KDD[((a * 3 + b) * NP + i) * NP + j];
+    A[i][j] = tau * v + c * g.det * dd;
+    A[i][NP + j] = (i == j) ? 1.0 : 0.0;
+  }
+  wave_invert<NP>(A, colb);
+  for (int idx = lane; idx < NP * NP; idx += kW3) {
+    const int i = idx / NP, j = idx % NP;
+    Pinv[(long)(i * NP + j) * nc + e] = A[i][NP + j];
+  }
+  for (int idx = lane; idx < NP * NL; idx += kW3) {
+    const int i = idx / NL, r = idx % NL, f = r / NF, mm = r % NF;
+    const int fp = fpv[f];
+    double nu[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) nu[a] = g.ij[a][0] * g.n[f][0] + g.ij[a][1] * g.n[f][1] + g.ij[a][2] * g.n[f][2];
+    double v = tau * t.Ehat[(fp * NF + mm) * NP + i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v += c * nu[a] * t.CD[((fp * 3 + a) * NF + mm) * NP + i];
+    W[i][r] = -g.a[f] * v;
+  }
+  __syncthreads();
+  for (int idx = lane; idx < NP * NL; idx += kW3) {
+    const int i = idx / NL, r = idx % NL;
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) v += A[i][NP + j] * W[j][r];
+    Y[i][r] = v;
+  }
+  __syncthreads();
+  const double cod = c / g.det;
+  for (int idx = lane; idx < NL * NL; idx += kW3) {
+    const int r = idx / NL, s = idx % NL;
+    const int f = r / NF, mm = r % NF, gg = s / NF, l = s % NF;
+    const double* cf = t.Chat + (long)(fpv[f] * NF + mm) * NS;
+    const double* cg = t.Chat + (long)(fpv[gg] * NF + l) * NS;
+    double cc = 0.0;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) cc += cf[q] * cg[q];
+    const double nn = g.n[f][0] * g.n[gg][0] + g.n[f][1] * g.n[gg][1] + g.n[f][2] * g.n[gg][2];
+    double v = (r == s) ? tau * g.a[f] : 0.0;
+    v += cod * g.a[f] * g.a[gg] * nn * cc;
+    double ww = 0.0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) ww += W[i][r] * Y[i][s];
+    SK[(long)(r * NL + s) * nc + e] = v - ww;
+  }
+}
+
+// Facet-block ELL assembly of S = sum_K S_K, one thread per facet (no
+// atomics).  Slot 0: the facet itself; slots 1-3: the other facets of K+ in
+// local order; slots 4-6: those of K- (column F with zero blocks on walls).
+template <int K>
+__global__ void __launch_bounds__(kBlock) k3_assemble(DMesh m, const double* __restrict__ SK,
+                                                      double* __restrict__ vals, int* __restrict__ cols,
+                                                      double* __restrict__ Dinv) {
+  using D = Dims3<K>;
+  constexpr int NF = D::NF, NL = D::NL;
+  const int F = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nF = m.nF;
+  if (F >= nF) return;
+  const long nc = m.nc;
+  const int Kp = m.fc_cell[F], fp = m.fc_f[F], Km = m.fc_cell[nF + F], fm = m.fc_f[nF + F];
+  auto put = [&](int slot, int col, int cell, int fr, int fcol, bool add) {
+    if (!add) cols[slot * nF + F] = col;
+    for (int i = 0; i < NF; ++i)
+      for (int j = 0; j < NF; ++j) {
+        const double v = cell >= 0 ? SK[(long)((fr * NF + i) * NL + fcol * NF + j) * nc + cell] : 0.0;
+        const long idx = ((long)(slot * NF + i) * NF + j) * nF + F;
+        vals[idx] = add ? vals[idx] + v : v;
+      }
+  };
+  put(0, F, Kp, fp, fp, false);
+  if (Km >= 0) put(0, F, Km, fm, fm, true);
+  for (int o = 1; o <= 3; ++o) {
+    const int gq = (fp + o) & 3;
+    put(o, m.cf_facet[gq * nc + Kp], Kp, fp, gq, false);
+  }
+  for (int o = 1; o <= 3; ++o) {
+    if (Km >= 0) {
+      const int gq = (fm + o) & 3;
+      put(3 + o, m.cf_facet[gq * nc + Km], Km, fm, gq, false);
+    } else {
+      put(3 + o, F, -1, 0, 0, false);
+    }
+  }
+  double A[NF][NF], B[NF][NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i)
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+      A[i][j] = vals[((long)i * NF + j) * nF + F];
+      B[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+#pragma unroll
+  for (int cidx = 0; cidx < NF; ++cidx) {
+    const double dd = 1.0 / A[cidx][cidx];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) { A[cidx][j] *= dd; B[cidx][j] *= dd; }
+#pragma unroll
+    for (int r = 0; r < NF; ++r) {
+      if (r == cidx) continue;
+      const double f = A[r][cidx];
+#pragma unroll
+      for (int j = 0; j < NF; ++j) { A[r][j] -= f * A[cidx][j]; B[r][j] -= f * B[cidx][j]; }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NF; ++i)
+#pragma unroll
+    for (int j = 0; j < NF; ++j) Dinv[(long)(i * NF + j) * nF + F] = B[i][j];
+}
+
+// ================================================================ a7, a9
+// Cell data of the condensed right-hand side and the back-substitution.
+// (Gp^T F)_i = det sum_a sum_s D_a[i][s] (sum_c iJ[a][c] F_c[s]).
+template <int K>
+__device__ __forceinline__ void stage_vel(const double* __restrict__ src, int e, double* dst) {
+  constexpr int NU = Dims3<K>::NU;
+  const int lane = threadIdx.x;
+  for (int i = lane; i < NU; i += kW3) dst[i] = src ? src[(long)e * NU + i] : 0.0;
+}
+
+// p = P^{-1} (fpsi - Gp^T fw / det) with fw, fpsi in LDS, p to LDS
+template <int K>
+__device__ __forceinline__ void pressure_solve3(const DTab3& t, const Geo3& g, const double* Pinv, long nc, int e,
+                                                const double* fw, const double* fpsi, double* b, double* p) {
+  using D = Dims3<K>;
+  constexpr int NS = D::NS, NP = D::NP;
+  const int lane = threadIdx.x;
+  for (int i = lane; i < NP; i += kW3) {
+    double v = 0.0;
+    for (int s = 0; s < NS; ++s) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double u = g.ij[a][0] * fw[s] + g.ij[a][1] * fw[NS + s] + g.ij[a][2] * fw[2 * NS + s];
+        v += t.D[(a * NP + i) * NS + s] * u;
+      }
+    }
+    b[i] = fpsi[i] - v;  // f_psi - (Gp^T f_w) / det
+  }
+  __syncthreads();
+  for (int i = lane; i < NP; i += kW3) {
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) v += Pinv[(long)(i * NP + j) * nc + e] * b[j];
+    p[i] = v;
+  }
+  __syncthreads();
+}
+
+// y[(f,m)] = -(Gl^T Fw)[(f,m)] / det - (W^T p0)[(f,m)],  p0 = P^{-1}(Fpsi - Gp^T Fw / det)
+template <int K>
+__global__ void __launch_bounds__(kW3) k3_rhs_condense(DMesh m, DTab3 t, double c, double tau,
+                                                       const double* __restrict__ Pinv, const double* __restrict__ Fw,
+                                                       const double* __restrict__ Fpsi, double* __restrict__ ycell) {
+  using D = Dims3<K>;
+  constexpr int NS = D::NS, NP = D::NP, NF = D::NF, NU = D::NU, NL = D::NL;
+  const int e = blockIdx.x, lane = threadIdx.x;
+  const long nc = m.nc;
+  const Geo3 g = load_geo3(m, e);
+  __shared__ double fw[NU], fpsi[NP], b[NP], p[NP];
+  stage_vel<K>(Fw, e, fw);
+  for (int i = lane; i < NP; i += kW3) fpsi[i] = Fpsi ? Fpsi[(long)e * NP + i] : 0.0;
+  __syncthreads();
+  pressure_solve3<K>(t, g, Pinv, nc, e, fw, fpsi, b, p);
+  for (int r = lane; r < NL; r += kW3) {
+    const int f = r / NF, mm = r % NF;
+    const int fp = 6 * f + m.cf_flip[f * nc + e];
+    double cf = 0.0;  // (Chat n.fw)
+    for (int s = 0; s < NS; ++s)
+      cf += t.Chat[(fp * NF + mm) * NS + s] * (g.n[f][0] * fw[s] + g.n[f][1] * fw[NS + s] + g.n[f][2] * fw[2 * NS + s]);
+    double nu[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) nu[a] = g.ij[a][0] * g.n[f][0] + g.ij[a][1] * g.n[f][1] + g.ij[a][2] * g.n[f][2];
+    double wp = 0.0;  // -(W^T p) / |F|
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      double v = tau * t.Ehat[(fp * NF + mm) * NP + j];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) v += c * nu[a] * t.CD[((fp * 3 + a) * NF + mm) * NP + j];
+      wp += v * p[j];
+    }
+    ycell[(long)r * nc + e] = g.a[f] * (cf / g.det + wp);
+  }
+}
+
+// x = A^{-1}(f - B lam):  fw' = Fw + c Gl lam,  fpsi' = Fpsi - Tpl lam,
+// p = P^{-1}(fpsi' - Gp^T fw' / det),  U = (fw' + c Gp p) / det
+template <int K>
+__global__ void __launch_bounds__(kW3) k3_backsub(DMesh m, DTab3 t, double c, double tau,
+                                                  const double* __restrict__ Pinv, const double* __restrict__ Fw,
+                                                  const double* __restrict__ Fpsi, const double* __restrict__ lam,
+                                                  double* __restrict__ U, double* __restrict__ P,
+                                                  double* __restrict__ cellint) {
+  using D = Dims3<K>;
+  constexpr int NS = D::NS, NP = D::NP, NF = D::NF, NU = D::NU, NL = D::NL;
+  const int e = blockIdx.x, lane = threadIdx.x;
+  const long nc = m.nc;
+  const Geo3 g = load_geo3(m, e);
+  __shared__ double fw[NU], fpsi[NP], b[NP], p[NP], l[NL];
+  __shared__ int fps[4];
+  if (lane < 4) fps[lane] = 6 * lane + m.cf_flip[lane * nc + e];
+  for (int r = lane; r < NL; r += kW3) {
+    const int f = r / NF, mm = r % NF;
+    l[r] = lam[(long)m.cf_facet[f * nc + e] * NF + mm];
+  }
+  __syncthreads();
+  for (int i = lane; i < NU; i += kW3) {
+    const int cc = i / NS, s = i % NS;
+    double v = 0.0;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      double a = 0.0;
+#pragma unroll
+      for (int mm = 0; mm < NF; ++mm) a += t.Chat[(fps[f] * NF + mm) * NS + s] * l[f * NF + mm];
+      v += g.a[f] * g.n[f][cc] * a;
+    }
+    fw[i] = (Fw ? Fw[(long)e * NU + i] : 0.0) - c * v;
+  }
+  for (int i = lane; i < NP; i += kW3) {
+    double v = 0.0;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      double a = 0.0;
+#pragma unroll
+      for (int mm = 0; mm < NF; ++mm) a += t.Ehat[(fps[f] * NF + mm) * NP + i] * l[f * NF + mm];
+      v += g.a[f] * a;
+    }
+    fpsi[i] = (Fpsi ? Fpsi[(long)e * NP + i] : 0.0) + tau * v;
+  }
+  __syncthreads();
+  pressure_solve3<K>(t, g, Pinv, nc, e, fw, fpsi, b, p);
+  const double idet = 1.0 / g.det;
+  for (int i = lane; i < NU; i += kW3) {
+    const int cc = i / NS, s = i % NS;
+    double v = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double d = 0.0;
+#pragma unroll
+      for (int j = 0; j < NP; ++j) d += t.D[(a * NP + j) * NS + s] * p[j];
+      v += g.ij[a][cc] * d;
+    }
+    U[(long)e * NU + i] = fw[i] * idet + c * v;
+  }
+  for (int i = lane; i < NP; i += kW3) P[(long)e * NP + i] = p[i];
+  // int_K p = det p_0 int phi_0, phi_0 = sqrt(6) on the reference cell of volume 1/6
+  if (lane == 0 && cellint) cellint[e] = g.det * p[0] * 0.40824829046386301637;
+}
+
+// partial sums of the per-cell pressure integrals over kBlock cells
+__global__ void __launch_bounds__(kBlock) k3_sum_cells(long nc, const double* __restrict__ v, double* __restrict__ part) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const double s = block_sum(e < nc ? v[e] : 0.0);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// shift (p, lam) by -mean: p_0 -= mean / sqrt(6), lam_0 -= mean (mu_0 = 1)
+template <int K>
+__global__ void k3_shift_mean(DMesh m, const double* __restrict__ mean, double* __restrict__ p,
+                              double* __restrict__ lam) {
+  constexpr int NP = Dims3<K>::NP, NF = Dims3<K>::NF;
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const double mv = mean[0];
+  if (tid < m.nc) p[tid * NP] -= mv * 0.40824829046386301637;
+  if (tid < m.nF && lam) lam[tid * NF] -= mv;
+}
+
+// Gamma(psi, mu, Q, P, lam) times scale: psi part per cell
+//   Gp^T Q + Tpp P + Tpl lam,
+// mu part per (cell, local facet) into ycell:
+//   |F| (Chat n.Q + tau Ehat P - tau lam)
+template <int K>
+__global__ void __launch_bounds__(kW3) k3_gamma(DMesh m, DTab3 t, double tau, double scale,
+                                                const double* __restrict__ Q, const double* __restrict__ Pv,
+                                                const double* __restrict__ lam, double* __restrict__ gpsi,
+                                                double* __restrict__ ycell) {
+  using D = Dims3<K>;
+  constexpr int NS = D::NS, NP = D::NP, NF = D::NF, NU = D::NU, NL = D::NL;
+  const int e = blockIdx.x, lane = threadIdx.x;
+  const long nc = m.nc;
+  const Geo3 g = load_geo3(m, e);
+  __shared__ double q[NU], p[NP], l[NL];
+  __shared__ int fps[4];
+  if (lane < 4) fps[lane] = 6 * lane + m.cf_flip[lane * nc + e];
+  stage_vel<K>(Q, e, q);
+  for (int i = lane; i < NP; i += kW3) p[i] = Pv ? Pv[(long)e * NP + i] : 0.0;
+  for (int r = lane; r < NL; r += kW3) {
+    const int f = r / NF, mm = r % NF;
+    l[r] = lam ? lam[(long)m.cf_facet[f * nc + e] * NF + mm] : 0.0;
+  }
+  __syncthreads();
+  for (int i = lane; i < NP; i += kW3) {
+    double v = 0.0;
+    for (int s = 0; s < NS; ++s) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double u = g.ij[a][0] * q[s] + g.ij[a][1] * q[NS + s] + g.ij[a][2] * q[2 * NS + s];
+        v += t.D[(a * NP + i) * NS + s] * u;
+      }
+    }
+    double tp = 0.0;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      double a = 0.0;
+#pragma unroll
+      for (int j = 0; j < NP; ++j) a += t.That[(f * NP + i) * NP + j] * p[j];
+#pragma unroll
+      for (int mm = 0; mm < NF; ++mm) a -= t.Ehat[(fps[f] * NF + mm) * NP + i] * l[f * NF + mm];
+      tp += g.a[f] * a;
+    }
+    gpsi[(long)e * NP + i] = scale * (g.det * v + tau * tp);
+  }
+  for (int r = lane; r < NL; r += kW3) {
+    const int f = r / NF, mm = r % NF;
+    const int fp = fps[f];
+    double cq = 0.0;
+    for (int s = 0; s < NS; ++s)
+      cq += t.Chat[(fp * NF + mm) * NS + s] * (g.n[f][0] * q[s] + g.n[f][1] * q[NS + s] + g.n[f][2] * q[2 * NS + s]);
+    double ep = 0.0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) ep += t.Ehat[(fp * NF + mm) * NP + j] * p[j];
+    ycell[(long)r * nc + e] = scale * g.a[f] * (cq + tau * ep - tau * l[r]);
+  }
+}
+
+template <int K>
+__global__ void k3_mass(DMesh m, double s, const double* __restrict__ x, double* __restrict__ y) {
+  constexpr int NU = Dims3<K>::NU;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)m.nc * NU) return;
+  y[i] = s * m.geo[(long)E3_DET * m.nc + i / NU] * x[i];
+}
+
+// ================================================================ a4, a5
+// Per-stage Step I data of the advecting velocity Q* (cell-major):
+//   V[e][i][j] = -sum_q det w_q phi_i (Q*.grad phi_j)   (the volume term of
+//   f_im, the same for every velocity component), and
+//   beta[e][f][q] = |F| 2 w_q (qn/2 - delta |qn|),  qn = {Q*}.n_K at the
+//   facet point (0 on walls, where f_im has the penalty term only).
+template <int K>
+__global__ void __launch_bounds__(kW3) k3_prep(DMesh m, DTab3 t, const double* __restrict__ Qs, double delta_up,
+                                               double* __restrict__ V, double* __restrict__ beta) {
+  using D = Dims3<K>;
+  constexpr int NS = D::NS, NU = D::NU, NQC = D::NQC, NQF = D::NQF;
+  const int e = blockIdx.x, lane = threadIdx.x;
+  const long nc = m.nc;
+  const Geo3 g = load_geo3(m, e);
+  __shared__ double q[NU], qn[NU], a[3][NQC];  // a: Q* in reference directions at the cell points
+  stage_vel<K>(Qs, e, q);
+  __syncthreads();
+  for (int iq = lane; iq < NQC; iq += kW3) {
+    double u[3] = {0.0, 0.0, 0.0};
+    for (int s = 0; s < NS; ++s) {
+      const double b = t.Bu[iq * NS + s];
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) u[cc] += b * q[cc * NS + s];
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) a[r][iq] = g.det * t.cw[iq] * (g.ij[r][0] * u[0] + g.ij[r][1] * u[1] + g.ij[r][2] * u[2]);
+  }
+  __syncthreads();
+  for (int idx = lane; idx < NS * NS; idx += kW3) {
+    const int i = idx / NS, j = idx % NS;
+    double v = 0.0;
+    for (int iq = 0; iq < NQC; ++iq) {
+      const double gj = a[0][iq] * t.dBu[(0 * NQC + iq) * NS + j] + a[1][iq] * t.dBu[(1 * NQC + iq) * NS + j] +
+                        a[2][iq] * t.dBu[(2 * NQC + iq) * NS + j];
+      v += t.Bu[iq * NS + i] * gj;
+    }
+    V[((long)e * NS + i) * NS + j] = -v;
+  }
+  for (int f = 0; f < 4; ++f) {
+    const int en = m.cf_nb[f * nc + e];
+    __syncthreads();
+    if (en >= 0) {
+      for (int i = lane; i < NU; i += kW3) qn[i] = Qs[(long)en * NU + i];
+    }
+    __syncthreads();
+    const int fp = 6 * f + m.cf_flip[f * nc + e];
+    const int fpn = en >= 0 ? 6 * m.cf_nbf[f * nc + e] + m.cf_flip[m.cf_nbf[f * nc + e] * nc + en] : 0;
+    for (int iq = lane; iq < NQF; iq += kW3) {
+      double w = 0.0;
+      if (en >= 0) {
+        double u = 0.0;
+        for (int s = 0; s < NS; ++s) {
+          const double b0 = t.FBu[(fp * NQF + iq) * NS + s], b1 = t.FBu[(fpn * NQF + iq) * NS + s];
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) u += g.n[f][cc] * (b0 * q[cc * NS + s] + b1 * qn[cc * NS + s]);
+        }
+        const double qv = 0.5 * u;
+        w = g.a[f] * 2.0 * t.fw[iq] * (0.5 * qv - delta_up * fabs(qv));
+      }
+      beta[((long)e * 4 + f) * NQF + iq] = w;
+    }
+  }
+}
+
+// Step I operator / residual on cell-major vectors, one wave per cell:
+//   F = f_im(x) = V x (per component) + sum over facets and facet points of
+//       phi_i [beta (x_K - x_N) - alpha 2 w_q n (n.(x_K - x_N))]   (x_N = 0 on walls)
+//   MODE 0: out = x - (adt/det) F
+//   MODE 1: out = (r - det x + adt (F + g(p, lam))) / det
+//   MODE 2: out = r - det x + adt (F + g(p, lam))
+// DOT (MODE 0): partial inner products per block as the structure-of-arrays
+// operator leaves them (dot 1: w.out; dot 2: out.x, out.out, w.x, w.out;
+// dot 3: out.sd, out.out, w.sd, w.out), nparts blocks per set.  Blocks of
+// 4 waves walk the cells with a stride of the grid.
+template <int K, int MODE, int DOT>
+__global__ void __launch_bounds__(256) k3_apply(DMesh m, DTab3 t, const double* __restrict__ V,
+                                                const double* __restrict__ beta, double alpha, double adt,
+                                                const double* __restrict__ x, const double* __restrict__ r,
+                                                const double* __restrict__ pv, const double* __restrict__ lam,
+                                                double* __restrict__ out, const double* __restrict__ w,
+                                                const double* __restrict__ sd, double* __restrict__ part) {
+  using D = Dims3<K>;
+  constexpr int NS = D::NS, NP = D::NP, NF = D::NF, NU = D::NU, NQF = D::NQF;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const long nc = m.nc;
+  __shared__ double xs[4][5][NU];
+  __shared__ double phi[4][4][NQF][3];
+  __shared__ double red[4][4];
+  double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+  const long stride = (long)gridDim.x * 4;
+  // every wave of a block runs the same number of rounds (the barriers)
+  for (long base = (long)blockIdx.x * 4; base < nc; base += stride) {
+    const long e = base + wv;
+    const bool act = e < nc;
+    const long ec = act ? e : base;  // an inactive wave reads a valid cell and writes nothing
+    double(&X)[5][NU] = xs[wv];
+    double(&PH)[4][NQF][3] = phi[wv];
+    int nb[4], fps[4], fpn[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      nb[f] = m.cf_nb[f * nc + ec];
+      fps[f] = 6 * f + m.cf_flip[f * nc + ec];
+      const int fn = m.cf_nbf[f * nc + ec];
+      fpn[f] = nb[f] >= 0 ? 6 * fn + m.cf_flip[fn * nc + nb[f]] : 0;
+    }
+    for (int i = lane; i < NU; i += 64) X[0][i] = x[ec * NU + i];
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+      if (nb[f] >= 0)
+        for (int i = lane; i < NU; i += 64) X[1 + f][i] = x[(long)nb[f] * NU + i];
+    double nrm[4][3];
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) nrm[f][cc] = m.geo[(long)(E3_N + 3 * f + cc) * nc + ec];
+    __syncthreads();
+    for (int idx = lane; idx < 4 * NQF; idx += 64) {
+      const int f = idx / NQF, iq = idx % NQF;
+      double du[3];
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) du[cc] = 0.0;
+      const double* b0 = t.FBu + (long)(fps[f] * NQF + iq) * NS;
+      for (int s = 0; s < NS; ++s) {
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) du[cc] += b0[s] * X[0][cc * NS + s];
+      }
+      if (nb[f] >= 0) {
+        const double* b1 = t.FBu + (long)(fpn[f] * NQF + iq) * NS;
+        for (int s = 0; s < NS; ++s) {
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) du[cc] -= b1[s] * X[1 + f][cc * NS + s];
+        }
+      }
+      const double bq = beta[(ec * 4 + f) * NQF + iq];
+      const double pen = alpha * 2.0 * t.fw[iq];
+      const double dn = nrm[f][0] * du[0] + nrm[f][1] * du[1] + nrm[f][2] * du[2];
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) PH[f][iq][cc] = bq * du[cc] - pen * nrm[f][cc] * dn;
+    }
+    __syncthreads();
+    const double det = m.geo[(long)E3_DET * nc + ec];
+    for (int i = act ? lane : NU; i < NU; i += 64) {
+      const int cc = i / NS, s = i % NS;
+      double F = 0.0;
+      const double* vr = V + (e * NS + s) * NS;
+      for (int j = 0; j < NS; ++j) F += vr[j] * X[0][cc * NS + j];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        const double* b0 = t.FBu + (long)fps[f] * NQF * NS + s;
+        for (int iq = 0; iq < NQF; ++iq) F += b0[iq * NS] * PH[f][iq][cc];
+      }
+      const long gi = e * NU + i;
+      double o;
+      if constexpr (MODE == 0) {
+        o = X[0][i] - adt / det * F;
+        if constexpr (DOT == 1) {
+          d0 += w[gi] * o;
+        } else if constexpr (DOT == 2 || DOT == 3) {
+          const double xr = DOT == 2 ? X[0][i] : sd[gi];
+          d0 += o * xr;
+          d1 += o * o;
+          d2 += w[gi] * xr;
+          d3 += w[gi] * o;
+        }
+      } else {
+        // g(p, lam) = Gp p + Gl lam
+        double gpl = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          double dd = 0.0;
+#pragma unroll
+          for (int j = 0; j < NP; ++j) dd += t.D[(a * NP + j) * NS + s] * pv[e * NP + j];
+          gpl += det * m.geo[(long)(E3_IJ + 3 * a + cc) * nc + e] * dd;
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          const long Ff = m.cf_facet[f * nc + e];
+          double a = 0.0;
+#pragma unroll
+          for (int mm = 0; mm < NF; ++mm) a += t.Chat[(fps[f] * NF + mm) * NS + s] * lam[Ff * NF + mm];
+          gpl -= m.geo[(long)(E3_A + f) * nc + e] * nrm[f][cc] * a;
+        }
+        o = r[gi] - det * X[0][i] + adt * (F + gpl);
+        if constexpr (MODE == 1) o /= det;
+      }
+      out[gi] = o;
+    }
+    __syncthreads();
+  }
+  if constexpr (MODE == 0 && DOT > 0) {
+    d0 = wave_sum(d0);
+    if constexpr (DOT >= 2) { d1 = wave_sum(d1); d2 = wave_sum(d2); d3 = wave_sum(d3); }
+    if (lane == 0) { red[wv][0] = d0; red[wv][1] = d1; red[wv][2] = d2; red[wv][3] = d3; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int nb = gridDim.x, blk = blockIdx.x;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) { s0 += red[i][0]; s1 += red[i][1]; s2 += red[i][2]; s3 += red[i][3]; }
+      part[blk] = s0;
+      if constexpr (DOT >= 2) { part[nb + blk] = s1; part[2 * nb + blk] = s2; part[3 * nb + blk] = s3; }
+    }
+  }
+}
+
+// Weak divergence Div(psi, F) times scale (central flux, walls excluded):
+//   -det sum_a sum_c iJ[a][c] (R_a F_c)_i + sum_f |F_f| 2 sum_q w_q psi_i {F}.n_K
+template <int K>
+__global__ void __launch_bounds__(kW3) k3_div(DMesh m, DTab3 t, const double* __restrict__ Fv, double scale,
+                                              double* __restrict__ out) {
+  using D = Dims3<K>;
+  constexpr int NS = D::NS, NP = D::NP, NU = D::NU, NQF = D::NQF;
+  const int e = blockIdx.x, lane = threadIdx.x;
+  const long nc = m.nc;
+  const Geo3 g = load_geo3(m, e);
+  __shared__ double X[5][NU];
+  __shared__ double fl[4][NQF];
+  int nb[4], fps[4], fpn[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    nb[f] = m.cf_nb[f * nc + e];
+    fps[f] = 6 * f + m.cf_flip[f * nc + e];
+    const int fn = m.cf_nbf[f * nc + e];
+    fpn[f] = nb[f] >= 0 ? 6 * fn + m.cf_flip[fn * nc + nb[f]] : 0;
+  }
+  for (int i = lane; i < NU; i += kW3) X[0][i] = Fv[(long)e * NU + i];
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+    if (nb[f] >= 0)
+      for (int i = lane; i < NU; i += kW3) X[1 + f][i] = Fv[(long)nb[f] * NU + i];
+  __syncthreads();
+  for (int idx = lane; idx < 4 * NQF; idx += kW3) {
+    const int f = idx / NQF, iq = idx % NQF;
+    double v = 0.0;
+    if (nb[f] >= 0) {
+      const double* b0 = t.FBu + (long)(fps[f] * NQF + iq) * NS;
+      const double* b1 = t.FBu + (long)(fpn[f] * NQF + iq) * NS;
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) v += g.n[f][cc] * (b0[s] * X[0][cc * NS + s] + b1[s] * X[1 + f][cc * NS + s]);
+      v *= 0.5 * g.a[f] * 2.0 * t.fw[iq];
+    }
+    fl[f][iq] = v;
+  }
+  __syncthreads();
+  for (int i = lane; i < NP; i += kW3) {
+    double vol = 0.0;
+    for (int s = 0; s < NS; ++s) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double u = g.ij[a][0] * X[0][s] + g.ij[a][1] * X[0][NS + s] + g.ij[a][2] * X[0][2 * NS + s];
+        vol += t.R[(a * NP + i) * NS + s] * u;
+      }
+    }
+    double fac = 0.0;
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+      for (int iq = 0; iq < NQF; ++iq) fac += t.FBp[(fps[f] * NQF + iq) * NP + i] * fl[f][iq];
+    out[(long)e * NP + i] = scale * (-g.det * vol + fac);
+  }
+}
+
+// BDM interpolant by the contravariant Piola map: the reference moments of
+// Qhat = det J^{-1} Q* are the physical ones (facet moments of {Q}.n against
+// P_{k+1} of each facet, zero on walls; interior moments of Q against the
+// first-kind Nedelec space, invariant under the covariant map), so
+// Qhat* = BDMinv rhs and Q* = J Qhat* / det.
+template <int K>
+__global__ void __launch_bounds__(kW3) k3_bdm(DMesh m, DTab3 t, const double* __restrict__ Q, double* __restrict__ Qs) {
+  using D = Dims3<K>;
+  constexpr int NS = D::NS, NU = D::NU, NQF = D::NQF, NB = D::NB, NNED = D::NNED;
+  const int e = blockIdx.x, lane = threadIdx.x;
+  const long nc = m.nc;
+  const Geo3 g = load_geo3(m, e);
+  __shared__ double X[5][NU];
+  __shared__ double fl[4][NQF];
+  __shared__ double rhs[NU], qh[NU];
+  int nb[4], fps[4], fpn[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    nb[f] = m.cf_nb[f * nc + e];
+    fps[f] = 6 * f + m.cf_flip[f * nc + e];
+    const int fn = m.cf_nbf[f * nc + e];
+    fpn[f] = nb[f] >= 0 ? 6 * fn + m.cf_flip[fn * nc + nb[f]] : 0;
+  }
+  for (int i = lane; i < NU; i += kW3) X[0][i] = Q[(long)e * NU + i];
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+    if (nb[f] >= 0)
+      for (int i = lane; i < NU; i += kW3) X[1 + f][i] = Q[(long)nb[f] * NU + i];
+  __syncthreads();
+  for (int idx = lane; idx < 4 * NQF; idx += kW3) {
+    const int f = idx / NQF, iq = idx % NQF;
+    double v = 0.0;
+    if (nb[f] >= 0) {
+      const double* b0 = t.FBu + (long)(fps[f] * NQF + iq) * NS;
+      const double* b1 = t.FBu + (long)(fpn[f] * NQF + iq) * NS;
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) v += g.n[f][cc] * (b0[s] * X[0][cc * NS + s] + b1[s] * X[1 + f][cc * NS + s]);
+      v *= 0.5 * g.a[f] * 2.0 * t.fw[iq];
+    }
+    fl[f][iq] = v;
+  }
+  __syncthreads();
+  for (int r = lane; r < NU; r += kW3) {
+    double v = 0.0;
+    if (r < 4 * NB) {
+      const int f = r / NB, mm = r % NB;
+      for (int iq = 0; iq < NQF; ++iq) v += t.NUL[(fps[f] * NQF + iq) * NB + mm] * fl[f][iq];
+    } else {
+      const int l = r - 4 * NB;
+      // (Q, J^{-T} vhat)_K = det sum_b sum_c iJ[b][c] (NEDM_b Q_c)
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          const double u = g.ij[b][0] * X[0][s] + g.ij[b][1] * X[0][NS + s] + g.ij[b][2] * X[0][2 * NS + s];
+          v += t.NEDM[(l * 3 + b) * NS + s] * u;
+        }
+      v *= g.det;
+    }
+    rhs[r] = v;
+  }
+  __syncthreads();
+  (void)NNED;
+  for (int i = lane; i < NU; i += kW3) {
+    double v = 0.0;
+    for (int j = 0; j < NU; ++j) v += t.BDMinv[(long)i * NU + j] * rhs[j];
+    qh[i] = v;
+  }
+  __syncthreads();
+  double J[3][3];
+  load_j3(m, e, J);
+  for (int i = lane; i < NU; i += kW3) {
+    const int cc = i / NS, s = i % NS;
+    Qs[(long)e * NU + i] = (J[cc][0] * qh[s] + J[cc][1] * qh[NS + s] + J[cc][2] * qh[2 * NS + s]) / g.det;
+  }
+}
+
+// f_p data of the pressure reconstruction: Div(psi, (Q.grad)Q) with the
+// broken gradient at the cell points and at both sides' facet points.
+template <int K>
+__global__ void __launch_bounds__(kW3) k3_recon_rhs(DMesh m, DTab3 t, const double* __restrict__ Q,
+                                                    double* __restrict__ out) {
+  using D = Dims3<K>;
+  constexpr int NS = D::NS, NP = D::NP, NU = D::NU, NQC = D::NQC, NQF = D::NQF;
+  const int e = blockIdx.x, lane = threadIdx.x;
+  const long nc = m.nc;
+  const Geo3 g = load_geo3(m, e);
+  __shared__ double X[5][NU];
+  __shared__ double fl[4][NQF];
+  __shared__ double cv[3][NQC];  // det w_q (Q.grad)Q at the cell points
+  int nb[4], fps[4], fpn[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    nb[f] = m.cf_nb[f * nc + e];
+    fps[f] = 6 * f + m.cf_flip[f * nc + e];
+    const int fn = m.cf_nbf[f * nc + e];
+    fpn[f] = nb[f] >= 0 ? 6 * fn + m.cf_flip[fn * nc + nb[f]] : 0;
+  }
+  for (int i = lane; i < NU; i += kW3) X[0][i] = Q[(long)e * NU + i];
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+    if (nb[f] >= 0)
+      for (int i = lane; i < NU; i += kW3) X[1 + f][i] = Q[(long)nb[f] * NU + i];
+  __syncthreads();
+  // (Q.grad)Q of cell `which` at a point with basis values b and reference gradients db[a]
+  auto conv = [&](const double* Xc, const double* b, const double* db0, const double* db1, const double* db2,
+                  long dstride, const double (&ij)[3][3], double (&o)[3]) {
+    double u[3] = {0.0, 0.0, 0.0}, gr[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    for (int s = 0; s < NS; ++s) {
+      const double d[3] = {db0[s * dstride], db1[s * dstride], db2[s * dstride]};
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        const double qv = Xc[cc * NS + s];
+        u[cc] += b[s * dstride] * qv;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gr[cc][a] += d[a] * qv;  // d/d xi_a
+      }
+    }
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      double v = 0.0;
+#pragma unroll
+      for (int x = 0; x < 3; ++x) {
+        const double dxq = gr[cc][0] * ij[0][x] + gr[cc][1] * ij[1][x] + gr[cc][2] * ij[2][x];
+        v += u[x] * dxq;
+      }
+      o[cc] = v;
+    }
+  };
+  for (int iq = lane; iq < NQC; iq += kW3) {
+    double o[3];
+    conv(X[0], t.Bu + (long)iq * NS, t.dBu + (long)iq * NS, t.dBu + (long)(NQC + iq) * NS,
+         t.dBu + (long)(2 * NQC + iq) * NS, 1, g.ij, o);
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) cv[cc][iq] = g.det * t.cw[iq] * o[cc];
+  }
+  for (int idx = lane; idx < 4 * NQF; idx += kW3) {
+    const int f = idx / NQF, iq = idx % NQF;
+    double v = 0.0;
+    if (nb[f] >= 0) {
+      double o0[3], o1[3], ijn[3][3];
+      conv(X[0], t.FBu + (long)(fps[f] * NQF + iq) * NS, t.FdBu + (long)((fps[f] * 3 + 0) * NQF + iq) * NS,
+           t.FdBu + (long)((fps[f] * 3 + 1) * NQF + iq) * NS, t.FdBu + (long)((fps[f] * 3 + 2) * NQF + iq) * NS, 1,
+           g.ij, o0);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) ijn[a][b] = m.geo[(long)(E3_IJ + 3 * a + b) * nc + nb[f]];
+      conv(X[1 + f], t.FBu + (long)(fpn[f] * NQF + iq) * NS, t.FdBu + (long)((fpn[f] * 3 + 0) * NQF + iq) * NS,
+           t.FdBu + (long)((fpn[f] * 3 + 1) * NQF + iq) * NS, t.FdBu + (long)((fpn[f] * 3 + 2) * NQF + iq) * NS, 1,
+           ijn, o1);
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) v += g.n[f][cc] * 0.5 * (o0[cc] + o1[cc]);
+      v *= g.a[f] * 2.0 * t.fw[iq];
+    }
+    fl[f][iq] = v;
+  }
+  __syncthreads();
+  for (int i = lane; i < NP; i += kW3) {
+    double vol = 0.0;
+    for (int iq = 0; iq < NQC; ++iq) {
+      double gp = 0.0;
+#pragma unroll
+      for (int x = 0; x < 3; ++x) {
+        const double dpx = t.dBp[(0 * NQC + iq) * NP + i] * g.ij[0][x] + t.dBp[(1 * NQC + iq) * NP + i] * g.ij[1][x] +
+                           t.dBp[(2 * NQC + iq) * NP + i] * g.ij[2][x];
+        gp += dpx * cv[x][iq];
+      }
+      vol += gp;
+    }
+    double fac = 0.0;
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+      for (int iq = 0; iq < NQF; ++iq) fac += t.FBp[(fps[f] * NQF + iq) * NP + i] * fl[f][iq];
+    out[(long)e * NP + i] = -vol + fac;
+  }
+}
+
+// velocity coefficients from values at the cell points [nc][NQC][3]:
+// coef[c][s] = sum_q w_q phi_s(q) v_c(q) (orthonormal reference basis)
+template <int K>
+__global__ void __launch_bounds__(kW3) k3_project(DMesh m, DTab3 t, const double* __restrict__ vals,
+                                                  double* __restrict__ Q) {
+  using D = Dims3<K>;
+  constexpr int NS = D::NS, NU = D::NU, NQC = D::NQC;
+  const int e = blockIdx.x, lane = threadIdx.x;
+  for (int i = lane; i < NU; i += kW3) {
+    const int cc = i / NS, s = i % NS;
+    double v = 0.0;
+    for (int iq = 0; iq < NQC; ++iq) v += t.cw[iq] * t.Bu[iq * NS + s] * vals[((long)e * NQC + iq) * 3 + cc];
+    Q[(long)e * NU + i] = v;
+  }
+}
+
+// ============================================================== launchers
+#define HDG3_DISPATCH(k, CALL)     \
+  switch (k) {                     \
+    case 1: { constexpr int KK = 1; CALL; } break; \
+    case 2: { constexpr int KK = 2; CALL; } break; \
+    default: break;                \
+  }
+
+void launch3_condense(int k, hipStream_t st, DMesh m, DTab3 t, double c, double tau, double* Pinv, double* SK) {
+  HDG3_DISPATCH(k, (k3_condense<KK><<<m.nc, kW3, 0, st>>>(m, t, c, tau, Pinv, SK)));
+}
+void launch3_assemble(int k, hipStream_t st, DMesh m, const double* SK, double* vals, int* cols, double* Dinv) {
+  HDG3_DISPATCH(k, (k3_assemble<KK><<<nblocks(m.nF), kBlock, 0, st>>>(m, SK, vals, cols, Dinv)));
+}
+void launch3_rhs_condense(int k, hipStream_t st, DMesh m, DTab3 t, double c, double tau, const double* Pinv,
+                          const double* Fw, const double* Fpsi, double* ycell) {
+  HDG3_DISPATCH(k, (k3_rhs_condense<KK><<<m.nc, kW3, 0, st>>>(m, t, c, tau, Pinv, Fw, Fpsi, ycell)));
+}
+void launch3_backsub(int k, hipStream_t st, DMesh m, DTab3 t, double c, double tau, const double* Pinv,
+                     const double* Fw, const double* Fpsi, const double* lam, double* U, double* p, double* cellint,
+                     double* part) {
+  HDG3_DISPATCH(k, (k3_backsub<KK><<<m.nc, kW3, 0, st>>>(m, t, c, tau, Pinv, Fw, Fpsi, lam, U, p, cellint)));
+  k3_sum_cells<<<nblocks(m.nc), kBlock, 0, st>>>(m.nc, cellint, part);
+}
+void launch3_shift_mean(int k, hipStream_t st, DMesh m, const double* mean, double* p, double* lam) {
+  const long n = m.nc > m.nF ? m.nc : m.nF;
+  HDG3_DISPATCH(k, (k3_shift_mean<KK><<<nblocks(n), kBlock, 0, st>>>(m, mean, p, lam)));
+}
+void launch3_gamma(int k, hipStream_t st, DMesh m, DTab3 t, double tau, double scale, const double* Q, const double* P,
+                   const double* lam, double* gpsi, double* ycell) {
+  HDG3_DISPATCH(k, (k3_gamma<KK><<<m.nc, kW3, 0, st>>>(m, t, tau, scale, Q, P, lam, gpsi, ycell)));
+}
+void launch3_mass(int k, hipStream_t st, DMesh m, double s, const double* x, double* y) {
+  HDG3_DISPATCH(k, (k3_mass<KK><<<nblocks((long)m.nc * Dims3<KK>::NU), kBlock, 0, st>>>(m, s, x, y)));
+}
+void launch3_prep(int k, hipStream_t st, DMesh m, DTab3 t, const double* Qs, double delta_up, double* V,
+                  double* beta) {
+  HDG3_DISPATCH(k, (k3_prep<KK><<<m.nc, kW3, 0, st>>>(m, t, Qs, delta_up, V, beta)));
+}
+int apply3_blocks(long nc) { return (int)((nc + 3) / 4 < 4096 ? (nc + 3) / 4 : 4096); }
+void launch3_apply(int k, hipStream_t st, int mode, int dot, DMesh m, DTab3 t, const double* V, const double* beta,
+                   double alpha, double adt, const double* x, const double* r, const double* p, const double* lam,
+                   double* out, const double* w, const double* sd, double* part, int nparts) {
+  const int nb = nparts > 0 ? nparts : apply3_blocks(m.nc);
+  if (mode == 0) {
+    switch (dot) {
+      case 0: HDG3_DISPATCH(k, (k3_apply<KK, 0, 0><<<nb, 256, 0, st>>>(m, t, V, beta, alpha, adt, x, r, p, lam, out, w, sd, part))); break;
+      case 1: HDG3_DISPATCH(k, (k3_apply<KK, 0, 1><<<nb, 256, 0, st>>>(m, t, V, beta, alpha, adt, x, r, p, lam, out, w, sd, part))); break;
+      case 2: HDG3_DISPATCH(k, (k3_apply<KK, 0, 2><<<nb, 256, 0, st>>>(m, t, V, beta, alpha, adt, x, r, p, lam, out, w, sd, part))); break;
+      default: HDG3_DISPATCH(k, (k3_apply<KK, 0, 3><<<nb, 256, 0, st>>>(m, t, V, beta, alpha, adt, x, r, p, lam, out, w, sd, part))); break;
+    }
+  } else if (mode == 1) {
+    HDG3_DISPATCH(k, (k3_apply<KK, 1, 0><<<nb, 256, 0, st>>>(m, t, V, beta, alpha, adt, x, r, p, lam, out, w, sd, part)));
+  } else {
+    HDG3_DISPATCH(k, (k3_apply<KK, 2, 0><<<nb, 256, 0, st>>>(m, t, V, beta, alpha, adt, x, r, p, lam, out, w, sd, part)));
+  }
+}
+void launch3_div(int k, hipStream_t st, DMesh m, DTab3 t, const double* F, double scale, double* out) {
+  HDG3_DISPATCH(k, (k3_div<KK><<<m.nc, kW3, 0, st>>>(m, t, F, scale, out)));
+}
+void launch3_bdm(int k, hipStream_t st, DMesh m, DTab3 t, const double* Q, double* Qs) {
+  HDG3_DISPATCH(k, (k3_bdm<KK><<<m.nc, kW3, 0, st>>>(m, t, Q, Qs)));
+}
+void launch3_recon_rhs(int k, hipStream_t st, DMesh m, DTab3 t, const double* Q, double* out) {
+  HDG3_DISPATCH(k, (k3_recon_rhs<KK><<<m.nc, kW3, 0, st>>>(m, t, Q, out)));
+}
+void launch3_project(int k, hipStream_t st, DMesh m, DTab3 t, const double* vals, double* Q) {
+  HDG3_DISPATCH(k, (k3_project<KK><<<m.nc, kW3, 0, st>>>(m, t, vals, Q)));
+}
+
+}  // namespace hdg

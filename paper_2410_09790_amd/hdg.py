@@ -31,7 +31,7 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NOT_CO
 EXPORTS = [
     "hdg_default_params", "hdg_create", "hdg_create_periodic", "hdg_destroy", "hdg_footprint_bytes",
     "hdg_batch_create", "hdg_batch_size", "hdg_batch_advance", "hdg_batch_destroy", "hdg_advance_stages",
-    "hdg_pending_stage", "hdg_eval_points", "hdg_eval_points_noalloc", "hdg_mesh_square", "hdg_set_tracer", "hdg_get_tracer",
+    "hdg_pending_stage", "hdg_eval_points", "hdg_eval_points_noalloc", "hdg_mesh_square", "hdg_mesh_unit_cube", "hdg_set_tracer", "hdg_get_tracer",
     "hdg_cg_project", "hdg_tracer_rate", "hdg_last_error", "hdg_sizes", "hdg_cell_points",
     "hdg_facet_points", "hdg_set_forcing", "hdg_set_time", "hdg_get_time", "hdg_set_velocity_from_points", "hdg_set_state", "hdg_get_state", "hdg_advance", "hdg_solve_trace",
     "hdg_trace_matvec", "hdg_bdm_project", "hdg_weak_divergence", "hdg_momentum_residual",
@@ -60,6 +60,7 @@ class Params(ctypes.Structure):
         ("step1_xcd", ctypes.c_int),
         ("step1_precond", ctypes.c_int),
         ("step2_reading", ctypes.c_int),
+        ("dim", ctypes.c_int),
     ]
 
 
@@ -94,6 +95,7 @@ def load_library(path: str = LIB_PATH):
         "hdg_pending_stage": (I, [P]),
         "hdg_eval_points": (I, [P, P, I, P, P]),
         "hdg_eval_points_noalloc": (I, [P, P, I, P, P]),
+        "hdg_mesh_unit_cube": (I, [I, P, P]),
         "hdg_mesh_square": (I, [I, D, I, I, P, P, P]),
         "hdg_set_tracer": (I, [P, P]),
         "hdg_get_tracer": (I, [P, P]),
@@ -197,7 +199,11 @@ class Context:
         rep = None if vertex_rep is None else np.ascontiguousarray(vertex_rep, dtype=np.int32)
         if rep is not None and rep.shape != (coords.shape[0],):
             raise ValueError("vertex_rep needs one entry per vertex")
-        self.params = default_params(**_with_launch(params, cells.shape[0]))
+        if coords.ndim != 2 or coords.shape[1] not in (2, 3) or cells.shape[1:] != (coords.shape[1] + 1,):
+            raise ValueError("coords [nv][d] and cells [nc][d+1] with d = 2 or 3")
+        params = {"dim": coords.shape[1], **params}
+        self.dim = params["dim"]
+        self.params = default_params(**(_with_launch(params, cells.shape[0]) if self.dim == 2 else params))
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -235,13 +241,16 @@ class Context:
 
     # ------------------------------------------------------------- state
     def cell_points(self) -> np.ndarray:
-        xy = np.empty((self.ncells, self.nq_cell, 2))
+        xy = np.empty((self.ncells, self.nq_cell, self.dim))
         self._check(self._lib.hdg_cell_points(self._h, xy.ctypes.data_as(ctypes.c_void_p)))
         return xy
 
     def facet_points(self) -> np.ndarray:
         nqf = (3 * self.degree + 5) // 2
-        xy = np.empty((self.ncells, 3, nqf, 2))
+        if self.dim == 3:  # the facet rule on triangles: nqf^2 points
+            xy = np.empty((self.ncells, 4, nqf * nqf, 3))
+        else:
+            xy = np.empty((self.ncells, 3, nqf, 2))
         self._check(self._lib.hdg_facet_points(self._h, xy.ctypes.data_as(ctypes.c_void_p)))
         return xy
 
@@ -267,6 +276,8 @@ class Context:
     def set_velocity_from_points(self, values):
         import torch
         v = torch.as_tensor(np.ascontiguousarray(values, dtype=np.float64)).to(self.device)
+        if v.numel() != self.ncells * self.nq_cell * self.dim:
+            raise ValueError(f"expected values at the cell points, shape ({self.ncells}, {self.nq_cell}, {self.dim})")
         self._check(self._lib.hdg_set_velocity_from_points(self._h, _ptr(v)))
 
     def set_state(self, Q, p, lam):
@@ -446,6 +457,17 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def mesh_unit_cube(n: int):
+    """The library's Kuhn mesh of the unit cube (6 n^3 tetrahedra): (coords, cells)."""
+    lib = load_library()
+    coords = np.empty(((n + 1) ** 3, 3), dtype=np.float64)
+    cells = np.empty((6 * n ** 3, 4), dtype=np.int32)
+    st = lib.hdg_mesh_unit_cube(int(n), coords.ctypes.data_as(ctypes.c_void_p), cells.ctypes.data_as(ctypes.c_void_p))
+    if st != 0:
+        raise HDGError(st, "invalid mesh size")
+    return coords, cells
 
 
 def mesh_square(n: int, length: float = 1.0, periodic: bool = False, diagonal: int = 0):

@@ -240,3 +240,41 @@ def test_library_mesh_other_diagonal(lib_path):
     assert hdg.footprint_bytes(X, C, 1e-3, degree=2) > 0
     Xp, Cp, rep = hdg.mesh_square(4, 2.0, periodic=True, diagonal=1)
     assert hdg.footprint_bytes(Xp, Cp, 1e-3, vertex_rep=rep, degree=1) > 0
+
+
+def test_library_cube_mesh_follows_the_documented_recipe(lib_path):
+    """hdg_mesh_unit_cube (host only) gives the Kuhn mesh of the input recipe."""
+    import hdg_inputs as hi
+    from paper_2410_09790_amd import hdg
+    for n in (1, 2, 3):
+        X, C = hdg.mesh_unit_cube(n)
+        X0, C0 = hi.unit_cube_mesh(n)
+        assert np.array_equal(X, X0) and np.array_equal(C, C0)
+    with pytest.raises(hdg.HDGError):
+        hdg.mesh_unit_cube(0)
+
+
+def test_tetrahedra_parameters_are_checked_on_the_host(lib_path):
+    """dim, degree, precision and mesh orientation on tetrahedra are checked
+    before any device work (no GPU needed)."""
+    import hdg_inputs as hi
+    from paper_2410_09790_amd import hdg
+    lib = hdg.load_library()
+    assert hdg.default_params().dim == 2
+    X, C = hi.unit_cube_mesh(1)
+    h = ctypes.c_void_p()
+
+    def create(p, X=X, C=C):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        C = np.ascontiguousarray(C, dtype=np.int32)
+        return lib.hdg_create(X.shape[0], X.ctypes.data_as(ctypes.c_void_p), C.shape[0],
+                              C.ctypes.data_as(ctypes.c_void_p), ctypes.byref(p), None, ctypes.byref(h))
+
+    assert create(hdg.default_params(dim=4)) == 1 and b"dim" in lib.hdg_last_error(None)
+    assert create(hdg.default_params(dim=3, degree=3)) == 6 and b"tetrahedra" in lib.hdg_last_error(None)
+    assert create(hdg.default_params(dim=3, degree=2, precision="mixed")) == 6
+    bad = C.copy()
+    bad[:, [2, 3]] = bad[:, [3, 2]]  # negatively oriented
+    assert create(hdg.default_params(dim=3, degree=2), C=bad) == 1
+    assert b"positively oriented" in lib.hdg_last_error(None)
+    assert not h.value
