@@ -107,6 +107,29 @@ def algorithmic_cost(kernel: str, k: int, nc: int, nF: int, nF_int: int | None =
     return None, None
 
 
+def algorithmic_cost_tet(kernel: str, k: int, nc: int, nF: int):
+    """(bytes, flops) per launch on tetrahedra (ns = (k+2)(k+3)(k+4)/6 per
+    velocity component, nf = (k+1)(k+2)/2 per facet, nq = ceil((3k+4)/2)^2
+    facet points).  trace_spmv: per facet row 7 blocks of nf^2 values (the
+    three of a wall facet's missing neighbour included: the ELL kernel reads
+    them), 7 int32 column ids, x read and y written.  apply_step1_operator:
+    per cell the ns x ns volume matrix, 4 nq upwind weights, det J and the
+    four normals (13 doubles), 16 int32 connectivity entries, the input,
+    output and inner-product vectors (3 x 3 ns doubles); flops: per
+    component 2 ns^2 for the volume term and per facet point 2 (3 ns) for
+    each of the own trace, the neighbour trace and the test sum."""
+    ns = (k + 2) * (k + 3) * (k + 4) // 6
+    nf = (k + 1) * (k + 2) // 2
+    nq = ((3 * k + 5) // 2) ** 2
+    if kernel == "trace_spmv":
+        return nF * (8 * 7 * nf * nf + 4 * 7 + 8 * 2 * nf), nF * 2 * 7 * nf * nf
+    if kernel == "apply_step1_operator":
+        nbytes = nc * (8 * (ns * ns + 4 * nq + 13 + 3 * 3 * ns) + 4 * 16)
+        flops = nc * (3 * 2 * ns * ns + 4 * nq * (3 * 2 * 3 * ns + 15))
+        return nbytes, flops
+    return None, None
+
+
 def method_bytes(kernel: str, k: int, nc: int):
     """Bytes per launch of the Step I operator if it read only what the method
     itself defines per cell: the input, output and inner-product vectors
@@ -236,6 +259,102 @@ def trace_operator_run(hdg, hi, torch, n: int = 512, k: int = 3, calls: int = 40
            if measured_traffic("trace_spmv_512") else None}
     log(f"trace operator {n}x{n} k={k}: {avg * 1e6:.1f} us per application, {gbs:.0f} GB/s "
         f"({gbs / HBM_PEAK_GBS:.3f} of peak)")
+    ctx.close()
+    return out
+
+
+TET_WORKLOAD = {"n": 32, "k": 2, "seed": 0, "scheme": "ars233", "dt": 1e-3, "n_richardson": 3,
+                "trace_solver": "mg_pcg", "rtol_trace": 1e-12, "rtol_velocity": 1e-10}
+
+
+def tet_run(hdg, hi, torch, n: int, steps: int, warmup: int, trace_calls: int = 20, pc_lag: int = 2):
+    """The three-dimensional workload: the unit cube in n^3 Kuhn cubes (6 n^3
+    tetrahedra), k = 2, the curl of the seeded vector potential, ARS(2,3,3),
+    dt = 1e-3, n_R = 3, MG-PCG, the paper's tolerances, FP64, the Step I
+    preconditioner rebuilt once per step (pc_lag stages; the two stages of
+    a step have the same adt).  Reports trace
+    DOF-stages/s over `steps` timed steps, the kernel classes with their
+    rooflines, and the assembled trace operator (c = gamma dt) applied
+    `trace_calls` times with event timing (out of the last-level cache at
+    n = 32)."""
+    import numpy as np
+    w = TET_WORKLOAD
+    k = w["k"]
+    X, C = hi.unit_cube_mesh(n)
+    t0 = time.perf_counter()
+    ctx = hdg.Context(X, C, degree=k, imex=w["scheme"], n_richardson=w["n_richardson"],
+                      trace_solver=w["trace_solver"], rtol_trace=w["rtol_trace"], rtol_velocity=w["rtol_velocity"],
+                      step1_precond_lag=pc_lag)
+    par = hi.vector_potential_params(w["seed"])
+    xyz = ctx.cell_points()
+    ctx.set_velocity_from_points(hi.curl_potential_velocity(par, xyz[..., 0], xyz[..., 1], xyz[..., 2]))
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    log(f"tet {n}^3: setup {setup:.2f} s, {ctx.ncells} cells, {ctx.nT} trace DOFs, {ctx.nQ} velocity DOFs")
+    t0 = time.perf_counter()
+    ctx.advance(w["dt"], warmup)
+    torch.cuda.synchronize()
+    log(f"tet {n}^3: warmup {warmup} step(s) {time.perf_counter() - t0:.2f} s")
+    before = ctx.info()
+    ctx.profile(PROFILE_EVERY)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.advance(w["dt"], steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    info = ctx.info()
+    ctx.profile(0)
+    Q, _, _ = ctx.get_state()
+    assert bool(torch.isfinite(Q).all()), "non-finite velocity"
+    stages = 2  # ARS(2,3,3): two implicit stages per step
+    value = ctx.nT * stages * steps / el
+    d = {key: info[key] - before[key] for key in ("pcg_iterations_total", "trace_solves", "velocity_iterations_total",
+                                                   "velocity_solves", "bicgstab_restarts", "pcg_floor_stops")}
+    log(f"tet {n}^3: {steps} steps {el:.3f} s, {1e3 * el / steps:.1f} ms/step, {value:.4g} trace DOF-stages/s; "
+        f"PCG {d['pcg_iterations_total']} its / {d['trace_solves']} solves, Step I "
+        f"{d['velocity_iterations_total']} its / {d['velocity_solves']} solves")
+    kernels = {}
+    for name, kv in info.get("kernels", {}).items():
+        if not kv.get("timed"):
+            continue
+        avg = kv["ms"] / kv["timed"] * 1e-3
+        rec = {"avg_launch_us": round(avg * 1e6, 2), "launches": kv["launches"],
+               "share_of_step": round(avg * kv["launches"] / el, 3)}
+        nb, fl = algorithmic_cost_tet(name, k, ctx.ncells, ctx.nfacets)
+        if nb is not None:
+            rec.update({"algorithmic_bytes_per_launch": nb, "achieved_GBps": round(nb / avg / 1e9, 1),
+                        "frac_hbm": round(nb / avg / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_flops_per_launch": fl,
+                        "achieved_TFLOPs": round(fl / avg / 1e12, 3),
+                        "frac_fp64": round(fl / avg / 1e12 / FP64_PEAK_TFLOPS, 4)})
+        kernels[name] = rec
+        log(f"  tet {name:24s} {kv['launches']:7d} launches {avg * 1e6:9.1f} us/launch, "
+            f"{rec['share_of_step']:.3f} of the step")
+    # the assembled trace operator alone (c = gamma dt), event-timed
+    c = (3.0 + 3.0 ** 0.5) / 6.0 * w["dt"]
+    x = torch.as_tensor(np.random.default_rng(3).standard_normal(ctx.nT)).cuda()
+    ctx.trace_matvec(c, x)
+    ctx.profile(1)
+    for _ in range(trace_calls):
+        ctx.trace_matvec(c, x)
+    kv = ctx.info()["kernels"]["trace_spmv"]
+    ctx.profile(0)
+    avg = kv["ms"] / kv["timed"] * 1e-3
+    nb, _ = algorithmic_cost_tet("trace_spmv", k, ctx.ncells, ctx.nfacets)
+    gbs = nb / avg / 1e9
+    trace = {"avg_launch_us": round(avg * 1e6, 2), "launches": kv["timed"], "algorithmic_bytes_per_launch": nb,
+             "achieved_GBps": round(gbs, 1), "peak": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4),
+             "traffic": measured_traffic("trace_spmv_tet")}
+    log(f"tet {n}^3 trace operator: {avg * 1e6:.1f} us per application, {nb / 1e6:.1f} MB, {gbs:.0f} GB/s "
+        f"({gbs / HBM_PEAK_GBS:.3f} of peak)")
+    out = {"workload": f"unit_cube_{n}^3_kuhn_k{k}_ars233 ({ctx.ncells} tetrahedra, {ctx.nT} trace DOFs)",
+           "metric": "trace DOF-IMEX-stages/sec (FP64)", "value": value, "unit": "trace-DOF-stages/s",
+           "steps": steps, "warmup": warmup, "ms_per_step": 1e3 * el / steps, "setup_s": round(setup, 2),
+           "dt": w["dt"], "n_richardson": w["n_richardson"], "rtol_trace": w["rtol_trace"],
+           "rtol_velocity": w["rtol_velocity"], "step1_precond_lag": pc_lag,
+           "pcg_iterations_per_solve": round(d["pcg_iterations_total"] / max(d["trace_solves"], 1), 1),
+           "velocity_iterations_per_solve": round(d["velocity_iterations_total"] / max(d["velocity_solves"], 1), 1),
+           "bicgstab_restarts": d["bicgstab_restarts"], "pcg_floor_stops": d["pcg_floor_stops"],
+           "kernels": kernels, "trace_operator": trace}
     ctx.close()
     return out
 
@@ -585,6 +704,12 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-instances sample")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sample")
     ap.add_argument("--no-trace-op", action="store_true", help="skip the out-of-cache trace-operator leg")
+    ap.add_argument("--no-tet", action="store_true", help="skip the three-dimensional (tetrahedra) leg")
+    ap.add_argument("--tet-n", type=int, default=TET_WORKLOAD["n"], help="cubes per side of the 3D leg")
+    ap.add_argument("--tet-steps", type=int, default=2, help="timed steps of the 3D leg (workload: 10)")
+    ap.add_argument("--tet-only", action="store_true", help="run only the three-dimensional leg")
+    ap.add_argument("--tet-pc-lag", type=int, default=2,
+                    help="stages between rebuilds of the 3D leg's Step I preconditioner (2: once per step)")
     ap.add_argument("--batched-instances", type=int, default=4, help="instances of the batched sample (recipe: 64)")
     ap.add_argument("--batched-steps", type=int, default=1, help="timed steps of the batched sample (recipe: 10)")
     ap.add_argument("--serving-jobs", type=int, default=16, help="jobs of the serving sample (recipe: 200)")
@@ -614,6 +739,10 @@ def main():
         serving = serving_run(hdg, hi, torch, args.serving_jobs, args.serving_nmax, args.serving_steps,
                               tuple(args.serving_rho), tuple(args.serving_workers))
         print(json.dumps({"metric": "serving job latency p50/p99 (s) and throughput", "serving": serving}), flush=True)
+        return
+    if args.tet_only:
+        tet = tet_run(hdg, hi, torch, args.tet_n, args.tet_steps, args.warmup, pc_lag=args.tet_pc_lag)
+        print(json.dumps({"metric": "trace DOF-IMEX-stages/sec (FP64), tetrahedra", "tet": tet}), flush=True)
         return
     if args.copy_probe:
         # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE counters
@@ -731,6 +860,9 @@ def main():
     trace_op = None
     if not args.no_trace_op:
         trace_op = trace_operator_run(hdg, hi, torch)
+    tet = None
+    if not args.no_tet:
+        tet = tet_run(hdg, hi, torch, args.tet_n, args.tet_steps, args.warmup, pc_lag=args.tet_pc_lag)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -770,6 +902,7 @@ def main():
         "batched": batched,
         "serving": serving,
         "trace_operator_out_of_cache": trace_op,
+        "tetrahedra": tet,
     }
     if mixed is not None:
         mixed["speedup_vs_fp64"] = round(mixed["value"] / value, 3)

@@ -158,6 +158,10 @@ typedef struct {
                             weight adt/h^2 as it does for cell blocks.  Device memory: 8 nu^2 +
                             12 nu^2 bytes per cell (nu = (k+2)(k+3)). */
   int step2_reading;     /* hdg_step2_reading */
+  int step1_precond_lag; /* the Step I preconditioner is rebuilt when the stage's adt changes and
+                            otherwise every this many stages (1, the default: every stage; its
+                            Q* is then that of the stage).  A lagged preconditioner changes the
+                            iteration count only, never the solution. */
   int dim;               /* 2: triangles (coords [nv][2], cells [nc][3]); 3: tetrahedra (coords
                             [nv][3], cells [nc][4], positively oriented, degree 1..2, FP64; the
                             method is stated for d = 2 and 3 in Sections "Discontinuous Galerkin
@@ -168,8 +172,8 @@ typedef struct {
                             monomials ((d+1)x - 1)^a.. by degree and then descending exponents,
                             Gram-Schmidt orthonormalised on the reference cell (trace: for twice
                             the reference triangle's measure).  Not available on tetrahedra:
-                            periodic meshes, forcing, the tracer, point evaluation, the mixed
-                            precision and the Step I preconditioner (step1_precond is ignored). */
+                            periodic meshes, forcing, the tracer, point evaluation and the mixed
+                            precision. */
 } hdg_params;
 
 /* Fill p with the defaults: k=1, tau=alpha=delta_up=1, ARS(2,2,2), n_R=3,

@@ -392,9 +392,13 @@ struct hdg_ctx {
   void* pcB = nullptr;            // patch inverses (FP16)
   long pc_builds = 0;
   void pc_prepare(double adt) {
-    if (!pc_on || (pc_gen == vk_gen && pc_adt == adt)) return;
+    // rebuilt for a new adt, else when the stage data are step1_precond_lag generations newer
+    if (!pc_on || (pc_adt == adt && pc_gen >= 0 && vk_gen - pc_gen < prm.step1_precond_lag)) return;
     hdg::Timed tm(prof, hdg::KC_PC_BUILD);
-    hdg::launch_pc_build(k, st, dm, dt, vk_qs, prm.delta_up, prm.alpha, adt, pcD, pcB);
+    if (dim == 3)  // from the stage's V and beta (prepare_step1)
+      hdg::launch3_pc_build(k, st, dm, dt.t3, (const double*)vk, (const double*)vbeta, prm.alpha, adt, pcD, pcB);
+    else
+      hdg::launch_pc_build(k, st, dm, dt, vk_qs, prm.delta_up, prm.alpha, adt, pcD, pcB);
     KCHK();
     pc_gen = vk_gen;
     pc_adt = adt;
@@ -402,7 +406,8 @@ struct hdg_ctx {
   }
   void pc_apply(const void* r, void* z) {
     hdg::Timed tm(prof, hdg::KC_PC_APPLY);
-    hdg::launch_pc_apply(k, st, dm, pcB, r, z, kx32);
+    if (dim == 3) hdg::launch3_pc_apply(k, st, dm, pcB, (const double*)r, (double*)z);
+    else hdg::launch_pc_apply(k, st, dm, pcB, r, z, kx32);
   }
   int bicgstab(double adt, const double* b, double* x);
   static constexpr int kBicgBlock = 8;  // BiCGStab iterations per captured block
@@ -540,7 +545,7 @@ void hdg_ctx::setup_tet() {
   DTab3& t = dt.t3;
   t.Bu = upload(rt3.Bu); t.dBu = upload(rt3.dBu); t.Bp = upload(rt3.Bp); t.dBp = upload(rt3.dBp);
   t.cw = upload(rt3.cq_w);
-  t.FBu = upload(rt3.FBu); t.FdBu = upload(rt3.FdBu); t.FBp = upload(rt3.FBp); t.fw = upload(rt3.fq_w);
+  t.FBu = upload(rt3.FBu); t.FBuT = upload(rt3.FBuT); t.FdBu = upload(rt3.FdBu); t.FBp = upload(rt3.FBp); t.fw = upload(rt3.fq_w);
   t.MU = upload(rt3.MU); t.NUL = upload(rt3.NUL);
   t.D = upload(rt3.D); t.R = upload(rt3.R); t.KDD = upload(rt3.KDD); t.That = upload(rt3.That);
   t.Chat = upload(rt3.Chat); t.Ehat = upload(rt3.Ehat); t.CD = upload(rt3.CD); t.NEDM = upload(rt3.NEDM);
@@ -569,14 +574,17 @@ void hdg_ctx::setup_work() {
   for (void** v : {&kd.b, &kd.x, &kd.r, &kd.rh, &kd.s, &kd.t, &kd.p, &kd.v}) *v = kvec();
   // the facet-patch preconditioner needs every cell on an interior facet
   // (else a cell would receive no correction)
-  pc_on = prm.step1_precond == 1 && prm.idr_s == 0 && dim == 2;
-  for (long e = 0; pc_on && e < nc; ++e)
-    pc_on = hm.cf_nb[e] >= 0 || hm.cf_nb[nc + e] >= 0 || hm.cf_nb[2 * nc + e] >= 0;
+  pc_on = prm.step1_precond == 1 && prm.idr_s == 0;
+  for (long e = 0; pc_on && e < nc; ++e) {
+    bool any = false;
+    for (int f = 0; f < nfc; ++f) any = any || hm.cf_nb[f * nc + e] >= 0;
+    pc_on = any;
+  }
   if (pc_on) {
     kd.ph = kvec();
     kd.sh = kvec();
     pcD = dalloc<double>(nc * nu * nu);
-    pcB = dalloc<uint16_t>(pc_entries(k, nc));
+    pcB = dalloc<uint16_t>(dim == 3 ? pc_entries3(k, nc) : pc_entries(k, nc));
   }
   const long nc32 = (nc + 31) / 32 * 32;
   vk32 = prm.precision == HDG_MIXED;
@@ -689,7 +697,7 @@ void hdg_ctx::build_mg(TraceOp& op) {
   Csr Rt = csr_transpose(Pt);
   Csr Ac = csr_multiply(Rt, csr_multiply(S, Pt));
   AmgHierarchy h;
-  amg_setup(Ac, h, 200);
+  amg_setup(Ac, h, 200, dim == 2);
   auto up = [&](const Csr& A) {
     DCsr d;
     d.n = (int)A.nrows;
@@ -1698,6 +1706,7 @@ void hdg_default_params(hdg_params* p) {
   p->step1_xcd = 1;
   p->step1_precond = 1;
   p->step2_reading = HDG_STEP2_PRINTED;
+  p->step1_precond_lag = 1;
   p->dim = 2;
 }
 
@@ -1726,7 +1735,7 @@ int hdg_create_periodic(int64_t nv, const double* coords, int64_t nc, const int3
       prm->precision < 0 || prm->precision > 1 || prm->use_graphs < 0 || prm->use_graphs > 1 ||
       (prm->step1_block != 64 && prm->step1_block != 128 && prm->step1_block != 256) || prm->step1_xcd < 0 ||
       prm->step1_xcd > 1 || prm->step1_precond < 0 || prm->step1_precond > 1 || prm->step2_reading < 0 ||
-      prm->step2_reading > 1) {
+      prm->step2_reading > 1 || prm->step1_precond_lag < 1) {
     g_create_error = "invalid parameter";
     return HDG_ERR_INVALID_ARG;
   }

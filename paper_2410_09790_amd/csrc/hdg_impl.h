@@ -97,6 +97,7 @@ struct RefTables3 {
   std::vector<double> Bu, dBu;                   // [nqc][ns], [3][nqc][ns]
   std::vector<double> Bp, dBp;                   // [nqc][np], [3][nqc][np]
   std::vector<double> FBu, FdBu, FBp;            // [24][nqf][ns], [24][3][nqf][ns], [24][nqf][np]
+  std::vector<double> FBuT;                      // [24][ns][nqf] (FBu with the points fastest)
   std::vector<double> MU;                        // [nqf][nf] trace basis
   std::vector<double> NUL;                       // [24][nqf][nb] BDM facet-moment basis, cell orientation
   std::vector<double> D, R;                      // [3][np][ns]: int psi d_a phi, int d_a psi phi
@@ -159,7 +160,7 @@ struct AmgHierarchy {
   int64_t ncoarse = 0;
   std::vector<double> coarse_pinv;  // dense pseudo-inverse of the coarsest operator
 };
-void amg_setup(const Csr& A, AmgHierarchy& h, int64_t coarsest = 200);
+void amg_setup(const Csr& A, AmgHierarchy& h, int64_t coarsest = 200, bool smooth = true);
 Csr csr_transpose(const Csr& A);
 Csr csr_multiply(const Csr& A, const Csr& B);
 

@@ -33,6 +33,7 @@ enum DGeo3 { E3_DET = 0, E3_IJ = 1, E3_J = 10, E3_N = 19, E3_A = 31, kDGeo3 = 35
 struct DTab3 {
   const double *Bu, *dBu, *Bp, *dBp, *cw;           // cell rule
   const double *FBu, *FdBu, *FBp, *fw, *MU, *NUL;   // facet rule
+  const double* FBuT;                                // FBu with the facet points fastest
   const double *D, *R, *KDD, *That, *Chat, *Ehat, *CD, *NEDM, *BDMinv;
 };
 
@@ -239,7 +240,7 @@ void launch3_shift_mean(int k, hipStream_t st, DMesh m, const double* mean, doub
 void launch3_gamma(int k, hipStream_t st, DMesh m, DTab3 t, double tau, double scale, const double* Q, const double* P,
                    const double* lam, double* gpsi, double* ycell);
 void launch3_mass(int k, hipStream_t st, DMesh m, double s, const double* x, double* y);
-// per-stage Step I data: V [nc][ns][ns], beta [nc][4][nq_facet]
+// per-stage Step I data: V [nc][ns][ns] (transposed: [cell][trial][test]), beta [nc][4][nq_facet]
 void launch3_prep(int k, hipStream_t st, DMesh m, DTab3 t, const double* Qs, double delta_up, double* V, double* beta);
 // Step I operator (mode 0, with the dot variants of launch_apply_soa over
 // nparts blocks) and residuals (modes 1, 2) as launch_apply describes them
@@ -249,6 +250,13 @@ void launch3_apply(int k, hipStream_t st, int mode, int dot, DMesh m, DTab3 t, c
 void launch3_div(int k, hipStream_t st, DMesh m, DTab3 t, const double* F, double scale, double* out);
 void launch3_bdm(int k, hipStream_t st, DMesh m, DTab3 t, const double* Q, double* Qs);
 void launch3_recon_rhs(int k, hipStream_t st, DMesh m, DTab3 t, const double* Q, double* out);
+// Step I preconditioner on tetrahedra (facet-patch additive Schwarz): built
+// from the per-stage V and beta of launch3_prep (D: scratch of nc nu^2
+// doubles; Binv: pc_entries3(k, nc) FP16 entries); z = B r on cell-major vectors
+void launch3_pc_build(int k, hipStream_t st, DMesh m, DTab3 t, const double* V, const double* beta, double alpha,
+                      double adt, double* D, void* Binv);
+void launch3_pc_apply(int k, hipStream_t st, DMesh m, const void* Binv, const double* r, double* z);
+long pc_entries3(int k, long nc);
 // velocity from values at the cell points [nc][nq_cell][3]
 void launch3_project(int k, hipStream_t st, DMesh m, DTab3 t, const double* vals, double* Q);
 

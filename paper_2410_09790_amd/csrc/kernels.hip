@@ -261,30 +261,38 @@ __global__ void __launch_bounds__(kBlock) k_spmv(int nF, const double* __restric
 }
 
 // The same product on tetrahedra (tk = 10 + k: (k+1)(k+2)/2 unknowns per
-// facet, 7 blocks per row).
+// facet, 7 blocks per row).  A facet row holds 7 x 36 values at k = 2, too
+// many for one thread's registers (one wave per SIMD), so a workgroup takes
+// 64 facets and each of its NF waves one row of their blocks: every value
+// load is still coalesced across the wave (facet index fastest), the waves
+// share the column ids and x entries through the L1, and the NF results of a
+// facet are staged in LDS so that y is written in contiguous runs.
 template <int TK>
-__global__ void __launch_bounds__(kBlock) k_spmv_tet(int nF, const double* __restrict__ vals,
-                                                     const int* __restrict__ cols, const double* __restrict__ x,
-                                                     const double* __restrict__ b, double* __restrict__ y) {
+__global__ void __launch_bounds__(64 * TraceDims<TK>::NF) k_spmv_tet(int nF, const double* __restrict__ vals,
+                                                                   const int* __restrict__ cols,
+                                                                   const double* __restrict__ x,
+                                                                   const double* __restrict__ b,
+                                                                   double* __restrict__ y) {
   constexpr int NF = TraceDims<TK>::NF, SL = TraceDims<TK>::SL;
-  const int F = blockIdx.x * blockDim.x + threadIdx.x;
-  if (F >= nF) return;
-  double acc[NF];
+  __shared__ double sy[NF][64];
+  const int lane = threadIdx.x & 63, i = threadIdx.x >> 6;
+  const long F0 = (long)blockIdx.x * 64;
+  const long F = F0 + lane;
+  if (F < nF) {
+    double acc = 0.0;
 #pragma unroll
-  for (int i = 0; i < NF; ++i) acc[i] = 0.0;
+    for (int s = 0; s < SL; ++s) {
+      const long col = cols[s * (long)nF + F];
+      const double* xc = x + col * NF;
+      const double* v = vals + ((long)(s * NF + i) * NF) * nF + F;
 #pragma unroll
-  for (int s = 0; s < SL; ++s) {
-    const int col = cols[s * nF + F];
-    double xc[NF];
-#pragma unroll
-    for (int j = 0; j < NF; ++j) xc[j] = x[(long)col * NF + j];
-#pragma unroll
-    for (int i = 0; i < NF; ++i)
-#pragma unroll
-      for (int j = 0; j < NF; ++j) acc[i] += vals[((long)(s * NF + i) * NF + j) * nF + F] * xc[j];
+      for (int j = 0; j < NF; ++j) acc += v[(long)j * nF] * xc[j];
+    }
+    sy[i][lane] = b ? b[F * NF + i] - acc : acc;
   }
-#pragma unroll
-  for (int i = 0; i < NF; ++i) y[(long)F * NF + i] = b ? b[(long)F * NF + i] - acc[i] : acc[i];
+  __syncthreads();
+  const long idx = F0 * NF + threadIdx.x;  // contiguous run of this block's outputs
+  if (idx < (long)nF * NF) y[idx] = sy[threadIdx.x % NF][threadIdx.x / NF];
 }
 
 // damped block-Jacobi sweep: xout = xin + omega Dinv (b - S xin); xin == nullptr means xin = 0
@@ -1266,12 +1274,14 @@ void launch_assemble(int k, hipStream_t st, DMesh m, const double* SK, double* v
   HDG_DISPATCH(k, (k_assemble<KK><<<nblocks(m.nF), kBlock, 0, st>>>(m, SK, vals, cols, Dinv)));
 }
 void launch_spmv(int k, hipStream_t st, int nF, const double* vals, const int* cols, const double* x, double* y) {
-  if (k > 10) TET_TRACE_DISPATCH(k, (k_spmv_tet<KK><<<nblocks(nF), kBlock, 0, st>>>(nF, vals, cols, x, nullptr, y)))
+  if (k > 10) TET_TRACE_DISPATCH(k, (k_spmv_tet<KK><<<(nF + 63) / 64, 64 * TraceDims<KK>::NF, 0, st>>>(
+                                            nF, vals, cols, x, nullptr, y)))
   else HDG_DISPATCH(k, (k_spmv<KK><<<nblocks(nF), kBlock, 0, st>>>(nF, vals, cols, x, nullptr, y)));
 }
 void launch_residual(int k, hipStream_t st, int nF, const double* vals, const int* cols, const double* b,
                      const double* x, double* r) {
-  if (k > 10) TET_TRACE_DISPATCH(k, (k_spmv_tet<KK><<<nblocks(nF), kBlock, 0, st>>>(nF, vals, cols, x, b, r)))
+  if (k > 10) TET_TRACE_DISPATCH(k, (k_spmv_tet<KK><<<(nF + 63) / 64, 64 * TraceDims<KK>::NF, 0, st>>>(
+                                            nF, vals, cols, x, b, r)))
   else HDG_DISPATCH(k, (k_spmv<KK><<<nblocks(nF), kBlock, 0, st>>>(nF, vals, cols, x, b, r)));
 }
 void launch_jacobi_sweep(int k, hipStream_t st, int nF, const double* vals, const int* cols, const double* Dinv,

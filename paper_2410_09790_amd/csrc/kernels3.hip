@@ -465,8 +465,9 @@ __global__ void k3_mass(DMesh m, double s, const double* __restrict__ x, double*
 
 // ================================================================ a4, a5
 // Per-stage Step I data of the advecting velocity Q* (cell-major):
-//   V[e][i][j] = -sum_q det w_q phi_i (Q*.grad phi_j)   (the volume term of
-//   f_im, the same for every velocity component), and
+//   V[e][j][i] = -sum_q det w_q phi_i (Q*.grad phi_j)   (the volume term of
+//   f_im, the same for every velocity component; stored with the test index
+//   i fastest, so that the lanes of the operator read it coalesced), and
 //   beta[e][f][q] = |F| 2 w_q (qn/2 - delta |qn|),  qn = {Q*}.n_K at the
 //   facet point (0 on walls, where f_im has the penalty term only).
 template <int K>
@@ -499,7 +500,7 @@ __global__ void __launch_bounds__(kW3) k3_prep(DMesh m, DTab3 t, const double* _
                         a[2][iq] * t.dBu[(2 * NQC + iq) * NS + j];
       v += t.Bu[iq * NS + i] * gj;
     }
-    V[((long)e * NS + i) * NS + j] = -v;
+    V[((long)e * NS + j) * NS + i] = -v;  // stored transposed: V[e][j][i]
   }
   for (int f = 0; f < 4; ++f) {
     const int en = m.cf_nb[f * nc + e];
@@ -528,7 +529,7 @@ __global__ void __launch_bounds__(kW3) k3_prep(DMesh m, DTab3 t, const double* _
 }
 
 // Step I operator / residual on cell-major vectors, one wave per cell:
-//   F = f_im(x) = V x (per component) + sum over facets and facet points of
+//   F = f_im(x) = V x (per component, V stored transposed) + sum over facets and facet points of
 //       phi_i [beta (x_K - x_N) - alpha 2 w_q n (n.(x_K - x_N))]   (x_N = 0 on walls)
 //   MODE 0: out = x - (adt/det) F
 //   MODE 1: out = (r - det x + adt (F + g(p, lam))) / det
@@ -555,7 +556,9 @@ __global__ void __launch_bounds__(256) k3_apply(DMesh m, DTab3 t, const double* 
   const long stride = (long)gridDim.x * 4;
   // every wave of a block runs the same number of rounds (the barriers)
   for (long base = (long)blockIdx.x * 4; base < nc; base += stride) {
-    const long e = base + wv;
+    // the cell index is the same on every lane of the wave: keep it (and all
+    // per-cell scalars loaded with it) in scalar registers
+    const long e = (long)__builtin_amdgcn_readfirstlane((int)(base + wv));
     const bool act = e < nc;
     const long ec = act ? e : base;  // an inactive wave reads a valid cell and writes nothing
     double(&X)[5][NU] = xs[wv];
@@ -584,16 +587,19 @@ __global__ void __launch_bounds__(256) k3_apply(DMesh m, DTab3 t, const double* 
       double du[3];
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc) du[cc] = 0.0;
-      const double* b0 = t.FBu + (long)(fps[f] * NQF + iq) * NS;
+      // points fastest: the lanes of one facet read consecutive table entries
+      const double* b0 = t.FBuT + (long)fps[f] * NS * NQF + iq;
+#pragma unroll 4
       for (int s = 0; s < NS; ++s) {
 #pragma unroll
-        for (int cc = 0; cc < 3; ++cc) du[cc] += b0[s] * X[0][cc * NS + s];
+        for (int cc = 0; cc < 3; ++cc) du[cc] += b0[s * NQF] * X[0][cc * NS + s];
       }
       if (nb[f] >= 0) {
-        const double* b1 = t.FBu + (long)(fpn[f] * NQF + iq) * NS;
+        const double* b1 = t.FBuT + (long)fpn[f] * NS * NQF + iq;
+#pragma unroll 4
         for (int s = 0; s < NS; ++s) {
 #pragma unroll
-          for (int cc = 0; cc < 3; ++cc) du[cc] -= b1[s] * X[1 + f][cc * NS + s];
+          for (int cc = 0; cc < 3; ++cc) du[cc] -= b1[s * NQF] * X[1 + f][cc * NS + s];
         }
       }
       const double bq = beta[(ec * 4 + f) * NQF + iq];
@@ -607,11 +613,13 @@ __global__ void __launch_bounds__(256) k3_apply(DMesh m, DTab3 t, const double* 
     for (int i = act ? lane : NU; i < NU; i += 64) {
       const int cc = i / NS, s = i % NS;
       double F = 0.0;
-      const double* vr = V + (e * NS + s) * NS;
-      for (int j = 0; j < NS; ++j) F += vr[j] * X[0][cc * NS + j];
+      const double* vr = V + e * NS * NS + s;
+#pragma unroll 4
+      for (int j = 0; j < NS; ++j) F += vr[j * NS] * X[0][cc * NS + j];
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
         const double* b0 = t.FBu + (long)fps[f] * NQF * NS + s;
+#pragma unroll 5
         for (int iq = 0; iq < NQF; ++iq) F += b0[iq * NS] * PH[f][iq][cc];
       }
       const long gi = e * NU + i;
@@ -919,6 +927,262 @@ __global__ void __launch_bounds__(kW3) k3_project(DMesh m, DTab3 t, const double
   }
 }
 
+// ================================================= Step I preconditioner
+// Additive Schwarz over facet patches, as on triangles: per interior facet F
+// with cells K+ and K-, A_F is the restriction of the mass-scaled Step I
+// operator to the 2 NU unknowns of the two cells, and z = B r sums, for each
+// cell, its rows of A_F^{-1} applied to (r_K, r_neighbour) over the cell's
+// interior facets.  The patches contain the fields whose normal component
+// is continuous across F, on which the penalty term of eq. (f_impl)
+// vanishes, so the iteration count does not grow with that term's weight.
+// Storage: per (cell, local facet), NU rows of 2 NU FP16 entries (own
+// columns first), as quads of 4 in tiles of 32 cells (cell fastest).
+using pc3_t = _Float16;
+typedef _Float16 f16x4_3 __attribute__((ext_vector_type(4)));
+template <int K>
+struct PcLayout3 {
+  static constexpr int NU = Dims3<K>::NU, NQ = 2 * NU / 4;
+  __device__ static long quad(long e, int f, int i, int jq) {
+    return ((((e >> 5) * 4 + f) * (long)NU + i) * NQ + jq) * 32 + (e & 31);
+  }
+};
+__device__ __forceinline__ pc3_t pc3_store(double v) {
+  const double lim = 65504.0;  // largest finite FP16
+  return (pc3_t)(v > lim ? lim : (v < -lim ? -lim : v));
+}
+
+// Own-cell block D_K = I - (adt/det) (volume term + own-side facet terms of
+// the four facets), FP64 [cell][row][col], rows and columns (c, s).  One
+// wave per cell; from the per-stage V (transposed) and beta of k3_prep:
+//   D[(c,s)][(c',s')] = delta - (adt/det) (delta_cc' (V_ss' + Mb_ss')
+//                        - alpha sum_f n_fc n_fc' Mp_f,ss'),
+//   Mb = sum_f sum_q beta_fq phi_s phi_s',  Mp_f = sum_q 2 w_q phi_s phi_s'.
+template <int K>
+__global__ void __launch_bounds__(kW3) k3_pc_cellblock(DMesh m, DTab3 t, const double* __restrict__ V,
+                                                       const double* __restrict__ beta, double alpha, double adt,
+                                                       double* __restrict__ Dout) {
+  using D = Dims3<K>;
+  constexpr int NS = D::NS, NU = D::NU, NQF = D::NQF;
+  const int e = blockIdx.x, lane = threadIdx.x;
+  const long nc = m.nc;
+  const Geo3 g = load_geo3(m, e);
+  __shared__ double mb[NS * NS], mp[4][NS * NS];
+  int fps[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) fps[f] = 6 * f + m.cf_flip[f * nc + e];
+  for (int idx = lane; idx < NS * NS; idx += kW3) {
+    const int s = idx / NS, s2 = idx % NS;
+    double b = 0.0;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      double pm = 0.0;
+      const double* tb = t.FBu + (long)fps[f] * NQF * NS;
+      for (int q = 0; q < NQF; ++q) {
+        const double pp = tb[q * NS + s] * tb[q * NS + s2];
+        b += beta[((long)e * 4 + f) * NQF + q] * pp;
+        pm += 2.0 * t.fw[q] * pp;
+      }
+      mp[f][idx] = pm;
+    }
+    mb[idx] = b + V[((long)e * NS + s2) * NS + s];  // V stored [trial][test]
+  }
+  __syncthreads();
+  const double sc = adt / g.det;
+  for (int idx = lane; idx < NU * NU; idx += kW3) {
+    const int i = idx / NU, j = idx % NU;
+    const int c = i / NS, s = i % NS, c2 = j / NS, s2 = j % NS;
+    double v = c == c2 ? mb[s * NS + s2] : 0.0;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) v -= alpha * g.n[f][c] * g.n[f][c2] * mp[f][s * NS + s2];
+    Dout[(long)e * NU * NU + idx] = (i == j ? 1.0 : 0.0) - sc * v;
+  }
+}
+
+// Threads of the patch kernel: NC column slots (64 per wave) times NH row
+// parts: each thread holds HN = N / NH rows of a column (four parts, so that
+// eight waves share the elimination of the 120 x 120 block at k = 2).
+template <int K>
+struct PcPatchShape3 {
+  static constexpr int NU = Dims3<K>::NU, N = 2 * NU;
+  static constexpr int NC = (N + 63) / 64 * 64;
+  static constexpr int NH = 4;
+  static constexpr int HN = N / NH;
+  static_assert(HN * NH == N, "rows split evenly");
+  static constexpr int NT = NC * NH;
+};
+
+// One workgroup per facet: A_F assembled in LDS from the two cell blocks and
+// the coupling through F,
+//   C[(c,s) of row cell][(c',s') of column cell] =
+//     (adt/det_row) sum_q phi_s phi'_s' (beta_row,q delta_cc' - alpha 2 w_q n_c n_c'),
+// (both cells see the facet's points in the facet's own order), inverted in
+// registers by Gauss-Jordan elimination without pivoting (the symmetric part
+// of A_F is positive definite, as on triangles), and each cell's rows of the
+// inverse stored (own columns first).  Wall facets return at once.
+template <int K>
+__global__ void __launch_bounds__(PcPatchShape3<K>::NT) k3_pc_patch(DMesh m, DTab3 t,
+                                                                    const double* __restrict__ beta, double alpha,
+                                                                    double adt, const double* __restrict__ Dc,
+                                                                    pc3_t* __restrict__ Binv) {
+  using Dm = Dims3<K>;
+  using Sh = PcPatchShape3<K>;
+  constexpr int NS = Dm::NS, NU = Dm::NU, NQF = Dm::NQF, N = Sh::N, NC = Sh::NC, HN = Sh::HN;
+  const int F = blockIdx.x;
+  const long nc = m.nc;
+  const int Km = m.fc_cell[m.nF + F];
+  if (Km < 0) return;  // wall facet (uniform over the workgroup)
+  const int Kp = m.fc_cell[F];
+  const int fp = m.fc_f[F], fm = m.fc_f[m.nF + F];
+  auto cell = [&](int side) { return side ? Km : Kp; };
+  auto lf = [&](int side) { return side ? fm : fp; };
+  const int tp = 6 * fp + m.cf_flip[fp * nc + Kp], tm = 6 * fm + m.cf_flip[fm * nc + Km];
+  auto tab = [&](int side) { return side ? tm : tp; };
+  __shared__ double sA[N][N + 1];
+  __shared__ double scol[2][N], srow[2][NC];
+  // the facet's data of both sides, then the three NS x NS facet matrices
+  //   Mb_side[s][s'] = sum_q beta_side,q phi^side_s phi^other_s',
+  //   Mw[s][s'] = sum_q 2 w_q phi^+_s phi^-_s'
+  // (every quantity the coupling blocks need, computed once per patch)
+  __shared__ double tb[2][NQF][NS], bq[2][NQF], w2[NQF];
+  __shared__ double Mb[2][NS][NS], Mw[NS][NS];
+  const int j = threadIdx.x % NC, h = threadIdx.x / NC;
+  const int jc = j < N ? j : 0;
+  for (int idx = threadIdx.x; idx < 2 * NQF * NS; idx += Sh::NT) {
+    const int side = idx / (NQF * NS), rem = idx % (NQF * NS);
+    tb[side][rem / NS][rem % NS] = t.FBu[(long)tab(side) * NQF * NS + rem];
+  }
+  for (int idx = threadIdx.x; idx < 2 * NQF; idx += Sh::NT) {
+    const int side = idx / NQF, q = idx % NQF;
+    bq[side][q] = beta[((long)cell(side) * 4 + lf(side)) * NQF + q];
+  }
+  for (int q = threadIdx.x; q < NQF; q += Sh::NT) w2[q] = 2.0 * t.fw[q];
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < 3 * NS * NS; idx += Sh::NT) {
+    const int which = idx / (NS * NS), s = (idx / NS) % NS, s2 = idx % NS;
+    double v = 0.0;
+    if (which < 2) {
+      for (int q = 0; q < NQF; ++q) v += bq[which][q] * tb[which][q][s] * tb[1 - which][q][s2];
+      Mb[which][s][s2] = v;
+    } else {
+      for (int q = 0; q < NQF; ++q) v += w2[q] * tb[0][q][s] * tb[1][q][s2];
+      Mw[s][s2] = v;
+    }
+  }
+  // the two cell blocks, a flat coalesced copy
+  for (int idx = threadIdx.x; idx < 2 * NU * NU; idx += Sh::NT) {
+    const int side = idx / (NU * NU), rem = idx % (NU * NU);
+    sA[side * NU + rem / NU][side * NU + rem % NU] = Dc[(long)cell(side) * NU * NU + rem];
+  }
+  __syncthreads();
+  // coupling blocks: row cell rs, column cell 1 - rs
+  for (int idx = threadIdx.x; idx < 2 * NU * NU; idx += Sh::NT) {
+    const int rs = idx / (NU * NU), rem = idx % (NU * NU);
+    const int rr = rem / NU, jj = rem % NU;
+    const int cr = rr / NS, sr = rr % NS, cj = jj / NS, s2 = jj % NS;
+    const int eo = cell(rs), fo = lf(rs);
+    const double nr = m.geo[(long)(E3_N + 3 * fo + cr) * nc + eo], nj = m.geo[(long)(E3_N + 3 * fo + cj) * nc + eo];
+    const double mw = rs == 0 ? Mw[sr][s2] : Mw[s2][sr];
+    const double v = (cr == cj ? Mb[rs][sr][s2] : 0.0) - alpha * nr * nj * mw;
+    sA[rs * NU + rr][(1 - rs) * NU + jj] = adt / m.geo[(long)E3_DET * nc + eo] * v;
+  }
+  __syncthreads();
+  double col[HN];
+#pragma unroll
+  for (int r = 0; r < HN; ++r) col[r] = sA[h * HN + r][jc];
+#pragma unroll 1
+  for (int p = 0; p < N; ++p) {
+    double* cp = scol[p & 1];
+    double* rp = srow[p & 1];
+    const int hp = p / HN, lp = p % HN;
+    if (j == p) {
+#pragma unroll
+      for (int r = 0; r < HN; ++r) cp[h * HN + r] = col[r];
+    }
+    if (h == hp) {
+      double v = 0.0;
+#pragma unroll
+      for (int r = 0; r < HN; ++r) v = r == lp ? col[r] : v;
+      rp[j] = v;
+    }
+    __syncthreads();
+    const double d = 1.0 / cp[p];
+    if (j == p) {
+#pragma unroll
+      for (int r = 0; r < HN; ++r) col[r] = (h == hp && r == lp) ? d : -cp[h * HN + r] * d;
+    } else {
+      const double a = rp[j] * d;
+#pragma unroll
+      for (int r = 0; r < HN; ++r) col[r] = (h == hp && r == lp) ? a : col[r] - cp[h * HN + r] * a;
+    }
+  }
+  if (j >= N) return;
+  // rows h HN .. h HN + HN - 1 (all of one side), column j: for K+ the
+  // column order is (own, neighbour); for K- its own columns are those of side 1
+  const int side = (h * HN) / NU;
+  const int jb = side == 0 ? j : (j >= NU ? j - NU : j + NU);
+#pragma unroll
+  for (int r = 0; r < HN; ++r)
+    Binv[4 * PcLayout3<K>::quad(cell(side), lf(side), (h * HN + r) % NU, jb >> 2) + (jb & 3)] = pc3_store(col[r]);
+}
+
+// z = B r on cell-major vectors: thread (cell e, row group g) sums over the
+// cell's interior facets its rows of A_F^{-1} applied to (r_e, r_neighbour).
+template <int K>
+struct PcApplyShape3 {
+  static constexpr int NU = Dims3<K>::NU;
+  static constexpr int G = K == 1 ? 3 : 6;  // row groups per cell
+  static constexpr int RG = NU / G;
+  static_assert(RG * G == NU, "rows split evenly");
+};
+template <int K>
+__global__ void __launch_bounds__(kBlock) k3_pc_apply(DMesh m, const pc3_t* __restrict__ Binv,
+                                                      const double* __restrict__ r, double* __restrict__ z) {
+  using Sh = PcApplyShape3<K>;
+  constexpr int NU = Dims3<K>::NU, NQ = PcLayout3<K>::NQ, G = Sh::G, RG = Sh::RG;
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nc = m.nc;
+  const long tile = tid / (G * 32);
+  const int rem = (int)(tid % (G * 32));
+  const int g = rem >> 5;
+  const long e = tile * 32 + (rem & 31);
+  if (e >= nc) return;
+  double acc[RG];
+#pragma unroll
+  for (int a = 0; a < RG; ++a) acc[a] = 0.0;
+  const f16x4_3* B4 = reinterpret_cast<const f16x4_3*>(Binv);
+#pragma unroll 1
+  for (int f = 0; f < 4; ++f) {
+    const long en = m.cf_nb[f * nc + e];
+    if (en < 0) continue;
+    const double* ro = r + e * NU;
+    const double* rn = r + en * NU;
+#pragma unroll 1
+    for (int jq = 0; jq < NQ; ++jq) {
+      // column 4 jq + u: own entries first, then the neighbour's (a quad may
+      // straddle the two when NU is not a multiple of 4)
+      double xv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int jx = 4 * jq + u;
+        xv[u] = *(jx < NU ? ro + jx : rn + (jx - NU));
+      }
+      const double x0 = xv[0], x1 = xv[1], x2 = xv[2], x3 = xv[3];
+#pragma unroll
+      for (int a = 0; a < RG; ++a) {
+        const f16x4_3 b = __builtin_nontemporal_load(&B4[PcLayout3<K>::quad(e, f, g * RG + a, jq)]);
+        acc[a] += (double)b.x * x0 + (double)b.y * x1 + (double)b.z * x2 + (double)b.w * x3;
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < RG; ++a) z[e * NU + g * RG + a] = acc[a];
+}
+
+long pc_entries3(int k, long nc) {
+  const long nu = 3L * (k + 2) * (k + 3) * (k + 4) / 6;
+  return (nc + 31) / 32 * 32 * 4 * nu * 2 * nu;
+}
+
 // ============================================================== launchers
 #define HDG3_DISPATCH(k, CALL)     \
   switch (k) {                     \
@@ -984,6 +1248,16 @@ void launch3_bdm(int k, hipStream_t st, DMesh m, DTab3 t, const double* Q, doubl
 }
 void launch3_recon_rhs(int k, hipStream_t st, DMesh m, DTab3 t, const double* Q, double* out) {
   HDG3_DISPATCH(k, (k3_recon_rhs<KK><<<m.nc, kW3, 0, st>>>(m, t, Q, out)));
+}
+void launch3_pc_build(int k, hipStream_t st, DMesh m, DTab3 t, const double* V, const double* beta, double alpha,
+                      double adt, double* D, void* Binv) {
+  HDG3_DISPATCH(k, (k3_pc_cellblock<KK><<<m.nc, kW3, 0, st>>>(m, t, V, beta, alpha, adt, D)));
+  HDG3_DISPATCH(k, (k3_pc_patch<KK><<<m.nF, PcPatchShape3<KK>::NT, 0, st>>>(m, t, beta, alpha, adt, D,
+                                                                             (pc3_t*)Binv)));
+}
+void launch3_pc_apply(int k, hipStream_t st, DMesh m, const void* Binv, const double* r, double* z) {
+  HDG3_DISPATCH(k, (k3_pc_apply<KK><<<nblocks((m.nc + 31) / 32 * 32 * PcApplyShape3<KK>::G), kBlock, 0, st>>>(
+                        m, (const pc3_t*)Binv, r, z)));
 }
 void launch3_project(int k, hipStream_t st, DMesh m, DTab3 t, const double* vals, double* Q) {
   HDG3_DISPATCH(k, (k3_project<KK><<<m.nc, kW3, 0, st>>>(m, t, vals, Q)));

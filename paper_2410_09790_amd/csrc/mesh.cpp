@@ -14,7 +14,9 @@
 // product P^T S P and is solved approximately by one smoothed-aggregation
 // V-cycle (standard greedy aggregation, Jacobi-smoothed tentative
 // prolongator, damped Jacobi smoothing, dense pseudo-inverse on the coarsest
-// level); the paper uses PETSc's GAMG for this level.
+// level); the paper uses PETSc's GAMG for this level.  On tetrahedra the
+// tentative prolongator is used unsmoothed: smoothing it fills the Galerkin
+// coarse operators of the three-dimensional P1 stencil far more than in 2D.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -278,7 +280,7 @@ static void sym_pinv(int64_t n, const Csr& A, std::vector<double>& out) {
   }
 }
 
-void amg_setup(const Csr& A0, AmgHierarchy& h, int64_t coarsest) {
+void amg_setup(const Csr& A0, AmgHierarchy& h, int64_t coarsest, bool smooth) {
   h.levels.clear();
   Csr A = A0;
   while (A.nrows > coarsest) {
@@ -303,11 +305,16 @@ void amg_setup(const Csr& A0, AmgHierarchy& h, int64_t coarsest) {
     T.idx.assign(agg.begin(), agg.end());
     T.val.resize(n);
     for (int64_t i = 0; i < n; ++i) T.val[i] = 1.0 / std::sqrt(cnt[agg[i]]);
-    Csr AT = csr_multiply(A, T);  // P = T - omega D^{-1} A T
+    Csr AT = smooth ? csr_multiply(A, T) : Csr{};  // P = T - omega D^{-1} A T (smooth), else P = T
     Csr P;
     P.nrows = n; P.ncols = na;
     P.ptr.assign(n + 1, 0);
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t i = 0; i < n && !smooth; ++i) {
+      P.idx.push_back(agg[i]);
+      P.val.push_back(T.val[i]);
+      P.ptr[i + 1] = (int32_t)P.idx.size();
+    }
+    for (int64_t i = 0; i < n && smooth; ++i) {
       std::vector<std::pair<int32_t, double>> row;
       for (int32_t p = AT.ptr[i]; p < AT.ptr[i + 1]; ++p) row.push_back({AT.idx[p], -L.omega * L.dinv[i] * AT.val[p]});
       bool found = false;

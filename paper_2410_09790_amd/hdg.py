@@ -60,6 +60,7 @@ class Params(ctypes.Structure):
         ("step1_xcd", ctypes.c_int),
         ("step1_precond", ctypes.c_int),
         ("step2_reading", ctypes.c_int),
+        ("step1_precond_lag", ctypes.c_int),
         ("dim", ctypes.c_int),
     ]
 
