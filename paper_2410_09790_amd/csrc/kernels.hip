@@ -262,37 +262,104 @@ __global__ void __launch_bounds__(kBlock) k_spmv(int nF, const double* __restric
 
 // The same product on tetrahedra (tk = 10 + k: (k+1)(k+2)/2 unknowns per
 // facet, 7 blocks per row).  A facet row holds 7 x 36 values at k = 2, too
-// many for one thread's registers (one wave per SIMD), so a workgroup takes
-// 64 facets and each of its NF waves one row of their blocks: every value
-// load is still coalesced across the wave (facet index fastest), the waves
-// share the column ids and x entries through the L1, and the NF results of a
-// facet are staged in LDS so that y is written in contiguous runs.
+// many for one thread's registers, so a workgroup takes 64 facets and each
+// of its NF waves one row of their blocks: every value load is coalesced
+// across the wave (facet index fastest).  The column ids and the x entries
+// the 64 rows touch are gathered once per workgroup into LDS (the NF waves
+// would otherwise each gather them again), and the NF results of a facet are
+// staged in LDS so that y is written in contiguous runs.
 template <int TK>
-__global__ void __launch_bounds__(64 * TraceDims<TK>::NF) k_spmv_tet(int nF, const double* __restrict__ vals,
-                                                                   const int* __restrict__ cols,
-                                                                   const double* __restrict__ x,
-                                                                   const double* __restrict__ b,
-                                                                   double* __restrict__ y) {
+struct TetRowsShape {
+  static constexpr int NF = TraceDims<TK>::NF, SL = TraceDims<TK>::SL, NT = 64 * NF;
+};
+// gathers cols and x of facets F0 .. F0 + 63 into sc[s][f], sx[s][j][f]
+template <int TK>
+__device__ __forceinline__ void tet_gather(int nF, long F0, const int* __restrict__ cols,
+                                           const double* __restrict__ x, int (&sc)[TraceDims<TK>::SL][64],
+                                           double (&sx)[TraceDims<TK>::SL][TraceDims<TK>::NF][64]) {
+  constexpr int NF = TraceDims<TK>::NF, SL = TraceDims<TK>::SL, NT = TetRowsShape<TK>::NT;
+  for (int idx = threadIdx.x; idx < SL * 64; idx += NT) {
+    const int sl = idx / 64, fl = idx % 64;
+    sc[sl][fl] = F0 + fl < nF ? cols[sl * (long)nF + F0 + fl] : 0;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < SL * 64 * NF; idx += NT) {
+    const int sl = idx / (64 * NF), rem = idx % (64 * NF), fl = rem / NF, jj = rem % NF;
+    sx[sl][jj][fl] = x[(long)sc[sl][fl] * NF + jj];  // consecutive threads: one facet's entries
+  }
+  __syncthreads();
+}
+template <int TK>
+__global__ void __launch_bounds__(TetRowsShape<TK>::NT) k_spmv_tet(int nF, const double* __restrict__ vals,
+                                                                 const int* __restrict__ cols,
+                                                                 const double* __restrict__ x,
+                                                                 const double* __restrict__ b,
+                                                                 double* __restrict__ y) {
   constexpr int NF = TraceDims<TK>::NF, SL = TraceDims<TK>::SL;
+  __shared__ int sc[SL][64];
+  __shared__ double sx[SL][NF][64];
   __shared__ double sy[NF][64];
   const int lane = threadIdx.x & 63, i = threadIdx.x >> 6;
   const long F0 = (long)blockIdx.x * 64;
   const long F = F0 + lane;
+  tet_gather<TK>(nF, F0, cols, x, sc, sx);
   if (F < nF) {
     double acc = 0.0;
 #pragma unroll
-    for (int s = 0; s < SL; ++s) {
-      const long col = cols[s * (long)nF + F];
-      const double* xc = x + col * NF;
-      const double* v = vals + ((long)(s * NF + i) * NF) * nF + F;
+    for (int sl = 0; sl < SL; ++sl) {
+      const double* v = vals + ((long)(sl * NF + i) * NF) * nF + F;
 #pragma unroll
-      for (int j = 0; j < NF; ++j) acc += v[(long)j * nF] * xc[j];
+      for (int jj = 0; jj < NF; ++jj) acc += v[(long)jj * nF] * sx[sl][jj][lane];
     }
     sy[i][lane] = b ? b[F * NF + i] - acc : acc;
   }
   __syncthreads();
   const long idx = F0 * NF + threadIdx.x;  // contiguous run of this block's outputs
   if (idx < (long)nF * NF) y[idx] = sy[threadIdx.x % NF][threadIdx.x / NF];
+}
+
+// damped block-Jacobi sweep on tetrahedra, the same arrangement:
+// xout = xin + omega Dinv (b - S xin) (xin == nullptr: xin = 0)
+template <int TK>
+__global__ void __launch_bounds__(TetRowsShape<TK>::NT) k_jacobi_tet(int nF, const double* __restrict__ vals,
+                                                                   const int* __restrict__ cols,
+                                                                   const double* __restrict__ Dinv, double omega,
+                                                                   const double* __restrict__ b,
+                                                                   const double* __restrict__ xin,
+                                                                   double* __restrict__ xout) {
+  constexpr int NF = TraceDims<TK>::NF, SL = TraceDims<TK>::SL;
+  __shared__ int sc[SL][64];
+  __shared__ double sx[SL][NF][64];
+  __shared__ double sr[NF][64], sz[NF][64];
+  const int lane = threadIdx.x & 63, i = threadIdx.x >> 6;
+  const long F0 = (long)blockIdx.x * 64;
+  const long F = F0 + lane;
+  if (xin) tet_gather<TK>(nF, F0, cols, xin, sc, sx);  // xin is uniform: every thread takes the same branch
+  if (F < nF) {
+    double acc = 0.0;
+    if (xin) {
+#pragma unroll
+      for (int sl = 0; sl < SL; ++sl) {
+        const double* v = vals + ((long)(sl * NF + i) * NF) * nF + F;
+#pragma unroll
+        for (int jj = 0; jj < NF; ++jj) acc += v[(long)jj * nF] * sx[sl][jj][lane];
+      }
+    }
+    sr[i][lane] = b[F * NF + i] - acc;
+  }
+  __syncthreads();
+  if (F < nF) {
+    double z = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < NF; ++jj) z += Dinv[(long)(i * NF + jj) * nF + F] * sr[jj][lane];
+    sz[i][lane] = z;
+  }
+  __syncthreads();
+  const long idx = F0 * NF + threadIdx.x;
+  if (idx < (long)nF * NF) {
+    const int fl = threadIdx.x / NF, ii = threadIdx.x % NF;
+    xout[idx] = (xin ? xin[idx] : 0.0) + omega * sz[ii][fl];
+  }
 }
 
 // damped block-Jacobi sweep: xout = xin + omega Dinv (b - S xin); xin == nullptr means xin = 0
@@ -1274,19 +1341,21 @@ void launch_assemble(int k, hipStream_t st, DMesh m, const double* SK, double* v
   HDG_DISPATCH(k, (k_assemble<KK><<<nblocks(m.nF), kBlock, 0, st>>>(m, SK, vals, cols, Dinv)));
 }
 void launch_spmv(int k, hipStream_t st, int nF, const double* vals, const int* cols, const double* x, double* y) {
-  if (k > 10) TET_TRACE_DISPATCH(k, (k_spmv_tet<KK><<<(nF + 63) / 64, 64 * TraceDims<KK>::NF, 0, st>>>(
+  if (k > 10) TET_TRACE_DISPATCH(k, (k_spmv_tet<KK><<<(nF + 63) / 64, TetRowsShape<KK>::NT, 0, st>>>(
                                             nF, vals, cols, x, nullptr, y)))
   else HDG_DISPATCH(k, (k_spmv<KK><<<nblocks(nF), kBlock, 0, st>>>(nF, vals, cols, x, nullptr, y)));
 }
 void launch_residual(int k, hipStream_t st, int nF, const double* vals, const int* cols, const double* b,
                      const double* x, double* r) {
-  if (k > 10) TET_TRACE_DISPATCH(k, (k_spmv_tet<KK><<<(nF + 63) / 64, 64 * TraceDims<KK>::NF, 0, st>>>(
+  if (k > 10) TET_TRACE_DISPATCH(k, (k_spmv_tet<KK><<<(nF + 63) / 64, TetRowsShape<KK>::NT, 0, st>>>(
                                             nF, vals, cols, x, b, r)))
   else HDG_DISPATCH(k, (k_spmv<KK><<<nblocks(nF), kBlock, 0, st>>>(nF, vals, cols, x, b, r)));
 }
 void launch_jacobi_sweep(int k, hipStream_t st, int nF, const double* vals, const int* cols, const double* Dinv,
                          double omega, const double* b, const double* xin, double* xout) {
-  TRACE_DISPATCH(k, (k_jacobi<KK><<<nblocks(nF), kBlock, 0, st>>>(nF, vals, cols, Dinv, omega, b, xin, xout)));
+  if (k > 10) TET_TRACE_DISPATCH(k, (k_jacobi_tet<KK><<<(nF + 63) / 64, TetRowsShape<KK>::NT, 0, st>>>(
+                                            nF, vals, cols, Dinv, omega, b, xin, xout)))
+  else TRACE_DISPATCH(k, (k_jacobi<KK><<<nblocks(nF), kBlock, 0, st>>>(nF, vals, cols, Dinv, omega, b, xin, xout)));
 }
 void launch_blockdiag(int k, hipStream_t st, int nF, const double* Dinv, const double* x, double* y) {
   TRACE_DISPATCH(k, (k_blockdiag<KK><<<nblocks(nF), kBlock, 0, st>>>(nF, Dinv, x, y)));
