@@ -58,6 +58,13 @@ MEASURED_TRAFFIC = {
                             "sha256": "6be723b4d110307c", "bytes_per_launch": 1660.3e6},
     "trace_spmv": {"src": "kernels.hip", "funcs": ["k_spmv"], "sha256": "96d7545c27858460", "bytes_per_launch": 159.1e6},
     "trace_spmv_512": {"src": "kernels.hip", "funcs": ["k_spmv"], "sha256": "96d7545c27858460", "bytes_per_launch": 627.3e6},
+    # tetrahedra, 32^3 Kuhn cubes, k = 2
+    "trace_spmv_tet": {"src": "kernels.hip", "funcs": ["TetRowsShape", "tet_gather", "k_spmv_tet"],
+                       "sha256": "4233bb038e2c001c", "bytes_per_launch": 915.8e6},
+    "apply_step1_operator_tet": {"src": "kernels3.hip", "funcs": ["wave_sum", "k3_apply"],
+                                 "sha256": "2543697c4399de76", "bytes_per_launch": 1470.8e6},
+    "step1_precond_apply_tet": {"src": "kernels3.hip", "funcs": ["PcLayout3", "PcApplyShape3", "k3_pc_apply"],
+                                "sha256": "05970de41ef8b9a6", "bytes_per_launch": 12485.0e6},
 }
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
 MIXED_RTOL_VELOCITY = 1e-5  # Step I tolerance of the mixed-precision run
@@ -107,7 +114,7 @@ def algorithmic_cost(kernel: str, k: int, nc: int, nF: int, nF_int: int | None =
     return None, None
 
 
-def algorithmic_cost_tet(kernel: str, k: int, nc: int, nF: int):
+def algorithmic_cost_tet(kernel: str, k: int, nc: int, nF: int, nF_int: int | None = None):
     """(bytes, flops) per launch on tetrahedra (ns = (k+2)(k+3)(k+4)/6 per
     velocity component, nf = (k+1)(k+2)/2 per facet, nq = ceil((3k+4)/2)^2
     facet points).  trace_spmv: per facet row 7 blocks of nf^2 values (the
@@ -117,7 +124,11 @@ def algorithmic_cost_tet(kernel: str, k: int, nc: int, nF: int):
     four normals (13 doubles), 16 int32 connectivity entries, the input,
     output and inner-product vectors (3 x 3 ns doubles); flops: per
     component 2 ns^2 for the volume term and per facet point 2 (3 ns) for
-    each of the own trace, the neighbour trace and the test sum."""
+    each of the own trace, the neighbour trace and the test sum.
+    step1_precond_apply: per interior facet (nF_int) the FP16 inverse of its
+    2 nu x 2 nu patch block (nu = 3 ns), read as two halves by its two cells,
+    plus per cell the input and output vectors (nu doubles each) and 4 int32
+    neighbour ids."""
     ns = (k + 2) * (k + 3) * (k + 4) // 6
     nf = (k + 1) * (k + 2) // 2
     nq = ((3 * k + 5) // 2) ** 2
@@ -127,6 +138,10 @@ def algorithmic_cost_tet(kernel: str, k: int, nc: int, nF: int):
         nbytes = nc * (8 * (ns * ns + 4 * nq + 13 + 3 * 3 * ns) + 4 * 16)
         flops = nc * (3 * 2 * ns * ns + 4 * nq * (3 * 2 * 3 * ns + 15))
         return nbytes, flops
+    if kernel == "step1_precond_apply":
+        nu = 3 * ns
+        ni = nF if nF_int is None else nF_int
+        return ni * (2 * nu) ** 2 * 2 + nc * (2 * 8 * nu + 4 * 4), ni * 2 * (2 * nu) ** 2
     return None, None
 
 
@@ -320,7 +335,9 @@ def tet_run(hdg, hi, torch, n: int, steps: int, warmup: int, trace_calls: int = 
         avg = kv["ms"] / kv["timed"] * 1e-3
         rec = {"avg_launch_us": round(avg * 1e6, 2), "launches": kv["launches"],
                "share_of_step": round(avg * kv["launches"] / el, 3)}
-        nb, fl = algorithmic_cost_tet(name, k, ctx.ncells, ctx.nfacets)
+        nb, fl = algorithmic_cost_tet(name, k, ctx.ncells, ctx.nfacets, ctx.nfacets - 12 * n * n)
+        if n == 32 and measured_traffic(name + "_tet") is not None:
+            rec["traffic"] = measured_traffic(name + "_tet")
         if nb is not None:
             rec.update({"algorithmic_bytes_per_launch": nb, "achieved_GBps": round(nb / avg / 1e9, 1),
                         "frac_hbm": round(nb / avg / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_flops_per_launch": fl,
@@ -343,7 +360,7 @@ def tet_run(hdg, hi, torch, n: int, steps: int, warmup: int, trace_calls: int = 
     gbs = nb / avg / 1e9
     trace = {"avg_launch_us": round(avg * 1e6, 2), "launches": kv["timed"], "algorithmic_bytes_per_launch": nb,
              "achieved_GBps": round(gbs, 1), "peak": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4),
-             "traffic": measured_traffic("trace_spmv_tet")}
+             "traffic": measured_traffic("trace_spmv_tet") if n == 32 else None}
     log(f"tet {n}^3 trace operator: {avg * 1e6:.1f} us per application, {nb / 1e6:.1f} MB, {gbs:.0f} GB/s "
         f"({gbs / HBM_PEAK_GBS:.3f} of peak)")
     out = {"workload": f"unit_cube_{n}^3_kuhn_k{k}_ars233 ({ctx.ncells} tetrahedra, {ctx.nT} trace DOFs)",
