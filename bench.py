@@ -40,6 +40,10 @@ if ROOT not in sys.path:
 
 WORKLOAD = {"workload": "unit_square_256x256_k3_ars222", "n": 256, "k": 3, "seed": 0, "scheme": "ars222",
             "dt": 1e-3, "n_richardson": 3, "trace_solver": "mg_pcg", "precision": "fp64",
+            # the Step I preconditioner rebuilt once per step (the two implicit
+            # stages of ARS(2,2,2) have the same a_ii dt); a solver setting:
+            # it changes iteration counts, not the solution
+            "step1_precond_lag": 2,
             # the paper's solver tolerances: trace system 1e-12, tentative velocity 1e-10
             "rtol_trace": 1e-12, "rtol_velocity": 1e-10}
 
@@ -282,7 +286,8 @@ TET_WORKLOAD = {"n": 32, "k": 2, "seed": 0, "scheme": "ars233", "dt": 1e-3, "n_r
                 "trace_solver": "mg_pcg", "rtol_trace": 1e-12, "rtol_velocity": 1e-10}
 
 
-def tet_run(hdg, hi, torch, n: int, steps: int, warmup: int, trace_calls: int = 20, pc_lag: int = 2):
+def tet_run(hdg, hi, torch, n: int, steps: int, warmup: int, trace_calls: int = 20, pc_lag: int = 2,
+            mixed: bool = False):
     """The three-dimensional workload: the unit cube in n^3 Kuhn cubes (6 n^3
     tetrahedra), k = 2, the curl of the seeded vector potential, ARS(2,3,3),
     dt = 1e-3, n_R = 3, MG-PCG, the paper's tolerances, FP64, the Step I
@@ -291,7 +296,9 @@ def tet_run(hdg, hi, torch, n: int, steps: int, warmup: int, trace_calls: int = 
     DOF-stages/s over `steps` timed steps, the kernel classes with their
     rooflines, and the assembled trace operator (c = gamma dt) applied
     `trace_calls` times with event timing (out of the last-level cache at
-    n = 32)."""
+    n = 32).  mixed: also the mixed-precision mode (Step I in FP32 stopped at
+    MIXED_RTOL_VELOCITY, FP64 Richardson residual and trace solves) and the
+    FP64 path at that Step I tolerance, each against the FP64 state."""
     import numpy as np
     w = TET_WORKLOAD
     k = w["k"]
@@ -363,6 +370,30 @@ def tet_run(hdg, hi, torch, n: int, steps: int, warmup: int, trace_calls: int = 
              "traffic": measured_traffic("trace_spmv_tet") if n == 32 else None}
     log(f"tet {n}^3 trace operator: {avg * 1e6:.1f} us per application, {nb / 1e6:.1f} MB, {gbs:.0f} GB/s "
         f"({gbs / HBM_PEAK_GBS:.3f} of peak)")
+    mixed_out = None
+    if mixed:
+        mixed_out = {}
+        ref = ctx.get_state()
+        for label, prec in (("mixed", "mixed"), ("fp64_same_rtol", "fp64")):
+            c2 = hdg.Context(X, C, degree=k, imex=w["scheme"], n_richardson=w["n_richardson"],
+                             trace_solver=w["trace_solver"], rtol_trace=w["rtol_trace"],
+                             rtol_velocity=MIXED_RTOL_VELOCITY, precision=prec, step1_precond_lag=pc_lag)
+            c2.set_velocity_from_points(hi.curl_potential_velocity(par, xyz[..., 0], xyz[..., 1], xyz[..., 2]))
+            c2.advance(w["dt"], warmup)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            c2.advance(w["dt"], steps)
+            torch.cuda.synchronize()
+            el2 = time.perf_counter() - t1
+            diffs = {nm: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+                     for nm, a, b in zip(("Q", "p", "lambda"), c2.get_state(), ref)}
+            mixed_out[label] = {"ms_per_step": 1e3 * el2 / steps, "value": c2.nT * stages * steps / el2,
+                                "rtol_velocity": MIXED_RTOL_VELOCITY, "rel_l2_diff_vs_fp64": diffs}
+            log(f"tet {n}^3 {label}: {1e3 * el2 / steps:.1f} ms/step, rel. L2 diff vs FP64 {diffs}")
+            c2.close()
+        mixed_out["speedup_vs_fp64"] = round(mixed_out["mixed"]["value"] / value, 3)
+        mixed_out["speedup_precision_only"] = round(mixed_out["mixed"]["value"] /
+                                                    mixed_out["fp64_same_rtol"]["value"], 3)
     out = {"workload": f"unit_cube_{n}^3_kuhn_k{k}_ars233 ({ctx.ncells} tetrahedra, {ctx.nT} trace DOFs)",
            "metric": "trace DOF-IMEX-stages/sec (FP64)", "value": value, "unit": "trace-DOF-stages/s",
            "steps": steps, "warmup": warmup, "ms_per_step": 1e3 * el / steps, "setup_s": round(setup, 2),
@@ -371,7 +402,7 @@ def tet_run(hdg, hi, torch, n: int, steps: int, warmup: int, trace_calls: int = 
            "pcg_iterations_per_solve": round(d["pcg_iterations_total"] / max(d["trace_solves"], 1), 1),
            "velocity_iterations_per_solve": round(d["velocity_iterations_total"] / max(d["velocity_solves"], 1), 1),
            "bicgstab_restarts": d["bicgstab_restarts"], "pcg_floor_stops": d["pcg_floor_stops"],
-           "kernels": kernels, "trace_operator": trace}
+           "kernels": kernels, "trace_operator": trace, "mixed": mixed_out}
     ctx.close()
     return out
 
@@ -387,7 +418,8 @@ def mixed_run(hdg, hi, torch, w, X, C, args, ref_ctx):
     alone)."""
     mctx = hdg.Context(X, C, degree=w["k"], imex=w["scheme"], n_richardson=w["n_richardson"],
                        trace_solver=w["trace_solver"], rtol_trace=w["rtol_trace"],
-                       rtol_velocity=MIXED_RTOL_VELOCITY, precision="mixed")
+                       rtol_velocity=MIXED_RTOL_VELOCITY, precision="mixed",
+                       step1_precond_lag=w["step1_precond_lag"])
     par = hi.stream_function_params(w["seed"])
     xy = mctx.cell_points()
     mctx.set_velocity_from_points(hi.streamfunction_velocity(par, xy[..., 0], xy[..., 1]))
@@ -408,7 +440,8 @@ def mixed_run(hdg, hi, torch, w, X, C, args, ref_ctx):
     # that the ratio measures the precision alone
     fctx = hdg.Context(X, C, degree=w["k"], imex=w["scheme"], n_richardson=w["n_richardson"],
                        trace_solver=w["trace_solver"], rtol_trace=w["rtol_trace"],
-                       rtol_velocity=MIXED_RTOL_VELOCITY, precision="fp64")
+                       rtol_velocity=MIXED_RTOL_VELOCITY, precision="fp64",
+                       step1_precond_lag=w["step1_precond_lag"])
     fctx.set_velocity_from_points(hi.streamfunction_velocity(par, xy[..., 0], xy[..., 1]))
     fctx.advance(w["dt"], args.warmup)
     torch.cuda.synchronize()
@@ -713,6 +746,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=WORKLOAD["n"], help="mesh size (experiments only)")
     ap.add_argument("--k", type=int, default=WORKLOAD["k"], help="degree (experiments only)")
+    ap.add_argument("--pc-lag", type=int, default=WORKLOAD["step1_precond_lag"],
+                    help="stages between rebuilds of the Step I preconditioner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with events")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision run")
@@ -725,6 +760,8 @@ def main():
     ap.add_argument("--tet-n", type=int, default=TET_WORKLOAD["n"], help="cubes per side of the 3D leg")
     ap.add_argument("--tet-steps", type=int, default=2, help="timed steps of the 3D leg (workload: 10)")
     ap.add_argument("--tet-only", action="store_true", help="run only the three-dimensional leg")
+    ap.add_argument("--tet-mixed", action="store_true",
+                    help="3D leg: also the mixed-precision mode and FP64 at its Step I tolerance")
     ap.add_argument("--tet-pc-lag", type=int, default=2,
                     help="stages between rebuilds of the 3D leg's Step I preconditioner (2: once per step)")
     ap.add_argument("--batched-instances", type=int, default=4, help="instances of the batched sample (recipe: 64)")
@@ -767,18 +804,19 @@ def main():
         torch.cuda.synchronize()
         log(f"copy probe: {args.copy_probe} MiB read + {args.copy_probe} MiB written per launch, 3 launches")
     if args.tet_only:
-        tet = tet_run(hdg, hi, torch, args.tet_n, args.tet_steps, args.warmup, pc_lag=args.tet_pc_lag)
+        tet = tet_run(hdg, hi, torch, args.tet_n, args.tet_steps, args.warmup, pc_lag=args.tet_pc_lag,
+                      mixed=args.tet_mixed)
         print(json.dumps({"metric": "trace DOF-IMEX-stages/sec (FP64), tetrahedra", "tet": tet}), flush=True)
         return
     w = dict(WORKLOAD)
-    w["n"], w["k"] = args.n, args.k
+    w["n"], w["k"], w["step1_precond_lag"] = args.n, args.k, args.pc_lag
     if (args.n, args.k) != (WORKLOAD["n"], WORKLOAD["k"]):
         w["workload"] = f"unit_square_{args.n}x{args.n}_k{args.k}_ars222"
     X, C = hi.unit_square_mesh(w["n"])
     t0 = time.perf_counter()
     ctx = hdg.Context(X, C, degree=w["k"], imex=w["scheme"], n_richardson=w["n_richardson"],
                       trace_solver=w["trace_solver"], rtol_trace=w["rtol_trace"],
-                      rtol_velocity=w["rtol_velocity"])
+                      rtol_velocity=w["rtol_velocity"], step1_precond_lag=w["step1_precond_lag"])
     par = hi.stream_function_params(w["seed"])
     xy = ctx.cell_points()
     ctx.set_velocity_from_points(hi.streamfunction_velocity(par, xy[..., 0], xy[..., 1]))
@@ -879,7 +917,8 @@ def main():
         trace_op = trace_operator_run(hdg, hi, torch)
     tet = None
     if not args.no_tet:
-        tet = tet_run(hdg, hi, torch, args.tet_n, args.tet_steps, args.warmup, pc_lag=args.tet_pc_lag)
+        tet = tet_run(hdg, hi, torch, args.tet_n, args.tet_steps, args.warmup, pc_lag=args.tet_pc_lag,
+                      mixed=args.tet_mixed)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -902,6 +941,7 @@ def main():
                    "imex": w["scheme"], "dt": w["dt"], "n_richardson": w["n_richardson"],
                    "trace_solver": w["trace_solver"], "rtol_trace": w["rtol_trace"],
                    "rtol_velocity": w["rtol_velocity"], "step1_precond": info.get("step1_precond"),
+                   "step1_precond_lag": w["step1_precond_lag"],
                    "pcg_iterations": pcg, "trace_solves": nsolves,
                    "pcg_iterations_per_solve": round(pcg / max(nsolves, 1), 1),
                    "velocity_iterations": bicg, "velocity_solves": nvel,

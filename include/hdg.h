@@ -172,8 +172,7 @@ typedef struct {
                             monomials ((d+1)x - 1)^a.. by degree and then descending exponents,
                             Gram-Schmidt orthonormalised on the reference cell (trace: for twice
                             the reference triangle's measure).  Not available on tetrahedra:
-                            periodic meshes, forcing, the tracer, point evaluation and the mixed
-                            precision. */
+                            periodic meshes, forcing, the tracer and point evaluation. */
 } hdg_params;
 
 /* Fill p with the defaults: k=1, tau=alpha=delta_up=1, ARS(2,2,2), n_R=3,

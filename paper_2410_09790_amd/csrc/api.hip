@@ -395,8 +395,8 @@ struct hdg_ctx {
     // rebuilt for a new adt, else when the stage data are step1_precond_lag generations newer
     if (!pc_on || (pc_adt == adt && pc_gen >= 0 && vk_gen - pc_gen < prm.step1_precond_lag)) return;
     hdg::Timed tm(prof, hdg::KC_PC_BUILD);
-    if (dim == 3)  // from the stage's V and beta (prepare_step1)
-      hdg::launch3_pc_build(k, st, dm, dt.t3, (const double*)vk, (const double*)vbeta, prm.alpha, adt, pcD, pcB);
+    if (dim == 3)  // from the stage's FP64 V and beta (prepare_step1, the residual kernels' copy)
+      hdg::launch3_pc_build(k, st, dm, dt.t3, adv, adv + hm.nc * (long)ns * ns, prm.alpha, adt, pcD, pcB);
     else
       hdg::launch_pc_build(k, st, dm, dt, vk_qs, prm.delta_up, prm.alpha, adt, pcD, pcB);
     KCHK();
@@ -406,7 +406,7 @@ struct hdg_ctx {
   }
   void pc_apply(const void* r, void* z) {
     hdg::Timed tm(prof, hdg::KC_PC_APPLY);
-    if (dim == 3) hdg::launch3_pc_apply(k, st, dm, pcB, (const double*)r, (double*)z);
+    if (dim == 3) hdg::launch3_pc_apply(k, st, dm, pcB, r, z, kx32);
     else hdg::launch_pc_apply(k, st, dm, pcB, r, z, kx32);
   }
   int bicgstab(double adt, const double* b, double* x);
@@ -1724,8 +1724,8 @@ int hdg_create_periodic(int64_t nv, const double* coords, int64_t nc, const int3
     g_create_error = prm->dim == 3 ? "degree must be in 1..2 on tetrahedra" : "degree must be in 1..4";
     return HDG_ERR_UNSUPPORTED;
   }
-  if (prm->dim == 3 && (vertex_rep || prm->precision != HDG_FP64)) {
-    g_create_error = "tetrahedra: no periodic meshes, FP64 only";
+  if (prm->dim == 3 && vertex_rep) {
+    g_create_error = "tetrahedra: no periodic meshes";
     return HDG_ERR_UNSUPPORTED;
   }
   if (prm->tau <= 0 || prm->alpha < 0 || prm->delta_up < 0 || prm->n_richardson < 1 || prm->max_it_trace < 1 ||

@@ -241,12 +241,17 @@ void launch3_gamma(int k, hipStream_t st, DMesh m, DTab3 t, double tau, double s
                    const double* lam, double* gpsi, double* ycell);
 void launch3_mass(int k, hipStream_t st, DMesh m, double s, const double* x, double* y);
 // per-stage Step I data: V [nc][ns][ns] (transposed: [cell][trial][test]), beta [nc][4][nq_facet]
-void launch3_prep(int k, hipStream_t st, DMesh m, DTab3 t, const double* Qs, double delta_up, double* V, double* beta);
+// (f32: V and beta in FP32, the mixed-precision Step I data)
+void launch3_prep(int k, hipStream_t st, DMesh m, DTab3 t, const double* Qs, double delta_up, void* V, void* beta,
+                  bool f32);
 // Step I operator (mode 0, with the dot variants of launch_apply_soa over
 // nparts blocks) and residuals (modes 1, 2) as launch_apply describes them
-void launch3_apply(int k, hipStream_t st, int mode, int dot, DMesh m, DTab3 t, const double* V, const double* beta,
-                   double alpha, double adt, const double* x, const double* r, const double* p, const double* lam,
-                   double* out, const double* w, const double* sd, double* part, int nparts);
+// (x32: V, beta, x, w, sd, out and the arithmetic in FP32, mode 0 only)
+void launch3_apply(int k, hipStream_t st, int mode, int dot, DMesh m, DTab3 t, const void* V, const void* beta,
+                   double alpha, double adt, const void* x, const double* r, const double* p, const double* lam,
+                   void* out, const void* w, const void* sd, double* part, int nparts, bool x32);
+// out = in converted between FP64 and FP32 (n entries)
+void launch3_convert(hipStream_t st, long n, const void* in, bool in32, void* out, bool out32);
 void launch3_div(int k, hipStream_t st, DMesh m, DTab3 t, const double* F, double scale, double* out);
 void launch3_bdm(int k, hipStream_t st, DMesh m, DTab3 t, const double* Q, double* Qs);
 void launch3_recon_rhs(int k, hipStream_t st, DMesh m, DTab3 t, const double* Q, double* out);
@@ -255,7 +260,7 @@ void launch3_recon_rhs(int k, hipStream_t st, DMesh m, DTab3 t, const double* Q,
 // doubles; Binv: pc_entries3(k, nc) FP16 entries); z = B r on cell-major vectors
 void launch3_pc_build(int k, hipStream_t st, DMesh m, DTab3 t, const double* V, const double* beta, double alpha,
                       double adt, double* D, void* Binv);
-void launch3_pc_apply(int k, hipStream_t st, DMesh m, const void* Binv, const double* r, double* z);
+void launch3_pc_apply(int k, hipStream_t st, DMesh m, const void* Binv, const void* r, void* z, bool x32);
 long pc_entries3(int k, long nc);
 // velocity from values at the cell points [nc][nq_cell][3]
 void launch3_project(int k, hipStream_t st, DMesh m, DTab3 t, const double* vals, double* Q);

@@ -1385,7 +1385,7 @@ void launch_gamma(int k, hipStream_t st, DMesh m, DTab t, double tau, double sca
 void launch_prep_adv(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, double* adv) {
   if (m.dim == 3) {  // adv: V [nc][ns][ns], then beta [nc][4][nq_facet]
     const long ns = (k + 2) * (k + 3) * (k + 4) / 6;
-    return launch3_prep(k, st, m, t.t3, Qs, delta_up, adv, adv + (long)m.nc * ns * ns);
+    return launch3_prep(k, st, m, t.t3, Qs, delta_up, adv, adv + (long)m.nc * ns * ns, false);
   }
   HDG_DISPATCH(k, (k_prep_adv<KK><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, Qs, delta_up, adv)));
 }
@@ -1394,7 +1394,7 @@ void launch_apply(int k, hipStream_t st, int mode, DMesh m, DTab t, const double
   if (m.dim == 3) {
     const long ns = (k + 2) * (k + 3) * (k + 4) / 6;
     return launch3_apply(k, st, mode, 0, m, t.t3, adv, adv + (long)m.nc * ns * ns, alpha, adt, x, r, p, lam, out,
-                         nullptr, nullptr, nullptr, 0);
+                         nullptr, nullptr, nullptr, 0, false);
   }
   if (mode == 0) {
     HDG_DISPATCH(k, (k_apply<KK, 0><<<nblocks(m.nc), kBlock, 0, st>>>(m, t, adv, alpha, adt, x, r, p, lam, out)));

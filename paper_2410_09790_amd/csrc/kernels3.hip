@@ -13,6 +13,8 @@
 // All reductions use a fixed grid and order (bitwise reproducible).
 #include <hip/hip_runtime.h>
 
+#include <stdexcept>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -470,9 +472,9 @@ __global__ void k3_mass(DMesh m, double s, const double* __restrict__ x, double*
 //   i fastest, so that the lanes of the operator read it coalesced), and
 //   beta[e][f][q] = |F| 2 w_q (qn/2 - delta |qn|),  qn = {Q*}.n_K at the
 //   facet point (0 on walls, where f_im has the penalty term only).
-template <int K>
+template <int K, typename TO>
 __global__ void __launch_bounds__(kW3) k3_prep(DMesh m, DTab3 t, const double* __restrict__ Qs, double delta_up,
-                                               double* __restrict__ V, double* __restrict__ beta) {
+                                               TO* __restrict__ V, TO* __restrict__ beta) {
   using D = Dims3<K>;
   constexpr int NS = D::NS, NU = D::NU, NQC = D::NQC, NQF = D::NQF;
   const int e = blockIdx.x, lane = threadIdx.x;
@@ -500,7 +502,7 @@ __global__ void __launch_bounds__(kW3) k3_prep(DMesh m, DTab3 t, const double* _
                         a[2][iq] * t.dBu[(2 * NQC + iq) * NS + j];
       v += t.Bu[iq * NS + i] * gj;
     }
-    V[((long)e * NS + j) * NS + i] = -v;  // stored transposed: V[e][j][i]
+    V[((long)e * NS + j) * NS + i] = (TO)(-v);  // stored transposed: V[e][j][i]
   }
   for (int f = 0; f < 4; ++f) {
     const int en = m.cf_nb[f * nc + e];
@@ -523,7 +525,7 @@ __global__ void __launch_bounds__(kW3) k3_prep(DMesh m, DTab3 t, const double* _
         const double qv = 0.5 * u;
         w = g.a[f] * 2.0 * t.fw[iq] * (0.5 * qv - delta_up * fabs(qv));
       }
-      beta[((long)e * 4 + f) * NQF + iq] = w;
+      beta[((long)e * 4 + f) * NQF + iq] = (TO)w;
     }
   }
 }
@@ -537,20 +539,23 @@ __global__ void __launch_bounds__(kW3) k3_prep(DMesh m, DTab3 t, const double* _
 // DOT (MODE 0): partial inner products per block as the structure-of-arrays
 // operator leaves them (dot 1: w.out; dot 2: out.x, out.out, w.x, w.out;
 // dot 3: out.sd, out.out, w.sd, w.out), nparts blocks per set.  Blocks of
-// 4 waves walk the cells with a stride of the grid.
-template <int K, int MODE, int DOT>
-__global__ void __launch_bounds__(256) k3_apply(DMesh m, DTab3 t, const double* __restrict__ V,
-                                                const double* __restrict__ beta, double alpha, double adt,
-                                                const double* __restrict__ x, const double* __restrict__ r,
+// 4 waves walk the cells with a stride of the grid.  TX: the type of V,
+// beta, the vectors and the arithmetic (float in the mixed-precision mode,
+// MODE 0 only); the inner products accumulate in FP64 either way.
+template <int K, int MODE, int DOT, typename TX = double>
+__global__ void __launch_bounds__(256) k3_apply(DMesh m, DTab3 t, const TX* __restrict__ V,
+                                                const TX* __restrict__ beta, double alpha, double adt,
+                                                const TX* __restrict__ x, const double* __restrict__ r,
                                                 const double* __restrict__ pv, const double* __restrict__ lam,
-                                                double* __restrict__ out, const double* __restrict__ w,
-                                                const double* __restrict__ sd, double* __restrict__ part) {
+                                                TX* __restrict__ out, const TX* __restrict__ w,
+                                                const TX* __restrict__ sd, double* __restrict__ part) {
   using D = Dims3<K>;
   constexpr int NS = D::NS, NP = D::NP, NF = D::NF, NU = D::NU, NQF = D::NQF;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const long nc = m.nc;
-  __shared__ double xs[4][5][NU];
-  __shared__ double phi[4][4][NQF][3];
+  static_assert(MODE == 0 || sizeof(TX) == sizeof(double), "the residual modes are FP64");
+  __shared__ TX xs[4][5][NU];
+  __shared__ TX phi[4][4][NQF][3];
   __shared__ double red[4][4];
   double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
   const long stride = (long)gridDim.x * 4;
@@ -561,8 +566,8 @@ __global__ void __launch_bounds__(256) k3_apply(DMesh m, DTab3 t, const double* 
     const long e = (long)__builtin_amdgcn_readfirstlane((int)(base + wv));
     const bool act = e < nc;
     const long ec = act ? e : base;  // an inactive wave reads a valid cell and writes nothing
-    double(&X)[5][NU] = xs[wv];
-    double(&PH)[4][NQF][3] = phi[wv];
+    TX(&X)[5][NU] = xs[wv];
+    TX(&PH)[4][NQF][3] = phi[wv];
     int nb[4], fps[4], fpn[4];
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
@@ -584,56 +589,57 @@ __global__ void __launch_bounds__(256) k3_apply(DMesh m, DTab3 t, const double* 
     __syncthreads();
     for (int idx = lane; idx < 4 * NQF; idx += 64) {
       const int f = idx / NQF, iq = idx % NQF;
-      double du[3];
+      TX du[3];
 #pragma unroll
-      for (int cc = 0; cc < 3; ++cc) du[cc] = 0.0;
+      for (int cc = 0; cc < 3; ++cc) du[cc] = (TX)0;
       // points fastest: the lanes of one facet read consecutive table entries
       const double* b0 = t.FBuT + (long)fps[f] * NS * NQF + iq;
 #pragma unroll 4
       for (int s = 0; s < NS; ++s) {
 #pragma unroll
-        for (int cc = 0; cc < 3; ++cc) du[cc] += b0[s * NQF] * X[0][cc * NS + s];
+        for (int cc = 0; cc < 3; ++cc) du[cc] += (TX)b0[s * NQF] * X[0][cc * NS + s];
       }
       if (nb[f] >= 0) {
         const double* b1 = t.FBuT + (long)fpn[f] * NS * NQF + iq;
 #pragma unroll 4
         for (int s = 0; s < NS; ++s) {
 #pragma unroll
-          for (int cc = 0; cc < 3; ++cc) du[cc] -= b1[s * NQF] * X[1 + f][cc * NS + s];
+          for (int cc = 0; cc < 3; ++cc) du[cc] -= (TX)b1[s * NQF] * X[1 + f][cc * NS + s];
         }
       }
-      const double bq = beta[(ec * 4 + f) * NQF + iq];
-      const double pen = alpha * 2.0 * t.fw[iq];
-      const double dn = nrm[f][0] * du[0] + nrm[f][1] * du[1] + nrm[f][2] * du[2];
+      const TX bq = beta[(ec * 4 + f) * NQF + iq];
+      const TX pen = (TX)(alpha * 2.0 * t.fw[iq]);
+      const TX dn = (TX)nrm[f][0] * du[0] + (TX)nrm[f][1] * du[1] + (TX)nrm[f][2] * du[2];
 #pragma unroll
-      for (int cc = 0; cc < 3; ++cc) PH[f][iq][cc] = bq * du[cc] - pen * nrm[f][cc] * dn;
+      for (int cc = 0; cc < 3; ++cc) PH[f][iq][cc] = bq * du[cc] - pen * (TX)nrm[f][cc] * dn;
     }
     __syncthreads();
     const double det = m.geo[(long)E3_DET * nc + ec];
     for (int i = act ? lane : NU; i < NU; i += 64) {
       const int cc = i / NS, s = i % NS;
-      double F = 0.0;
-      const double* vr = V + e * NS * NS + s;
+      TX F = (TX)0;
+      const TX* vr = V + e * NS * NS + s;
 #pragma unroll 4
       for (int j = 0; j < NS; ++j) F += vr[j * NS] * X[0][cc * NS + j];
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
         const double* b0 = t.FBu + (long)fps[f] * NQF * NS + s;
 #pragma unroll 5
-        for (int iq = 0; iq < NQF; ++iq) F += b0[iq * NS] * PH[f][iq][cc];
+        for (int iq = 0; iq < NQF; ++iq) F += (TX)b0[iq * NS] * PH[f][iq][cc];
       }
       const long gi = e * NU + i;
-      double o;
+      TX o;
       if constexpr (MODE == 0) {
-        o = X[0][i] - adt / det * F;
+        o = X[0][i] - (TX)(adt / det) * F;
         if constexpr (DOT == 1) {
-          d0 += w[gi] * o;
+          d0 += (double)w[gi] * (double)o;
         } else if constexpr (DOT == 2 || DOT == 3) {
-          const double xr = DOT == 2 ? X[0][i] : sd[gi];
-          d0 += o * xr;
-          d1 += o * o;
-          d2 += w[gi] * xr;
-          d3 += w[gi] * o;
+          const double xr = DOT == 2 ? (double)X[0][i] : (double)sd[gi];
+          const double od = (double)o, wd = (double)w[gi];
+          d0 += od * xr;
+          d1 += od * od;
+          d2 += wd * xr;
+          d3 += wd * od;
         }
       } else {
         // g(p, lam) = Gp p + Gl lam
@@ -1134,9 +1140,9 @@ struct PcApplyShape3 {
   static constexpr int RG = NU / G;
   static_assert(RG * G == NU, "rows split evenly");
 };
-template <int K>
+template <int K, typename TX>
 __global__ void __launch_bounds__(kBlock) k3_pc_apply(DMesh m, const pc3_t* __restrict__ Binv,
-                                                      const double* __restrict__ r, double* __restrict__ z) {
+                                                      const TX* __restrict__ r, TX* __restrict__ z) {
   using Sh = PcApplyShape3<K>;
   constexpr int NU = Dims3<K>::NU, NQ = PcLayout3<K>::NQ, G = Sh::G, RG = Sh::RG;
   const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1154,8 +1160,8 @@ __global__ void __launch_bounds__(kBlock) k3_pc_apply(DMesh m, const pc3_t* __re
   for (int f = 0; f < 4; ++f) {
     const long en = m.cf_nb[f * nc + e];
     if (en < 0) continue;
-    const double* ro = r + e * NU;
-    const double* rn = r + en * NU;
+    const TX* ro = r + e * NU;
+    const TX* rn = r + en * NU;
 #pragma unroll 1
     for (int jq = 0; jq < NQ; ++jq) {
       // column 4 jq + u: own entries first, then the neighbour's (a quad may
@@ -1164,7 +1170,7 @@ __global__ void __launch_bounds__(kBlock) k3_pc_apply(DMesh m, const pc3_t* __re
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int jx = 4 * jq + u;
-        xv[u] = *(jx < NU ? ro + jx : rn + (jx - NU));
+        xv[u] = (double)*(jx < NU ? ro + jx : rn + (jx - NU));
       }
       const double x0 = xv[0], x1 = xv[1], x2 = xv[2], x3 = xv[3];
 #pragma unroll
@@ -1175,12 +1181,18 @@ __global__ void __launch_bounds__(kBlock) k3_pc_apply(DMesh m, const pc3_t* __re
     }
   }
 #pragma unroll
-  for (int a = 0; a < RG; ++a) z[e * NU + g * RG + a] = acc[a];
+  for (int a = 0; a < RG; ++a) z[e * NU + g * RG + a] = (TX)acc[a];
 }
 
 long pc_entries3(int k, long nc) {
   const long nu = 3L * (k + 2) * (k + 3) * (k + 4) / 6;
   return (nc + 31) / 32 * 32 * 4 * nu * 2 * nu;
+}
+
+template <typename TI, typename TO>
+__global__ void k3_convert(long n, const TI* __restrict__ in, TO* __restrict__ out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (TO)in[i];
 }
 
 // ============================================================== launchers
@@ -1218,27 +1230,41 @@ void launch3_gamma(int k, hipStream_t st, DMesh m, DTab3 t, double tau, double s
 void launch3_mass(int k, hipStream_t st, DMesh m, double s, const double* x, double* y) {
   HDG3_DISPATCH(k, (k3_mass<KK><<<nblocks((long)m.nc * Dims3<KK>::NU), kBlock, 0, st>>>(m, s, x, y)));
 }
-void launch3_prep(int k, hipStream_t st, DMesh m, DTab3 t, const double* Qs, double delta_up, double* V,
-                  double* beta) {
-  HDG3_DISPATCH(k, (k3_prep<KK><<<m.nc, kW3, 0, st>>>(m, t, Qs, delta_up, V, beta)));
+void launch3_prep(int k, hipStream_t st, DMesh m, DTab3 t, const double* Qs, double delta_up, void* V, void* beta,
+                  bool f32) {
+  if (f32) HDG3_DISPATCH(k, (k3_prep<KK, float><<<m.nc, kW3, 0, st>>>(m, t, Qs, delta_up, (float*)V, (float*)beta)))
+  else HDG3_DISPATCH(k, (k3_prep<KK, double><<<m.nc, kW3, 0, st>>>(m, t, Qs, delta_up, (double*)V, (double*)beta)));
 }
 int apply3_blocks(long nc) { return (int)((nc + 3) / 4 < 4096 ? (nc + 3) / 4 : 4096); }
-void launch3_apply(int k, hipStream_t st, int mode, int dot, DMesh m, DTab3 t, const double* V, const double* beta,
-                   double alpha, double adt, const double* x, const double* r, const double* p, const double* lam,
-                   double* out, const double* w, const double* sd, double* part, int nparts) {
+void launch3_apply(int k, hipStream_t st, int mode, int dot, DMesh m, DTab3 t, const void* V, const void* beta,
+                   double alpha, double adt, const void* x, const double* r, const double* p, const double* lam,
+                   void* out, const void* w, const void* sd, double* part, int nparts, bool x32) {
   const int nb = nparts > 0 ? nparts : apply3_blocks(m.nc);
-  if (mode == 0) {
-    switch (dot) {
-      case 0: HDG3_DISPATCH(k, (k3_apply<KK, 0, 0><<<nb, 256, 0, st>>>(m, t, V, beta, alpha, adt, x, r, p, lam, out, w, sd, part))); break;
-      case 1: HDG3_DISPATCH(k, (k3_apply<KK, 0, 1><<<nb, 256, 0, st>>>(m, t, V, beta, alpha, adt, x, r, p, lam, out, w, sd, part))); break;
-      case 2: HDG3_DISPATCH(k, (k3_apply<KK, 0, 2><<<nb, 256, 0, st>>>(m, t, V, beta, alpha, adt, x, r, p, lam, out, w, sd, part))); break;
-      default: HDG3_DISPATCH(k, (k3_apply<KK, 0, 3><<<nb, 256, 0, st>>>(m, t, V, beta, alpha, adt, x, r, p, lam, out, w, sd, part))); break;
-    }
-  } else if (mode == 1) {
-    HDG3_DISPATCH(k, (k3_apply<KK, 1, 0><<<nb, 256, 0, st>>>(m, t, V, beta, alpha, adt, x, r, p, lam, out, w, sd, part)));
-  } else {
-    HDG3_DISPATCH(k, (k3_apply<KK, 2, 0><<<nb, 256, 0, st>>>(m, t, V, beta, alpha, adt, x, r, p, lam, out, w, sd, part)));
+  using D = const double*;
+  using F = const float*;
+  if (x32) {
+    if (mode != 0) throw std::invalid_argument("launch3_apply: the residual modes are FP64");
+#define K3F(DT) HDG3_DISPATCH(k, (k3_apply<KK, 0, DT, float><<<nb, 256, 0, st>>>(m, t, (F)V, (F)beta, alpha, adt, \
+                                  (F)x, r, p, lam, (float*)out, (F)w, (F)sd, part)))
+    switch (dot) { case 0: K3F(0); break; case 1: K3F(1); break; case 2: K3F(2); break; default: K3F(3); break; }
+#undef K3F
+    return;
   }
+#define K3D(MD, DT) HDG3_DISPATCH(k, (k3_apply<KK, MD, DT, double><<<nb, 256, 0, st>>>(m, t, (D)V, (D)beta, alpha, \
+                                      adt, (D)x, r, p, lam, (double*)out, (D)w, (D)sd, part)))
+  if (mode == 0) {
+    switch (dot) { case 0: K3D(0, 0); break; case 1: K3D(0, 1); break; case 2: K3D(0, 2); break; default: K3D(0, 3); break; }
+  } else if (mode == 1) {
+    K3D(1, 0);
+  } else {
+    K3D(2, 0);
+  }
+#undef K3D
+}
+void launch3_convert(hipStream_t st, long n, const void* in, bool in32, void* out, bool out32) {
+  if (in32 == out32) throw std::invalid_argument("launch3_convert: same types");
+  if (in32) k3_convert<float, double><<<nblocks(n), kBlock, 0, st>>>(n, (const float*)in, (double*)out);
+  else k3_convert<double, float><<<nblocks(n), kBlock, 0, st>>>(n, (const double*)in, (float*)out);
 }
 void launch3_div(int k, hipStream_t st, DMesh m, DTab3 t, const double* F, double scale, double* out) {
   HDG3_DISPATCH(k, (k3_div<KK><<<m.nc, kW3, 0, st>>>(m, t, F, scale, out)));
@@ -1255,9 +1281,12 @@ void launch3_pc_build(int k, hipStream_t st, DMesh m, DTab3 t, const double* V, 
   HDG3_DISPATCH(k, (k3_pc_patch<KK><<<m.nF, PcPatchShape3<KK>::NT, 0, st>>>(m, t, beta, alpha, adt, D,
                                                                              (pc3_t*)Binv)));
 }
-void launch3_pc_apply(int k, hipStream_t st, DMesh m, const void* Binv, const double* r, double* z) {
-  HDG3_DISPATCH(k, (k3_pc_apply<KK><<<nblocks((m.nc + 31) / 32 * 32 * PcApplyShape3<KK>::G), kBlock, 0, st>>>(
-                        m, (const pc3_t*)Binv, r, z)));
+void launch3_pc_apply(int k, hipStream_t st, DMesh m, const void* Binv, const void* r, void* z, bool x32) {
+  const long nc32 = (m.nc + 31) / 32 * 32;
+  if (x32) HDG3_DISPATCH(k, (k3_pc_apply<KK, float><<<nblocks(nc32 * PcApplyShape3<KK>::G), kBlock, 0, st>>>(
+                                m, (const pc3_t*)Binv, (const float*)r, (float*)z)))
+  else HDG3_DISPATCH(k, (k3_pc_apply<KK, double><<<nblocks(nc32 * PcApplyShape3<KK>::G), kBlock, 0, st>>>(
+                            m, (const pc3_t*)Binv, (const double*)r, (double*)z)));
 }
 void launch3_project(int k, hipStream_t st, DMesh m, DTab3 t, const double* vals, double* Q) {
   HDG3_DISPATCH(k, (k3_project<KK><<<m.nc, kW3, 0, st>>>(m, t, vals, Q)));

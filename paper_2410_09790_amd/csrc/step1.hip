@@ -781,8 +781,10 @@ __global__ void __launch_bounds__(kBlock) k_pc_apply(DMesh m, const pc_t* __rest
 // ============================================================== launchers
 void launch_step1_matrix(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, void* V, bool v32,
                          void* beta, bool b32) {
-  if (m.dim == 3)  // tetrahedra: FP64 cell-major V [nc][ns][ns] and beta [nc][4][nq_facet]
-    return launch3_prep(k, st, m, t.t3, Qs, delta_up, (double*)V, (double*)beta);
+  if (m.dim == 3) {  // tetrahedra: cell-major V [nc][ns][ns] and beta [nc][4][nq_facet], one type for both
+    if (v32 != b32) throw std::invalid_argument("launch_step1_matrix: V and beta of one type on tetrahedra");
+    return launch3_prep(k, st, m, t.t3, Qs, delta_up, V, beta, v32);
+  }
   const int nb = nblocks((long)m.nc * (k + 2) * (k + 3) / 2);
   if (v32) {
     HDG_DISPATCH(k, (k_step1_matrix<KK, float><<<nb, kBlock, 0, st>>>(m, t, Qs, (float*)V)));
@@ -823,10 +825,11 @@ static void apply_soa_t(int k, hipStream_t st, Step1Launch ln, int dot, DMesh m,
 void launch_apply_soa(int k, hipStream_t st, Step1Launch ln, int dot, DMesh m, DTab t, const void* V, bool v32,
                       const void* beta, double alpha, double adt, const void* x, const void* w, void* out,
                       double* part, const void* sd, bool x32) {
-  if (m.dim == 3)
-    return launch3_apply(k, st, 0, dot, m, t.t3, (const double*)V, (const double*)beta, alpha, adt, (const double*)x,
-                         nullptr, nullptr, nullptr, (double*)out, (const double*)w, (const double*)sd, part,
-                         apply_soa_blocks(m.nc, ln.block));
+  if (m.dim == 3) {
+    if (v32 != x32) throw std::invalid_argument("launch_apply_soa: V and the vectors of one type on tetrahedra");
+    return launch3_apply(k, st, 0, dot, m, t.t3, V, beta, alpha, adt, x, nullptr, nullptr, nullptr, out, w, sd,
+                         part, apply_soa_blocks(m.nc, ln.block), x32);
+  }
   if (x32) {  // FP32 vectors and arithmetic (the cell matrices are FP32 too)
     apply_soa_t(k, st, ln, dot, m, t, (const float*)V, (const float*)beta, alpha, adt, (const float*)x,
                 (const float*)w, (const float*)sd, (float*)out, part);
@@ -859,16 +862,22 @@ void launch_bicg_xrp(hipStream_t st, long n, int np, const double* part2, double
 }
 void launch_bicg_init(hipStream_t st, double* sc) { k_bicg_init<<<1, 64, 0, st>>>(sc); }
 void launch_to_soa(int k, hipStream_t st, DMesh m, int inv_det, const double* x, void* y, bool x32) {
-  if (m.dim == 3) {  // tetrahedra: the Step I vectors stay cell-major
+  if (m.dim == 3) {  // tetrahedra: the Step I vectors stay cell-major (FP32 in the mixed mode)
     if (inv_det) throw std::invalid_argument("launch_to_soa: inv_det is not available on tetrahedra");
-    return launch_vcopy(st, (long)m.nc * 3 * (k + 2) * (k + 3) * (k + 4) / 6, x, y, x32);
+    const long n = (long)m.nc * 3 * (k + 2) * (k + 3) * (k + 4) / 6;
+    if (x32) return launch3_convert(st, n, x, false, y, true);
+    return launch_vcopy(st, n, x, y, false);
   }
   const int nb = nblocks((long)m.nc * (k + 2) * (k + 3));
   if (x32) { HDG_DISPATCH(k, (k_to_soa<KK, float><<<nb, kBlock, 0, st>>>(m, inv_det, x, (float*)y))); }
   else { HDG_DISPATCH(k, (k_to_soa<KK, double><<<nb, kBlock, 0, st>>>(m, inv_det, x, (double*)y))); }
 }
 void launch_to_aos(int k, hipStream_t st, DMesh m, const void* x, double* y, bool x32) {
-  if (m.dim == 3) return launch_copy(st, (long)m.nc * 3 * (k + 2) * (k + 3) * (k + 4) / 6, (const double*)x, y);
+  if (m.dim == 3) {
+    const long n = (long)m.nc * 3 * (k + 2) * (k + 3) * (k + 4) / 6;
+    if (x32) return launch3_convert(st, n, x, true, y, false);
+    return launch_copy(st, n, (const double*)x, y);
+  }
   const int nb = nblocks((long)m.nc * (k + 2) * (k + 3));
   if (x32) { HDG_DISPATCH(k, (k_to_aos<KK, float><<<nb, kBlock, 0, st>>>(m, (const float*)x, y))); }
   else { HDG_DISPATCH(k, (k_to_aos<KK, double><<<nb, kBlock, 0, st>>>(m, (const double*)x, y))); }

@@ -272,7 +272,6 @@ def test_tetrahedra_parameters_are_checked_on_the_host(lib_path):
 
     assert create(hdg.default_params(dim=4)) == 1 and b"dim" in lib.hdg_last_error(None)
     assert create(hdg.default_params(dim=3, degree=3)) == 6 and b"tetrahedra" in lib.hdg_last_error(None)
-    assert create(hdg.default_params(dim=3, degree=2, precision="mixed")) == 6
     bad = C.copy()
     bad[:, [2, 3]] = bad[:, [3, 2]]  # negatively oriented
     assert create(hdg.default_params(dim=3, degree=2), C=bad) == 1

@@ -157,7 +157,7 @@ def test_pressure_reconstruction(n, k, pert):
     assert rel_l2_trace(d, host(lg), lam) < 1e-10
 
 
-def _run_both(n, k, nsteps, dt, nR, pert=0.0, solver="mg_pcg", seed=0):
+def _run_both(n, k, nsteps, dt, nR, pert=0.0, solver="mg_pcg", seed=0, precision="fp64", rtol_velocity=1e-13):
     X, C = cube(n, pert)
     d = Discretisation3D(X, C, k)
     par = hi.vector_potential_params(seed)
@@ -165,7 +165,7 @@ def _run_both(n, k, nsteps, dt, nR, pert=0.0, solver="mg_pcg", seed=0):
     Q, p, lam = st.initial_state(lambda x, y, z: hi.curl_potential_velocity(par, x, y, z))
     Q, p, lam = st.run(Q, p, lam, 0.0, nsteps)
     ctx = context(X, C, degree=k, imex="ars233", n_richardson=nR, trace_solver=solver, rtol_trace=1e-13,
-                  rtol_velocity=1e-13)
+                  rtol_velocity=rtol_velocity, precision=precision)
     xyz = ctx.cell_points()
     ctx.set_velocity_from_points(hi.curl_potential_velocity(par, xyz[..., 0], xyz[..., 1], xyz[..., 2]))
     ctx.advance(dt, nsteps)
@@ -245,3 +245,16 @@ def test_step1_solve_with_and_without_preconditioner():
     assert rel_l2_cells(d, sol[1], sol[0], d.nu) < 1e-9
     print(f"tet 6^3 k=2 Step I BiCGStab iterations: {its[0]} without, {its[1]} with the preconditioner")
     assert its[1] * 3 < its[0], its
+
+
+@pytest.mark.parametrize("n,k,pert", [(2, 1, 0.1), (3, 2, 0.05)])
+def test_mixed_steps(n, k, pert):
+    """The mixed-precision mode on tetrahedra (Step I in FP32, stopped at
+    1e-5, refined by the FP64 Richardson residual): two ARS(2,3,3) steps within
+    1e-6 of the FP64 oracle."""
+    torch_or_skip()
+    d, ref, got, _ = _run_both(n, k, 2, 2e-3, 3, pert=pert, precision="mixed", rtol_velocity=1e-5)
+    errs = (rel_l2_cells(d, got[0], ref[0], d.nu), rel_l2_cells(d, got[1], ref[1], d.npp),
+            rel_l2_trace(d, got[2], ref[2]))
+    print(f"tet mixed n={n} k={k}: rel L2 Q {errs[0]:.2e} p {errs[1]:.2e} lam {errs[2]:.2e}")
+    assert max(errs) < 1e-6, errs
