@@ -58,8 +58,8 @@ MEASURED_TRAFFIC = {
     "apply_step1_operator": {"src": "step1.hip", "funcs": ["pair_swap", "tile_idx", "VPairs", "step1_core",
                                                            "xcd_block", "stage_fbu", "k_apply_soa"],
                              "sha256": "7ee582c4c3bd27ad", "bytes_per_launch": 403.9e6},
-    "step1_precond_apply": {"src": "step1.hip", "funcs": ["PcLayout", "PcApplyShape", "k_pc_apply"],
-                            "sha256": "6be723b4d110307c", "bytes_per_launch": 1660.3e6},
+    "step1_precond_apply": {"src": "step1.hip", "funcs": ["PcWood", "k_pc_pass1", "k_pc_pass2"],
+                            "sha256": "2f89933d19e0075e", "bytes_per_launch": 1085.9e6},
     "trace_spmv": {"src": "kernels.hip", "funcs": ["k_spmv"], "sha256": "96d7545c27858460", "bytes_per_launch": 159.1e6},
     "trace_spmv_512": {"src": "kernels.hip", "funcs": ["k_spmv"], "sha256": "96d7545c27858460", "bytes_per_launch": 627.3e6},
     # tetrahedra, 32^3 Kuhn cubes, k = 2
@@ -92,11 +92,16 @@ def algorithmic_cost(kernel: str, k: int, nc: int, nF: int, nF_int: int | None =
     (own trace, neighbour trace, projection) plus ~10 for the jump and flux.
     trace_spmv (facet-block ELL, FP64): per facet row 5 blocks of (k+1)^2
     values, 5 int32 column ids, reads x and writes y ((k+1) doubles each).
-    step1_precond_apply (facet-patch Schwarz of the Step I operator): per
-    interior facet the FP16 inverse of its 2 nu x 2 nu block (nu = 2 ns),
-    read as two halves by the two cells, plus per cell the input and output
-    vectors (nu doubles each) and 3 int32 neighbour entries.  nF_int: the
-    interior facets (default nF).
+    step1_precond_apply (facet-patch Schwarz of the Step I operator in
+    Woodbury form, two launches per application; m = 2 (k+2) trace
+    coefficients of a cell on a facet, nu = 2 ns): per cell the FP16 rows
+    of the first pass (A_e^{-1} and the three rotated trace maps G_f, nu + 3m
+    rows of nu) and of H (nu x 3m), the input and output vectors (nu doubles
+    each), the first-pass results (nu + 3m doubles) written once and read
+    once, 3 int32 neighbour entries; per interior facet the two cells' rows
+    of the FP16 correction (2 x m x 2m) and two FP32 scales.  Flops: the two
+    matrix passes and three m x 2m products per cell.  nF_int: the interior
+    facets (default nF).
     """
     ns = (k + 2) * (k + 3) // 2
     nqf = (3 * k + 5) // 2
@@ -108,8 +113,10 @@ def algorithmic_cost(kernel: str, k: int, nc: int, nF: int, nF_int: int | None =
         return nbytes, flops
     if kernel == "step1_precond_apply":
         ni = nF if nF_int is None else nF_int
-        nbytes = ni * (2 * nu) ** 2 * 2 + nc * (2 * 8 * nu + 4 * 3)
-        flops = ni * 2 * 2 * nu * nu * 2
+        mt = 2 * (k + 2)
+        r1 = nu + 3 * mt
+        nbytes = nc * (2 * r1 * nu + 2 * nu * 3 * mt + 2 * 8 * nu + 2 * 8 * r1 + 4 * 3) + ni * (4 * mt * mt * 2 + 2 * 4)
+        flops = nc * (2 * r1 * nu + 2 * nu * 3 * mt + 2 * 6 * mt * mt)
         return nbytes, flops
     if kernel == "trace_spmv":
         nbytes = nF * (8 * 5 * nf * nf + 4 * 5 + 8 * 2 * nf)

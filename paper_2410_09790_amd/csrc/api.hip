@@ -389,7 +389,8 @@ struct hdg_ctx {
   double pc_adt = 0.0;
   bool pc_on = false;
   double* pcD = nullptr;          // cell blocks (FP64 scratch of the build)
-  void* pcB = nullptr;            // patch inverses (FP16)
+  void* pcB = nullptr;            // patch inverses (FP16; in 2D the cell inverses and facet corrections)
+  void* pcS = nullptr;            // 2D: first-pass results (A^{-1} r and the facet traces)
   long pc_builds = 0;
   void pc_prepare(double adt) {
     // rebuilt for a new adt, else when the stage data are step1_precond_lag generations newer
@@ -407,7 +408,7 @@ struct hdg_ctx {
   void pc_apply(const void* r, void* z) {
     hdg::Timed tm(prof, hdg::KC_PC_APPLY);
     if (dim == 3) hdg::launch3_pc_apply(k, st, dm, pcB, r, z, kx32);
-    else hdg::launch_pc_apply(k, st, dm, pcB, r, z, kx32);
+    else hdg::launch_pc_apply(k, st, dm, pcB, pcS, r, z, kx32);
   }
   int bicgstab(double adt, const double* b, double* x);
   static constexpr int kBicgBlock = 8;  // BiCGStab iterations per captured block
@@ -521,7 +522,7 @@ void hdg_ctx::setup_tri() {
   dt.Bu = cu(rt.Bu); dt.Gux = cu(rt.Gux); dt.Guy = cu(rt.Guy);
   dt.Bp = cu(rt.Bp); dt.Gpx = cu(rt.Gpx); dt.Gpy = cu(rt.Gpy); dt.cw = cu(rt.cq_w);
   dt.FBu = cu(rt.FBu); dt.FGux = cu(rt.FGux); dt.FGuy = cu(rt.FGuy); dt.FBp = cu(rt.FBp);
-  dt.fw = cu(rt.fq_w); dt.MU = cu(rt.MU); dt.NUB = cu(rt.NUB);
+  dt.fw = cu(rt.fq_w); dt.MU = cu(rt.MU); dt.NUB = cu(rt.NUB); dt.TRU = cu(rt.TRU);
   dt.Dx = cu(rt.Dx); dt.Dy = cu(rt.Dy); dt.Rx = cu(rt.Rx); dt.Ry = cu(rt.Ry);
   dt.Chat = cu(rt.Chat); dt.That = cu(rt.That); dt.Ehat = cu(rt.Ehat); dt.CC = cu(rt.CC);
   dt.KDD = cu(rt.KDD); dt.CD = cu(rt.CD); dt.BDMinv = cu(rt.BDMinv); dt.NED = cu(rt.NED);
@@ -584,7 +585,10 @@ void hdg_ctx::setup_work() {
     kd.ph = kvec();
     kd.sh = kvec();
     pcD = dalloc<double>(nc * nu * nu);
-    pcB = dalloc<uint16_t>(dim == 3 ? pc_entries3(k, nc) : pc_entries(k, nc));
+    const long npc = dim == 3 ? pc_entries3(k, nc) : pc_entries(k, nc);
+    pcB = dalloc<uint16_t>(npc);
+    HIPCHK(hipMemsetAsync(pcB, 0, npc * sizeof(uint16_t), st));  // padding entries stay zero
+    if (dim == 2) pcS = kx32 ? (void*)dalloc<float>(pc_scratch(k, nc)) : (void*)dalloc<double>(pc_scratch(k, nc));
   }
   const long nc32 = (nc + 31) / 32 * 32;
   vk32 = prm.precision == HDG_MIXED;
@@ -1643,7 +1647,7 @@ static void estimate_footprint(const hdg::HostMesh& m, const hdg::RefTables& rt,
   // mesh (geometry, connectivity, packed neighbours) and reference tables
   b += 8.0 * kDGeo * nc + 4.0 * 5 * 3 * nc + 4.0 * 4 * nF;
   for (const std::vector<double>* v : {&rt.Bu, &rt.Gux, &rt.Guy, &rt.Bp, &rt.Gpx, &rt.Gpy, &rt.cq_w, &rt.FBu, &rt.FGux,
-                                       &rt.FGuy, &rt.FBp, &rt.fq_w, &rt.MU, &rt.NUB, &rt.Dx, &rt.Dy, &rt.Rx, &rt.Ry,
+                                       &rt.FGuy, &rt.FBp, &rt.fq_w, &rt.MU, &rt.NUB, &rt.TRU, &rt.Dx, &rt.Dy, &rt.Rx, &rt.Ry,
                                        &rt.Chat, &rt.That, &rt.Ehat, &rt.CC, &rt.KDD, &rt.CD, &rt.BDMinv, &rt.NED})
     b += 8.0 * v->size();
   // work vectors: cell duals, trace vectors, Krylov and stage vectors
@@ -1657,7 +1661,8 @@ static void estimate_footprint(const hdg::HostMesh& m, const hdg::RefTables& rt,
   if (prm.idr_s > 0) b += 8.0 * (3.0 * prm.idr_s * nQ + kIdrMax + 8);
   // Step I preconditioner: two direction vectors, the cell blocks and the patch inverses
   if (prm.step1_precond == 1 && prm.idr_s == 0)
-    b += (x32 ? 4.0 : 8.0) * 2 * nQ + 8.0 * nc * nu * nu + 2.0 * (double)pc_entries(rt.k, (long)m.nc);
+    b += (x32 ? 4.0 : 8.0) * 2 * nQ + 8.0 * nc * nu * nu + 2.0 * (double)pc_entries(rt.k, (long)m.nc) +
+         (x32 ? 4.0 : 8.0) * (double)pc_scratch(rt.k, (long)m.nc);
   // trace operators
   std::set<double> cs = {1.0, tab.bim[tab.s - 1] * dtv};
   for (int i = 1; i < tab.s; ++i) cs.insert(tab.Aim[i][i] * dtv);

@@ -39,6 +39,7 @@ struct RefTables {
   std::vector<double> FBp;                       // [3][nqf][np]
   std::vector<double> MU;                        // [nqf][nf]   trace basis at s_q (local parameter)
   std::vector<double> NUB;                       // [nqf][k+2]  BDM facet-moment basis
+  std::vector<double> TRU;                       // [3][k+2][ns] Legendre coefficients of the trace on facet f
   // reference matrices
   std::vector<double> Dx, Dy;                    // [np][ns]  int psi_i d_a phi_s
   std::vector<double> Rx, Ry;                    // [np][ns]  int d_a psi_i phi_s

@@ -42,7 +42,7 @@ struct DTab3 {
 typedef const __attribute__((address_space(4))) double* cdptr;
 struct DTab {
   cdptr Bu, Gux, Guy, Bp, Gpx, Gpy, cw;
-  cdptr FBu, FGux, FGuy, FBp, fw, MU, NUB;
+  cdptr FBu, FGux, FGuy, FBp, fw, MU, NUB, TRU;
   cdptr Dx, Dy, Rx, Ry, Chat, That, Ehat, CC, KDD, CD, BDMinv, NED;
   DTab3 t3;  // tetrahedra
 };
@@ -146,14 +146,16 @@ void launch_bicg_xrp(hipStream_t st, long n, int np, const double* part2, double
                      bool x32);
 void launch_bicg_init(hipStream_t st, double* sc);  // zero a slot except BS_RHO
 // Step I preconditioner: additive Schwarz over facet patches (two cells per
-// interior facet) of the mass-scaled Step I operator.  launch_pc_build forms
-// the patch inverses for the Q* and adt of a stage (D: scratch of
-// nc * nu * nu doubles; Binv: pc_entries(k, nc) FP16 entries); launch_pc_apply
-// gives z = B r on structure-of-arrays vectors.
+// interior facet) of the mass-scaled Step I operator, in Woodbury form (cell
+// inverses and per-facet trace corrections).  launch_pc_build forms them for
+// the Q* and adt of a stage (D: scratch of nc * nu * nu doubles; Binv:
+// pc_entries(k, nc) FP16 entries); launch_pc_apply gives z = B r on
+// structure-of-arrays vectors (X: scratch of pc_scratch(k, nc) entries of the vectors' type).
 void launch_pc_build(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, double alpha,
                      double adt, double* D, void* Binv);
-void launch_pc_apply(int k, hipStream_t st, DMesh m, const void* Binv, const void* r, void* z, bool x32);
+void launch_pc_apply(int k, hipStream_t st, DMesh m, const void* Binv, void* X, const void* r, void* z, bool x32);
 long pc_entries(int k, long nc);
+long pc_scratch(int k, long nc);
 void launch_to_soa(int k, hipStream_t st, DMesh m, int inv_det, const double* x, void* y, bool x32);
 void launch_to_aos(int k, hipStream_t st, DMesh m, const void* x, double* y, bool x32);
 // Step I vectors in either type (x32: FP32): copy, fill, a x + b y, and FP64

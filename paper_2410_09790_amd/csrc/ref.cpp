@@ -218,6 +218,15 @@ void build_reference(int k, RefTables& t) {
     for (int m = 0; m < nf; ++m) t.MU[q * nf + m] = legendre01(m, t.fq_s[q]);
     for (int m = 0; m < k + 2; ++m) t.NUB[q * (k + 2) + m] = legendre01(m, t.fq_s[q]);
   }
+  // trace of a velocity-degree function on local facet f as a polynomial of
+  // degree k+1 in the facet parameter: its coefficients in the orthonormal
+  // Legendre basis (exact: the facet rule integrates degree 2k+2)
+  t.TRU.assign(3 * (k + 2) * ns, 0.0);
+  for (int f = 0; f < 3; ++f)
+    for (int q = 0; q < nq; ++q)
+      for (int m = 0; m < k + 2; ++m)
+        for (int s = 0; s < ns; ++s)
+          t.TRU[(f * (k + 2) + m) * ns + s] += t.fq_w[q] * t.NUB[q * (k + 2) + m] * t.FBu[(f * nq + q) * ns + s];
   // reference matrices
   t.Dx.assign(np * ns, 0.0); t.Dy.assign(np * ns, 0.0); t.Rx.assign(np * ns, 0.0); t.Ry.assign(np * ns, 0.0);
   for (int q = 0; q < t.nqc; ++q)

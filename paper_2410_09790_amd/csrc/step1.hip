@@ -492,28 +492,71 @@ __global__ void __launch_bounds__(kBlock) k_vdot(long n, const TX* __restrict__ 
 // is; single-cell blocks (block Jacobi) hold no such function across a
 // facet and lose that property.
 //
-// Storage: per (cell e, local facet f) the NU rows of A_F^{-1} that belong
-// to e, with the columns of e first and those of the neighbour after them,
-// as quads of adjacent columns in tiles of 32 cells (quad jq of row i at
-// ((((e/32)*3 + f)*NU + i)*NS + jq)*32 + e%32, NS = 2 NU / 4 quads per
-// row), in FP16: one 8-byte load per lane brings four entries.  Slots of
-// wall facets are never read.  Precision: the entries are bounded (the
-// symmetric part of A_F is at least the identity up to the divergence of Q*,
-// so |A_F^{-1}| <~ 1), and FP16 keeps them to 5e-4 relative; a preconditioner
-// that accurate converges like the exact one, and the solution does not
-// depend on it.  The conversion saturates, so no entry can become infinite.
+// Woodbury form.  Within a patch the two cells are coupled only through
+// their traces on F, and the trace of a velocity-degree function is a
+// polynomial of degree k+1 in the facet parameter.  With L_f the map from a
+// cell's coefficients to the orthonormal Legendre coefficients of its trace
+// on local facet f (nm = k+2 per component, m = 2 nm in all, in the cell's
+// own facet parameter; the reference table TRU), the patch block is
+//   A_F = Bd + U^T Kf U,  Bd = diag(A_+, A_-),  U = diag(L_{f+}, L_{f-}),
+// where A_e is the whole own-cell block of the operator and Kf (2m x 2m) the
+// facet quadrature of the two coupling blocks (zero diagonal blocks).  Then
+//   A_F^{-1} = Bd^{-1} - Bd^{-1} U^T M_F U Bd^{-1},  M_F = (I + Kf U Bd^{-1} U^T)^{-1} Kf,
+// an exact identity, so this is the same preconditioner as the dense patch
+// inverses.  Per cell, with R_f the rotation of the trace components into
+// the (normal, tangent) frame of facet f,
+//   z_e = n_int(e) A_e^{-1} r_e - sum_f H_f W_f [G_f r_e ; G_{f'} r_{n(f)}],
+//   G_f = R_f L_f A_e^{-1},  H_f = A_e^{-1} L_f^T R_f^T,
+// W_f the m rows of M_F that belong to e, rotated on both sides (own trace
+// columns first, the neighbour's in its own frame).  The rotation is what
+// makes FP16 storage safe: M_F grows like adt/h^2 in its normal-normal block
+// only, the normal traces of A_e^{-1} r are smaller by the same factor, and
+// in x/y components those small normal traces would be differences of O(1)
+// numbers that FP16 cannot resolve.  In the facet frame every stored number
+// keeps its own relative precision.  The products G_f, H_f are stored, not
+// formed from A_e^{-1} in the apply, for the same reason.
+//
+// Storage (FP16, in tiles of 32 cells; thread g of a cell's G = 6 threads
+// reads one contiguous run of quads, lane = cell % 32 fastest, zero padded):
+// * pass 1, rows [g RG1, (g+1) RG1) of the stacked [A_e^{-1}; G_0; G_1; G_2]
+//   (NU + 3m rows of NU entries);
+// * W: thread g = 2 f + h holds the nm rows of W_f of frame component h
+//   (normal, tangent), each of 2m entries;
+// * H: rows [g RG, (g+1) RG) of [H_0 H_1 H_2] (NU rows of 3m entries);
+// * one FP32 scale per (cell, facet), a power of two: W is stored divided by
+//   it, so that its largest entry is at most 2^14 whatever the mesh size and
+//   time step.
+// At k = 3: 1,800 + 600 + 900 entries per cell against 3 x 1,800 for the
+// dense rows.  Slots of wall facets are never written or read.
 using pc_t = _Float16;
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
-template <int K>
-struct PcLayout {
-  static constexpr int NU = Dims<K>::NU, NQ = Dims<K>::NS;  // 2 NU = 4 NQ
-  __device__ static long quad(long e, int f, int i, int jq) {
-    return ((((e >> 5) * 3 + f) * (long)NU + i) * NQ + jq) * 32 + (e & 31);
-  }
-};
 __device__ __forceinline__ pc_t pc_store(double v) {
   const double lim = 65504.0;  // largest finite FP16
   return (pc_t)(v > lim ? lim : (v < -lim ? -lim : v));
+}
+template <int K>
+struct PcWood {
+  static constexpr int NU = Dims<K>::NU, NS = Dims<K>::NS, NM = K + 2;
+  static constexpr int M = 2 * NM;                 // trace coefficients of one cell on one facet
+  static constexpr int G = 6;                      // threads per cell in the apply (3 facets x 2)
+  static constexpr int R1 = NU + 3 * M;            // rows of the pass-1 matrix
+  static constexpr int RG1 = (R1 + G - 1) / G;     // pass-1 rows per thread
+  static constexpr int NQ1 = (RG1 * NU + 3) / 4;   // pass-1 quads per thread
+  static constexpr int NQW = NM * NM;              // W quads per thread: nm rows of 2m = 4 nm entries
+  static constexpr int RG = (NU + G - 1) / G;      // H rows per thread
+  static constexpr int NQH = (RG * 3 * M + 3) / 4; // H quads per thread
+  __host__ __device__ static long w_off(long nc32) { return nc32 * G * NQ1 * 4; }
+  __host__ __device__ static long h_off(long nc32) { return w_off(nc32) + nc32 * G * NQW * 4; }
+  __host__ __device__ static long scale_off(long nc32) { return h_off(nc32) + nc32 * G * NQH * 4; }
+  __host__ __device__ static long entries(long nc32) { return scale_off(nc32) + 2 * 3 * nc32; }
+  __device__ static long q(long e, int g, int nq, int i) { return (((e >> 5) * G + g) * (long)nq + i) * 32 + (e & 31); }
+};
+// Rotation of facet f of cell e: row 0 the outward normal n, row 1 the tangent (-n_y, n_x).
+__device__ __forceinline__ void facet_frame(const DMesh& m, long e, int f, double R[2][2]) {
+  const long nc = m.nc;
+  const double nx = m.geo[(D_NX0 + 2 * f) * nc + e], ny = m.geo[(D_NY0 + 2 * f) * nc + e];
+  R[0][0] = nx; R[0][1] = ny;
+  R[1][0] = -ny; R[1][1] = nx;
 }
 
 // Own-cell block of the mass-scaled Step I operator, row i = (c, s) of cell
@@ -588,50 +631,135 @@ __global__ void __launch_bounds__(kBlock) k_pc_cellblock(DMesh m, DTab t, const 
   }
 }
 
-// Threads of the patch kernel: NC column slots (64 per wave) times NH row
-// parts.  At k >= 3 a column of 2 NU rows would not fit in registers, so it
-// is split between two waves, one per cell of the patch.
+// In-place inverse of each cell block (FP64, kept for the facet pass), and
+// its FP16 products in the apply layout: A_e^{-1}, G_f and H_f.  Gauss-Jordan
+// elimination without pivoting (the symmetric part of the block is positive
+// definite, as for the patches), one thread per column holding it in
+// registers, the pivot column and row through LDS (two buffers each, one
+// barrier per pivot); then the inverse goes through LDS once more so that
+// thread j can read row j for H.  NC lanes per cell, 64 / NC cells per
+// workgroup.
 template <int K>
-struct PcPatchShape {
-  static constexpr int N = 2 * Dims<K>::NU;
-  static constexpr int NH = N > 40 ? 2 : 1;
-  static constexpr int NC = (N + 63) / 64 * 64;
-  static constexpr int HN = N / NH;  // rows per thread
-  static constexpr int NT = NC * NH;
+struct PcInvShape {
+  static constexpr int NC = Dims<K>::NU <= 32 ? 32 : 64;
+  static constexpr int CPB = 64 / NC;
 };
-
-// One workgroup per facet: assemble A_F of an interior facet column by column
-// (thread (j, h) holds rows [h HN, (h+1) HN) of column j in registers), invert
-// it by Gauss-Jordan elimination without pivoting (the symmetric part of A_F
-// is positive definite: mass plus the dissipative penalty and upwind terms,
-// the advective part being skew up to the own-side flux
-// (1/2 - delta_up)|Q*.n| <= 0 on the cut facets), and store each cell's rows
-// of the inverse as described above.  Wall facets return at once.
 template <int K>
-__global__ void __launch_bounds__(PcPatchShape<K>::NT) k_pc_patch(DMesh m, DTab t, const double* __restrict__ Qs,
-                                                                  double delta_up, double alpha, double adt,
-                                                                  const double* __restrict__ D,
-                                                                  pc_t* __restrict__ Binv) {
+__global__ void __launch_bounds__(64) k_pc_cellinv(DMesh m, DTab t, double* __restrict__ D, pc_t* __restrict__ P) {
+  using W = PcWood<K>;
+  constexpr int NU = W::NU, NS = W::NS, NM = W::NM, M = W::M, RG1 = W::RG1, NQ1 = W::NQ1, RG = W::RG,
+                NQH = W::NQH, NC = PcInvShape<K>::NC, CPB = PcInvShape<K>::CPB;
+  const long nc = m.nc, nc32 = (nc + 31) / 32 * 32;
+  __shared__ double scol[2][CPB][NU], srow[2][CPB][NC];
+  __shared__ double sinv[CPB][NU][NU + 1];
+  const int slot = threadIdx.x / NC, j = threadIdx.x % NC;
+  const long e = (long)blockIdx.x * CPB + slot;
+  const long ec = e < nc ? e : nc - 1;  // a spare slot inverts a copy of the last cell
+  const int jc = j < NU ? j : 0;        // idle lanes carry a copy of column 0
+  double col[NU];
+#pragma unroll
+  for (int r = 0; r < NU; ++r) col[r] = D[(ec * NU + r) * NU + jc];
+#pragma unroll 1
+  for (int p = 0; p < NU; ++p) {
+    double* cp = scol[p & 1][slot];
+    double* rp = srow[p & 1][slot];
+    if (j == p) {
+#pragma unroll
+      for (int r = 0; r < NU; ++r) cp[r] = col[r];
+    }
+    double v = 0.0;
+#pragma unroll
+    for (int r = 0; r < NU; ++r) v = r == p ? col[r] : v;
+    rp[j] = v;
+    __syncthreads();
+    const double d = 1.0 / cp[p];
+    if (j == p) {
+#pragma unroll
+      for (int r = 0; r < NU; ++r) col[r] = r == p ? d : -cp[r] * d;
+    } else {
+      const double a = rp[j] * d;
+#pragma unroll
+      for (int r = 0; r < NU; ++r) col[r] = r == p ? a : col[r] - cp[r] * a;
+    }
+  }
+  if (j < NU) {
+#pragma unroll
+    for (int r = 0; r < NU; ++r) sinv[slot][r][j] = col[r];
+  }
+  __syncthreads();
+  if (e >= nc || j >= NU) return;
+  auto put1 = [&](int row, double v) {  // entry (row, j) of the pass-1 matrix
+    const int flat = (row % RG1) * NU + j;
+    P[4 * W::q(e, row / RG1, NQ1, flat >> 2) + (flat & 3)] = pc_store(v);
+  };
+#pragma unroll
+  for (int r = 0; r < NU; ++r) {
+    D[(e * NU + r) * NU + j] = col[r];
+    put1(r, col[r]);
+  }
+  pc_t* PH = P + W::h_off(nc32);
+#pragma unroll 1
+  for (int f = 0; f < 3; ++f) {
+    double R[2][2];
+    facet_frame(m, e, f, R);
+    for (int mm = 0; mm < NM; ++mm) {
+      // column j of L_f A^{-1} (both components), then rotated: G_f[:, j]
+      double lx = 0.0, ly = 0.0, hx = 0.0, hy = 0.0;
+      for (int s = 0; s < NS; ++s) {
+        const double l = t.TRU[(f * NM + mm) * NS + s];
+        lx += l * col[s];
+        ly += l * col[NS + s];
+        hx += l * sinv[slot][j][s];  // row j of A^{-1} L_f^T
+        hy += l * sinv[slot][j][NS + s];
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        put1(NU + f * M + h * NM + mm, R[h][0] * lx + R[h][1] * ly);
+        const int flat = (j % RG) * 3 * M + f * M + h * NM + mm;
+        PH[4 * W::q(e, j / RG, NQH, flat >> 2) + (flat & 3)] = pc_store(R[h][0] * hx + R[h][1] * hy);
+      }
+    }
+  }
+}
+
+// One 64-thread workgroup per interior facet: the two cell inverses into
+// LDS, S_side = L A_side^{-1} L^T, the coupling Kf from the facet rule (the
+// same terms as the patch entries: upwind weight on the own component,
+// normal-jump penalty on both, scaled by adt / det of the row cell), then
+// [I + Kf S | Kf] reduced by Gauss-Jordan elimination with partial pivoting
+// (I + Kf S need not be diagonally dominant), and each cell's rows of M_F,
+// rotated into the facet frames, stored with their scale.  Wall facets
+// return at once.
+template <int K>
+__global__ void __launch_bounds__(64) k_pc_facet(DMesh m, DTab t, const double* __restrict__ Qs, double delta_up,
+                                                 double alpha, double adt, const double* __restrict__ Ai,
+                                                 pc_t* __restrict__ P) {
   using Dm = Dims<K>;
-  using Sh = PcPatchShape<K>;
-  constexpr int NS = Dm::NS, NU = Dm::NU, NQF = Dm::NQF, N = Sh::N, NH = Sh::NH, HN = Sh::HN, NC = Sh::NC;
+  using W = PcWood<K>;
+  constexpr int NS = Dm::NS, NU = Dm::NU, NQF = Dm::NQF, NM = W::NM, M = W::M, M2 = 2 * M, NQW = W::NQW;
   const int F = blockIdx.x;
-  const long nc = m.nc;
+  const long nc = m.nc, nc32 = (nc + 31) / 32 * 32;
   const int Km = m.fc_cell[m.nF + F];
-  if (Km < 0) return;  // wall facet: no patch (uniform over the workgroup)
+  if (Km < 0) return;  // uniform over the workgroup
   const int Kp = m.fc_cell[F];
   const int fp = m.fc_f[F], fm = m.fc_f[m.nF + F];
   const int rev = (m.cf_nbx[fp * nc + Kp] & 1);
-  // side 0 = K+, side 1 = K- (selects, not arrays: an array indexed by a
-  // runtime side would live in scratch memory)
   auto cell = [&](int side) { return side ? Km : Kp; };
   auto lf = [&](int side) { return side ? fm : fp; };
-  __shared__ double sbeta[2][NQF];
-  __shared__ double scol[2][N], srow[2][NC];
-  const int j = threadIdx.x % NC, h = threadIdx.x / NC;
-  // upwind weights of both sides at their own facet points (side 0 = K+)
-  if (threadIdx.x < 2 * NQF) {
-    const int side = threadIdx.x / NQF, qq = threadIdx.x % NQF;
+  __shared__ double sA[2][NU][NU + 1];
+  __shared__ double sT[2][NU][M];
+  __shared__ double sS[2][M][M];
+  __shared__ double sa[M2][2 * M2 + 1];
+  __shared__ double sw[M][M2];
+  __shared__ double sbeta[2][NQF], scp[M2], smax[64];
+  __shared__ int spiv;
+  const int tid = threadIdx.x;
+  for (int x = tid; x < 2 * NU * NU; x += 64) {
+    const int side = x / (NU * NU), i = (x / NU) % NU, j = x % NU;
+    sA[side][i][j] = Ai[((long)cell(side) * NU + i) * NU + j];
+  }
+  if (tid < 2 * NQF) {  // upwind weights of both sides at their own facet points
+    const int side = tid / NQF, qq = tid % NQF;
     const int e = cell(side), f = lf(side);
     const double nx = m.geo[(D_NX0 + 2 * f) * nc + e], ny = m.geo[(D_NY0 + 2 * f) * nc + e];
     const double hf = m.geo[(D_H0 + f) * nc + e];
@@ -645,137 +773,226 @@ __global__ void __launch_bounds__(PcPatchShape<K>::NT) k_pc_patch(DMesh m, DTab 
     sbeta[side][qq] = t.fw[qq] * hf * (0.5 * qn - delta_up * fabs(qn));
   }
   __syncthreads();
-  const int jc = j < N ? j : 0;          // idle lanes build a copy of column 0 and discard it
-  const int sj = jc / NU, jj = jc % NU;  // column side and unknown (c', s') on that side
-  const int cj = jj / NS, s2 = jj % NS;
-  // row r of the patch on side rs: the cell block when rs == sj, else the
-  // coupling of the row cell (side rs) to the column cell through F
-  auto entry = [&](int rs, int rr) -> double {
-    if (rs == sj) return D[((long)cell(sj) * NU + rr) * NU + jj];
-    const int eo = cell(rs), fo = lf(rs), fcol = lf(sj);
-    const double nx = m.geo[(D_NX0 + 2 * fo) * nc + eo], ny = m.geo[(D_NY0 + 2 * fo) * nc + eo];
-    const int cr = rr / NS, sr = rr % NS;
-    const double ncr = cr ? ny : nx, ncj = cj ? ny : nx;
+  // T = A^{-1} L^T (rows (c, s), columns (c', m'))
+  for (int x = tid; x < 2 * NU * M; x += 64) {
+    const int side = x / (NU * M), i = (x / M) % NU, cm = x % M;
+    const int c2 = cm / NM, m2 = cm % NM, f = lf(side);
     double v = 0.0;
-    for (int qq = 0; qq < NQF; ++qq) {
-      const double coef = (cr == cj ? sbeta[rs][qq] : 0.0) - alpha * t.fw[qq] * ncr * ncj;
-      v += t.FBu[(fo * NQF + qq) * NS + sr] * t.FBu[(fcol * NQF + (rev ? NQF - 1 - qq : qq)) * NS + s2] * coef;
+    for (int s2 = 0; s2 < NS; ++s2) v += sA[side][i][c2 * NS + s2] * t.TRU[(f * NM + m2) * NS + s2];
+    sT[side][i][cm] = v;
+  }
+  // Kf into the right half of the augmented matrix
+  for (int x = tid; x < M2 * M2; x += 64) {
+    const int r = x / M2, jj = x % M2, a = r / M, b = jj / M;
+    double v = 0.0;
+    if (a != b) {
+      const int e = cell(a), f = lf(a);
+      const int c = (r % M) / NM, mr = (r % M) % NM, c2 = (jj % M) / NM, mc = (jj % M) % NM;
+      const double nx = m.geo[(D_NX0 + 2 * f) * nc + e], ny = m.geo[(D_NY0 + 2 * f) * nc + e];
+      const double nn = (c ? ny : nx) * (c2 ? ny : nx);
+      for (int qq = 0; qq < NQF; ++qq) {
+        const double coef = (c == c2 ? sbeta[a][qq] : 0.0) - alpha * t.fw[qq] * nn;
+        v += t.NUB[qq * NM + mr] * t.NUB[(rev ? NQF - 1 - qq : qq) * NM + mc] * coef;
+      }
+      v *= adt / m.geo[D_DET * nc + e];
     }
-    return adt / m.geo[D_DET * nc + eo] * v;
-  };
-  // the block is assembled in LDS (a loop that is not unrolled, so the
-  // assembly's table loads do not crowd the registers), then each thread
-  // takes its part of a column into registers
-  __shared__ double sA[N][N + 1];
-  if (j < N) {
-#pragma unroll 1
-    for (int r = 0; r < HN; ++r) {
-      const int gr = h * HN + r;  // patch row (h is uniform per wave)
-      sA[gr][j] = entry(gr / NU, gr % NU);
-    }
+    sa[r][M2 + jj] = v;
   }
   __syncthreads();
-  double col[HN];
-#pragma unroll
-  for (int r = 0; r < HN; ++r) col[r] = sA[h * HN + r][jc];
-  // in-place Gauss-Jordan inversion; the pivot column and the pivot row go
-  // through LDS (two buffers each, so the next pivot's writes need no
-  // second barrier)
-  // (the pivot loop is not unrolled: the pivot's row is picked out of the
-  // registers by selects, never by a runtime index)
+  // S = L T
+  for (int x = tid; x < 2 * M * M; x += 64) {
+    const int side = x / (M * M), r = (x / M) % M, cm = x % M;
+    const int c = r / NM, mr = r % NM, f = lf(side);
+    double v = 0.0;
+    for (int s = 0; s < NS; ++s) v += t.TRU[(f * NM + mr) * NS + s] * sT[side][c * NS + s][cm];
+    sS[side][r][cm] = v;
+  }
+  __syncthreads();
+  // left half: I + Kf S (S block diagonal, Kf off-diagonal)
+  for (int x = tid; x < M2 * M2; x += 64) {
+    const int r = x / M2, jj = x % M2, a = r / M, b = jj / M;
+    double v = r == jj ? 1.0 : 0.0;
+    if (a != b)
+      for (int i = 0; i < M; ++i) v += sa[r][M2 + b * M + i] * sS[b][i][jj % M];
+    sa[r][jj] = v;
+  }
+  __syncthreads();
 #pragma unroll 1
-  for (int p = 0; p < N; ++p) {
-    double* cp = scol[p & 1];
-    double* rp = srow[p & 1];
-    const int hp = p / HN, lp = p % HN;
-    if (j == p) {
-#pragma unroll
-      for (int r = 0; r < HN; ++r) cp[h * HN + r] = col[r];
-    }
-    if (h == hp) {
-      double v = 0.0;
-#pragma unroll
-      for (int r = 0; r < HN; ++r) v = r == lp ? col[r] : v;
-      rp[j] = v;
+  for (int p = 0; p < M2; ++p) {
+    if (tid == 0) {
+      int best = p;
+      double bv = fabs(sa[p][p]);
+      for (int r = p + 1; r < M2; ++r)
+        if (fabs(sa[r][p]) > bv) { bv = fabs(sa[r][p]); best = r; }
+      spiv = best;
     }
     __syncthreads();
-    const double d = 1.0 / cp[p];
-    if (j == p) {
-#pragma unroll
-      for (int r = 0; r < HN; ++r) col[r] = (h == hp && r == lp) ? d : -cp[h * HN + r] * d;
-    } else {
-      const double a = rp[j] * d;
-#pragma unroll
-      for (int r = 0; r < HN; ++r) col[r] = (h == hp && r == lp) ? a : col[r] - cp[h * HN + r] * a;
+    const int pv = spiv;
+    if (pv != p)
+      for (int j = tid; j < 2 * M2; j += 64) {
+        const double v = sa[p][j];
+        sa[p][j] = sa[pv][j];
+        sa[pv][j] = v;
+      }
+    __syncthreads();
+    for (int r = tid; r < M2; r += 64) scp[r] = sa[r][p];
+    __syncthreads();
+    const double d = 1.0 / scp[p];
+    for (int j = tid; j < 2 * M2; j += 64) {
+      const double rowp = sa[p][j] * d;
+      for (int r = 0; r < M2; ++r) sa[r][j] = r == p ? rowp : sa[r][j] - scp[r] * rowp;
     }
+    __syncthreads();
   }
-  if (j >= N) return;
-  // rows of column j of the inverse: rows of K+ keep the column order (own,
-  // then neighbour); rows of K- see K- as own and K+ as neighbour
-#pragma unroll
-  for (int r = 0; r < HN; ++r) {
-    const int gr = h * HN + r, side = gr / NU, rr = gr % NU;
-    const int jb = side == 0 ? j : (j >= NU ? j - NU : j + NU);
-    Binv[4 * PcLayout<K>::quad(cell(side), lf(side), rr, jb >> 2) + (jb & 3)] = pc_store(col[r]);
+  // M_F = right half.  Side a keeps rows [a M, (a+1) M), its own columns
+  // first; rows and columns rotated by the frame of the side they belong to.
+  float* scale = reinterpret_cast<float*>(P + W::scale_off(nc32));
+  pc_t* PW = P + W::w_off(nc32);
+#pragma unroll 1
+  for (int a = 0; a < 2; ++a) {
+    double Ra[2][2], Rb[2][2];
+    facet_frame(m, cell(a), lf(a), Ra);
+    facet_frame(m, cell(1 - a), lf(1 - a), Rb);
+    double mx = 0.0;
+    for (int x = tid; x < M * M2; x += 64) {
+      const int r = x / M2, j = x % M2;
+      const int h = r / NM, mr = r % NM, own = j < M, h2 = (j % M) / NM, mc = (j % M) % NM;
+      const int b = own ? a : 1 - a;
+      double v = 0.0;
+      for (int c = 0; c < 2; ++c)
+        for (int c2 = 0; c2 < 2; ++c2)
+          v += Ra[h][c] * sa[a * M + c * NM + mr][M2 + b * M + c2 * NM + mc] * (own ? Ra[h2][c2] : Rb[h2][c2]);
+      sw[r][j] = v;
+      mx = fmax(mx, fabs(v));
+    }
+    smax[tid] = mx;
+    __syncthreads();
+    if (tid == 0) {
+      double v = 0.0;
+      for (int i = 0; i < 64; ++i) v = fmax(v, smax[i]);
+      smax[0] = v > 0.0 ? ldexp(1.0, ilogb(v) - 13) : 1.0;  // v / sc < 2^14
+    }
+    __syncthreads();
+    const double sc = smax[0];
+    const long e = cell(a);
+    const int f = lf(a);
+    if (tid == 0) scale[f * nc32 + e] = (float)sc;
+    for (int x = tid; x < M * M2; x += 64) {
+      const int r = x / M2, j = x % M2;
+      const int h = r / NM, mr = r % NM, flat = mr * M2 + j;
+      PW[4 * W::q(e, 2 * f + h, NQW, flat >> 2) + (flat & 3)] = pc_store(sw[r][j] / sc);
+    }
+    __syncthreads();
   }
 }
 
-// z = B r on structure-of-arrays vectors: thread (cell e, rows i in group g)
-// sums over the cell's interior facets the rows of A_F^{-1} applied to
-// (r_e, r_neighbour); no scatter, so no atomics, and a fixed order.
-template <int K>
-struct PcApplyShape {
-  static constexpr int NU = Dims<K>::NU;
-  static constexpr int G = K == 1 ? 2 : (K == 2 ? 4 : 6);  // row groups per cell
-  static constexpr int RG = NU / G;
-  static_assert(RG * G == NU, "rows split evenly");
-};
+// z = B r, first pass: the stacked rows [A_e^{-1}; G_0; G_1; G_2] applied to
+// r_e, G threads per cell, thread g the rows [g RG1, (g+1) RG1): into X
+// the NU entries of s = A_e^{-1} r_e, then the 3m rotated traces.  X is
+// structure-of-arrays, row i of cell e at i * nc + e.  Both passes compute
+// in the type of the Krylov vectors: in FP32 the preconditioner's rounding
+// would change with its input at the 1e-7 level, and BiCGStab, which
+// assumes a fixed preconditioner, slows down on the way to 1e-10.
 template <int K, typename TX>
-__global__ void __launch_bounds__(kBlock) k_pc_apply(DMesh m, const pc_t* __restrict__ Binv,
-                                                     const TX* __restrict__ r, TX* __restrict__ z) {
-  using Sh = PcApplyShape<K>;
-  constexpr int NU = Dims<K>::NU, NQ = PcLayout<K>::NQ, G = Sh::G, RG = Sh::RG;
+__global__ void __launch_bounds__(kBlock) k_pc_pass1(long nc, const pc_t* __restrict__ P, const TX* __restrict__ r,
+                                                     TX* __restrict__ X) {
+  using W = PcWood<K>;
+  constexpr int NU = W::NU, G = W::G, RG1 = W::RG1, NQ1 = W::NQ1, R1 = W::R1;
   const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long nc = m.nc;
   const long tile = tid / (G * 32);
   const int rem = (int)(tid % (G * 32));
   const int g = rem >> 5;
   const long e = tile * 32 + (rem & 31);
   if (e >= nc) return;
-  double acc[RG];
+  TX rv[NU], acc[RG1];
 #pragma unroll
-  for (int a = 0; a < RG; ++a) acc[a] = 0.0;
-  double ro[NU];
+  for (int a = 0; a < NU; ++a) rv[a] = r[(long)a * nc + e];
 #pragma unroll
-  for (int a = 0; a < NU; ++a) ro[a] = r[(long)a * nc + e];
-  const f16x4* B4 = reinterpret_cast<const f16x4*>(Binv);
-#pragma unroll 1
-  for (int f = 0; f < 3; ++f) {
-    const int nbx = m.cf_nbx[f * nc + e];
-    if (nbx < 0) continue;
-    const long en = nbx >> 3;
-    double rn[NU];
+  for (int a = 0; a < RG1; ++a) acc[a] = 0;
+  const f16x4* A4 = reinterpret_cast<const f16x4*>(P);
 #pragma unroll
-    for (int a = 0; a < NU; ++a) rn[a] = r[(long)a * nc + en];
+  for (int q = 0; q < NQ1; ++q) {
+    const f16x4 b = __builtin_nontemporal_load(&A4[W::q(e, g, NQ1, q)]);
+    const TX bv[4] = {(TX)b.x, (TX)b.y, (TX)b.z, (TX)b.w};
 #pragma unroll
-    for (int a = 0; a < RG; ++a) {
-      const int i = g * RG + a;
-      double v = 0.0;
-#pragma unroll
-      for (int jq = 0; jq < NQ; ++jq) {
-        const f16x4 b = __builtin_nontemporal_load(&B4[PcLayout<K>::quad(e, f, i, jq)]);
-        const double bv[4] = {(double)b.x, (double)b.y, (double)b.z, (double)b.w};
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int jx = 4 * jq + u;
-          v += bv[u] * (jx < NU ? ro[jx] : rn[jx - NU]);
-        }
-      }
-      acc[a] += v;
+    for (int u = 0; u < 4; ++u) {
+      const int flat = 4 * q + u;
+      if (flat < RG1 * NU) acc[flat / NU] += bv[u] * rv[flat % NU];
     }
   }
 #pragma unroll
-  for (int a = 0; a < RG; ++a) z[(long)(g * RG + a) * nc + e] = (TX)acc[a];
+  for (int a = 0; a < RG1; ++a)
+    if (g * RG1 + a < R1) X[(long)(g * RG1 + a) * nc + e] = acc[a];
+}
+
+// Second pass, one workgroup per tile of 32 cells (G half-wave groups):
+// thread g = 2 f + h applies the frame-component-h rows of W_f to the own
+// and the neighbour's rotated traces on facet f (LDS exchange), then thread
+// g writes its rows of n_int s - sum_f H_f c_f.
+template <int K, typename TX>
+__global__ void __launch_bounds__(PcWood<K>::G * 32) k_pc_pass2(DMesh m, const pc_t* __restrict__ P,
+                                                                const TX* __restrict__ X, TX* __restrict__ z) {
+  using W = PcWood<K>;
+  constexpr int NU = W::NU, NM = W::NM, M = W::M, RG = W::RG, NQW = W::NQW, NQH = W::NQH;
+  const long nc = m.nc, nc32 = (nc + 31) / 32 * 32;
+  const int lane = threadIdx.x & 31, g = threadIdx.x >> 5;
+  const long e = (long)blockIdx.x * 32 + lane;
+  const long ec = e < nc ? e : nc - 1;
+  const int f = g >> 1, h = g & 1;
+  __shared__ TX sC[3][M][32];
+  {
+    const int nbx = m.cf_nbx[f * nc + ec];
+    TX cc[NM];
+#pragma unroll
+    for (int mm = 0; mm < NM; ++mm) cc[mm] = 0;
+    if (nbx >= 0) {
+      const long x = nbx >> 3;
+      const int fx = (nbx >> 1) & 3;
+      TX tau[2 * M];
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        tau[j] = X[(long)(NU + f * M + j) * nc + ec];
+        tau[M + j] = X[(long)(NU + fx * M + j) * nc + x];
+      }
+      const f16x4* W4 = reinterpret_cast<const f16x4*>(P + W::w_off(nc32));
+#pragma unroll
+      for (int q = 0; q < NQW; ++q) {
+        const f16x4 b = __builtin_nontemporal_load(&W4[W::q(ec, g, NQW, q)]);
+        const TX bv[4] = {(TX)b.x, (TX)b.y, (TX)b.z, (TX)b.w};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cc[(4 * q + v) / (2 * M)] += bv[v] * tau[(4 * q + v) % (2 * M)];
+      }
+      const TX sc = reinterpret_cast<const float*>(P + W::scale_off(nc32))[f * nc32 + ec];
+#pragma unroll
+      for (int mm = 0; mm < NM; ++mm) cc[mm] *= sc;
+    }
+#pragma unroll
+    for (int mm = 0; mm < NM; ++mm) sC[f][h * NM + mm][lane] = cc[mm];
+  }
+  __syncthreads();
+  if (e >= nc) return;
+  TX c[3 * M], acc[RG];
+#pragma unroll
+  for (int j = 0; j < 3 * M; ++j) c[j] = sC[j / M][j % M][lane];
+#pragma unroll
+  for (int a = 0; a < RG; ++a) acc[a] = 0;
+  const f16x4* H4 = reinterpret_cast<const f16x4*>(P + W::h_off(nc32));
+#pragma unroll
+  for (int q = 0; q < NQH; ++q) {
+    const f16x4 b = __builtin_nontemporal_load(&H4[W::q(e, g, NQH, q)]);
+    const TX bv[4] = {(TX)b.x, (TX)b.y, (TX)b.z, (TX)b.w};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int flat = 4 * q + v;
+      if (flat < RG * 3 * M) acc[flat / (3 * M)] += bv[v] * c[flat % (3 * M)];
+    }
+  }
+  const TX nint = (TX)((m.cf_nbx[e] >= 0) + (m.cf_nbx[nc + e] >= 0) + (m.cf_nbx[2 * nc + e] >= 0));
+#pragma unroll
+  for (int a = 0; a < RG; ++a) {
+    const int row = g * RG + a;
+    if (row < NU) z[(long)row * nc + e] = nint * X[(long)row * nc + e] - acc[a];
+  }
 }
 
 // ============================================================== launchers
@@ -899,27 +1116,41 @@ void launch_vdot(hipStream_t st, long n, const void* a, const void* b, double* p
   else k_vdot<double><<<kRedBlocks, kBlock, 0, st>>>(n, (const double*)a, (const double*)b, part);
 }
 // Facet-patch preconditioner of the Step I operator for the Q* and adt of a
-// stage: cell blocks (D, FP64 scratch of nc*NU*NU doubles) then the patch
-// inverses (Binv, pc_entries(k, nc) = ceil(nc/32)*32*3*NU*2NU entries of FP16).
+// stage, in Woodbury form: cell blocks (D, FP64 scratch of nc*NU*NU doubles,
+// left holding their inverses), then the FP16 cell inverses and facet
+// corrections (Binv, pc_entries(k, nc) FP16 entries).
 void launch_pc_build(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, double alpha,
                      double adt, double* D, void* Binv) {
   HDG_DISPATCH(k, (k_pc_cellblock<KK><<<nblocks((long)m.nc * Dims<KK>::NU), kBlock, 0, st>>>(m, t, Qs, delta_up,
                                                                                               alpha, adt, D)));
-  HDG_DISPATCH(k, (k_pc_patch<KK><<<m.nF, PcPatchShape<KK>::NT, 0, st>>>(m, t, Qs, delta_up, alpha, adt, D,
-                                                                         (pc_t*)Binv)));
+  HDG_DISPATCH(k, (k_pc_cellinv<KK><<<(m.nc + PcInvShape<KK>::CPB - 1) / PcInvShape<KK>::CPB, 64, 0, st>>>(
+                      m, t, D, (pc_t*)Binv)));
+  HDG_DISPATCH(k, (k_pc_facet<KK><<<m.nF, 64, 0, st>>>(m, t, Qs, delta_up, alpha, adt, D, (pc_t*)Binv)));
 }
-void launch_pc_apply(int k, hipStream_t st, DMesh m, const void* Binv, const void* r, void* z, bool x32) {
+// z = B r: the first pass into the scratch X (pc_scratch(k, nc) entries
+// of the vectors' type), then the trace correction
+void launch_pc_apply(int k, hipStream_t st, DMesh m, const void* Binv, void* X, const void* r, void* z, bool x32) {
+  const long nc32 = ((long)m.nc + 31) / 32 * 32;
+  const int nb1 = nblocks(nc32 * 6), nb2 = (int)(nc32 / 32);
   if (x32) {
-    HDG_DISPATCH(k, (k_pc_apply<KK, float><<<nblocks((long)(m.nc + 31) / 32 * 32 * PcApplyShape<KK>::G), kBlock, 0,
-                                             st>>>(m, (const pc_t*)Binv, (const float*)r, (float*)z)));
+    HDG_DISPATCH(k, (k_pc_pass1<KK, float><<<nb1, kBlock, 0, st>>>(m.nc, (const pc_t*)Binv, (const float*)r,
+                                                                    (float*)X)));
+    HDG_DISPATCH(k, (k_pc_pass2<KK, float><<<nb2, PcWood<KK>::G * 32, 0, st>>>(m, (const pc_t*)Binv, (const float*)X,
+                                                                                (float*)z)));
   } else {
-    HDG_DISPATCH(k, (k_pc_apply<KK, double><<<nblocks((long)(m.nc + 31) / 32 * 32 * PcApplyShape<KK>::G), kBlock, 0,
-                                              st>>>(m, (const pc_t*)Binv, (const double*)r, (double*)z)));
+    HDG_DISPATCH(k, (k_pc_pass1<KK, double><<<nb1, kBlock, 0, st>>>(m.nc, (const pc_t*)Binv, (const double*)r,
+                                                                     (double*)X)));
+    HDG_DISPATCH(k, (k_pc_pass2<KK, double><<<nb2, PcWood<KK>::G * 32, 0, st>>>(m, (const pc_t*)Binv,
+                                                                                 (const double*)X, (double*)z)));
   }
 }
-// per (cell, facet) slot: NU rows of 2 NU entries (own cell, then neighbour)
+long pc_scratch(int k, long nc) {
+  HDG_DISPATCH(k, return nc * PcWood<KK>::R1);
+  return 0;
+}
 long pc_entries(int k, long nc) {
-  const long nu = (long)(k + 2) * (k + 3);
-  return (nc + 31) / 32 * 32 * 3 * nu * 2 * nu;
+  const long nc32 = (nc + 31) / 32 * 32;
+  HDG_DISPATCH(k, return PcWood<KK>::entries(nc32));
+  return 0;
 }
 }  // namespace hdg

@@ -65,9 +65,11 @@ def test_kernel_source_extraction():
 
 def test_preconditioner_bytes():
     import bench
-    # 256 x 256, k = 3: 196096 interior facets, each a 60 x 60 FP16 inverse
+    # 256 x 256, k = 3: per cell the 60 x 30 first-pass rows and the 30 x 30
+    # H in FP16, two FP64 vectors, 60 FP64 first-pass results written and
+    # read; per interior facet (196096) a 20 x 20 FP16 correction and two scales
     nbytes, _ = bench.algorithmic_cost("step1_precond_apply", 3, 131072, 197120, 196096)
-    assert nbytes == 196096 * 2 * 30 * 60 * 2 + 131072 * (2 * 8 * 30 + 12)
+    assert nbytes == 131072 * (60 * 30 * 2 + 30 * 30 * 2 + 2 * 8 * 30 + 2 * 8 * 60 + 12) + 196096 * (20 * 20 * 2 + 8)
     # the operator on the method's own data: 4 vectors of 30 doubles (input,
     # output, inner-product vector, Q*), 7 geometry doubles, 9 int32 entries
     assert bench.method_bytes("apply_step1_operator", 3, 131072) == 131072 * (8 * (120 + 7) + 36)

@@ -18,21 +18,88 @@ def _advecting_velocity(d, seed=1):
     return d.bdm_project(d.l2_project_velocity(lambda x, y: hi.streamfunction_velocity(par, x, y)))
 
 
-def _facet_schwarz(d, Ahat, r, fp16=False):
+def _facet_schwarz(d, Ahat, r):
     """sum_F R_F^T A_F^{-1} R_F r over interior facets F, A_F the block of the
-    mass-scaled operator on the two cells of F; fp16: with every entry of
-    A_F^{-1} rounded to FP16 (saturating), the library's storage."""
+    mass-scaled operator on the two cells of F."""
     nu = d.nu
     fc = d.mesh.facet_cells
     z = np.zeros_like(r)
     A = Ahat.tocsr()
     for F in np.nonzero(fc[:, 2] >= 0)[0]:
         idx = np.concatenate([fc[F, 0] * nu + np.arange(nu), fc[F, 2] * nu + np.arange(nu)])
-        inv = np.linalg.inv(A[idx][:, idx].toarray())
-        if fp16:
-            inv = np.clip(inv, -65504.0, 65504.0).astype(np.float16).astype(np.float64)
-        z[idx] += inv @ r[idx]
+        z[idx] += np.linalg.solve(A[idx][:, idx].toarray(), r[idx])
     return z
+
+
+def _round16(x):
+    return np.clip(x, -65504.0, 65504.0).astype(np.float16).astype(np.float64)
+
+
+def _facet_schwarz_woodbury_fp16(d, Ahat, r):
+    """The same sum in the library's storage.  The patch block is written as
+    diag(A_+, A_-) + U^T Kf U (U: each cell's Legendre trace coefficients on
+    F in its own facet parameter, found here by least squares from the
+    oracle's basis values at its facet points; Kf recovered from the assembled
+    coupling blocks), so A_F^{-1} = Bd^{-1} - Bd^{-1} U^T M_F U Bd^{-1} with
+    M_F = (I + Kf U Bd^{-1} U^T)^{-1} Kf.  Stored in FP16: A_e^{-1},
+    G_f = R_f L_f A_e^{-1}, H_f = A_e^{-1} L_f^T R_f^T (R_f: rotation of the
+    trace components into the facet's normal/tangent frame), and each cell's
+    rows of M_F rotated into the frames of both sides, divided by a power of
+    two (largest entry below 2^14)."""
+    from numpy.polynomial.legendre import leggauss, legval
+    nu, ns, nc, k = d.nu, d.nsu, d.mesh.ncells, d.k
+    nm = k + 2
+    m2 = 2 * nm
+    fc = d.mesh.facet_cells
+    A = Ahat.tocsr()
+    blocks = np.array([A[e * nu:(e + 1) * nu, e * nu:(e + 1) * nu].toarray() for e in range(nc)])
+    binv = np.linalg.inv(blocks)
+    nq = d.cf_x.shape[2]
+    g, _ = leggauss(nq)
+    psi = np.stack([np.sqrt(2 * j + 1) * legval(g, np.eye(nm)[j]) for j in range(nm)], axis=1)
+
+    def lmap(e, f):
+        L = np.linalg.lstsq(psi, d.cf_Bu[e, f], rcond=None)[0]
+        out = np.zeros((m2, nu))
+        out[:nm, :ns] = L
+        out[nm:, ns:] = L
+        return out
+
+    def frame(e, f):
+        nx, ny = d.n[e, f]
+        return np.kron(np.array([[nx, ny], [-ny, nx]]), np.eye(nm))
+
+    L = np.array([[lmap(e, f) for f in range(3)] for e in range(nc)])
+    R = np.array([[frame(e, f) for f in range(3)] for e in range(nc)])
+    Gs = np.einsum("efab,efbi,eij->efaj", R, L, binv)
+    Hs = np.einsum("eij,efbj,efab->efia", binv, L, R)
+    slot = {}
+    for F in np.nonzero(fc[:, 2] >= 0)[0]:
+        kp, fp_, km, fm = fc[F]
+        ip, im = kp * nu + np.arange(nu), km * nu + np.arange(nu)
+        Lp, Lm = L[kp, fp_], L[km, fm]
+        Kf = np.zeros((2 * m2, 2 * m2))
+        Kf[:m2, m2:] = np.linalg.pinv(Lp.T) @ A[ip][:, im].toarray() @ np.linalg.pinv(Lm)
+        Kf[m2:, :m2] = np.linalg.pinv(Lm.T) @ A[im][:, ip].toarray() @ np.linalg.pinv(Lp)
+        S = np.zeros((2 * m2, 2 * m2))
+        S[:m2, :m2] = Lp @ binv[kp] @ Lp.T
+        S[m2:, m2:] = Lm @ binv[km] @ Lm.T
+        MF = np.linalg.solve(np.eye(2 * m2) + Kf @ S, Kf)
+        sides = ((kp, fp_, km, fm, slice(0, m2)), (km, fm, kp, fp_, slice(m2, 2 * m2)))
+        for a, (e, f, en, fn) in enumerate(s_[:4] for s_ in sides):
+            rows = sides[a][4]
+            own, nb = (slice(0, m2), slice(m2, 2 * m2)) if a == 0 else (slice(m2, 2 * m2), slice(0, m2))
+            W = np.concatenate([R[e, f] @ MF[rows, own] @ R[e, f].T, R[e, f] @ MF[rows, nb] @ R[en, fn].T], axis=1)
+            sc = 2.0 ** (np.floor(np.log2(np.abs(W).max())) - 13)
+            slot[(e, f)] = (_round16(W / sc) * sc, en, fn)
+    b16, g16, h16 = _round16(binv), _round16(Gs), _round16(Hs)
+    rc = r.reshape(nc, nu)
+    s = np.einsum("eij,ej->ei", b16, rc)
+    tau = np.einsum("efmi,ei->efm", g16, rc)
+    z = np.zeros((nc, nu))
+    for (e, f), (W, en, fn) in slot.items():
+        z[e] += s[e] - h16[e, f] @ (W @ np.concatenate([tau[e, f], tau[en, fn]]))
+    return z.ravel()
 
 
 @pytest.mark.parametrize("n,k,pert,periodic", [(3, 1, 0.1, False), (4, 2, 0.15, False), (3, 3, 0.1, False),
@@ -53,17 +120,17 @@ def test_patch_preconditioner_matches_dense(n, k, pert, periodic):
     adt = 0.02
     Ahat = sp.diags(1.0 / d.mass().diagonal()) @ (d.mass() - adt * d.advection(Qs))
     r = np.random.default_rng(5).standard_normal(d.nQ)
-    ref = _facet_schwarz(d, Ahat, r, fp16=True)
+    ref = _facet_schwarz_woodbury_fp16(d, Ahat, r)
     exact = _facet_schwarz(d, Ahat, r)
     ctx = context(X, C, vertex_rep=rep, degree=k)
     got = host(ctx.step1_precond(adt, dev(torch, Qs), dev(torch, r)))
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     err_exact = np.linalg.norm(got - exact) / np.linalg.norm(exact)
-    print(f"n={n} k={k} periodic={periodic}: relative difference {err:.2e} from the FP16-rounded patch inverses, "
-          f"{err_exact:.2e} from the exact ones")
-    # the inverses are formed in FP64 (elimination without pivoting, against
-    # NumPy's pivoted LU), so an entry lying on an FP16 rounding boundary may
-    # round the other way: a few FP16 ulps at most
+    print(f"n={n} k={k} periodic={periodic}: relative difference {err:.2e} from the same construction with "
+          f"FP16 storage, {err_exact:.2e} from the exact patch inverses")
+    # the library forms its inverses in FP64 (elimination without pivoting,
+    # against NumPy's pivoted LU), so an entry lying on an FP16 rounding
+    # boundary may round the other way, and it applies them in FP32
     assert err < 1e-5, err
     assert err_exact < 2e-3, err_exact
     ctx.close()
