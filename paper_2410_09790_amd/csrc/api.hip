@@ -736,7 +736,6 @@ void hdg_ctx::vcycle(TraceOp& op, int l) {
     return;
   }
   DevLevel& L = op.levels[l];
-  Timed tm(prof, KC_AMG);
   launch_csr_jacobi(st, L.A, L.dinv, L.omega, L.b, nullptr, L.x);
   launch_csr_jacobi(st, L.A, L.dinv, L.omega, L.b, L.x, L.x2);
   launch_csr_spmv(st, L.A, L.x2, L.r, 0.0);
@@ -765,9 +764,12 @@ void hdg_ctx::mg_apply(TraceOp& op, const double* r, double* z) {
   }
   double* b0 = op.levels.empty() ? op.cb : op.levels[0].b;
   double* x0 = op.levels.empty() ? op.cx : op.levels[0].x;
-  launch_csr_spmv(st, op.Rt, t3, b0, 0.0);
-  vcycle(op, 0);
-  launch_csr_spmv(st, op.Pt, x0, t2, 1.0);
+  {
+    Timed tm(prof, KC_AMG);  // the whole coarse correction, transfers included
+    launch_csr_spmv(st, op.Rt, t3, b0, 0.0);
+    vcycle(op, 0);
+    launch_csr_spmv(st, op.Pt, x0, t2, 1.0);
+  }
   Timed tm(prof, KC_SMOOTH);
   launch_jacobi_sweep(tk, st, nF, op.vals, op.cols, op.Dinv, om, r, t2, t1);
   launch_jacobi_sweep(tk, st, nF, op.vals, op.cols, op.Dinv, om, r, t1, z);
