@@ -65,8 +65,8 @@ MEASURED_TRAFFIC = {
     # tetrahedra, 32^3 Kuhn cubes, k = 2
     "trace_spmv_tet": {"src": "kernels.hip", "funcs": ["TetRowsShape", "tet_gather", "k_spmv_tet"],
                        "sha256": "4233bb038e2c001c", "bytes_per_launch": 915.8e6},
-    "apply_step1_operator_tet": {"src": "kernels3.hip", "funcs": ["wave_sum", "k3_apply"],
-                                 "sha256": "2327c77aa6613203", "bytes_per_launch": 1470.8e6},
+    "apply_step1_operator_tet": {"src": "kernels3.hip", "funcs": ["wave_sum", "Apply3Shape", "k3_apply"],
+                                 "sha256": "2f38edc18632650d", "bytes_per_launch": 1306.9e6},
     "step1_precond_apply_tet": {"src": "kernels3.hip", "funcs": ["PcLayout3", "PcApplyShape3", "k3_pc_apply"],
                                 "sha256": "05c242fd8b89e85b", "bytes_per_launch": 12485.2e6},
 }

@@ -539,11 +539,22 @@ __global__ void __launch_bounds__(kW3) k3_prep(DMesh m, DTab3 t, const double* _
 // DOT (MODE 0): partial inner products per block as the structure-of-arrays
 // operator leaves them (dot 1: w.out; dot 2: out.x, out.out, w.x, w.out;
 // dot 3: out.sd, out.out, w.sd, w.out), nparts blocks per set.  Blocks of
-// 4 waves walk the cells with a stride of the grid.  TX: the type of V,
+// WPB waves walk the cells with a stride of the grid.  TX: the type of V,
 // beta, the vectors and the arithmetic (float in the mixed-precision mode,
 // MODE 0 only); the inner products accumulate in FP64 either way.
+// The facet-point tables of the 24 (local facet, orientation) point sets are
+// copied into LDS once per workgroup: every cell reads about 200 of their
+// rows, and from the 96 KB tables in L2 those reads bound the kernel (1.74 ms
+// per launch at 32^3, k = 2, against 0.22 ms for its HBM bytes).  The table
+// rows are padded by one entry against LDS bank conflicts; the table takes
+// 100.8 KB at k = 2, which leaves room for the per-cell buffers of 12 waves.
+template <int K>
+struct Apply3Shape {
+  static constexpr int WPB = 12;               // waves (cells in flight) per workgroup
+  static constexpr int TS = Dims3<K>::NS + 1;  // padded table row
+};
 template <int K, int MODE, int DOT, typename TX = double>
-__global__ void __launch_bounds__(256) k3_apply(DMesh m, DTab3 t, const TX* __restrict__ V,
+__global__ void __launch_bounds__(Apply3Shape<K>::WPB * 64) k3_apply(DMesh m, DTab3 t, const TX* __restrict__ V,
                                                 const TX* __restrict__ beta, double alpha, double adt,
                                                 const TX* __restrict__ x, const double* __restrict__ r,
                                                 const double* __restrict__ pv, const double* __restrict__ lam,
@@ -551,16 +562,20 @@ __global__ void __launch_bounds__(256) k3_apply(DMesh m, DTab3 t, const TX* __re
                                                 const TX* __restrict__ sd, double* __restrict__ part) {
   using D = Dims3<K>;
   constexpr int NS = D::NS, NP = D::NP, NF = D::NF, NU = D::NU, NQF = D::NQF;
+  constexpr int WPB = Apply3Shape<K>::WPB, TS = Apply3Shape<K>::TS;
+  static_assert(NU <= 64, "one lane per cell unknown");
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const long nc = m.nc;
   static_assert(MODE == 0 || sizeof(TX) == sizeof(double), "the residual modes are FP64");
-  __shared__ TX xs[4][5][NU];
-  __shared__ TX phi[4][4][NQF][3];
-  __shared__ double red[4][4];
+  __shared__ double tab[24][NQF][TS];
+  __shared__ TX xs[WPB][5][NU];
+  __shared__ TX phi[WPB][4][NQF][3];
+  __shared__ double red[WPB][4];
+  for (int i = threadIdx.x; i < 24 * NQF * NS; i += WPB * 64) tab[i / (NQF * NS)][(i / NS) % NQF][i % NS] = t.FBu[i];
   double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
-  const long stride = (long)gridDim.x * 4;
+  const long stride = (long)gridDim.x * WPB;
   // every wave of a block runs the same number of rounds (the barriers)
-  for (long base = (long)blockIdx.x * 4; base < nc; base += stride) {
+  for (long base = (long)blockIdx.x * WPB; base < nc; base += stride) {
     // the cell index is the same on every lane of the wave: keep it (and all
     // per-cell scalars loaded with it) in scalar registers
     const long e = (long)__builtin_amdgcn_readfirstlane((int)(base + wv));
@@ -576,11 +591,16 @@ __global__ void __launch_bounds__(256) k3_apply(DMesh m, DTab3 t, const TX* __re
       const int fn = m.cf_nbf[f * nc + ec];
       fpn[f] = nb[f] >= 0 ? 6 * fn + m.cf_flip[fn * nc + nb[f]] : 0;
     }
-    for (int i = lane; i < NU; i += 64) X[0][i] = x[ec * NU + i];
+    {  // the cell's and its neighbours' unknowns, all five loads in flight together
+      TX xv[5];
+      xv[0] = lane < NU ? x[ec * NU + lane] : (TX)0;
 #pragma unroll
-    for (int f = 0; f < 4; ++f)
-      if (nb[f] >= 0)
-        for (int i = lane; i < NU; i += 64) X[1 + f][i] = x[(long)nb[f] * NU + i];
+      for (int f = 0; f < 4; ++f) xv[1 + f] = (lane < NU && nb[f] >= 0) ? x[(long)nb[f] * NU + lane] : (TX)0;
+      if (lane < NU) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) X[v][lane] = xv[v];
+      }
+    }
     double nrm[4][3];
 #pragma unroll
     for (int f = 0; f < 4; ++f)
@@ -592,19 +612,18 @@ __global__ void __launch_bounds__(256) k3_apply(DMesh m, DTab3 t, const TX* __re
       TX du[3];
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc) du[cc] = (TX)0;
-      // points fastest: the lanes of one facet read consecutive table entries
-      const double* b0 = t.FBuT + (long)fps[f] * NS * NQF + iq;
+      const double* b0 = tab[fps[f]][iq];
 #pragma unroll 4
       for (int s = 0; s < NS; ++s) {
 #pragma unroll
-        for (int cc = 0; cc < 3; ++cc) du[cc] += (TX)b0[s * NQF] * X[0][cc * NS + s];
+        for (int cc = 0; cc < 3; ++cc) du[cc] += (TX)b0[s] * X[0][cc * NS + s];
       }
       if (nb[f] >= 0) {
-        const double* b1 = t.FBuT + (long)fpn[f] * NS * NQF + iq;
+        const double* b1 = tab[fpn[f]][iq];
 #pragma unroll 4
         for (int s = 0; s < NS; ++s) {
 #pragma unroll
-          for (int cc = 0; cc < 3; ++cc) du[cc] -= (TX)b1[s * NQF] * X[1 + f][cc * NS + s];
+          for (int cc = 0; cc < 3; ++cc) du[cc] -= (TX)b1[s] * X[1 + f][cc * NS + s];
         }
       }
       const TX bq = beta[(ec * 4 + f) * NQF + iq];
@@ -623,9 +642,8 @@ __global__ void __launch_bounds__(256) k3_apply(DMesh m, DTab3 t, const TX* __re
       for (int j = 0; j < NS; ++j) F += vr[j * NS] * X[0][cc * NS + j];
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
-        const double* b0 = t.FBu + (long)fps[f] * NQF * NS + s;
 #pragma unroll 5
-        for (int iq = 0; iq < NQF; ++iq) F += (TX)b0[iq * NS] * PH[f][iq][cc];
+        for (int iq = 0; iq < NQF; ++iq) F += (TX)tab[fps[f]][iq][s] * PH[f][iq][cc];
       }
       const long gi = e * NU + i;
       TX o;
@@ -675,7 +693,7 @@ __global__ void __launch_bounds__(256) k3_apply(DMesh m, DTab3 t, const TX* __re
       const int nb = gridDim.x, blk = blockIdx.x;
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) { s0 += red[i][0]; s1 += red[i][1]; s2 += red[i][2]; s3 += red[i][3]; }
+      for (int i = 0; i < WPB; ++i) { s0 += red[i][0]; s1 += red[i][1]; s2 += red[i][2]; s3 += red[i][3]; }
       part[blk] = s0;
       if constexpr (DOT >= 2) { part[nb + blk] = s1; part[2 * nb + blk] = s2; part[3 * nb + blk] = s3; }
     }
@@ -1244,13 +1262,15 @@ void launch3_apply(int k, hipStream_t st, int mode, int dot, DMesh m, DTab3 t, c
   using F = const float*;
   if (x32) {
     if (mode != 0) throw std::invalid_argument("launch3_apply: the residual modes are FP64");
-#define K3F(DT) HDG3_DISPATCH(k, (k3_apply<KK, 0, DT, float><<<nb, 256, 0, st>>>(m, t, (F)V, (F)beta, alpha, adt, \
+#define K3F(DT) HDG3_DISPATCH(k, (k3_apply<KK, 0, DT, float><<<nb, Apply3Shape<KK>::WPB * 64, 0, st>>>(m, t, (F)V, \
+                                  (F)beta, alpha, adt, \
                                   (F)x, r, p, lam, (float*)out, (F)w, (F)sd, part)))
     switch (dot) { case 0: K3F(0); break; case 1: K3F(1); break; case 2: K3F(2); break; default: K3F(3); break; }
 #undef K3F
     return;
   }
-#define K3D(MD, DT) HDG3_DISPATCH(k, (k3_apply<KK, MD, DT, double><<<nb, 256, 0, st>>>(m, t, (D)V, (D)beta, alpha, \
+#define K3D(MD, DT) HDG3_DISPATCH(k, (k3_apply<KK, MD, DT, double><<<nb, Apply3Shape<KK>::WPB * 64, 0, st>>>(m, t, \
+                                      (D)V, (D)beta, alpha, \
                                       adt, (D)x, r, p, lam, (double*)out, (D)w, (D)sd, part)))
   if (mode == 0) {
     switch (dot) { case 0: K3D(0, 0); break; case 1: K3D(0, 1); break; case 2: K3D(0, 2); break; default: K3D(0, 3); break; }
