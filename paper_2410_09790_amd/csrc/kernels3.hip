@@ -1129,15 +1129,18 @@ __global__ void __launch_bounds__(PcPatchShape3<K>::NT) k3_pc_patch(DMesh m, DTa
       rp[j] = v;
     }
     __syncthreads();
+    // branch-free update (per-row conditions compiled to branches put one
+    // LDS round trip behind each row): the pivot column's rows in registers
+    // first, then one select per row
+    double cpv[HN];
+#pragma unroll
+    for (int r = 0; r < HN; ++r) cpv[r] = cp[h * HN + r];
     const double d = 1.0 / cp[p];
-    if (j == p) {
+    const bool piv = j == p;
+    const double a = piv ? d : rp[j] * d;
+    const int sel = h == hp ? lp : -1;  // this thread's row that is the pivot row, if any
 #pragma unroll
-      for (int r = 0; r < HN; ++r) col[r] = (h == hp && r == lp) ? d : -cp[h * HN + r] * d;
-    } else {
-      const double a = rp[j] * d;
-#pragma unroll
-      for (int r = 0; r < HN; ++r) col[r] = (h == hp && r == lp) ? a : col[r] - cp[h * HN + r] * a;
-    }
+    for (int r = 0; r < HN; ++r) col[r] = r == sel ? a : (piv ? 0.0 : col[r]) - cpv[r] * a;
   }
   if (j >= N) return;
   // rows h HN .. h HN + HN - 1 (all of one side), column j: for K+ the

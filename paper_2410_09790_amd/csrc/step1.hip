@@ -672,15 +672,15 @@ __global__ void __launch_bounds__(64) k_pc_cellinv(DMesh m, DTab t, double* __re
     for (int r = 0; r < NU; ++r) v = r == p ? col[r] : v;
     rp[j] = v;
     __syncthreads();
+    // branch-free update: the pivot column in registers, one select per row
+    double cpv[NU];
+#pragma unroll
+    for (int r = 0; r < NU; ++r) cpv[r] = cp[r];
     const double d = 1.0 / cp[p];
-    if (j == p) {
+    const bool piv = j == p;
+    const double a = piv ? d : rp[j] * d;
 #pragma unroll
-      for (int r = 0; r < NU; ++r) col[r] = r == p ? d : -cp[r] * d;
-    } else {
-      const double a = rp[j] * d;
-#pragma unroll
-      for (int r = 0; r < NU; ++r) col[r] = r == p ? a : col[r] - cp[r] * a;
-    }
+    for (int r = 0; r < NU; ++r) col[r] = r == p ? a : (piv ? 0.0 : col[r]) - cpv[r] * a;
   }
   if (j < NU) {
 #pragma unroll
