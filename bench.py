@@ -55,9 +55,9 @@ CSRC = os.path.join(ROOT, "paper_2410_09790_amd", "csrc")
 # (the kernel and the device functions it calls), so an edit elsewhere in the
 # file leaves a record valid and an edit of the kernel voids it
 MEASURED_TRAFFIC = {
-    "apply_step1_operator": {"src": "step1.hip", "funcs": ["pair_swap", "tile_idx", "VPairs", "step1_core",
-                                                           "xcd_block", "stage_fbu", "k_apply_soa"],
-                             "sha256": "7ee582c4c3bd27ad", "bytes_per_launch": 403.9e6},
+    "apply_step1_operator": {"src": "step1.hip", "funcs": ["pair_swap", "tile_idx", "step1_core", "xcd_block",
+                                                           "stage_fbu", "k_apply_soa"],
+                             "sha256": "7c4357a97939b50c", "bytes_per_launch": 244.8e6},
     "step1_precond_apply": {"src": "step1.hip", "funcs": ["PcWood", "k_pc_pass1", "k_pc_pass2"],
                             "sha256": "2f89933d19e0075e", "bytes_per_launch": 1085.9e6},
     "trace_spmv": {"src": "kernels.hip", "funcs": ["k_spmv"], "sha256": "96d7545c27858460", "bytes_per_launch": 159.1e6},
@@ -85,11 +85,13 @@ def algorithmic_cost(kernel: str, k: int, nc: int, nF: int, nF_int: int | None =
     apply_step1_operator (mass-scaled Step I operator on structure-of-arrays
     vectors; the event class covers its two BiCGStab launches, v = A p with
     rh.v and t = A s with four inner products, which move the same data): per
-    cell the ns x ns volume matrix, 3 nq_facet upwind weights, det J and the
-    three normals (7 doubles), 9 int32 connectivity entries, and 3 velocity
-    vectors of 2 ns doubles (input, rh, output).  Flops: per cell and
-    component ns^2 FMA for the volume matrix, and per facet point 3 ns FMA
-    (own trace, neighbour trace, projection) plus ~10 for the jump and flux.
+    cell the advecting field at the nq_cell cell points (2 doubles each),
+    3 nq_facet upwind weights, det J and the three normals (7 doubles),
+    9 int32 connectivity entries, and 3 velocity vectors of 2 ns doubles
+    (input, rh, output).  Flops: per cell and component, per cell point
+    3 ns + 2 FMA (the reference gradient, its product with the field, the
+    test sum), and per facet point 3 ns FMA (own trace, neighbour trace,
+    projection) plus ~10 for the jump and flux.
     trace_spmv (facet-block ELL, FP64): per facet row 5 blocks of (k+1)^2
     values, 5 int32 column ids, reads x and writes y ((k+1) doubles each).
     step1_precond_apply (facet-patch Schwarz of the Step I operator in
@@ -108,8 +110,9 @@ def algorithmic_cost(kernel: str, k: int, nc: int, nF: int, nF_int: int | None =
     nf = k + 1
     nu = 2 * ns
     if kernel == "apply_step1_operator":
-        nbytes = nc * (8 * (ns * ns + 3 * nqf + 7 + 3 * 2 * ns) + 4 * 9)
-        flops = nc * 2 * (2 * ns * ns + 3 * nqf * (6 * ns + 10) + 2 * ns)
+        nqc = ((3 * k + 4) // 2) ** 2
+        nbytes = nc * (8 * (2 * nqc + 3 * nqf + 7 + 3 * 2 * ns) + 4 * 9)
+        flops = nc * 2 * (nqc * (6 * ns + 4) + 3 * nqf * (6 * ns + 10) + 2 * ns)
         return nbytes, flops
     if kernel == "step1_precond_apply":
         ni = nF if nF_int is None else nF_int
@@ -160,8 +163,9 @@ def method_bytes(kernel: str, k: int, nc: int):
     """Bytes per launch of the Step I operator if it read only what the method
     itself defines per cell: the input, output and inner-product vectors
     (3 x 2 ns doubles), Q* (2 ns doubles), det J and the three normals
-    (7 doubles) and 9 int32 connectivity entries; the per-stage cell matrices
-    and upwind weights the kernel streams are a design choice on top."""
+    (7 doubles) and 9 int32 connectivity entries; the per-stage field at the
+    cell points and upwind weights the kernel streams are a design choice on
+    top."""
     if kernel != "apply_step1_operator":
         return None
     ns = (k + 2) * (k + 3) // 2
@@ -214,7 +218,11 @@ def measured_traffic(kernel: str):
     rec = MEASURED_TRAFFIC.get(kernel)
     if rec is None:
         return None
-    return rec["bytes_per_launch"] if kernel_sha(rec) == rec["sha256"] else None
+    try:
+        sha = kernel_sha(rec)
+    except KeyError:  # a listed function no longer exists: the record is void
+        return None
+    return rec["bytes_per_launch"] if sha == rec["sha256"] else None
 
 
 def cpu_baseline():

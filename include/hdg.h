@@ -83,8 +83,9 @@ typedef enum {
 typedef enum { HDG_TRACE_JACOBI_PCG = 0, HDG_TRACE_MG_PCG = 1 } hdg_trace_solver;
 typedef enum { HDG_PRESSURE_RECONSTRUCT = 0, HDG_PRESSURE_FIRST_ORDER = 1 } hdg_pressure_update;
 /* HDG_MIXED: the tentative-velocity solve (Algorithm 2, Step I) runs in
- * FP32: Krylov vectors, the per-stage cell matrices and upwind weights, and
- * the operator's arithmetic; its inner products accumulate in FP64, and it
+ * FP32: Krylov vectors, the per-stage volume data (the advecting field at the
+ * cell points on triangles, the cell matrices on tetrahedra) and upwind
+ * weights, and the operator's arithmetic; its inner products accumulate in FP64, and it
  * stops at max(rtol_velocity, 1e-6) (FP32 cannot go tighter).  Everything
  * else stays FP64: the Richardson residual of Algorithm 2 (eq. (f_impl) in
  * FP64), which refines each stage, the trace solves, the final projection

@@ -365,12 +365,13 @@ struct hdg_ctx {
          *v = nullptr;
     void *ph = nullptr, *sh = nullptr;  // preconditioned directions (right preconditioning)
   };
-  bool kx32 = false;  // FP32 Step I: vectors, upwind weights, cell matrices and arithmetic
+  bool kx32 = false;  // FP32 Step I: vectors, volume data, upwind weights and arithmetic
   static constexpr double kMixedRtolFloor = 1e-6;
   KrylovBuf kd;
-  // per-stage Step I data of the current Q*: cell volume matrices (FP32 in
-  // the mixed-precision mode) and facet upwind weights (tiles of 32 cells)
-  // for the structure-of-arrays operator, and the advection data of the
+  // per-stage Step I data of the current Q*: the volume data (triangles: the
+  // advecting field at the cell points; tetrahedra: the cell volume
+  // matrices; FP32 in the mixed-precision mode) and facet upwind weights
+  // (tiles of 32 cells) for the Step I operator, and the advection data of the
   // cell-major residual kernels (FP64 in both modes: the Richardson residual
   // is the accuracy reference)
   void* vk = nullptr;
@@ -592,7 +593,9 @@ void hdg_ctx::setup_work() {
   }
   const long nc32 = (nc + 31) / 32 * 32;
   vk32 = prm.precision == HDG_MIXED;
-  vk = vk32 ? (void*)dalloc<float>((long)ns * ns * nc32) : (void*)dalloc<double>((long)ns * ns * nc32);
+  // Step I volume data: tetrahedra, the cell matrices (ns x ns); triangles, the field at the cell points
+  const long nvk = dim == 3 ? (long)ns * ns : 2L * nqc;
+  vk = vk32 ? (void*)dalloc<float>(nvk * nc32) : (void*)dalloc<double>(nvk * nc32);
   vbeta = kx32 ? (void*)dalloc<float>((long)nfc * nqf * nc32) : (void*)dalloc<double>((long)nfc * nqf * nc32);
   br = dalloc<double>(nQ); bt = dalloc<double>(nQ);
   // residual-kernel advection data (tetrahedra: the cell volume matrices and the facet weights)
@@ -1014,9 +1017,8 @@ void hdg_ctx::solve_trace(double c, const double* Fw, const double* Fpsi, const 
 }
 
 // BiCGStab on the mass-scaled Step I operator  x - (adt/det) f_im(x) = b,
-// with FP64 arithmetic (FP32 operator arithmetic makes BiCGStab stall or
-// diverge on this advection-dominated operator; the mixed mode only stores
-// the cell matrices in FP32).  An iteration is four launches: v = A p
+// in the vectors' type (FP64; in the mixed-precision mode FP32, stopped no
+// tighter than kMixedRtolFloor and refined by the FP64 Richardson residual).  An iteration is four launches: v = A p
 // (with partials of rh.v), s = r - alpha v (alpha finished there), t = A s
 // (with partials of t.s, t.t, rh.s, rh.t), and the x, r, p updates (omega
 // and beta finished there, partials of r.r).  Coefficients stay in device
@@ -1658,8 +1660,8 @@ static void estimate_footprint(const hdg::HostMesh& m, const hdg::RefTables& rt,
   if (x32) b -= 4.0 * 8 * nQ;
   b += 8.0 * ((double)kRedBlocks * kIdrMax + 2.0 * kRedBlocks + 3.0 * (prm.max_it_trace + 4) + 16 +
               (double)BS_STRIDE * std::max(prm.max_it_velocity + 6, 10) + 2 * (4 * blocks + 16));
-  // Step I data: cell matrices, upwind weights, residual-kernel advection data
-  b += ns * ns * nc32 * (x32 ? 4.0 : 8.0) + (x32 ? 4.0 : 8.0) * 3 * nqf * nc32 + 8.0 * nc * (2 * nqc + 3 * nqf);
+  // Step I data: the field at the cell points, upwind weights, residual-kernel advection data
+  b += 2 * nqc * nc32 * (x32 ? 4.0 : 8.0) + (x32 ? 4.0 : 8.0) * 3 * nqf * nc32 + 8.0 * nc * (2 * nqc + 3 * nqf);
   if (prm.idr_s > 0) b += 8.0 * (3.0 * prm.idr_s * nQ + kIdrMax + 8);
   // Step I preconditioner: two direction vectors, the cell blocks and the patch inverses
   if (prm.step1_precond == 1 && prm.idr_s == 0)

@@ -30,45 +30,29 @@ __device__ __forceinline__ float pair_swap(float v) {
 // streams small.  Arrays hold ceil(nc/32)*32 cells.
 __device__ __forceinline__ long tile_idx(long e, int j, int nj) { return ((e >> 5) * nj + j) * 32 + (e & 31); }
 
-// The cell matrices are stored as pairs of adjacent row entries, so that one
-// load per lane brings two of them (16 bytes in FP64, 8 in FP32): row s of
-// cell e holds NP2 = floor(NS/2) pairs, pair pi of row s at
-// pair(e, s, pi) in units of pairs, in tiles of 32 cells; when NS is odd the
-// last entry of every row follows all pairs, at tail(nc) + tile_idx(e, s, NS)
-// in units of entries.  The array holds ceil(nc/32)*32*NS*NS entries either way.
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
-template <typename TV> struct Pair2;
-template <> struct Pair2<float> { using T = f32x2; };
-template <> struct Pair2<double> { using T = f64x2; };
-template <int K>
-struct VPairs {
-  static constexpr int NS = Dims<K>::NS;
-  static constexpr int NP2 = NS / 2;
-  __device__ static long pair(long e, int s, int pi) { return ((e >> 5) * (long)(NS * NP2) + s * NP2 + pi) * 32 + (e & 31); }
-  __device__ static long tail(long nc) { return ((nc + 31) >> 5) * 32 * (long)NS * (2 * NP2); }
-};
 
-// Per-cell volume matrix of the Step I form, for the Q* of a stage:
-//   V[s][s'] = -sum_q w_q phi_s(q) (Q*(q) . grad phi_s'(q)) det J
-// (the volume term -(Q*.grad x, w) of eq. (f_impl) acts on each velocity
-// component alike), entry s*NS + s' in tiles.  TV is the storage type: FP64,
-// or FP32 in the mixed-precision mode (the operator still computes in FP64).
-// One thread per (cell, row s).
+// Per-cell advecting field of the Step I volume term at the cell points,
+// for the Q* of a stage.  The volume term -(Q*.grad x, w) of eq. (f_impl)
+// is, on every velocity component alike,
+//   -sum_q w_q phi_s(q) (Q*(q) . grad phi_s'(q)) det J
+//     = sum_q phi_s(q) (A_q . grad_ref phi_s'(q)),  A_q = -w_q det J^{-1} Q*(q)
+// (grad = J^{-T} grad_ref), so the operator evaluates it at the NQC cell
+// points from A_q (2 numbers per point) instead of streaming an NS x NS
+// matrix per cell.  Entry 2q + d of cell e in tiles of 32 cells; TV is the
+// storage type (FP32 in the mixed-precision mode).  One thread per cell.
 template <int K, typename TV>
-__global__ void __launch_bounds__(kBlock) k_step1_matrix(DMesh m, DTab t, const double* __restrict__ Qs,
-                                                         TV* __restrict__ V) {
+__global__ void __launch_bounds__(kBlock) k_step1_field(DMesh m, DTab t, const double* __restrict__ Qs,
+                                                        TV* __restrict__ A) {
   using D = Dims<K>;
   constexpr int NS = D::NS, NU = D::NU, NQC = D::NQC;
-  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long nc = m.nc;
-  if (tid >= nc * NS) return;
-  const int e = (int)(tid % nc), s = (int)(tid / nc);
-  double q[NU], row[NS];
+  if (e >= nc) return;
+  double q[NU];
 #pragma unroll
-  for (int i = 0; i < NU; ++i) q[i] = Qs[(long)e * NU + i];
-#pragma unroll
-  for (int i = 0; i < NS; ++i) row[i] = 0.0;
+  for (int i = 0; i < NU; ++i) q[i] = Qs[e * NU + i];
   const double det = m.geo[D_DET * nc + e];
   const double i00 = det * m.geo[D_IJ00 * nc + e], i01 = det * m.geo[D_IJ01 * nc + e];
   const double i10 = det * m.geo[D_IJ10 * nc + e], i11 = det * m.geo[D_IJ11 * nc + e];
@@ -79,21 +63,10 @@ __global__ void __launch_bounds__(kBlock) k_step1_matrix(DMesh m, DTab t, const 
       qx += t.Bu[qq * NS + i] * q[i];
       qy += t.Bu[qq * NS + i] * q[NS + i];
     }
-    const double w = -t.cw[qq] * t.Bu[qq * NS + s];
-    const double a0 = w * (i00 * qx + i01 * qy), a1 = w * (i10 * qx + i11 * qy);
-#pragma unroll
-    for (int i = 0; i < NS; ++i) row[i] += a0 * t.Gux[qq * NS + i] + a1 * t.Guy[qq * NS + i];
+    const double w = -t.cw[qq];
+    A[tile_idx(e, 2 * qq, 2 * NQC)] = (TV)(w * (i00 * qx + i01 * qy));
+    A[tile_idx(e, 2 * qq + 1, 2 * NQC)] = (TV)(w * (i10 * qx + i11 * qy));
   }
-  using TV2 = typename Pair2<TV>::T;
-  TV2* V2 = reinterpret_cast<TV2*>(V);
-#pragma unroll
-  for (int pi = 0; pi < VPairs<K>::NP2; ++pi) {
-    TV2 v;
-    v.x = (TV)row[2 * pi];
-    v.y = (TV)row[2 * pi + 1];
-    V2[VPairs<K>::pair(e, s, pi)] = v;
-  }
-  if constexpr (NS & 1) V[VPairs<K>::tail(nc) + tile_idx(e, s, NS)] = (TV)row[NS - 1];
 }
 
 // Upwind weights of the Step I facet term at the facet points, for the Q*
@@ -126,62 +99,44 @@ __global__ void __launch_bounds__(kBlock) k_step1_beta(DMesh m, DTab t, const do
 
 // The Step I form f_im(w, x; Q*) of eq. (f_impl) for one cell e and one
 // velocity component c on structure-of-arrays data x[(c*NS + s)*nc + e]:
-// the volume term through the cell matrix V, and per facet the upwinded
-// advective jump term beta(q) [[x]] (beta = w_q h (Q*.n/2 - delta_up
-// |Q*.n|) at the facet points, precomputed per stage in tiles, entry
-// f*NQF + q, zero on walls) and the normal-jump penalty
-// alpha ([[x]].n)(w.n).  Two threads per cell (lanes 2i, 2i+1, one per
-// component) exchange their components of the jump with pair_swap.  y
-// receives the result in reference scaling (the caller multiplies by
-// adt/det).  The neighbour's input value at structure-of-arrays index idx
-// is nb(idx); sFBu is the facet trace table staged in LDS.  TC is the
-// arithmetic type (FP64, or FP32 in the mixed-precision mode), TV the
-// storage type of the cell matrices.
+// the volume term at the cell points from the per-stage field A_q
+// (k_step1_field), and per facet the upwinded advective jump term
+// beta(q) [[x]] (beta = w_q h (Q*.n/2 - delta_up |Q*.n|) at the facet
+// points, precomputed per stage in tiles, entry f*NQF + q, zero on walls)
+// and the normal-jump penalty alpha ([[x]].n)(w.n).  Two threads per cell
+// (lanes 2i, 2i+1, one per component) exchange their components of the jump
+// with pair_swap.  y receives the result in reference scaling (the caller
+// multiplies by adt/det).  The neighbour's input value at structure-of-arrays
+// index idx is nb(idx); sFBu is the facet trace table staged in LDS.  TC is
+// the arithmetic type (FP64, or FP32 in the mixed-precision mode), TV the
+// storage type of the field.  The reference tables are indexed by loop
+// counters only, the same on every lane: scalar loads.
 template <int K, typename TV, typename TC, typename NbVal>
 __device__ __forceinline__ void step1_core(const DMesh& m, const DTab& t, const TC* sFBu,
-                                           const TV* __restrict__ V, const TC* __restrict__ beta, long nc,
+                                           const TV* __restrict__ A, const TC* __restrict__ beta, long nc,
                                            int e, int c, TC alpha, const TC (&xv)[Dims<K>::NS],
                                            TC (&y)[Dims<K>::NS], const NbVal& nb) {
   using D = Dims<K>;
-  constexpr int NS = D::NS, NQF = D::NQF;
-  // volume: the two lanes of a cell split the rows of V (lane c takes rows
-  // 2r + c) and apply them to both components, so that every lane loads
-  // distinct entries; the partner's results come back through pair_swap.
-  // V and the upwind weights are read once per application: non-temporal
-  // loads keep them from evicting the velocity vectors (read again by the
+  constexpr int NS = D::NS, NQF = D::NQF, NQC = D::NQC;
+  // volume: the reference gradient of x at each cell point, dotted with A_q,
+  // tested against phi_s.  A is read once per application: non-temporal
+  // loads keep it from evicting the velocity vectors (read again by the
   // neighbouring cells) from the caches.
-  {
-    using TV2 = typename Pair2<TV>::T;
-    const long vtail = VPairs<K>::tail(nc);
-    TC xo[NS];
 #pragma unroll
-    for (int i = 0; i < NS; ++i) xo[i] = pair_swap(xv[i]);
+  for (int s = 0; s < NS; ++s) y[s] = 0;
+#pragma unroll 2
+  for (int qq = 0; qq < NQC; ++qq) {
+    const TC a0 = (TC)__builtin_nontemporal_load(&A[tile_idx(e, 2 * qq, 2 * NQC)]);
+    const TC a1 = (TC)__builtin_nontemporal_load(&A[tile_idx(e, 2 * qq + 1, 2 * NQC)]);
+    TC gx = 0, gy = 0;
 #pragma unroll
-    for (int r = 0; r < (NS + 1) / 2; ++r) {
-      const int s = 2 * r + c < NS ? 2 * r + c : NS - 1;
-      TC am = 0, ao = 0;
-      const TV2* V2 = reinterpret_cast<const TV2*>(V);
-#pragma unroll
-      for (int pi = 0; pi < VPairs<K>::NP2; ++pi) {
-        const TV2 v = __builtin_nontemporal_load(&V2[VPairs<K>::pair(e, s, pi)]);
-        am += (TC)v.x * xv[2 * pi];
-        ao += (TC)v.x * xo[2 * pi];
-        am += (TC)v.y * xv[2 * pi + 1];
-        ao += (TC)v.y * xo[2 * pi + 1];
-      }
-      if constexpr (NS & 1) {
-        const TC v = (TC)__builtin_nontemporal_load(&V[vtail + tile_idx(e, s, NS)]);
-        am += v * xv[NS - 1];
-        ao += v * xo[NS - 1];
-      }
-      const TC recv = pair_swap(ao);
-      if (2 * r + 1 < NS) {
-        y[2 * r] = c ? recv : am;
-        y[2 * r + 1] = c ? am : recv;
-      } else {
-        y[2 * r] = c ? recv : am;
-      }
+    for (int s = 0; s < NS; ++s) {
+      gx += (TC)t.Gux[qq * NS + s] * xv[s];
+      gy += (TC)t.Guy[qq * NS + s] * xv[s];
     }
+    const TC tq = a0 * gx + a1 * gy;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) y[s] += (TC)t.Bu[qq * NS + s] * tq;
   }
   int nbx[3];
 #pragma unroll
@@ -261,7 +216,7 @@ __device__ __forceinline__ void stage_fbu(const DTab& t, TC* sFBu) {
 // hardware order.  TX: the vectors' type and the arithmetic type (FP64, or
 // FP32 in the mixed-precision mode); the inner products accumulate in FP64.
 template <int K, int DOT, typename TV, int BS, typename TX>
-__global__ void __launch_bounds__(BS, kStep1Waves) k_apply_soa(DMesh m, DTab t, const TV* __restrict__ V,
+__global__ void __launch_bounds__(BS, kStep1Waves) k_apply_soa(DMesh m, DTab t, const TV* __restrict__ A,
                                                                const TX* __restrict__ beta, double alpha,
                                                                double adt, const TX* __restrict__ x,
                                                                const TX* __restrict__ w,
@@ -281,7 +236,7 @@ __global__ void __launch_bounds__(BS, kStep1Waves) k_apply_soa(DMesh m, DTab t, 
     TX xv[NS], y[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) xv[s] = x[(long)(c * NS + s) * nc + e];
-    step1_core<K, TV, TX>(m, t, sFBu, V, beta, nc, e, c, (TX)alpha, xv, y, [&](long i) { return x[i]; });
+    step1_core<K, TV, TX>(m, t, sFBu, A, beta, nc, e, c, (TX)alpha, xv, y, [&](long i) { return x[i]; });
     const TX sc = (TX)(adt / m.geo[D_DET * nc + e]);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -1002,11 +957,11 @@ void launch_step1_matrix(int k, hipStream_t st, DMesh m, DTab t, const double* Q
     if (v32 != b32) throw std::invalid_argument("launch_step1_matrix: V and beta of one type on tetrahedra");
     return launch3_prep(k, st, m, t.t3, Qs, delta_up, V, beta, v32);
   }
-  const int nb = nblocks((long)m.nc * (k + 2) * (k + 3) / 2);
+  const int nb = nblocks((long)m.nc);
   if (v32) {
-    HDG_DISPATCH(k, (k_step1_matrix<KK, float><<<nb, kBlock, 0, st>>>(m, t, Qs, (float*)V)));
+    HDG_DISPATCH(k, (k_step1_field<KK, float><<<nb, kBlock, 0, st>>>(m, t, Qs, (float*)V)));
   } else {
-    HDG_DISPATCH(k, (k_step1_matrix<KK, double><<<nb, kBlock, 0, st>>>(m, t, Qs, (double*)V)));
+    HDG_DISPATCH(k, (k_step1_field<KK, double><<<nb, kBlock, 0, st>>>(m, t, Qs, (double*)V)));
   }
   if (b32) {
     HDG_DISPATCH(k, (k_step1_beta<KK, float><<<nblocks(3L * m.nc), kBlock, 0, st>>>(m, t, Qs, delta_up, (float*)beta)));
@@ -1047,7 +1002,7 @@ void launch_apply_soa(int k, hipStream_t st, Step1Launch ln, int dot, DMesh m, D
     return launch3_apply(k, st, 0, dot, m, t.t3, V, beta, alpha, adt, x, nullptr, nullptr, nullptr, out, w, sd,
                          part, apply_soa_blocks(m.nc, ln.block), x32);
   }
-  if (x32) {  // FP32 vectors and arithmetic (the cell matrices are FP32 too)
+  if (x32) {  // FP32 vectors and arithmetic (the field is FP32 too)
     apply_soa_t(k, st, ln, dot, m, t, (const float*)V, (const float*)beta, alpha, adt, (const float*)x,
                 (const float*)w, (const float*)sd, (float*)out, part);
   } else if (v32) {

@@ -22,9 +22,10 @@ def test_algorithmic_bytes_of_the_operators():
     import bench
     # 256 x 256 split squares, k = 3: 131072 cells, 197120 facets
     nbytes, flops = bench.algorithmic_cost("apply_step1_operator", 3, 131072, 197120)
-    # per cell: 15 x 15 volume matrix, 21 upwind weights, 7 geometry doubles,
-    # three vectors of 30 doubles, 9 int32 connectivity entries
-    assert nbytes == 131072 * (8 * (225 + 21 + 7 + 90) + 36) == 364380160
+    # per cell: the advecting field at 36 cell points (72 doubles), 21 upwind
+    # weights, 7 geometry doubles, three vectors of 30 doubles, 9 int32
+    # connectivity entries
+    assert nbytes == 131072 * (8 * (72 + 21 + 7 + 90) + 36) == 203948032
     assert flops > 0
     nbytes, _ = bench.algorithmic_cost("trace_spmv", 3, 131072, 197120)
     # per facet row: 5 blocks of 4 x 4, 5 column ids, x and y (4 doubles each)
