@@ -339,6 +339,7 @@ def tet_run(hdg, hi, torch, n: int, steps: int, warmup: int, trace_calls: int = 
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     info = ctx.info()
+    ref = tuple(t_.clone() for t_ in ctx.get_state()) if mixed else None  # the mixed runs' reference
     # kernel timing in one more step (event timing replays no graphs)
     ctx.profile(PROFILE_EVERY)
     torch.cuda.synchronize()
@@ -395,7 +396,6 @@ def tet_run(hdg, hi, torch, n: int, steps: int, warmup: int, trace_calls: int = 
     mixed_out = None
     if mixed:
         mixed_out = {}
-        ref = ctx.get_state()
         for label, prec in (("mixed", "mixed"), ("fp64_same_rtol", "fp64")):
             c2 = hdg.Context(X, C, degree=k, imex=w["scheme"], n_richardson=w["n_richardson"],
                              trace_solver=w["trace_solver"], rtol_trace=w["rtol_trace"],
