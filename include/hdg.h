@@ -151,13 +151,19 @@ typedef struct {
                             preconditioning, so the
                             stopping residual is that of the unpreconditioned system): 1 =
                             additive Schwarz over facet patches (per interior facet, the block
-                            of the operator on its two cells, inverted per stage in FP64 and
+                            of the operator on its two cells, formed per stage in FP64 and
                             stored in FP16, which changes the convergence, not the solution);
                             0 = none.  The patches contain the normal-continuous fields on
                             which the penalty term alpha h^-1 <[Q.n][w.n]> of eq. (f_impl)
                             vanishes, so the iteration count does not grow with that term's
-                            weight adt/h^2 as it does for cell blocks.  Device memory: 8 nu^2 +
-                            12 nu^2 bytes per cell (nu = (k+2)(k+3)). */
+                            weight adt/h^2 as it does for cell blocks.  On triangles the patch
+                            inverses are held in Woodbury form (cell inverses and per-facet
+                            trace-space corrections, the same operator); device memory per
+                            cell: 8 nu^2 bytes of build scratch, 2 ((nu + 3m) nu + 3 nu m +
+                            6 m^2) + 12 bytes of FP16 factors and (nu + 3m) vector entries of
+                            apply scratch (nu = (k+2)(k+3), m = 2(k+2)).  On tetrahedra the
+                            dense patch inverses: 8 nu^2 + 16 nu^2 bytes per cell
+                            (nu = 3 dim P_{k+1}). */
   int step2_reading;     /* hdg_step2_reading */
   int step1_precond_lag; /* the Step I preconditioner is rebuilt when the stage's adt changes and
                             otherwise every this many stages (1, the default: every stage; its
