@@ -379,7 +379,7 @@ struct hdg_ctx {
   void* vbeta = nullptr;  // upwind weights, FP32 when kx32
   void prepare_step1(const double* Qstar) {
     hdg::launch_prep_adv(k, st, dm, dt, Qstar, prm.delta_up, adv);
-    hdg::launch_step1_matrix(k, st, dm, dt, Qstar, prm.delta_up, vk, vk32, vbeta, kx32);
+    hdg::launch_step1_data(k, st, dm, dt, Qstar, prm.delta_up, vk, vk32, vbeta, kx32);
     vk_qs = Qstar;
     ++vk_gen;
   }
@@ -547,7 +547,7 @@ void hdg_ctx::setup_tet() {
   DTab3& t = dt.t3;
   t.Bu = upload(rt3.Bu); t.dBu = upload(rt3.dBu); t.Bp = upload(rt3.Bp); t.dBp = upload(rt3.dBp);
   t.cw = upload(rt3.cq_w);
-  t.FBu = upload(rt3.FBu); t.FBuT = upload(rt3.FBuT); t.FdBu = upload(rt3.FdBu); t.FBp = upload(rt3.FBp); t.fw = upload(rt3.fq_w);
+  t.FBu = upload(rt3.FBu); t.FdBu = upload(rt3.FdBu); t.FBp = upload(rt3.FBp); t.fw = upload(rt3.fq_w);
   t.MU = upload(rt3.MU); t.NUL = upload(rt3.NUL);
   t.D = upload(rt3.D); t.R = upload(rt3.R); t.KDD = upload(rt3.KDD); t.That = upload(rt3.That);
   t.Chat = upload(rt3.Chat); t.Ehat = upload(rt3.Ehat); t.CD = upload(rt3.CD); t.NEDM = upload(rt3.NEDM);

@@ -98,7 +98,6 @@ struct RefTables3 {
   std::vector<double> Bu, dBu;                   // [nqc][ns], [3][nqc][ns]
   std::vector<double> Bp, dBp;                   // [nqc][np], [3][nqc][np]
   std::vector<double> FBu, FdBu, FBp;            // [24][nqf][ns], [24][3][nqf][ns], [24][nqf][np]
-  std::vector<double> FBuT;                      // [24][ns][nqf] (FBu with the points fastest)
   std::vector<double> MU;                        // [nqf][nf] trace basis
   std::vector<double> NUL;                       // [24][nqf][nb] BDM facet-moment basis, cell orientation
   std::vector<double> D, R;                      // [3][np][ns]: int psi d_a phi, int d_a psi phi

@@ -33,7 +33,6 @@ enum DGeo3 { E3_DET = 0, E3_IJ = 1, E3_J = 10, E3_N = 19, E3_A = 31, kDGeo3 = 35
 struct DTab3 {
   const double *Bu, *dBu, *Bp, *dBp, *cw;           // cell rule
   const double *FBu, *FdBu, *FBp, *fw, *MU, *NUL;   // facet rule
-  const double* FBuT;                                // FBu with the facet points fastest
   const double *D, *R, *KDD, *That, *Chat, *Ehat, *CD, *NEDM, *BDMinv;
 };
 
@@ -105,16 +104,14 @@ void launch_prep_adv(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, d
 void launch_apply(int k, hipStream_t st, int mode, DMesh m, DTab t, const double* adv, double alpha, double adt,
                   const double* x, const double* r, const double* p, const double* lam, double* out);
 // Per-stage data of the Step I operator for advecting velocity Qs (AoS): the
-// per-cell volume matrices V (ns*ns entries, FP32 when v32, else FP64) and the
-// facet upwind weights beta (3*nq_facet FP64 entries), in tiles of 32 cells
-// (arrays hold ceil(nc/32)*32 cells).  beta: entry j of cell e at
-// ((e/32)*nj + j)*32 + e%32.  V: each row as floor(ns/2) pairs of adjacent
-// entries tiled that way (pair pi of row s as entry s*floor(ns/2) + pi, in
-// units of pairs), then, for odd ns, the last entry of every row tiled as
-// entry s of a second array that follows all pairs.
-// (beta FP32 when b32, else FP64)
-void launch_step1_matrix(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, void* V, bool v32,
-                         void* beta, bool b32);
+// volume data V (FP32 when v32, else FP64) and the facet upwind weights beta
+// (3*nq_facet entries, FP32 when b32, else FP64).  Triangles: V is the
+// advecting field at the cell points (2*nq_cell entries per cell), both in
+// tiles of 32 cells (arrays hold ceil(nc/32)*32 cells; entry j of cell e at
+// ((e/32)*nj + j)*32 + e%32).  Tetrahedra: cell-major volume matrices
+// [nc][ns][ns] and weights [nc][4][nq_facet].
+void launch_step1_data(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, void* V, bool v32,
+                       void* beta, bool b32);
 // Launch shape of the Step I operator: threads per workgroup (64, 128 or
 // 256; two threads per cell) and the workgroup-to-XCD order (1: each XCD
 // takes a contiguous eighth of the cells, 0: hardware order).

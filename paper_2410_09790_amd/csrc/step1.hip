@@ -951,10 +951,10 @@ __global__ void __launch_bounds__(PcWood<K>::G * 32) k_pc_pass2(DMesh m, const p
 }
 
 // ============================================================== launchers
-void launch_step1_matrix(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, void* V, bool v32,
-                         void* beta, bool b32) {
+void launch_step1_data(int k, hipStream_t st, DMesh m, DTab t, const double* Qs, double delta_up, void* V, bool v32,
+                       void* beta, bool b32) {
   if (m.dim == 3) {  // tetrahedra: cell-major V [nc][ns][ns] and beta [nc][4][nq_facet], one type for both
-    if (v32 != b32) throw std::invalid_argument("launch_step1_matrix: V and beta of one type on tetrahedra");
+    if (v32 != b32) throw std::invalid_argument("launch_step1_data: V and beta of one type on tetrahedra");
     return launch3_prep(k, st, m, t.t3, Qs, delta_up, V, beta, v32);
   }
   const int nb = nblocks((long)m.nc);

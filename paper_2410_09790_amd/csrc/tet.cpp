@@ -287,10 +287,6 @@ void build_reference3(int k, RefTables3& t) {
         for (int m = 0; m < nb; ++m) t.NUL[((size_t)fp * nqf + q) * nb + m] = nuv[m];
       }
     }
-  t.FBuT.assign((size_t)24 * ns * nqf, 0.0);
-  for (int fp = 0; fp < 24; ++fp)
-    for (int q = 0; q < nqf; ++q)
-      for (int s = 0; s < ns; ++s) t.FBuT[((size_t)fp * ns + s) * nqf + q] = t.FBu[((size_t)fp * nqf + q) * ns + s];
   t.MU.assign((size_t)nqf * nf, 0.0);
   for (int q = 0; q < nqf; ++q) {
     bmu.eval(rf.x[q], rf.y[q], 0.0, muv.data(), nullptr, nullptr, nullptr);
