@@ -708,7 +708,9 @@ def serving_run(hdg, hi, torch, njobs: int = 16, nmax: int = 48, steps: int = 10
                                                 "mean_latency_s": float(np.mean(fifo_lat)),
                                                 "throughput": work / fifo_span}}
         for nw in workers:
-            srv = serve.Server(64 << 30, workers=nw)
+            srv = serve.Server(64 << 30, workers=nw,
+                               on_done=lambda r, nw=nw: log(f"serving rho={rho}, {nw} workers: job "
+                                                            f"{srv.results.index(r)} done at {r.end:.1f} s"))
 
             def feed():
                 t0 = srv.now()
@@ -721,12 +723,7 @@ def serving_run(hdg, hi, torch, njobs: int = 16, nmax: int = 48, steps: int = 10
             th = threading.Thread(target=feed)
             th.start()
             th.join()
-            while True:
-                try:
-                    srv.drain(timeout=30)
-                    break
-                except TimeoutError:  # a progress line every 30 s
-                    log(f"serving rho={rho}, {nw} workers: {sum(r.end > 0 for r in srv.results)} of {njobs} done")
+            srv.drain()
             res = srv.results
             same = all(r.error is None and all(np.array_equal(x, y) for x, y in zip(r.state, a[1]))
                        for r, a in zip(res, alone))

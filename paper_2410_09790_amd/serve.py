@@ -85,7 +85,7 @@ class Server:
     are bit for bit those of a lone run (any chunking of hdg_advance_stages
     gives the same bits, and contexts share no buffers)."""
 
-    def __init__(self, budget_bytes: int, workers: int = 2, slots: int = 16, policies=None):
+    def __init__(self, budget_bytes: int, workers: int = 2, slots: int = 16, policies=None, on_done=None):
         import torch
         if workers < 1 or slots < workers:
             raise ValueError("workers >= 1, slots >= workers")
@@ -108,6 +108,7 @@ class Server:
         self.max_in_use = 0
         self.max_active = 0
         self.results: list[Result] = []
+        self.on_done = on_done  # called with each finished Result, from its worker thread
         self._t0 = time.perf_counter()
         self._threads = [threading.Thread(target=self._worker, args=(pol,), daemon=True) for pol in self.policies]
         for t in self._threads:
@@ -205,6 +206,8 @@ class Server:
                     self._streams.append(res._stream)
                     self._admit()
                 self._cv.notify_all()
+            if done and self.on_done is not None:
+                self.on_done(res)
 
     def drain(self, timeout: float | None = None):
         """Wait until every submitted job has finished, then stop the workers."""
