@@ -1022,35 +1022,47 @@ __global__ void __launch_bounds__(kW3) k3_pc_cellblock(DMesh m, DTab3 t, const d
   }
 }
 
-// Threads of the patch kernel: NC column slots (64 per wave) times NH row
-// parts: each thread holds HN = N / NH rows of a column (four parts, so that
-// eight waves share the elimination of the 120 x 120 block at k = 2).
+// Patch inversion on the FP64 matrix cores.  v_mfma_f64_16x16x4f64 forms
+// D = A B + C for a 16 x 4 A, a 4 x 16 B and a 16 x 16 C: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16] and holds D[4 v + l / 16][l % 16]
+// in its four accumulator doubles v (rows interleaved over the four lane
+// groups; measured on gfx950).  The patch block (N = 2 NU, padded with
+// the identity to NT tiles of 16) stays in registers as accumulator tiles,
+// wave w holding tile row w.
+typedef double f64x4_3 __attribute__((ext_vector_type(4)));
 template <int K>
 struct PcPatchShape3 {
   static constexpr int NU = Dims3<K>::NU, N = 2 * NU;
-  static constexpr int NC = (N + 63) / 64 * 64;
-  static constexpr int NH = 4;
-  static constexpr int HN = N / NH;
-  static_assert(HN * NH == N, "rows split evenly");
-  static constexpr int NT = NC * NH;
+  static constexpr int NT = (N + 15) / 16;  // tiles per row and column, and waves per workgroup
+  static constexpr int NB = N / 4;          // pivot blocks of four
+  static_assert(NB * 4 == N, "four-row pivot blocks");
+  static constexpr int NTH = NT * 64;
 };
 
-// One workgroup per facet: A_F assembled in LDS from the two cell blocks and
-// the coupling through F,
+// One workgroup per facet: A_F assembled from the two cell blocks and the
+// coupling through F,
 //   C[(c,s) of row cell][(c',s') of column cell] =
 //     (adt/det_row) sum_q phi_s phi'_s' (beta_row,q delta_cc' - alpha 2 w_q n_c n_c'),
-// (both cells see the facet's points in the facet's own order), inverted in
-// registers by Gauss-Jordan elimination without pivoting (the symmetric part
-// of A_F is positive definite, as on triangles), and each cell's rows of the
-// inverse stored (own columns first).  Wall facets return at once.
+// (both cells see the facet's points in the facet's own order), inverted by
+// block Gauss-Jordan elimination without pivoting (the symmetric part of A_F
+// is positive definite, as on triangles) on pivot blocks P of four rows:
+// with E = A[:, P] - I[:, P] (so E_P = A_PP - I), R = A_PP^{-1} A[P, :] except
+// R[:, P] = A_PP^{-1}, and A[:, P] replaced by I[:, P], one step is the
+// rank-4 update A <- A - E R, which leaves the in-place inverse's rows P and
+// columns P where Gauss-Jordan puts them.  Each step is one matrix-core
+// product per tile; the wave holding rows P inverts the 4 x 4 block and
+// writes R to LDS (double-buffered: one barrier per step).  Each cell's rows
+// of the inverse are stored in FP16 (own columns first).  Wall facets return
+// at once.
 template <int K>
-__global__ void __launch_bounds__(PcPatchShape3<K>::NT) k3_pc_patch(DMesh m, DTab3 t,
-                                                                    const double* __restrict__ beta, double alpha,
-                                                                    double adt, const double* __restrict__ Dc,
-                                                                    pc3_t* __restrict__ Binv) {
+__global__ void __launch_bounds__(PcPatchShape3<K>::NTH) __attribute__((amdgpu_waves_per_eu(4)))
+k3_pc_patch(DMesh m, DTab3 t,
+                                                                     const double* __restrict__ beta, double alpha,
+                                                                     double adt, const double* __restrict__ Dc,
+                                                                     pc3_t* __restrict__ Binv) {
   using Dm = Dims3<K>;
   using Sh = PcPatchShape3<K>;
-  constexpr int NS = Dm::NS, NU = Dm::NU, NQF = Dm::NQF, N = Sh::N, NC = Sh::NC, HN = Sh::HN;
+  constexpr int NS = Dm::NS, NU = Dm::NU, NQF = Dm::NQF, N = Sh::N, NT = Sh::NT, NTH = Sh::NTH;
   const int F = blockIdx.x;
   const long nc = m.nc;
   const int Km = m.fc_cell[m.nF + F];
@@ -1061,27 +1073,24 @@ __global__ void __launch_bounds__(PcPatchShape3<K>::NT) k3_pc_patch(DMesh m, DTa
   auto lf = [&](int side) { return side ? fm : fp; };
   const int tp = 6 * fp + m.cf_flip[fp * nc + Kp], tm = 6 * fm + m.cf_flip[fm * nc + Km];
   auto tab = [&](int side) { return side ? tm : tp; };
-  __shared__ double sA[N][N + 1];
-  __shared__ double scol[2][N], srow[2][NC];
   // the facet's data of both sides, then the three NS x NS facet matrices
   //   Mb_side[s][s'] = sum_q beta_side,q phi^side_s phi^other_s',
   //   Mw[s][s'] = sum_q 2 w_q phi^+_s phi^-_s'
   // (every quantity the coupling blocks need, computed once per patch)
   __shared__ double tb[2][NQF][NS], bq[2][NQF], w2[NQF];
   __shared__ double Mb[2][NS][NS], Mw[NS][NS];
-  const int j = threadIdx.x % NC, h = threadIdx.x / NC;
-  const int jc = j < N ? j : 0;
-  for (int idx = threadIdx.x; idx < 2 * NQF * NS; idx += Sh::NT) {
+  __shared__ double sR[2][4][NT * 16];
+  for (int idx = threadIdx.x; idx < 2 * NQF * NS; idx += NTH) {
     const int side = idx / (NQF * NS), rem = idx % (NQF * NS);
     tb[side][rem / NS][rem % NS] = t.FBu[(long)tab(side) * NQF * NS + rem];
   }
-  for (int idx = threadIdx.x; idx < 2 * NQF; idx += Sh::NT) {
+  for (int idx = threadIdx.x; idx < 2 * NQF; idx += NTH) {
     const int side = idx / NQF, q = idx % NQF;
     bq[side][q] = beta[((long)cell(side) * 4 + lf(side)) * NQF + q];
   }
-  for (int q = threadIdx.x; q < NQF; q += Sh::NT) w2[q] = 2.0 * t.fw[q];
+  for (int q = threadIdx.x; q < NQF; q += NTH) w2[q] = 2.0 * t.fw[q];
   __syncthreads();
-  for (int idx = threadIdx.x; idx < 3 * NS * NS; idx += Sh::NT) {
+  for (int idx = threadIdx.x; idx < 3 * NS * NS; idx += NTH) {
     const int which = idx / (NS * NS), s = (idx / NS) % NS, s2 = idx % NS;
     double v = 0.0;
     if (which < 2) {
@@ -1092,64 +1101,117 @@ __global__ void __launch_bounds__(PcPatchShape3<K>::NT) k3_pc_patch(DMesh m, DTa
       Mw[s][s2] = v;
     }
   }
-  // the two cell blocks, a flat coalesced copy
-  for (int idx = threadIdx.x; idx < 2 * NU * NU; idx += Sh::NT) {
-    const int side = idx / (NU * NU), rem = idx % (NU * NU);
-    sA[side * NU + rem / NU][side * NU + rem % NU] = Dc[(long)cell(side) * NU * NU + rem];
-  }
   __syncthreads();
-  // coupling blocks: row cell rs, column cell 1 - rs
-  for (int idx = threadIdx.x; idx < 2 * NU * NU; idx += Sh::NT) {
-    const int rs = idx / (NU * NU), rem = idx % (NU * NU);
-    const int rr = rem / NU, jj = rem % NU;
-    const int cr = rr / NS, sr = rr % NS, cj = jj / NS, s2 = jj % NS;
-    const int eo = cell(rs), fo = lf(rs);
-    const double nr = m.geo[(long)(E3_N + 3 * fo + cr) * nc + eo], nj = m.geo[(long)(E3_N + 3 * fo + cj) * nc + eo];
-    const double mw = rs == 0 ? Mw[sr][s2] : Mw[s2][sr];
-    const double v = (cr == cj ? Mb[rs][sr][s2] : 0.0) - alpha * nr * nj * mw;
-    sA[rs * NU + rr][(1 - rs) * NU + jj] = adt / m.geo[(long)E3_DET * nc + eo] * v;
-  }
-  __syncthreads();
-  double col[HN];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int lr = l >> 4, lc = l & 15;  // accumulator rows 16 w + 4 v + lr, columns 16 J + lc
+  f64x4_3 acc[NT];
 #pragma unroll
-  for (int r = 0; r < HN; ++r) col[r] = sA[h * HN + r][jc];
-#pragma unroll 1
-  for (int p = 0; p < N; ++p) {
-    double* cp = scol[p & 1];
-    double* rp = srow[p & 1];
-    const int hp = p / HN, lp = p % HN;
-    if (j == p) {
+  for (int J = 0; J < NT; ++J)
 #pragma unroll
-      for (int r = 0; r < HN; ++r) cp[h * HN + r] = col[r];
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * w + 4 * v + lr, col = 16 * J + lc;
+      double x;
+      if (row >= N || col >= N) {
+        x = row == col ? 1.0 : 0.0;
+      } else {
+        const int rs = row / NU, cs = col / NU, rr = row % NU, jj = col % NU;
+        if (rs == cs) {
+          x = Dc[((long)cell(rs) * NU + rr) * NU + jj];
+        } else {  // coupling block: row cell rs, column cell 1 - rs
+          const int cr = rr / NS, sr = rr % NS, cj = jj / NS, s2 = jj % NS;
+          const int eo = cell(rs), fo = lf(rs);
+          const double nr = m.geo[(long)(E3_N + 3 * fo + cr) * nc + eo];
+          const double nj = m.geo[(long)(E3_N + 3 * fo + cj) * nc + eo];
+          const double mw = rs == 0 ? Mw[sr][s2] : Mw[s2][sr];
+          x = adt / m.geo[(long)E3_DET * nc + eo] * ((cr == cj ? Mb[rs][sr][s2] : 0.0) - alpha * nr * nj * mw);
+        }
+      }
+      acc[J][v] = x;
     }
-    if (h == hp) {
-      double v = 0.0;
+#pragma unroll 1
+  for (int p = 0; p < Sh::NB; ++p) {
+    const int P0 = 4 * p, Tp = P0 >> 4, q0 = P0 & 15;  // rows and columns P0..P0+3: tile Tp, local q0..q0+3
+    // this wave's tiles of the pivot columns (tile column Tp, a uniform choice)
+    f64x4_3 ct = acc[0];
 #pragma unroll
-      for (int r = 0; r < HN; ++r) v = r == lp ? col[r] : v;
-      rp[j] = v;
+    for (int J = 1; J < NT; ++J) ct = J == Tp ? acc[J] : ct;
+    // A operand: E[16 w + lc][lr] = A[16 w + lc][P0 + lr] - delta, held by
+    // lane 16 (lc % 4) + q0 + lr of this wave in accumulator v = lc / 4
+    double e;
+    {
+      const int src = 16 * (lc & 3) + q0 + lr;
+      const double e0 = __shfl(ct[0], src), e1 = __shfl(ct[1], src), e2 = __shfl(ct[2], src),
+                   e3 = __shfl(ct[3], src);
+      const int v = lc >> 2;
+      e = v == 0 ? e0 : (v == 1 ? e1 : (v == 2 ? e2 : e3));
+      if (w == Tp && lc == q0 + lr) e -= 1.0;
+    }
+    double* R = &sR[p & 1][0][0];
+    if (w == Tp) {  // the wave holding rows P: the 4 x 4 pivot block, its inverse, then R
+      // row P0 + i of column 16 J + c sits in lane 16 i + c, accumulator g0
+      const int g0 = q0 >> 2;
+      const double cg = g0 == 0 ? ct[0] : (g0 == 1 ? ct[1] : (g0 == 2 ? ct[2] : ct[3]));
+      double d[4][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) d[i][j] = __shfl(cg, 16 * i + q0 + j);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {  // in-place Gauss-Jordan of the 4 x 4 block
+        const double r = 1.0 / d[q][q];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) d[q][j] = j == q ? r : d[q][j] * r;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (i == q) continue;
+          const double a = d[i][q];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) d[i][j] = j == q ? -a * r : d[i][j] - a * d[q][j];
+        }
+      }
+      // lane (lr, lc) forms R[lr][16 J + lc] from the four pivot rows of its column
+      const double di0 = lr == 0 ? d[0][0] : (lr == 1 ? d[1][0] : (lr == 2 ? d[2][0] : d[3][0]));
+      const double di1 = lr == 0 ? d[0][1] : (lr == 1 ? d[1][1] : (lr == 2 ? d[2][1] : d[3][1]));
+      const double di2 = lr == 0 ? d[0][2] : (lr == 1 ? d[1][2] : (lr == 2 ? d[2][2] : d[3][2]));
+      const double di3 = lr == 0 ? d[0][3] : (lr == 1 ? d[1][3] : (lr == 2 ? d[2][3] : d[3][3]));
+#pragma unroll
+      for (int J = 0; J < NT; ++J) {
+        const double aJ = g0 == 0 ? acc[J][0] : (g0 == 1 ? acc[J][1] : (g0 == 2 ? acc[J][2] : acc[J][3]));
+        double v = di0 * __shfl(aJ, lc) + di1 * __shfl(aJ, 16 + lc) + di2 * __shfl(aJ, 32 + lc) +
+                   di3 * __shfl(aJ, 48 + lc);
+        if (J == Tp && lc >= q0 && lc < q0 + 4) {
+          const int jp = lc - q0;
+          v = jp == 0 ? di0 : (jp == 1 ? di1 : (jp == 2 ? di2 : di3));
+        }
+        R[lr * NT * 16 + 16 * J + lc] = v;
+      }
+    }
+    // columns P become I[:, P]
+#pragma unroll
+    for (int J = 0; J < NT; ++J) {
+      if (J == Tp && lc >= q0 && lc < q0 + 4) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[J][v] = (w == Tp && 4 * v + lr == lc) ? 1.0 : 0.0;
+      }
     }
     __syncthreads();
-    // branch-free update (per-row conditions compiled to branches put one
-    // LDS round trip behind each row): the pivot column's rows in registers
-    // first, then one select per row
-    double cpv[HN];
 #pragma unroll
-    for (int r = 0; r < HN; ++r) cpv[r] = cp[h * HN + r];
-    const double d = 1.0 / cp[p];
-    const bool piv = j == p;
-    const double a = piv ? d : rp[j] * d;
-    const int sel = h == hp ? lp : -1;  // this thread's row that is the pivot row, if any
-#pragma unroll
-    for (int r = 0; r < HN; ++r) col[r] = r == sel ? a : (piv ? 0.0 : col[r]) - cpv[r] * a;
+    for (int J = 0; J < NT; ++J)
+      acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(-e, R[lr * NT * 16 + 16 * J + lc], acc[J], 0, 0, 0);
   }
-  if (j >= N) return;
-  // rows h HN .. h HN + HN - 1 (all of one side), column j: for K+ the
-  // column order is (own, neighbour); for K- its own columns are those of side 1
-  const int side = (h * HN) / NU;
-  const int jb = side == 0 ? j : (j >= NU ? j - NU : j + NU);
+  // rows of one side each: for K+ the column order is (own, neighbour); for
+  // K- its own columns are those of side 1
 #pragma unroll
-  for (int r = 0; r < HN; ++r)
-    Binv[4 * PcLayout3<K>::quad(cell(side), lf(side), (h * HN + r) % NU, jb >> 2) + (jb & 3)] = pc3_store(col[r]);
+  for (int J = 0; J < NT; ++J)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * w + 4 * v + lr, col = 16 * J + lc;
+      if (row < N && col < N) {
+        const int side = row / NU;
+        const int jb = side == 0 ? col : (col >= NU ? col - NU : col + NU);
+        Binv[4 * PcLayout3<K>::quad(cell(side), lf(side), row % NU, jb >> 2) + (jb & 3)] = pc3_store(acc[J][v]);
+      }
+    }
 }
 
 // z = B r on cell-major vectors: thread (cell e, row group g) sums over the
@@ -1301,7 +1363,7 @@ void launch3_recon_rhs(int k, hipStream_t st, DMesh m, DTab3 t, const double* Q,
 void launch3_pc_build(int k, hipStream_t st, DMesh m, DTab3 t, const double* V, const double* beta, double alpha,
                       double adt, double* D, void* Binv) {
   HDG3_DISPATCH(k, (k3_pc_cellblock<KK><<<m.nc, kW3, 0, st>>>(m, t, V, beta, alpha, adt, D)));
-  HDG3_DISPATCH(k, (k3_pc_patch<KK><<<m.nF, PcPatchShape3<KK>::NT, 0, st>>>(m, t, beta, alpha, adt, D,
+  HDG3_DISPATCH(k, (k3_pc_patch<KK><<<m.nF, PcPatchShape3<KK>::NTH, 0, st>>>(m, t, beta, alpha, adt, D,
                                                                              (pc3_t*)Binv)));
 }
 void launch3_pc_apply(int k, hipStream_t st, DMesh m, const void* Binv, const void* r, void* z, bool x32) {
