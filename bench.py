@@ -142,7 +142,11 @@ def algorithmic_cost_tet(kernel: str, k: int, nc: int, nF: int, nF_int: int | No
     step1_precond_apply: per interior facet (nF_int) the FP16 inverse of its
     2 nu x 2 nu patch block (nu = 3 ns), read as two halves by its two cells,
     plus per cell the input and output vectors (nu doubles each) and 4 int32
-    neighbour ids."""
+    neighbour ids.  step1_precond_build (the class covers the cell blocks and
+    the patch inversions, once per step): per cell its nu x nu FP64 block
+    written and read back, per interior facet the FP16 inverse written;
+    flops: 2 (2 nu)^3 per interior facet for the inversion (the matrix cores
+    run the rank-4 updates on the block padded to a multiple of 16)."""
     ns = (k + 2) * (k + 3) * (k + 4) // 6
     nf = (k + 1) * (k + 2) // 2
     nq = ((3 * k + 5) // 2) ** 2
@@ -156,6 +160,10 @@ def algorithmic_cost_tet(kernel: str, k: int, nc: int, nF: int, nF_int: int | No
         nu = 3 * ns
         ni = nF if nF_int is None else nF_int
         return ni * (2 * nu) ** 2 * 2 + nc * (2 * 8 * nu + 4 * 4), ni * 2 * (2 * nu) ** 2
+    if kernel == "step1_precond_build":
+        nu = 3 * ns
+        ni = nF if nF_int is None else nF_int
+        return nc * 2 * 8 * nu * nu + ni * (2 * nu) ** 2 * 2, ni * 2 * (2 * nu) ** 3
     return None, None
 
 
