@@ -36,6 +36,7 @@ struct Dims3 {
 };
 
 constexpr int kW3 = 64;  // lanes per cell
+typedef double f64x4_3 __attribute__((ext_vector_type(4)));  // accumulator of v_mfma_f64_16x16x4f64
 
 struct Geo3 {
   double det, ij[3][3], n[4][3], a[4];
@@ -152,31 +153,58 @@ __global__ void __launch_bounds__(kW3) k3_condense(DMesh m, DTab3 t, double c, d
     W[i][r] = -g.a[f] * v;
   }
   __syncthreads();
-  for (int idx = lane; idx < NP * NL; idx += kW3) {
-    const int i = idx / NL, r = idx % NL;
-    double v = 0.0;
+  // Y = P^{-1} W and W^T Y on the FP64 matrix cores (v_mfma_f64_16x16x4f64:
+  // lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
+  // D[4 v + l / 16][l % 16] in its accumulator double v), zero-padded to
+  // tiles of 16 rows and columns and steps of 4 in the contracted index.
+  constexpr int NLT = (NL + 15) / 16, NKP = (NP + 3) / 4;
+  static_assert(NP <= 16, "one row tile of P^{-1}");
+  const int lr = lane >> 4, lc = lane & 15;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) v += A[i][NP + j] * W[j][r];
-    Y[i][r] = v;
+  for (int tj = 0; tj < NLT; ++tj) {
+    const int col = 16 * tj + lc;
+    f64x4_3 y = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < NKP; ++kk) {
+      const int kq = 4 * kk + lr;
+      const double a = (lc < NP && kq < NP) ? A[lc][NP + kq] : 0.0;
+      const double b = (kq < NP && col < NL) ? W[kq][col] : 0.0;
+      y = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, y, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (4 * v + lr < NP && col < NL) Y[4 * v + lr][col] = y[v];
   }
   __syncthreads();
   const double cod = c / g.det;
-  for (int idx = lane; idx < NL * NL; idx += kW3) {
-    const int r = idx / NL, s = idx % NL;
-    const int f = r / NF, mm = r % NF, gg = s / NF, l = s % NF;
-    const double* cf = t.Chat + (long)(fpv[f] * NF + mm) * NS;
-    const double* cg = t.Chat + (long)(fpv[gg] * NF + l) * NS;
-    double cc = 0.0;
 #pragma unroll
-    for (int q = 0; q < NS; ++q) cc += cf[q] * cg[q];
-    const double nn = g.n[f][0] * g.n[gg][0] + g.n[f][1] * g.n[gg][1] + g.n[f][2] * g.n[gg][2];
-    double v = (r == s) ? tau * g.a[f] : 0.0;
-    v += cod * g.a[f] * g.a[gg] * nn * cc;
-    double ww = 0.0;
+  for (int ti = 0; ti < NLT; ++ti)
 #pragma unroll
-    for (int i = 0; i < NP; ++i) ww += W[i][r] * Y[i][s];
-    SK[(long)(r * NL + s) * nc + e] = v - ww;
-  }
+    for (int tj = 0; tj < NLT; ++tj) {
+      f64x4_3 ww = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < NKP; ++kk) {
+        const int kq = 4 * kk + lr;
+        const double a = (kq < NP && 16 * ti + lc < NL) ? W[kq][16 * ti + lc] : 0.0;  // W^T
+        const double b = (kq < NP && 16 * tj + lc < NL) ? Y[kq][16 * tj + lc] : 0.0;
+        ww = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, ww, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * ti + 4 * v + lr, s = 16 * tj + lc;
+        if (r >= NL || s >= NL) continue;
+        const int f = r / NF, mm = r % NF, gg = s / NF, l = s % NF;
+        const double* cf = t.Chat + (long)(fpv[f] * NF + mm) * NS;
+        const double* cg = t.Chat + (long)(fpv[gg] * NF + l) * NS;
+        double cc = 0.0;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) cc += cf[q] * cg[q];
+        const double nn = g.n[f][0] * g.n[gg][0] + g.n[f][1] * g.n[gg][1] + g.n[f][2] * g.n[gg][2];
+        double x = (r == s) ? tau * g.a[f] : 0.0;
+        x += cod * g.a[f] * g.a[gg] * nn * cc;
+        SK[(long)(r * NL + s) * nc + e] = x - ww[v];
+      }
+    }
 }
 
 // Facet-block ELL assembly of S = sum_K S_K, one thread per facet (no
@@ -1029,7 +1057,6 @@ __global__ void __launch_bounds__(kW3) k3_pc_cellblock(DMesh m, DTab3 t, const d
 // groups; measured on gfx950).  The patch block (N = 2 NU, padded with
 // the identity to NT tiles of 16) stays in registers as accumulator tiles,
 // wave w holding tile row w.
-typedef double f64x4_3 __attribute__((ext_vector_type(4)));
 template <int K>
 struct PcPatchShape3 {
   static constexpr int NU = Dims3<K>::NU, N = 2 * NU;
