@@ -106,7 +106,7 @@ struct RefTables3 {
   std::vector<double> Chat, Ehat;                // [24][nf][ns], [24][nf][np]
   std::vector<double> CD;                        // [24][3][nf][np] = Chat D_a^T
   std::vector<double> NEDM;                      // [nned][3][ns] interior moments of the reference Nedelec basis
-  std::vector<double> BDMinv;                    // [3ns][3ns] inverse of the reference BDM moment matrix
+  std::vector<double> BDMinv;                    // [3ns][3ns] inverse of the reference BDM moment matrix, column-major
 };
 void build_reference3(int k, RefTables3& t);
 

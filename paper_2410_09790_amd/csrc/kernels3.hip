@@ -509,6 +509,7 @@ __global__ void __launch_bounds__(kW3) k3_prep(DMesh m, DTab3 t, const double* _
   const long nc = m.nc;
   const Geo3 g = load_geo3(m, e);
   __shared__ double q[NU], qn[NU], a[3][NQC];  // a: Q* in reference directions at the cell points
+  __shared__ double Mq[NQC][NS];                // (a . grad_ref) phi_j at the cell points
   stage_vel<K>(Qs, e, q);
   __syncthreads();
   for (int iq = lane; iq < NQC; iq += kW3) {
@@ -522,15 +523,37 @@ __global__ void __launch_bounds__(kW3) k3_prep(DMesh m, DTab3 t, const double* _
     for (int r = 0; r < 3; ++r) a[r][iq] = g.det * t.cw[iq] * (g.ij[r][0] * u[0] + g.ij[r][1] * u[1] + g.ij[r][2] * u[2]);
   }
   __syncthreads();
-  for (int idx = lane; idx < NS * NS; idx += kW3) {
-    const int i = idx / NS, j = idx % NS;
-    double v = 0.0;
-    for (int iq = 0; iq < NQC; ++iq) {
-      const double gj = a[0][iq] * t.dBu[(0 * NQC + iq) * NS + j] + a[1][iq] * t.dBu[(1 * NQC + iq) * NS + j] +
-                        a[2][iq] * t.dBu[(2 * NQC + iq) * NS + j];
-      v += t.Bu[iq * NS + i] * gj;
-    }
-    V[((long)e * NS + j) * NS + i] = (TO)(-v);  // stored transposed: V[e][j][i]
+  for (int idx = lane; idx < NQC * NS; idx += kW3) {
+    const int iq = idx / NS, j = idx % NS;
+    Mq[iq][j] = a[0][iq] * t.dBu[(0 * NQC + iq) * NS + j] + a[1][iq] * t.dBu[(1 * NQC + iq) * NS + j] +
+                a[2][iq] * t.dBu[(2 * NQC + iq) * NS + j];
+  }
+  __syncthreads();
+  // V = Bu^T Mq (NS x NS, contracted over the NQC cell points) on the FP64
+  // matrix cores: tiles of 16 x 16 zero-padded, steps of 4 points; lane l
+  // supplies A[l % 16][l / 16], B[l / 16][l % 16] and holds D[4 v + l / 16][l % 16]
+  {
+    constexpr int NST = (NS + 15) / 16, NKQ = (NQC + 3) / 4;
+    const int lr = lane >> 4, lc = lane & 15;
+#pragma unroll
+    for (int ti = 0; ti < NST; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < NST; ++tj) {
+        f64x4_3 acc = {0.0, 0.0, 0.0, 0.0};
+        const int ia = 16 * ti + lc, jb = 16 * tj + lc;
+#pragma unroll 4
+        for (int kk = 0; kk < NKQ; ++kk) {
+          const int kq = 4 * kk + lr;
+          const double av = (kq < NQC && ia < NS) ? t.Bu[kq * NS + ia] : 0.0;
+          const double bv = (kq < NQC && jb < NS) ? Mq[kq][jb] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 16 * ti + 4 * v + lr, j = 16 * tj + lc;
+          if (i < NS && j < NS) V[((long)e * NS + j) * NS + i] = (TO)(-acc[v]);  // stored transposed: V[e][j][i]
+        }
+      }
   }
   for (int f = 0; f < 4; ++f) {
     const int en = m.cf_nb[f * nc + e];
@@ -850,7 +873,7 @@ __global__ void __launch_bounds__(kW3) k3_bdm(DMesh m, DTab3 t, const double* __
   (void)NNED;
   for (int i = lane; i < NU; i += kW3) {
     double v = 0.0;
-    for (int j = 0; j < NU; ++j) v += t.BDMinv[(long)i * NU + j] * rhs[j];
+    for (int j = 0; j < NU; ++j) v += t.BDMinv[(long)j * NU + i] * rhs[j];  // column-major: coalesced
     qh[i] = v;
   }
   __syncthreads();

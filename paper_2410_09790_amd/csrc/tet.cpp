@@ -403,7 +403,13 @@ void build_reference3(int k, RefTables3& t) {
   for (int l = 0; l < t.nned; ++l)
     for (int b = 0; b < 3; ++b)
       for (int s = 0; s < ns; ++s) A[((size_t)4 * nb + l) * nu + b * ns + s] = t.NEDM[((size_t)l * 3 + b) * ns + s];
-  invert_dense(nu, A, t.BDMinv);
+  std::vector<double> inv;
+  invert_dense(nu, A, inv);
+  // stored transposed: lane i of a wave forms row i of the product, so
+  // column-major storage makes the wave's loads of one column contiguous
+  t.BDMinv.assign((size_t)nu * nu, 0.0);
+  for (int i = 0; i < nu; ++i)
+    for (int j = 0; j < nu; ++j) t.BDMinv[(size_t)j * nu + i] = inv[(size_t)i * nu + j];
 }
 
 // ------------------------------------------------------------------ mesh
