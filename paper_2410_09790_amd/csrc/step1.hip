@@ -679,14 +679,15 @@ __global__ void __launch_bounds__(64) k_pc_cellinv(DMesh m, DTab t, double* __re
   }
 }
 
-// One 64-thread workgroup per interior facet: the two cell inverses into
-// LDS, S_side = L A_side^{-1} L^T, the coupling Kf from the facet rule (the
-// same terms as the patch entries: upwind weight on the own component,
-// normal-jump penalty on both, scaled by adt / det of the row cell), then
-// [I + Kf S | Kf] reduced by Gauss-Jordan elimination with partial pivoting
-// (I + Kf S need not be diagonally dominant), and each cell's rows of M_F,
-// rotated into the facet frames, stored with their scale.  Wall facets
-// return at once.
+// One wave per interior facet: T_side = A_side^{-1} L^T from the two cell
+// inverses (read from global memory, each row once), S_side = L T_side, the
+// coupling Kf from the facet rule (the same terms as the patch entries:
+// upwind weight on the own component, normal-jump penalty on both, scaled by
+// adt / det of the row cell), then [I + Kf S | Kf] reduced by Gauss-Jordan
+// elimination with partial pivoting (I + Kf S need not be diagonally
+// dominant; the pivot row found by a wave reduction, the first of equal
+// magnitudes), and each cell's rows of M_F, rotated into the facet frames,
+// stored with their scale.  Wall facets return at once.
 template <int K>
 __global__ void __launch_bounds__(64) k_pc_facet(DMesh m, DTab t, const double* __restrict__ Qs, double delta_up,
                                                  double alpha, double adt, const double* __restrict__ Ai,
@@ -703,18 +704,13 @@ __global__ void __launch_bounds__(64) k_pc_facet(DMesh m, DTab t, const double* 
   const int rev = (m.cf_nbx[fp * nc + Kp] & 1);
   auto cell = [&](int side) { return side ? Km : Kp; };
   auto lf = [&](int side) { return side ? fm : fp; };
-  __shared__ double sA[2][NU][NU + 1];
   __shared__ double sT[2][NU][M];
   __shared__ double sS[2][M][M];
   __shared__ double sa[M2][2 * M2 + 1];
   __shared__ double sw[M][M2];
-  __shared__ double sbeta[2][NQF], scp[M2], smax[64];
-  __shared__ int spiv;
+  __shared__ double sbeta[2][NQF], scp[M2];
   const int tid = threadIdx.x;
-  for (int x = tid; x < 2 * NU * NU; x += 64) {
-    const int side = x / (NU * NU), i = (x / NU) % NU, j = x % NU;
-    sA[side][i][j] = Ai[((long)cell(side) * NU + i) * NU + j];
-  }
+  static_assert(M2 <= 64, "one lane per row of the facet system");
   if (tid < 2 * NQF) {  // upwind weights of both sides at their own facet points
     const int side = tid / NQF, qq = tid % NQF;
     const int e = cell(side), f = lf(side);
@@ -729,14 +725,21 @@ __global__ void __launch_bounds__(64) k_pc_facet(DMesh m, DTab t, const double* 
     const double qn = vx * nx + vy * ny;
     sbeta[side][qq] = t.fw[qq] * hf * (0.5 * qn - delta_up * fabs(qn));
   }
-  __syncthreads();
-  // T = A^{-1} L^T (rows (c, s), columns (c', m'))
-  for (int x = tid; x < 2 * NU * M; x += 64) {
-    const int side = x / (NU * M), i = (x / M) % NU, cm = x % M;
-    const int c2 = cm / NM, m2 = cm % NM, f = lf(side);
-    double v = 0.0;
-    for (int s2 = 0; s2 < NS; ++s2) v += sA[side][i][c2 * NS + s2] * t.TRU[(f * NM + m2) * NS + s2];
-    sT[side][i][cm] = v;
+  // T = A^{-1} L^T (rows (c, s), columns (c', m')): lane x holds row i of
+  // one side's inverse, component c2, and forms its NM entries
+  for (int x = tid; x < 2 * NU * 2; x += 64) {
+    const int side = x / (NU * 2), i = (x / 2) % NU, c2 = x % 2, f = lf(side);
+    const double* arow = Ai + ((long)cell(side) * NU + i) * NU + c2 * NS;
+    double a[NS];
+#pragma unroll
+    for (int s2 = 0; s2 < NS; ++s2) a[s2] = arow[s2];
+#pragma unroll
+    for (int m2 = 0; m2 < NM; ++m2) {
+      double v = 0.0;
+#pragma unroll
+      for (int s2 = 0; s2 < NS; ++s2) v += a[s2] * t.TRU[(f * NM + m2) * NS + s2];
+      sT[side][i][c2 * NM + m2] = v;
+    }
   }
   // Kf into the right half of the augmented matrix
   for (int x = tid; x < M2 * M2; x += 64) {
@@ -776,15 +779,15 @@ __global__ void __launch_bounds__(64) k_pc_facet(DMesh m, DTab t, const double* 
   __syncthreads();
 #pragma unroll 1
   for (int p = 0; p < M2; ++p) {
-    if (tid == 0) {
-      int best = p;
-      double bv = fabs(sa[p][p]);
-      for (int r = p + 1; r < M2; ++r)
-        if (fabs(sa[r][p]) > bv) { bv = fabs(sa[r][p]); best = r; }
-      spiv = best;
+    // pivot row: the largest |sa[r][p]| over r >= p, the first of equal ones
+    double bv = tid >= p && tid < M2 ? fabs(sa[tid][p]) : -1.0;
+    int pv = tid;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(bv, o, 64);
+      const int oi = __shfl_xor(pv, o, 64);
+      if (ov > bv || (ov == bv && oi < pv)) { bv = ov; pv = oi; }
     }
-    __syncthreads();
-    const int pv = spiv;
     if (pv != p)
       for (int j = tid; j < 2 * M2; j += 64) {
         const double v = sa[p][j];
@@ -822,15 +825,10 @@ __global__ void __launch_bounds__(64) k_pc_facet(DMesh m, DTab t, const double* 
       sw[r][j] = v;
       mx = fmax(mx, fabs(v));
     }
-    smax[tid] = mx;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
     __syncthreads();
-    if (tid == 0) {
-      double v = 0.0;
-      for (int i = 0; i < 64; ++i) v = fmax(v, smax[i]);
-      smax[0] = v > 0.0 ? ldexp(1.0, ilogb(v) - 13) : 1.0;  // v / sc < 2^14
-    }
-    __syncthreads();
-    const double sc = smax[0];
+    const double sc = mx > 0.0 ? ldexp(1.0, ilogb(mx) - 13) : 1.0;  // max |W| / sc < 2^14
     const long e = cell(a);
     const int f = lf(a);
     if (tid == 0) scale[f * nc32 + e] = (float)sc;
