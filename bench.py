@@ -809,7 +809,7 @@ def main():
                     help="also run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU decomposition is a design, not code)", file=sys.stderr)
         sys.exit(2)
     import numpy as np

@@ -63,7 +63,7 @@ typedef enum {
   HDG_ERR_DEVICE = 3,        /* a HIP call failed */
   HDG_ERR_NOT_CONVERGED = 4, /* a Krylov solve hit its iteration cap; the result is kept */
   HDG_ERR_BAD_STATE = 5,     /* e.g. hdg_advance before any state was set */
-  HDG_ERR_UNSUPPORTED = 6    /* feature outside this build (3D, degree > 4, ...) */
+  HDG_ERR_UNSUPPORTED = 6    /* not available: degree > 4, k > 2 or forcing, tracer, periodic meshes on tetrahedra */
 } hdg_status;
 
 /* IMEX schemes (Appendix A): IMEX Euler as printed; ARS(2,2,2) and ARS(2,3,3)
