@@ -1154,6 +1154,14 @@ k3_pc_patch(DMesh m, DTab3 t,
   __syncthreads();
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int lr = l >> 4, lc = l & 15;  // accumulator rows 16 w + 4 v + lr, columns 16 J + lc
+  // the row cell's facet normal and adt / det, both sides, loaded once
+  double nrm[2][3], sc[2];
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+#pragma unroll
+    for (int c3 = 0; c3 < 3; ++c3) nrm[side][c3] = m.geo[(long)(E3_N + 3 * lf(side) + c3) * nc + cell(side)];
+    sc[side] = adt / m.geo[(long)E3_DET * nc + cell(side)];
+  }
   f64x4_3 acc[NT];
 #pragma unroll
   for (int J = 0; J < NT; ++J)
@@ -1169,11 +1177,12 @@ k3_pc_patch(DMesh m, DTab3 t,
           x = Dc[((long)cell(rs) * NU + rr) * NU + jj];
         } else {  // coupling block: row cell rs, column cell 1 - rs
           const int cr = rr / NS, sr = rr % NS, cj = jj / NS, s2 = jj % NS;
-          const int eo = cell(rs), fo = lf(rs);
-          const double nr = m.geo[(long)(E3_N + 3 * fo + cr) * nc + eo];
-          const double nj = m.geo[(long)(E3_N + 3 * fo + cj) * nc + eo];
+          // selects, not indexing: a per-lane index into a register array would go to scratch
+          const double n0 = rs ? nrm[1][0] : nrm[0][0], n1 = rs ? nrm[1][1] : nrm[0][1],
+                       n2 = rs ? nrm[1][2] : nrm[0][2];
+          const double nr = cr == 0 ? n0 : (cr == 1 ? n1 : n2), nj = cj == 0 ? n0 : (cj == 1 ? n1 : n2);
           const double mw = rs == 0 ? Mw[sr][s2] : Mw[s2][sr];
-          x = adt / m.geo[(long)E3_DET * nc + eo] * ((cr == cj ? Mb[rs][sr][s2] : 0.0) - alpha * nr * nj * mw);
+          x = (rs ? sc[1] : sc[0]) * ((cr == cj ? Mb[rs][sr][s2] : 0.0) - alpha * nr * nj * mw);
         }
       }
       acc[J][v] = x;
