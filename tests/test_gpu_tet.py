@@ -201,7 +201,7 @@ def _facet_schwarz(d, Ahat, r, fp16=False):
     return z
 
 
-@pytest.mark.parametrize("n,k,pert", [(2, 1, 0.1), (2, 2, 0.1)])
+@pytest.mark.parametrize("n,k,pert", [(2, 1, 0.1), (2, 2, 0.1), (3, 2, 0.05)])
 def test_patch_preconditioner_matches_dense(n, k, pert):
     import scipy.sparse as sp
     torch = torch_or_skip()
